@@ -1,0 +1,349 @@
+"""Seeded synthetic inputs: NURBS multipatch geometries and Dirichlet data.
+
+This module holds no arithmetic of the boundary element method itself.  It
+only produces *inputs*: NURBS control nets (the geometry description of
+Section 2.2, eq. def::geom), seeded point sets and manufactured boundary data
+of the kind used in Sections 5.1 and 5.3.  Both the CPU oracle and the HIP
+path consume these, so nothing here may depend on either of them.
+
+Geometries
+----------
+* ``sphere_patches()``: the unit sphere as 6 NURBS patches in a cube topology
+  (Section 5).  Each patch is an *exact* rational Bezier patch of bidegree
+  (4,4), obtained as the inverse stereographic projection of a planar
+  rational biquadratic patch bounded by four circular arcs (the stereographic
+  images of the great circles through the cube edges).  The composition of a
+  bidegree-(2,2) rational map with the quadratic map sigma is bidegree (4,4),
+  which matches the degree-4 patches named in Section 5.
+* ``torus_patches()``: the torus with R=2, r=0.5 as 16 rational biquadratic
+  patches, each a 90 degree by 90 degree piece (Section 5).
+* ``flat_patch()`` / ``cube_patches()``: bilinear patches for tests.
+
+Every patch is a dict with keys ``deg_u, deg_v, knots_u, knots_v, cpw`` where
+``cpw`` has shape ``(n_v, n_u, 4)`` holding ``x, y, z, w`` (w > 0, control
+points not premultiplied by w; u runs fastest in memory).
+"""
+from __future__ import annotations
+
+import math
+from math import comb
+
+import numpy as np
+
+__all__ = [
+    "sphere_patches",
+    "torus_patches",
+    "flat_patch",
+    "cube_patches",
+    "perturbed_sphere_patches",
+    "random_directions",
+    "config_small_sphere",
+    "config_sphere_h2",
+    "config_torus_helmholtz",
+    "interior_ball_points",
+    "point_charges",
+]
+
+
+# ---------------------------------------------------------------------------
+# helpers for building control nets (geometric modelling, not the BEM method)
+# ---------------------------------------------------------------------------
+def _bezier_product(f: np.ndarray, g: np.ndarray) -> np.ndarray:
+    """Bernstein coefficients of the product of two tensor Bernstein polynomials.
+
+    ``f`` has shape (a+1, b+1), ``g`` (c+1, d+1); the result has shape
+    (a+c+1, b+d+1).  Uses B_i^a B_j^c = C(a,i)C(c,j)/C(a+c,i+j) B_{i+j}^{a+c}.
+    """
+    a, b = f.shape[0] - 1, f.shape[1] - 1
+    c, d = g.shape[0] - 1, g.shape[1] - 1
+    out = np.zeros((a + c + 1, b + d + 1))
+    for i in range(a + 1):
+        for j in range(b + 1):
+            for k in range(c + 1):
+                for l in range(d + 1):
+                    cu = comb(a, i) * comb(c, k) / comb(a + c, i + k)
+                    cv = comb(b, j) * comb(d, l) / comb(b + d, j + l)
+                    out[i + k, j + l] += f[i, j] * g[k, l] * cu * cv
+    return out
+
+
+def _bezier_knots(deg: int) -> np.ndarray:
+    return np.array([0.0] * (deg + 1) + [1.0] * (deg + 1))
+
+
+def _patch(deg_u, deg_v, knots_u, knots_v, cpw) -> dict:
+    cpw = np.ascontiguousarray(cpw, dtype=np.float64)
+    assert cpw.ndim == 3 and cpw.shape[2] == 4
+    return {
+        "deg_u": int(deg_u),
+        "deg_v": int(deg_v),
+        "knots_u": np.ascontiguousarray(knots_u, dtype=np.float64),
+        "knots_v": np.ascontiguousarray(knots_v, dtype=np.float64),
+        "cpw": cpw,
+    }
+
+
+def _rotate_patch(patch: dict, R: np.ndarray) -> dict:
+    cpw = patch["cpw"].copy()
+    cpw[..., :3] = cpw[..., :3] @ R.T
+    return _patch(patch["deg_u"], patch["deg_v"], patch["knots_u"], patch["knots_v"], cpw)
+
+
+# ---------------------------------------------------------------------------
+# unit sphere, 6 exact rational patches of bidegree (4,4)
+# ---------------------------------------------------------------------------
+def _sphere_top_patch() -> dict:
+    """Patch covering the cap {|x| <= z, |y| <= z} of the unit sphere."""
+    s3 = math.sqrt(3.0)
+    c = (s3 - 1.0) / 2.0            # corner of the curvilinear square (cube corner image)
+    t = 2.0 * s3 - 3.0              # tangent intersection of the 30 degree arcs
+    we = math.cos(math.pi / 12.0)   # conic weight of a 30 degree circular arc
+    wc = we * we                    # centre weight
+    # planar control net: index [i][j], i along u (first plane coordinate a),
+    # j along v (second coordinate b)
+    pos = np.zeros((3, 3, 2))
+    wgt = np.zeros((3, 3))
+    for i in range(3):
+        for j in range(3):
+            ci, cj = i - 1, j - 1
+            if ci != 0 and cj != 0:
+                pos[i, j] = (ci * c, cj * c)
+                wgt[i, j] = 1.0
+            elif ci == 0 and cj == 0:
+                pos[i, j] = (0.0, 0.0)
+                wgt[i, j] = wc
+            elif ci == 0:
+                pos[i, j] = (0.0, cj * t)
+                wgt[i, j] = we
+            else:
+                pos[i, j] = (ci * t, 0.0)
+                wgt[i, j] = we
+    A = pos[..., 0] * wgt            # homogeneous planar coordinates
+    B = pos[..., 1] * wgt
+    W = wgt
+    AW = _bezier_product(A, W)
+    BW = _bezier_product(B, W)
+    WW = _bezier_product(W, W)
+    AA = _bezier_product(A, A)
+    BB = _bezier_product(B, B)
+    X = 2.0 * AW
+    Y = 2.0 * BW
+    Z = WW - AA - BB
+    H = WW + AA + BB
+    if not np.all(H > 0):
+        raise RuntimeError("sphere construction produced a non-positive weight")
+    # cpw layout (n_v, n_u, 4): [j][i]
+    cpw = np.zeros((5, 5, 4))
+    for i in range(5):
+        for j in range(5):
+            h = H[i, j]
+            cpw[j, i] = (X[i, j] / h, Y[i, j] / h, Z[i, j] / h, h)
+    return _patch(4, 4, _bezier_knots(4), _bezier_knots(4), cpw)
+
+
+_FACE_ROTATIONS = {
+    "+z": np.eye(3),
+    "-z": np.array([[1.0, 0, 0], [0, -1.0, 0], [0, 0, -1.0]]),
+    "+x": np.array([[0.0, 0, 1.0], [0, 1.0, 0], [-1.0, 0, 0]]),
+    "-x": np.array([[0.0, 0, -1.0], [0, 1.0, 0], [1.0, 0, 0]]),
+    "+y": np.array([[1.0, 0, 0], [0, 0, 1.0], [0, -1.0, 0]]),
+    "-y": np.array([[1.0, 0, 0], [0, 0, -1.0], [0, 1.0, 0]]),
+}
+
+
+def sphere_patches(radius: float = 1.0) -> list[dict]:
+    """Exact sphere of the given radius as 6 rational bidegree-(4,4) patches."""
+    top = _sphere_top_patch()
+    out = []
+    for key in ("+z", "-z", "+x", "-x", "+y", "-y"):
+        p = _rotate_patch(top, _FACE_ROTATIONS[key])
+        p["cpw"][..., :3] *= radius
+        out.append(p)
+    return out
+
+
+def perturbed_sphere_patches(amplitude: float, seed: int, max_degree: int = 6) -> list[dict]:
+    """Sphere with control points moved radially, c -> c (1 + amplitude rho(c/|c|)).
+
+    rho is a seeded random combination of real spherical-harmonic-like
+    polynomials of degree <= max_degree (here: random homogeneous polynomials
+    restricted to the sphere), normalised so max|rho| = 1 on a sample.  The
+    result is still an exact NURBS description of a smooth closed surface.
+    """
+    rng = np.random.default_rng(seed)
+    terms = []
+    for deg in range(1, max_degree + 1):
+        for _ in range(2 * deg + 1):
+            e = rng.integers(0, deg + 1, size=2)
+            a = min(int(e[0]), deg)
+            b = min(int(e[1]), deg - a)
+            terms.append((a, b, deg - a - b, rng.standard_normal()))
+
+    def rho(v):
+        v = v / np.linalg.norm(v, axis=-1, keepdims=True)
+        s = 0.0
+        for a, b, c, coef in terms:
+            s = s + coef * v[..., 0] ** a * v[..., 1] ** b * v[..., 2] ** c
+        return s
+
+    sample = random_directions(4096, seed + 7919)
+    scale = np.max(np.abs(rho(sample)))
+    out = []
+    for p in sphere_patches():
+        cpw = p["cpw"].copy()
+        pts = cpw[..., :3]
+        fac = 1.0 + amplitude * rho(pts) / scale
+        cpw[..., :3] = pts * fac[..., None]
+        out.append(_patch(p["deg_u"], p["deg_v"], p["knots_u"], p["knots_v"], cpw))
+    return out
+
+
+# ---------------------------------------------------------------------------
+# torus, 16 rational biquadratic patches
+# ---------------------------------------------------------------------------
+def _quarter_arc(a0: float):
+    """Control points and weights of the unit-circle arc [a0, a0 + pi/2]."""
+    c0, s0 = math.cos(a0), math.sin(a0)
+    c2, s2 = math.cos(a0 + math.pi / 2), math.sin(a0 + math.pi / 2)
+    pts = np.array([[c0, s0], [c0 + c2, s0 + s2], [c2, s2]])
+    w = np.array([1.0, math.sqrt(0.5), 1.0])
+    return pts, w
+
+
+def torus_patches(R: float = 2.0, r: float = 0.5) -> list[dict]:
+    """Torus around the z axis; u runs along the big circle, v around the tube."""
+    out = []
+    for i in range(4):            # toroidal quarter
+        Q, wq = _quarter_arc(i * math.pi / 2)
+        for j in range(4):        # poloidal quarter
+            C, wcirc = _quarter_arc(j * math.pi / 2)
+            cpw = np.zeros((3, 3, 4))
+            for b in range(3):    # v index (tube)
+                rho = R + r * C[b, 0]
+                z = r * C[b, 1]
+                for a in range(3):  # u index
+                    cpw[b, a] = (rho * Q[a, 0], rho * Q[a, 1], z, wq[a] * wcirc[b])
+            out.append(_patch(2, 2, _bezier_knots(2), _bezier_knots(2), cpw))
+    return out
+
+
+# ---------------------------------------------------------------------------
+# flat test patches
+# ---------------------------------------------------------------------------
+def flat_patch(p00, p10, p01, p11) -> dict:
+    """Bilinear patch with corners F(0,0)=p00, F(1,0)=p10, F(0,1)=p01, F(1,1)=p11."""
+    cpw = np.zeros((2, 2, 4))
+    cpw[0, 0, :3], cpw[0, 1, :3] = p00, p10
+    cpw[1, 0, :3], cpw[1, 1, :3] = p01, p11
+    cpw[..., 3] = 1.0
+    return _patch(1, 1, _bezier_knots(1), _bezier_knots(1), cpw)
+
+
+def cube_patches(edge: float = 2.0) -> list[dict]:
+    """Surface of the cube [-edge/2, edge/2]^3 as 6 bilinear patches (outward normals)."""
+    h = edge / 2.0
+    out = []
+    for key in ("+z", "-z", "+x", "-x", "+y", "-y"):
+        R = _FACE_ROTATIONS[key]
+        corners = [np.array(c) for c in ((-h, -h, h), (h, -h, h), (-h, h, h), (h, h, h))]
+        out.append(flat_patch(*[R @ c for c in corners]))
+    return out
+
+
+# ---------------------------------------------------------------------------
+# seeded point sets and data
+# ---------------------------------------------------------------------------
+def random_directions(n: int, seed: int) -> np.ndarray:
+    """n unit vectors: normalised standard normals from PCG64(seed)."""
+    rng = np.random.default_rng(seed)
+    v = rng.standard_normal((n, 3))
+    return v / np.linalg.norm(v, axis=1, keepdims=True)
+
+
+def interior_ball_points(n: int, seed: int, radius: float = 0.85) -> np.ndarray:
+    """n points uniform in the ball of the given radius (seeded)."""
+    rng = np.random.default_rng(seed)
+    d = rng.standard_normal((n, 3))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    rad = radius * rng.random(n) ** (1.0 / 3.0)
+    return d * rad[:, None]
+
+
+def point_charges(n: int, seed: int, rmin: float = 1.5, rmax: float = 3.0):
+    """n exterior charges: positions at radius U[rmin,rmax] and strengths U[-1,1]."""
+    rng = np.random.default_rng(seed)
+    d = rng.standard_normal((n, 3))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    rad = rng.uniform(rmin, rmax, n)
+    q = rng.uniform(-1.0, 1.0, n)
+    return d * rad[:, None], q
+
+
+def laplace_charge_field(points: np.ndarray, pos: np.ndarray, q: np.ndarray) -> np.ndarray:
+    """Harmonic field sum_i q_i / (4 pi |x - x_i|) at the given points (data, not the method)."""
+    pts = np.asarray(points, dtype=np.float64).reshape(-1, 3)
+    out = np.zeros(pts.shape[0])
+    for x0, c in zip(pos, q):
+        out += c / (4.0 * math.pi * np.linalg.norm(pts - x0, axis=1))
+    return out
+
+
+def helmholtz_point_source(points: np.ndarray, v, kappa: float) -> np.ndarray:
+    """exp(i kappa |x - v|) / |x - v| at the given points (Section 5.3 data family)."""
+    pts = np.asarray(points, dtype=np.float64).reshape(-1, 3)
+    d = np.linalg.norm(pts - np.asarray(v, dtype=np.float64), axis=1)
+    return np.exp(1j * kappa * d) / d
+
+
+# ---------------------------------------------------------------------------
+# named workloads
+# ---------------------------------------------------------------------------
+def config_small_sphere() -> dict:
+    """Laplace interior Dirichlet on the 6-patch unit sphere, p=1, 4x4 elements per patch,
+    Gauss order 6, dense (every element pair in the near field); data = 1/|x - x0|
+    with x0 seeded at radius 2; 100 seeded interior evaluation points."""
+    x0 = 2.0 * random_directions(1, 1)[0]
+    return {
+        "name": "laplace_sphere_p1_m2_dense",
+        "patches": sphere_patches(),
+        "kernel": 0, "wavenumber": 0.0,
+        "p": 1, "m": 2, "q": 8, "eta": 1.6, "gauss_regular": 6,
+        "dense": True,
+        "source": x0,
+        "eval_points": interior_ball_points(100, 1),
+    }
+
+
+def config_sphere_h2() -> dict:
+    """Laplace on the 6-patch unit sphere, p=3, 32x32 elements per patch (m=5), H2 with
+    q=8 Chebyshev nodes per parametric direction, eta=1.6, Gauss order 6; data from 4
+    seeded exterior point charges."""
+    pos, q = point_charges(4, 2)
+    return {
+        "name": "laplace_sphere_p3_m5_q8",
+        "patches": sphere_patches(),
+        "kernel": 0, "wavenumber": 0.0,
+        "p": 3, "m": 5, "q": 8, "eta": 1.6, "gauss_regular": 6,
+        "dense": False,
+        "charges": (pos, q),
+        "eval_points": interior_ball_points(100, 2),
+    }
+
+
+def config_torus_helmholtz() -> dict:
+    """Helmholtz exterior on the 16-patch torus (R=2, r=0.5), p=2, 64x64 elements per
+    patch (m=6), kappa=8, q=10; plane wave with seeded unit direction; potential on a
+    64x64 grid of the plane z=1, x,y in [-4,4]."""
+    d = random_directions(1, 3)[0]
+    xs = np.linspace(-4.0, 4.0, 64)
+    gx, gy = np.meshgrid(xs, xs, indexing="xy")
+    grid = np.stack([gx.ravel(), gy.ravel(), np.ones(gx.size)], axis=1)
+    return {
+        "name": "helmholtz_torus_p2_m6_q10_k8",
+        "patches": torus_patches(),
+        "kernel": 1, "wavenumber": 8.0,
+        "p": 2, "m": 6, "q": 10, "eta": 1.6, "gauss_regular": 6,
+        "dense": False,
+        "direction": d,
+        "eval_points": grid,
+    }

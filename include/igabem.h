@@ -1,0 +1,207 @@
+/*
+ * libigabem: fast isogeometric single-layer BEM for the 3D Laplace and
+ * Helmholtz Dirichlet problems on NURBS multipatch surfaces, with the
+ * Galerkin matrix compressed by interpolation-based (tensor Chebyshev,
+ * nested / H2) fast multipole, after Doelz, Harbrecht, Kurz, Schoeps, Wolf,
+ * "A Fast Isogeometric BEM for the Three Dimensional Laplace- and Helmholtz
+ * Problems" (arXiv 1708.09162).  All compute runs in HIP kernels on one
+ * gfx950 GPU in FP64.
+ *
+ * Conventions (apply to every entry point):
+ *  - Host structs and arrays are read during the call and copied; the library
+ *    keeps no host pointer of the caller.
+ *  - "_dev" pointers are device (HBM) pointers owned by the caller.  Calls that
+ *    take them are ordered on the operator's HIP stream and return before the
+ *    work completes unless stated otherwise.
+ *  - Real problems (Laplace) use double.  Helmholtz problems use interleaved
+ *    (re, im) double pairs, the layout of complex128.
+ *  - S = the spline space of Sec. 2.2 (eq. def::space), dimension
+ *    n (2^m + p)^2; dof index patch*(2^m+p)^2 + j2*(2^m+p) + j1 (u fastest).
+ *  - S* = the discontinuous Bernstein superspace of Sec. 4.3, dimension
+ *    n (2^m (p+1))^2; external index E*(p+1)^2 + r2*(p+1) + r1 with element
+ *    E = patch*4^m + e2*2^m + e1.
+ *  - Cluster ids (Sec. 4.1, the tuple (i, j, k) of a cluster): within a level
+ *    l, id = patch*4^l + k2*2^l + k1 for the parameter square
+ *    [k1, k1+1] x [k2, k2+1] * 2^-l of patch `patch`.
+ *  - Return value: IGB_OK (0), a negative error, or a positive warning.  On a
+ *    non-zero return igb_last_error() gives a message (thread-local).
+ */
+#ifndef IGABEM_H
+#define IGABEM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t igb_status;
+
+#define IGB_OK 0
+#define IGB_ENOT_CONVERGED 1     /* warning: solver stopped at max_iter; w holds the last iterate */
+#define IGB_EINVAL (-1)          /* invalid argument (null pointer, bad knots, weights, sizes ...) */
+#define IGB_EHIP (-2)            /* a HIP runtime call or kernel launch failed */
+#define IGB_ENOMEM (-3)          /* device or host allocation failed */
+#define IGB_EUNSUPPORTED (-4)    /* valid request outside what this build implements */
+
+#define IGB_LAPLACE 0            /* interior Laplace, kernel 1/(4 pi |x-y|) (Sec. 3.1, eq. fundament1) */
+#define IGB_HELMHOLTZ 1          /* exterior Helmholtz, exp(i k |x-y|)/(4 pi |x-y|) (eq. fundament2) */
+
+#define IGB_DENSE 0              /* every element pair by quadrature, no compression */
+#define IGB_H2_STORED 1          /* near field + far field with coupling blocks stored in HBM */
+
+#define IGB_FP64 0
+
+/* One NURBS patch F_j : [0,1]^2 -> Gamma_j (Sec. 2.2, eq. def::geom).
+ * knots_u has n_u + deg_u + 1 entries, p-open (Sec. 2.1): deg_u+1 zeros first,
+ * deg_u+1 ones last, non-decreasing; the same for v.  Interior knots must lie
+ * on the refinement grid k/2^m of the operator built on it.
+ * cpw holds n_v*n_u*4 doubles (x, y, z, w), u fastest, w > 0, points not
+ * premultiplied by w.  Neighbouring patches must agree on shared edges up to
+ * a rotation of the parameter square (Sec. 2.2). */
+typedef struct {
+    int32_t deg_u, deg_v;
+    int32_t n_u, n_v;
+    const double *knots_u;
+    const double *knots_v;
+    const double *cpw;
+} igb_nurbs_patch;
+
+/* Discretisation and compression parameters. */
+typedef struct {
+    int32_t kernel;          /* IGB_LAPLACE or IGB_HELMHOLTZ */
+    double wavenumber;       /* kappa >= 0 (Helmholtz only) */
+    int32_t p;               /* spline degree, 0 <= p <= 6 (Sec. 2.2) */
+    int32_t m;               /* refinement level, 2^m x 2^m elements per patch, 0 <= m <= 10 */
+    int32_t q;               /* Chebyshev nodes per parametric direction, 1 <= q <= 16 (Sec. 4.2) */
+    double eta;              /* admissibility max(diam) < eta * dist, eta > 0 (Sec. 4.2 Def.) */
+    int32_t leaf_depth;      /* levels between leaf clusters and elements; -1: smallest d with (p+1)^2 4^d >= q^2 */
+    int32_t gauss_regular;   /* g0: Gauss points per direction for well separated pairs, 1..36 */
+    int32_t gauss_singular;  /* points per variable in the regularised touching-pair rules; -1: g0+2 */
+    int32_t gauss_rhs;       /* points per direction for right-hand side and potential; -1: max(g0, p+4) */
+    int32_t mode;            /* IGB_DENSE or IGB_H2_STORED */
+    int32_t far_precision;   /* IGB_FP64 */
+} igb_params;
+
+/* Sizes of an assembled operator (host struct filled by igb_operator_info). */
+typedef struct {
+    int64_t n_dof;             /* dim S */
+    int64_t n_dof_super;       /* dim S* */
+    int64_t n_elements;
+    int64_t n_rhs_points;      /* n_elements * gauss_rhs^2 */
+    int32_t leaf_level;        /* L = m - leaf_depth */
+    int32_t gauss_singular;
+    int32_t gauss_rhs;
+    int32_t pad0;
+    int64_t n_near_blocks;     /* leaf pairs in the near field */
+    int64_t n_far_blocks;      /* admissible cluster pairs, all levels */
+    int64_t n_pairs[4];        /* element pairs by class: regular, identical, common edge, common vertex */
+    int64_t near_bytes;        /* HBM bytes of the stored near-field blocks */
+    int64_t coupling_bytes;    /* HBM bytes of the stored coupling blocks */
+    int64_t matvec_bytes;      /* algorithmic HBM bytes of one superspace matvec */
+    double setup_seconds;      /* host part of igb_operator_create (tree, partition, lists) */
+    double assembly_seconds;   /* whole igb_operator_create, device work included */
+} igb_info;
+
+typedef struct {
+    int32_t iterations;        /* operator applications in the Krylov loop */
+    int32_t converged;         /* 1 if the true relative residual reached rel_tol */
+    double rel_residual;       /* final true relative residual ||b - A w|| / ||b|| */
+} igb_solve_info;
+
+typedef struct igb_geometry igb_geometry;
+typedef struct igb_operator igb_operator;
+
+/* Message for the last non-zero status returned on this thread. */
+const char *igb_last_error(void);
+
+/* Validates and copies n_patches NURBS patches (Sec. 2.2).
+ * IGB_EINVAL: null pointers, degrees outside 0..8, n < deg+1, knot vectors
+ * that are not p-open or decrease, weights <= 0 or non-finite coordinates. */
+igb_status igb_geometry_create(int32_t n_patches, const igb_nurbs_patch *patches, igb_geometry **out);
+void igb_geometry_destroy(igb_geometry *geo);
+
+/* Assembles the operator A (Sec. 4): Bezier extraction of the geometry onto
+ * the 2^m x 2^m element grid, cluster tree and block partition (Sec. 4.1,
+ * 4.2), near-field Galerkin quadrature (Sec. 3.2; Sec. 4 item 4), coupling
+ * blocks and moment/transfer matrices (Sec. 4.2), Jacobi diagonal.  Device
+ * memory is allocated here and freed by igb_operator_destroy.  `hip_stream`
+ * is a hipStream_t (NULL = default stream) used by every later call on the
+ * operator.  Synchronises the stream before returning.
+ * IGB_EINVAL for parameters out of range or geometry whose interior knots are
+ * off the refinement grid; IGB_ENOMEM if HBM runs out; IGB_EHIP otherwise. */
+igb_status igb_operator_create(const igb_geometry *geo, const igb_params *prm, void *hip_stream,
+                               igb_operator **out);
+void igb_operator_destroy(igb_operator *op);
+
+/* Fills `out` (host).  Synchronous. */
+igb_status igb_operator_info(const igb_operator *op, igb_info *out);
+
+/* Quadrature points where the Dirichlet data g must be sampled: n_rhs_points
+ * x 3 doubles written to xyz_dev, element-major, then v-node outer, u-node
+ * inner, Gauss order gauss_rhs per direction (Sec. 3.2, right-hand side). */
+igb_status igb_rhs_points(const igb_operator *op, double *xyz_dev);
+
+/* b = T g* with g*_a = int g(F x) kappa(x) phi_a(x) dx (Sec. 3.2; Sec. 4.3).
+ * g_dev: n_rhs_points values at igb_rhs_points; b_dev: n_dof values. */
+igb_status igb_rhs_assemble(const igb_operator *op, const void *g_dev, void *b_dev);
+
+/* y = T A T^T x on S (Sec. 4.3): x_dev, y_dev n_dof values, must not alias. */
+igb_status igb_matvec(const igb_operator *op, const void *x_dev, void *y_dev);
+
+/* y* = A x* on S* (external S* order): xs_dev, ys_dev n_dof_super values, no aliasing. */
+igb_status igb_matvec_super(const igb_operator *op, const void *xs_dev, void *ys_dev);
+
+/* xs = T^T w (S -> S*) and y = T ys (S* -> S), Sec. 4.3; external S* order. */
+igb_status igb_apply_Tt(const igb_operator *op, const void *w_dev, void *xs_dev);
+igb_status igb_apply_T(const igb_operator *op, const void *ys_dev, void *y_dev);
+
+/* Jacobi diagonal D_i = t_i^T A t_i, t_i = T^T e_i (far-field terms included): n_dof values. */
+igb_status igb_jacobi_diag(const igb_operator *op, void *d_dev);
+
+/* Solves T A T^T w = b (Sec. 4.3) with Jacobi-preconditioned CG (Laplace) or
+ * restarted GMRES (Helmholtz) (Sec. 4 item 3).  w_dev holds the initial guess
+ * on entry and the density coefficients on exit.  Stops when the true relative
+ * residual ||b - A w|| <= rel_tol ||b|| or after max_iter operator
+ * applications (then IGB_ENOT_CONVERGED, w = last iterate).  `restart` is the
+ * GMRES cycle length (ignored by CG).  Synchronous; `info` (host) may be NULL. */
+igb_status igb_solve(const igb_operator *op, const void *b_dev, void *w_dev, double rel_tol, int32_t max_iter,
+                     int32_t restart, igb_solve_info *info);
+
+/* Potential u(x) = (V~ mu_h)(x) for x off Gamma (Sec. 3.1, eq. eq::repform),
+ * mu_h the density with S coefficients w_dev; Gauss order gauss_rhs per
+ * element.  xyz_dev: n_pts x 3 doubles; u_dev: n_pts values. */
+igb_status igb_potential(const igb_operator *op, const void *w_dev, int64_t n_pts, const double *xyz_dev,
+                         void *u_dev);
+
+/* Host-only planning: the cluster tree, block partition (Sec. 4.1, Sec. 4.2
+ * Def.) and near-field element-pair classification that igb_operator_create
+ * would build for the same geometry and parameters, without any GPU work.
+ * Same errors as igb_operator_create's parameter checks. */
+typedef struct igb_plan igb_plan;
+igb_status igb_plan_create(const igb_geometry *geo, const igb_params *prm, igb_plan **out);
+void igb_plan_destroy(igb_plan *plan);
+/* sizes (device byte counts are those the operator would allocate) */
+igb_status igb_plan_info(const igb_plan *plan, igb_info *out);
+/* same layouts as igb_export_partition / igb_export_pair_classes */
+igb_status igb_plan_export_partition(const igb_plan *plan, int32_t *near_host, int32_t *far_host);
+igb_status igb_plan_export_pair_classes(const igb_plan *plan, int32_t *pairs_host);
+
+/* Diagnostics for parity checks (host outputs, synchronous). */
+/* near_host: n_near_blocks x 2 (target leaf, source leaf), far_host:
+ * n_far_blocks x 3 (level, target, source); both sorted lexicographically. */
+igb_status igb_export_partition(const igb_operator *op, int32_t *near_host, int32_t *far_host);
+/* element-pair classes of the near field: for each of n_pairs_total computed
+ * pairs (E <= F), 4 int32: E, F, class (0 regular, 1 identical, 2 edge,
+ * 3 vertex), Gauss order. Sorted by (E, F). */
+igb_status igb_export_pair_classes(const igb_operator *op, int32_t *pairs_host);
+/* the stored near-field block of elements (E, F) (row = E's functions): nloc^2 values */
+igb_status igb_export_near_block(const igb_operator *op, int32_t E, int32_t F, double *blk_host);
+/* the stored coupling block of a far pair, q^2 x q^2 row-major (row = target node) */
+igb_status igb_export_coupling_block(const igb_operator *op, int32_t level, int32_t tgt, int32_t src,
+                                     double *blk_host);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* IGABEM_H */

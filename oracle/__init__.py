@@ -75,6 +75,8 @@ def _load():
     lib.or_solve.restype = C.c_int
     lib.or_solve.argtypes = [P, dp, dp, dp, C.c_double, C.c_int, C.c_int, ip, dp]
     lib.or_potential.argtypes = [P, dp, C.c_int64, dp, dp]
+    lib.or_near_pair_classes.restype = C.c_int64
+    lib.or_near_pair_classes.argtypes = [P, ip]
     lib.or_gauss.restype = C.c_int
     lib.or_gauss.argtypes = [C.c_int, dp, dp]
     lib.or_num_threads.restype = C.c_int
@@ -180,6 +182,14 @@ class Problem:
     def pair_class(self, E: int, F: int):
         out = np.zeros(8, dtype=np.int32)
         _load().or_pair_class(self._h, int(E), int(F), _i(out))
+        return out
+
+    def near_pair_classes(self):
+        """(n, 4) int32 rows (E, F, class, order) of the near-field pairs E <= F, sorted."""
+        lib = _load()
+        n = int(lib.or_near_pair_classes(self._h, None))
+        out = np.zeros((n, 4), dtype=np.int32)
+        lib.or_near_pair_classes(self._h, _i(out))
         return out
 
     def pair_block(self, E: int, F: int, symmetric=True):

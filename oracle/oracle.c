@@ -1651,3 +1651,41 @@ int or_num_threads(void)
     return 1;
 #endif
 }
+
+/* All computed near-field element pairs (E <= F) with their classification:  */
+/* rows (E, F, class, order), sorted by (E, F).  Returns the count; writes    */
+/* when out != NULL.                                                           */
+static int cmp_int4(const void *x, const void *y)
+{
+    const int32_t *a = (const int32_t *)x, *b = (const int32_t *)y;
+    if (a[0] != b[0]) return a[0] < b[0] ? -1 : 1;
+    if (a[1] != b[1]) return a[1] < b[1] ? -1 : 1;
+    return 0;
+}
+
+int64_t or_near_pair_classes(or_problem *P, int32_t *out)
+{
+    build_near_csr(P);
+    int64_t cnt = 0;
+    for (int E = 0; E < P->nelem; ++E)
+        for (int64_t k = P->nb_ptr[E]; k < P->nb_ptr[E + 1]; ++k)
+            if (P->nb_idx[k] >= E) ++cnt;
+    if (!out) return cnt;
+    int64_t t = 0;
+    for (int E = 0; E < P->nelem; ++E)
+        for (int64_t k = P->nb_ptr[E]; k < P->nb_ptr[E + 1]; ++k) {
+            int F = P->nb_idx[k];
+            if (F < E) continue;
+            out[4 * t] = E;
+            out[4 * t + 1] = F;
+            t++;
+        }
+#pragma omp parallel for schedule(dynamic, 256)
+    for (int64_t i = 0; i < cnt; ++i) {
+        pair_info pi = classify(P, out[4 * i], out[4 * i + 1]);
+        out[4 * i + 2] = pi.cls;
+        out[4 * i + 3] = pi.order;
+    }
+    qsort(out, cnt, 4 * sizeof(int32_t), cmp_int4);
+    return cnt;
+}

@@ -1,0 +1,1864 @@
+// libigabem: HIP kernels and C-ABI entry points for the isogeometric
+// single-layer BEM with nested-basis (H2) interpolation compression.
+// Target: gfx950 (MI355X), FP64 throughout.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "kernels.h"
+#include "setup.h"
+
+using namespace igb;
+
+static thread_local std::string g_err;
+
+static igb_status fail(igb_status s, const std::string &m)
+{
+    g_err = m;
+    return s;
+}
+
+#define HIPCHK(x)                                                                                  \
+    do {                                                                                           \
+        hipError_t e_ = (x);                                                                       \
+        if (e_ != hipSuccess)                                                                      \
+            return fail(e_ == hipErrorOutOfMemory ? IGB_ENOMEM : IGB_EHIP,                         \
+                        std::string(#x) + ": " + hipGetErrorString(e_));                           \
+    } while (0)
+
+#define LAUNCHCHK()                                                                                \
+    do {                                                                                           \
+        hipError_t e_ = hipGetLastError();                                                         \
+        if (e_ != hipSuccess) return fail(IGB_EHIP, std::string("kernel launch: ") + hipGetErrorString(e_)); \
+    } while (0)
+
+struct igb_geometry {
+    Geometry g;
+};
+
+// ===========================================================================
+// kernels: geometry
+// ===========================================================================
+
+// Geometry at the tensor Gauss nodes of order g of every element:
+// out[(E*g*g + j*g + i)*4 + {0,1,2,3}] = x, y, z, kappa_local * w_i * w_j.
+__global__ void k_gauss_geom(int nelem, int stride, const double *__restrict__ tiles, const int32_t *__restrict__ tdeg,
+                             int g, const double *__restrict__ x, const double *__restrict__ w, double *__restrict__ out)
+{
+    int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int gg = g * g;
+    if (idx >= (int64_t)nelem * gg) return;
+    int E = (int)(idx / gg), k = (int)(idx % gg), j = k / g, i = k % g;
+    double X[3], kap;
+    tile_point(tiles + (size_t)E * stride, tdeg[2 * E], tdeg[2 * E + 1], x[i], x[j], X, &kap);
+    out[idx * 4 + 0] = X[0];
+    out[idx * 4 + 1] = X[1];
+    out[idx * 4 + 2] = X[2];
+    out[idx * 4 + 3] = kap * w[i] * w[j];
+}
+
+// Chebyshev-node geometry of every cluster (all levels): point and surface
+// measure times the affine Jacobian 4^-l of the cluster map,
+// nodes[(gc*q2 + mu)*4 + c], mu = mu2*q + mu1.
+__global__ void k_cluster_nodes(int64_t ncl_all, int L, const int64_t *__restrict__ cl_off, int q, int m, int ne,
+                                const double *__restrict__ z, int stride, const double *__restrict__ tiles,
+                                const int32_t *__restrict__ tdeg, double *__restrict__ nodes)
+{
+    int q2 = q * q;
+    int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= ncl_all * q2) return;
+    int64_t gc = idx / q2;
+    int mu = (int)(idx % q2), mu2 = mu / q, mu1 = mu % q;
+    int l = 0;
+    while (l < L && gc >= cl_off[l + 1]) ++l;
+    int id = (int)(gc - cl_off[l]);
+    int n = 1 << l;
+    int patch = id / (n * n), r = id % (n * n), k2 = r / n, k1 = r % n;
+    double a = (k1 + z[mu1]) * (double)(ne >> l), b = (k2 + z[mu2]) * (double)(ne >> l);
+    int e1 = (int)floor(a), e2 = (int)floor(b);
+    e1 = e1 < 0 ? 0 : (e1 > ne - 1 ? ne - 1 : e1);
+    e2 = e2 < 0 ? 0 : (e2 > ne - 1 ? ne - 1 : e2);
+    int E = patch * ne * ne + e2 * ne + e1;
+    double X[3], kap;
+    tile_point(tiles + (size_t)E * stride, tdeg[2 * E], tdeg[2 * E + 1], a - e1, b - e2, X, &kap);
+    // kappa_patch = kappa_local * ne^2; times 4^-l  ->  kappa_local * 4^(m-l)
+    double sc = (double)(1LL << (2 * (m - l)));
+    nodes[idx * 4 + 0] = X[0];
+    nodes[idx * 4 + 1] = X[1];
+    nodes[idx * 4 + 2] = X[2];
+    nodes[idx * 4 + 3] = kap * sc;
+}
+
+// ===========================================================================
+// kernels: near-field quadrature
+// ===========================================================================
+
+// Position of entry (row a of element elE, column b of element elF) in a
+// column-major leaf block of nl x nl.
+__device__ inline int64_t blk_pos(int nl, int nloc, int elE, int a, int elF, int b)
+{
+    return (int64_t)(elF * nloc + b) * nl + elE * nloc + a;
+}
+
+// Well separated pairs: tensor Gauss of order g in all four variables.
+// One workgroup per pair; kernel rows K(x_i, .) are formed by thread i and
+// contracted with the Bernstein values of F, then with those of E.
+template <class T, int P>
+__global__ void __launch_bounds__(128) k_near_regular(const PairRec *__restrict__ pairs, int npairs, int g,
+                                                      const double *__restrict__ gp, const double *__restrict__ btab,
+                                                      double kappa, int nl, T *__restrict__ blocks)
+{
+    constexpr int P1 = P + 1, NLOC = P1 * P1;
+    extern __shared__ double sh[];
+    int gg = g * g;
+    double *X = sh;                        // gg*4
+    double *Y = X + gg * 4;                // gg*4
+    double *psi = Y + gg * 4;              // gg*NLOC
+    T *tmp = (T *)(psi + (size_t)gg * NLOC);  // gg*NLOC
+    PairRec R = pairs[blockIdx.x];
+    const double *gE = gp + (size_t)R.E * gg * 4, *gF = gp + (size_t)R.F * gg * 4;
+    for (int k = threadIdx.x; k < gg * 4; k += blockDim.x) {
+        X[k] = gE[k];
+        Y[k] = gF[k];
+    }
+    for (int k = threadIdx.x; k < gg * NLOC; k += blockDim.x) {
+        int j = k / NLOC, b = k % NLOC;
+        int j2 = j / g, j1 = j % g, b2 = b / P1, b1 = b % P1;
+        psi[k] = btab[j1 * P1 + b1] * btab[j2 * P1 + b2];
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < gg; i += blockDim.x) {
+        T acc[NLOC];
+#pragma unroll
+        for (int b = 0; b < NLOC; ++b) acc[b] = zero<T>();
+        double x0 = X[4 * i], x1 = X[4 * i + 1], x2 = X[4 * i + 2];
+        for (int j = 0; j < gg; ++j) {
+            double d0 = x0 - Y[4 * j], d1 = x1 - Y[4 * j + 1], d2 = x2 - Y[4 * j + 2];
+            double r = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+            T k = green<T>(r, kappa) * Y[4 * j + 3];
+            const double *ps = psi + j * NLOC;
+#pragma unroll
+            for (int b = 0; b < NLOC; ++b) acc[b] += k * ps[b];
+        }
+        double kw = X[4 * i + 3];
+#pragma unroll
+        for (int b = 0; b < NLOC; ++b) tmp[i * NLOC + b] = acc[b] * kw;
+    }
+    __syncthreads();
+    T *out1 = blocks + (int64_t)R.blk1 * nl * nl;
+    T *out2 = R.blk2 >= 0 ? blocks + (int64_t)R.blk2 * nl * nl : nullptr;
+    for (int o = threadIdx.x; o < NLOC * NLOC; o += blockDim.x) {
+        int a = o / NLOC, b = o % NLOC;
+        T s = zero<T>();
+        for (int i = 0; i < gg; ++i) s += psi[i * NLOC + a] * tmp[i * NLOC + b];
+        out1[blk_pos(nl, NLOC, R.elE, a, R.elF, b)] = s;
+        if (out2) out2[blk_pos(nl, NLOC, R.elF, b, R.elE, a)] = s;
+    }
+}
+
+__device__ inline void frame_map(int o, int a, int b, double s, double t, double &x, double &y)
+{
+    const double cx[4] = {0.0, 1.0, 1.0, 0.0}, cy[4] = {0.0, 0.0, 1.0, 1.0};
+    x = cx[o] + s * (cx[a] - cx[o]) + t * (cx[b] - cx[o]);
+    y = cy[o] + s * (cy[a] - cy[o]) + t * (cy[b] - cy[o]);
+}
+
+// Touching pairs (identical / common edge / common vertex): regularising
+// Duffy-type substitutions of [0,1]^4 (8 / 6 / 4 regions), Gauss of order gs
+// per variable.  One workgroup of 256 threads per pair; each thread forms the
+// weighted kernel value of one quadrature point and the Bernstein vectors of
+// both points, a batch is staged in LDS and reduced into the nloc x nloc block.
+template <class T, int P, int BATCH>
+__global__ void __launch_bounds__(256) k_near_singular(const PairRec *__restrict__ pairs, int npairs, int gs,
+                                                       const double *__restrict__ gxs, const double *__restrict__ gws,
+                                                       const double *__restrict__ tiles,
+                                                       const int32_t *__restrict__ tdeg, int stride, double kappa,
+                                                       int nl, T *__restrict__ blocks)
+{
+    constexpr int P1 = P + 1, NLOC = P1 * P1, NOUT = NLOC * NLOC;
+    constexpr int NACC = (NOUT + 255) / 256;
+    extern __shared__ double sh[];
+    double *tE = sh;                       // stride
+    double *tF = tE + stride;              // stride
+    double *nx = tF + stride;              // gs
+    double *nw = nx + 64;                  // gs
+    T *U = (T *)(nw + 64);                 // BATCH*NLOC
+    double *V = (double *)(U + BATCH * NLOC);  // BATCH*NLOC
+    PairRec R = pairs[blockIdx.x];
+    for (int k = threadIdx.x; k < stride; k += blockDim.x) {
+        tE[k] = tiles[(size_t)R.E * stride + k];
+        tF[k] = tiles[(size_t)R.F * stride + k];
+    }
+    for (int k = threadIdx.x; k < gs; k += blockDim.x) {
+        nx[k] = gxs[k];
+        nw[k] = gws[k];
+    }
+    int puE = tdeg[2 * R.E], pvE = tdeg[2 * R.E + 1], puF = tdeg[2 * R.F], pvF = tdeg[2 * R.F + 1];
+    __syncthreads();
+    int g2 = gs * gs, g4 = g2 * g2;
+    int nreg = R.cls == 1 ? 8 : (R.cls == 2 ? 6 : 4);
+    int npts = nreg * g4;
+    T acc[NACC];
+#pragma unroll
+    for (int k = 0; k < NACC; ++k) acc[k] = zero<T>();
+    for (int base = 0; base < npts; base += BATCH) {
+        for (int t = threadIdx.x; t < BATCH; t += blockDim.x) {
+            int idx = base + t;
+            T *u = U + t * NLOC;
+            double *v = V + t * NLOC;
+            if (idx >= npts) {
+#pragma unroll
+                for (int a = 0; a < NLOC; ++a) { u[a] = zero<T>(); v[a] = 0.0; }
+                continue;
+            }
+            int reg = idx / g4, rem = idx % g4;
+            int ia = rem / (g2 * gs), ib = (rem / g2) % gs, ic = (rem / gs) % gs, id = rem % gs;
+            double va = nx[ia], vb = nx[ib], vc = nx[ic], vd = nx[id];
+            double W = nw[ia] * nw[ib] * nw[ic] * nw[id];
+            double xs, xt, ys, yt;  // element-local coordinates of x (in E) and y (in F)
+            if (R.cls == 1) {
+                int sg1 = reg & 1, sg2 = (reg >> 1) & 1, tri = reg >> 2;
+                double xi = va, eta = vb;
+                double z1 = tri == 0 ? xi : xi * eta, z2 = tri == 0 ? xi * eta : xi;
+                if (sg1 == 0) { xs = (1 - z1) * vc; ys = xs + z1; } else { ys = (1 - z1) * vc; xs = ys + z1; }
+                if (sg2 == 0) { xt = (1 - z2) * vd; yt = xt + z2; } else { yt = (1 - z2) * vd; xt = yt + z2; }
+                W *= xi * (1 - z1) * (1 - z2);
+            } else if (R.cls == 2) {
+                int sg = reg & 1, pyr = reg >> 1;
+                double xi = va, e1 = vb, e2 = vc, s = vd;
+                double zz, ct, dt;
+                if (pyr == 0) { zz = xi; ct = xi * e1; dt = xi * e2; }
+                else if (pyr == 1) { ct = xi; zz = xi * e1; dt = xi * e2; }
+                else { dt = xi; zz = xi * e1; ct = xi * e2; }
+                double cs, ds;
+                if (sg == 0) { cs = (1 - zz) * s; ds = cs + zz; } else { ds = (1 - zz) * s; cs = ds + zz; }
+                W *= xi * xi * (1 - zz);
+                frame_map(R.oE, R.aE, R.bE, cs, ct, xs, xt);
+                frame_map(R.oF, R.aF, R.bF, ds, dt, ys, yt);
+            } else {
+                double xi = va, v4[4];
+                double e[3] = {vb, vc, vd};
+                int k = 0;
+                for (int q = 0; q < 4; ++q) v4[q] = (q == reg) ? xi : xi * e[k++];
+                W *= xi * xi * xi;
+                frame_map(R.oE, R.aE, R.bE, v4[0], v4[1], xs, xt);
+                frame_map(R.oF, R.aF, R.bF, v4[2], v4[3], ys, yt);
+            }
+            double X[3], Yp[3], kx, ky;
+            tile_point(tE, puE, pvE, xs, xt, X, &kx);
+            tile_point(tF, puF, pvF, ys, yt, Yp, &ky);
+            double d0 = X[0] - Yp[0], d1 = X[1] - Yp[1], d2 = X[2] - Yp[2];
+            double r = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+            T c = green<T>(r, kappa) * (W * kx * ky);
+            double bx1[P1], bx2[P1], by1[P1], by2[P1];
+            bernstein(P, xs, bx1);
+            bernstein(P, xt, bx2);
+            bernstein(P, ys, by1);
+            bernstein(P, yt, by2);
+#pragma unroll
+            for (int a2 = 0; a2 < P1; ++a2)
+#pragma unroll
+                for (int a1 = 0; a1 < P1; ++a1) {
+                    u[a2 * P1 + a1] = c * (bx1[a1] * bx2[a2]);
+                    v[a2 * P1 + a1] = by1[a1] * by2[a2];
+                }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < NACC; ++k) {
+            int o = threadIdx.x + 256 * k;
+            if (o < NOUT) {
+                int a = o / NLOC, b = o % NLOC;
+                T s = acc[k];
+                for (int t = 0; t < BATCH; ++t) s += U[t * NLOC + a] * V[t * NLOC + b];
+                acc[k] = s;
+            }
+        }
+        __syncthreads();
+    }
+    // write (identical blocks symmetrised as (B + B^T)/2)
+    T *full = U;  // reuse LDS: NOUT entries fit (BATCH >= NLOC)
+#pragma unroll
+    for (int k = 0; k < NACC; ++k) {
+        int o = threadIdx.x + 256 * k;
+        if (o < NOUT) full[o] = acc[k];
+    }
+    __syncthreads();
+    T *out1 = blocks + (int64_t)R.blk1 * nl * nl;
+    T *out2 = R.blk2 >= 0 ? blocks + (int64_t)R.blk2 * nl * nl : nullptr;
+    for (int o = threadIdx.x; o < NOUT; o += blockDim.x) {
+        int a = o / NLOC, b = o % NLOC;
+        T s = full[o];
+        if (R.cls == 1) s = 0.5 * (full[a * NLOC + b] + full[b * NLOC + a]);
+        out1[blk_pos(nl, NLOC, R.elE, a, R.elF, b)] = s;
+        if (out2) out2[blk_pos(nl, NLOC, R.elF, b, R.elE, a)] = s;
+    }
+}
+
+// ===========================================================================
+// kernels: far field
+// ===========================================================================
+
+// Coupling block of every admissible pair: the localised kernel at the
+// Chebyshev node pairs (Sec. 4.2), stored column-major (col = source node).
+template <class T>
+__global__ void __launch_bounds__(256) k_coupling(int64_t nfar, const int32_t *__restrict__ far_tgt,
+                                                  const int32_t *__restrict__ far_src, int q2,
+                                                  const double *__restrict__ nodes, double kappa, T *__restrict__ coup)
+{
+    int64_t k = blockIdx.x;
+    int tg = far_tgt[k], sc = far_src[k];
+    const double *xt = nodes + (size_t)tg * q2 * 4, *xsrc = nodes + (size_t)sc * q2 * 4;
+    T *out = coup + k * q2 * q2;
+    for (int idx = threadIdx.x; idx < q2 * q2; idx += blockDim.x) {
+        int nu = idx / q2, mu = idx % q2;
+        double d0 = xt[4 * mu] - xsrc[4 * nu], d1 = xt[4 * mu + 1] - xsrc[4 * nu + 1], d2 = xt[4 * mu + 2] - xsrc[4 * nu + 2];
+        double r = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+        out[idx] = green<T>(r, kappa) * (xt[4 * mu + 3] * xsrc[4 * nu + 3]);
+    }
+}
+
+// Leaf moments X^ = M1^T X M1 (X the leaf's coefficients as an n1 x n1 array).
+template <class T>
+__global__ void k_leaf_moments(int n1, int q, int side, int P1, int nloc, int nl, const double *__restrict__ M1,
+                               const T *__restrict__ xs, T *__restrict__ Xh)
+{
+    extern __shared__ double sh[];
+    T *X = (T *)sh;        // n1*n1
+    T *Z = X + n1 * n1;    // n1*q
+    int leaf = blockIdx.x;
+    for (int f = threadIdx.x; f < nl; f += blockDim.x) {
+        int el = f / nloc, r = f % nloc;
+        int i1 = (el % side) * P1 + r % P1, i2 = (el / side) * P1 + r / P1;
+        X[i2 * n1 + i1] = xs[(int64_t)leaf * nl + f];
+    }
+    __syncthreads();
+    for (int o = threadIdx.x; o < n1 * q; o += blockDim.x) {
+        int i2 = o / q, mu1 = o % q;
+        T s = zero<T>();
+        for (int i1 = 0; i1 < n1; ++i1) s += M1[i1 * q + mu1] * X[i2 * n1 + i1];
+        Z[o] = s;
+    }
+    __syncthreads();
+    for (int o = threadIdx.x; o < q * q; o += blockDim.x) {
+        int mu2 = o / q, mu1 = o % q;
+        T s = zero<T>();
+        for (int i2 = 0; i2 < n1; ++i2) s += M1[i2 * q + mu2] * Z[i2 * q + mu1];
+        Xh[(int64_t)leaf * q * q + o] = s;
+    }
+}
+
+// Upward pass, one level: X^_P = 1/4 sum_c (E_c1 (x) E_c2)^T X^_c (nested bases).
+template <class T>
+__global__ void k_upward(int l, int q, const double *__restrict__ E2, const T *__restrict__ Xc_lvl, T *__restrict__ Xp_lvl)
+{
+    extern __shared__ double sh[];
+    int q2 = q * q;
+    T *Xc = (T *)sh;   // q2
+    T *Z = Xc + q2;    // q2
+    int n = 1 << l, nn = 2 * n;
+    int pid = blockIdx.x;
+    int patch = pid / (n * n), r = pid % (n * n), k2 = r / n, k1 = r % n;
+    T acc[4];
+    for (int k = 0; k < 4; ++k) acc[k] = zero<T>();
+    for (int c2 = 0; c2 < 2; ++c2)
+        for (int c1 = 0; c1 < 2; ++c1) {
+            int cid = patch * nn * nn + (2 * k2 + c2) * nn + 2 * k1 + c1;
+            for (int o = threadIdx.x; o < q2; o += blockDim.x) Xc[o] = Xc_lvl[(int64_t)cid * q2 + o];
+            __syncthreads();
+            const double *Ec1 = E2 + c1 * q2, *Ec2 = E2 + c2 * q2;
+            for (int o = threadIdx.x; o < q2; o += blockDim.x) {
+                int nu2 = o / q, mu1 = o % q;
+                T s = zero<T>();
+                for (int nu1 = 0; nu1 < q; ++nu1) s += Ec1[nu1 * q + mu1] * Xc[nu2 * q + nu1];
+                Z[o] = s;
+            }
+            __syncthreads();
+            for (int k = 0, o = threadIdx.x; o < q2; o += blockDim.x, ++k) {
+                int mu2 = o / q, mu1 = o % q;
+                T s = zero<T>();
+                for (int nu2 = 0; nu2 < q; ++nu2) s += Ec2[nu2 * q + mu2] * Z[nu2 * q + mu1];
+                acc[k] += s;
+            }
+            __syncthreads();
+        }
+    for (int k = 0, o = threadIdx.x; o < q2; o += blockDim.x, ++k) Xp_lvl[(int64_t)pid * q2 + o] = 0.25 * acc[k];
+}
+
+// Downward pass, one level: Y^_c += 1/4 (E_c1 (x) E_c2) Y^_P.
+template <class T>
+__global__ void k_downward(int lc, int q, const double *__restrict__ E2, const T *__restrict__ Yp_lvl, T *__restrict__ Yc_lvl)
+{
+    extern __shared__ double sh[];
+    int q2 = q * q;
+    T *Yp = (T *)sh;
+    T *Z = Yp + q2;
+    int n = 1 << lc, np = n / 2;
+    int cid = blockIdx.x;
+    int patch = cid / (n * n), r = cid % (n * n), k2 = r / n, k1 = r % n;
+    int pid = patch * np * np + (k2 >> 1) * np + (k1 >> 1);
+    int c1 = k1 & 1, c2 = k2 & 1;
+    for (int o = threadIdx.x; o < q2; o += blockDim.x) Yp[o] = Yp_lvl[(int64_t)pid * q2 + o];
+    __syncthreads();
+    const double *Ec1 = E2 + c1 * q2, *Ec2 = E2 + c2 * q2;
+    for (int o = threadIdx.x; o < q2; o += blockDim.x) {
+        int mu2 = o / q, nu1 = o % q;
+        T s = zero<T>();
+        for (int mu1 = 0; mu1 < q; ++mu1) s += Ec1[nu1 * q + mu1] * Yp[mu2 * q + mu1];
+        Z[o] = s;
+    }
+    __syncthreads();
+    for (int o = threadIdx.x; o < q2; o += blockDim.x) {
+        int nu2 = o / q, nu1 = o % q;
+        T s = zero<T>();
+        for (int mu2 = 0; mu2 < q; ++mu2) s += Ec2[nu2 * q + mu2] * Z[mu2 * q + nu1];
+        Yc_lvl[(int64_t)cid * q2 + o] += 0.25 * s;
+    }
+}
+
+// Leaf back-moments: y* += M1 Y^ M1^T.
+template <class T>
+__global__ void k_leaf_back(int n1, int q, int side, int P1, int nloc, int nl, const double *__restrict__ M1,
+                            const T *__restrict__ Yh, T *__restrict__ ys)
+{
+    extern __shared__ double sh[];
+    int q2 = q * q;
+    T *Y = (T *)sh;   // q2
+    T *Z = Y + q2;    // q*n1
+    int leaf = blockIdx.x;
+    for (int o = threadIdx.x; o < q2; o += blockDim.x) Y[o] = Yh[(int64_t)leaf * q2 + o];
+    __syncthreads();
+    for (int o = threadIdx.x; o < q * n1; o += blockDim.x) {
+        int mu2 = o / n1, i1 = o % n1;
+        T s = zero<T>();
+        for (int mu1 = 0; mu1 < q; ++mu1) s += M1[i1 * q + mu1] * Y[mu2 * q + mu1];
+        Z[o] = s;
+    }
+    __syncthreads();
+    for (int f = threadIdx.x; f < nl; f += blockDim.x) {
+        int el = f / nloc, r = f % nloc;
+        int i1 = (el % side) * P1 + r % P1, i2 = (el / side) * P1 + r / P1;
+        T s = zero<T>();
+        for (int mu2 = 0; mu2 < q; ++mu2) s += M1[i2 * q + mu2] * Z[mu2 * n1 + i1];
+        ys[(int64_t)leaf * nl + f] += s;
+    }
+}
+
+// Block-sparse matrix-vector product y_t = sum_k B_k x_src(k) over a CSR of
+// column-major nb x nb blocks (near field: leaf blocks; far field: coupling
+// blocks over all levels).  One workgroup per target row, waves split the
+// row's blocks, lanes own block rows; the block stream is read once,
+// coalesced.
+template <class T>
+__global__ void __launch_bounds__(256) k_bsr_gemv(int nb, const int64_t *__restrict__ ptr, const int32_t *__restrict__ src,
+                                                  const T *__restrict__ blocks, const T *__restrict__ x, T *__restrict__ y,
+                                                  int64_t row0)
+{
+    extern __shared__ double sh[];
+    T *part = (T *)sh;  // nw * nb
+    int64_t t = row0 + blockIdx.x;
+    int64_t k0 = ptr[t], k1 = ptr[t + 1];
+    int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    int nw = blockDim.x >> 6;
+    for (int a0 = 0; a0 < nb; a0 += 64) {
+        int a = a0 + lane;
+        T acc = zero<T>();
+        if (a < nb) {
+            for (int64_t k = k0 + wave; k < k1; k += nw) {
+                const T *B = blocks + k * (int64_t)nb * nb + a;
+                const T *xs = x + (int64_t)src[k] * nb;
+                int b = 0;
+                for (; b + 4 <= nb; b += 4) {
+                    T v0 = B[(int64_t)b * nb], v1 = B[(int64_t)(b + 1) * nb], v2 = B[(int64_t)(b + 2) * nb],
+                      v3 = B[(int64_t)(b + 3) * nb];
+                    acc += v0 * xs[b];
+                    acc += v1 * xs[b + 1];
+                    acc += v2 * xs[b + 2];
+                    acc += v3 * xs[b + 3];
+                }
+                for (; b < nb; ++b) acc += B[(int64_t)b * nb] * xs[b];
+            }
+            part[wave * nb + a] = acc;
+        }
+    }
+    __syncthreads();
+    for (int a = threadIdx.x; a < nb; a += blockDim.x) {
+        T s = part[a];
+        for (int w = 1; w < nw; ++w) s += part[w * nb + a];
+        y[t * nb + a] = s;
+    }
+}
+
+// ===========================================================================
+// kernels: S <-> S* (Sec. 4.3) and order permutations
+// ===========================================================================
+
+struct Layout {
+    int p, P1, nloc, nl, side, L, ne, ns1;
+};
+
+// internal S* index -> (patch, e1, e2, r1, r2)
+__device__ inline void decode_internal(const Layout &lo, int64_t a, int &patch, int &e1, int &e2, int &r1, int &r2)
+{
+    int64_t leaf = a / lo.nl;
+    int f = (int)(a % lo.nl);
+    int el = f / lo.nloc, r = f % lo.nloc;
+    int nL = 1 << lo.L;
+    patch = (int)(leaf / (nL * nL));
+    int rl = (int)(leaf % (nL * nL));
+    int k2 = rl / nL, k1 = rl % nL;
+    e1 = k1 * lo.side + el % lo.side;
+    e2 = k2 * lo.side + el / lo.side;
+    r1 = r % lo.P1;
+    r2 = r / lo.P1;
+}
+
+__device__ inline int64_t encode_internal(const Layout &lo, int patch, int e1, int e2, int r1, int r2)
+{
+    int nL = 1 << lo.L;
+    int64_t leaf = (int64_t)patch * nL * nL + (e2 / lo.side) * nL + e1 / lo.side;
+    int el = (e2 % lo.side) * lo.side + e1 % lo.side;
+    return leaf * lo.nl + el * lo.nloc + r2 * lo.P1 + r1;
+}
+
+template <class T>
+__global__ void k_Tt(Layout lo, int64_t nsup, const double *__restrict__ Tb, const T *__restrict__ w, T *__restrict__ xs)
+{
+    int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (a >= nsup) return;
+    int patch, e1, e2, r1, r2;
+    decode_internal(lo, a, patch, e1, e2, r1, r2);
+    const double *t1 = Tb + (e1 * lo.P1 + r1) * lo.P1, *t2 = Tb + (e2 * lo.P1 + r2) * lo.P1;
+    const T *wp = w + (int64_t)patch * lo.ns1 * lo.ns1;
+    T s = zero<T>();
+    for (int j2 = 0; j2 < lo.P1; ++j2)
+        for (int j1 = 0; j1 < lo.P1; ++j1) s += (t1[j1] * t2[j2]) * wp[(e2 + j2) * lo.ns1 + e1 + j1];
+    xs[a] = s;
+}
+
+template <class T>
+__global__ void k_T(Layout lo, int64_t ndof, const double *__restrict__ Tb, const T *__restrict__ ys, T *__restrict__ y)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= ndof) return;
+    int nn = lo.ns1 * lo.ns1;
+    int patch = (int)(i / nn), r = (int)(i % nn), j2 = r / lo.ns1, j1 = r % lo.ns1;
+    T s = zero<T>();
+    int lo1 = j1 - lo.p < 0 ? 0 : j1 - lo.p, hi1 = j1 < lo.ne - 1 ? j1 : lo.ne - 1;
+    int lo2 = j2 - lo.p < 0 ? 0 : j2 - lo.p, hi2 = j2 < lo.ne - 1 ? j2 : lo.ne - 1;
+    for (int e2 = lo2; e2 <= hi2; ++e2)
+        for (int e1 = lo1; e1 <= hi1; ++e1)
+            for (int r2 = 0; r2 < lo.P1; ++r2)
+                for (int r1 = 0; r1 < lo.P1; ++r1) {
+                    double t = Tb[(e1 * lo.P1 + r1) * lo.P1 + (j1 - e1)] * Tb[(e2 * lo.P1 + r2) * lo.P1 + (j2 - e2)];
+                    s += t * ys[encode_internal(lo, patch, e1, e2, r1, r2)];
+                }
+    y[i] = s;
+}
+
+// external S* order (element-major) <-> internal (leaf-major)
+template <class T>
+__global__ void k_perm(Layout lo, int64_t nsup, const T *__restrict__ in, T *__restrict__ out, int to_internal)
+{
+    int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (a >= nsup) return;
+    int patch, e1, e2, r1, r2;
+    decode_internal(lo, a, patch, e1, e2, r1, r2);
+    int64_t ext = ((int64_t)patch * lo.ne * lo.ne + (int64_t)e2 * lo.ne + e1) * lo.nloc + r2 * lo.P1 + r1;
+    if (to_internal) out[a] = in[ext];
+    else out[ext] = in[a];
+}
+
+// ===========================================================================
+// kernels: right-hand side and potential
+// ===========================================================================
+
+__global__ void k_rhs_points(int64_t n, const double *__restrict__ rp, double *__restrict__ xyz)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    xyz[3 * i] = rp[4 * i];
+    xyz[3 * i + 1] = rp[4 * i + 1];
+    xyz[3 * i + 2] = rp[4 * i + 2];
+}
+
+// g*_a = sum_q g(x_q) kappa w_q phi_a(x_q) on the element of a (internal order)
+template <class T>
+__global__ void k_rhs_super(Layout lo, int64_t nsup, int g, const double *__restrict__ gxr, const double *__restrict__ rp,
+                            const T *__restrict__ gv, T *__restrict__ gs)
+{
+    int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (a >= nsup) return;
+    int patch, e1, e2, r1, r2;
+    decode_internal(lo, a, patch, e1, e2, r1, r2);
+    int64_t E = (int64_t)patch * lo.ne * lo.ne + (int64_t)e2 * lo.ne + e1;
+    T s = zero<T>();
+    double B[9];
+    for (int j = 0; j < g; ++j) {
+        bernstein(lo.p, gxr[j], B);
+        double b2 = B[r2];
+        for (int i = 0; i < g; ++i) {
+            bernstein(lo.p, gxr[i], B);
+            int64_t k = E * g * g + j * g + i;
+            s += gv[k] * (rp[4 * k + 3] * B[r1] * b2);
+        }
+    }
+    gs[a] = s;
+}
+
+// per quadrature point of the potential: c_q = mu_h(y_q) kappa w_q
+template <class T>
+__global__ void k_pot_prep(Layout lo, int nelem, int g, const double *__restrict__ gxr, const double *__restrict__ rp,
+                           const T *__restrict__ xs, T *__restrict__ c)
+{
+    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int gg = g * g;
+    if (k >= (int64_t)nelem * gg) return;
+    int E = (int)(k / gg), ij = (int)(k % gg), j = ij / g, i = ij % g;
+    int patch = E / (lo.ne * lo.ne), r = E % (lo.ne * lo.ne), e2 = r / lo.ne, e1 = r % lo.ne;
+    double Bi[9], Bj[9];
+    bernstein(lo.p, gxr[i], Bi);
+    bernstein(lo.p, gxr[j], Bj);
+    T s = zero<T>();
+    for (int r2 = 0; r2 < lo.P1; ++r2)
+        for (int r1 = 0; r1 < lo.P1; ++r1) s += (Bi[r1] * Bj[r2]) * xs[encode_internal(lo, patch, e1, e2, r1, r2)];
+    c[k] = s * rp[4 * k + 3];
+}
+
+// direct sum over source chunks: part[chunk * npts + x] = sum_q c_q G(x, y_q)
+template <class T>
+__global__ void __launch_bounds__(256) k_pot_eval(int64_t npts, const double *__restrict__ X, int64_t nsrc,
+                                                  const double *__restrict__ rp, const T *__restrict__ c, double kappa,
+                                                  int64_t chunk, T *__restrict__ part)
+{
+    __shared__ double sy[256 * 3];
+    __shared__ T sc[256];
+    int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t s0 = (int64_t)blockIdx.y * chunk, s1 = s0 + chunk < nsrc ? s0 + chunk : nsrc;
+    double px = 0, py = 0, pz = 0;
+    if (x < npts) { px = X[3 * x]; py = X[3 * x + 1]; pz = X[3 * x + 2]; }
+    T acc = zero<T>();
+    for (int64_t b = s0; b < s1; b += 256) {
+        int64_t q = b + threadIdx.x;
+        if (q < s1) {
+            sy[3 * threadIdx.x] = rp[4 * q];
+            sy[3 * threadIdx.x + 1] = rp[4 * q + 1];
+            sy[3 * threadIdx.x + 2] = rp[4 * q + 2];
+            sc[threadIdx.x] = c[q];
+        }
+        __syncthreads();
+        int nb = (int)((s1 - b) < 256 ? (s1 - b) : 256);
+        for (int k = 0; k < nb; ++k) {
+            double d0 = px - sy[3 * k], d1 = py - sy[3 * k + 1], d2 = pz - sy[3 * k + 2];
+            acc += green<T>(sqrt(d0 * d0 + d1 * d1 + d2 * d2), kappa) * sc[k];
+        }
+        __syncthreads();
+    }
+    if (x < npts) part[(int64_t)blockIdx.y * npts + x] = acc;
+}
+
+template <class T>
+__global__ void k_pot_reduce(int64_t npts, int nchunk, const T *__restrict__ part, T *__restrict__ u)
+{
+    int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= npts) return;
+    T s = zero<T>();
+    for (int c = 0; c < nchunk; ++c) s += part[(int64_t)c * npts + x];
+    u[x] = s;
+}
+
+// ===========================================================================
+// kernels: Jacobi diagonal D_i = t_i^T A t_i
+// ===========================================================================
+
+__device__ inline int64_t csr_find(const int64_t *ptr, const int32_t *idx, int64_t row, int32_t key)
+{
+    int64_t lo = ptr[row], hi = ptr[row + 1] - 1;
+    while (lo <= hi) {
+        int64_t mid = (lo + hi) >> 1;
+        int32_t v = idx[mid];
+        if (v == key) return mid;
+        if (v < key) lo = mid + 1; else hi = mid - 1;
+    }
+    return -1;
+}
+
+struct DiagArgs {
+    Layout lo;
+    int m, q, lmin;
+    const double *Tb;
+    const double *Mlev;
+    const int64_t *Mlev_off;
+    const int64_t *cl_off;
+    const int64_t *near_ptr;
+    const int32_t *near_src;
+    const int64_t *far_ptr;
+    const int32_t *far_src;
+};
+
+template <class T>
+__global__ void __launch_bounds__(256) k_diag(DiagArgs A, int64_t ndof, const T *__restrict__ nearb,
+                                              const T *__restrict__ coup, T *__restrict__ D)
+{
+    extern __shared__ double sh[];
+    __shared__ T red[256];
+    const Layout &lo = A.lo;
+    int q = A.q, q2 = q * q;
+    int64_t i = blockIdx.x;
+    int nn = lo.ns1 * lo.ns1;
+    int patch = (int)(i / nn), rr = (int)(i % nn), j2 = rr / lo.ns1, j1 = rr % lo.ns1;
+    int lo1 = j1 - lo.p < 0 ? 0 : j1 - lo.p, hi1 = j1 < lo.ne - 1 ? j1 : lo.ne - 1;
+    int lo2 = j2 - lo.p < 0 ? 0 : j2 - lo.p, hi2 = j2 < lo.ne - 1 ? j2 : lo.ne - 1;
+    T acc = zero<T>();
+    double *mv = sh;  // up to (p+2)^2 clusters x q2
+    // far field, level by level
+    for (int l = A.lmin; l <= lo.L; ++l) {
+        int nsub = lo.ne >> l, n = 1 << l;
+        int c1lo = lo1 / nsub, c1hi = hi1 / nsub, c2lo = lo2 / nsub, c2hi = hi2 / nsub;
+        int nc1 = c1hi - c1lo + 1, nc = nc1 * (c2hi - c2lo + 1);
+        const double *Ml = A.Mlev + A.Mlev_off[l];
+        for (int o = threadIdx.x; o < nc * q2; o += blockDim.x) {
+            int c = o / q2, mu = o % q2, mu2 = mu / q, mu1 = mu % q;
+            int cc1 = c1lo + c % nc1, cc2 = c2lo + c / nc1;
+            double s = 0.0;
+            for (int e2 = (lo2 > cc2 * nsub ? lo2 : cc2 * nsub); e2 <= hi2 && e2 < (cc2 + 1) * nsub; ++e2)
+                for (int e1 = (lo1 > cc1 * nsub ? lo1 : cc1 * nsub); e1 <= hi1 && e1 < (cc1 + 1) * nsub; ++e1)
+                    for (int r2 = 0; r2 < lo.P1; ++r2)
+                        for (int r1 = 0; r1 < lo.P1; ++r1) {
+                            double t = A.Tb[(e1 * lo.P1 + r1) * lo.P1 + (j1 - e1)] * A.Tb[(e2 * lo.P1 + r2) * lo.P1 + (j2 - e2)];
+                            s += t * Ml[((e1 - cc1 * nsub) * lo.P1 + r1) * q + mu1] * Ml[((e2 - cc2 * nsub) * lo.P1 + r2) * q + mu2];
+                        }
+            mv[o] = s;
+        }
+        __syncthreads();
+        for (int ca = 0; ca < nc; ++ca)
+            for (int cb = 0; cb < nc; ++cb) {
+                int ida = patch * n * n + (c2lo + ca / nc1) * n + c1lo + ca % nc1;
+                int idb = patch * n * n + (c2lo + cb / nc1) * n + c1lo + cb % nc1;
+                int64_t k = csr_find(A.far_ptr, A.far_src, A.cl_off[l] + ida, (int32_t)(A.cl_off[l] + idb));
+                if (k < 0) continue;
+                const T *K = coup + k * q2 * q2;
+                for (int nu = threadIdx.x; nu < q2; nu += blockDim.x) {
+                    T s = zero<T>();
+                    for (int mu = 0; mu < q2; ++mu) s += K[(int64_t)nu * q2 + mu] * mv[ca * q2 + mu];
+                    acc += s * mv[cb * q2 + nu];
+                }
+            }
+        __syncthreads();
+    }
+    // near field at the leaf level
+    {
+        int nsub = lo.side, n = 1 << lo.L;
+        int c1lo = lo1 / nsub, c1hi = hi1 / nsub, c2lo = lo2 / nsub, c2hi = hi2 / nsub;
+        int nc1 = c1hi - c1lo + 1, nc = nc1 * (c2hi - c2lo + 1);
+        for (int ca = 0; ca < nc; ++ca)
+            for (int cb = 0; cb < nc; ++cb) {
+                int ka1 = c1lo + ca % nc1, ka2 = c2lo + ca / nc1, kb1 = c1lo + cb % nc1, kb2 = c2lo + cb / nc1;
+                int ida = patch * n * n + ka2 * n + ka1, idb = patch * n * n + kb2 * n + kb1;
+                int64_t k = csr_find(A.near_ptr, A.near_src, ida, idb);
+                if (k < 0) continue;
+                const T *B = nearb + k * (int64_t)lo.nl * lo.nl;
+                // functions of the support in both leaves: loop over (row fa, col fb) pairs
+                for (int o = threadIdx.x; o < lo.nl * lo.nl; o += blockDim.x) {
+                    int fb = o / lo.nl, fa = o % lo.nl;
+                    int ela = fa / lo.nloc, ra = fa % lo.nloc, elb = fb / lo.nloc, rb = fb % lo.nloc;
+                    int ea1 = ka1 * nsub + ela % nsub, ea2 = ka2 * nsub + ela / nsub;
+                    int eb1 = kb1 * nsub + elb % nsub, eb2 = kb2 * nsub + elb / nsub;
+                    if (ea1 < lo1 || ea1 > hi1 || ea2 < lo2 || ea2 > hi2 || eb1 < lo1 || eb1 > hi1 || eb2 < lo2 || eb2 > hi2)
+                        continue;
+                    double ta = A.Tb[(ea1 * lo.P1 + ra % lo.P1) * lo.P1 + (j1 - ea1)] * A.Tb[(ea2 * lo.P1 + ra / lo.P1) * lo.P1 + (j2 - ea2)];
+                    double tb = A.Tb[(eb1 * lo.P1 + rb % lo.P1) * lo.P1 + (j1 - eb1)] * A.Tb[(eb2 * lo.P1 + rb / lo.P1) * lo.P1 + (j2 - eb2)];
+                    if (ta == 0.0 || tb == 0.0) continue;
+                    acc += B[o] * (ta * tb);
+                }
+            }
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) D[i] = red[0];
+}
+
+// ===========================================================================
+// kernels: Krylov helpers
+// ===========================================================================
+
+// partial sums of conj(a) . b per block
+template <class T>
+__global__ void __launch_bounds__(256) k_dot_partial(int64_t n, const T *__restrict__ a, const T *__restrict__ b,
+                                                     T *__restrict__ part)
+{
+    __shared__ T red[256];
+    T s = zero<T>();
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        s += conj_(a[i]) * b[i];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int k = blockDim.x / 2; k > 0; k >>= 1) {
+        if ((int)threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+template <class T>
+__global__ void k_reduce_to(int nparts, const T *__restrict__ part, T *__restrict__ out)
+{
+    __shared__ T red[256];
+    T s = zero<T>();
+    for (int i = threadIdx.x; i < nparts; i += blockDim.x) s += part[i];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int k = blockDim.x / 2; k > 0; k >>= 1) {
+        if ((int)threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = red[0];
+}
+
+// CG (real): scal = [rz, pAp, rz_new, rr]
+__global__ void k_cg_update(int64_t n, const double *__restrict__ scal, double *__restrict__ w, double *__restrict__ r,
+                            const double *__restrict__ p, const double *__restrict__ Ap, const double *__restrict__ D,
+                            double *__restrict__ z)
+{
+    double alpha = scal[0] / scal[1];
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        w[i] += alpha * p[i];
+        double ri = r[i] - alpha * Ap[i];
+        r[i] = ri;
+        z[i] = ri / D[i];
+    }
+}
+
+__global__ void k_cg_direction(int64_t n, double *__restrict__ scal, double *__restrict__ p, const double *__restrict__ z)
+{
+    double beta = scal[2] / scal[0];
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = z[i] + beta * p[i];
+}
+
+__global__ void k_copy_scalar(double *scal, int from, int to) { scal[to] = scal[from]; }
+
+template <class T>
+__global__ void k_axpby(int64_t n, T alpha, const T *__restrict__ x, T beta, T *__restrict__ y)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        y[i] = alpha * x[i] + beta * y[i];
+}
+
+template <class T>
+__global__ void k_div(int64_t n, const T *__restrict__ x, const T *__restrict__ D, T *__restrict__ y);
+
+template <>
+__global__ void k_div<double>(int64_t n, const double *__restrict__ x, const double *__restrict__ D, double *__restrict__ y)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        y[i] = x[i] / D[i];
+}
+
+template <>
+__global__ void k_div<cd>(int64_t n, const cd *__restrict__ x, const cd *__restrict__ D, cd *__restrict__ y)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        cd d = D[i];
+        double den = d.re * d.re + d.im * d.im;
+        cd a = x[i];
+        y[i] = {(a.re * d.re + a.im * d.im) / den, (a.im * d.re - a.re * d.im) / den};
+    }
+}
+
+// GMRES: h[j] = <v_j, w> for j < k (classical Gram-Schmidt pass), partial per block
+template <class T>
+__global__ void __launch_bounds__(256) k_multidot_partial(int64_t n, int k, const T *__restrict__ V, int64_t ldv,
+                                                          const T *__restrict__ w, T *__restrict__ part, int nblk)
+{
+    __shared__ T red[256];
+    for (int j = 0; j < k; ++j) {
+        T s = zero<T>();
+        const T *v = V + (int64_t)j * ldv;
+        for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+            s += conj_(v[i]) * w[i];
+        red[threadIdx.x] = s;
+        __syncthreads();
+        for (int q = blockDim.x / 2; q > 0; q >>= 1) {
+            if ((int)threadIdx.x < q) red[threadIdx.x] += red[threadIdx.x + q];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) part[(int64_t)j * nblk + blockIdx.x] = red[0];
+        __syncthreads();
+    }
+}
+
+template <class T>
+__global__ void k_multireduce(int k, int nblk, const T *__restrict__ part, T *__restrict__ h)
+{
+    int j = blockIdx.x;
+    __shared__ T red[256];
+    T s = zero<T>();
+    for (int i = threadIdx.x; i < nblk; i += blockDim.x) s += part[(int64_t)j * nblk + i];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int q = blockDim.x / 2; q > 0; q >>= 1) {
+        if ((int)threadIdx.x < q) red[threadIdx.x] += red[threadIdx.x + q];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) h[j] = red[0];
+}
+
+// w -= V h (first k columns)
+template <class T>
+__global__ void k_sub_Vh(int64_t n, int k, const T *__restrict__ V, int64_t ldv, const T *__restrict__ h, T *__restrict__ w)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        T s = w[i];
+        for (int j = 0; j < k; ++j) s -= h[j] * V[(int64_t)j * ldv + i];
+        w[i] = s;
+    }
+}
+
+// ===========================================================================
+// operator object
+// ===========================================================================
+
+struct igb_operator {
+    Setup s;
+    hipStream_t st = nullptr;
+    bool cplx = false;
+    size_t esz = 8;
+    Layout lo{};
+    int lmin = 0;  // coarsest level with far blocks (L+1 if none)
+    // device data
+    double *tiles = nullptr;
+    int32_t *tdeg = nullptr;
+    double *gx = nullptr, *gw = nullptr;
+    double *btab = nullptr;        // per order n: n*(p+1) Bernstein values, offset goff[n]*(p+1)
+    double *gpts[3] = {nullptr, nullptr, nullptr};
+    int gord[3] = {0, 0, 0};
+    double *rpts = nullptr;        // rhs/potential order geometry
+    double *nodes = nullptr;
+    double *zdev = nullptr;        // Chebyshev nodes
+    int64_t *cl_off = nullptr;
+    double *M1 = nullptr, *E2 = nullptr, *Mlev = nullptr, *Tb = nullptr;
+    int64_t *Mlev_off = nullptr;
+    int64_t *near_ptr = nullptr;
+    int32_t *near_src = nullptr;
+    void *nearb = nullptr;
+    int64_t *far_ptr = nullptr;
+    int32_t *far_src = nullptr, *far_tgt = nullptr;
+    void *coup = nullptr;
+    void *xs = nullptr, *ys = nullptr, *Xh = nullptr, *Yh = nullptr, *ext = nullptr;
+    void *diag = nullptr;
+    // solver work
+    void *r = nullptr, *z = nullptr, *pv = nullptr, *Ap = nullptr, *tmp = nullptr;
+    void *part = nullptr;
+    double *scal = nullptr;
+    double *h_scal = nullptr;  // pinned
+    void *V = nullptr;         // GMRES basis (Vcols columns of ndof)
+    int Vcols = 0;
+    void *hdev = nullptr;      // GMRES projection coefficients
+    void *mpart = nullptr;     // GMRES multi-dot partial sums
+    void *potc = nullptr;      // potential: weighted density at the quadrature points
+    int64_t near_bytes = 0, coup_bytes = 0;
+    double assembly_seconds = 0.0;
+    std::vector<void *> owned;
+};
+
+static igb_status dalloc(igb_operator *op, void **p, size_t bytes)
+{
+    if (bytes == 0) bytes = 8;
+    hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess) {
+        *p = nullptr;
+        return fail(e == hipErrorOutOfMemory ? IGB_ENOMEM : IGB_EHIP,
+                    "hipMalloc(" + std::to_string(bytes) + " bytes): " + hipGetErrorString(e));
+    }
+    op->owned.push_back(*p);
+    return IGB_OK;
+}
+
+template <class P>
+static igb_status upload(igb_operator *op, P **dst, const void *src, size_t bytes)
+{
+    igb_status s = dalloc(op, (void **)dst, bytes);
+    if (s) return s;
+    if (bytes) HIPCHK(hipMemcpyAsync(*dst, src, bytes, hipMemcpyHostToDevice, op->st));
+    return IGB_OK;
+}
+
+static inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+
+// ---------------------------------------------------------------------------
+// template launchers
+// ---------------------------------------------------------------------------
+template <class T, int P>
+static igb_status launch_regular_p(igb_operator *op, const PairRec *d_pairs, int64_t n, int g, const double *gp)
+{
+    int gg = g * g, NLOC = (P + 1) * (P + 1);
+    size_t shm = (size_t)gg * 8 * sizeof(double) + (size_t)gg * NLOC * sizeof(double) + (size_t)gg * NLOC * sizeof(T);
+    if (shm > 160 * 1024) return fail(IGB_EUNSUPPORTED, "regular quadrature order too large for LDS");
+    (void)hipFuncSetAttribute((const void *)k_near_regular<T, P>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+    for (int64_t off = 0; off < n; off += 1 << 20) {
+        int64_t cnt = std::min<int64_t>(n - off, 1 << 20);
+        hipLaunchKernelGGL((k_near_regular<T, P>), dim3((unsigned)cnt), dim3(128), shm, op->st, d_pairs + off, (int)cnt, g,
+                           gp, op->btab + (size_t)op->s.goff[g] * (P + 1), op->s.kappa, op->s.nl, (T *)op->nearb);
+        LAUNCHCHK();
+    }
+    return IGB_OK;
+}
+
+template <class T, int P>
+static igb_status launch_singular_p(igb_operator *op, const PairRec *d_pairs, int64_t n)
+{
+    constexpr int NLOC = (P + 1) * (P + 1);
+    constexpr int BATCH = (NLOC * (int)(sizeof(T) + 8) * 256 <= 64 * 1024) ? 256 : ((NLOC * (int)(sizeof(T) + 8) * 128 <= 96 * 1024) ? 128 : 64);
+    size_t shm = (size_t)(2 * op->s.tile_stride + 128) * sizeof(double) + (size_t)BATCH * NLOC * (sizeof(T) + sizeof(double));
+    size_t need_full = (size_t)NLOC * NLOC * sizeof(T);
+    if (need_full > (size_t)BATCH * NLOC * sizeof(T)) return fail(IGB_EUNSUPPORTED, "singular block too large");
+    (void)hipFuncSetAttribute((const void *)k_near_singular<T, P, BATCH>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+    int gs = op->s.gs;
+    for (int64_t off = 0; off < n; off += 1 << 20) {
+        int64_t cnt = std::min<int64_t>(n - off, 1 << 20);
+        hipLaunchKernelGGL((k_near_singular<T, P, BATCH>), dim3((unsigned)cnt), dim3(256), shm, op->st, d_pairs + off, (int)cnt,
+                           gs, op->gx + op->s.goff[gs], op->gw + op->s.goff[gs], op->tiles, op->tdeg, op->s.tile_stride,
+                           op->s.kappa, op->s.nl, (T *)op->nearb);
+        LAUNCHCHK();
+    }
+    return IGB_OK;
+}
+
+template <class T>
+static igb_status launch_regular(igb_operator *op, const PairRec *d, int64_t n, int g, const double *gp)
+{
+    switch (op->s.p) {
+    case 0: return launch_regular_p<T, 0>(op, d, n, g, gp);
+    case 1: return launch_regular_p<T, 1>(op, d, n, g, gp);
+    case 2: return launch_regular_p<T, 2>(op, d, n, g, gp);
+    case 3: return launch_regular_p<T, 3>(op, d, n, g, gp);
+    case 4: return launch_regular_p<T, 4>(op, d, n, g, gp);
+    case 5: return launch_regular_p<T, 5>(op, d, n, g, gp);
+    case 6: return launch_regular_p<T, 6>(op, d, n, g, gp);
+    }
+    return fail(IGB_EUNSUPPORTED, "p > 6");
+}
+
+template <class T>
+static igb_status launch_singular(igb_operator *op, const PairRec *d, int64_t n)
+{
+    switch (op->s.p) {
+    case 0: return launch_singular_p<T, 0>(op, d, n);
+    case 1: return launch_singular_p<T, 1>(op, d, n);
+    case 2: return launch_singular_p<T, 2>(op, d, n);
+    case 3: return launch_singular_p<T, 3>(op, d, n);
+    case 4: return launch_singular_p<T, 4>(op, d, n);
+    case 5: return launch_singular_p<T, 5>(op, d, n);
+    case 6: return launch_singular_p<T, 6>(op, d, n);
+    }
+    return fail(IGB_EUNSUPPORTED, "p > 6");
+}
+
+// superspace matvec on internal vectors: ys = A xs
+template <class T>
+static igb_status matvec_internal(igb_operator *op, const T *xs, T *ys)
+{
+    const Setup &s = op->s;
+    int q = s.q, q2 = q * q;
+    T *Xh = (T *)op->Xh, *Yh = (T *)op->Yh;
+    bool has_far = op->lmin <= s.L;
+    if (has_far) {
+        size_t shm = (size_t)(s.n1 * s.n1 + s.n1 * q) * sizeof(T);
+        hipLaunchKernelGGL((k_leaf_moments<T>), dim3(s.nleaf), dim3(64), shm, op->st, s.n1, q, s.side, s.p + 1, s.nloc,
+                           s.nl, op->M1, xs, Xh + s.cl_off[s.L] * q2);
+        LAUNCHCHK();
+        for (int l = s.L - 1; l >= op->lmin; --l) {
+            hipLaunchKernelGGL((k_upward<T>), dim3((unsigned)(s.cl_off[l + 1] - s.cl_off[l])), dim3(64), 2 * q2 * sizeof(T),
+                               op->st, l, q, op->E2, Xh + s.cl_off[l + 1] * q2, Xh + s.cl_off[l] * q2);
+            LAUNCHCHK();
+        }
+        int64_t row0 = s.cl_off[op->lmin], nrows = s.cl_off[s.L + 1] - row0;
+        hipLaunchKernelGGL((k_bsr_gemv<T>), dim3((unsigned)nrows), dim3(256), 4 * q2 * sizeof(T), op->st, q2, op->far_ptr,
+                           op->far_src, (const T *)op->coup, (const T *)Xh, Yh, row0);
+        LAUNCHCHK();
+        for (int l = op->lmin; l < s.L; ++l) {
+            hipLaunchKernelGGL((k_downward<T>), dim3((unsigned)(s.cl_off[l + 2] - s.cl_off[l + 1])), dim3(64),
+                               2 * q2 * sizeof(T), op->st, l + 1, q, op->E2, Yh + s.cl_off[l] * q2,
+                               Yh + s.cl_off[l + 1] * q2);
+            LAUNCHCHK();
+        }
+    }
+    hipLaunchKernelGGL((k_bsr_gemv<T>), dim3(s.nleaf), dim3(256), 4 * s.nl * sizeof(T), op->st, s.nl, op->near_ptr,
+                       op->near_src, (const T *)op->nearb, xs, ys, (int64_t)0);
+    LAUNCHCHK();
+    if (has_far) {
+        size_t shm = (size_t)(q2 + q * s.n1) * sizeof(T);
+        hipLaunchKernelGGL((k_leaf_back<T>), dim3(s.nleaf), dim3(64), shm, op->st, s.n1, q, s.side, s.p + 1, s.nloc, s.nl,
+                           op->M1, (const T *)(Yh + s.cl_off[s.L] * q2), ys);
+        LAUNCHCHK();
+    }
+    return IGB_OK;
+}
+
+template <class T>
+static igb_status apply_Tt(igb_operator *op, const T *w, T *xs)
+{
+    hipLaunchKernelGGL((k_Tt<T>), dim3(nblk(op->s.nsup, 256)), dim3(256), 0, op->st, op->lo, op->s.nsup, op->Tb, w, xs);
+    LAUNCHCHK();
+    return IGB_OK;
+}
+
+template <class T>
+static igb_status apply_T(igb_operator *op, const T *ys, T *y)
+{
+    hipLaunchKernelGGL((k_T<T>), dim3(nblk(op->s.ndof, 256)), dim3(256), 0, op->st, op->lo, op->s.ndof, op->Tb, ys, y);
+    LAUNCHCHK();
+    return IGB_OK;
+}
+
+template <class T>
+static igb_status matvec_S(igb_operator *op, const T *x, T *y)
+{
+    igb_status rc;
+    if ((rc = apply_Tt<T>(op, x, (T *)op->xs))) return rc;
+    if ((rc = matvec_internal<T>(op, (const T *)op->xs, (T *)op->ys))) return rc;
+    return apply_T<T>(op, (const T *)op->ys, y);
+}
+
+static const int kRedBlocks = 256;
+
+template <class T>
+static igb_status dot_dev(igb_operator *op, int64_t n, const T *a, const T *b, T *out)
+{
+    hipLaunchKernelGGL((k_dot_partial<T>), dim3(kRedBlocks), dim3(256), 0, op->st, n, a, b, (T *)op->part);
+    LAUNCHCHK();
+    hipLaunchKernelGGL((k_reduce_to<T>), dim3(1), dim3(256), 0, op->st, kRedBlocks, (const T *)op->part, out);
+    LAUNCHCHK();
+    return IGB_OK;
+}
+
+template <class T>
+static igb_status assemble(igb_operator *op)
+{
+    Setup &s = op->s;
+    igb_status rc;
+    int q2 = s.q * s.q;
+    // geometry at the three regular Gauss orders and at the rhs/potential order
+    int ords[3] = {s.g0, std::min(40, s.g0 + 2), std::min(40, s.g0 + 4)};
+    for (int k = 0; k < 3; ++k) {
+        op->gord[k] = ords[k];
+        int g = ords[k];
+        if ((rc = dalloc(op, (void **)&op->gpts[k], (size_t)s.nelem * g * g * 4 * sizeof(double)))) return rc;
+        hipLaunchKernelGGL(k_gauss_geom, dim3(nblk((int64_t)s.nelem * g * g, 256)), dim3(256), 0, op->st, s.nelem,
+                           s.tile_stride, op->tiles, op->tdeg, g, op->gx + s.goff[g], op->gw + s.goff[g], op->gpts[k]);
+        LAUNCHCHK();
+    }
+    {
+        int g = s.grhs;
+        if ((rc = dalloc(op, (void **)&op->rpts, (size_t)s.nelem * g * g * 4 * sizeof(double)))) return rc;
+        hipLaunchKernelGGL(k_gauss_geom, dim3(nblk((int64_t)s.nelem * g * g, 256)), dim3(256), 0, op->st, s.nelem,
+                           s.tile_stride, op->tiles, op->tdeg, g, op->gx + s.goff[g], op->gw + s.goff[g], op->rpts);
+        LAUNCHCHK();
+    }
+    // near-field blocks
+    op->near_bytes = (int64_t)s.near_src.size() * s.nl * s.nl * (int64_t)sizeof(T);
+    if ((rc = dalloc(op, &op->nearb, op->near_bytes))) return rc;
+    HIPCHK(hipMemsetAsync(op->nearb, 0, op->near_bytes, op->st));
+    {
+        std::vector<PairRec> lists[6];
+        for (const PairRec &R : s.pairs) {
+            if (R.cls == kRegular) lists[R.order == ords[0] ? 0 : (R.order == ords[1] ? 1 : 2)].push_back(R);
+            else lists[3 + R.cls - 1].push_back(R);
+        }
+        for (int k = 0; k < 6; ++k) {
+            if (lists[k].empty()) continue;
+            PairRec *d = nullptr;
+            if ((rc = upload(op, &d, lists[k].data(), lists[k].size() * sizeof(PairRec)))) return rc;
+            if (k < 3) rc = launch_regular<T>(op, d, (int64_t)lists[k].size(), ords[k], op->gpts[k]);
+            else rc = launch_singular<T>(op, d, (int64_t)lists[k].size());
+            if (rc) return rc;
+        }
+    }
+    // far field: Chebyshev-node geometry of every cluster, coupling blocks
+    int64_t ncl_all = s.cl_off[s.L + 1];
+    int64_t nfar = (int64_t)s.far_src.size();
+    op->coup_bytes = nfar * q2 * q2 * (int64_t)sizeof(T);
+    if ((rc = dalloc(op, (void **)&op->nodes, (size_t)ncl_all * q2 * 4 * sizeof(double)))) return rc;
+    hipLaunchKernelGGL(k_cluster_nodes, dim3(nblk(ncl_all * q2, 256)), dim3(256), 0, op->st, ncl_all, s.L, op->cl_off,
+                       s.q, s.m, s.ne, op->zdev, s.tile_stride, op->tiles, op->tdeg, op->nodes);
+    LAUNCHCHK();
+    if ((rc = dalloc(op, &op->coup, op->coup_bytes))) return rc;
+    if (nfar > 0) {
+        hipLaunchKernelGGL((k_coupling<T>), dim3((unsigned)nfar), dim3(256), 0, op->st, nfar, op->far_tgt, op->far_src, q2,
+                           op->nodes, s.kappa, (T *)op->coup);
+        LAUNCHCHK();
+    }
+    // Jacobi diagonal
+    if ((rc = dalloc(op, &op->diag, (size_t)s.ndof * sizeof(T)))) return rc;
+    {
+        DiagArgs A;
+        A.lo = op->lo;
+        A.m = s.m;
+        A.q = s.q;
+        A.lmin = op->lmin;
+        A.Tb = op->Tb;
+        A.Mlev = op->Mlev;
+        A.Mlev_off = op->Mlev_off;
+        A.cl_off = op->cl_off;
+        A.near_ptr = op->near_ptr;
+        A.near_src = op->near_src;
+        A.far_ptr = op->far_ptr;
+        A.far_src = op->far_src;
+        size_t shm = (size_t)(s.p + 2) * (s.p + 2) * q2 * sizeof(double);
+        if (shm > 150 * 1024) return fail(IGB_EUNSUPPORTED, "Jacobi diagonal: (p+2)^2 q^2 too large");
+        (void)hipFuncSetAttribute((const void *)k_diag<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+        hipLaunchKernelGGL((k_diag<T>), dim3((unsigned)s.ndof), dim3(256), shm, op->st, A, s.ndof, (const T *)op->nearb,
+                           (const T *)op->coup, (T *)op->diag);
+        LAUNCHCHK();
+    }
+    return IGB_OK;
+}
+
+static igb_status create_device(igb_operator *op)
+{
+    Setup &s = op->s;
+    igb_status rc;
+    size_t esz = op->esz;
+    int q2 = s.q * s.q;
+    if ((rc = upload(op, &op->tiles, s.tiles.data(), s.tiles.size() * sizeof(double)))) return rc;
+    if ((rc = upload(op, &op->tdeg, s.tile_deg.data(), s.tile_deg.size() * sizeof(int32_t)))) return rc;
+    if ((rc = upload(op, &op->gx, s.gx.data(), s.gx.size() * sizeof(double)))) return rc;
+    if ((rc = upload(op, &op->gw, s.gw.data(), s.gw.size() * sizeof(double)))) return rc;
+    {
+        std::vector<double> bt(s.gx.size() * (s.p + 1));
+        for (size_t k = 0; k < s.gx.size(); ++k) {
+            double t = s.gx[k];
+            for (int r = 0; r <= s.p; ++r) {
+                double c = 1.0;
+                for (int i = 1; i <= r; ++i) c = c * (s.p - r + i) / i;
+                bt[k * (s.p + 1) + r] = c * std::pow(t, r) * std::pow(1.0 - t, s.p - r);
+            }
+        }
+        if ((rc = upload(op, &op->btab, bt.data(), bt.size() * sizeof(double)))) return rc;
+    }
+    if ((rc = upload(op, &op->cl_off, s.cl_off.data(), s.cl_off.size() * sizeof(int64_t)))) return rc;
+    if ((rc = upload(op, &op->zdev, s.z.data(), s.z.size() * sizeof(double)))) return rc;
+    if ((rc = upload(op, &op->M1, s.M1.data(), s.M1.size() * sizeof(double)))) return rc;
+    if ((rc = upload(op, &op->E2, s.E2.data(), s.E2.size() * sizeof(double)))) return rc;
+    if ((rc = upload(op, &op->Mlev, s.Mlev.data(), s.Mlev.size() * sizeof(double)))) return rc;
+    if ((rc = upload(op, &op->Mlev_off, s.Mlev_off.data(), s.Mlev_off.size() * sizeof(int64_t)))) return rc;
+    if ((rc = upload(op, &op->Tb, s.Tb.data(), s.Tb.size() * sizeof(double)))) return rc;
+    if ((rc = upload(op, &op->near_ptr, s.near_ptr.data(), s.near_ptr.size() * sizeof(int64_t)))) return rc;
+    if ((rc = upload(op, &op->near_src, s.near_src.data(), s.near_src.size() * sizeof(int32_t)))) return rc;
+    if ((rc = upload(op, &op->far_ptr, s.far_ptr.data(), s.far_ptr.size() * sizeof(int64_t)))) return rc;
+    if ((rc = upload(op, &op->far_src, s.far_src.data(), s.far_src.size() * sizeof(int32_t)))) return rc;
+    {
+        std::vector<int32_t> tg(s.far_src.size());
+        for (int64_t c = 0; c + 1 < (int64_t)s.far_ptr.size(); ++c)
+            for (int64_t k = s.far_ptr[c]; k < s.far_ptr[c + 1]; ++k) tg[k] = (int32_t)c;
+        if ((rc = upload(op, &op->far_tgt, tg.data(), tg.size() * sizeof(int32_t)))) return rc;
+    }
+    int64_t ncl_all = s.cl_off[s.L + 1];
+    if ((rc = dalloc(op, &op->xs, s.nsup * esz))) return rc;
+    if ((rc = dalloc(op, &op->ys, s.nsup * esz))) return rc;
+    if ((rc = dalloc(op, &op->Xh, ncl_all * q2 * esz))) return rc;
+    if ((rc = dalloc(op, &op->Yh, ncl_all * q2 * esz))) return rc;
+    HIPCHK(hipMemsetAsync(op->Xh, 0, ncl_all * q2 * esz, op->st));
+    HIPCHK(hipMemsetAsync(op->Yh, 0, ncl_all * q2 * esz, op->st));
+    for (void **v : {&op->r, &op->z, &op->pv, &op->Ap, &op->tmp})
+        if ((rc = dalloc(op, v, s.ndof * esz))) return rc;
+    if ((rc = dalloc(op, &op->part, kRedBlocks * esz))) return rc;
+    if ((rc = dalloc(op, (void **)&op->scal, 16 * sizeof(double)))) return rc;
+    HIPCHK(hipHostMalloc((void **)&op->h_scal, 16 * sizeof(double), hipHostMallocDefault));
+    if ((rc = dalloc(op, &op->potc, (size_t)s.nelem * s.grhs * s.grhs * esz))) return rc;
+    return op->cplx ? assemble<cd>(op) : assemble<double>(op);
+}
+
+// ---------------------------------------------------------------------------
+// Krylov solvers
+// ---------------------------------------------------------------------------
+static igb_status read_scalar(igb_operator *op, int idx, double *out)
+{
+    HIPCHK(hipMemcpyAsync(op->h_scal + idx, op->scal + idx, sizeof(double), hipMemcpyDeviceToHost, op->st));
+    HIPCHK(hipStreamSynchronize(op->st));
+    *out = op->h_scal[idx];
+    return IGB_OK;
+}
+
+static igb_status solve_cg(igb_operator *op, const double *b, double *w, double tol, int maxit, igb_solve_info *info)
+{
+    int64_t n = op->s.ndof;
+    double *r = (double *)op->r, *z = (double *)op->z, *p = (double *)op->pv, *Ap = (double *)op->Ap;
+    const double *D = (const double *)op->diag;
+    double *sc = op->scal;
+    igb_status rc;
+    unsigned gb = std::min<unsigned>(nblk(n, 256), 1024);
+    double bn2, rr;
+    if ((rc = dot_dev<double>(op, n, b, b, sc + 3))) return rc;
+    if ((rc = read_scalar(op, 3, &bn2))) return rc;
+    double bn = std::sqrt(bn2);
+    if (bn == 0.0) bn = 1.0;
+    int it = 0;
+    double rel = 0.0;
+    for (;;) {
+        if ((rc = matvec_S<double>(op, w, Ap))) return rc;
+        HIPCHK(hipMemcpyAsync(r, b, n * sizeof(double), hipMemcpyDeviceToDevice, op->st));
+        hipLaunchKernelGGL((k_axpby<double>), dim3(gb), dim3(256), 0, op->st, n, -1.0, Ap, 1.0, r);
+        LAUNCHCHK();
+        if ((rc = dot_dev<double>(op, n, r, r, sc + 3))) return rc;
+        if ((rc = read_scalar(op, 3, &rr))) return rc;
+        rel = std::sqrt(rr) / bn;
+        if (rel <= tol || it >= maxit) break;
+        hipLaunchKernelGGL((k_div<double>), dim3(gb), dim3(256), 0, op->st, n, r, D, z);
+        LAUNCHCHK();
+        HIPCHK(hipMemcpyAsync(p, z, n * sizeof(double), hipMemcpyDeviceToDevice, op->st));
+        if ((rc = dot_dev<double>(op, n, r, z, sc + 0))) return rc;
+        while (it < maxit) {
+            if ((rc = matvec_S<double>(op, p, Ap))) return rc;
+            if ((rc = dot_dev<double>(op, n, p, Ap, sc + 1))) return rc;
+            hipLaunchKernelGGL(k_cg_update, dim3(gb), dim3(256), 0, op->st, n, sc, w, r, p, Ap, D, z);
+            LAUNCHCHK();
+            if ((rc = dot_dev<double>(op, n, r, z, sc + 2))) return rc;
+            if ((rc = dot_dev<double>(op, n, r, r, sc + 3))) return rc;
+            if ((rc = read_scalar(op, 3, &rr))) return rc;
+            ++it;
+            if (std::sqrt(rr) / bn <= tol) break;
+            hipLaunchKernelGGL(k_cg_direction, dim3(gb), dim3(256), 0, op->st, n, sc, p, z);
+            LAUNCHCHK();
+            hipLaunchKernelGGL(k_copy_scalar, dim3(1), dim3(1), 0, op->st, sc, 2, 0);
+            LAUNCHCHK();
+        }
+    }
+    if (info) {
+        info->iterations = it;
+        info->rel_residual = rel;
+        info->converged = rel <= tol;
+    }
+    return rel <= tol ? IGB_OK : fail(IGB_ENOT_CONVERGED, "CG stopped at max_iter with relative residual " + std::to_string(rel));
+}
+
+static igb_status solve_gmres(igb_operator *op, const cd *b, cd *w, double tol, int maxit, int restart, igb_solve_info *info)
+{
+    int64_t n = op->s.ndof;
+    int R = std::max(1, std::min(restart, std::max(1, maxit)));
+    igb_status rc;
+    if (op->Vcols < R + 1) {
+        if (op->V) { (void)hipFree(op->V); (void)hipFree(op->hdev); (void)hipFree(op->mpart); }
+        op->V = op->hdev = op->mpart = nullptr;
+        HIPCHK(hipMalloc(&op->V, (size_t)(R + 1) * n * sizeof(cd)));
+        HIPCHK(hipMalloc(&op->hdev, (size_t)(R + 1) * sizeof(cd)));
+        HIPCHK(hipMalloc(&op->mpart, (size_t)(R + 1) * kRedBlocks * sizeof(cd)));
+        op->Vcols = R + 1;
+    }
+    cd *V = (cd *)op->V, *hd = (cd *)op->hdev, *t = (cd *)op->tmp, *r = (cd *)op->r, *t2 = (cd *)op->z;
+    const cd *D = (const cd *)op->diag;
+    unsigned gb = std::min<unsigned>(nblk(n, 256), 1024);
+    auto norm2 = [&](const cd *x, double *out) -> igb_status {
+        igb_status c;
+        if ((c = dot_dev<cd>(op, n, x, x, (cd *)op->scal))) return c;
+        return read_scalar(op, 0, out);
+    };
+    double bn2;
+    if ((rc = norm2(b, &bn2))) return rc;
+    double bn = std::sqrt(bn2);
+    if (bn == 0.0) bn = 1.0;
+    std::vector<cd> H((size_t)(R + 1) * R), cs(R), sn(R), g(R + 1), y(R), hcol(R + 1);
+    int it = 0;
+    double rel = 0.0;
+    for (;;) {
+        if ((rc = matvec_S<cd>(op, w, t))) return rc;
+        HIPCHK(hipMemcpyAsync(r, b, n * sizeof(cd), hipMemcpyDeviceToDevice, op->st));
+        hipLaunchKernelGGL((k_axpby<cd>), dim3(gb), dim3(256), 0, op->st, n, cd{-1.0, 0.0}, t, cd{1.0, 0.0}, r);
+        LAUNCHCHK();
+        double beta2;
+        if ((rc = norm2(r, &beta2))) return rc;
+        double beta = std::sqrt(beta2);
+        rel = beta / bn;
+        if (rel <= tol || it >= maxit) break;
+        hipLaunchKernelGGL((k_axpby<cd>), dim3(gb), dim3(256), 0, op->st, n, cd{1.0 / beta, 0.0}, r, cd{0.0, 0.0}, V);
+        LAUNCHCHK();
+        std::fill(g.begin(), g.end(), cd{0.0, 0.0});
+        std::fill(H.begin(), H.end(), cd{0.0, 0.0});
+        g[0] = cd{beta, 0.0};
+        int k = 0;
+        for (; k < R && it < maxit;) {
+            cd *vk = V + (size_t)k * n, *vn = V + (size_t)(k + 1) * n;
+            hipLaunchKernelGGL((k_div<cd>), dim3(gb), dim3(256), 0, op->st, n, vk, D, t);
+            LAUNCHCHK();
+            if ((rc = matvec_S<cd>(op, t, vn))) return rc;
+            std::fill(hcol.begin(), hcol.end(), cd{0.0, 0.0});
+            for (int pass = 0; pass < 2; ++pass) {  // classical Gram-Schmidt, twice
+                hipLaunchKernelGGL((k_multidot_partial<cd>), dim3(kRedBlocks), dim3(256), 0, op->st, n, k + 1, V, n, vn,
+                                   (cd *)op->mpart, kRedBlocks);
+                LAUNCHCHK();
+                hipLaunchKernelGGL((k_multireduce<cd>), dim3(k + 1), dim3(256), 0, op->st, k + 1, kRedBlocks,
+                                   (const cd *)op->mpart, hd);
+                LAUNCHCHK();
+                hipLaunchKernelGGL((k_sub_Vh<cd>), dim3(gb), dim3(256), 0, op->st, n, k + 1, V, n, hd, vn);
+                LAUNCHCHK();
+                std::vector<cd> hh(k + 1);
+                HIPCHK(hipMemcpyAsync(hh.data(), hd, (k + 1) * sizeof(cd), hipMemcpyDeviceToHost, op->st));
+                HIPCHK(hipStreamSynchronize(op->st));
+                for (int j = 0; j <= k; ++j) hcol[j] += hh[j];
+            }
+            double hn2;
+            if ((rc = norm2(vn, &hn2))) return rc;
+            double hn = std::sqrt(hn2);
+            hcol[k + 1] = cd{hn, 0.0};
+            if (hn > 0.0) {
+                hipLaunchKernelGGL((k_axpby<cd>), dim3(gb), dim3(256), 0, op->st, n, cd{1.0 / hn, 0.0}, vn, cd{0.0, 0.0}, vn);
+                LAUNCHCHK();
+            }
+            // Givens rotations on the new column
+            for (int j = 0; j < k; ++j) {
+                cd a = hcol[j], bb = hcol[j + 1];
+                hcol[j] = conj_(cs[j]) * a + conj_(sn[j]) * bb;
+                hcol[j + 1] = cd{-1.0, 0.0} * sn[j] * a + cs[j] * bb;
+            }
+            cd a = hcol[k], bb = hcol[k + 1];
+            double den = std::sqrt(abs2(a) + abs2(bb));
+            cs[k] = a * (1.0 / den);
+            sn[k] = bb * (1.0 / den);
+            hcol[k] = cd{den, 0.0};
+            hcol[k + 1] = cd{0.0, 0.0};
+            g[k + 1] = cd{-1.0, 0.0} * sn[k] * g[k];
+            g[k] = conj_(cs[k]) * g[k];
+            for (int j = 0; j <= k; ++j) H[(size_t)j * R + k] = hcol[j];
+            ++k;
+            ++it;
+            if (std::sqrt(abs2(g[k])) / bn <= tol) break;
+        }
+        // y = H^-1 g (upper triangular k x k), w += D^-1 V y
+        for (int j = k - 1; j >= 0; --j) {
+            cd s = g[j];
+            for (int l = j + 1; l < k; ++l) s -= H[(size_t)j * R + l] * y[l];
+            cd d = H[(size_t)j * R + j];
+            double den = abs2(d);
+            y[j] = cd{(s.re * d.re + s.im * d.im) / den, (s.im * d.re - s.re * d.im) / den};
+        }
+        std::vector<cd> ny(k);
+        for (int j = 0; j < k; ++j) ny[j] = cd{-y[j].re, -y[j].im};
+        HIPCHK(hipMemcpyAsync(hd, ny.data(), k * sizeof(cd), hipMemcpyHostToDevice, op->st));
+        HIPCHK(hipMemsetAsync(t, 0, n * sizeof(cd), op->st));
+        hipLaunchKernelGGL((k_sub_Vh<cd>), dim3(gb), dim3(256), 0, op->st, n, k, V, n, hd, t);
+        LAUNCHCHK();
+        hipLaunchKernelGGL((k_div<cd>), dim3(gb), dim3(256), 0, op->st, n, t, D, t2);
+        LAUNCHCHK();
+        hipLaunchKernelGGL((k_axpby<cd>), dim3(gb), dim3(256), 0, op->st, n, cd{1.0, 0.0}, t2, cd{1.0, 0.0}, w);
+        LAUNCHCHK();
+        HIPCHK(hipStreamSynchronize(op->st));
+    }
+    if (info) {
+        info->iterations = it;
+        info->rel_residual = rel;
+        info->converged = rel <= tol;
+    }
+    return rel <= tol ? IGB_OK : fail(IGB_ENOT_CONVERGED, "GMRES stopped at max_iter with relative residual " + std::to_string(rel));
+}
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+
+#define CHECK_OP(op)                                                       \
+    do {                                                                   \
+        if (!(op)) return fail(IGB_EINVAL, "operator is null");            \
+    } while (0)
+
+// The entry points below have C linkage through their declarations in igabem.h.
+
+const char *igb_last_error(void) { return g_err.c_str(); }
+
+igb_status igb_geometry_create(int32_t n_patches, const igb_nurbs_patch *patches, igb_geometry **out)
+{
+    if (!out) return fail(IGB_EINVAL, "out is null");
+    *out = nullptr;
+    igb_geometry *g = new igb_geometry();
+    std::string err = make_geometry(n_patches, patches, g->g);
+    if (!err.empty()) {
+        delete g;
+        return fail(IGB_EINVAL, err);
+    }
+    *out = g;
+    return IGB_OK;
+}
+
+void igb_geometry_destroy(igb_geometry *geo) { delete geo; }
+
+void igb_operator_destroy(igb_operator *op)
+{
+    if (!op) return;
+    (void)hipStreamSynchronize(op->st);
+    for (void *p : op->owned) (void)hipFree(p);
+    if (op->V) (void)hipFree(op->V);
+    if (op->hdev) (void)hipFree(op->hdev);
+    if (op->mpart) (void)hipFree(op->mpart);
+    if (op->h_scal) (void)hipHostFree(op->h_scal);
+    delete op;
+}
+
+igb_status igb_operator_create(const igb_geometry *geo, const igb_params *prm, void *hip_stream, igb_operator **out)
+{
+    if (!geo || !prm || !out) return fail(IGB_EINVAL, "null argument");
+    *out = nullptr;
+    auto t0 = std::chrono::steady_clock::now();
+    igb_operator *op = new igb_operator();
+    op->st = (hipStream_t)hip_stream;
+    std::string err;
+    try {
+        err = build_setup(geo->g, *prm, op->s);
+    } catch (const std::bad_alloc &) {
+        delete op;
+        return fail(IGB_ENOMEM, "host allocation failed during setup");
+    }
+    if (!err.empty()) {
+        delete op;
+        return fail(IGB_EINVAL, err);
+    }
+    Setup &s = op->s;
+    op->cplx = s.kernel == IGB_HELMHOLTZ;
+    op->esz = op->cplx ? sizeof(cd) : sizeof(double);
+    op->lo = Layout{s.p, s.p + 1, s.nloc, s.nl, s.side, s.L, s.ne, s.ns1};
+    op->lmin = s.L + 1;
+    for (size_t k = 0; k < s.far.size(); k += 3) op->lmin = std::min(op->lmin, (int)s.far[k]);
+    igb_status rc = create_device(op);
+    if (rc == IGB_OK) {
+        hipError_t e = hipStreamSynchronize(op->st);
+        if (e != hipSuccess) rc = fail(IGB_EHIP, std::string("assembly: ") + hipGetErrorString(e));
+    }
+    if (rc != IGB_OK) {
+        std::string msg = g_err;
+        igb_operator_destroy(op);
+        g_err = msg;
+        return rc;
+    }
+    op->assembly_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    *out = op;
+    return IGB_OK;
+}
+
+static void fill_info(const Setup &s, size_t esz, igb_info *out);
+
+igb_status igb_operator_info(const igb_operator *op, igb_info *out)
+{
+    CHECK_OP(op);
+    if (!out) return fail(IGB_EINVAL, "out is null");
+    fill_info(op->s, op->esz, out);
+    out->assembly_seconds = op->assembly_seconds;
+    return IGB_OK;
+}
+
+igb_status igb_rhs_points(const igb_operator *op, double *xyz_dev)
+{
+    CHECK_OP(op);
+    if (!xyz_dev) return fail(IGB_EINVAL, "xyz_dev is null");
+    int64_t n = (int64_t)op->s.nelem * op->s.grhs * op->s.grhs;
+    hipLaunchKernelGGL(k_rhs_points, dim3(nblk(n, 256)), dim3(256), 0, op->st, n, op->rpts, xyz_dev);
+    LAUNCHCHK();
+    return IGB_OK;
+}
+
+template <class T>
+static igb_status rhs_impl(igb_operator *op, const T *g, T *b)
+{
+    const Setup &s = op->s;
+    hipLaunchKernelGGL((k_rhs_super<T>), dim3(nblk(s.nsup, 256)), dim3(256), 0, op->st, op->lo, s.nsup, s.grhs,
+                       op->gx + s.goff[s.grhs], op->rpts, g, (T *)op->ys);
+    LAUNCHCHK();
+    return apply_T<T>(op, (const T *)op->ys, b);
+}
+
+igb_status igb_rhs_assemble(const igb_operator *cop, const void *g_dev, void *b_dev)
+{
+    CHECK_OP(cop);
+    if (!g_dev || !b_dev) return fail(IGB_EINVAL, "null device pointer");
+    igb_operator *op = const_cast<igb_operator *>(cop);
+    return op->cplx ? rhs_impl<cd>(op, (const cd *)g_dev, (cd *)b_dev) : rhs_impl<double>(op, (const double *)g_dev, (double *)b_dev);
+}
+
+igb_status igb_matvec(const igb_operator *cop, const void *x_dev, void *y_dev)
+{
+    CHECK_OP(cop);
+    if (!x_dev || !y_dev) return fail(IGB_EINVAL, "null device pointer");
+    if (x_dev == y_dev) return fail(IGB_EINVAL, "x and y must not alias");
+    igb_operator *op = const_cast<igb_operator *>(cop);
+    return op->cplx ? matvec_S<cd>(op, (const cd *)x_dev, (cd *)y_dev) : matvec_S<double>(op, (const double *)x_dev, (double *)y_dev);
+}
+
+template <class T>
+static igb_status matvec_super_impl(igb_operator *op, const T *x, T *y)
+{
+    const Setup &s = op->s;
+    hipLaunchKernelGGL((k_perm<T>), dim3(nblk(s.nsup, 256)), dim3(256), 0, op->st, op->lo, s.nsup, x, (T *)op->xs, 1);
+    LAUNCHCHK();
+    igb_status rc = matvec_internal<T>(op, (const T *)op->xs, (T *)op->ys);
+    if (rc) return rc;
+    hipLaunchKernelGGL((k_perm<T>), dim3(nblk(s.nsup, 256)), dim3(256), 0, op->st, op->lo, s.nsup, (const T *)op->ys, y, 0);
+    LAUNCHCHK();
+    return IGB_OK;
+}
+
+igb_status igb_matvec_super(const igb_operator *cop, const void *xs_dev, void *ys_dev)
+{
+    CHECK_OP(cop);
+    if (!xs_dev || !ys_dev) return fail(IGB_EINVAL, "null device pointer");
+    if (xs_dev == ys_dev) return fail(IGB_EINVAL, "xs and ys must not alias");
+    igb_operator *op = const_cast<igb_operator *>(cop);
+    return op->cplx ? matvec_super_impl<cd>(op, (const cd *)xs_dev, (cd *)ys_dev)
+                    : matvec_super_impl<double>(op, (const double *)xs_dev, (double *)ys_dev);
+}
+
+template <class T>
+static igb_status Tt_impl(igb_operator *op, const T *w, T *xs)
+{
+    igb_status rc = apply_Tt<T>(op, w, (T *)op->xs);
+    if (rc) return rc;
+    hipLaunchKernelGGL((k_perm<T>), dim3(nblk(op->s.nsup, 256)), dim3(256), 0, op->st, op->lo, op->s.nsup, (const T *)op->xs, xs, 0);
+    LAUNCHCHK();
+    return IGB_OK;
+}
+
+template <class T>
+static igb_status T_impl(igb_operator *op, const T *ys, T *y)
+{
+    hipLaunchKernelGGL((k_perm<T>), dim3(nblk(op->s.nsup, 256)), dim3(256), 0, op->st, op->lo, op->s.nsup, ys, (T *)op->ys, 1);
+    LAUNCHCHK();
+    return apply_T<T>(op, (const T *)op->ys, y);
+}
+
+igb_status igb_apply_Tt(const igb_operator *cop, const void *w_dev, void *xs_dev)
+{
+    CHECK_OP(cop);
+    if (!w_dev || !xs_dev) return fail(IGB_EINVAL, "null device pointer");
+    igb_operator *op = const_cast<igb_operator *>(cop);
+    return op->cplx ? Tt_impl<cd>(op, (const cd *)w_dev, (cd *)xs_dev) : Tt_impl<double>(op, (const double *)w_dev, (double *)xs_dev);
+}
+
+igb_status igb_apply_T(const igb_operator *cop, const void *ys_dev, void *y_dev)
+{
+    CHECK_OP(cop);
+    if (!ys_dev || !y_dev) return fail(IGB_EINVAL, "null device pointer");
+    igb_operator *op = const_cast<igb_operator *>(cop);
+    return op->cplx ? T_impl<cd>(op, (const cd *)ys_dev, (cd *)y_dev) : T_impl<double>(op, (const double *)ys_dev, (double *)y_dev);
+}
+
+igb_status igb_jacobi_diag(const igb_operator *op, void *d_dev)
+{
+    CHECK_OP(op);
+    if (!d_dev) return fail(IGB_EINVAL, "d_dev is null");
+    HIPCHK(hipMemcpyAsync(d_dev, op->diag, op->s.ndof * op->esz, hipMemcpyDeviceToDevice, op->st));
+    return IGB_OK;
+}
+
+igb_status igb_solve(const igb_operator *cop, const void *b_dev, void *w_dev, double rel_tol, int32_t max_iter,
+                     int32_t restart, igb_solve_info *info)
+{
+    CHECK_OP(cop);
+    if (!b_dev || !w_dev) return fail(IGB_EINVAL, "null device pointer");
+    if (b_dev == w_dev) return fail(IGB_EINVAL, "b and w must not alias");
+    if (!(rel_tol > 0.0) || max_iter < 0) return fail(IGB_EINVAL, "rel_tol must be > 0 and max_iter >= 0");
+    igb_operator *op = const_cast<igb_operator *>(cop);
+    if (op->cplx) {
+        if (restart < 1) return fail(IGB_EINVAL, "restart must be >= 1");
+        return solve_gmres(op, (const cd *)b_dev, (cd *)w_dev, rel_tol, max_iter, restart, info);
+    }
+    return solve_cg(op, (const double *)b_dev, (double *)w_dev, rel_tol, max_iter, info);
+}
+
+template <class T>
+static igb_status potential_impl(igb_operator *op, const T *w, int64_t npts, const double *X, T *u)
+{
+    const Setup &s = op->s;
+    igb_status rc = apply_Tt<T>(op, w, (T *)op->xs);
+    if (rc) return rc;
+    int64_t nq = (int64_t)s.nelem * s.grhs * s.grhs;
+    hipLaunchKernelGGL((k_pot_prep<T>), dim3(nblk(nq, 256)), dim3(256), 0, op->st, op->lo, s.nelem, s.grhs,
+                       op->gx + s.goff[s.grhs], op->rpts, (const T *)op->xs, (T *)op->potc);
+    LAUNCHCHK();
+    if (npts == 0) return IGB_OK;
+    int64_t tb = (npts + 255) / 256;
+    int64_t nchunk = std::max<int64_t>(1, std::min<int64_t>(4096 / tb + 1, (nq + 4095) / 4096));
+    int64_t chunk = (nq + nchunk - 1) / nchunk;
+    T *part = nullptr;
+    HIPCHK(hipMalloc((void **)&part, (size_t)nchunk * npts * sizeof(T)));
+    hipLaunchKernelGGL((k_pot_eval<T>), dim3((unsigned)tb, (unsigned)nchunk), dim3(256), 0, op->st, npts, X, nq, op->rpts,
+                       (const T *)op->potc, s.kappa, chunk, part);
+    hipError_t e1 = hipGetLastError();
+    hipLaunchKernelGGL((k_pot_reduce<T>), dim3((unsigned)tb), dim3(256), 0, op->st, npts, (int)nchunk, (const T *)part, u);
+    hipError_t e2 = hipGetLastError();
+    hipError_t e3 = hipStreamSynchronize(op->st);
+    (void)hipFree(part);
+    if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) return fail(IGB_EHIP, "potential evaluation failed");
+    return IGB_OK;
+}
+
+igb_status igb_potential(const igb_operator *cop, const void *w_dev, int64_t n_pts, const double *xyz_dev, void *u_dev)
+{
+    CHECK_OP(cop);
+    if (n_pts < 0) return fail(IGB_EINVAL, "n_pts < 0");
+    if (!w_dev || (n_pts > 0 && (!xyz_dev || !u_dev))) return fail(IGB_EINVAL, "null device pointer");
+    igb_operator *op = const_cast<igb_operator *>(cop);
+    return op->cplx ? potential_impl<cd>(op, (const cd *)w_dev, n_pts, xyz_dev, (cd *)u_dev)
+                    : potential_impl<double>(op, (const double *)w_dev, n_pts, xyz_dev, (double *)u_dev);
+}
+
+igb_status igb_export_partition(const igb_operator *op, int32_t *near_host, int32_t *far_host)
+{
+    CHECK_OP(op);
+    if ((!near_host && !op->s.near.empty()) || (!far_host && !op->s.far.empty())) return fail(IGB_EINVAL, "null host pointer");
+    if (!op->s.near.empty()) std::memcpy(near_host, op->s.near.data(), op->s.near.size() * sizeof(int32_t));
+    if (!op->s.far.empty()) std::memcpy(far_host, op->s.far.data(), op->s.far.size() * sizeof(int32_t));
+    return IGB_OK;
+}
+
+igb_status igb_export_pair_classes(const igb_operator *op, int32_t *pairs_host)
+{
+    CHECK_OP(op);
+    if (!pairs_host && !op->s.pairs.empty()) return fail(IGB_EINVAL, "null host pointer");
+    for (size_t k = 0; k < op->s.pairs.size(); ++k) {
+        const PairRec &R = op->s.pairs[k];
+        pairs_host[4 * k] = R.E;
+        pairs_host[4 * k + 1] = R.F;
+        pairs_host[4 * k + 2] = R.cls;
+        pairs_host[4 * k + 3] = R.order;
+    }
+    return IGB_OK;
+}
+
+igb_status igb_export_near_block(const igb_operator *op, int32_t E, int32_t F, double *blk_host)
+{
+    CHECK_OP(op);
+    const Setup &s = op->s;
+    if (!blk_host || E < 0 || F < 0 || E >= s.nelem || F >= s.nelem) return fail(IGB_EINVAL, "bad element index");
+    auto leaf_of = [&](int e, int &el) {
+        int pt = e / (s.ne * s.ne), r = e % (s.ne * s.ne), e2 = r / s.ne, e1 = r % s.ne, nL = 1 << s.L;
+        el = (e2 % s.side) * s.side + e1 % s.side;
+        return pt * nL * nL + (e2 / s.side) * nL + e1 / s.side;
+    };
+    int elE, elF;
+    int lE = leaf_of(E, elE), lF = leaf_of(F, elF);
+    auto b = s.near_src.begin() + s.near_ptr[lE], e = s.near_src.begin() + s.near_ptr[lE + 1];
+    auto it = std::lower_bound(b, e, lF);
+    if (it == e || *it != lF) return fail(IGB_EINVAL, "element pair is not in the near field");
+    int64_t k = it - s.near_src.begin();
+    size_t nb = (size_t)s.nl * s.nl;
+    std::vector<unsigned char> buf(nb * op->esz);
+    HIPCHK(hipStreamSynchronize(op->st));
+    HIPCHK(hipMemcpy(buf.data(), (const char *)op->nearb + k * nb * op->esz, nb * op->esz, hipMemcpyDeviceToHost));
+    int nc = op->cplx ? 2 : 1;
+    const double *B = (const double *)buf.data();
+    for (int a = 0; a < s.nloc; ++a)
+        for (int c = 0; c < s.nloc; ++c) {
+            int64_t pos = (int64_t)(elF * s.nloc + c) * s.nl + elE * s.nloc + a;
+            for (int z = 0; z < nc; ++z) blk_host[(a * s.nloc + c) * nc + z] = B[pos * nc + z];
+        }
+    return IGB_OK;
+}
+
+igb_status igb_export_coupling_block(const igb_operator *op, int32_t level, int32_t tgt, int32_t src, double *blk_host)
+{
+    CHECK_OP(op);
+    const Setup &s = op->s;
+    if (!blk_host || level < 0 || level > s.L) return fail(IGB_EINVAL, "bad level");
+    int64_t ncl = (int64_t)s.npatch << (2 * level);
+    if (tgt < 0 || src < 0 || tgt >= ncl || src >= ncl) return fail(IGB_EINVAL, "bad cluster id");
+    int64_t row = s.cl_off[level] + tgt;
+    int32_t key = (int32_t)(s.cl_off[level] + src);
+    auto b = s.far_src.begin() + s.far_ptr[row], e = s.far_src.begin() + s.far_ptr[row + 1];
+    auto it = std::lower_bound(b, e, key);
+    if (it == e || *it != key) return fail(IGB_EINVAL, "cluster pair is not a far block");
+    int64_t k = it - s.far_src.begin();
+    int q2 = s.q * s.q;
+    size_t nb = (size_t)q2 * q2;
+    std::vector<unsigned char> buf(nb * op->esz);
+    HIPCHK(hipStreamSynchronize(op->st));
+    HIPCHK(hipMemcpy(buf.data(), (const char *)op->coup + k * nb * op->esz, nb * op->esz, hipMemcpyDeviceToHost));
+    int nc = op->cplx ? 2 : 1;
+    const double *B = (const double *)buf.data();
+    for (int mu = 0; mu < q2; ++mu)
+        for (int nu = 0; nu < q2; ++nu)
+            for (int z = 0; z < nc; ++z) blk_host[((size_t)mu * q2 + nu) * nc + z] = B[((size_t)nu * q2 + mu) * nc + z];
+    return IGB_OK;
+}
+
+
+
+// ---------------------------------------------------------------------------
+// host-only planning
+// ---------------------------------------------------------------------------
+struct igb_plan {
+    Setup s;
+};
+
+static void fill_info(const Setup &s, size_t esz, igb_info *out)
+{
+    std::memset(out, 0, sizeof(*out));
+    out->n_dof = s.ndof;
+    out->n_dof_super = s.nsup;
+    out->n_elements = s.nelem;
+    out->n_rhs_points = (int64_t)s.nelem * s.grhs * s.grhs;
+    out->leaf_level = s.L;
+    out->gauss_singular = s.gs;
+    out->gauss_rhs = s.grhs;
+    out->n_near_blocks = (int64_t)s.near_src.size();
+    out->n_far_blocks = (int64_t)s.far_src.size();
+    for (int c = 0; c < 4; ++c) out->n_pairs[c] = s.npairs_class[c];
+    int64_t q2 = (int64_t)s.q * s.q, ncl = s.cl_off[s.L + 1];
+    out->near_bytes = out->n_near_blocks * s.nl * s.nl * (int64_t)esz;
+    out->coupling_bytes = out->n_far_blocks * q2 * q2 * (int64_t)esz;
+    out->matvec_bytes = out->near_bytes + out->coupling_bytes + (int64_t)esz * (3 * s.nsup + 4 * q2 * ncl);
+    out->setup_seconds = s.setup_seconds;
+}
+
+igb_status igb_plan_create(const igb_geometry *geo, const igb_params *prm, igb_plan **out)
+{
+    if (!geo || !prm || !out) return fail(IGB_EINVAL, "null argument");
+    *out = nullptr;
+    igb_plan *pl = new igb_plan();
+    std::string err = build_setup(geo->g, *prm, pl->s);
+    if (!err.empty()) {
+        delete pl;
+        return fail(IGB_EINVAL, err);
+    }
+    *out = pl;
+    return IGB_OK;
+}
+
+void igb_plan_destroy(igb_plan *plan) { delete plan; }
+
+igb_status igb_plan_info(const igb_plan *plan, igb_info *out)
+{
+    if (!plan || !out) return fail(IGB_EINVAL, "null argument");
+    fill_info(plan->s, plan->s.kernel == IGB_HELMHOLTZ ? sizeof(cd) : sizeof(double), out);
+    return IGB_OK;
+}
+
+igb_status igb_plan_export_partition(const igb_plan *plan, int32_t *near_host, int32_t *far_host)
+{
+    if (!plan) return fail(IGB_EINVAL, "plan is null");
+    const Setup &s = plan->s;
+    if ((!near_host && !s.near.empty()) || (!far_host && !s.far.empty())) return fail(IGB_EINVAL, "null host pointer");
+    if (!s.near.empty()) std::memcpy(near_host, s.near.data(), s.near.size() * sizeof(int32_t));
+    if (!s.far.empty()) std::memcpy(far_host, s.far.data(), s.far.size() * sizeof(int32_t));
+    return IGB_OK;
+}
+
+igb_status igb_plan_export_pair_classes(const igb_plan *plan, int32_t *pairs_host)
+{
+    if (!plan) return fail(IGB_EINVAL, "plan is null");
+    const Setup &s = plan->s;
+    if (!pairs_host && !s.pairs.empty()) return fail(IGB_EINVAL, "null host pointer");
+    for (size_t k = 0; k < s.pairs.size(); ++k) {
+        const PairRec &R = s.pairs[k];
+        pairs_host[4 * k] = R.E;
+        pairs_host[4 * k + 1] = R.F;
+        pairs_host[4 * k + 2] = R.cls;
+        pairs_host[4 * k + 3] = R.order;
+    }
+    return IGB_OK;
+}

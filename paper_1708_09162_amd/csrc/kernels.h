@@ -1,0 +1,116 @@
+// Device helpers shared by the libigabem kernels: a complex type, the
+// fundamental solutions, Bernstein bases and rational Bezier tile evaluation.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace igb {
+
+struct cd {
+    double re, im;
+};
+
+__host__ __device__ inline cd operator+(cd a, cd b) { return {a.re + b.re, a.im + b.im}; }
+__host__ __device__ inline cd operator-(cd a, cd b) { return {a.re - b.re, a.im - b.im}; }
+__host__ __device__ inline cd operator*(cd a, cd b) { return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re}; }
+__host__ __device__ inline cd operator*(cd a, double b) { return {a.re * b, a.im * b}; }
+__host__ __device__ inline cd operator*(double b, cd a) { return {a.re * b, a.im * b}; }
+__host__ __device__ inline cd &operator+=(cd &a, cd b) { a.re += b.re; a.im += b.im; return a; }
+__host__ __device__ inline cd &operator-=(cd &a, cd b) { a.re -= b.re; a.im -= b.im; return a; }
+
+template <class T> __host__ __device__ inline T zero();
+template <> __host__ __device__ inline double zero<double>() { return 0.0; }
+template <> __host__ __device__ inline cd zero<cd>() { return {0.0, 0.0}; }
+
+__host__ __device__ inline double conj_(double a) { return a; }
+__host__ __device__ inline cd conj_(cd a) { return {a.re, -a.im}; }
+__host__ __device__ inline double abs2(double a) { return a * a; }
+__host__ __device__ inline double abs2(cd a) { return a.re * a.re + a.im * a.im; }
+
+// Fundamental solutions of Sec. 3.1 (eq. fundament1 / fundament2) at distance r.
+template <class T> __device__ inline T green(double r, double kappa);
+template <> __device__ inline double green<double>(double r, double) { return 0.07957747154594767 / r; }
+template <> __device__ inline cd green<cd>(double r, double kappa)
+{
+    double s, c;
+    sincos(kappa * r, &s, &c);
+    double f = 0.07957747154594767 / r;
+    return {c * f, s * f};
+}
+
+// Bernstein polynomials of degree p at t (and derivatives), p <= 8.
+__device__ inline void bernstein(int p, double t, double *B)
+{
+    double s = 1.0 - t;
+    B[0] = 1.0;
+    for (int k = 1; k <= p; ++k) {
+        B[k] = t * B[k - 1];
+        for (int i = k - 1; i >= 1; --i) B[i] = s * B[i] + t * B[i - 1];
+        B[0] = s * B[0];
+    }
+}
+
+__device__ inline void bernstein_d(int p, double t, double *B, double *dB)
+{
+    if (p == 0) {
+        B[0] = 1.0;
+        dB[0] = 0.0;
+        return;
+    }
+    double lo[9];
+    double s = 1.0 - t;
+    lo[0] = 1.0;
+    for (int k = 1; k < p; ++k) {
+        lo[k] = t * lo[k - 1];
+        for (int i = k - 1; i >= 1; --i) lo[i] = s * lo[i] + t * lo[i - 1];
+        lo[0] = s * lo[0];
+    }
+    B[p] = t * lo[p - 1];
+    for (int i = p - 1; i >= 1; --i) B[i] = s * lo[i] + t * lo[i - 1];
+    B[0] = s * lo[0];
+    dB[0] = -p * lo[0];
+    for (int i = 1; i < p; ++i) dB[i] = p * (lo[i - 1] - lo[i]);
+    dB[p] = p * lo[p - 1];
+}
+
+// Rational Bezier tile (homogeneous control points H[(j*(pu+1)+i)*4 + c]) at
+// element-local (u, v): point X and surface measure w.r.t. (u, v).
+__device__ inline void tile_point(const double *H, int pu, int pv, double u, double v, double X[3], double *kap)
+{
+    double Bu[9], dBu[9], Bv[9], dBv[9];
+    bernstein_d(pu, u, Bu, dBu);
+    bernstein_d(pv, v, Bv, dBv);
+    double S0 = 0, S1 = 0, S2 = 0, S3 = 0, U0 = 0, U1 = 0, U2 = 0, U3 = 0, V0 = 0, V1 = 0, V2 = 0, V3 = 0;
+    for (int j = 0; j <= pv; ++j) {
+        double a0 = 0, a1 = 0, a2 = 0, a3 = 0, d0 = 0, d1 = 0, d2 = 0, d3 = 0;
+        const double *h = H + 4 * j * (pu + 1);
+        for (int i = 0; i <= pu; ++i) {
+            double b = Bu[i], db = dBu[i];
+            a0 += b * h[4 * i];
+            a1 += b * h[4 * i + 1];
+            a2 += b * h[4 * i + 2];
+            a3 += b * h[4 * i + 3];
+            d0 += db * h[4 * i];
+            d1 += db * h[4 * i + 1];
+            d2 += db * h[4 * i + 2];
+            d3 += db * h[4 * i + 3];
+        }
+        double bv = Bv[j], dbv = dBv[j];
+        S0 += bv * a0; S1 += bv * a1; S2 += bv * a2; S3 += bv * a3;
+        U0 += bv * d0; U1 += bv * d1; U2 += bv * d2; U3 += bv * d3;
+        V0 += dbv * a0; V1 += dbv * a1; V2 += dbv * a2; V3 += dbv * a3;
+    }
+    double iw = 1.0 / S3;
+    double x0 = S0 * iw, x1 = S1 * iw, x2 = S2 * iw;
+    double u0 = (U0 - x0 * U3) * iw, u1 = (U1 - x1 * U3) * iw, u2 = (U2 - x2 * U3) * iw;
+    double v0 = (V0 - x0 * V3) * iw, v1 = (V1 - x1 * V3) * iw, v2 = (V2 - x2 * V3) * iw;
+    X[0] = x0;
+    X[1] = x1;
+    X[2] = x2;
+    double n0 = u1 * v2 - u2 * v1, n1 = u2 * v0 - u0 * v2, n2 = u0 * v1 - u1 * v0;
+    *kap = sqrt(n0 * n0 + n1 * n1 + n2 * n2);
+}
+
+}  // namespace igb

@@ -1,0 +1,690 @@
+// Host-side setup of libigabem: geometry validation, Bezier extraction by
+// knot insertion, Gauss rules, Chebyshev moment/transfer tables, the per-patch
+// cluster tree with its block partition (Sec. 4.1, Sec. 4.2 Def.) and the
+// near-field element-pair work lists (Sec. 4 item 4).
+#include "setup.h"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+
+namespace igb {
+
+// ---------------------------------------------------------------------------
+// Gauss-Legendre on [0,1]: Newton on P_n from Chebyshev-like initial guesses.
+// ---------------------------------------------------------------------------
+void gauss_rule(int n, double *x, double *w)
+{
+    for (int k = 0; k < (n + 1) / 2; ++k) {
+        double t = std::cos(M_PI * (4.0 * k + 3.0) / (4.0 * n + 2.0));
+        double pn = 0, dpn = 1;
+        for (int it = 0; it < 60; ++it) {
+            double a = 1.0, b = t;  // P_0, P_1
+            for (int j = 2; j <= n; ++j) {
+                double c = ((2 * j - 1) * t * b - (j - 1) * a) / j;
+                a = b;
+                b = c;
+            }
+            pn = (n == 1) ? t : b;
+            double pm = (n == 1) ? 1.0 : a;
+            dpn = n * (pm - t * pn) / (1.0 - t * t);
+            double step = pn / dpn;
+            t -= step;
+            if (std::fabs(step) <= 1e-17) break;
+        }
+        {
+            double a = 1.0, b = t;
+            for (int j = 2; j <= n; ++j) {
+                double c = ((2 * j - 1) * t * b - (j - 1) * a) / j;
+                a = b;
+                b = c;
+            }
+            pn = (n == 1) ? t : b;
+            double pm = (n == 1) ? 1.0 : a;
+            dpn = n * (pm - t * pn) / (1.0 - t * t);
+        }
+        double wt = 1.0 / ((1.0 - t * t) * dpn * dpn);  // half of the [-1,1] weight
+        // t is the k-th largest root; mirror pairs
+        x[n - 1 - k] = 0.5 * (1.0 + t);
+        w[n - 1 - k] = wt;
+        x[k] = 0.5 * (1.0 - t);
+        w[k] = wt;
+    }
+    if (n % 2 == 1) x[n / 2] = 0.5;
+}
+
+// ---------------------------------------------------------------------------
+// geometry validation
+// ---------------------------------------------------------------------------
+static bool p_open(const double *U, int n, int p, std::string &why)
+{
+    int nk = n + p + 1;
+    for (int i = 0; i < nk; ++i)
+        if (!std::isfinite(U[i])) { why = "non-finite knot"; return false; }
+    for (int i = 0; i + 1 < nk; ++i)
+        if (U[i + 1] < U[i]) { why = "decreasing knot vector"; return false; }
+    for (int i = 0; i <= p; ++i)
+        if (U[i] != 0.0 || U[nk - 1 - i] != 1.0) { why = "knot vector is not p-open on [0,1]"; return false; }
+    for (int i = p + 1; i < n; ++i) {
+        int mult = 1;
+        while (i + mult < n && U[i + mult] == U[i]) ++mult;
+        if (mult > p && p > 0) { why = "interior knot multiplicity exceeds the degree"; return false; }
+        if (U[i] <= 0.0 || U[i] >= 1.0) { why = "interior knot outside (0,1)"; return false; }
+    }
+    return true;
+}
+
+std::string make_geometry(int32_t n, const igb_nurbs_patch *in, Geometry &out)
+{
+    if (n < 1 || !in) return "n_patches < 1 or null patch array";
+    out.patches.clear();
+    for (int i = 0; i < n; ++i) {
+        const igb_nurbs_patch &s = in[i];
+        if (!s.knots_u || !s.knots_v || !s.cpw) return "patch " + std::to_string(i) + ": null pointer";
+        if (s.deg_u < 0 || s.deg_u > 8 || s.deg_v < 0 || s.deg_v > 8)
+            return "patch " + std::to_string(i) + ": degree outside 0..8";
+        if (s.n_u < s.deg_u + 1 || s.n_v < s.deg_v + 1 || s.n_u > 4096 || s.n_v > 4096)
+            return "patch " + std::to_string(i) + ": control point count";
+        std::string why;
+        if (!p_open(s.knots_u, s.n_u, s.deg_u, why)) return "patch " + std::to_string(i) + " u: " + why;
+        if (!p_open(s.knots_v, s.n_v, s.deg_v, why)) return "patch " + std::to_string(i) + " v: " + why;
+        Patch P;
+        P.pu = s.deg_u;
+        P.pv = s.deg_v;
+        P.nu = s.n_u;
+        P.nv = s.n_v;
+        P.U.assign(s.knots_u, s.knots_u + s.n_u + s.deg_u + 1);
+        P.V.assign(s.knots_v, s.knots_v + s.n_v + s.deg_v + 1);
+        P.cpw.assign(s.cpw, s.cpw + (size_t)4 * s.n_u * s.n_v);
+        for (size_t k = 0; k < P.cpw.size(); ++k)
+            if (!std::isfinite(P.cpw[k])) return "patch " + std::to_string(i) + ": non-finite control data";
+        for (size_t k = 3; k < P.cpw.size(); k += 4)
+            if (!(P.cpw[k] > 0.0)) return "patch " + std::to_string(i) + ": weight <= 0";
+        out.patches.push_back(std::move(P));
+    }
+    return "";
+}
+
+// ---------------------------------------------------------------------------
+// Bezier extraction by repeated knot insertion (Boehm).  Returns, for a
+// degree-p spline space with knots U (n functions), the matrix M (rows =
+// functions of the refined space with every breakpoint k/ne at multiplicity p,
+// columns = original functions): N_j = sum_k M[k][j] N'_k.  On element e the
+// refined functions e*p .. e*p+p are the Bernstein polynomials of degree p.
+// ---------------------------------------------------------------------------
+static std::string extraction(int p, const std::vector<double> &U0, int n0, int ne, std::vector<double> &M, int &nr)
+{
+    std::vector<double> U = U0;
+    int n = n0;
+    // interior knots must lie on the grid
+    for (int i = p + 1; i < n; ++i) {
+        double t = U[i] * ne;
+        if (std::fabs(t - std::round(t)) > 1e-12) return "interior knot off the refinement grid k/2^m";
+        U[i] = std::round(t) / ne;
+    }
+    M.assign((size_t)n * n0, 0.0);
+    for (int i = 0; i < n; ++i) M[(size_t)i * n0 + i] = 1.0;
+    if (p == 0) {
+        // piecewise constants: every breakpoint once
+        for (int k = 1; k < ne; ++k) {
+            double t = (double)k / ne;
+            int span = -1;
+            for (int i = 0; i + 1 < (int)U.size(); ++i)
+                if (U[i] <= t && t < U[i + 1]) span = i;
+            if (U[span] == t) continue;
+            // insert: function span is split into two copies
+            std::vector<double> Mn((size_t)(n + 1) * n0);
+            for (int i = 0; i <= n; ++i) {
+                int src = i <= span ? i : i - 1;
+                std::memcpy(&Mn[(size_t)i * n0], &M[(size_t)src * n0], sizeof(double) * n0);
+            }
+            M.swap(Mn);
+            U.insert(U.begin() + span + 1, t);
+            ++n;
+        }
+        nr = n;
+        return "";
+    }
+    for (int k = 1; k < ne; ++k) {
+        double t = (double)k / ne;
+        int mult = 0;
+        for (double u : U)
+            if (u == t) ++mult;
+        for (int rep = mult; rep < p; ++rep) {
+            int span = 0;
+            for (int i = 0; i + 1 < (int)U.size(); ++i)
+                if (U[i] <= t && t < U[i + 1]) span = i;
+            std::vector<double> Mn((size_t)(n + 1) * n0, 0.0);
+            for (int i = 0; i <= n; ++i) {
+                double *row = &Mn[(size_t)i * n0];
+                if (i <= span - p) {
+                    std::memcpy(row, &M[(size_t)i * n0], sizeof(double) * n0);
+                } else if (i >= span + 1) {
+                    std::memcpy(row, &M[(size_t)(i - 1) * n0], sizeof(double) * n0);
+                } else {
+                    double a = (t - U[i]) / (U[i + p] - U[i]);
+                    for (int c = 0; c < n0; ++c) row[c] = a * M[(size_t)i * n0 + c] + (1.0 - a) * M[(size_t)(i - 1) * n0 + c];
+                }
+            }
+            M.swap(Mn);
+            U.insert(U.begin() + span + 1, t);
+            ++n;
+        }
+    }
+    nr = n;
+    if (nr != p * ne + 1) return "extraction produced an unexpected number of functions";
+    return "";
+}
+
+// Bernstein values and derivatives of degree p at t
+static inline void bern(int p, double t, double *B, double *dB)
+{
+    double s = 1.0 - t;
+    // values of degree p-1 for the derivative
+    double lo[16];
+    if (p == 0) {
+        B[0] = 1.0;
+        if (dB) dB[0] = 0.0;
+        return;
+    }
+    lo[0] = 1.0;
+    for (int k = 1; k < p; ++k) {
+        lo[k] = 0.0;
+        for (int i = k; i >= 1; --i) lo[i] = s * lo[i] + t * lo[i - 1];
+        lo[0] = s * lo[0];
+    }
+    // degree p from degree p-1
+    B[p] = t * lo[p - 1];
+    for (int i = p - 1; i >= 1; --i) B[i] = s * lo[i] + t * lo[i - 1];
+    B[0] = s * lo[0];
+    if (dB) {
+        dB[0] = -p * lo[0];
+        for (int i = 1; i < p; ++i) dB[i] = p * (lo[i - 1] - lo[i]);
+        dB[p] = p * lo[p - 1];
+    }
+}
+
+void tile_eval(const Setup &s, int E, double u, double v, double X[3], double *kap)
+{
+    int pu = s.tile_deg[2 * E], pv = s.tile_deg[2 * E + 1];
+    const double *H = &s.tiles[(size_t)E * s.tile_stride];
+    double Bu[16], dBu[16], Bv[16], dBv[16];
+    bern(pu, u, Bu, dBu);
+    bern(pv, v, Bv, dBv);
+    double S[4] = {0, 0, 0, 0}, Su[4] = {0, 0, 0, 0}, Sv[4] = {0, 0, 0, 0};
+    for (int j = 0; j <= pv; ++j) {
+        double A[4] = {0, 0, 0, 0}, Ad[4] = {0, 0, 0, 0};
+        for (int i = 0; i <= pu; ++i) {
+            const double *h = H + 4 * (j * (pu + 1) + i);
+            for (int c = 0; c < 4; ++c) {
+                A[c] += Bu[i] * h[c];
+                Ad[c] += dBu[i] * h[c];
+            }
+        }
+        for (int c = 0; c < 4; ++c) {
+            S[c] += Bv[j] * A[c];
+            Su[c] += Bv[j] * Ad[c];
+            Sv[c] += dBv[j] * A[c];
+        }
+    }
+    double iw = 1.0 / S[3];
+    double x[3], xu[3], xv[3];
+    for (int c = 0; c < 3; ++c) {
+        x[c] = S[c] * iw;
+        xu[c] = (Su[c] - x[c] * Su[3]) * iw;
+        xv[c] = (Sv[c] - x[c] * Sv[3]) * iw;
+    }
+    X[0] = x[0];
+    X[1] = x[1];
+    X[2] = x[2];
+    if (kap) {
+        double n0 = xu[1] * xv[2] - xu[2] * xv[1];
+        double n1 = xu[2] * xv[0] - xu[0] * xv[2];
+        double n2 = xu[0] * xv[1] - xu[1] * xv[0];
+        *kap = std::sqrt(n0 * n0 + n1 * n1 + n2 * n2);
+    }
+}
+
+// point at patch parameter (u, v) via the element tiles
+static void patch_point(const Setup &s, int patch, double u, double v, double X[3])
+{
+    double a = u * s.ne, b = v * s.ne;
+    int e1 = (int)std::floor(a), e2 = (int)std::floor(b);
+    e1 = std::min(std::max(e1, 0), s.ne - 1);
+    e2 = std::min(std::max(e2, 0), s.ne - 1);
+    int E = patch * s.ne * s.ne + e2 * s.ne + e1;
+    tile_eval(s, E, a - e1, b - e2, X, nullptr);
+}
+
+static inline double dist(const double *a, const double *b)
+{
+    double x = a[0] - b[0], y = a[1] - b[1], z = a[2] - b[2];
+    return std::sqrt(x * x + y * y + z * z);
+}
+
+// Lagrange basis polynomial mu on the Chebyshev nodes z, evaluated at t
+static double lagr(const std::vector<double> &z, int mu, double t)
+{
+    double r = 1.0;
+    for (size_t k = 0; k < z.size(); ++k)
+        if ((int)k != mu) r *= (t - z[k]) / (z[mu] - z[k]);
+    return r;
+}
+
+// ---------------------------------------------------------------------------
+// the partition: level-synchronous recursion over block pairs
+// ---------------------------------------------------------------------------
+namespace {
+struct LevelGeo {
+    std::vector<double> pts;   // ncl*25*3
+    std::vector<double> diam;  // ncl
+    std::vector<double> cen;   // ncl*3 (grid centre point)
+    std::vector<double> rad;   // ncl (max distance centre -> grid point)
+};
+}  // namespace
+
+static void level_geo(const Setup &s, int l, LevelGeo &G)
+{
+    int n = 1 << l;
+    int ncl = s.npatch * n * n;
+    G.pts.resize((size_t)ncl * 75);
+    G.diam.resize(ncl);
+    G.cen.resize((size_t)ncl * 3);
+    G.rad.resize(ncl);
+    double sc = 1.0 / n;
+    for (int c = 0; c < ncl; ++c) {
+        int patch = c / (n * n), r = c % (n * n), k2 = r / n, k1 = r % n;
+        double *P = &G.pts[(size_t)c * 75];
+        for (int b = 0; b < 5; ++b)
+            for (int a = 0; a < 5; ++a) patch_point(s, patch, (k1 + 0.25 * a) * sc, (k2 + 0.25 * b) * sc, P + 3 * (b * 5 + a));
+        double d = 0.0;
+        for (int i = 0; i < 25; ++i)
+            for (int j = i + 1; j < 25; ++j) d = std::max(d, dist(P + 3 * i, P + 3 * j));
+        G.diam[c] = d;
+        const double *C = P + 3 * 12;
+        G.cen[3 * c] = C[0];
+        G.cen[3 * c + 1] = C[1];
+        G.cen[3 * c + 2] = C[2];
+        double rr = 0.0;
+        for (int i = 0; i < 25; ++i) rr = std::max(rr, dist(C, P + 3 * i));
+        G.rad[c] = rr;
+    }
+}
+
+// admissibility max(diam) < eta * dist over the 5x5 grids (bounds decide clear cases)
+static bool admissible(const Setup &s, const LevelGeo &G, int a, int b)
+{
+    double md = std::max(G.diam[a], G.diam[b]);
+    double cc = dist(&G.cen[3 * a], &G.cen[3 * b]);
+    double lb = cc - G.rad[a] - G.rad[b];
+    if (lb > 0 && md < s.eta * lb * (1.0 - 1e-12)) return true;
+    if (md > s.eta * cc * (1.0 + 1e-12)) return false;
+    const double *A = &G.pts[(size_t)a * 75], *B = &G.pts[(size_t)b * 75];
+    double dmin = 1e300;
+    for (int i = 0; i < 25; ++i)
+        for (int j = 0; j < 25; ++j) dmin = std::min(dmin, dist(A + 3 * i, B + 3 * j));
+    return md < s.eta * dmin;
+}
+
+static void build_partition(Setup &s)
+{
+    struct BP { int32_t t, src; };
+    std::vector<BP> cur;
+    for (int i = 0; i < s.npatch; ++i)
+        for (int j = 0; j < s.npatch; ++j) cur.push_back({i, j});
+    s.near.clear();
+    s.far.clear();
+    for (int l = 0; l <= s.L; ++l) {
+        LevelGeo G;
+        bool dense = (s.mode == IGB_DENSE);
+        if (!dense) level_geo(s, l, G);
+        std::vector<BP> nxt;
+        int n = 1 << l, nn = 2 * n;
+        for (const BP &bp : cur) {
+            if (!dense && admissible(s, G, bp.t, bp.src)) {
+                s.far.push_back(l);
+                s.far.push_back(bp.t);
+                s.far.push_back(bp.src);
+            } else if (l == s.L) {
+                s.near.push_back(bp.t);
+                s.near.push_back(bp.src);
+            } else {
+                int pt = bp.t / (n * n), rt = bp.t % (n * n), t2 = rt / n, t1 = rt % n;
+                int ps = bp.src / (n * n), rs = bp.src % (n * n), s2 = rs / n, s1 = rs % n;
+                for (int a2 = 0; a2 < 2; ++a2)
+                    for (int a1 = 0; a1 < 2; ++a1)
+                        for (int b2 = 0; b2 < 2; ++b2)
+                            for (int b1 = 0; b1 < 2; ++b1)
+                                nxt.push_back({pt * nn * nn + (2 * t2 + a2) * nn + 2 * t1 + a1,
+                                               ps * nn * nn + (2 * s2 + b2) * nn + 2 * s1 + b1});
+            }
+        }
+        cur.swap(nxt);
+    }
+    // sort
+    {
+        size_t nb = s.near.size() / 2;
+        std::vector<size_t> idx(nb);
+        std::iota(idx.begin(), idx.end(), 0);
+        std::sort(idx.begin(), idx.end(), [&](size_t x, size_t y) {
+            return std::make_pair(s.near[2 * x], s.near[2 * x + 1]) < std::make_pair(s.near[2 * y], s.near[2 * y + 1]);
+        });
+        std::vector<int32_t> v(s.near.size());
+        for (size_t k = 0; k < nb; ++k) { v[2 * k] = s.near[2 * idx[k]]; v[2 * k + 1] = s.near[2 * idx[k] + 1]; }
+        s.near.swap(v);
+    }
+    {
+        size_t nb = s.far.size() / 3;
+        std::vector<size_t> idx(nb);
+        std::iota(idx.begin(), idx.end(), 0);
+        auto key = [&](size_t x) { return std::make_tuple(s.far[3 * x], s.far[3 * x + 1], s.far[3 * x + 2]); };
+        std::sort(idx.begin(), idx.end(), [&](size_t x, size_t y) { return key(x) < key(y); });
+        std::vector<int32_t> v(s.far.size());
+        for (size_t k = 0; k < nb; ++k)
+            for (int c = 0; c < 3; ++c) v[3 * k + c] = s.far[3 * idx[k] + c];
+        s.far.swap(v);
+    }
+    // CSR structures
+    s.near_ptr.assign(s.nleaf + 1, 0);
+    s.near_src.resize(s.near.size() / 2);
+    for (size_t k = 0; k < s.near.size() / 2; ++k) {
+        s.near_ptr[s.near[2 * k] + 1]++;
+        s.near_src[k] = s.near[2 * k + 1];
+    }
+    for (int i = 0; i < s.nleaf; ++i) s.near_ptr[i + 1] += s.near_ptr[i];
+    int64_t ncl_all = s.cl_off[s.L + 1];
+    s.far_ptr.assign(ncl_all + 1, 0);
+    s.far_src.resize(s.far.size() / 3);
+    for (size_t k = 0; k < s.far.size() / 3; ++k) {
+        int l = s.far[3 * k];
+        s.far_ptr[s.cl_off[l] + s.far[3 * k + 1] + 1]++;
+        s.far_src[k] = (int32_t)(s.cl_off[l] + s.far[3 * k + 2]);
+    }
+    for (int64_t i = 0; i < ncl_all; ++i) s.far_ptr[i + 1] += s.far_ptr[i];
+}
+
+// ---------------------------------------------------------------------------
+// near-field element pairs: classification and frames (same reading as the
+// paper's "order raised towards the singularity"; see build notes)
+// ---------------------------------------------------------------------------
+static const int kCorner[4][2] = {{0, 0}, {1, 0}, {1, 1}, {0, 1}};
+
+static int other_adjacent(int o, int a)
+{
+    int n1 = (o + 1) & 3, n2 = (o + 3) & 3;
+    return a == n1 ? n2 : n1;
+}
+
+static std::string build_pairs(Setup &s)
+{
+    // element corners and 3x3 grids
+    std::vector<double> corner((size_t)s.nelem * 12), grid((size_t)s.nelem * 27), diam(s.nelem);
+    for (int E = 0; E < s.nelem; ++E) {
+        for (int c = 0; c < 4; ++c) tile_eval(s, E, kCorner[c][0], kCorner[c][1], &corner[(size_t)E * 12 + 3 * c], nullptr);
+        for (int b = 0; b < 3; ++b)
+            for (int a = 0; a < 3; ++a) tile_eval(s, E, 0.5 * a, 0.5 * b, &grid[(size_t)E * 27 + 3 * (3 * b + a)], nullptr);
+        double d = 0.0;
+        for (int i = 0; i < 9; ++i)
+            for (int j = i + 1; j < 9; ++j) d = std::max(d, dist(&grid[(size_t)E * 27 + 3 * i], &grid[(size_t)E * 27 + 3 * j]));
+        diam[E] = d;
+    }
+    auto leaf_of = [&](int E, int &el) {
+        int pt = E / (s.ne * s.ne), r = E % (s.ne * s.ne), e2 = r / s.ne, e1 = r % s.ne;
+        int nL = 1 << s.L;
+        el = (e2 % s.side) * s.side + (e1 % s.side);
+        return pt * nL * nL + (e2 / s.side) * nL + (e1 / s.side);
+    };
+    auto block_index = [&](int t, int src) -> int32_t {
+        auto b = s.near_src.begin() + s.near_ptr[t], e = s.near_src.begin() + s.near_ptr[t + 1];
+        auto it = std::lower_bound(b, e, src);
+        if (it == e || *it != src) return -1;
+        return (int32_t)(it - s.near_src.begin());
+    };
+    s.pairs.clear();
+    for (int c = 0; c < 4; ++c) s.npairs_class[c] = 0;
+    int nL = 1 << s.L;
+    for (size_t k = 0; k < s.near.size() / 2; ++k) {
+        int t = s.near[2 * k], src = s.near[2 * k + 1];
+        int pt = t / (nL * nL), rt = t % (nL * nL), t2 = rt / nL, t1 = rt % nL;
+        int ps = src / (nL * nL), rs = src % (nL * nL), s2 = rs / nL, s1 = rs % nL;
+        for (int a2 = 0; a2 < s.side; ++a2)
+            for (int a1 = 0; a1 < s.side; ++a1) {
+                int E = pt * s.ne * s.ne + (t2 * s.side + a2) * s.ne + t1 * s.side + a1;
+                for (int b2 = 0; b2 < s.side; ++b2)
+                    for (int b1 = 0; b1 < s.side; ++b1) {
+                        int F = ps * s.ne * s.ne + (s2 * s.side + b2) * s.ne + s1 * s.side + b1;
+                        if (F < E) continue;
+                        PairRec R;
+                        std::memset(&R, 0, sizeof R);
+                        R.E = E;
+                        R.F = F;
+                        int elE, elF;
+                        int lE = leaf_of(E, elE), lF = leaf_of(F, elF);
+                        R.elE = (int8_t)elE;
+                        R.elF = (int8_t)elF;
+                        R.blk1 = block_index(lE, lF);
+                        R.blk2 = (E == F) ? -1 : block_index(lF, lE);
+                        if (R.blk1 < 0 || (E != F && R.blk2 < 0)) return "near-field partition is not symmetric";
+                        R.oE = 0; R.aE = 1; R.bE = 3; R.oF = 0; R.aF = 1; R.bF = 3;
+                        double md = std::max(diam[E], diam[F]);
+                        if (E == F) {
+                            R.cls = kIdentical;
+                            R.order = s.gs;
+                        } else {
+                            double tol = 1e-10 * md;
+                            int match[4], nsh = 0;
+                            for (int c = 0; c < 4; ++c) {
+                                match[c] = -1;
+                                for (int dd = 0; dd < 4; ++dd)
+                                    if (dist(&corner[(size_t)E * 12 + 3 * c], &corner[(size_t)F * 12 + 3 * dd]) <= tol) match[c] = dd;
+                                if (match[c] >= 0) ++nsh;
+                            }
+                            if (nsh == 2) {
+                                int i = -1, j = -1;
+                                for (int c = 0; c < 4; ++c)
+                                    if (match[c] >= 0) { if (i < 0) i = c; else j = c; }
+                                R.cls = kEdge;
+                                R.order = s.gs;
+                                R.oE = i; R.aE = j; R.bE = other_adjacent(i, j);
+                                R.oF = match[i]; R.aF = match[j]; R.bF = other_adjacent(match[i], match[j]);
+                            } else if (nsh == 1) {
+                                int i = 0;
+                                for (int c = 0; c < 4; ++c)
+                                    if (match[c] >= 0) i = c;
+                                R.cls = kVertex;
+                                R.order = s.gs;
+                                R.oE = i; R.aE = (i + 1) & 3; R.bE = (i + 3) & 3;
+                                int kk = match[i];
+                                R.oF = kk; R.aF = (kk + 1) & 3; R.bF = (kk + 3) & 3;
+                            } else {
+                                double dmin = 1e300;
+                                for (int a = 0; a < 9; ++a)
+                                    for (int b = 0; b < 9; ++b)
+                                        dmin = std::min(dmin, dist(&grid[(size_t)E * 27 + 3 * a], &grid[(size_t)F * 27 + 3 * b]));
+                                double r = dmin / md;
+                                int g = s.g0;
+                                if (r < 0.6) g = s.g0 + 4;
+                                else if (r < 1.2) g = s.g0 + 2;
+                                if (g > 40) g = 40;
+                                R.cls = kRegular;
+                                R.order = g;
+                            }
+                        }
+                        s.npairs_class[R.cls]++;
+                        s.pairs.push_back(R);
+                    }
+            }
+    }
+    std::sort(s.pairs.begin(), s.pairs.end(), [](const PairRec &a, const PairRec &b) {
+        return std::make_pair(a.E, a.F) < std::make_pair(b.E, b.F);
+    });
+    return "";
+}
+
+// ---------------------------------------------------------------------------
+std::string build_setup(const Geometry &geo, const igb_params &prm, Setup &s)
+{
+    auto t0 = std::chrono::steady_clock::now();
+    if (prm.kernel != IGB_LAPLACE && prm.kernel != IGB_HELMHOLTZ) return "kernel must be IGB_LAPLACE or IGB_HELMHOLTZ";
+    if (prm.p < 0 || prm.p > 6) return "p outside 0..6";
+    if (prm.m < 0 || prm.m > 10) return "m outside 0..10";
+    if (prm.q < 1 || prm.q > 16) return "q outside 1..16";
+    if (!(prm.eta > 0.0) || !std::isfinite(prm.eta)) return "eta must be > 0";
+    if (prm.kernel == IGB_HELMHOLTZ && (!(prm.wavenumber >= 0.0) || !std::isfinite(prm.wavenumber)))
+        return "wavenumber must be >= 0";
+    if (prm.gauss_regular < 1 || prm.gauss_regular > 36) return "gauss_regular outside 1..36";
+    if (prm.gauss_singular != -1 && (prm.gauss_singular < 1 || prm.gauss_singular > 40)) return "gauss_singular outside 1..40";
+    if (prm.gauss_rhs != -1 && (prm.gauss_rhs < 1 || prm.gauss_rhs > 40)) return "gauss_rhs outside 1..40";
+    if (prm.mode != IGB_DENSE && prm.mode != IGB_H2_STORED) return "mode must be IGB_DENSE or IGB_H2_STORED";
+    if (prm.far_precision != IGB_FP64) return "far_precision must be IGB_FP64";
+    if (prm.leaf_depth < -1 || prm.leaf_depth > 10) return "leaf_depth outside -1..10";
+
+    s.kernel = prm.kernel;
+    s.kappa = prm.kernel == IGB_HELMHOLTZ ? prm.wavenumber : 0.0;
+    s.p = prm.p;
+    s.m = prm.m;
+    s.q = prm.q;
+    s.eta = prm.eta;
+    s.g0 = prm.gauss_regular;
+    s.gs = prm.gauss_singular > 0 ? prm.gauss_singular : std::min(40, s.g0 + 2);
+    s.grhs = prm.gauss_rhs > 0 ? prm.gauss_rhs : std::max(s.g0, s.p + 4);
+    s.mode = prm.mode;
+    int d = prm.leaf_depth;
+    if (d < 0) {
+        d = 0;
+        while ((s.p + 1) * (s.p + 1) * (1 << (2 * d)) < s.q * s.q && d < s.m) ++d;
+    }
+    d = std::min(d, s.m);
+    if (d > 3) return "leaf_depth > 3 (more than 64 elements per leaf) is not supported";
+    s.d = d;
+    s.L = s.m - d;
+    s.npatch = (int)geo.patches.size();
+    s.ne = 1 << s.m;
+    s.nelem = s.npatch * s.ne * s.ne;
+    s.nloc = (s.p + 1) * (s.p + 1);
+    s.ns1 = s.ne + s.p;
+    s.nsup = (int64_t)s.nelem * s.nloc;
+    s.ndof = (int64_t)s.npatch * s.ns1 * s.ns1;
+    s.side = 1 << d;
+    s.nl = s.side * s.side * s.nloc;
+    s.n1 = s.side * (s.p + 1);
+    s.nleaf = s.npatch << (2 * s.L);
+    s.cl_off.assign(s.L + 2, 0);
+    for (int l = 0; l <= s.L; ++l) s.cl_off[l + 1] = s.cl_off[l] + ((int64_t)s.npatch << (2 * l));
+
+    // Gauss rules 1..40
+    s.goff.assign(42, 0);
+    for (int n = 1; n <= 40; ++n) s.goff[n + 1] = s.goff[n] + n;
+    s.gx.assign(s.goff[41], 0.0);
+    s.gw.assign(s.goff[41], 0.0);
+    for (int n = 1; n <= 40; ++n) gauss_rule(n, &s.gx[s.goff[n]], &s.gw[s.goff[n]]);
+
+    // element tiles by Bezier extraction
+    int pmax = 0;
+    for (const Patch &P : geo.patches) pmax = std::max(pmax, std::max(P.pu, P.pv));
+    s.tile_stride = (pmax + 1) * (pmax + 1) * 4;
+    s.tiles.assign((size_t)s.nelem * s.tile_stride, 0.0);
+    s.tile_deg.assign((size_t)s.nelem * 2, 0);
+    for (int pt = 0; pt < s.npatch; ++pt) {
+        const Patch &P = geo.patches[pt];
+        std::vector<double> Mu, Mv;
+        int nru, nrv;
+        std::string err = extraction(P.pu, P.U, P.nu, s.ne, Mu, nru);
+        if (!err.empty()) return "patch " + std::to_string(pt) + " u: " + err;
+        err = extraction(P.pv, P.V, P.nv, s.ne, Mv, nrv);
+        if (!err.empty()) return "patch " + std::to_string(pt) + " v: " + err;
+        int su = std::max(P.pu, 1) , sv = std::max(P.pv, 1);
+        if (P.pu == 0) su = 1;
+        if (P.pv == 0) sv = 1;
+        for (int e2 = 0; e2 < s.ne; ++e2)
+            for (int e1 = 0; e1 < s.ne; ++e1) {
+                int E = pt * s.ne * s.ne + e2 * s.ne + e1;
+                s.tile_deg[2 * E] = P.pu;
+                s.tile_deg[2 * E + 1] = P.pv;
+                double *H = &s.tiles[(size_t)E * s.tile_stride];
+                for (int rv = 0; rv <= P.pv; ++rv)
+                    for (int ru = 0; ru <= P.pu; ++ru) {
+                        int ku = (P.pu == 0 ? e1 : e1 * su + ru), kv = (P.pv == 0 ? e2 : e2 * sv + rv);
+                        double acc[4] = {0, 0, 0, 0};
+                        for (int j = 0; j < P.nv; ++j) {
+                            double cv = Mv[(size_t)kv * P.nv + j];
+                            if (cv == 0.0) continue;
+                            for (int i = 0; i < P.nu; ++i) {
+                                double cu = Mu[(size_t)ku * P.nu + i];
+                                if (cu == 0.0) continue;
+                                const double *c = &P.cpw[4 * ((size_t)j * P.nu + i)];
+                                double f = cu * cv * c[3];
+                                acc[0] += f * c[0];
+                                acc[1] += f * c[1];
+                                acc[2] += f * c[2];
+                                acc[3] += f;
+                            }
+                        }
+                        double *h = H + 4 * (rv * (P.pu + 1) + ru);
+                        for (int c = 0; c < 4; ++c) h[c] = acc[c];
+                    }
+            }
+    }
+    // T band on Xi_{p,m}
+    {
+        int p = s.p;
+        std::vector<double> U(s.ns1 + p + 1);
+        for (int i = 0; i <= p; ++i) { U[i] = 0.0; U[s.ns1 + i] = 1.0; }
+        for (int i = 1; i < s.ne; ++i) U[p + i] = (double)i / s.ne;
+        std::vector<double> M;
+        int nr;
+        std::string err = extraction(p, U, s.ns1, s.ne, M, nr);
+        if (!err.empty()) return "spline space: " + err;
+        s.Tb.assign((size_t)s.ne * (p + 1) * (p + 1), 0.0);
+        for (int e = 0; e < s.ne; ++e)
+            for (int r = 0; r <= p; ++r)
+                for (int jj = 0; jj <= p; ++jj) {
+                    int j = e + jj;
+                    int k = (p == 0) ? e : e * p + r;
+                    s.Tb[((size_t)e * (p + 1) + r) * (p + 1) + jj] = (j < s.ns1) ? M[(size_t)k * s.ns1 + j] : 0.0;
+                }
+    }
+    // Chebyshev nodes, moments, transfers
+    s.z.resize(s.q);
+    for (int k = 0; k < s.q; ++k) s.z[k] = 0.5 * (1.0 + std::cos((2.0 * k + 1.0) * M_PI / (2.0 * s.q)));
+    {
+        int ng = (s.q + s.p) / 2 + 2;
+        const double *x = &s.gx[s.goff[ng]], *w = &s.gw[s.goff[ng]];
+        auto mom = [&](int nsub, int el, int r, int mu) {
+            double acc = 0.0;
+            double B[16];
+            for (int i = 0; i < ng; ++i) {
+                bern(s.p, x[i], B, nullptr);
+                acc += w[i] * lagr(s.z, mu, (el + x[i]) / nsub) * B[r];
+            }
+            return acc / nsub;
+        };
+        s.M1.assign((size_t)s.n1 * s.q, 0.0);
+        for (int el = 0; el < s.side; ++el)
+            for (int r = 0; r <= s.p; ++r)
+                for (int mu = 0; mu < s.q; ++mu) s.M1[(size_t)(el * (s.p + 1) + r) * s.q + mu] = mom(s.side, el, r, mu);
+        s.E2.assign((size_t)2 * s.q * s.q, 0.0);
+        for (int c = 0; c < 2; ++c)
+            for (int nu = 0; nu < s.q; ++nu)
+                for (int mu = 0; mu < s.q; ++mu) s.E2[((size_t)c * s.q + nu) * s.q + mu] = lagr(s.z, mu, 0.5 * (c + s.z[nu]));
+        s.Mlev_off.assign(s.L + 2, 0);
+        for (int l = 0; l <= s.L; ++l) s.Mlev_off[l + 1] = s.Mlev_off[l] + (int64_t)(s.ne >> l) * (s.p + 1) * s.q;
+        s.Mlev.assign(s.Mlev_off[s.L + 1], 0.0);
+        for (int l = 0; l <= s.L; ++l) {
+            int nsub = s.ne >> l;
+            for (int el = 0; el < nsub; ++el)
+                for (int r = 0; r <= s.p; ++r)
+                    for (int mu = 0; mu < s.q; ++mu)
+                        s.Mlev[s.Mlev_off[l] + (size_t)(el * (s.p + 1) + r) * s.q + mu] = mom(nsub, el, r, mu);
+        }
+    }
+    build_partition(s);
+    std::string perr = build_pairs(s);
+    if (!perr.empty()) return perr;
+    s.setup_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    return "";
+}
+
+}  // namespace igb

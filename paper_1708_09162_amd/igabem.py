@@ -1,0 +1,395 @@
+"""Thin ctypes binding of libigabem (declared in include/igabem.h).
+
+Argument marshalling only: every step of the method runs in the library's HIP
+kernels.  Device vectors are torch tensors on the GPU (float64, or complex128
+for Helmholtz); the operator runs on the torch stream that is current when it
+is created.  There is no CPU fallback: if the shared library is missing or
+cannot be loaded, importing this module raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libigabem.so")
+
+IGB_OK = 0
+IGB_ENOT_CONVERGED = 1
+IGB_EINVAL = -1
+IGB_EHIP = -2
+IGB_ENOMEM = -3
+IGB_EUNSUPPORTED = -4
+IGB_LAPLACE = 0
+IGB_HELMHOLTZ = 1
+IGB_DENSE = 0
+IGB_H2_STORED = 1
+IGB_FP64 = 0
+
+EXPORTED = [
+    "igb_last_error", "igb_geometry_create", "igb_geometry_destroy", "igb_operator_create",
+    "igb_operator_destroy", "igb_operator_info", "igb_rhs_points", "igb_rhs_assemble", "igb_matvec",
+    "igb_matvec_super", "igb_apply_Tt", "igb_apply_T", "igb_jacobi_diag", "igb_solve", "igb_potential",
+    "igb_export_partition", "igb_export_pair_classes", "igb_export_near_block", "igb_export_coupling_block",
+    "igb_plan_create", "igb_plan_destroy", "igb_plan_info", "igb_plan_export_partition",
+    "igb_plan_export_pair_classes",
+]
+
+
+class igb_nurbs_patch(C.Structure):
+    _fields_ = [("deg_u", C.c_int32), ("deg_v", C.c_int32), ("n_u", C.c_int32), ("n_v", C.c_int32),
+                ("knots_u", C.POINTER(C.c_double)), ("knots_v", C.POINTER(C.c_double)),
+                ("cpw", C.POINTER(C.c_double))]
+
+
+class igb_params(C.Structure):
+    _fields_ = [("kernel", C.c_int32), ("wavenumber", C.c_double), ("p", C.c_int32), ("m", C.c_int32),
+                ("q", C.c_int32), ("eta", C.c_double), ("leaf_depth", C.c_int32), ("gauss_regular", C.c_int32),
+                ("gauss_singular", C.c_int32), ("gauss_rhs", C.c_int32), ("mode", C.c_int32),
+                ("far_precision", C.c_int32)]
+
+
+class igb_info(C.Structure):
+    _fields_ = [("n_dof", C.c_int64), ("n_dof_super", C.c_int64), ("n_elements", C.c_int64),
+                ("n_rhs_points", C.c_int64), ("leaf_level", C.c_int32), ("gauss_singular", C.c_int32),
+                ("gauss_rhs", C.c_int32), ("pad0", C.c_int32), ("n_near_blocks", C.c_int64),
+                ("n_far_blocks", C.c_int64), ("n_pairs", C.c_int64 * 4), ("near_bytes", C.c_int64),
+                ("coupling_bytes", C.c_int64), ("matvec_bytes", C.c_int64), ("setup_seconds", C.c_double),
+                ("assembly_seconds", C.c_double)]
+
+
+class igb_solve_info(C.Structure):
+    _fields_ = [("iterations", C.c_int32), ("converged", C.c_int32), ("rel_residual", C.c_double)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"libigabem.so not built at {LIB_PATH}; run paper_1708_09162_amd/build.py")
+    lib = C.CDLL(LIB_PATH)
+    vp, dp, ip = C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int32)
+    sig = {
+        "igb_last_error": (C.c_char_p, []),
+        "igb_geometry_create": (C.c_int32, [C.c_int32, C.POINTER(igb_nurbs_patch), C.POINTER(vp)]),
+        "igb_geometry_destroy": (None, [vp]),
+        "igb_operator_create": (C.c_int32, [vp, C.POINTER(igb_params), vp, C.POINTER(vp)]),
+        "igb_operator_destroy": (None, [vp]),
+        "igb_operator_info": (C.c_int32, [vp, C.POINTER(igb_info)]),
+        "igb_rhs_points": (C.c_int32, [vp, vp]),
+        "igb_rhs_assemble": (C.c_int32, [vp, vp, vp]),
+        "igb_matvec": (C.c_int32, [vp, vp, vp]),
+        "igb_matvec_super": (C.c_int32, [vp, vp, vp]),
+        "igb_apply_Tt": (C.c_int32, [vp, vp, vp]),
+        "igb_apply_T": (C.c_int32, [vp, vp, vp]),
+        "igb_jacobi_diag": (C.c_int32, [vp, vp]),
+        "igb_solve": (C.c_int32, [vp, vp, vp, C.c_double, C.c_int32, C.c_int32, C.POINTER(igb_solve_info)]),
+        "igb_potential": (C.c_int32, [vp, vp, C.c_int64, vp, vp]),
+        "igb_export_partition": (C.c_int32, [vp, ip, ip]),
+        "igb_export_pair_classes": (C.c_int32, [vp, ip]),
+        "igb_export_near_block": (C.c_int32, [vp, C.c_int32, C.c_int32, dp]),
+        "igb_export_coupling_block": (C.c_int32, [vp, C.c_int32, C.c_int32, C.c_int32, dp]),
+        "igb_plan_create": (C.c_int32, [vp, C.POINTER(igb_params), C.POINTER(vp)]),
+        "igb_plan_destroy": (None, [vp]),
+        "igb_plan_info": (C.c_int32, [vp, C.POINTER(igb_info)]),
+        "igb_plan_export_partition": (C.c_int32, [vp, ip, ip]),
+        "igb_plan_export_pair_classes": (C.c_int32, [vp, ip]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    return lib
+
+
+_lib = _load()
+
+
+class IgbError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"libigabem status {status}: {msg}")
+        self.status = status
+
+
+def igb_last_error() -> str:
+    return (_lib.igb_last_error() or b"").decode()
+
+
+def _check(status: int, allow=(IGB_OK,)):
+    if status not in allow:
+        raise IgbError(status, igb_last_error())
+    return status
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr())
+
+
+# ---------------------------------------------------------------------------
+# same-name wrappers of the C entry points
+# ---------------------------------------------------------------------------
+def igb_geometry_create(patches) -> C.c_void_p:
+    """patches: list of dicts with deg_u, deg_v, knots_u, knots_v, cpw (n_v, n_u, 4)."""
+    keep, arr = [], (igb_nurbs_patch * len(patches))()
+    for i, p in enumerate(patches):
+        cpw = np.ascontiguousarray(p["cpw"], dtype=np.float64)
+        ku = np.ascontiguousarray(p["knots_u"], dtype=np.float64)
+        kv = np.ascontiguousarray(p["knots_v"], dtype=np.float64)
+        keep += [cpw, ku, kv]
+        arr[i] = igb_nurbs_patch(int(p["deg_u"]), int(p["deg_v"]), cpw.shape[1], cpw.shape[0],
+                                 ku.ctypes.data_as(C.POINTER(C.c_double)), kv.ctypes.data_as(C.POINTER(C.c_double)),
+                                 cpw.ctypes.data_as(C.POINTER(C.c_double)))
+    h = C.c_void_p()
+    _check(_lib.igb_geometry_create(len(patches), arr, C.byref(h)))
+    return h
+
+
+def igb_geometry_destroy(h):
+    _lib.igb_geometry_destroy(h)
+
+
+def igb_operator_create(geo, prm: igb_params, stream) -> C.c_void_p:
+    h = C.c_void_p()
+    _check(_lib.igb_operator_create(geo, C.byref(prm), C.c_void_p(stream), C.byref(h)))
+    return h
+
+
+def igb_operator_destroy(h):
+    _lib.igb_operator_destroy(h)
+
+
+def igb_operator_info(op) -> igb_info:
+    out = igb_info()
+    _check(_lib.igb_operator_info(op, C.byref(out)))
+    return out
+
+
+def igb_rhs_points(op, xyz):
+    _check(_lib.igb_rhs_points(op, _ptr(xyz)))
+
+
+def igb_rhs_assemble(op, g, b):
+    _check(_lib.igb_rhs_assemble(op, _ptr(g), _ptr(b)))
+
+
+def igb_matvec(op, x, y):
+    _check(_lib.igb_matvec(op, _ptr(x), _ptr(y)))
+
+
+def igb_matvec_super(op, xs, ys):
+    _check(_lib.igb_matvec_super(op, _ptr(xs), _ptr(ys)))
+
+
+def igb_apply_Tt(op, w, xs):
+    _check(_lib.igb_apply_Tt(op, _ptr(w), _ptr(xs)))
+
+
+def igb_apply_T(op, ys, y):
+    _check(_lib.igb_apply_T(op, _ptr(ys), _ptr(y)))
+
+
+def igb_jacobi_diag(op, d):
+    _check(_lib.igb_jacobi_diag(op, _ptr(d)))
+
+
+def igb_solve(op, b, w, rel_tol, max_iter, restart) -> igb_solve_info:
+    info = igb_solve_info()
+    _check(_lib.igb_solve(op, _ptr(b), _ptr(w), float(rel_tol), int(max_iter), int(restart), C.byref(info)),
+           allow=(IGB_OK, IGB_ENOT_CONVERGED))
+    return info
+
+
+def igb_potential(op, w, xyz, u):
+    n = xyz.shape[0]
+    _check(_lib.igb_potential(op, _ptr(w), int(n), _ptr(xyz) if n else None, _ptr(u) if n else None))
+
+
+def igb_export_partition(op, info: igb_info):
+    near = np.zeros((info.n_near_blocks, 2), dtype=np.int32)
+    far = np.zeros((info.n_far_blocks, 3), dtype=np.int32)
+    _check(_lib.igb_export_partition(op, near.ctypes.data_as(C.POINTER(C.c_int32)),
+                                     far.ctypes.data_as(C.POINTER(C.c_int32))))
+    return near, far
+
+
+def igb_export_pair_classes(op, info: igb_info):
+    n = int(sum(info.n_pairs))
+    out = np.zeros((n, 4), dtype=np.int32)
+    _check(_lib.igb_export_pair_classes(op, out.ctypes.data_as(C.POINTER(C.c_int32))))
+    return out
+
+
+def igb_export_near_block(op, E, F, nloc, cplx):
+    out = np.zeros((nloc, nloc, 2 if cplx else 1))
+    _check(_lib.igb_export_near_block(op, int(E), int(F), out.ctypes.data_as(C.POINTER(C.c_double))))
+    return out[..., 0] + 1j * out[..., 1] if cplx else out[..., 0]
+
+
+def igb_export_coupling_block(op, level, tgt, src, q2, cplx):
+    out = np.zeros((q2, q2, 2 if cplx else 1))
+    _check(_lib.igb_export_coupling_block(op, int(level), int(tgt), int(src),
+                                          out.ctypes.data_as(C.POINTER(C.c_double))))
+    return out[..., 0] + 1j * out[..., 1] if cplx else out[..., 0]
+
+
+def make_params(*, kernel=IGB_LAPLACE, wavenumber=0.0, p=1, m=2, q=8, eta=1.6, leaf_depth=-1, gauss_regular=6,
+                gauss_singular=-1, gauss_rhs=-1, mode=IGB_H2_STORED) -> igb_params:
+    return igb_params(int(kernel), float(wavenumber), int(p), int(m), int(q), float(eta), int(leaf_depth),
+                      int(gauss_regular), int(gauss_singular), int(gauss_rhs), int(mode), IGB_FP64)
+
+
+def igb_plan_create(geo, prm: igb_params):
+    h = C.c_void_p()
+    _check(_lib.igb_plan_create(geo, C.byref(prm), C.byref(h)))
+    return h
+
+
+def igb_plan_destroy(h):
+    _lib.igb_plan_destroy(h)
+
+
+def igb_plan_info(plan) -> igb_info:
+    out = igb_info()
+    _check(_lib.igb_plan_info(plan, C.byref(out)))
+    return out
+
+
+def igb_plan_export_partition(plan, info: igb_info):
+    near = np.zeros((info.n_near_blocks, 2), dtype=np.int32)
+    far = np.zeros((info.n_far_blocks, 3), dtype=np.int32)
+    _check(_lib.igb_plan_export_partition(plan, near.ctypes.data_as(C.POINTER(C.c_int32)),
+                                          far.ctypes.data_as(C.POINTER(C.c_int32))))
+    return near, far
+
+
+def igb_plan_export_pair_classes(plan, info: igb_info):
+    out = np.zeros((int(sum(info.n_pairs)), 4), dtype=np.int32)
+    _check(_lib.igb_plan_export_pair_classes(plan, out.ctypes.data_as(C.POINTER(C.c_int32))))
+    return out
+
+
+class Plan:
+    """Host-only plan: partition and pair classification without GPU work."""
+
+    def __init__(self, geometry: "Geometry", **params):
+        self.geometry = geometry
+        self.h = igb_plan_create(geometry.h, make_params(**params))
+        self.info = igb_plan_info(self.h)
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            igb_plan_destroy(self.h)
+            self.h = None
+
+    def partition(self):
+        return igb_plan_export_partition(self.h, self.info)
+
+    def pair_classes(self):
+        return igb_plan_export_pair_classes(self.h, self.info)
+
+
+# ---------------------------------------------------------------------------
+# convenience objects (still only marshalling)
+# ---------------------------------------------------------------------------
+class Geometry:
+    def __init__(self, patches):
+        self.h = igb_geometry_create(patches)
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            igb_geometry_destroy(self.h)
+            self.h = None
+
+
+class Operator:
+    """An assembled single-layer operator on the current torch CUDA (HIP) stream."""
+
+    def __init__(self, geometry: Geometry, *, kernel=IGB_LAPLACE, wavenumber=0.0, p=1, m=2, q=8, eta=1.6,
+                 leaf_depth=-1, gauss_regular=6, gauss_singular=-1, gauss_rhs=-1, mode=IGB_H2_STORED,
+                 device="cuda:0"):
+        import torch
+
+        self.torch = torch
+        self.device = torch.device(device)
+        self.geometry = geometry
+        prm = make_params(kernel=kernel, wavenumber=wavenumber, p=p, m=m, q=q, eta=eta, leaf_depth=leaf_depth,
+                          gauss_regular=gauss_regular, gauss_singular=gauss_singular, gauss_rhs=gauss_rhs, mode=mode)
+        with torch.cuda.device(self.device):
+            self.stream = torch.cuda.current_stream(self.device)
+            self.h = igb_operator_create(geometry.h, prm, self.stream.cuda_stream)
+        self.info = igb_operator_info(self.h)
+        self.cplx = kernel == IGB_HELMHOLTZ
+        self.dtype = torch.complex128 if self.cplx else torch.float64
+        self.p, self.q = p, q
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            igb_operator_destroy(self.h)
+            self.h = None
+
+    def _vec(self, n):
+        return self.torch.zeros(int(n), dtype=self.dtype, device=self.device)
+
+    def _in(self, t, n):
+        t = t.to(device=self.device, dtype=self.dtype).contiguous()
+        if t.numel() != n:
+            raise ValueError(f"expected {n} values, got {t.numel()}")
+        return t
+
+    def rhs_points(self):
+        xyz = self.torch.zeros((self.info.n_rhs_points, 3), dtype=self.torch.float64, device=self.device)
+        igb_rhs_points(self.h, xyz)
+        return xyz
+
+    def rhs(self, g):
+        b = self._vec(self.info.n_dof)
+        igb_rhs_assemble(self.h, self._in(g, self.info.n_rhs_points), b)
+        return b
+
+    def matvec(self, x):
+        y = self._vec(self.info.n_dof)
+        igb_matvec(self.h, self._in(x, self.info.n_dof), y)
+        return y
+
+    def matvec_super(self, xs):
+        ys = self._vec(self.info.n_dof_super)
+        igb_matvec_super(self.h, self._in(xs, self.info.n_dof_super), ys)
+        return ys
+
+    def apply_Tt(self, w):
+        xs = self._vec(self.info.n_dof_super)
+        igb_apply_Tt(self.h, self._in(w, self.info.n_dof), xs)
+        return xs
+
+    def apply_T(self, ys):
+        y = self._vec(self.info.n_dof)
+        igb_apply_T(self.h, self._in(ys, self.info.n_dof_super), y)
+        return y
+
+    def jacobi_diag(self):
+        d = self._vec(self.info.n_dof)
+        igb_jacobi_diag(self.h, d)
+        return d
+
+    def solve(self, b, w0=None, tol=1e-8, max_iter=1000, restart=100):
+        w = self._vec(self.info.n_dof) if w0 is None else self._in(w0, self.info.n_dof).clone()
+        info = igb_solve(self.h, self._in(b, self.info.n_dof), w, tol, max_iter, restart)
+        return w, info
+
+    def potential(self, w, points):
+        pts = self.torch.as_tensor(points, dtype=self.torch.float64).to(self.device).reshape(-1, 3).contiguous()
+        u = self._vec(pts.shape[0])
+        igb_potential(self.h, self._in(w, self.info.n_dof), pts, u)
+        return u
+
+    def partition(self):
+        return igb_export_partition(self.h, self.info)
+
+    def pair_classes(self):
+        return igb_export_pair_classes(self.h, self.info)
+
+    def near_block(self, E, F):
+        return igb_export_near_block(self.h, E, F, (self.p + 1) ** 2, self.cplx)
+
+    def coupling_block(self, level, tgt, src):
+        return igb_export_coupling_block(self.h, level, tgt, src, self.q * self.q, self.cplx)

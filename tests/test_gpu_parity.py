@@ -1,0 +1,281 @@
+"""GPU parity: the HIP path (through the C-ABI) against the FP64 CPU oracle, element by element.
+
+Bars: superspace / S matvec within 1e-12 relative l2; stored blocks within 1e-12 of their scale;
+solved densities (both sides solved to relative residual 1e-13) within 1e-10; potentials computed
+from the same density within 1e-12; integer/partition data bit-exact (checked on the CPU in
+test_abi_host.py).
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1708_09162_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+igb = pytest.importorskip("paper_1708_09162_amd.igabem")
+
+DEV = "cuda:0"
+
+
+def say(msg):
+    print(f"[gpu-parity] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+def rel(a, b):
+    a, b = np.asarray(a), np.asarray(b)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def make(patches, dense=False, **kw):
+    """(gpu operator, oracle problem) with identical parameters."""
+    g = igb.Geometry(patches)
+    mode = igb.IGB_DENSE if dense else igb.IGB_H2_STORED
+    op = igb.Operator(g, mode=mode, device=DEV, **kw)
+    okw = {k: v for k, v in kw.items() if k in ("p", "m", "q", "eta", "leaf_depth", "gauss_regular", "gauss_singular",
+                                                 "gauss_rhs")}
+    if "kernel" in kw:
+        okw["kernel"] = kw["kernel"]
+        okw["wavenumber"] = kw.get("wavenumber", 0.0)
+    if dense:
+        okw["eta"] = 1e-12
+    P = oracle.Problem(patches, **okw)
+    return op, P
+
+
+def to_np(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def rand(n, seed, cplx=False):
+    rng = np.random.default_rng(seed)
+    v = rng.standard_normal(n)
+    if cplx:
+        v = v + 1j * rng.standard_normal(n)
+    return v
+
+
+# ---------------------------------------------------------------------------
+# dense (every pair in the near field): 6-patch sphere, p=1, 4x4 elements per patch, Gauss 6
+# ---------------------------------------------------------------------------
+@pytest.fixture(scope="module")
+def small():
+    say("small dense sphere p=1 m=2 g0=6: assemble")
+    cfg = W.config_small_sphere()
+    op, P = make(cfg["patches"], dense=True, p=1, m=2, q=8, gauss_regular=6)
+    A = P.dense_super()
+    return cfg, op, P, A
+
+
+def test_small_T_and_Tt(small):
+    _, op, P, _ = small
+    say("small: T, T^T")
+    w = rand(P.ndof, 1)
+    assert rel(to_np(op.apply_Tt(torch.tensor(w))), P.apply_Tt(w)) < 1e-14
+    ys = rand(P.nsup, 2)
+    assert rel(to_np(op.apply_T(torch.tensor(ys))), P.apply_T(ys)) < 1e-14
+
+
+def test_small_near_blocks_every_class(small):
+    _, op, P, A = small
+    say("small: near blocks")
+    pairs = op.pair_classes()
+    seen = set()
+    for E, F, cls, order in pairs:
+        if cls in seen and cls != 0:
+            continue
+        if cls == 0 and len(seen & {0}) and (E + F) % 17:
+            continue
+        seen.add(int(cls))
+        g = op.near_block(E, F)
+        o = P.pair_block(E, F)
+        assert np.abs(g - o).max() <= 1e-12 * np.abs(o).max(), (E, F, cls)
+        # the mirrored block is the exact transpose
+        assert np.array_equal(op.near_block(F, E), g.T)
+    assert seen == {0, 1, 2, 3}
+
+
+def test_small_superspace_matvec(small):
+    _, op, P, A = small
+    say("small: superspace matvec")
+    xs = rand(P.nsup, 3)
+    ys = to_np(op.matvec_super(torch.tensor(xs)))
+    assert rel(ys, A @ xs) < 1e-12
+
+
+def test_small_matvec(small):
+    _, op, P, A = small
+    say("small: S matvec")
+    x = rand(P.ndof, 4)
+    y = to_np(op.matvec(torch.tensor(x)))
+    assert rel(y, P.matvec(x, dense=True)) < 1e-12
+
+
+def test_small_rhs_points_and_rhs(small):
+    cfg, op, P, _ = small
+    say("small: rhs")
+    pts = to_np(op.rhs_points())
+    assert np.abs(pts - P.rhs_points()).max() < 1e-14
+    g = 1.0 / np.linalg.norm(pts - cfg["source"], axis=1)
+    b = to_np(op.rhs(torch.tensor(g)))
+    assert rel(b, P.rhs(g)) < 1e-13
+
+
+def test_small_jacobi_diag(small):
+    _, op, P, _ = small
+    say("small: jacobi diagonal")
+    assert rel(to_np(op.jacobi_diag()), P.jacobi_diag(dense=True)) < 1e-12
+
+
+def test_small_solve_and_potential(small):
+    cfg, op, P, _ = small
+    say("small: solve + potential")
+    pts = P.rhs_points()
+    g = 1.0 / np.linalg.norm(pts - cfg["source"], axis=1)
+    b = P.rhs(g)
+    w_ref = np.linalg.solve(P.dense_system(), b)
+    w, info = op.solve(torch.tensor(b), tol=1e-13, max_iter=500)
+    assert info.converged == 1 and info.rel_residual <= 1e-13
+    wn = to_np(w)
+    assert rel(wn, w_ref) < 1e-10
+    ev = cfg["eval_points"]
+    u = to_np(op.potential(torch.tensor(wn), ev))
+    u_ref = P.potential(P.apply_Tt(wn), ev)
+    assert rel(u, u_ref) < 1e-12
+    exact = 1.0 / np.linalg.norm(ev - cfg["source"], axis=1)
+    e_gpu, e_or = np.abs(u - exact).max(), np.abs(P.potential(P.apply_Tt(w_ref), ev) - exact).max()
+    assert abs(e_gpu - e_or) <= 1e-10 * max(e_or, 1e-16) + 1e-14
+    # a 1e-8 solve converges too and reports its true residual
+    w8, info8 = op.solve(torch.tensor(b), tol=1e-8, max_iter=500)
+    assert info8.converged == 1 and info8.rel_residual <= 1e-8
+
+
+def test_small_not_converged_and_alias_errors(small):
+    _, op, P, _ = small
+    say("small: error paths")
+    b = torch.tensor(rand(P.ndof, 5), device=DEV)
+    w, info = op.solve(b, tol=1e-14, max_iter=1)
+    assert info.converged == 0 and info.iterations == 1
+    with pytest.raises(igb.IgbError) as e:
+        igb.igb_matvec(op.h, b, b)
+    assert e.value.status == igb.IGB_EINVAL
+
+
+# ---------------------------------------------------------------------------
+# H2 (nested bases, stored coupling): several levels of far field
+# ---------------------------------------------------------------------------
+H2_CASES = {
+    "sphere_p1_m3_q4": (W.sphere_patches, dict(p=1, m=3, q=4, leaf_depth=1, eta=1.6, gauss_regular=6)),
+    "sphere_p3_m3_q8": (W.sphere_patches, dict(p=3, m=3, q=8, eta=1.6, gauss_regular=6)),
+    "torus_p2_m2_q4": (W.torus_patches, dict(p=2, m=2, q=4, leaf_depth=1, eta=1.6, gauss_regular=6)),
+    "sphere_p0_m4_q3": (W.sphere_patches, dict(p=0, m=4, q=3, leaf_depth=1, eta=1.6, gauss_regular=4)),
+}
+
+
+@pytest.mark.parametrize("case", list(H2_CASES))
+def test_h2_superspace_matvec(case):
+    geo, kw = H2_CASES[case]
+    say(f"h2 {case}: assemble")
+    op, P = make(geo(), **kw)
+    assert op.info.n_far_blocks > 0
+    P.h2_assemble(store_coupling=True)
+    xs = rand(P.nsup, 6)
+    say(f"h2 {case}: matvec")
+    ys = to_np(op.matvec_super(torch.tensor(xs)))
+    assert rel(ys, P.h2_matvec_super(xs)) < 1e-12
+    near, far = op.partition()
+    for lv, t, s in far[:: max(1, len(far) // 7)]:
+        g = op.coupling_block(lv, t, s)
+        o = P.coupling_block(lv, t, s)
+        assert np.abs(g - o).max() <= 1e-13 * np.abs(o).max()
+    x = rand(P.ndof, 7)
+    assert rel(to_np(op.matvec(torch.tensor(x))), P.matvec(x)) < 1e-12
+    say(f"h2 {case}: jacobi diagonal")
+    assert rel(to_np(op.jacobi_diag()), P.jacobi_diag()) < 1e-12
+
+
+def test_h2_solve_density_parity():
+    say("h2 solve: sphere p=1 m=3 q=4")
+    op, P = make(W.sphere_patches(), p=1, m=3, q=4, leaf_depth=1, eta=1.6, gauss_regular=6)
+    P.h2_assemble(store_coupling=True)
+    pos, qs = W.point_charges(4, 2)
+    pts = P.rhs_points()
+    g = W.laplace_charge_field(pts, pos, qs)
+    b = P.rhs(g)
+    w_or, it_or, rr_or = P.solve(b, tol=1e-13, maxit=3000)
+    w, info = op.solve(torch.tensor(b), tol=1e-13, max_iter=3000)
+    assert info.converged == 1 and rr_or <= 1e-13
+    assert rel(to_np(w), w_or) < 1e-10
+
+
+# ---------------------------------------------------------------------------
+# Helmholtz
+# ---------------------------------------------------------------------------
+def test_helmholtz_dense_sphere():
+    say("helmholtz dense sphere k=1 p=1 m=1")
+    k = 1.0
+    op, P = make(W.sphere_patches(), dense=True, kernel=igb.IGB_HELMHOLTZ, wavenumber=k, p=1, m=1, q=2,
+                 gauss_regular=6)
+    A = P.dense_super()
+    xs = rand(P.nsup, 8, cplx=True)
+    assert rel(to_np(op.matvec_super(torch.tensor(xs))), A @ xs) < 1e-12
+    v = np.array([0.1, -0.2, 0.15])
+    pts = P.rhs_points()
+    b = P.rhs(W.helmholtz_point_source(pts, v, k))
+    w_ref = np.linalg.solve(P.dense_system(), b)
+    w, info = op.solve(torch.tensor(b), tol=1e-13, max_iter=400, restart=50)
+    assert info.converged == 1
+    assert rel(to_np(w), w_ref) < 1e-10
+    ev = 6.0 * W.random_directions(8, 11)
+    u = to_np(op.potential(torch.tensor(to_np(w)), ev))
+    assert rel(u, P.potential(P.apply_Tt(to_np(w)), ev)) < 1e-12
+    assert rel(to_np(op.jacobi_diag()), P.jacobi_diag(dense=True)) < 1e-12
+
+
+def test_helmholtz_h2_torus():
+    say("helmholtz h2 torus k=2 p=1 m=2 q=4")
+    op, P = make(W.torus_patches(), kernel=igb.IGB_HELMHOLTZ, wavenumber=2.0, p=1, m=2, q=4, leaf_depth=1, eta=1.6,
+                 gauss_regular=6)
+    assert op.info.n_far_blocks > 0
+    P.h2_assemble(store_coupling=True)
+    xs = rand(P.nsup, 9, cplx=True)
+    assert rel(to_np(op.matvec_super(torch.tensor(xs))), P.h2_matvec_super(xs)) < 1e-12
+    assert rel(to_np(op.jacobi_diag()), P.jacobi_diag()) < 1e-12
+
+
+# ---------------------------------------------------------------------------
+# full size (the benchmark workload): sphere p=3, 32x32 elements per patch, q=8, eta=1.6
+# ---------------------------------------------------------------------------
+def test_full_size_sampled_rows():
+    say("full size sphere p=3 m=5 q=8: assemble")
+    cfg = W.config_sphere_h2()
+    op, P = make(cfg["patches"], p=3, m=5, q=8, eta=1.6, gauss_regular=6)
+    xs = rand(P.nsup, 10)
+    say("full size: matvec")
+    ys = to_np(op.matvec_super(torch.tensor(xs)))
+    rng = np.random.default_rng(11)
+    leaves = np.sort(rng.choice(6 * 16 * 16, 12, replace=False)).astype(np.int32)
+    say("full size: oracle rows")
+    rows = P.h2_matvec_rows(xs, leaves)
+    ne, side, n = 32, 2, 16
+    got = []
+    for li, leaf in enumerate(leaves):
+        pt, r = divmod(int(leaf), n * n)
+        k2, k1 = divmod(r, n)
+        for a2 in range(side):
+            for a1 in range(side):
+                E = pt * ne * ne + (k2 * side + a2) * ne + k1 * side + a1
+                got.append(ys[E * 16:(E + 1) * 16])
+    assert rel(np.concatenate(got), rows.reshape(-1)) < 1e-12
+    # symmetry of the assembled operator (Galerkin matrix is symmetric)
+    zs = rand(P.nsup, 12)
+    yz = to_np(op.matvec_super(torch.tensor(zs)))
+    assert abs(zs @ ys - xs @ yz) <= 1e-12 * abs(zs @ ys)

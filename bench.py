@@ -1,0 +1,273 @@
+#!/usr/bin/env python3
+"""Time-to-solve and H2 matvec bandwidth of the isogeometric single-layer BEM on one MI355X.
+
+Workload (the metric's configuration): interior Laplace Dirichlet problem on the unit sphere given
+as 6 exact rational NURBS patches, spline degree p=3, 32x32 elements per patch (m=5; dim S = 7,350,
+dim S* = 98,304), H2 compression with q=8 Chebyshev nodes per parametric direction and eta=1.6,
+Gauss order 6; Dirichlet data from 4 seeded exterior point charges; Jacobi-preconditioned CG to
+true relative residual 1e-8; potential at 100 seeded interior points.
+
+One step = operator assembly (Bezier extraction, partition, near-field quadrature, coupling blocks,
+Jacobi diagonal) + right-hand side + solve + potential: the whole hot path once.  Inputs (the NURBS
+control nets, 24 KB) are host data handed to the library; everything after that runs on the GPU.
+
+Prints one JSON line.  Extra keys: h2_matvec_GBps (algorithmic bytes of one matvec / median time of
+igb_matvec), per-stage matvec times, roofline of the dominant matvec kernel, and the CPU oracle
+baseline projected from a timed sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "time-to-solve (rel res 1e-8) + H2 matvec GB/s; mixed/learned vs plain FP64"
+HBM_PEAK_GBPS = 8000.0
+WORKLOAD = "laplace_sphere_p3_m5_q8"
+PRM = dict(p=3, m=5, q=8, eta=1.6, gauss_regular=6)
+TOL = 1e-8
+PROFILE_DIR = os.path.join(ROOT, "profiles")
+KERNEL_SRC = os.path.join(ROOT, "paper_1708_09162_amd", "csrc", "igabem.hip")
+
+
+def source_sha() -> str:
+    with open(KERNEL_SRC, "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()[:16]
+
+
+def read_traffic(stage: str):
+    """HBM bytes per launch of a kernel from committed rocprofv3 counter summaries, or None when
+    missing or taken on a different kernel source."""
+    path = os.path.join(PROFILE_DIR, f"{stage}_{WORKLOAD}_pmc.txt")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    with open(path) as fh:
+        for ln in fh:
+            if ":" in ln and not ln.startswith("#"):
+                k, v = ln.split(":", 1)
+                vals[k.strip()] = v.strip()
+    if vals.get("source_sha256_16") != source_sha():
+        return None
+    try:
+        kib = float(vals["FETCH_SIZE_KiB_per_dispatch"]) + float(vals["WRITE_SIZE_KiB_per_dispatch"])
+        return kib * 1024.0 * float(vals.get("copy_scale", "1.0"))
+    except (KeyError, ValueError):
+        return None
+
+
+def calibrate_copy():
+    """A plain device copy of known size (1 GiB read + 1 GiB written per launch) for scaling
+    the HBM byte counters."""
+    import torch
+
+    n = (1 << 30) // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda:0")
+    b = torch.empty_like(a)
+    for _ in range(5):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": n * 8, "copy_bytes_written": n * 8, "launches": 5}), flush=True)
+
+
+def charge_field(torch, pts, pos, q):
+    g = torch.zeros(pts.shape[0], dtype=torch.float64, device=pts.device)
+    for x0, c in zip(pos, q):
+        d = torch.linalg.norm(pts - torch.tensor(x0, dtype=torch.float64, device=pts.device), dim=1)
+        g += float(c) / (4.0 * math.pi * d)
+    return g
+
+
+def one_step(torch, igb, geo, cfg, ev_dev):
+    """The whole path once; returns (operator, density, solve info, potential, timings)."""
+    t = {}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    op = igb.Operator(geo, device="cuda:0", **PRM)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    pts = op.rhs_points()
+    b = op.rhs(charge_field(torch, pts, *cfg["charges"]))
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    w, info = op.solve(b, tol=TOL, max_iter=20000)
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    u = op.potential(w, ev_dev)
+    torch.cuda.synchronize()
+    t4 = time.perf_counter()
+    t.update(assembly_s=t1 - t0, rhs_s=t2 - t1, solve_s=t3 - t2, potential_s=t4 - t3, total_s=t4 - t0)
+    return op, w, info, u, t
+
+
+def cpu_baseline(cfg, iterations: int, seed: int = 7):
+    """Oracle time-to-solve projected from a timed stratified sample of the same workload:
+    near-field pair quadrature (per class) and coupling-block evaluation (the oracle evaluates
+    coupling blocks inside every matvec)."""
+    import oracle
+
+    P = oracle.Problem(cfg["patches"], **PRM)
+    threads = oracle.num_threads()
+    classes = P.near_pair_classes()
+    _, far = P.partition()
+    rng = np.random.default_rng(seed)
+    t_asm, parts = 0.0, []
+    for c in range(4):
+        rows = classes[classes[:, 2] == c]
+        k = max(32, len(rows) // 100)
+        pick = rows[rng.choice(len(rows), min(k, len(rows)), replace=False)]
+        t0 = time.perf_counter()
+        P.pair_blocks(pick[:, :2])
+        dt = time.perf_counter() - t0
+        t_asm += dt / len(pick) * len(rows)
+        parts.append(f"{len(pick)}/{len(rows)} class-{c} pairs")
+    kf = max(200, len(far) // 100)
+    pick = far[rng.choice(len(far), min(kf, len(far)), replace=False)]
+    t0 = time.perf_counter()
+    P.coupling_blocks(pick)
+    dt = time.perf_counter() - t0
+    t_far = dt / len(pick) * len(far)
+    parts.append(f"{len(pick)}/{len(far)} coupling blocks")
+    value = t_asm + (iterations + 2) * t_far
+    return {"value": value, "unit": "s", "cores": threads, "kind": "oracle",
+            "sample": "projected from a timed random sample of the full workload: " + ", ".join(parts)
+                      + f"; time = near quadrature + (CG iterations + 2) x coupling evaluation per matvec",
+            "assembly_s": t_asm, "matvec_s": t_far}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--matvec-reps", type=int, default=20)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true", help="only run a plain 1 GiB device copy")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py: this build runs its whole path on one GPU; multi-GPU runs (--gpus > 1) are not "
+              "supported (see DESIGN.md for how the path would shard).", file=sys.stderr, flush=True)
+        sys.exit(2)
+    if args.calibrate_copy:
+        calibrate_copy()
+        return
+
+    import torch
+
+    from paper_1708_09162_amd import igabem as igb
+    from paper_1708_09162_amd import workloads as W
+
+    cfg = W.config_sphere_h2()
+    geo = igb.Geometry(cfg["patches"])
+    ev = cfg["eval_points"]
+    ev_dev = torch.tensor(ev, dtype=torch.float64, device="cuda:0")
+    print(f"[bench] workload {WORKLOAD}: warmup {args.warmup}, steps {args.steps}", file=sys.stderr, flush=True)
+    op = None
+    for i in range(args.warmup):
+        if op is not None:
+            del op
+        op, w, info, u, t = one_step(torch, igb, geo, cfg, ev_dev)
+        print(f"[bench] warmup {i}: {t['total_s']:.3f} s, {info.iterations} it", file=sys.stderr, flush=True)
+    times = []
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for i in range(args.steps):
+        if op is not None:
+            del op
+        op, w, info, u, t = one_step(torch, igb, geo, cfg, ev_dev)
+        times.append(t)
+        print(f"[bench] step {i}: {t['total_s']:.3f} s (assembly {t['assembly_s']:.3f}, solve {t['solve_s']:.3f},"
+              f" {info.iterations} it, relres {info.rel_residual:.2e})", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    ms_per_step = 1e3 * elapsed / max(1, args.steps)
+
+    # accuracy of the last step against the exact interior potential
+    exact = W.laplace_charge_field(ev, *cfg["charges"])
+    pot_err = float(np.abs(u.cpu().numpy() - exact).max())
+
+    # H2 matvec bandwidth: algorithmic bytes / median time of igb_matvec
+    x = torch.randn(op.info.n_dof, dtype=torch.float64, device="cuda:0")
+    for _ in range(3):
+        op.matvec(x)
+    mv = []
+    for _ in range(args.matvec_reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        op.matvec(x)
+        e1.record()
+        e1.synchronize()
+        mv.append(e0.elapsed_time(e1))
+    mv_ms = float(np.median(mv))
+    gbps = op.info.matvec_bytes / (mv_ms * 1e-3) / 1e9
+
+    # per-stage durations (HIP events on the operator's stream) and the dominant kernel's roofline
+    stages = op.profile(reps=args.matvec_reps)
+    near, far = op.partition()
+    q2 = PRM["q"] ** 2
+    npatch = len(cfg["patches"])
+    off = np.concatenate([[0], np.cumsum([npatch << (2 * l) for l in range(op.info.leaf_level + 1)])])
+    rows = len(np.unique(off[far[:, 0]] + far[:, 1]))  # clusters with coupling blocks (rows written)
+    srcs = len(np.unique(off[far[:, 0]] + far[:, 2]))  # distinct source moment vectors read
+    alg_bytes = {
+        "coupling_gemv": op.info.coupling_bytes + 8 * q2 * (rows + srcs),
+        "near_gemv": op.info.near_bytes + 8 * 2 * op.info.n_dof_super,
+    }
+    dom = max(alg_bytes, key=lambda k: stages[k])
+    achieved = alg_bytes[dom] / (stages[dom] * 1e-3) / 1e9
+    kname = {"coupling_gemv": "k_bsr_gemv<double, 1>", "near_gemv": "k_bsr_gemv<double, 0>"}[dom]
+    roofline = {"bound": "hbm", "kernel": kname, "achieved": round(achieved, 1),
+                "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
+                "traffic": read_traffic(dom), "algorithmic_bytes": int(alg_bytes[dom]),
+                "avg_ms": round(stages[dom], 4)}
+
+    mean = {k: float(np.mean([t[k] for t in times])) for k in times[0]} if times else {}
+    out = {
+        "metric": METRIC,
+        "value": round(ms_per_step / 1e3, 5),
+        "unit": "s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": WORKLOAD, "geometry": "unit sphere, 6 rational NURBS patches of bidegree 4",
+                   "kernel": "laplace", "p": PRM["p"], "m": PRM["m"], "q": PRM["q"], "eta": PRM["eta"],
+                   "gauss_regular": PRM["gauss_regular"], "n_dof": int(op.info.n_dof),
+                   "n_dof_super": int(op.info.n_dof_super), "rel_tol": TOL, "mode": "h2_stored"},
+        "h2_matvec_GBps": round(gbps, 1),
+        "h2_matvec_ms": round(mv_ms, 4),
+        "matvec_bytes": int(op.info.matvec_bytes),
+        "stage_ms": {k: round(v, 4) for k, v in stages.items()},
+        "breakdown_s": {k: round(v, 4) for k, v in mean.items()},
+        "iterations": int(info.iterations),
+        "rel_residual": float(info.rel_residual),
+        "potential_max_err": pot_err,
+        "near_blocks": int(op.info.n_near_blocks),
+        "far_blocks": int(op.info.n_far_blocks),
+        "roofline": roofline,
+        "cpu_baseline": None,
+    }
+    if not args.no_cpu_baseline:
+        print("[bench] cpu baseline (oracle sample)", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(cfg, int(info.iterations))
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -174,6 +174,15 @@ igb_status igb_solve(const igb_operator *op, const void *b_dev, void *w_dev, dou
 igb_status igb_potential(const igb_operator *op, const void *w_dev, int64_t n_pts, const double *xyz_dev,
                          void *u_dev);
 
+/* Timing of the superspace matvec by stage: runs `reps` products on the
+ * operator's internal work vectors with HIP events recorded on its stream
+ * between stages and writes the mean milliseconds per stage to
+ * stage_ms_host[IGB_NUM_MATVEC_STAGES]: 0 leaf moments, 1 upward transfers,
+ * 2 coupling block GEMV, 3 downward transfers, 4 near-field block GEMV,
+ * 5 leaf back-moments (Sec. 4.2).  Synchronous. */
+#define IGB_NUM_MATVEC_STAGES 6
+igb_status igb_matvec_profile(const igb_operator *op, int32_t reps, double *stage_ms_host);
+
 /* Host-only planning: the cluster tree, block partition (Sec. 4.1, Sec. 4.2
  * Def.) and near-field element-pair classification that igb_operator_create
  * would build for the same geometry and parameters, without any GPU work.

@@ -75,6 +75,8 @@ def _load():
     lib.or_solve.restype = C.c_int
     lib.or_solve.argtypes = [P, dp, dp, dp, C.c_double, C.c_int, C.c_int, ip, dp]
     lib.or_potential.argtypes = [P, dp, C.c_int64, dp, dp]
+    lib.or_pair_blocks.argtypes = [P, C.c_int64, ip, dp]
+    lib.or_coupling_blocks.argtypes = [P, C.c_int64, ip, dp]
     lib.or_near_pair_classes.restype = C.c_int64
     lib.or_near_pair_classes.argtypes = [P, ip]
     lib.or_gauss.restype = C.c_int
@@ -196,6 +198,21 @@ class Problem:
         out = np.zeros((self.nloc, self.nloc), dtype=np.complex128)
         fn = _load().or_pair_block_sym if symmetric else _load().or_pair_block
         fn(self._h, int(E), int(F), out.ctypes.data_as(C.POINTER(C.c_double)))
+        return self._out(out)
+
+    def pair_blocks(self, pairs):
+        """Blocks of a list of element pairs (n, 2), symmetric convention, computed in parallel."""
+        pairs = np.ascontiguousarray(np.asarray(pairs, dtype=np.int32).reshape(-1, 2))
+        out = np.zeros((len(pairs), self.nloc, self.nloc), dtype=np.complex128)
+        _load().or_pair_blocks(self._h, len(pairs), _i(pairs), _d(out.view(np.float64)))
+        return self._out(out)
+
+    def coupling_blocks(self, blocks):
+        """Coupling blocks of a list of far pairs (n, 3) = (level, tgt, src), computed in parallel."""
+        blocks = np.ascontiguousarray(np.asarray(blocks, dtype=np.int32).reshape(-1, 3))
+        q2 = self.q * self.q
+        out = np.zeros((len(blocks), q2, q2), dtype=np.complex128)
+        _load().or_coupling_blocks(self._h, len(blocks), _i(blocks), _d(out.view(np.float64)))
         return self._out(out)
 
     def coupling_block(self, level: int, tgt: int, src: int):

@@ -1689,3 +1689,22 @@ int64_t or_near_pair_classes(or_problem *P, int32_t *out)
     qsort(out, cnt, 4 * sizeof(int32_t), cmp_int4);
     return cnt;
 }
+
+/* Batch forms of or_pair_block_sym / or_coupling_block over a list, parallel */
+/* over the list (used to time samples of a workload).  pairs: n x (E, F);    */
+/* out: n blocks of nloc^2 complex values.                                    */
+void or_pair_blocks(const or_problem *P, int64_t n, const int32_t *pairs, double *out)
+{
+    int nl = P->nloc;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t i = 0; i < n; ++i) pair_block_sym(P, pairs[2 * i], pairs[2 * i + 1], (cplx *)out + i * nl * nl);
+}
+
+/* blocks: n x (level, tgt, src); out: n blocks of q^4 complex values */
+void or_coupling_blocks(const or_problem *P, int64_t n, const int32_t *blocks, double *out)
+{
+    int64_t q4 = (int64_t)P->q * P->q * P->q * P->q;
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t i = 0; i < n; ++i)
+        or_coupling_block(P, blocks[3 * i], blocks[3 * i + 1], blocks[3 * i + 2], (cplx *)out + i * q4);
+}

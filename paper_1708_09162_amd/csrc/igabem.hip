@@ -453,8 +453,9 @@ __global__ void k_leaf_back(int n1, int q, int side, int P1, int nloc, int nl, c
 // column-major nb x nb blocks (near field: leaf blocks; far field: coupling
 // blocks over all levels).  One workgroup per target row, waves split the
 // row's blocks, lanes own block rows; the block stream is read once,
-// coalesced.
-template <class T>
+// coalesced.  ROLE only names the instantiation (0 near field, 1 coupling)
+// so that profiles tell the two launches apart.
+template <class T, int ROLE>
 __global__ void __launch_bounds__(256) k_bsr_gemv(int nb, const int64_t *__restrict__ ptr, const int32_t *__restrict__ src,
                                                   const T *__restrict__ blocks, const T *__restrict__ x, T *__restrict__ y,
                                                   int64_t row0)
@@ -1064,28 +1065,46 @@ static igb_status launch_singular(igb_operator *op, const PairRec *d, int64_t n)
     return fail(IGB_EUNSUPPORTED, "p > 6");
 }
 
-// superspace matvec on internal vectors: ys = A xs
+// superspace matvec on internal vectors: ys = A xs.  When ev is given, ev[k]
+// is recorded on the operator's stream before stage k and ev[6] at the end:
+// stages 0 leaf moments, 1 upward, 2 coupling GEMV, 3 downward, 4 near GEMV,
+// 5 leaf back-moments.
 template <class T>
-static igb_status matvec_internal(igb_operator *op, const T *xs, T *ys)
+static igb_status matvec_internal(igb_operator *op, const T *xs, T *ys, hipEvent_t *ev = nullptr)
 {
     const Setup &s = op->s;
     int q = s.q, q2 = q * q;
     T *Xh = (T *)op->Xh, *Yh = (T *)op->Yh;
     bool has_far = op->lmin <= s.L;
+    auto mark = [&](int k) -> igb_status {
+        if (ev) HIPCHK(hipEventRecord(ev[k], op->st));
+        return IGB_OK;
+    };
+    igb_status rc;
+    if ((rc = mark(0))) return rc;
     if (has_far) {
         size_t shm = (size_t)(s.n1 * s.n1 + s.n1 * q) * sizeof(T);
         hipLaunchKernelGGL((k_leaf_moments<T>), dim3(s.nleaf), dim3(64), shm, op->st, s.n1, q, s.side, s.p + 1, s.nloc,
                            s.nl, op->M1, xs, Xh + s.cl_off[s.L] * q2);
         LAUNCHCHK();
+    }
+    if ((rc = mark(1))) return rc;
+    if (has_far) {
         for (int l = s.L - 1; l >= op->lmin; --l) {
             hipLaunchKernelGGL((k_upward<T>), dim3((unsigned)(s.cl_off[l + 1] - s.cl_off[l])), dim3(64), 2 * q2 * sizeof(T),
                                op->st, l, q, op->E2, Xh + s.cl_off[l + 1] * q2, Xh + s.cl_off[l] * q2);
             LAUNCHCHK();
         }
+    }
+    if ((rc = mark(2))) return rc;
+    if (has_far) {
         int64_t row0 = s.cl_off[op->lmin], nrows = s.cl_off[s.L + 1] - row0;
-        hipLaunchKernelGGL((k_bsr_gemv<T>), dim3((unsigned)nrows), dim3(256), 4 * q2 * sizeof(T), op->st, q2, op->far_ptr,
+        hipLaunchKernelGGL((k_bsr_gemv<T, 1>), dim3((unsigned)nrows), dim3(256), 4 * q2 * sizeof(T), op->st, q2, op->far_ptr,
                            op->far_src, (const T *)op->coup, (const T *)Xh, Yh, row0);
         LAUNCHCHK();
+    }
+    if ((rc = mark(3))) return rc;
+    if (has_far) {
         for (int l = op->lmin; l < s.L; ++l) {
             hipLaunchKernelGGL((k_downward<T>), dim3((unsigned)(s.cl_off[l + 2] - s.cl_off[l + 1])), dim3(64),
                                2 * q2 * sizeof(T), op->st, l + 1, q, op->E2, Yh + s.cl_off[l] * q2,
@@ -1093,16 +1112,18 @@ static igb_status matvec_internal(igb_operator *op, const T *xs, T *ys)
             LAUNCHCHK();
         }
     }
-    hipLaunchKernelGGL((k_bsr_gemv<T>), dim3(s.nleaf), dim3(256), 4 * s.nl * sizeof(T), op->st, s.nl, op->near_ptr,
+    if ((rc = mark(4))) return rc;
+    hipLaunchKernelGGL((k_bsr_gemv<T, 0>), dim3(s.nleaf), dim3(256), 4 * s.nl * sizeof(T), op->st, s.nl, op->near_ptr,
                        op->near_src, (const T *)op->nearb, xs, ys, (int64_t)0);
     LAUNCHCHK();
+    if ((rc = mark(5))) return rc;
     if (has_far) {
         size_t shm = (size_t)(q2 + q * s.n1) * sizeof(T);
         hipLaunchKernelGGL((k_leaf_back<T>), dim3(s.nleaf), dim3(64), shm, op->st, s.n1, q, s.side, s.p + 1, s.nloc, s.nl,
                            op->M1, (const T *)(Yh + s.cl_off[s.L] * q2), ys);
         LAUNCHCHK();
     }
-    return IGB_OK;
+    return mark(6);
 }
 
 template <class T>
@@ -1861,4 +1882,38 @@ igb_status igb_plan_export_pair_classes(const igb_plan *plan, int32_t *pairs_hos
         pairs_host[4 * k + 3] = R.order;
     }
     return IGB_OK;
+}
+
+// ---------------------------------------------------------------------------
+// per-stage timing of the superspace matvec (HIP events on the operator stream)
+// ---------------------------------------------------------------------------
+template <class T>
+static igb_status profile_impl(igb_operator *op, int reps, double *ms)
+{
+    hipEvent_t ev[7];
+    for (int k = 0; k < 7; ++k) HIPCHK(hipEventCreate(&ev[k]));
+    for (int k = 0; k < IGB_NUM_MATVEC_STAGES; ++k) ms[k] = 0.0;
+    igb_status rc = IGB_OK;
+    for (int r = 0; r < reps && rc == IGB_OK; ++r) {
+        rc = matvec_internal<T>(op, (const T *)op->xs, (T *)op->ys, ev);
+        if (rc) break;
+        if (hipEventSynchronize(ev[6]) != hipSuccess) { rc = fail(IGB_EHIP, "event synchronize"); break; }
+        for (int k = 0; k < 6; ++k) {
+            float t = 0.f;
+            if (hipEventElapsedTime(&t, ev[k], ev[k + 1]) != hipSuccess) { rc = fail(IGB_EHIP, "event elapsed"); break; }
+            ms[k] += t;
+        }
+    }
+    for (int k = 0; k < 7; ++k) (void)hipEventDestroy(ev[k]);
+    if (rc) return rc;
+    for (int k = 0; k < IGB_NUM_MATVEC_STAGES; ++k) ms[k] /= reps;
+    return IGB_OK;
+}
+
+igb_status igb_matvec_profile(const igb_operator *cop, int32_t reps, double *stage_ms_host)
+{
+    CHECK_OP(cop);
+    if (reps < 1 || !stage_ms_host) return fail(IGB_EINVAL, "reps < 1 or null output");
+    igb_operator *op = const_cast<igb_operator *>(cop);
+    return op->cplx ? profile_impl<cd>(op, reps, stage_ms_host) : profile_impl<double>(op, reps, stage_ms_host);
 }

@@ -34,8 +34,9 @@ EXPORTED = [
     "igb_matvec_super", "igb_apply_Tt", "igb_apply_T", "igb_jacobi_diag", "igb_solve", "igb_potential",
     "igb_export_partition", "igb_export_pair_classes", "igb_export_near_block", "igb_export_coupling_block",
     "igb_plan_create", "igb_plan_destroy", "igb_plan_info", "igb_plan_export_partition",
-    "igb_plan_export_pair_classes",
+    "igb_plan_export_pair_classes", "igb_matvec_profile",
 ]
+STAGES = ["leaf_moments", "upward", "coupling_gemv", "downward", "near_gemv", "leaf_back"]
 
 
 class igb_nurbs_patch(C.Structure):
@@ -89,6 +90,7 @@ def _load():
         "igb_export_pair_classes": (C.c_int32, [vp, ip]),
         "igb_export_near_block": (C.c_int32, [vp, C.c_int32, C.c_int32, dp]),
         "igb_export_coupling_block": (C.c_int32, [vp, C.c_int32, C.c_int32, C.c_int32, dp]),
+        "igb_matvec_profile": (C.c_int32, [vp, C.c_int32, dp]),
         "igb_plan_create": (C.c_int32, [vp, C.POINTER(igb_params), C.POINTER(vp)]),
         "igb_plan_destroy": (None, [vp]),
         "igb_plan_info": (C.c_int32, [vp, C.POINTER(igb_info)]),
@@ -230,6 +232,12 @@ def igb_export_coupling_block(op, level, tgt, src, q2, cplx):
     _check(_lib.igb_export_coupling_block(op, int(level), int(tgt), int(src),
                                           out.ctypes.data_as(C.POINTER(C.c_double))))
     return out[..., 0] + 1j * out[..., 1] if cplx else out[..., 0]
+
+
+def igb_matvec_profile(op, reps):
+    out = np.zeros(len(STAGES))
+    _check(_lib.igb_matvec_profile(op, int(reps), out.ctypes.data_as(C.POINTER(C.c_double))))
+    return dict(zip(STAGES, out.tolist()))
 
 
 def make_params(*, kernel=IGB_LAPLACE, wavenumber=0.0, p=1, m=2, q=8, eta=1.6, leaf_depth=-1, gauss_regular=6,
@@ -381,6 +389,10 @@ class Operator:
         u = self._vec(pts.shape[0])
         igb_potential(self.h, self._in(w, self.info.n_dof), pts, u)
         return u
+
+    def profile(self, reps=10):
+        """Mean milliseconds per matvec stage, from HIP events on the operator's stream."""
+        return igb_matvec_profile(self.h, reps)
 
     def partition(self):
         return igb_export_partition(self.h, self.info)

@@ -255,6 +255,7 @@ def main():
         "matvec_bytes": int(op.info.matvec_bytes),
         "stage_ms": {k: round(v, 4) for k, v in stages.items()},
         "breakdown_s": {k: round(v, 4) for k, v in mean.items()},
+        "host_setup_s": round(float(op.info.setup_seconds), 4),
         "iterations": int(info.iterations),
         "rel_residual": float(info.rel_residual),
         "potential_max_err": pot_err,

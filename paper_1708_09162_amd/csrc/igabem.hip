@@ -170,57 +170,67 @@ __device__ inline void frame_map(int o, int a, int b, double s, double t, double
 
 // Touching pairs (identical / common edge / common vertex): regularising
 // Duffy-type substitutions of [0,1]^4 (8 / 6 / 4 regions), Gauss of order gs
-// per variable.  One workgroup of 256 threads per pair; each thread forms the
-// weighted kernel value of one quadrature point and the Bernstein vectors of
-// both points, a batch is staged in LDS and reduced into the nloc x nloc block.
-template <class T, int P, int BATCH>
-__global__ void __launch_bounds__(256) k_near_singular(const PairRec *__restrict__ pairs, int npairs, int gs,
-                                                       const double *__restrict__ gxs, const double *__restrict__ gws,
-                                                       const double *__restrict__ tiles,
-                                                       const int32_t *__restrict__ tdeg, int stride, double kappa,
-                                                       int nl, T *__restrict__ blocks)
+// per variable.  One workgroup per pair; every lane forms one quadrature
+// point (geometry of both elements, weighted kernel value, Bernstein vectors),
+// each wave stages its 64 points in LDS and accumulates the nloc x nloc block
+// B += U^T V with FP64 MFMA (v_mfma_f64_16x16x4f64: 4 points per step),
+// complex kernels as two real accumulations.  Waves are reduced through LDS
+// at the end.
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+template <class T, int P, int PG, int WAVES>
+__global__ void __launch_bounds__(64 * WAVES, NComp<T>::value == 1 ? 3 : 1) k_near_singular(const PairRec *__restrict__ pairs, int gs,
+                                                             const double *__restrict__ gxs, const double *__restrict__ gws,
+                                                             const double *__restrict__ tiles, double kappa, int nl,
+                                                             T *__restrict__ blocks)
 {
-    constexpr int P1 = P + 1, NLOC = P1 * P1, NOUT = NLOC * NLOC;
-    constexpr int NACC = (NOUT + 255) / 256;
+    constexpr int P1 = P + 1, NLOC = P1 * P1, NT = (NLOC + 15) / 16, NPAD = 16 * NT;
+    constexpr int NC = NComp<T>::value;
+    constexpr int G1 = PG + 1, TS = G1 * G1 * 4;
+    constexpr int STAGE = 64 * (NC + 1) * NPAD;  // doubles per wave
     extern __shared__ double sh[];
-    double *tE = sh;                       // stride
-    double *tF = tE + stride;              // stride
-    double *nx = tF + stride;              // gs
-    double *nw = nx + 64;                  // gs
-    T *U = (T *)(nw + 64);                 // BATCH*NLOC
-    double *V = (double *)(U + BATCH * NLOC);  // BATCH*NLOC
-    PairRec R = pairs[blockIdx.x];
-    for (int k = threadIdx.x; k < stride; k += blockDim.x) {
-        tE[k] = tiles[(size_t)R.E * stride + k];
-        tF[k] = tiles[(size_t)R.F * stride + k];
+    double *tE = sh, *tF = tE + TS, *nx = tF + TS, *nw = nx + 64;
+    double *stg = nw + 64;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    double *Ub = stg + wave * STAGE;   // [NC][64][NPAD]
+    double *Vb = Ub + NC * 64 * NPAD;  // [64][NPAD]
+    const PairRec R = pairs[blockIdx.x];
+    for (int k = threadIdx.x; k < TS; k += blockDim.x) {
+        tE[k] = tiles[(size_t)R.E * TS + k];
+        tF[k] = tiles[(size_t)R.F * TS + k];
     }
     for (int k = threadIdx.x; k < gs; k += blockDim.x) {
         nx[k] = gxs[k];
         nw[k] = gws[k];
     }
-    int puE = tdeg[2 * R.E], pvE = tdeg[2 * R.E + 1], puF = tdeg[2 * R.F], pvF = tdeg[2 * R.F + 1];
+    // zero padding columns once (never written afterwards)
+    for (int k = lane; k < 64 * (NPAD - NLOC); k += 64) {
+        int pt = k / (NPAD - NLOC), a = NLOC + k % (NPAD - NLOC);
+#pragma unroll
+        for (int c = 0; c < NC; ++c) Ub[c * 64 * NPAD + pt * NPAD + a] = 0.0;
+        Vb[pt * NPAD + a] = 0.0;
+    }
     __syncthreads();
-    int g2 = gs * gs, g4 = g2 * g2;
-    int nreg = R.cls == 1 ? 8 : (R.cls == 2 ? 6 : 4);
-    int npts = nreg * g4;
-    T acc[NACC];
+    const int g2 = gs * gs, g4 = g2 * g2;
+    const int nreg = R.cls == 1 ? 8 : (R.cls == 2 ? 6 : 4);
+    const int npts = nreg * g4;
+    const int niter = (npts + 64 * WAVES - 1) / (64 * WAVES);
+    v4d acc[NC][NT][NT];
 #pragma unroll
-    for (int k = 0; k < NACC; ++k) acc[k] = zero<T>();
-    for (int base = 0; base < npts; base += BATCH) {
-        for (int t = threadIdx.x; t < BATCH; t += blockDim.x) {
-            int idx = base + t;
-            T *u = U + t * NLOC;
-            double *v = V + t * NLOC;
-            if (idx >= npts) {
+    for (int c = 0; c < NC; ++c)
 #pragma unroll
-                for (int a = 0; a < NLOC; ++a) { u[a] = zero<T>(); v[a] = 0.0; }
-                continue;
-            }
-            int reg = idx / g4, rem = idx % g4;
+        for (int i = 0; i < NT; ++i)
+#pragma unroll
+            for (int j = 0; j < NT; ++j) acc[c][i][j] = v4d{0.0, 0.0, 0.0, 0.0};
+    for (int it = 0; it < niter; ++it) {
+        int idx = (it * WAVES + wave) * 64 + lane;
+        // inactive lanes: two distinct points and zero weight
+        double xs = 0.25, xt = 0.25, ys = 0.75, yt = 0.75, W = 0.0;
+        if (idx < npts) {
+            int reg = idx / g4, rem = idx - reg * g4;
             int ia = rem / (g2 * gs), ib = (rem / g2) % gs, ic = (rem / gs) % gs, id = rem % gs;
             double va = nx[ia], vb = nx[ib], vc = nx[ic], vd = nx[id];
-            double W = nw[ia] * nw[ib] * nw[ic] * nw[id];
-            double xs, xt, ys, yt;  // element-local coordinates of x (in E) and y (in F)
+            W = nw[ia] * nw[ib] * nw[ic] * nw[id];
             if (R.cls == 1) {
                 int sg1 = reg & 1, sg2 = (reg >> 1) & 1, tri = reg >> 2;
                 double xi = va, eta = vb;
@@ -230,71 +240,109 @@ __global__ void __launch_bounds__(256) k_near_singular(const PairRec *__restrict
                 W *= xi * (1 - z1) * (1 - z2);
             } else if (R.cls == 2) {
                 int sg = reg & 1, pyr = reg >> 1;
-                double xi = va, e1 = vb, e2 = vc, s = vd;
+                double xi = va, e1 = vb, e2 = vc, sv = vd;
                 double zz, ct, dt;
                 if (pyr == 0) { zz = xi; ct = xi * e1; dt = xi * e2; }
                 else if (pyr == 1) { ct = xi; zz = xi * e1; dt = xi * e2; }
                 else { dt = xi; zz = xi * e1; ct = xi * e2; }
                 double cs, ds;
-                if (sg == 0) { cs = (1 - zz) * s; ds = cs + zz; } else { ds = (1 - zz) * s; cs = ds + zz; }
+                if (sg == 0) { cs = (1 - zz) * sv; ds = cs + zz; } else { ds = (1 - zz) * sv; cs = ds + zz; }
                 W *= xi * xi * (1 - zz);
                 frame_map(R.oE, R.aE, R.bE, cs, ct, xs, xt);
                 frame_map(R.oF, R.aF, R.bF, ds, dt, ys, yt);
             } else {
-                double xi = va, v4[4];
-                double e[3] = {vb, vc, vd};
-                int k = 0;
-                for (int q = 0; q < 4; ++q) v4[q] = (q == reg) ? xi : xi * e[k++];
+                double xi = va;
+                double v0 = reg == 0 ? xi : xi * vb;
+                double v1 = reg == 1 ? xi : xi * (reg == 0 ? vb : vc);
+                double v2 = reg == 2 ? xi : xi * (reg == 3 ? vd : vc);
+                double v3 = reg == 3 ? xi : xi * vd;
                 W *= xi * xi * xi;
-                frame_map(R.oE, R.aE, R.bE, v4[0], v4[1], xs, xt);
-                frame_map(R.oF, R.aF, R.bF, v4[2], v4[3], ys, yt);
+                frame_map(R.oE, R.aE, R.bE, v0, v1, xs, xt);
+                frame_map(R.oF, R.aF, R.bF, v2, v3, ys, yt);
             }
-            double X[3], Yp[3], kx, ky;
-            tile_point(tE, puE, pvE, xs, xt, X, &kx);
-            tile_point(tF, puF, pvF, ys, yt, Yp, &ky);
-            double d0 = X[0] - Yp[0], d1 = X[1] - Yp[1], d2 = X[2] - Yp[2];
-            double r = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
-            T c = green<T>(r, kappa) * (W * kx * ky);
-            double bx1[P1], bx2[P1], by1[P1], by2[P1];
-            bernstein(P, xs, bx1);
-            bernstein(P, xt, bx2);
-            bernstein(P, ys, by1);
-            bernstein(P, yt, by2);
+        }
+        // an opaque zero offset keeps the tile reads inside the loop: hoisting
+        // both tiles into registers would cost 4 (PG+1)^2 VGPRs each
+        int zoff = 0;
+        asm volatile("" : "+v"(zoff));
+        double X[3], Yp[3], kx, ky;
+        tile_point_t<PG>(tE + zoff, xs, xt, X, &kx);
+        tile_point_t<PG>(tF + zoff, ys, yt, Yp, &ky);
+        double d0 = X[0] - Yp[0], d1 = X[1] - Yp[1], d2 = X[2] - Yp[2];
+        T c = green<T>(sqrt(d0 * d0 + d1 * d1 + d2 * d2), kappa) * (W * kx * ky);
+        double bx1[P1], bx2[P1], by1[P1], by2[P1];
+        bernstein_t<P>(xs, bx1);
+        bernstein_t<P>(xt, bx2);
+        bernstein_t<P>(ys, by1);
+        bernstein_t<P>(yt, by2);
+        double cre = re_(c), cim = im_(c);
 #pragma unroll
-            for (int a2 = 0; a2 < P1; ++a2)
+        for (int a2 = 0; a2 < P1; ++a2)
 #pragma unroll
-                for (int a1 = 0; a1 < P1; ++a1) {
-                    u[a2 * P1 + a1] = c * (bx1[a1] * bx2[a2]);
-                    v[a2 * P1 + a1] = by1[a1] * by2[a2];
+            for (int a1 = 0; a1 < P1; ++a1) {
+                double fx = bx1[a1] * bx2[a2];
+                Ub[lane * NPAD + a2 * P1 + a1] = cre * fx;
+                if constexpr (NC == 2) Ub[64 * NPAD + lane * NPAD + a2 * P1 + a1] = cim * fx;
+                Vb[lane * NPAD + a2 * P1 + a1] = by1[a1] * by2[a2];
+            }
+        __syncthreads();
+        const int col = lane & 15, sub = lane >> 4;
+#pragma unroll 4
+        for (int j = 0; j < 16; ++j) {
+            const int pt = 4 * j + sub;
+            double bv[NT];
+#pragma unroll
+            for (int tb = 0; tb < NT; ++tb) bv[tb] = Vb[pt * NPAD + 16 * tb + col];
+#pragma unroll
+            for (int c2 = 0; c2 < NC; ++c2)
+#pragma unroll
+                for (int ta = 0; ta < NT; ++ta) {
+                    double av = Ub[c2 * 64 * NPAD + pt * NPAD + 16 * ta + col];
+#pragma unroll
+                    for (int tb = 0; tb < NT; ++tb)
+                        acc[c2][ta][tb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv[tb], acc[c2][ta][tb], 0, 0, 0);
                 }
         }
         __syncthreads();
-#pragma unroll
-        for (int k = 0; k < NACC; ++k) {
-            int o = threadIdx.x + 256 * k;
-            if (o < NOUT) {
-                int a = o / NLOC, b = o % NLOC;
-                T s = acc[k];
-                for (int t = 0; t < BATCH; ++t) s += U[t * NLOC + a] * V[t * NLOC + b];
-                acc[k] = s;
-            }
-        }
-        __syncthreads();
     }
-    // write (identical blocks symmetrised as (B + B^T)/2)
-    T *full = U;  // reuse LDS: NOUT entries fit (BATCH >= NLOC)
+    // reduce the per-wave accumulators: red[(w*NC + c)*NPAD*NPAD + row*NPAD + col]
+    double *red = stg;
+    {
+        const int col = lane & 15, sub = lane >> 4;
 #pragma unroll
-    for (int k = 0; k < NACC; ++k) {
-        int o = threadIdx.x + 256 * k;
-        if (o < NOUT) full[o] = acc[k];
+        for (int c2 = 0; c2 < NC; ++c2)
+#pragma unroll
+            for (int ta = 0; ta < NT; ++ta)
+#pragma unroll
+                for (int tb = 0; tb < NT; ++tb)
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        // v_mfma_f64_16x16x4f64 result layout: lane l, element e holds D[4e + l/16][l%16]
+                        int row = 16 * ta + 4 * e + sub, cc = 16 * tb + col;
+                        red[((size_t)(wave * NC + c2) * NPAD + row) * NPAD + cc] = acc[c2][ta][tb][e];
+                    }
     }
     __syncthreads();
     T *out1 = blocks + (int64_t)R.blk1 * nl * nl;
     T *out2 = R.blk2 >= 0 ? blocks + (int64_t)R.blk2 * nl * nl : nullptr;
-    for (int o = threadIdx.x; o < NOUT; o += blockDim.x) {
+    for (int o = threadIdx.x; o < NLOC * NLOC; o += blockDim.x) {
         int a = o / NLOC, b = o % NLOC;
-        T s = full[o];
-        if (R.cls == 1) s = 0.5 * (full[a * NLOC + b] + full[b * NLOC + a]);
+        double sre = 0.0, sim = 0.0, tre = 0.0, tim = 0.0;
+        for (int w = 0; w < WAVES; ++w) {
+            sre += red[((size_t)(w * NC) * NPAD + a) * NPAD + b];
+            tre += red[((size_t)(w * NC) * NPAD + b) * NPAD + a];
+            if constexpr (NC == 2) {
+                sim += red[((size_t)(w * NC + 1) * NPAD + a) * NPAD + b];
+                tim += red[((size_t)(w * NC + 1) * NPAD + b) * NPAD + a];
+            }
+        }
+        if (R.cls == 1) {
+            sre = 0.5 * (sre + tre);
+            sim = 0.5 * (sim + tim);
+        }
+        T s;
+        if constexpr (NC == 2) s = T{sre, sim};
+        else s = sre;
         out1[blk_pos(nl, NLOC, R.elE, a, R.elF, b)] = s;
         if (out2) out2[blk_pos(nl, NLOC, R.elF, b, R.elE, a)] = s;
     }
@@ -1015,24 +1063,38 @@ static igb_status launch_regular_p(igb_operator *op, const PairRec *d_pairs, int
     return IGB_OK;
 }
 
-template <class T, int P>
-static igb_status launch_singular_p(igb_operator *op, const PairRec *d_pairs, int64_t n)
+template <class T, int P, int PG>
+static igb_status launch_singular_pg(igb_operator *op, const PairRec *d_pairs, int64_t n)
 {
-    constexpr int NLOC = (P + 1) * (P + 1);
-    constexpr int BATCH = (NLOC * (int)(sizeof(T) + 8) * 256 <= 64 * 1024) ? 256 : ((NLOC * (int)(sizeof(T) + 8) * 128 <= 96 * 1024) ? 128 : 64);
-    size_t shm = (size_t)(2 * op->s.tile_stride + 128) * sizeof(double) + (size_t)BATCH * NLOC * (sizeof(T) + sizeof(double));
-    size_t need_full = (size_t)NLOC * NLOC * sizeof(T);
-    if (need_full > (size_t)BATCH * NLOC * sizeof(T)) return fail(IGB_EUNSUPPORTED, "singular block too large");
-    (void)hipFuncSetAttribute((const void *)k_near_singular<T, P, BATCH>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+    constexpr int NLOC = (P + 1) * (P + 1), NPAD = 16 * ((NLOC + 15) / 16), NC = NComp<T>::value;
+    constexpr int STAGE_BYTES = 64 * (NC + 1) * NPAD * 8;
+    constexpr int WAVES = STAGE_BYTES * 4 <= 64 * 1024 ? 4 : (STAGE_BYTES * 2 <= 96 * 1024 ? 2 : 1);
+    constexpr int TS = (PG + 1) * (PG + 1) * 4;
+    size_t shm = (size_t)(2 * TS + 128) * sizeof(double) + (size_t)WAVES * STAGE_BYTES;
+    if (shm > 160 * 1024) return fail(IGB_EUNSUPPORTED, "touching-pair quadrature: LDS too small for this degree");
+    (void)hipFuncSetAttribute((const void *)k_near_singular<T, P, PG, WAVES>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)shm);
     int gs = op->s.gs;
     for (int64_t off = 0; off < n; off += 1 << 20) {
         int64_t cnt = std::min<int64_t>(n - off, 1 << 20);
-        hipLaunchKernelGGL((k_near_singular<T, P, BATCH>), dim3((unsigned)cnt), dim3(256), shm, op->st, d_pairs + off, (int)cnt,
-                           gs, op->gx + op->s.goff[gs], op->gw + op->s.goff[gs], op->tiles, op->tdeg, op->s.tile_stride,
-                           op->s.kappa, op->s.nl, (T *)op->nearb);
+        hipLaunchKernelGGL((k_near_singular<T, P, PG, WAVES>), dim3((unsigned)cnt), dim3(64 * WAVES), shm, op->st,
+                           d_pairs + off, gs, op->gx + op->s.goff[gs], op->gw + op->s.goff[gs], op->tiles, op->s.kappa,
+                           op->s.nl, (T *)op->nearb);
         LAUNCHCHK();
     }
     return IGB_OK;
+}
+
+template <class T, int P>
+static igb_status launch_singular_p(igb_operator *op, const PairRec *d_pairs, int64_t n)
+{
+    switch (op->s.tile_degree) {
+    case 1: return launch_singular_pg<T, P, 1>(op, d_pairs, n);
+    case 2: return launch_singular_pg<T, P, 2>(op, d_pairs, n);
+    case 4: return launch_singular_pg<T, P, 4>(op, d_pairs, n);
+    case 8: return launch_singular_pg<T, P, 8>(op, d_pairs, n);
+    }
+    return fail(IGB_EUNSUPPORTED, "tile degree");
 }
 
 template <class T>

@@ -113,4 +113,90 @@ __device__ inline void tile_point(const double *H, int pu, int pv, double u, dou
     *kap = sqrt(n0 * n0 + n1 * n1 + n2 * n2);
 }
 
+// Compile-time-degree Bernstein values and derivatives (loops fully unrolled).
+template <int P>
+__device__ inline void bernstein_t(double t, double *B)
+{
+    double s = 1.0 - t;
+    B[0] = 1.0;
+#pragma unroll
+    for (int k = 1; k <= P; ++k) {
+        B[k] = t * B[k - 1];
+#pragma unroll
+        for (int i = k - 1; i >= 1; --i) B[i] = s * B[i] + t * B[i - 1];
+        B[0] = s * B[0];
+    }
+}
+
+template <int P>
+__device__ inline void bernstein_d_t(double t, double *B, double *dB)
+{
+    if constexpr (P == 0) {
+        B[0] = 1.0;
+        dB[0] = 0.0;
+    } else {
+        double lo[P];
+        bernstein_t<P - 1>(t, lo);
+        double s = 1.0 - t;
+        B[P] = t * lo[P - 1];
+#pragma unroll
+        for (int i = P - 1; i >= 1; --i) B[i] = s * lo[i] + t * lo[i - 1];
+        B[0] = s * lo[0];
+        dB[0] = -P * lo[0];
+#pragma unroll
+        for (int i = 1; i < P; ++i) dB[i] = P * (lo[i - 1] - lo[i]);
+        dB[P] = P * lo[P - 1];
+    }
+}
+
+// Rational Bezier tile of bidegree (PG, PG) at element-local (u, v): point and
+// surface measure w.r.t. (u, v).
+template <int PG>
+__device__ inline void tile_point_t(const double *H, double u, double v, double X[3], double *kap)
+{
+    constexpr int G1 = PG + 1;
+    double Bu[G1], dBu[G1], Bv[G1], dBv[G1];
+    bernstein_d_t<PG>(u, Bu, dBu);
+    bernstein_d_t<PG>(v, Bv, dBv);
+    double S0 = 0, S1 = 0, S2 = 0, S3 = 0, U0 = 0, U1 = 0, U2 = 0, U3 = 0, V0 = 0, V1 = 0, V2 = 0, V3 = 0;
+#pragma unroll
+    for (int j = 0; j < G1; ++j) {
+        double a0 = 0, a1 = 0, a2 = 0, a3 = 0, d0 = 0, d1 = 0, d2 = 0, d3 = 0;
+        const double *h = H + 4 * j * G1;
+#pragma unroll
+        for (int i = 0; i < G1; ++i) {
+            double b = Bu[i], db = dBu[i];
+            a0 += b * h[4 * i];
+            a1 += b * h[4 * i + 1];
+            a2 += b * h[4 * i + 2];
+            a3 += b * h[4 * i + 3];
+            d0 += db * h[4 * i];
+            d1 += db * h[4 * i + 1];
+            d2 += db * h[4 * i + 2];
+            d3 += db * h[4 * i + 3];
+        }
+        double bv = Bv[j], dbv = dBv[j];
+        S0 += bv * a0; S1 += bv * a1; S2 += bv * a2; S3 += bv * a3;
+        U0 += bv * d0; U1 += bv * d1; U2 += bv * d2; U3 += bv * d3;
+        V0 += dbv * a0; V1 += dbv * a1; V2 += dbv * a2; V3 += dbv * a3;
+    }
+    double iw = 1.0 / S3;
+    double x0 = S0 * iw, x1 = S1 * iw, x2 = S2 * iw;
+    double u0 = (U0 - x0 * U3) * iw, u1 = (U1 - x1 * U3) * iw, u2 = (U2 - x2 * U3) * iw;
+    double v0 = (V0 - x0 * V3) * iw, v1 = (V1 - x1 * V3) * iw, v2 = (V2 - x2 * V3) * iw;
+    X[0] = x0;
+    X[1] = x1;
+    X[2] = x2;
+    double n0 = u1 * v2 - u2 * v1, n1 = u2 * v0 - u0 * v2, n2 = u0 * v1 - u1 * v0;
+    *kap = sqrt(n0 * n0 + n1 * n1 + n2 * n2);
+}
+
+template <class T> struct NComp { static constexpr int value = 1; };
+template <> struct NComp<cd> { static constexpr int value = 2; };
+
+__device__ inline double re_(double a) { return a; }
+__device__ inline double re_(cd a) { return a.re; }
+__device__ inline double im_(double) { return 0.0; }
+__device__ inline double im_(cd a) { return a.im; }
+
 }  // namespace igb

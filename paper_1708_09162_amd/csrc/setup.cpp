@@ -9,8 +9,35 @@
 #include <cmath>
 #include <cstring>
 #include <numeric>
+#include <thread>
 
 namespace igb {
+
+// Run f(begin, end, worker) over [0, n) split into contiguous chunks on up to
+// hardware_concurrency threads (at most 32).  Results that must stay ordered
+// are written per chunk by the callers and concatenated in chunk order.
+template <class F>
+static void parallel_chunks(int64_t n, int max_chunks, F f)
+{
+    unsigned hw = std::max(1u, std::min(32u, std::thread::hardware_concurrency()));
+    int nch = (int)std::max<int64_t>(1, std::min<int64_t>({(int64_t)hw, (int64_t)max_chunks, n}));
+    if (nch <= 1 || n < 64) {
+        f((int64_t)0, n, 0);
+        return;
+    }
+    std::vector<std::thread> th;
+    for (int c = 0; c < nch; ++c) {
+        int64_t b = n * c / nch, e = n * (c + 1) / nch;
+        th.emplace_back([=, &f] { f(b, e, c); });
+    }
+    for (auto &t : th) t.join();
+}
+
+static int num_workers(int64_t n)
+{
+    unsigned hw = std::max(1u, std::min(32u, std::thread::hardware_concurrency()));
+    return (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)hw, n));
+}
 
 // ---------------------------------------------------------------------------
 // Gauss-Legendre on [0,1]: Newton on P_n from Chebyshev-like initial guesses.
@@ -294,7 +321,8 @@ static void level_geo(const Setup &s, int l, LevelGeo &G)
     G.cen.resize((size_t)ncl * 3);
     G.rad.resize(ncl);
     double sc = 1.0 / n;
-    for (int c = 0; c < ncl; ++c) {
+    parallel_chunks(ncl, 64, [&](int64_t cb, int64_t ce, int) {
+    for (int c = (int)cb; c < (int)ce; ++c) {
         int patch = c / (n * n), r = c % (n * n), k2 = r / n, k1 = r % n;
         double *P = &G.pts[(size_t)c * 75];
         for (int b = 0; b < 5; ++b)
@@ -311,6 +339,7 @@ static void level_geo(const Setup &s, int l, LevelGeo &G)
         for (int i = 0; i < 25; ++i) rr = std::max(rr, dist(C, P + 3 * i));
         G.rad[c] = rr;
     }
+    });
 }
 
 // admissibility max(diam) < eta * dist over the 5x5 grids (bounds decide clear cases)
@@ -342,8 +371,14 @@ static void build_partition(Setup &s)
         if (!dense) level_geo(s, l, G);
         std::vector<BP> nxt;
         int n = 1 << l, nn = 2 * n;
-        for (const BP &bp : cur) {
-            if (!dense && admissible(s, G, bp.t, bp.src)) {
+        std::vector<char> adm(cur.size(), 0);
+        if (!dense)
+            parallel_chunks((int64_t)cur.size(), 1 << 30, [&](int64_t b, int64_t e, int) {
+                for (int64_t k = b; k < e; ++k) adm[k] = admissible(s, G, cur[k].t, cur[k].src) ? 1 : 0;
+            });
+        for (size_t k = 0; k < cur.size(); ++k) {
+            const BP &bp = cur[k];
+            if (adm[k]) {
                 s.far.push_back(l);
                 s.far.push_back(bp.t);
                 s.far.push_back(bp.src);
@@ -421,7 +456,8 @@ static std::string build_pairs(Setup &s)
 {
     // element corners and 3x3 grids
     std::vector<double> corner((size_t)s.nelem * 12), grid((size_t)s.nelem * 27), diam(s.nelem);
-    for (int E = 0; E < s.nelem; ++E) {
+    parallel_chunks(s.nelem, 1 << 30, [&](int64_t eb, int64_t ee, int) {
+    for (int E = (int)eb; E < (int)ee; ++E) {
         for (int c = 0; c < 4; ++c) tile_eval(s, E, kCorner[c][0], kCorner[c][1], &corner[(size_t)E * 12 + 3 * c], nullptr);
         for (int b = 0; b < 3; ++b)
             for (int a = 0; a < 3; ++a) tile_eval(s, E, 0.5 * a, 0.5 * b, &grid[(size_t)E * 27 + 3 * (3 * b + a)], nullptr);
@@ -430,6 +466,7 @@ static std::string build_pairs(Setup &s)
             for (int j = i + 1; j < 9; ++j) d = std::max(d, dist(&grid[(size_t)E * 27 + 3 * i], &grid[(size_t)E * 27 + 3 * j]));
         diam[E] = d;
     }
+    });
     auto leaf_of = [&](int E, int &el) {
         int pt = E / (s.ne * s.ne), r = E % (s.ne * s.ne), e2 = r / s.ne, e1 = r % s.ne;
         int nL = 1 << s.L;
@@ -445,7 +482,13 @@ static std::string build_pairs(Setup &s)
     s.pairs.clear();
     for (int c = 0; c < 4; ++c) s.npairs_class[c] = 0;
     int nL = 1 << s.L;
-    for (size_t k = 0; k < s.near.size() / 2; ++k) {
+    int64_t nnear = (int64_t)(s.near.size() / 2);
+    int nw = num_workers(nnear);
+    std::vector<std::vector<PairRec>> part(nw);
+    std::vector<int> bad(nw, 0);
+    parallel_chunks(nnear, nw, [&](int64_t kb, int64_t ke, int w) {
+    std::vector<PairRec> &out = part[w];
+    for (int64_t k = kb; k < ke; ++k) {
         int t = s.near[2 * k], src = s.near[2 * k + 1];
         int pt = t / (nL * nL), rt = t % (nL * nL), t2 = rt / nL, t1 = rt % nL;
         int ps = src / (nL * nL), rs = src % (nL * nL), s2 = rs / nL, s1 = rs % nL;
@@ -466,7 +509,7 @@ static std::string build_pairs(Setup &s)
                         R.elF = (int8_t)elF;
                         R.blk1 = block_index(lE, lF);
                         R.blk2 = (E == F) ? -1 : block_index(lF, lE);
-                        if (R.blk1 < 0 || (E != F && R.blk2 < 0)) return "near-field partition is not symmetric";
+                        if (R.blk1 < 0 || (E != F && R.blk2 < 0)) { bad[w] = 1; continue; }
                         R.oE = 0; R.aE = 1; R.bE = 3; R.oF = 0; R.aF = 1; R.bF = 3;
                         double md = std::max(diam[E], diam[F]);
                         if (E == F) {
@@ -512,15 +555,62 @@ static std::string build_pairs(Setup &s)
                                 R.order = g;
                             }
                         }
-                        s.npairs_class[R.cls]++;
-                        s.pairs.push_back(R);
+                        out.push_back(R);
                     }
             }
+    }
+    });
+    for (int w = 0; w < nw; ++w) {
+        if (bad[w]) return "near-field partition is not symmetric";
+        for (const PairRec &R : part[w]) s.npairs_class[R.cls]++;
+        s.pairs.insert(s.pairs.end(), part[w].begin(), part[w].end());
     }
     std::sort(s.pairs.begin(), s.pairs.end(), [](const PairRec &a, const PairRec &b) {
         return std::make_pair(a.E, a.F) < std::make_pair(b.E, b.F);
     });
     return "";
+}
+
+// ---------------------------------------------------------------------------
+// Degree elevation of a rational Bezier tile in homogeneous form from (pu, pv)
+// to (PG, PG): c'_i = i/(p+1) c_{i-1} + (1 - i/(p+1)) c_i, one degree at a time.
+// ---------------------------------------------------------------------------
+static void elevate_tile(const std::vector<double> &Hin, int pu, int pv, int PG, double *out)
+{
+    std::vector<double> H = Hin;
+    int cu = pu, cv = pv;
+    auto at = [&](std::vector<double> &A, int nu, int i, int j) { return &A[4 * ((size_t)j * (nu + 1) + i)]; };
+    while (cu < PG) {
+        std::vector<double> N((size_t)(cu + 2) * (cv + 1) * 4, 0.0);
+        for (int j = 0; j <= cv; ++j)
+            for (int i = 0; i <= cu + 1; ++i) {
+                double a = (double)i / (cu + 1);
+                for (int c = 0; c < 4; ++c) {
+                    double v = 0.0;
+                    if (i >= 1) v += a * at(H, cu, i - 1, j)[c];
+                    if (i <= cu) v += (1.0 - a) * at(H, cu, i, j)[c];
+                    at(N, cu + 1, i, j)[c] = v;
+                }
+            }
+        H.swap(N);
+        ++cu;
+    }
+    while (cv < PG) {
+        std::vector<double> N((size_t)(cu + 1) * (cv + 2) * 4, 0.0);
+        for (int j = 0; j <= cv + 1; ++j)
+            for (int i = 0; i <= cu; ++i) {
+                double a = (double)j / (cv + 1);
+                for (int c = 0; c < 4; ++c) {
+                    double v = 0.0;
+                    if (j >= 1) v += a * at(H, cu, i, j - 1)[c];
+                    if (j <= cv) v += (1.0 - a) * at(H, cu, i, j)[c];
+                    at(N, cu, i, j)[c] = v;
+                }
+            }
+        H.swap(N);
+        ++cv;
+    }
+    std::memcpy(out, H.data(), sizeof(double) * 4 * (PG + 1) * (PG + 1));
 }
 
 // ---------------------------------------------------------------------------
@@ -581,12 +671,15 @@ std::string build_setup(const Geometry &geo, const igb_params &prm, Setup &s)
     s.gw.assign(s.goff[41], 0.0);
     for (int n = 1; n <= 40; ++n) gauss_rule(n, &s.gx[s.goff[n]], &s.gw[s.goff[n]]);
 
-    // element tiles by Bezier extraction
+    // element tiles by Bezier extraction, degree-elevated to one common bidegree
+    // (exact) so that every tile has the same compile-time shape on the device
     int pmax = 0;
     for (const Patch &P : geo.patches) pmax = std::max(pmax, std::max(P.pu, P.pv));
-    s.tile_stride = (pmax + 1) * (pmax + 1) * 4;
+    int PG = pmax <= 1 ? 1 : (pmax <= 2 ? 2 : (pmax <= 4 ? 4 : 8));
+    s.tile_degree = PG;
+    s.tile_stride = (PG + 1) * (PG + 1) * 4;
     s.tiles.assign((size_t)s.nelem * s.tile_stride, 0.0);
-    s.tile_deg.assign((size_t)s.nelem * 2, 0);
+    s.tile_deg.assign((size_t)s.nelem * 2, PG);
     for (int pt = 0; pt < s.npatch; ++pt) {
         const Patch &P = geo.patches[pt];
         std::vector<double> Mu, Mv;
@@ -595,18 +688,13 @@ std::string build_setup(const Geometry &geo, const igb_params &prm, Setup &s)
         if (!err.empty()) return "patch " + std::to_string(pt) + " u: " + err;
         err = extraction(P.pv, P.V, P.nv, s.ne, Mv, nrv);
         if (!err.empty()) return "patch " + std::to_string(pt) + " v: " + err;
-        int su = std::max(P.pu, 1) , sv = std::max(P.pv, 1);
-        if (P.pu == 0) su = 1;
-        if (P.pv == 0) sv = 1;
+        std::vector<double> H((size_t)(P.pu + 1) * (P.pv + 1) * 4);
         for (int e2 = 0; e2 < s.ne; ++e2)
             for (int e1 = 0; e1 < s.ne; ++e1) {
                 int E = pt * s.ne * s.ne + e2 * s.ne + e1;
-                s.tile_deg[2 * E] = P.pu;
-                s.tile_deg[2 * E + 1] = P.pv;
-                double *H = &s.tiles[(size_t)E * s.tile_stride];
                 for (int rv = 0; rv <= P.pv; ++rv)
                     for (int ru = 0; ru <= P.pu; ++ru) {
-                        int ku = (P.pu == 0 ? e1 : e1 * su + ru), kv = (P.pv == 0 ? e2 : e2 * sv + rv);
+                        int ku = (P.pu == 0 ? e1 : e1 * P.pu + ru), kv = (P.pv == 0 ? e2 : e2 * P.pv + rv);
                         double acc[4] = {0, 0, 0, 0};
                         for (int j = 0; j < P.nv; ++j) {
                             double cv = Mv[(size_t)kv * P.nv + j];
@@ -622,9 +710,9 @@ std::string build_setup(const Geometry &geo, const igb_params &prm, Setup &s)
                                 acc[3] += f;
                             }
                         }
-                        double *h = H + 4 * (rv * (P.pu + 1) + ru);
-                        for (int c = 0; c < 4; ++c) h[c] = acc[c];
+                        for (int c = 0; c < 4; ++c) H[4 * (rv * (P.pu + 1) + ru) + c] = acc[c];
                     }
+                elevate_tile(H, P.pu, P.pv, PG, &s.tiles[(size_t)E * s.tile_stride]);
             }
     }
     // T band on Xi_{p,m}

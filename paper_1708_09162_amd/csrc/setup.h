@@ -50,6 +50,7 @@ struct Setup {
     int n1 = 1;          // 1D leaf functions per direction (2^d (p+1))
     int nleaf = 0;       // clusters at level L
     // element geometry: homogeneous rational Bezier tiles, stride tile_stride doubles
+    int tile_degree = 1;             // common bidegree of all tiles (1, 2, 4 or 8)
     int tile_stride = 0;
     std::vector<int32_t> tile_deg;   // per element: pu, pv
     std::vector<double> tiles;

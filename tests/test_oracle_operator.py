@@ -158,3 +158,20 @@ def test_h2_approaches_dense_as_q_grows():
         errs.append(np.linalg.norm(P.h2_matvec_super(x) - y) / np.linalg.norm(y))
     assert errs[0] > errs[1] > errs[2]
     assert errs[2] < 2e-4
+
+
+def test_helmholtz_h2_approaches_dense():
+    """The complex far field (Helmholtz kernel at Chebyshev node pairs) converges to the dense operator."""
+    k = 1.5
+    Pd = oracle.Problem(SPH, kernel=oracle.HELMHOLTZ, wavenumber=k, p=0, m=3, q=2, gauss_regular=4)
+    A = Pd.dense_super()
+    rng = np.random.default_rng(6)
+    x = rng.standard_normal(Pd.nsup) + 1j * rng.standard_normal(Pd.nsup)
+    y = A @ x
+    errs = []
+    for q in (2, 4, 6):
+        P = oracle.Problem(SPH, kernel=oracle.HELMHOLTZ, wavenumber=k, p=0, m=3, q=q, leaf_depth=1, eta=1.6,
+                           gauss_regular=4)
+        errs.append(np.linalg.norm(P.h2_matvec_super(x) - y) / np.linalg.norm(y))
+    assert errs[0] > errs[1] > errs[2]
+    assert errs[2] < 5e-4

@@ -60,8 +60,9 @@ def read_traffic(stage: str):
     if vals.get("source_sha256_16") != source_sha():
         return None
     try:
-        kib = float(vals["FETCH_SIZE_KiB_per_dispatch"]) + float(vals["WRITE_SIZE_KiB_per_dispatch"])
-        return kib * 1024.0 * float(vals.get("copy_scale", "1.0"))
+        fetch = float(vals["FETCH_SIZE_KiB_per_dispatch"]) * float(vals.get("fetch_scale", "1.0"))
+        write = float(vals["WRITE_SIZE_KiB_per_dispatch"]) * float(vals.get("write_scale", "1.0"))
+        return int(round((fetch + write) * 1024.0))
     except (KeyError, ValueError):
         return None
 

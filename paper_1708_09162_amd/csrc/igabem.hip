@@ -590,23 +590,42 @@ __global__ void k_Tt(Layout lo, int64_t nsup, const double *__restrict__ Tb, con
     xs[a] = s;
 }
 
+// y = T ys applied as (T1 (x) T1) per patch in two separable passes.
+// Pass 1: Z[patch][e2][r2][j1] = sum_{e1, r1} T1[j1, (e1, r1)] ys[patch, e1, e2, r1, r2]
 template <class T>
-__global__ void k_T(Layout lo, int64_t ndof, const double *__restrict__ Tb, const T *__restrict__ ys, T *__restrict__ y)
+__global__ void k_T_pass1(Layout lo, int npatch, const double *__restrict__ Tb, const T *__restrict__ ys, T *__restrict__ Z)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t n = (int64_t)npatch * lo.ne * lo.P1 * lo.ns1;
+    if (i >= n) return;
+    int j1 = (int)(i % lo.ns1);
+    int64_t rest = i / lo.ns1;
+    int r2 = (int)(rest % lo.P1);
+    rest /= lo.P1;
+    int e2 = (int)(rest % lo.ne);
+    int patch = (int)(rest / lo.ne);
+    int lo1 = j1 - lo.p < 0 ? 0 : j1 - lo.p, hi1 = j1 < lo.ne - 1 ? j1 : lo.ne - 1;
+    T s = zero<T>();
+    for (int e1 = lo1; e1 <= hi1; ++e1)
+        for (int r1 = 0; r1 < lo.P1; ++r1)
+            s += Tb[(e1 * lo.P1 + r1) * lo.P1 + (j1 - e1)] * ys[encode_internal(lo, patch, e1, e2, r1, r2)];
+    Z[i] = s;
+}
+
+// Pass 2: y[patch][j2][j1] = sum_{e2, r2} T1[j2, (e2, r2)] Z[patch][e2][r2][j1]
+template <class T>
+__global__ void k_T_pass2(Layout lo, int64_t ndof, const double *__restrict__ Tb, const T *__restrict__ Z, T *__restrict__ y)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= ndof) return;
     int nn = lo.ns1 * lo.ns1;
     int patch = (int)(i / nn), r = (int)(i % nn), j2 = r / lo.ns1, j1 = r % lo.ns1;
-    T s = zero<T>();
-    int lo1 = j1 - lo.p < 0 ? 0 : j1 - lo.p, hi1 = j1 < lo.ne - 1 ? j1 : lo.ne - 1;
     int lo2 = j2 - lo.p < 0 ? 0 : j2 - lo.p, hi2 = j2 < lo.ne - 1 ? j2 : lo.ne - 1;
+    const T *Zp = Z + (int64_t)patch * lo.ne * lo.P1 * lo.ns1;
+    T s = zero<T>();
     for (int e2 = lo2; e2 <= hi2; ++e2)
-        for (int e1 = lo1; e1 <= hi1; ++e1)
-            for (int r2 = 0; r2 < lo.P1; ++r2)
-                for (int r1 = 0; r1 < lo.P1; ++r1) {
-                    double t = Tb[(e1 * lo.P1 + r1) * lo.P1 + (j1 - e1)] * Tb[(e2 * lo.P1 + r2) * lo.P1 + (j2 - e2)];
-                    s += t * ys[encode_internal(lo, patch, e1, e2, r1, r2)];
-                }
+        for (int r2 = 0; r2 < lo.P1; ++r2)
+            s += Tb[(e2 * lo.P1 + r2) * lo.P1 + (j2 - e2)] * Zp[((int64_t)e2 * lo.P1 + r2) * lo.ns1 + j1];
     y[i] = s;
 }
 
@@ -1015,6 +1034,7 @@ struct igb_operator {
     void *hdev = nullptr;      // GMRES projection coefficients
     void *mpart = nullptr;     // GMRES multi-dot partial sums
     void *potc = nullptr;      // potential: weighted density at the quadrature points
+    void *tz = nullptr;        // intermediate of the separable T application
     int64_t near_bytes = 0, coup_bytes = 0;
     double assembly_seconds = 0.0;
     std::vector<void *> owned;
@@ -1199,7 +1219,12 @@ static igb_status apply_Tt(igb_operator *op, const T *w, T *xs)
 template <class T>
 static igb_status apply_T(igb_operator *op, const T *ys, T *y)
 {
-    hipLaunchKernelGGL((k_T<T>), dim3(nblk(op->s.ndof, 256)), dim3(256), 0, op->st, op->lo, op->s.ndof, op->Tb, ys, y);
+    int64_t nz = (int64_t)op->s.npatch * op->s.ne * (op->s.p + 1) * op->s.ns1;
+    hipLaunchKernelGGL((k_T_pass1<T>), dim3(nblk(nz, 256)), dim3(256), 0, op->st, op->lo, op->s.npatch, op->Tb, ys,
+                       (T *)op->tz);
+    LAUNCHCHK();
+    hipLaunchKernelGGL((k_T_pass2<T>), dim3(nblk(op->s.ndof, 256)), dim3(256), 0, op->st, op->lo, op->s.ndof, op->Tb,
+                       (const T *)op->tz, y);
     LAUNCHCHK();
     return IGB_OK;
 }
@@ -1356,6 +1381,7 @@ static igb_status create_device(igb_operator *op)
     for (void **v : {&op->r, &op->z, &op->pv, &op->Ap, &op->tmp})
         if ((rc = dalloc(op, v, s.ndof * esz))) return rc;
     if ((rc = dalloc(op, &op->part, kRedBlocks * esz))) return rc;
+    if ((rc = dalloc(op, &op->tz, (size_t)s.npatch * s.ne * (s.p + 1) * s.ns1 * esz))) return rc;
     if ((rc = dalloc(op, (void **)&op->scal, 16 * sizeof(double)))) return rc;
     HIPCHK(hipHostMalloc((void **)&op->h_scal, 16 * sizeof(double), hipHostMallocDefault));
     if ((rc = dalloc(op, &op->potc, (size_t)s.nelem * s.grhs * s.grhs * esz))) return rc;

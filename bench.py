@@ -33,8 +33,14 @@ if ROOT not in sys.path:
 
 METRIC = "time-to-solve (rel res 1e-8) + H2 matvec GB/s; mixed/learned vs plain FP64"
 HBM_PEAK_GBPS = 8000.0
+# FP64 vector peak: 256 CUs x 4 SIMDs x 16 lanes x 2 flop (FMA) x 2.4 GHz = 78.6 TFLOP/s
+FP64_VECTOR_PEAK_TFLOPS = 78.6
+# flop model of one Laplace kernel evaluation in the far field: 3 differences, 5 for |d|^2,
+# 2 for the reciprocal square root, 2 for the accumulation
+FLOP_PER_EVAL_LAPLACE = 12
 WORKLOAD = "laplace_sphere_p3_m5_q8"
 PRM = dict(p=3, m=5, q=8, eta=1.6, gauss_regular=6)
+MODES = {"onthefly": 2, "stored": 1}
 TOL = 1e-8
 PROFILE_DIR = os.path.join(ROOT, "profiles")
 KERNEL_SRC = os.path.join(ROOT, "paper_1708_09162_amd", "csrc", "igabem.hip")
@@ -89,12 +95,12 @@ def charge_field(torch, pts, pos, q):
     return g
 
 
-def one_step(torch, igb, geo, cfg, ev_dev):
+def one_step(torch, igb, geo, cfg, ev_dev, mode):
     """The whole path once; returns (operator, density, solve info, potential, timings)."""
     t = {}
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    op = igb.Operator(geo, device="cuda:0", **PRM)
+    op = igb.Operator(geo, device="cuda:0", mode=MODES[mode], **PRM)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     pts = op.rhs_points()
@@ -153,6 +159,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--matvec-reps", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--mode", choices=sorted(MODES), default="onthefly",
+                    help="far field: coupling blocks generated in every matvec (default) or stored in HBM")
     ap.add_argument("--calibrate-copy", action="store_true", help="only run a plain 1 GiB device copy")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -178,7 +186,7 @@ def main():
     for i in range(args.warmup):
         if op is not None:
             del op
-        op, w, info, u, t = one_step(torch, igb, geo, cfg, ev_dev)
+        op, w, info, u, t = one_step(torch, igb, geo, cfg, ev_dev, args.mode)
         print(f"[bench] warmup {i}: {t['total_s']:.3f} s, {info.iterations} it", file=sys.stderr, flush=True)
     times = []
     torch.cuda.synchronize()
@@ -186,7 +194,7 @@ def main():
     for i in range(args.steps):
         if op is not None:
             del op
-        op, w, info, u, t = one_step(torch, igb, geo, cfg, ev_dev)
+        op, w, info, u, t = one_step(torch, igb, geo, cfg, ev_dev, args.mode)
         times.append(t)
         print(f"[bench] step {i}: {t['total_s']:.3f} s (assembly {t['assembly_s']:.3f}, solve {t['solve_s']:.3f},"
               f" {info.iterations} it, relres {info.rel_residual:.2e})", file=sys.stderr, flush=True)
@@ -213,25 +221,42 @@ def main():
     mv_ms = float(np.median(mv))
     gbps = op.info.matvec_bytes / (mv_ms * 1e-3) / 1e9
 
-    # per-stage durations (HIP events on the operator's stream) and the dominant kernel's roofline
+    # per-stage durations (HIP events on the operator's stream) and the rooflines of the two
+    # dominant matvec kernels: near-field block GEMV (HBM) and far field (HBM when coupling
+    # blocks are stored, FP64 ALU when they are generated on the fly)
     stages = op.profile(reps=args.matvec_reps)
     near, far = op.partition()
     q2 = PRM["q"] ** 2
     npatch = len(cfg["patches"])
     off = np.concatenate([[0], np.cumsum([npatch << (2 * l) for l in range(op.info.leaf_level + 1)])])
-    rows = len(np.unique(off[far[:, 0]] + far[:, 1]))  # clusters with coupling blocks (rows written)
+    rows = len(np.unique(off[far[:, 0]] + far[:, 1]))  # clusters with far blocks (rows written)
     srcs = len(np.unique(off[far[:, 0]] + far[:, 2]))  # distinct source moment vectors read
-    alg_bytes = {
-        "coupling_gemv": op.info.coupling_bytes + 8 * q2 * (rows + srcs),
-        "near_gemv": op.info.near_bytes + 8 * 2 * op.info.n_dof_super,
-    }
-    dom = max(alg_bytes, key=lambda k: stages[k])
-    achieved = alg_bytes[dom] / (stages[dom] * 1e-3) / 1e9
-    kname = {"coupling_gemv": "k_bsr_gemv<double, 1>", "near_gemv": "k_bsr_gemv<double, 0>"}[dom]
-    roofline = {"bound": "hbm", "kernel": kname, "achieved": round(achieved, 1),
-                "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
-                "traffic": read_traffic(dom), "algorithmic_bytes": int(alg_bytes[dom]),
-                "avg_ms": round(stages[dom], 4)}
+    roofs = {}
+    near_bytes = op.info.near_bytes + 8 * 2 * op.info.n_dof_super
+    a = near_bytes / (stages["near_gemv"] * 1e-3) / 1e9
+    roofs["near_gemv"] = {"bound": "hbm", "kernel": "k_bsr_gemv<double, 0>", "achieved": round(a, 1),
+                          "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": round(a / HBM_PEAK_GBPS, 4),
+                          "traffic": read_traffic("near_gemv"), "algorithmic_bytes": int(near_bytes),
+                          "avg_ms": round(stages["near_gemv"], 4)}
+    if args.mode == "stored":
+        cb = op.info.coupling_bytes + 8 * q2 * (rows + srcs)
+        a = cb / (stages["coupling_gemv"] * 1e-3) / 1e9
+        roofs["coupling_gemv"] = {"bound": "hbm", "kernel": "k_bsr_gemv<double, 1>", "achieved": round(a, 1),
+                                  "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": round(a / HBM_PEAK_GBPS, 4),
+                                  "traffic": read_traffic("coupling_gemv"), "algorithmic_bytes": int(cb),
+                                  "avg_ms": round(stages["coupling_gemv"], 4)}
+    else:
+        evals = len(far) * q2 * q2
+        flops = FLOP_PER_EVAL_LAPLACE * evals
+        a = flops / (stages["coupling_gemv"] * 1e-3) / 1e12
+        roofs["coupling_gemv"] = {"bound": "alu", "kernel": "k_far_onthefly<double>", "achieved": round(a, 2),
+                                  "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                                  "frac": round(a / FP64_VECTOR_PEAK_TFLOPS, 4), "traffic": None,
+                                  "algorithmic_flops": int(flops), "kernel_evaluations": int(evals),
+                                  "flop_per_evaluation": FLOP_PER_EVAL_LAPLACE,
+                                  "avg_ms": round(stages["coupling_gemv"], 4)}
+    dom = max(roofs, key=lambda k: stages[k])
+    roofline = roofs[dom]
 
     mean = {k: float(np.mean([t[k] for t in times])) for k in times[0]} if times else {}
     out = {
@@ -250,7 +275,7 @@ def main():
         "config": {"workload": WORKLOAD, "geometry": "unit sphere, 6 rational NURBS patches of bidegree 4",
                    "kernel": "laplace", "p": PRM["p"], "m": PRM["m"], "q": PRM["q"], "eta": PRM["eta"],
                    "gauss_regular": PRM["gauss_regular"], "n_dof": int(op.info.n_dof),
-                   "n_dof_super": int(op.info.n_dof_super), "rel_tol": TOL, "mode": "h2_stored"},
+                   "n_dof_super": int(op.info.n_dof_super), "rel_tol": TOL, "mode": "h2_" + args.mode},
         "h2_matvec_GBps": round(gbps, 1),
         "h2_matvec_ms": round(mv_ms, 4),
         "matvec_bytes": int(op.info.matvec_bytes),
@@ -263,6 +288,7 @@ def main():
         "near_blocks": int(op.info.n_near_blocks),
         "far_blocks": int(op.info.n_far_blocks),
         "roofline": roofline,
+        "roofline_stages": roofs,
         "cpu_baseline": None,
     }
     if not args.no_cpu_baseline:

@@ -49,6 +49,7 @@ typedef int32_t igb_status;
 
 #define IGB_DENSE 0              /* every element pair by quadrature, no compression */
 #define IGB_H2_STORED 1          /* near field + far field with coupling blocks stored in HBM */
+#define IGB_H2_ONTHEFLY 2        /* near field stored; coupling blocks generated inside every matvec */
 
 #define IGB_FP64 0
 
@@ -79,7 +80,7 @@ typedef struct {
     int32_t gauss_regular;   /* g0: Gauss points per direction for well separated pairs, 1..36 */
     int32_t gauss_singular;  /* points per variable in the regularised touching-pair rules; -1: g0+2 */
     int32_t gauss_rhs;       /* points per direction for right-hand side and potential; -1: max(g0, p+4) */
-    int32_t mode;            /* IGB_DENSE or IGB_H2_STORED */
+    int32_t mode;            /* IGB_DENSE, IGB_H2_STORED or IGB_H2_ONTHEFLY */
     int32_t far_precision;   /* IGB_FP64 */
 } igb_params;
 

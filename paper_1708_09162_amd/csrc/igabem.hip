@@ -179,35 +179,32 @@ __device__ inline void frame_map(int o, int a, int b, double s, double t, double
 typedef double v4d __attribute__((ext_vector_type(4)));
 
 template <class T, int P, int PG, int WAVES>
-__global__ void __launch_bounds__(64 * WAVES, NComp<T>::value == 1 ? 3 : 1) k_near_singular(const PairRec *__restrict__ pairs, int gs,
-                                                             const double *__restrict__ gxs, const double *__restrict__ gws,
-                                                             const double *__restrict__ tiles, double kappa, int nl,
-                                                             T *__restrict__ blocks)
+__global__ void __launch_bounds__(64 * WAVES, NComp<T>::value == 1 ? 3 : 1) k_near_singular(
+    const PairRec *__restrict__ pairs, int gs, const double *__restrict__ gxs, const double *__restrict__ gws,
+    const double *__restrict__ tiles, double kappa, int nl, T *__restrict__ blocks)
 {
     constexpr int P1 = P + 1, NLOC = P1 * P1, NT = (NLOC + 15) / 16, NPAD = 16 * NT;
     constexpr int NC = NComp<T>::value;
-    constexpr int G1 = PG + 1, TS = G1 * G1 * 4;
-    constexpr int STAGE = 64 * (NC + 1) * NPAD;  // doubles per wave
+    constexpr int TS = (PG + 1) * (PG + 1) * 4;
+    constexpr int HALF = 32;                        // points staged per half-batch
+    constexpr int STAGE = HALF * (NC + 1) * NPAD;  // doubles per wave
     extern __shared__ double sh[];
-    double *tE = sh, *tF = tE + TS, *nx = tF + TS, *nw = nx + 64;
+    double *nx = sh, *nw = nx + 64;
     double *stg = nw + 64;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    double *Ub = stg + wave * STAGE;   // [NC][64][NPAD]
-    double *Vb = Ub + NC * 64 * NPAD;  // [64][NPAD]
+    double *Ub = stg + wave * STAGE;     // [NC][HALF][NPAD]
+    double *Vb = Ub + NC * HALF * NPAD;  // [HALF][NPAD]
     const PairRec R = pairs[blockIdx.x];
-    for (int k = threadIdx.x; k < TS; k += blockDim.x) {
-        tE[k] = tiles[(size_t)R.E * TS + k];
-        tF[k] = tiles[(size_t)R.F * TS + k];
-    }
+    // tiles are read through the scalar cache (uniform addresses, SGPR operands)
+    const double *tEg = tiles + (size_t)R.E * TS, *tFg = tiles + (size_t)R.F * TS;
     for (int k = threadIdx.x; k < gs; k += blockDim.x) {
         nx[k] = gxs[k];
         nw[k] = gws[k];
     }
-    // zero padding columns once (never written afterwards)
-    for (int k = lane; k < 64 * (NPAD - NLOC); k += 64) {
+    for (int k = lane; k < HALF * (NPAD - NLOC); k += 64) {
         int pt = k / (NPAD - NLOC), a = NLOC + k % (NPAD - NLOC);
 #pragma unroll
-        for (int c = 0; c < NC; ++c) Ub[c * 64 * NPAD + pt * NPAD + a] = 0.0;
+        for (int c = 0; c < NC; ++c) Ub[c * HALF * NPAD + pt * NPAD + a] = 0.0;
         Vb[pt * NPAD + a] = 0.0;
     }
     __syncthreads();
@@ -215,13 +212,16 @@ __global__ void __launch_bounds__(64 * WAVES, NComp<T>::value == 1 ? 3 : 1) k_ne
     const int nreg = R.cls == 1 ? 8 : (R.cls == 2 ? 6 : 4);
     const int npts = nreg * g4;
     const int niter = (npts + 64 * WAVES - 1) / (64 * WAVES);
-    v4d acc[NC][NT][NT];
+    v4d acc[2][NC][NT][NT];
 #pragma unroll
-    for (int c = 0; c < NC; ++c)
+    for (int h = 0; h < 2; ++h)
 #pragma unroll
-        for (int i = 0; i < NT; ++i)
+        for (int c = 0; c < NC; ++c)
 #pragma unroll
-            for (int j = 0; j < NT; ++j) acc[c][i][j] = v4d{0.0, 0.0, 0.0, 0.0};
+            for (int i = 0; i < NT; ++i)
+#pragma unroll
+                for (int j = 0; j < NT; ++j) acc[h][c][i][j] = v4d{0.0, 0.0, 0.0, 0.0};
+    const int col = lane & 15, sub = lane >> 4;
     for (int it = 0; it < niter; ++it) {
         int idx = (it * WAVES + wave) * 64 + lane;
         // inactive lanes: two distinct points and zero weight
@@ -261,13 +261,13 @@ __global__ void __launch_bounds__(64 * WAVES, NComp<T>::value == 1 ? 3 : 1) k_ne
                 frame_map(R.oF, R.aF, R.bF, v2, v3, ys, yt);
             }
         }
-        // an opaque zero offset keeps the tile reads inside the loop: hoisting
-        // both tiles into registers would cost 4 (PG+1)^2 VGPRs each
+        // an opaque zero offset (in a scalar register) keeps the tile reads inside
+        // the loop: hoisting both tiles would cost 4 (PG+1)^2 registers each
         int zoff = 0;
-        asm volatile("" : "+v"(zoff));
+        asm volatile("" : "+s"(zoff));
         double X[3], Yp[3], kx, ky;
-        tile_point_t<PG>(tE + zoff, xs, xt, X, &kx);
-        tile_point_t<PG>(tF + zoff, ys, yt, Yp, &ky);
+        tile_point_t<PG>(tEg + zoff, xs, xt, X, &kx);
+        tile_point_t<PG>(tFg + zoff, ys, yt, Yp, &ky);
         double d0 = X[0] - Yp[0], d1 = X[1] - Yp[1], d2 = X[2] - Yp[2];
         T c = green<T>(sqrt(d0 * d0 + d1 * d1 + d2 * d2), kappa) * (W * kx * ky);
         double bx1[P1], bx2[P1], by1[P1], by2[P1];
@@ -275,53 +275,61 @@ __global__ void __launch_bounds__(64 * WAVES, NComp<T>::value == 1 ? 3 : 1) k_ne
         bernstein_t<P>(xt, bx2);
         bernstein_t<P>(ys, by1);
         bernstein_t<P>(yt, by2);
-        double cre = re_(c), cim = im_(c);
+        const double cre = re_(c), cim = im_(c);
+        // two half-batches of 32 points: stage, then 8 MFMA steps of 4 points each
 #pragma unroll
-        for (int a2 = 0; a2 < P1; ++a2)
+        for (int hb = 0; hb < 2; ++hb) {
+            if ((lane >> 5) == hb) {
+                const int pl = lane & 31;
 #pragma unroll
-            for (int a1 = 0; a1 < P1; ++a1) {
-                double fx = bx1[a1] * bx2[a2];
-                Ub[lane * NPAD + a2 * P1 + a1] = cre * fx;
-                if constexpr (NC == 2) Ub[64 * NPAD + lane * NPAD + a2 * P1 + a1] = cim * fx;
-                Vb[lane * NPAD + a2 * P1 + a1] = by1[a1] * by2[a2];
+                for (int a2 = 0; a2 < P1; ++a2)
+#pragma unroll
+                    for (int a1 = 0; a1 < P1; ++a1) {
+                        double fx = bx1[a1] * bx2[a2];
+                        Ub[pl * NPAD + a2 * P1 + a1] = cre * fx;
+                        if constexpr (NC == 2) Ub[HALF * NPAD + pl * NPAD + a2 * P1 + a1] = cim * fx;
+                        Vb[pl * NPAD + a2 * P1 + a1] = by1[a1] * by2[a2];
+                    }
             }
-        __syncthreads();
-        const int col = lane & 15, sub = lane >> 4;
-#pragma unroll 4
-        for (int j = 0; j < 16; ++j) {
-            const int pt = 4 * j + sub;
-            double bv[NT];
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
 #pragma unroll
-            for (int tb = 0; tb < NT; ++tb) bv[tb] = Vb[pt * NPAD + 16 * tb + col];
+            for (int j = 0; j < HALF / 4; ++j) {
+                const int pt = 4 * j + sub;
+                double bv[NT];
 #pragma unroll
-            for (int c2 = 0; c2 < NC; ++c2)
+                for (int tb = 0; tb < NT; ++tb) bv[tb] = Vb[pt * NPAD + 16 * tb + col];
 #pragma unroll
-                for (int ta = 0; ta < NT; ++ta) {
-                    double av = Ub[c2 * 64 * NPAD + pt * NPAD + 16 * ta + col];
+                for (int c2 = 0; c2 < NC; ++c2)
 #pragma unroll
-                    for (int tb = 0; tb < NT; ++tb)
-                        acc[c2][ta][tb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv[tb], acc[c2][ta][tb], 0, 0, 0);
-                }
+                    for (int ta = 0; ta < NT; ++ta) {
+                        double av = Ub[c2 * HALF * NPAD + pt * NPAD + 16 * ta + col];
+#pragma unroll
+                        for (int tb = 0; tb < NT; ++tb)
+                            acc[j & 1][c2][ta][tb] =
+                                __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv[tb], acc[j & 1][c2][ta][tb], 0, 0, 0);
+                    }
+            }
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
         }
-        __syncthreads();
     }
     // reduce the per-wave accumulators: red[(w*NC + c)*NPAD*NPAD + row*NPAD + col]
+    __syncthreads();
     double *red = stg;
-    {
-        const int col = lane & 15, sub = lane >> 4;
 #pragma unroll
-        for (int c2 = 0; c2 < NC; ++c2)
+    for (int c2 = 0; c2 < NC; ++c2)
 #pragma unroll
-            for (int ta = 0; ta < NT; ++ta)
+        for (int ta = 0; ta < NT; ++ta)
 #pragma unroll
-                for (int tb = 0; tb < NT; ++tb)
+            for (int tb = 0; tb < NT; ++tb)
 #pragma unroll
-                    for (int e = 0; e < 4; ++e) {
-                        // v_mfma_f64_16x16x4f64 result layout: lane l, element e holds D[4e + l/16][l%16]
-                        int row = 16 * ta + 4 * e + sub, cc = 16 * tb + col;
-                        red[((size_t)(wave * NC + c2) * NPAD + row) * NPAD + cc] = acc[c2][ta][tb][e];
-                    }
-    }
+                for (int e = 0; e < 4; ++e) {
+                    // v_mfma_f64_16x16x4f64 result layout: lane l, element e holds D[4e + l/16][l%16]
+                    int row = 16 * ta + 4 * e + sub, cc = 16 * tb + col;
+                    red[((size_t)(wave * NC + c2) * NPAD + row) * NPAD + cc] =
+                        acc[0][c2][ta][tb][e] + acc[1][c2][ta][tb][e];
+                }
     __syncthreads();
     T *out1 = blocks + (int64_t)R.blk1 * nl * nl;
     T *out2 = R.blk2 >= 0 ? blocks + (int64_t)R.blk2 * nl * nl : nullptr;
@@ -540,6 +548,89 @@ __global__ void __launch_bounds__(256) k_bsr_gemv(int nb, const int64_t *__restr
         T s = part[a];
         for (int w = 1; w < nw; ++w) s += part[w * nb + a];
         y[t * nb + a] = s;
+    }
+}
+
+// Far field with coupling blocks generated on the fly (Sec. 4.2): for target
+// cluster t, Y^_t[mu] = kappa_t[mu] sum_{s far} sum_nu G(x_mu, y_nu) kappa_s[nu] X^_s[nu].
+// One workgroup per target row; each wave takes every 4th far block of the
+// row, stages the source nodes and kappa-weighted moments in its own LDS
+// slice, and its lanes own target nodes (up to 4 per lane for q^2 <= 256).
+template <class T>
+__global__ void __launch_bounds__(256) k_far_onthefly(int q2, const int64_t *__restrict__ ptr, const int32_t *__restrict__ src,
+                                                      const double *__restrict__ nodes, const T *__restrict__ Xh,
+                                                      double kappa, T *__restrict__ Yh, int64_t row0)
+{
+    constexpr int NC = NComp<T>::value;
+    constexpr int ST = 3 + NC;  // staged doubles per source node: x, y, z, weight (re, im)
+    extern __shared__ double sh[];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int nw = blockDim.x >> 6;
+    double *S = sh + (size_t)wave * q2 * ST;
+    T *part = (T *)(sh + (size_t)nw * q2 * ST);  // nw * q2
+    const int64_t t = row0 + blockIdx.x;
+    const int64_t k0 = ptr[t], k1 = ptr[t + 1];
+    const int nch = (q2 + 63) >> 6;
+    double tx[4], ty[4], tz[4];
+    T acc[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        int mu = lane + 64 * c;
+        acc[c] = zero<T>();
+        tx[c] = ty[c] = tz[c] = 0.0;
+        if (c < nch && mu < q2) {
+            const double *nd = nodes + ((size_t)t * q2 + mu) * 4;
+            tx[c] = nd[0];
+            ty[c] = nd[1];
+            tz[c] = nd[2];
+        }
+    }
+    for (int64_t k = k0 + wave; k < k1; k += nw) {
+        const int64_t sc = src[k];
+        for (int nu = lane; nu < q2; nu += 64) {
+            const double *nd = nodes + ((size_t)sc * q2 + nu) * 4;
+            T w = Xh[(size_t)sc * q2 + nu] * nd[3];
+            S[nu * ST + 0] = nd[0];
+            S[nu * ST + 1] = nd[1];
+            S[nu * ST + 2] = nd[2];
+            S[nu * ST + 3] = re_(w);
+            if constexpr (NC == 2) S[nu * ST + 4] = im_(w);
+        }
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        for (int nu = 0; nu < q2; ++nu) {
+            const double sx = S[nu * ST], sy = S[nu * ST + 1], sz = S[nu * ST + 2], swr = S[nu * ST + 3];
+            double swi = 0.0;
+            if constexpr (NC == 2) swi = S[nu * ST + 4];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                if (c < nch) {
+                    double d0 = tx[c] - sx, d1 = ty[c] - sy, d2 = tz[c] - sz;
+                    double r2 = d0 * d0 + d1 * d1 + d2 * d2;
+                    if constexpr (NC == 1) {
+                        acc[c] += rsqrt(r2) * swr;
+                    } else {
+                        double ir = rsqrt(r2), sn, cs;
+                        sincos(kappa * (r2 * ir), &sn, &cs);
+                        double gr = cs * ir, gi = sn * ir;
+                        acc[c] += T{gr * swr - gi * swi, gr * swi + gi * swr};
+                    }
+                }
+            }
+        }
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    }
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        int mu = lane + 64 * c;
+        if (c < nch && mu < q2) part[wave * q2 + mu] = acc[c];
+    }
+    __syncthreads();
+    for (int mu = threadIdx.x; mu < q2; mu += blockDim.x) {
+        T sum = part[mu];
+        for (int w = 1; w < nw; ++w) sum += part[w * q2 + mu];
+        Yh[(size_t)t * q2 + mu] = sum * (0.07957747154594767 * nodes[((size_t)t * q2 + mu) * 4 + 3]);
     }
 }
 
@@ -767,6 +858,8 @@ struct DiagArgs {
     const int32_t *near_src;
     const int64_t *far_ptr;
     const int32_t *far_src;
+    const double *nodes;
+    double kappa;
 };
 
 template <class T>
@@ -808,13 +901,20 @@ __global__ void __launch_bounds__(256) k_diag(DiagArgs A, int64_t ndof, const T 
             for (int cb = 0; cb < nc; ++cb) {
                 int ida = patch * n * n + (c2lo + ca / nc1) * n + c1lo + ca % nc1;
                 int idb = patch * n * n + (c2lo + cb / nc1) * n + c1lo + cb % nc1;
-                int64_t k = csr_find(A.far_ptr, A.far_src, A.cl_off[l] + ida, (int32_t)(A.cl_off[l] + idb));
+                int64_t ga = A.cl_off[l] + ida, gb = A.cl_off[l] + idb;
+                int64_t k = csr_find(A.far_ptr, A.far_src, ga, (int32_t)gb);
                 if (k < 0) continue;
-                const T *K = coup + k * q2 * q2;
+                // coupling entries K[mu][nu] = G(x_mu, y_nu) kappa_mu kappa_nu from the node geometry
+                const double *na = A.nodes + (size_t)ga * q2 * 4, *nb = A.nodes + (size_t)gb * q2 * 4;
                 for (int nu = threadIdx.x; nu < q2; nu += blockDim.x) {
                     T s = zero<T>();
-                    for (int mu = 0; mu < q2; ++mu) s += K[(int64_t)nu * q2 + mu] * mv[ca * q2 + mu];
-                    acc += s * mv[cb * q2 + nu];
+                    const double *y = nb + 4 * nu;
+                    for (int mu = 0; mu < q2; ++mu) {
+                        const double *x = na + 4 * mu;
+                        double d0 = x[0] - y[0], d1 = x[1] - y[1], d2 = x[2] - y[2];
+                        s += green<T>(sqrt(d0 * d0 + d1 * d1 + d2 * d2), A.kappa) * (x[3] * mv[ca * q2 + mu]);
+                    }
+                    acc += s * (y[3] * mv[cb * q2 + nu]);
                 }
             }
         __syncthreads();
@@ -1087,10 +1187,12 @@ template <class T, int P, int PG>
 static igb_status launch_singular_pg(igb_operator *op, const PairRec *d_pairs, int64_t n)
 {
     constexpr int NLOC = (P + 1) * (P + 1), NPAD = 16 * ((NLOC + 15) / 16), NC = NComp<T>::value;
-    constexpr int STAGE_BYTES = 64 * (NC + 1) * NPAD * 8;
-    constexpr int WAVES = STAGE_BYTES * 4 <= 64 * 1024 ? 4 : (STAGE_BYTES * 2 <= 96 * 1024 ? 2 : 1);
-    constexpr int TS = (PG + 1) * (PG + 1) * 4;
-    size_t shm = (size_t)(2 * TS + 128) * sizeof(double) + (size_t)WAVES * STAGE_BYTES;
+    constexpr int STAGE_BYTES = 32 * (NC + 1) * NPAD * 8;
+    constexpr int WAVES = 4;
+    // the final reduction reuses the stage: it needs WAVES * NC * NPAD^2 doubles
+    constexpr size_t RED_BYTES = (size_t)WAVES * NC * NPAD * NPAD * 8;
+    size_t stage = std::max<size_t>((size_t)WAVES * STAGE_BYTES, RED_BYTES);
+    size_t shm = (size_t)128 * sizeof(double) + stage;
     if (shm > 160 * 1024) return fail(IGB_EUNSUPPORTED, "touching-pair quadrature: LDS too small for this degree");
     (void)hipFuncSetAttribute((const void *)k_near_singular<T, P, PG, WAVES>, hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)shm);
@@ -1181,8 +1283,14 @@ static igb_status matvec_internal(igb_operator *op, const T *xs, T *ys, hipEvent
     if ((rc = mark(2))) return rc;
     if (has_far) {
         int64_t row0 = s.cl_off[op->lmin], nrows = s.cl_off[s.L + 1] - row0;
-        hipLaunchKernelGGL((k_bsr_gemv<T, 1>), dim3((unsigned)nrows), dim3(256), 4 * q2 * sizeof(T), op->st, q2, op->far_ptr,
-                           op->far_src, (const T *)op->coup, (const T *)Xh, Yh, row0);
+        if (s.mode == IGB_H2_ONTHEFLY) {
+            size_t shm = (size_t)4 * q2 * (3 + NComp<T>::value) * sizeof(double) + (size_t)4 * q2 * sizeof(T);
+            hipLaunchKernelGGL((k_far_onthefly<T>), dim3((unsigned)nrows), dim3(256), shm, op->st, q2, op->far_ptr,
+                               op->far_src, op->nodes, (const T *)Xh, s.kappa, Yh, row0);
+        } else {
+            hipLaunchKernelGGL((k_bsr_gemv<T, 1>), dim3((unsigned)nrows), dim3(256), 4 * q2 * sizeof(T), op->st, q2,
+                               op->far_ptr, op->far_src, (const T *)op->coup, (const T *)Xh, Yh, row0);
+        }
         LAUNCHCHK();
     }
     if ((rc = mark(3))) return rc;
@@ -1300,8 +1408,9 @@ static igb_status assemble(igb_operator *op)
     hipLaunchKernelGGL(k_cluster_nodes, dim3(nblk(ncl_all * q2, 256)), dim3(256), 0, op->st, ncl_all, s.L, op->cl_off,
                        s.q, s.m, s.ne, op->zdev, s.tile_stride, op->tiles, op->tdeg, op->nodes);
     LAUNCHCHK();
+    if (s.mode != IGB_H2_STORED) op->coup_bytes = 0;
     if ((rc = dalloc(op, &op->coup, op->coup_bytes))) return rc;
-    if (nfar > 0) {
+    if (nfar > 0 && s.mode == IGB_H2_STORED) {
         hipLaunchKernelGGL((k_coupling<T>), dim3((unsigned)nfar), dim3(256), 0, op->st, nfar, op->far_tgt, op->far_src, q2,
                            op->nodes, s.kappa, (T *)op->coup);
         LAUNCHCHK();
@@ -1322,6 +1431,8 @@ static igb_status assemble(igb_operator *op)
         A.near_src = op->near_src;
         A.far_ptr = op->far_ptr;
         A.far_src = op->far_src;
+        A.nodes = op->nodes;
+        A.kappa = s.kappa;
         size_t shm = (size_t)(s.p + 2) * (s.p + 2) * q2 * sizeof(double);
         if (shm > 150 * 1024) return fail(IGB_EUNSUPPORTED, "Jacobi diagonal: (p+2)^2 q^2 too large");
         (void)hipFuncSetAttribute((const void *)k_diag<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
@@ -1886,7 +1997,31 @@ igb_status igb_export_coupling_block(const igb_operator *op, int32_t level, int3
     size_t nb = (size_t)q2 * q2;
     std::vector<unsigned char> buf(nb * op->esz);
     HIPCHK(hipStreamSynchronize(op->st));
-    HIPCHK(hipMemcpy(buf.data(), (const char *)op->coup + k * nb * op->esz, nb * op->esz, hipMemcpyDeviceToHost));
+    if (s.mode == IGB_H2_STORED) {
+        HIPCHK(hipMemcpy(buf.data(), (const char *)op->coup + k * nb * op->esz, nb * op->esz, hipMemcpyDeviceToHost));
+    } else {
+        // generate this one block with the coupling kernel
+        int32_t hp[2] = {(int32_t)row, key};
+        int32_t *dp = nullptr;
+        void *db = nullptr;
+        HIPCHK(hipMalloc((void **)&dp, sizeof hp));
+        hipError_t e = hipMalloc(&db, nb * op->esz);
+        if (e == hipSuccess) e = hipMemcpy(dp, hp, sizeof hp, hipMemcpyHostToDevice);
+        if (e == hipSuccess) {
+            if (op->cplx)
+                hipLaunchKernelGGL((k_coupling<cd>), dim3(1), dim3(256), 0, op->st, (int64_t)1, dp, dp + 1, q2, op->nodes,
+                                   s.kappa, (cd *)db);
+            else
+                hipLaunchKernelGGL((k_coupling<double>), dim3(1), dim3(256), 0, op->st, (int64_t)1, dp, dp + 1, q2,
+                                   op->nodes, s.kappa, (double *)db);
+            e = hipGetLastError();
+        }
+        if (e == hipSuccess) e = hipStreamSynchronize(op->st);
+        if (e == hipSuccess) e = hipMemcpy(buf.data(), db, nb * op->esz, hipMemcpyDeviceToHost);
+        (void)hipFree(dp);
+        (void)hipFree(db);
+        if (e != hipSuccess) return fail(IGB_EHIP, std::string("coupling block export: ") + hipGetErrorString(e));
+    }
     int nc = op->cplx ? 2 : 1;
     const double *B = (const double *)buf.data();
     for (int mu = 0; mu < q2; ++mu)
@@ -1919,8 +2054,11 @@ static void fill_info(const Setup &s, size_t esz, igb_info *out)
     for (int c = 0; c < 4; ++c) out->n_pairs[c] = s.npairs_class[c];
     int64_t q2 = (int64_t)s.q * s.q, ncl = s.cl_off[s.L + 1];
     out->near_bytes = out->n_near_blocks * s.nl * s.nl * (int64_t)esz;
-    out->coupling_bytes = out->n_far_blocks * q2 * q2 * (int64_t)esz;
-    out->matvec_bytes = out->near_bytes + out->coupling_bytes + (int64_t)esz * (3 * s.nsup + 4 * q2 * ncl);
+    out->coupling_bytes = s.mode == IGB_H2_STORED ? out->n_far_blocks * q2 * q2 * (int64_t)esz : 0;
+    // one superspace matvec moves every stored block once, the S* vector in and
+    // out, the moment vectors of all clusters, and (on the fly) the node data
+    out->matvec_bytes = out->near_bytes + out->coupling_bytes + (int64_t)esz * (3 * s.nsup + 4 * q2 * ncl) +
+                        (s.mode == IGB_H2_ONTHEFLY ? (int64_t)32 * q2 * ncl : 0);
     out->setup_seconds = s.setup_seconds;
 }
 

@@ -627,7 +627,8 @@ std::string build_setup(const Geometry &geo, const igb_params &prm, Setup &s)
     if (prm.gauss_regular < 1 || prm.gauss_regular > 36) return "gauss_regular outside 1..36";
     if (prm.gauss_singular != -1 && (prm.gauss_singular < 1 || prm.gauss_singular > 40)) return "gauss_singular outside 1..40";
     if (prm.gauss_rhs != -1 && (prm.gauss_rhs < 1 || prm.gauss_rhs > 40)) return "gauss_rhs outside 1..40";
-    if (prm.mode != IGB_DENSE && prm.mode != IGB_H2_STORED) return "mode must be IGB_DENSE or IGB_H2_STORED";
+    if (prm.mode != IGB_DENSE && prm.mode != IGB_H2_STORED && prm.mode != IGB_H2_ONTHEFLY)
+        return "mode must be IGB_DENSE, IGB_H2_STORED or IGB_H2_ONTHEFLY";
     if (prm.far_precision != IGB_FP64) return "far_precision must be IGB_FP64";
     if (prm.leaf_depth < -1 || prm.leaf_depth > 10) return "leaf_depth outside -1..10";
 

@@ -26,6 +26,7 @@ IGB_LAPLACE = 0
 IGB_HELMHOLTZ = 1
 IGB_DENSE = 0
 IGB_H2_STORED = 1
+IGB_H2_ONTHEFLY = 2
 IGB_FP64 = 0
 
 EXPORTED = [

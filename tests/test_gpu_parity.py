@@ -34,10 +34,11 @@ def rel(a, b):
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
 
 
-def make(patches, dense=False, **kw):
+def make(patches, dense=False, mode=None, **kw):
     """(gpu operator, oracle problem) with identical parameters."""
     g = igb.Geometry(patches)
-    mode = igb.IGB_DENSE if dense else igb.IGB_H2_STORED
+    if mode is None:
+        mode = igb.IGB_DENSE if dense else igb.IGB_H2_STORED
     op = igb.Operator(g, mode=mode, device=DEV, **kw)
     okw = {k: v for k, v in kw.items() if k in ("p", "m", "q", "eta", "leaf_depth", "gauss_regular", "gauss_singular",
                                                  "gauss_rhs")}
@@ -180,11 +181,12 @@ H2_CASES = {
 }
 
 
+@pytest.mark.parametrize("mode", ["stored", "onthefly"])
 @pytest.mark.parametrize("case", list(H2_CASES))
-def test_h2_superspace_matvec(case):
+def test_h2_superspace_matvec(case, mode):
     geo, kw = H2_CASES[case]
-    say(f"h2 {case}: assemble")
-    op, P = make(geo(), **kw)
+    say(f"h2 {case} {mode}: assemble")
+    op, P = make(geo(), mode=igb.IGB_H2_STORED if mode == "stored" else igb.IGB_H2_ONTHEFLY, **kw)
     assert op.info.n_far_blocks > 0
     P.h2_assemble(store_coupling=True)
     xs = rand(P.nsup, 6)
@@ -240,10 +242,11 @@ def test_helmholtz_dense_sphere():
     assert rel(to_np(op.jacobi_diag()), P.jacobi_diag(dense=True)) < 1e-12
 
 
-def test_helmholtz_h2_torus():
-    say("helmholtz h2 torus k=2 p=1 m=2 q=4")
-    op, P = make(W.torus_patches(), kernel=igb.IGB_HELMHOLTZ, wavenumber=2.0, p=1, m=2, q=4, leaf_depth=1, eta=1.6,
-                 gauss_regular=6)
+@pytest.mark.parametrize("mode", ["stored", "onthefly"])
+def test_helmholtz_h2_torus(mode):
+    say(f"helmholtz h2 torus k=2 p=1 m=2 q=4 {mode}")
+    op, P = make(W.torus_patches(), mode=igb.IGB_H2_STORED if mode == "stored" else igb.IGB_H2_ONTHEFLY,
+                 kernel=igb.IGB_HELMHOLTZ, wavenumber=2.0, p=1, m=2, q=4, leaf_depth=1, eta=1.6, gauss_regular=6)
     assert op.info.n_far_blocks > 0
     P.h2_assemble(store_coupling=True)
     xs = rand(P.nsup, 9, cplx=True)
@@ -254,10 +257,12 @@ def test_helmholtz_h2_torus():
 # ---------------------------------------------------------------------------
 # full size (the benchmark workload): sphere p=3, 32x32 elements per patch, q=8, eta=1.6
 # ---------------------------------------------------------------------------
-def test_full_size_sampled_rows():
-    say("full size sphere p=3 m=5 q=8: assemble")
+@pytest.mark.parametrize("mode", ["stored", "onthefly"])
+def test_full_size_sampled_rows(mode):
+    say(f"full size sphere p=3 m=5 q=8 {mode}: assemble")
     cfg = W.config_sphere_h2()
-    op, P = make(cfg["patches"], p=3, m=5, q=8, eta=1.6, gauss_regular=6)
+    op, P = make(cfg["patches"], mode=igb.IGB_H2_STORED if mode == "stored" else igb.IGB_H2_ONTHEFLY,
+                 p=3, m=5, q=8, eta=1.6, gauss_regular=6)
     xs = rand(P.nsup, 10)
     say("full size: matvec")
     ys = to_np(op.matvec_super(torch.tensor(xs)))

@@ -181,7 +181,7 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 template <class T, int P, int PG, int WAVES>
 __global__ void __launch_bounds__(64 * WAVES, NComp<T>::value == 1 ? 3 : 1) k_near_singular(
     const PairRec *__restrict__ pairs, int gs, const double *__restrict__ gxs, const double *__restrict__ gws,
-    const double *__restrict__ tiles, double kappa, int nl, T *__restrict__ blocks)
+    const double *__restrict__ tiles, double kappa, T *__restrict__ pairbuf)
 {
     constexpr int P1 = P + 1, NLOC = P1 * P1, NT = (NLOC + 15) / 16, NPAD = 16 * NT;
     constexpr int NC = NComp<T>::value;
@@ -331,8 +331,7 @@ __global__ void __launch_bounds__(64 * WAVES, NComp<T>::value == 1 ? 3 : 1) k_ne
                         acc[0][c2][ta][tb][e] + acc[1][c2][ta][tb][e];
                 }
     __syncthreads();
-    T *out1 = blocks + (int64_t)R.blk1 * nl * nl;
-    T *out2 = R.blk2 >= 0 ? blocks + (int64_t)R.blk2 * nl * nl : nullptr;
+    T *out = pairbuf + (int64_t)blockIdx.x * NLOC * NLOC;
     for (int o = threadIdx.x; o < NLOC * NLOC; o += blockDim.x) {
         int a = o / NLOC, b = o % NLOC;
         double sre = 0.0, sim = 0.0, tre = 0.0, tim = 0.0;
@@ -351,8 +350,25 @@ __global__ void __launch_bounds__(64 * WAVES, NComp<T>::value == 1 ? 3 : 1) k_ne
         T s;
         if constexpr (NC == 2) s = T{sre, sim};
         else s = sre;
-        out1[blk_pos(nl, NLOC, R.elE, a, R.elF, b)] = s;
-        if (out2) out2[blk_pos(nl, NLOC, R.elF, b, R.elE, a)] = s;
+        out[o] = s;
+    }
+}
+
+// Places staged touching-pair blocks (row-major nloc x nloc per pair, in the
+// order of `pairs`) into the near-field leaf blocks and their mirrors.
+template <class T>
+__global__ void k_scatter_pairs(const PairRec *__restrict__ pairs, int nloc, int nl, const T *__restrict__ pairbuf,
+                                T *__restrict__ blocks)
+{
+    const PairRec R = pairs[blockIdx.x];
+    const T *in = pairbuf + (int64_t)blockIdx.x * nloc * nloc;
+    T *out1 = blocks + (int64_t)R.blk1 * nl * nl;
+    T *out2 = R.blk2 >= 0 ? blocks + (int64_t)R.blk2 * nl * nl : nullptr;
+    for (int o = threadIdx.x; o < nloc * nloc; o += blockDim.x) {
+        int a = o / nloc, b = o % nloc;
+        T v = in[o];
+        out1[blk_pos(nl, nloc, R.elE, a, R.elF, b)] = v;
+        if (out2) out2[blk_pos(nl, nloc, R.elF, b, R.elE, a)] = v;
     }
 }
 
@@ -1135,6 +1151,10 @@ struct igb_operator {
     void *mpart = nullptr;     // GMRES multi-dot partial sums
     void *potc = nullptr;      // potential: weighted density at the quadrature points
     void *tz = nullptr;        // intermediate of the separable T application
+    void *pairbuf = nullptr;   // staged touching-pair blocks (nloc^2 per pair)
+    PairRec *d_touch = nullptr;
+    int64_t ntouch = 0;
+    std::vector<PairRec> touch;  // host copy of the staged touching pairs
     int64_t near_bytes = 0, coup_bytes = 0;
     double assembly_seconds = 0.0;
     std::vector<void *> owned;
@@ -1201,7 +1221,7 @@ static igb_status launch_singular_pg(igb_operator *op, const PairRec *d_pairs, i
         int64_t cnt = std::min<int64_t>(n - off, 1 << 20);
         hipLaunchKernelGGL((k_near_singular<T, P, PG, WAVES>), dim3((unsigned)cnt), dim3(64 * WAVES), shm, op->st,
                            d_pairs + off, gs, op->gx + op->s.goff[gs], op->gw + op->s.goff[gs], op->tiles, op->s.kappa,
-                           op->s.nl, (T *)op->nearb);
+                           (T *)op->pairbuf + off * NLOC * NLOC);
         LAUNCHCHK();
     }
     return IGB_OK;
@@ -1358,13 +1378,14 @@ static igb_status dot_dev(igb_operator *op, int64_t n, const T *a, const T *b, T
     return IGB_OK;
 }
 
+// Assembly, first part (needs only the element geometry): Gauss-node geometry
+// and the touching-pair quadrature into a staging buffer.  Runs on the GPU
+// while the host builds the cluster tree and the block partition.
 template <class T>
-static igb_status assemble(igb_operator *op)
+static igb_status assemble_touching(igb_operator *op)
 {
     Setup &s = op->s;
     igb_status rc;
-    int q2 = s.q * s.q;
-    // geometry at the three regular Gauss orders and at the rhs/potential order
     int ords[3] = {s.g0, std::min(40, s.g0 + 2), std::min(40, s.g0 + 4)};
     for (int k = 0; k < 3; ++k) {
         op->gord[k] = ords[k];
@@ -1381,23 +1402,56 @@ static igb_status assemble(igb_operator *op)
                            s.tile_stride, op->tiles, op->tdeg, g, op->gx + s.goff[g], op->gw + s.goff[g], op->rpts);
         LAUNCHCHK();
     }
+    std::vector<PairRec> &touch = op->touch;
+    std::string err = enumerate_touching(s, touch);
+    if (!err.empty()) return fail(IGB_EINVAL, err);
+    op->ntouch = (int64_t)touch.size();
+    if ((rc = upload(op, &op->d_touch, touch.data(), touch.size() * sizeof(PairRec)))) return rc;
+    if ((rc = dalloc(op, &op->pairbuf, (size_t)op->ntouch * s.nloc * s.nloc * sizeof(T)))) return rc;
+    if (op->ntouch > 0) return launch_singular<T>(op, op->d_touch, op->ntouch);
+    return IGB_OK;
+}
+
+// Assembly, second part (needs the plan): near-field blocks (regular pairs by
+// quadrature, touching pairs scattered from the staging buffer), cluster-node
+// geometry, stored coupling blocks, Jacobi diagonal.
+template <class T>
+static igb_status assemble(igb_operator *op)
+{
+    Setup &s = op->s;
+    igb_status rc;
+    int q2 = s.q * s.q;
+    const int *ords = op->gord;
+    // the touching pairs of the plan must be exactly the ones quadrature already ran on
+    std::string terr = check_touching(s, op->touch);
+    if (!terr.empty()) return fail(IGB_EINVAL, terr);
+    std::vector<PairRec> touch;
+    touch.reserve(op->ntouch);
+    for (const PairRec &R : s.pairs)
+        if (R.cls != kRegular) touch.push_back(R);
     // near-field blocks
     op->near_bytes = (int64_t)s.near_src.size() * s.nl * s.nl * (int64_t)sizeof(T);
     if ((rc = dalloc(op, &op->nearb, op->near_bytes))) return rc;
     HIPCHK(hipMemsetAsync(op->nearb, 0, op->near_bytes, op->st));
     {
-        std::vector<PairRec> lists[6];
-        for (const PairRec &R : s.pairs) {
+        std::vector<PairRec> lists[3];
+        for (const PairRec &R : s.pairs)
             if (R.cls == kRegular) lists[R.order == ords[0] ? 0 : (R.order == ords[1] ? 1 : 2)].push_back(R);
-            else lists[3 + R.cls - 1].push_back(R);
-        }
-        for (int k = 0; k < 6; ++k) {
+        for (int k = 0; k < 3; ++k) {
             if (lists[k].empty()) continue;
             PairRec *d = nullptr;
             if ((rc = upload(op, &d, lists[k].data(), lists[k].size() * sizeof(PairRec)))) return rc;
-            if (k < 3) rc = launch_regular<T>(op, d, (int64_t)lists[k].size(), ords[k], op->gpts[k]);
-            else rc = launch_singular<T>(op, d, (int64_t)lists[k].size());
-            if (rc) return rc;
+            if ((rc = launch_regular<T>(op, d, (int64_t)lists[k].size(), ords[k], op->gpts[k]))) return rc;
+        }
+        if (!touch.empty()) {
+            PairRec *d = nullptr;
+            if ((rc = upload(op, &d, touch.data(), touch.size() * sizeof(PairRec)))) return rc;
+            for (int64_t off = 0; off < (int64_t)touch.size(); off += 1 << 20) {
+                int64_t cnt = std::min<int64_t>((int64_t)touch.size() - off, 1 << 20);
+                hipLaunchKernelGGL((k_scatter_pairs<T>), dim3((unsigned)cnt), dim3(256), 0, op->st, d + off, s.nloc, s.nl,
+                                   (const T *)op->pairbuf + off * s.nloc * s.nloc, (T *)op->nearb);
+                LAUNCHCHK();
+            }
         }
     }
     // far field: Chebyshev-node geometry of every cluster, coupling blocks
@@ -1443,7 +1497,7 @@ static igb_status assemble(igb_operator *op)
     return IGB_OK;
 }
 
-static igb_status create_device(igb_operator *op)
+static igb_status create_device_geometry(igb_operator *op)
 {
     Setup &s = op->s;
     igb_status rc;
@@ -1472,16 +1526,6 @@ static igb_status create_device(igb_operator *op)
     if ((rc = upload(op, &op->Mlev, s.Mlev.data(), s.Mlev.size() * sizeof(double)))) return rc;
     if ((rc = upload(op, &op->Mlev_off, s.Mlev_off.data(), s.Mlev_off.size() * sizeof(int64_t)))) return rc;
     if ((rc = upload(op, &op->Tb, s.Tb.data(), s.Tb.size() * sizeof(double)))) return rc;
-    if ((rc = upload(op, &op->near_ptr, s.near_ptr.data(), s.near_ptr.size() * sizeof(int64_t)))) return rc;
-    if ((rc = upload(op, &op->near_src, s.near_src.data(), s.near_src.size() * sizeof(int32_t)))) return rc;
-    if ((rc = upload(op, &op->far_ptr, s.far_ptr.data(), s.far_ptr.size() * sizeof(int64_t)))) return rc;
-    if ((rc = upload(op, &op->far_src, s.far_src.data(), s.far_src.size() * sizeof(int32_t)))) return rc;
-    {
-        std::vector<int32_t> tg(s.far_src.size());
-        for (int64_t c = 0; c + 1 < (int64_t)s.far_ptr.size(); ++c)
-            for (int64_t k = s.far_ptr[c]; k < s.far_ptr[c + 1]; ++k) tg[k] = (int32_t)c;
-        if ((rc = upload(op, &op->far_tgt, tg.data(), tg.size() * sizeof(int32_t)))) return rc;
-    }
     int64_t ncl_all = s.cl_off[s.L + 1];
     if ((rc = dalloc(op, &op->xs, s.nsup * esz))) return rc;
     if ((rc = dalloc(op, &op->ys, s.nsup * esz))) return rc;
@@ -1496,6 +1540,23 @@ static igb_status create_device(igb_operator *op)
     if ((rc = dalloc(op, (void **)&op->scal, 16 * sizeof(double)))) return rc;
     HIPCHK(hipHostMalloc((void **)&op->h_scal, 16 * sizeof(double), hipHostMallocDefault));
     if ((rc = dalloc(op, &op->potc, (size_t)s.nelem * s.grhs * s.grhs * esz))) return rc;
+    return op->cplx ? assemble_touching<cd>(op) : assemble_touching<double>(op);
+}
+
+static igb_status create_device_plan(igb_operator *op)
+{
+    Setup &s = op->s;
+    igb_status rc;
+    if ((rc = upload(op, &op->near_ptr, s.near_ptr.data(), s.near_ptr.size() * sizeof(int64_t)))) return rc;
+    if ((rc = upload(op, &op->near_src, s.near_src.data(), s.near_src.size() * sizeof(int32_t)))) return rc;
+    if ((rc = upload(op, &op->far_ptr, s.far_ptr.data(), s.far_ptr.size() * sizeof(int64_t)))) return rc;
+    if ((rc = upload(op, &op->far_src, s.far_src.data(), s.far_src.size() * sizeof(int32_t)))) return rc;
+    {
+        std::vector<int32_t> tg(s.far_src.size());
+        for (int64_t c = 0; c + 1 < (int64_t)s.far_ptr.size(); ++c)
+            for (int64_t k = s.far_ptr[c]; k < s.far_ptr[c + 1]; ++k) tg[k] = (int32_t)c;
+        if ((rc = upload(op, &op->far_tgt, tg.data(), tg.size() * sizeof(int32_t)))) return rc;
+    }
     return op->cplx ? assemble<cd>(op) : assemble<double>(op);
 }
 
@@ -1731,7 +1792,7 @@ igb_status igb_operator_create(const igb_geometry *geo, const igb_params *prm, v
     op->st = (hipStream_t)hip_stream;
     std::string err;
     try {
-        err = build_setup(geo->g, *prm, op->s);
+        err = build_setup_geometry(geo->g, *prm, op->s);
     } catch (const std::bad_alloc &) {
         delete op;
         return fail(IGB_ENOMEM, "host allocation failed during setup");
@@ -1744,9 +1805,21 @@ igb_status igb_operator_create(const igb_geometry *geo, const igb_params *prm, v
     op->cplx = s.kernel == IGB_HELMHOLTZ;
     op->esz = op->cplx ? sizeof(cd) : sizeof(double);
     op->lo = Layout{s.p, s.p + 1, s.nloc, s.nl, s.side, s.L, s.ne, s.ns1};
-    op->lmin = s.L + 1;
-    for (size_t k = 0; k < s.far.size(); k += 3) op->lmin = std::min(op->lmin, (int)s.far[k]);
-    igb_status rc = create_device(op);
+    // GPU: geometry and touching-pair quadrature; host meanwhile: tree, partition, pair lists
+    igb_status rc = create_device_geometry(op);
+    if (rc == IGB_OK) {
+        try {
+            err = build_setup_plan(s);
+        } catch (const std::bad_alloc &) {
+            err = "host allocation failed during setup";
+        }
+        if (!err.empty()) rc = fail(IGB_EINVAL, err);
+    }
+    if (rc == IGB_OK) {
+        op->lmin = s.L + 1;
+        for (size_t k = 0; k < s.far.size(); k += 3) op->lmin = std::min(op->lmin, (int)s.far[k]);
+        rc = create_device_plan(op);
+    }
     if (rc == IGB_OK) {
         hipError_t e = hipStreamSynchronize(op->st);
         if (e != hipSuccess) rc = fail(IGB_EHIP, std::string("assembly: ") + hipGetErrorString(e));

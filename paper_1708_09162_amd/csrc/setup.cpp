@@ -10,6 +10,7 @@
 #include <cstring>
 #include <numeric>
 #include <thread>
+#include <unordered_map>
 
 namespace igb {
 
@@ -452,21 +453,123 @@ static int other_adjacent(int o, int a)
     return a == n1 ? n2 : n1;
 }
 
+// element corners (physical), 3x3 grids and grid diameters, used by the
+// touching test and the regular-pair order
+static void element_geometry(Setup &s)
+{
+    s.ecorner.assign((size_t)s.nelem * 12, 0.0);
+    s.egrid.assign((size_t)s.nelem * 27, 0.0);
+    s.ediam.assign(s.nelem, 0.0);
+    parallel_chunks(s.nelem, 1 << 30, [&](int64_t eb, int64_t ee, int) {
+        for (int E = (int)eb; E < (int)ee; ++E) {
+            for (int c = 0; c < 4; ++c) tile_eval(s, E, kCorner[c][0], kCorner[c][1], &s.ecorner[(size_t)E * 12 + 3 * c], nullptr);
+            for (int b = 0; b < 3; ++b)
+                for (int a = 0; a < 3; ++a) tile_eval(s, E, 0.5 * a, 0.5 * b, &s.egrid[(size_t)E * 27 + 3 * (3 * b + a)], nullptr);
+            double d = 0.0;
+            for (int i = 0; i < 9; ++i)
+                for (int j = i + 1; j < 9; ++j) d = std::max(d, dist(&s.egrid[(size_t)E * 27 + 3 * i], &s.egrid[(size_t)E * 27 + 3 * j]));
+            s.ediam[E] = d;
+        }
+    });
+}
+
+// Classification of one element pair E <= F (class, Gauss order, canonical frames).
+// Touching is decided physically: corners coincide within 1e-10 * max diam.
+static void classify_pair(const Setup &s, int E, int F, PairRec &R)
+{
+    R.E = E;
+    R.F = F;
+    R.oE = 0; R.aE = 1; R.bE = 3; R.oF = 0; R.aF = 1; R.bF = 3;
+    double md = std::max(s.ediam[E], s.ediam[F]);
+    if (E == F) {
+        R.cls = kIdentical;
+        R.order = s.gs;
+        return;
+    }
+    const double *cE = &s.ecorner[(size_t)E * 12], *cF = &s.ecorner[(size_t)F * 12];
+    double tol = 1e-10 * md;
+    int match[4], nsh = 0;
+    for (int c = 0; c < 4; ++c) {
+        match[c] = -1;
+        for (int dd = 0; dd < 4; ++dd)
+            if (dist(cE + 3 * c, cF + 3 * dd) <= tol) match[c] = dd;
+        if (match[c] >= 0) ++nsh;
+    }
+    if (nsh == 2) {
+        int i = -1, j = -1;
+        for (int c = 0; c < 4; ++c)
+            if (match[c] >= 0) { if (i < 0) i = c; else j = c; }
+        R.cls = kEdge;
+        R.order = s.gs;
+        R.oE = i; R.aE = j; R.bE = other_adjacent(i, j);
+        R.oF = match[i]; R.aF = match[j]; R.bF = other_adjacent(match[i], match[j]);
+        return;
+    }
+    if (nsh == 1) {
+        int i = 0;
+        for (int c = 0; c < 4; ++c)
+            if (match[c] >= 0) i = c;
+        R.cls = kVertex;
+        R.order = s.gs;
+        R.oE = i; R.aE = (i + 1) & 3; R.bE = (i + 3) & 3;
+        int kk = match[i];
+        R.oF = kk; R.aF = (kk + 1) & 3; R.bF = (kk + 3) & 3;
+        return;
+    }
+    const double *gE = &s.egrid[(size_t)E * 27], *gF = &s.egrid[(size_t)F * 27];
+    double dmin = 1e300;
+    for (int a = 0; a < 9; ++a)
+        for (int b = 0; b < 9; ++b) dmin = std::min(dmin, dist(gE + 3 * a, gF + 3 * b));
+    double r = dmin / md;
+    int g = s.g0;
+    if (r < 0.6) g = s.g0 + 4;
+    else if (r < 1.2) g = s.g0 + 2;
+    if (g > 40) g = 40;
+    R.cls = kRegular;
+    R.order = g;
+}
+
+std::string enumerate_touching(const Setup &s, std::vector<PairRec> &out)
+{
+    out.clear();
+    double dmin = 1e300, dmax = 0.0;
+    for (double d : s.ediam) { dmin = std::min(dmin, d); dmax = std::max(dmax, d); }
+    if (!(dmax > 0.0)) return "degenerate elements (zero diameter)";
+    double cell = (dmin > 0.0 ? dmin : dmax) * 0.25;
+    auto key = [&](const double *x, int dx, int dy, int dz) {
+        int64_t i = (int64_t)std::floor(x[0] / cell) + dx, j = (int64_t)std::floor(x[1] / cell) + dy,
+                k = (int64_t)std::floor(x[2] / cell) + dz;
+        return (i * 73856093) ^ (j * 19349663) ^ (k * 83492791);
+    };
+    std::unordered_map<int64_t, std::vector<int32_t>> buckets;
+    for (int E = 0; E < s.nelem; ++E)
+        for (int c = 0; c < 4; ++c) buckets[key(&s.ecorner[(size_t)E * 12 + 3 * c], 0, 0, 0)].push_back(E);
+    std::vector<int64_t> cand;
+    for (int E = 0; E < s.nelem; ++E) {
+        cand.push_back(((int64_t)E << 32) | (uint32_t)E);
+        for (int c = 0; c < 4; ++c)
+            for (int dx = -1; dx <= 1; ++dx)
+                for (int dy = -1; dy <= 1; ++dy)
+                    for (int dz = -1; dz <= 1; ++dz) {
+                        auto it = buckets.find(key(&s.ecorner[(size_t)E * 12 + 3 * c], dx, dy, dz));
+                        if (it == buckets.end()) continue;
+                        for (int32_t F : it->second)
+                            if (F > E) cand.push_back(((int64_t)E << 32) | (uint32_t)F);
+                    }
+    }
+    std::sort(cand.begin(), cand.end());
+    cand.erase(std::unique(cand.begin(), cand.end()), cand.end());
+    for (int64_t c : cand) {
+        PairRec R;
+        std::memset(&R, 0, sizeof R);
+        classify_pair(s, (int)(c >> 32), (int)(c & 0xffffffff), R);
+        if (R.cls != kRegular) out.push_back(R);
+    }
+    return "";
+}
+
 static std::string build_pairs(Setup &s)
 {
-    // element corners and 3x3 grids
-    std::vector<double> corner((size_t)s.nelem * 12), grid((size_t)s.nelem * 27), diam(s.nelem);
-    parallel_chunks(s.nelem, 1 << 30, [&](int64_t eb, int64_t ee, int) {
-    for (int E = (int)eb; E < (int)ee; ++E) {
-        for (int c = 0; c < 4; ++c) tile_eval(s, E, kCorner[c][0], kCorner[c][1], &corner[(size_t)E * 12 + 3 * c], nullptr);
-        for (int b = 0; b < 3; ++b)
-            for (int a = 0; a < 3; ++a) tile_eval(s, E, 0.5 * a, 0.5 * b, &grid[(size_t)E * 27 + 3 * (3 * b + a)], nullptr);
-        double d = 0.0;
-        for (int i = 0; i < 9; ++i)
-            for (int j = i + 1; j < 9; ++j) d = std::max(d, dist(&grid[(size_t)E * 27 + 3 * i], &grid[(size_t)E * 27 + 3 * j]));
-        diam[E] = d;
-    }
-    });
     auto leaf_of = [&](int E, int &el) {
         int pt = E / (s.ne * s.ne), r = E % (s.ne * s.ne), e2 = r / s.ne, e1 = r % s.ne;
         int nL = 1 << s.L;
@@ -487,78 +590,35 @@ static std::string build_pairs(Setup &s)
     std::vector<std::vector<PairRec>> part(nw);
     std::vector<int> bad(nw, 0);
     parallel_chunks(nnear, nw, [&](int64_t kb, int64_t ke, int w) {
-    std::vector<PairRec> &out = part[w];
-    for (int64_t k = kb; k < ke; ++k) {
-        int t = s.near[2 * k], src = s.near[2 * k + 1];
-        int pt = t / (nL * nL), rt = t % (nL * nL), t2 = rt / nL, t1 = rt % nL;
-        int ps = src / (nL * nL), rs = src % (nL * nL), s2 = rs / nL, s1 = rs % nL;
-        for (int a2 = 0; a2 < s.side; ++a2)
-            for (int a1 = 0; a1 < s.side; ++a1) {
-                int E = pt * s.ne * s.ne + (t2 * s.side + a2) * s.ne + t1 * s.side + a1;
-                for (int b2 = 0; b2 < s.side; ++b2)
-                    for (int b1 = 0; b1 < s.side; ++b1) {
-                        int F = ps * s.ne * s.ne + (s2 * s.side + b2) * s.ne + s1 * s.side + b1;
-                        if (F < E) continue;
-                        PairRec R;
-                        std::memset(&R, 0, sizeof R);
-                        R.E = E;
-                        R.F = F;
-                        int elE, elF;
-                        int lE = leaf_of(E, elE), lF = leaf_of(F, elF);
-                        R.elE = (int8_t)elE;
-                        R.elF = (int8_t)elF;
-                        R.blk1 = block_index(lE, lF);
-                        R.blk2 = (E == F) ? -1 : block_index(lF, lE);
-                        if (R.blk1 < 0 || (E != F && R.blk2 < 0)) { bad[w] = 1; continue; }
-                        R.oE = 0; R.aE = 1; R.bE = 3; R.oF = 0; R.aF = 1; R.bF = 3;
-                        double md = std::max(diam[E], diam[F]);
-                        if (E == F) {
-                            R.cls = kIdentical;
-                            R.order = s.gs;
-                        } else {
-                            double tol = 1e-10 * md;
-                            int match[4], nsh = 0;
-                            for (int c = 0; c < 4; ++c) {
-                                match[c] = -1;
-                                for (int dd = 0; dd < 4; ++dd)
-                                    if (dist(&corner[(size_t)E * 12 + 3 * c], &corner[(size_t)F * 12 + 3 * dd]) <= tol) match[c] = dd;
-                                if (match[c] >= 0) ++nsh;
+        std::vector<PairRec> &out = part[w];
+        for (int64_t k = kb; k < ke; ++k) {
+            int t = s.near[2 * k], src = s.near[2 * k + 1];
+            int pt = t / (nL * nL), rt = t % (nL * nL), t2 = rt / nL, t1 = rt % nL;
+            int ps = src / (nL * nL), rs = src % (nL * nL), s2 = rs / nL, s1 = rs % nL;
+            for (int a2 = 0; a2 < s.side; ++a2)
+                for (int a1 = 0; a1 < s.side; ++a1) {
+                    int E = pt * s.ne * s.ne + (t2 * s.side + a2) * s.ne + t1 * s.side + a1;
+                    for (int b2 = 0; b2 < s.side; ++b2)
+                        for (int b1 = 0; b1 < s.side; ++b1) {
+                            int F = ps * s.ne * s.ne + (s2 * s.side + b2) * s.ne + s1 * s.side + b1;
+                            if (F < E) continue;
+                            PairRec R;
+                            std::memset(&R, 0, sizeof R);
+                            classify_pair(s, E, F, R);
+                            int elE, elF;
+                            int lE = leaf_of(E, elE), lF = leaf_of(F, elF);
+                            R.elE = (int8_t)elE;
+                            R.elF = (int8_t)elF;
+                            R.blk1 = block_index(lE, lF);
+                            R.blk2 = (E == F) ? -1 : block_index(lF, lE);
+                            if (R.blk1 < 0 || (E != F && R.blk2 < 0)) {
+                                bad[w] = 1;
+                                continue;
                             }
-                            if (nsh == 2) {
-                                int i = -1, j = -1;
-                                for (int c = 0; c < 4; ++c)
-                                    if (match[c] >= 0) { if (i < 0) i = c; else j = c; }
-                                R.cls = kEdge;
-                                R.order = s.gs;
-                                R.oE = i; R.aE = j; R.bE = other_adjacent(i, j);
-                                R.oF = match[i]; R.aF = match[j]; R.bF = other_adjacent(match[i], match[j]);
-                            } else if (nsh == 1) {
-                                int i = 0;
-                                for (int c = 0; c < 4; ++c)
-                                    if (match[c] >= 0) i = c;
-                                R.cls = kVertex;
-                                R.order = s.gs;
-                                R.oE = i; R.aE = (i + 1) & 3; R.bE = (i + 3) & 3;
-                                int kk = match[i];
-                                R.oF = kk; R.aF = (kk + 1) & 3; R.bF = (kk + 3) & 3;
-                            } else {
-                                double dmin = 1e300;
-                                for (int a = 0; a < 9; ++a)
-                                    for (int b = 0; b < 9; ++b)
-                                        dmin = std::min(dmin, dist(&grid[(size_t)E * 27 + 3 * a], &grid[(size_t)F * 27 + 3 * b]));
-                                double r = dmin / md;
-                                int g = s.g0;
-                                if (r < 0.6) g = s.g0 + 4;
-                                else if (r < 1.2) g = s.g0 + 2;
-                                if (g > 40) g = 40;
-                                R.cls = kRegular;
-                                R.order = g;
-                            }
+                            out.push_back(R);
                         }
-                        out.push_back(R);
-                    }
-            }
-    }
+                }
+        }
     });
     for (int w = 0; w < nw; ++w) {
         if (bad[w]) return "near-field partition is not symmetric";
@@ -614,7 +674,7 @@ static void elevate_tile(const std::vector<double> &Hin, int pu, int pv, int PG,
 }
 
 // ---------------------------------------------------------------------------
-std::string build_setup(const Geometry &geo, const igb_params &prm, Setup &s)
+std::string build_setup_geometry(const Geometry &geo, const igb_params &prm, Setup &s)
 {
     auto t0 = std::chrono::steady_clock::now();
     if (prm.kernel != IGB_LAPLACE && prm.kernel != IGB_HELMHOLTZ) return "kernel must be IGB_LAPLACE or IGB_HELMHOLTZ";
@@ -769,11 +829,45 @@ std::string build_setup(const Geometry &geo, const igb_params &prm, Setup &s)
                         s.Mlev[s.Mlev_off[l] + (size_t)(el * (s.p + 1) + r) * s.q + mu] = mom(nsub, el, r, mu);
         }
     }
-    build_partition(s);
-    std::string perr = build_pairs(s);
-    if (!perr.empty()) return perr;
+    element_geometry(s);
     s.setup_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     return "";
+}
+
+std::string build_setup_plan(Setup &s)
+{
+    auto t0 = std::chrono::steady_clock::now();
+    build_partition(s);
+    std::string perr = build_pairs(s);
+    s.setup_seconds += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    return perr;
+}
+
+std::string check_touching(const Setup &s, const std::vector<PairRec> &touch)
+{
+    size_t k = 0;
+    for (const PairRec &R : s.pairs) {
+        if (R.cls == kRegular) continue;
+        if (k >= touch.size()) return "touching pairs outside the enumerated set";
+        const PairRec &T = touch[k++];
+        if (T.E != R.E || T.F != R.F || T.cls != R.cls || T.order != R.order || T.oE != R.oE || T.aE != R.aE ||
+            T.bE != R.bE || T.oF != R.oF || T.aF != R.aF || T.bF != R.bF)
+            return "touching pair enumeration differs from the near-field pairs";
+    }
+    if (k != touch.size()) return "enumerated touching pairs missing from the near field";
+    return "";
+}
+
+std::string build_setup(const Geometry &geo, const igb_params &prm, Setup &s)
+{
+    std::string err = build_setup_geometry(geo, prm, s);
+    if (!err.empty()) return err;
+    std::vector<PairRec> touch;
+    err = enumerate_touching(s, touch);
+    if (!err.empty()) return err;
+    err = build_setup_plan(s);
+    if (!err.empty()) return err;
+    return check_touching(s, touch);
 }
 
 }  // namespace igb

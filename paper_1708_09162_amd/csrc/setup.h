@@ -71,6 +71,8 @@ struct Setup {
     std::vector<int32_t> near_src;
     std::vector<int64_t> far_ptr;    // CSR over global clusters
     std::vector<int32_t> far_src;    // global cluster index of sources
+    // element corners (4 x 3), 3x3 grids (9 x 3) and grid diameters
+    std::vector<double> ecorner, egrid, ediam;
     // near-field element pairs
     std::vector<PairRec> pairs;
     int64_t npairs_class[4] = {0, 0, 0, 0};
@@ -84,7 +86,18 @@ struct Setup {
 std::string make_geometry(int32_t n, const igb_nurbs_patch *in, Geometry &out);
 
 // Build everything host-side for the given parameters; returns "" or an error message.
+// build_setup = build_setup_geometry (parameters, element tiles, tables, element
+// corners) followed by build_setup_plan (cluster tree, partition, near-field pairs).
 std::string build_setup(const Geometry &g, const igb_params &prm, Setup &s);
+std::string build_setup_geometry(const Geometry &g, const igb_params &prm, Setup &s);
+std::string build_setup_plan(Setup &s);
+
+// Touching element pairs (identical, common edge, common vertex; E <= F, sorted)
+// from physical corner coincidence alone, without the partition.  Every touching
+// pair lies in the near field, so this list equals the touching part of the plan.
+std::string enumerate_touching(const Setup &s, std::vector<PairRec> &out);
+// "" if the touching pairs of the plan are exactly `touch` (same order, class, frames).
+std::string check_touching(const Setup &s, const std::vector<PairRec> &touch);
 
 // Host evaluation of an element tile: point and surface measure w.r.t. element-local coordinates.
 void tile_eval(const Setup &s, int E, double u, double v, double X[3], double *kap_local);

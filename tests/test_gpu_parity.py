@@ -284,3 +284,33 @@ def test_full_size_sampled_rows(mode):
     zs = rand(P.nsup, 12)
     yz = to_np(op.matvec_super(torch.tensor(zs)))
     assert abs(zs @ ys - xs @ yz) <= 1e-12 * abs(zs @ ys)
+
+
+def test_full_size_helmholtz_torus_sampled_rows():
+    """Helmholtz on the 16-patch torus, kappa=8, p=2, 64x64 elements per patch, q=10 (on-the-fly far
+    field): GPU superspace product against the oracle's row-sampled product on random target leaves."""
+    say("full size helmholtz torus p=2 m=6 q=10 k=8 onthefly: assemble")
+    cfg = W.config_torus_helmholtz()
+    op, P = make(cfg["patches"], mode=igb.IGB_H2_ONTHEFLY, kernel=igb.IGB_HELMHOLTZ, wavenumber=cfg["wavenumber"],
+                 p=2, m=6, q=10, eta=1.6, gauss_regular=6)
+    assert op.info.n_dof == 69696 and op.info.n_dof_super == 589824
+    xs = rand(P.nsup, 13, cplx=True)
+    say("full size helmholtz: matvec")
+    ys = to_np(op.matvec_super(torch.tensor(xs)))
+    del op
+    torch.cuda.empty_cache()
+    rng = np.random.default_rng(14)
+    nleaf = 16 * 16 * 16
+    leaves = np.sort(rng.choice(nleaf, 3, replace=False)).astype(np.int32)
+    say(f"full size helmholtz: oracle rows for leaves {leaves.tolist()}")
+    rows = P.h2_matvec_rows(xs, leaves)
+    ne, side, n, nloc = 64, 4, 16, 9
+    got = []
+    for li, leaf in enumerate(leaves):
+        pt, r = divmod(int(leaf), n * n)
+        k2, k1 = divmod(r, n)
+        for a2 in range(side):
+            for a1 in range(side):
+                E = pt * ne * ne + (k2 * side + a2) * ne + k1 * side + a1
+                got.append(ys[E * nloc:(E + 1) * nloc])
+    assert rel(np.concatenate(got), rows.reshape(-1)) < 1e-12

@@ -179,9 +179,11 @@ igb_status igb_potential(const igb_operator *op, const void *w_dev, int64_t n_pt
  * operator's internal work vectors with HIP events recorded on its stream
  * between stages and writes the mean milliseconds per stage to
  * stage_ms_host[IGB_NUM_MATVEC_STAGES]: 0 leaf moments, 1 upward transfers,
- * 2 coupling block GEMV, 3 downward transfers, 4 near-field block GEMV,
- * 5 leaf back-moments (Sec. 4.2).  Synchronous. */
-#define IGB_NUM_MATVEC_STAGES 6
+ * 2 coupling blocks (stored GEMV, or generated on the fly), 3 gather of the
+ * coupling partial rows (on the fly with q^2 <= 64: each pair of mirrored
+ * blocks is evaluated once; 0 otherwise), 4 downward transfers, 5 near-field
+ * block GEMV, 6 leaf back-moments (Sec. 4.2).  Synchronous. */
+#define IGB_NUM_MATVEC_STAGES 7
 igb_status igb_matvec_profile(const igb_operator *op, int32_t reps, double *stage_ms_host);
 
 /* Host-only planning: the cluster tree, block partition (Sec. 4.1, Sec. 4.2

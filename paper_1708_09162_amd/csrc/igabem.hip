@@ -201,11 +201,13 @@ __global__ void __launch_bounds__(64 * WAVES, NComp<T>::value == 1 ? 3 : 1) k_ne
         nx[k] = gxs[k];
         nw[k] = gws[k];
     }
-    for (int k = lane; k < HALF * (NPAD - NLOC); k += 64) {
-        int pt = k / (NPAD - NLOC), a = NLOC + k % (NPAD - NLOC);
+    if constexpr (NPAD > NLOC) {
+        for (int k = lane; k < HALF * (NPAD - NLOC); k += 64) {
+            int pt = k / (NPAD - NLOC), a = NLOC + k % (NPAD - NLOC);
 #pragma unroll
-        for (int c = 0; c < NC; ++c) Ub[c * HALF * NPAD + pt * NPAD + a] = 0.0;
-        Vb[pt * NPAD + a] = 0.0;
+            for (int c = 0; c < NC; ++c) Ub[c * HALF * NPAD + pt * NPAD + a] = 0.0;
+            Vb[pt * NPAD + a] = 0.0;
+        }
     }
     __syncthreads();
     const int g2 = gs * gs, g4 = g2 * g2;
@@ -647,6 +649,139 @@ __global__ void __launch_bounds__(256) k_far_onthefly(int q2, const int64_t *__r
         T sum = part[mu];
         for (int w = 1; w < nw; ++w) sum += part[w * q2 + mu];
         Yh[(size_t)t * q2 + mu] = sum * (0.07957747154594767 * nodes[((size_t)t * q2 + mu) * 4 + 3]);
+    }
+}
+
+// 1/sqrt(r2) for finite r2 > 0: the hardware estimate refined by the
+// second-order expansion of (1 - e)^(-1/2) = 1 + e/2 + 3e^2/8, e = 1 - r2 y^2.
+__device__ inline double rsqrt_pos(double r2)
+{
+    double y = __builtin_amdgcn_rsq(r2);
+    double e = fma(-r2 * y, y, 1.0);
+    return fma(y * e, fma(e, 0.375, 0.5), y);
+}
+
+// Far field generated on the fly, once per mirrored pair of coupling blocks
+// (Sec. 4.2): G is symmetric, so the block of (s, t) is the transpose of the
+// block of (t, s) and one evaluation of G(x_i, y_j) serves both products.
+// One wave per pair k (t < s, same level); its 64 lanes form an 8 x 8 grid and
+// lane (li, lj) owns targets li*TT .. li*TT+TT-1 and sources lj*TT .. lj*TT+TT-1
+// (q^2 <= 8 TT).  The unscaled products are written as partial rows:
+// part[2k] = sum_j G_ij w_j X_s[j] (for cluster t), part[2k+1] = sum_i G_ij w_i X_t[i]
+// (for cluster s); k_far_gather sums them per cluster and applies the weights.
+template <class T, int TT>
+__global__ void __launch_bounds__(256) k_far_sym(int64_t nup, const int32_t *__restrict__ up_t,
+                                                 const int32_t *__restrict__ up_s, int q2,
+                                                 const double *__restrict__ nodes, const T *__restrict__ Xh,
+                                                 double kappa, T *__restrict__ part)
+{
+    constexpr int W = 8 * TT;  // padded nodes per cluster
+    __shared__ T buf[4][8 * W];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t k = (int64_t)blockIdx.x * 4 + wave;
+    if (k >= nup) return;  // whole waves only; no block-wide barrier follows
+    const int li = lane >> 3, lj = lane & 7;
+    const int64_t t = up_t[k], sc = up_s[k];
+    T *cb = buf[wave];
+    double tx[TT], ty[TT], tz[TT];
+    T wt[TT], racc[TT];
+#pragma unroll
+    for (int ii = 0; ii < TT; ++ii) {
+        const int i = li * TT + ii;
+        racc[ii] = zero<T>();
+        if (i < q2) {
+            const double *nd = nodes + ((size_t)t * q2 + i) * 4;
+            tx[ii] = nd[0];
+            ty[ii] = nd[1];
+            tz[ii] = nd[2];
+            wt[ii] = Xh[(size_t)t * q2 + i] * nd[3];
+        } else {  // padding: far from every node, zero weight
+            tx[ii] = 1e100;
+            ty[ii] = tz[ii] = 0.0;
+            wt[ii] = zero<T>();
+        }
+    }
+    // source node jj (padding: far from every node, zero weight), loaded one ahead
+    auto load_src = [&](int jj, double &x, double &y, double &z, double &w, T &xv) {
+        const int j = lj * TT + jj;
+        x = -1e100;
+        y = z = w = 0.0;
+        xv = zero<T>();
+        if (jj < TT && j < q2) {
+            const double *nd = nodes + ((size_t)sc * q2 + j) * 4;
+            x = nd[0];
+            y = nd[1];
+            z = nd[2];
+            w = nd[3];
+            xv = Xh[(size_t)sc * q2 + j];
+        }
+    };
+    double nsx, nsy, nsz, nsw;
+    T nxv;
+    load_src(0, nsx, nsy, nsz, nsw, nxv);
+#pragma unroll 1
+    for (int jj = 0; jj < TT; ++jj) {
+        const int j = lj * TT + jj;
+        const double sx = nsx, sy = nsy, sz = nsz;
+        const T ws = nxv * nsw;
+        load_src(jj + 1, nsx, nsy, nsz, nsw, nxv);
+        T csum = zero<T>();
+#pragma unroll
+        for (int ii = 0; ii < TT; ++ii) {
+            const double d0 = tx[ii] - sx, d1 = ty[ii] - sy, d2 = tz[ii] - sz;
+            const double r2 = d0 * d0 + d1 * d1 + d2 * d2;
+            const double ir = rsqrt_pos(r2);
+            if constexpr (NComp<T>::value == 1) {
+                racc[ii] += ir * ws;
+                csum += ir * wt[ii];
+            } else {
+                double sn, cs;
+                sincos(kappa * (r2 * ir), &sn, &cs);
+                const T g{cs * ir, sn * ir};
+                racc[ii] += g * ws;
+                csum += g * wt[ii];
+            }
+        }
+        cb[li * W + j] = csum;
+    }
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    T *pc = part + (size_t)(2 * k + 1) * q2;
+    for (int j = lane; j < q2; j += 64) {
+        T v = cb[j];
+#pragma unroll
+        for (int r = 1; r < 8; ++r) v += cb[r * W + j];
+        pc[j] = v;
+    }
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+#pragma unroll
+    for (int ii = 0; ii < TT; ++ii) cb[lj * W + li * TT + ii] = racc[ii];
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    T *pr = part + (size_t)(2 * k) * q2;
+    for (int i = lane; i < q2; i += 64) {
+        T v = cb[i];
+#pragma unroll
+        for (int r = 1; r < 8; ++r) v += cb[r * W + i];
+        pr[i] = v;
+    }
+}
+
+// Coupling result of every cluster t >= row0: the partial rows of its far
+// blocks (pidx[e] for CSR entry e) summed in CSR order, times the node weights
+// and the 1/(4 pi) of the kernel.  One wave per cluster.
+template <class T>
+__global__ void __launch_bounds__(64) k_far_gather(int q2, const int64_t *__restrict__ ptr,
+                                                   const int32_t *__restrict__ pidx, const T *__restrict__ part,
+                                                   const double *__restrict__ nodes, T *__restrict__ Yh, int64_t row0)
+{
+    const int64_t t = row0 + blockIdx.x;
+    const int64_t k0 = ptr[t], k1 = ptr[t + 1];
+    for (int i = threadIdx.x; i < q2; i += 64) {
+        T acc = zero<T>();
+        for (int64_t e = k0; e < k1; ++e) acc += part[(size_t)pidx[e] * q2 + i];
+        Yh[(size_t)t * q2 + i] = acc * (0.07957747154594767 * nodes[((size_t)t * q2 + i) * 4 + 3]);
     }
 }
 
@@ -1138,6 +1273,11 @@ struct igb_operator {
     int64_t *far_ptr = nullptr;
     int32_t *far_src = nullptr, *far_tgt = nullptr;
     void *coup = nullptr;
+    // on-the-fly far field by mirrored block pairs (q^2 <= 64): the pairs t < s,
+    // the partial-row index of every CSR far entry, the partial rows
+    int64_t nup = 0;
+    int32_t *up_t = nullptr, *up_s = nullptr, *far_pidx = nullptr;
+    void *fpart = nullptr;
     void *xs = nullptr, *ys = nullptr, *Xh = nullptr, *Yh = nullptr, *ext = nullptr;
     void *diag = nullptr;
     // solver work
@@ -1270,9 +1410,16 @@ static igb_status launch_singular(igb_operator *op, const PairRec *d, int64_t n)
 }
 
 // superspace matvec on internal vectors: ys = A xs.  When ev is given, ev[k]
-// is recorded on the operator's stream before stage k and ev[6] at the end:
-// stages 0 leaf moments, 1 upward, 2 coupling GEMV, 3 downward, 4 near GEMV,
-// 5 leaf back-moments.
+// is recorded on the operator's stream before stage k and ev[7] at the end:
+// stages 0 leaf moments, 1 upward, 2 coupling blocks, 3 coupling gather (on
+// the fly by mirrored pairs only), 4 downward, 5 near GEMV, 6 leaf back-moments.
+template <class T, int TT>
+static void launch_far_sym(igb_operator *op, const T *Xh)
+{
+    hipLaunchKernelGGL((k_far_sym<T, TT>), dim3((unsigned)((op->nup + 3) / 4)), dim3(256), 0, op->st, op->nup, op->up_t,
+                       op->up_s, op->s.q * op->s.q, op->nodes, Xh, op->s.kappa, (T *)op->fpart);
+}
+
 template <class T>
 static igb_status matvec_internal(igb_operator *op, const T *xs, T *ys, hipEvent_t *ev = nullptr)
 {
@@ -1301,9 +1448,21 @@ static igb_status matvec_internal(igb_operator *op, const T *xs, T *ys, hipEvent
         }
     }
     if ((rc = mark(2))) return rc;
+    int64_t row0 = s.cl_off[op->lmin], nrows = s.cl_off[s.L + 1] - row0;
+    const bool sym = has_far && op->fpart != nullptr;
     if (has_far) {
-        int64_t row0 = s.cl_off[op->lmin], nrows = s.cl_off[s.L + 1] - row0;
-        if (s.mode == IGB_H2_ONTHEFLY) {
+        if (sym) {
+            switch ((q2 + 7) / 8) {
+            case 1: launch_far_sym<T, 1>(op, Xh); break;
+            case 2: launch_far_sym<T, 2>(op, Xh); break;
+            case 3: launch_far_sym<T, 3>(op, Xh); break;
+            case 4: launch_far_sym<T, 4>(op, Xh); break;
+            case 5: launch_far_sym<T, 5>(op, Xh); break;
+            case 6: launch_far_sym<T, 6>(op, Xh); break;
+            case 7: launch_far_sym<T, 7>(op, Xh); break;
+            default: launch_far_sym<T, 8>(op, Xh); break;
+            }
+        } else if (s.mode == IGB_H2_ONTHEFLY) {
             size_t shm = (size_t)4 * q2 * (3 + NComp<T>::value) * sizeof(double) + (size_t)4 * q2 * sizeof(T);
             hipLaunchKernelGGL((k_far_onthefly<T>), dim3((unsigned)nrows), dim3(256), shm, op->st, q2, op->far_ptr,
                                op->far_src, op->nodes, (const T *)Xh, s.kappa, Yh, row0);
@@ -1314,6 +1473,12 @@ static igb_status matvec_internal(igb_operator *op, const T *xs, T *ys, hipEvent
         LAUNCHCHK();
     }
     if ((rc = mark(3))) return rc;
+    if (sym) {
+        hipLaunchKernelGGL((k_far_gather<T>), dim3((unsigned)nrows), dim3(64), 0, op->st, q2, op->far_ptr, op->far_pidx,
+                           (const T *)op->fpart, op->nodes, Yh, row0);
+        LAUNCHCHK();
+    }
+    if ((rc = mark(4))) return rc;
     if (has_far) {
         for (int l = op->lmin; l < s.L; ++l) {
             hipLaunchKernelGGL((k_downward<T>), dim3((unsigned)(s.cl_off[l + 2] - s.cl_off[l + 1])), dim3(64),
@@ -1322,18 +1487,18 @@ static igb_status matvec_internal(igb_operator *op, const T *xs, T *ys, hipEvent
             LAUNCHCHK();
         }
     }
-    if ((rc = mark(4))) return rc;
+    if ((rc = mark(5))) return rc;
     hipLaunchKernelGGL((k_bsr_gemv<T, 0>), dim3(s.nleaf), dim3(256), 4 * s.nl * sizeof(T), op->st, s.nl, op->near_ptr,
                        op->near_src, (const T *)op->nearb, xs, ys, (int64_t)0);
     LAUNCHCHK();
-    if ((rc = mark(5))) return rc;
+    if ((rc = mark(6))) return rc;
     if (has_far) {
         size_t shm = (size_t)(q2 + q * s.n1) * sizeof(T);
         hipLaunchKernelGGL((k_leaf_back<T>), dim3(s.nleaf), dim3(64), shm, op->st, s.n1, q, s.side, s.p + 1, s.nloc, s.nl,
                            op->M1, (const T *)(Yh + s.cl_off[s.L] * q2), ys);
         LAUNCHCHK();
     }
-    return mark(6);
+    return mark(7);
 }
 
 template <class T>
@@ -1423,12 +1588,10 @@ static igb_status assemble(igb_operator *op)
     int q2 = s.q * s.q;
     const int *ords = op->gord;
     // the touching pairs of the plan must be exactly the ones quadrature already ran on
-    std::string terr = check_touching(s, op->touch);
-    if (!terr.empty()) return fail(IGB_EINVAL, terr);
+    // (and, sorted like them, they carry the near-block indices for the scatter)
     std::vector<PairRec> touch;
-    touch.reserve(op->ntouch);
-    for (const PairRec &R : s.pairs)
-        if (R.cls != kRegular) touch.push_back(R);
+    std::string terr = check_touching(s, op->touch, &touch);
+    if (!terr.empty()) return fail(IGB_EINVAL, terr);
     // near-field blocks
     op->near_bytes = (int64_t)s.near_src.size() * s.nl * s.nl * (int64_t)sizeof(T);
     if ((rc = dalloc(op, &op->nearb, op->near_bytes))) return rc;
@@ -1556,6 +1719,39 @@ static igb_status create_device_plan(igb_operator *op)
         for (int64_t c = 0; c + 1 < (int64_t)s.far_ptr.size(); ++c)
             for (int64_t k = s.far_ptr[c]; k < s.far_ptr[c + 1]; ++k) tg[k] = (int32_t)c;
         if ((rc = upload(op, &op->far_tgt, tg.data(), tg.size() * sizeof(int32_t)))) return rc;
+    }
+    if (s.mode == IGB_H2_ONTHEFLY && s.q * s.q <= 64 && !s.far_src.empty()) {
+        // mirrored pairs: entry e = (c, src) with src > c owns pair k; its mirror
+        // (src, c) reads the column part of k
+        int64_t nfar = (int64_t)s.far_src.size(), ncl = (int64_t)s.far_ptr.size() - 1;
+        std::vector<int64_t> upk(nfar, -1);
+        std::vector<int32_t> ut, us, pidx(nfar);
+        for (int64_t c = 0; c < ncl; ++c)
+            for (int64_t e = s.far_ptr[c]; e < s.far_ptr[c + 1]; ++e)
+                if (s.far_src[e] > c) {
+                    upk[e] = (int64_t)ut.size();
+                    ut.push_back((int32_t)c);
+                    us.push_back(s.far_src[e]);
+                }
+        if ((int64_t)ut.size() * 2 >= ((int64_t)1 << 31)) return fail(IGB_EUNSUPPORTED, "too many far blocks");
+        for (int64_t c = 0; c < ncl; ++c)
+            for (int64_t e = s.far_ptr[c]; e < s.far_ptr[c + 1]; ++e) {
+                int32_t src = s.far_src[e];
+                if (src > c) {
+                    pidx[e] = (int32_t)(2 * upk[e]);
+                    continue;
+                }
+                auto b = s.far_src.begin() + s.far_ptr[src], en = s.far_src.begin() + s.far_ptr[src + 1];
+                auto it = std::lower_bound(b, en, (int32_t)c);
+                if (src == c || it == en || *it != (int32_t)c)
+                    return fail(IGB_EINVAL, "far-field partition is not symmetric");
+                pidx[e] = (int32_t)(2 * upk[it - s.far_src.begin()] + 1);
+            }
+        op->nup = (int64_t)ut.size();
+        if ((rc = upload(op, &op->up_t, ut.data(), ut.size() * sizeof(int32_t)))) return rc;
+        if ((rc = upload(op, &op->up_s, us.data(), us.size() * sizeof(int32_t)))) return rc;
+        if ((rc = upload(op, &op->far_pidx, pidx.data(), pidx.size() * sizeof(int32_t)))) return rc;
+        if ((rc = dalloc(op, &op->fpart, (size_t)2 * op->nup * s.q * s.q * op->esz))) return rc;
     }
     return op->cplx ? assemble<cd>(op) : assemble<double>(op);
 }
@@ -2013,13 +2209,7 @@ igb_status igb_export_pair_classes(const igb_operator *op, int32_t *pairs_host)
 {
     CHECK_OP(op);
     if (!pairs_host && !op->s.pairs.empty()) return fail(IGB_EINVAL, "null host pointer");
-    for (size_t k = 0; k < op->s.pairs.size(); ++k) {
-        const PairRec &R = op->s.pairs[k];
-        pairs_host[4 * k] = R.E;
-        pairs_host[4 * k + 1] = R.F;
-        pairs_host[4 * k + 2] = R.cls;
-        pairs_host[4 * k + 3] = R.order;
-    }
+    sorted_pair_classes(op->s, pairs_host);
     return IGB_OK;
 }
 
@@ -2173,13 +2363,7 @@ igb_status igb_plan_export_pair_classes(const igb_plan *plan, int32_t *pairs_hos
     if (!plan) return fail(IGB_EINVAL, "plan is null");
     const Setup &s = plan->s;
     if (!pairs_host && !s.pairs.empty()) return fail(IGB_EINVAL, "null host pointer");
-    for (size_t k = 0; k < s.pairs.size(); ++k) {
-        const PairRec &R = s.pairs[k];
-        pairs_host[4 * k] = R.E;
-        pairs_host[4 * k + 1] = R.F;
-        pairs_host[4 * k + 2] = R.cls;
-        pairs_host[4 * k + 3] = R.order;
-    }
+    sorted_pair_classes(s, pairs_host);
     return IGB_OK;
 }
 
@@ -2189,21 +2373,22 @@ igb_status igb_plan_export_pair_classes(const igb_plan *plan, int32_t *pairs_hos
 template <class T>
 static igb_status profile_impl(igb_operator *op, int reps, double *ms)
 {
-    hipEvent_t ev[7];
-    for (int k = 0; k < 7; ++k) HIPCHK(hipEventCreate(&ev[k]));
-    for (int k = 0; k < IGB_NUM_MATVEC_STAGES; ++k) ms[k] = 0.0;
+    constexpr int NS = IGB_NUM_MATVEC_STAGES;
+    hipEvent_t ev[NS + 1];
+    for (int k = 0; k <= NS; ++k) HIPCHK(hipEventCreate(&ev[k]));
+    for (int k = 0; k < NS; ++k) ms[k] = 0.0;
     igb_status rc = IGB_OK;
     for (int r = 0; r < reps && rc == IGB_OK; ++r) {
         rc = matvec_internal<T>(op, (const T *)op->xs, (T *)op->ys, ev);
         if (rc) break;
-        if (hipEventSynchronize(ev[6]) != hipSuccess) { rc = fail(IGB_EHIP, "event synchronize"); break; }
-        for (int k = 0; k < 6; ++k) {
+        if (hipEventSynchronize(ev[NS]) != hipSuccess) { rc = fail(IGB_EHIP, "event synchronize"); break; }
+        for (int k = 0; k < NS; ++k) {
             float t = 0.f;
             if (hipEventElapsedTime(&t, ev[k], ev[k + 1]) != hipSuccess) { rc = fail(IGB_EHIP, "event elapsed"); break; }
             ms[k] += t;
         }
     }
-    for (int k = 0; k < 7; ++k) (void)hipEventDestroy(ev[k]);
+    for (int k = 0; k <= NS; ++k) (void)hipEventDestroy(ev[k]);
     if (rc) return rc;
     for (int k = 0; k < IGB_NUM_MATVEC_STAGES; ++k) ms[k] /= reps;
     return IGB_OK;

@@ -5,6 +5,10 @@
 #include "setup.h"
 
 #include <algorithm>
+#include <atomic>
+#include <condition_variable>
+#include <functional>
+#include <mutex>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -14,30 +18,104 @@
 
 namespace igb {
 
-// Run f(begin, end, worker) over [0, n) split into contiguous chunks on up to
-// hardware_concurrency threads (at most 32).  Results that must stay ordered
+// A process-wide pool of worker threads, created on first use and kept until
+// the process ends (never destroyed, so no thread outlives its state).  One
+// parallel region runs at a time; a caller that finds the pool busy (another
+// host thread inside a region) runs its chunks itself.
+namespace {
+class Pool {
+  public:
+    static Pool &get()
+    {
+        static Pool *p = new Pool();
+        return *p;
+    }
+    int size() const { return (int)workers_.size() + 1; }
+    // run job(c) for c in [0, n); the caller takes part
+    template <class J>
+    void run(int n, J &job)
+    {
+        std::unique_lock<std::mutex> region(region_, std::try_to_lock);
+        if (!region.owns_lock() || n <= 1) {
+            for (int c = 0; c < n; ++c) job(c);
+            return;
+        }
+        {
+            std::lock_guard<std::mutex> g(mu_);
+            fn_ = [&job](int c) { job(c); };
+            nchunk_ = n;
+            next_.store(0);
+            done_ = 0;
+            ++gen_;
+        }
+        cv_.notify_all();
+        int c, mine = 0;
+        while ((c = next_.fetch_add(1)) < n) { job(c); ++mine; }
+        std::unique_lock<std::mutex> g(mu_);
+        done_ += mine;
+        // every chunk ran and no worker still holds this region's job
+        finished_.wait(g, [&] { return done_ == nchunk_ && active_ == 0; });
+        fn_ = nullptr;
+    }
+
+  private:
+    Pool()
+    {
+        unsigned hw = std::max(1u, std::min(32u, std::thread::hardware_concurrency()));
+        for (unsigned i = 1; i < hw; ++i) workers_.emplace_back([this] { loop(); });
+        for (auto &t : workers_) t.detach();
+    }
+    void loop()
+    {
+        uint64_t seen = 0;
+        for (;;) {
+            std::function<void(int)> fn;
+            int n;
+            {
+                std::unique_lock<std::mutex> g(mu_);
+                cv_.wait(g, [&] { return gen_ != seen; });
+                seen = gen_;
+                if (!fn_) continue;  // woke after that region had ended
+                fn = fn_;
+                n = nchunk_;
+                ++active_;
+            }
+            int c, mine = 0;
+            while ((c = next_.fetch_add(1)) < n) { fn(c); ++mine; }
+            std::lock_guard<std::mutex> g(mu_);
+            done_ += mine;
+            --active_;
+            if (done_ == nchunk_ && active_ == 0) finished_.notify_all();
+        }
+    }
+    std::vector<std::thread> workers_;
+    std::mutex region_, mu_;
+    std::condition_variable cv_, finished_;
+    std::function<void(int)> fn_;
+    std::atomic<int> next_{0};
+    int nchunk_ = 0, done_ = 0, active_ = 0;
+    uint64_t gen_ = 0;
+};
+}  // namespace
+
+// Run f(begin, end, chunk) over [0, n) split into contiguous chunks (at most
+// max_chunks, at most one per pool thread).  Results that must stay ordered
 // are written per chunk by the callers and concatenated in chunk order.
 template <class F>
 static void parallel_chunks(int64_t n, int max_chunks, F f)
 {
-    unsigned hw = std::max(1u, std::min(32u, std::thread::hardware_concurrency()));
-    int nch = (int)std::max<int64_t>(1, std::min<int64_t>({(int64_t)hw, (int64_t)max_chunks, n}));
+    int nch = (int)std::max<int64_t>(1, std::min<int64_t>({(int64_t)Pool::get().size(), (int64_t)max_chunks, n}));
     if (nch <= 1 || n < 64) {
         f((int64_t)0, n, 0);
         return;
     }
-    std::vector<std::thread> th;
-    for (int c = 0; c < nch; ++c) {
-        int64_t b = n * c / nch, e = n * (c + 1) / nch;
-        th.emplace_back([=, &f] { f(b, e, c); });
-    }
-    for (auto &t : th) t.join();
+    auto job = [&](int c) { f(n * c / nch, n * (c + 1) / nch, c); };
+    Pool::get().run(nch, job);
 }
 
 static int num_workers(int64_t n)
 {
-    unsigned hw = std::max(1u, std::min(32u, std::thread::hardware_concurrency()));
-    return (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)hw, n));
+    return (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)Pool::get().size(), n));
 }
 
 // ---------------------------------------------------------------------------
@@ -351,11 +429,17 @@ static bool admissible(const Setup &s, const LevelGeo &G, int a, int b)
     double lb = cc - G.rad[a] - G.rad[b];
     if (lb > 0 && md < s.eta * lb * (1.0 - 1e-12)) return true;
     if (md > s.eta * cc * (1.0 + 1e-12)) return false;
+    // md < eta * min_ij |A_i - B_j| holds iff it holds for every pair (i, j)
+    // (rounded sqrt and product are monotone); rows of A whose distance bound
+    // to B's sphere clears the threshold with margin are skipped
     const double *A = &G.pts[(size_t)a * 75], *B = &G.pts[(size_t)b * 75];
-    double dmin = 1e300;
-    for (int i = 0; i < 25; ++i)
-        for (int j = 0; j < 25; ++j) dmin = std::min(dmin, dist(A + 3 * i, B + 3 * j));
-    return md < s.eta * dmin;
+    const double thr = md / s.eta * (1.0 + 1e-12);
+    for (int i = 0; i < 25; ++i) {
+        if (dist(A + 3 * i, &G.cen[3 * b]) - G.rad[b] > thr) continue;
+        for (int j = 0; j < 25; ++j)
+            if (!(md < s.eta * dist(A + 3 * i, B + 3 * j))) return false;
+    }
+    return true;
 }
 
 static void build_partition(Setup &s)
@@ -399,28 +483,29 @@ static void build_partition(Setup &s)
         }
         cur.swap(nxt);
     }
-    // sort
+    // sort (packed keys; cluster indices are below 2^29 by the size limits)
     {
         size_t nb = s.near.size() / 2;
-        std::vector<size_t> idx(nb);
-        std::iota(idx.begin(), idx.end(), 0);
-        std::sort(idx.begin(), idx.end(), [&](size_t x, size_t y) {
-            return std::make_pair(s.near[2 * x], s.near[2 * x + 1]) < std::make_pair(s.near[2 * y], s.near[2 * y + 1]);
-        });
-        std::vector<int32_t> v(s.near.size());
-        for (size_t k = 0; k < nb; ++k) { v[2 * k] = s.near[2 * idx[k]]; v[2 * k + 1] = s.near[2 * idx[k] + 1]; }
-        s.near.swap(v);
+        std::vector<uint64_t> key(nb);
+        for (size_t k = 0; k < nb; ++k) key[k] = ((uint64_t)(uint32_t)s.near[2 * k] << 32) | (uint32_t)s.near[2 * k + 1];
+        std::sort(key.begin(), key.end());
+        for (size_t k = 0; k < nb; ++k) {
+            s.near[2 * k] = (int32_t)(key[k] >> 32);
+            s.near[2 * k + 1] = (int32_t)(key[k] & 0xffffffffu);
+        }
     }
     {
         size_t nb = s.far.size() / 3;
-        std::vector<size_t> idx(nb);
-        std::iota(idx.begin(), idx.end(), 0);
-        auto key = [&](size_t x) { return std::make_tuple(s.far[3 * x], s.far[3 * x + 1], s.far[3 * x + 2]); };
-        std::sort(idx.begin(), idx.end(), [&](size_t x, size_t y) { return key(x) < key(y); });
-        std::vector<int32_t> v(s.far.size());
+        std::vector<uint64_t> key(nb);
         for (size_t k = 0; k < nb; ++k)
-            for (int c = 0; c < 3; ++c) v[3 * k + c] = s.far[3 * idx[k] + c];
-        s.far.swap(v);
+            key[k] = ((uint64_t)s.far[3 * k] << 58) | ((uint64_t)(uint32_t)s.far[3 * k + 1] << 29) | (uint32_t)s.far[3 * k + 2];
+        std::sort(key.begin(), key.end());
+        const uint64_t m29 = (1ull << 29) - 1;
+        for (size_t k = 0; k < nb; ++k) {
+            s.far[3 * k] = (int32_t)(key[k] >> 58);
+            s.far[3 * k + 1] = (int32_t)((key[k] >> 29) & m29);
+            s.far[3 * k + 2] = (int32_t)(key[k] & m29);
+        }
     }
     // CSR structures
     s.near_ptr.assign(s.nleaf + 1, 0);
@@ -455,27 +540,25 @@ static int other_adjacent(int o, int a)
 
 // element corners (physical), 3x3 grids and grid diameters, used by the
 // touching test and the regular-pair order
-static void element_geometry(Setup &s)
+static void element_geometry_one(Setup &s, int E)
 {
-    s.ecorner.assign((size_t)s.nelem * 12, 0.0);
-    s.egrid.assign((size_t)s.nelem * 27, 0.0);
-    s.ediam.assign(s.nelem, 0.0);
-    parallel_chunks(s.nelem, 1 << 30, [&](int64_t eb, int64_t ee, int) {
-        for (int E = (int)eb; E < (int)ee; ++E) {
-            for (int c = 0; c < 4; ++c) tile_eval(s, E, kCorner[c][0], kCorner[c][1], &s.ecorner[(size_t)E * 12 + 3 * c], nullptr);
-            for (int b = 0; b < 3; ++b)
-                for (int a = 0; a < 3; ++a) tile_eval(s, E, 0.5 * a, 0.5 * b, &s.egrid[(size_t)E * 27 + 3 * (3 * b + a)], nullptr);
-            double d = 0.0;
-            for (int i = 0; i < 9; ++i)
-                for (int j = i + 1; j < 9; ++j) d = std::max(d, dist(&s.egrid[(size_t)E * 27 + 3 * i], &s.egrid[(size_t)E * 27 + 3 * j]));
-            s.ediam[E] = d;
-        }
-    });
+    for (int c = 0; c < 4; ++c) tile_eval(s, E, kCorner[c][0], kCorner[c][1], &s.ecorner[(size_t)E * 12 + 3 * c], nullptr);
+    for (int b = 0; b < 3; ++b)
+        for (int a = 0; a < 3; ++a) tile_eval(s, E, 0.5 * a, 0.5 * b, &s.egrid[(size_t)E * 27 + 3 * (3 * b + a)], nullptr);
+    double d = 0.0;
+    for (int i = 0; i < 9; ++i)
+        for (int j = i + 1; j < 9; ++j) d = std::max(d, dist(&s.egrid[(size_t)E * 27 + 3 * i], &s.egrid[(size_t)E * 27 + 3 * j]));
+    s.ediam[E] = d;
+    // bounding sphere of the 3x3 grid about its centre point
+    const double *C = &s.egrid[(size_t)E * 27 + 12];
+    double r = 0.0;
+    for (int i = 0; i < 9; ++i) r = std::max(r, dist(C, &s.egrid[(size_t)E * 27 + 3 * i]));
+    s.erad[E] = r;
 }
 
 // Classification of one element pair E <= F (class, Gauss order, canonical frames).
 // Touching is decided physically: corners coincide within 1e-10 * max diam.
-static void classify_pair(const Setup &s, int E, int F, PairRec &R)
+static void classify_pair(const Setup &s, int E, int F, PairRec &R, bool touching_only = false)
 {
     R.E = E;
     R.F = F;
@@ -488,6 +571,21 @@ static void classify_pair(const Setup &s, int E, int F, PairRec &R)
     }
     const double *cE = &s.ecorner[(size_t)E * 12], *cF = &s.ecorner[(size_t)F * 12];
     double tol = 1e-10 * md;
+    // lower bound on every grid-point distance from the two bounding spheres
+    // (corners are grid points); it settles most pairs without the full search
+    double cc = dist(&s.egrid[(size_t)E * 27 + 12], &s.egrid[(size_t)F * 27 + 12]);
+    double lb = cc - s.erad[E] - s.erad[F] - 1e-14 * cc;
+    if (lb > tol) {
+        R.cls = kRegular;
+        if (touching_only) {
+            R.order = s.g0;
+            return;
+        }
+        if (lb >= 1.2 * md * (1.0 + 1e-12)) {
+            R.order = s.g0;
+            return;
+        }
+    }
     int match[4], nsh = 0;
     for (int c = 0; c < 4; ++c) {
         match[c] = -1;
@@ -516,6 +614,9 @@ static void classify_pair(const Setup &s, int E, int F, PairRec &R)
         R.oF = kk; R.aF = (kk + 1) & 3; R.bF = (kk + 3) & 3;
         return;
     }
+    R.cls = kRegular;
+    R.order = s.g0;
+    if (touching_only) return;
     const double *gE = &s.egrid[(size_t)E * 27], *gF = &s.egrid[(size_t)F * 27];
     double dmin = 1e300;
     for (int a = 0; a < 9; ++a)
@@ -535,47 +636,79 @@ std::string enumerate_touching(const Setup &s, std::vector<PairRec> &out)
     double dmin = 1e300, dmax = 0.0;
     for (double d : s.ediam) { dmin = std::min(dmin, d); dmax = std::max(dmax, d); }
     if (!(dmax > 0.0)) return "degenerate elements (zero diameter)";
-    double cell = (dmin > 0.0 ? dmin : dmax) * 0.25;
-    auto key = [&](const double *x, int dx, int dy, int dz) {
-        int64_t i = (int64_t)std::floor(x[0] / cell) + dx, j = (int64_t)std::floor(x[1] / cell) + dy,
-                k = (int64_t)std::floor(x[2] / cell) + dz;
-        return (i * 73856093) ^ (j * 19349663) ^ (k * 83492791);
+    // Corners are binned on a grid of cell size dmin/4.  Two corners within the
+    // touching tolerance (at most 1e-10 dmax apart) share a cell unless one of
+    // them lies within that tolerance of a cell face; only then are the
+    // neighbouring cells across that face searched as well.
+    const double cell = (dmin > 0.0 ? dmin : dmax) * 0.25;
+    const double margin = 4e-10 * dmax / cell + 1e-12;
+    auto cell_hash = [](int64_t i, int64_t j, int64_t k) {
+        uint64_t h = (uint64_t)i * 0x9E3779B97F4A7C15ull;
+        h ^= (uint64_t)j * 0xC2B2AE3D27D4EB4Full + (h << 6) + (h >> 2);
+        h ^= (uint64_t)k * 0x165667B19E3779F9ull + (h << 6) + (h >> 2);
+        return h;
     };
-    std::unordered_map<int64_t, std::vector<int32_t>> buckets;
-    for (int E = 0; E < s.nelem; ++E)
-        for (int c = 0; c < 4; ++c) buckets[key(&s.ecorner[(size_t)E * 12 + 3 * c], 0, 0, 0)].push_back(E);
-    std::vector<int64_t> cand;
-    for (int E = 0; E < s.nelem; ++E) {
-        cand.push_back(((int64_t)E << 32) | (uint32_t)E);
-        for (int c = 0; c < 4; ++c)
-            for (int dx = -1; dx <= 1; ++dx)
-                for (int dy = -1; dy <= 1; ++dy)
-                    for (int dz = -1; dz <= 1; ++dz) {
-                        auto it = buckets.find(key(&s.ecorner[(size_t)E * 12 + 3 * c], dx, dy, dz));
-                        if (it == buckets.end()) continue;
-                        for (int32_t F : it->second)
-                            if (F > E) cand.push_back(((int64_t)E << 32) | (uint32_t)F);
-                    }
-    }
-    std::sort(cand.begin(), cand.end());
-    cand.erase(std::unique(cand.begin(), cand.end()), cand.end());
-    for (int64_t c : cand) {
-        PairRec R;
-        std::memset(&R, 0, sizeof R);
-        classify_pair(s, (int)(c >> 32), (int)(c & 0xffffffff), R);
-        if (R.cls != kRegular) out.push_back(R);
-    }
+    const int64_t ncorner = (int64_t)s.nelem * 4;
+    std::vector<std::pair<uint64_t, int32_t>> tab(ncorner);
+    parallel_chunks(ncorner, 1 << 30, [&](int64_t b, int64_t e, int) {
+        for (int64_t k = b; k < e; ++k) {
+            const double *x = &s.ecorner[(size_t)k * 3];
+            tab[k] = {cell_hash((int64_t)std::floor(x[0] / cell), (int64_t)std::floor(x[1] / cell),
+                                (int64_t)std::floor(x[2] / cell)),
+                      (int32_t)(k / 4)};
+        }
+    });
+    std::sort(tab.begin(), tab.end());
+    int nw = num_workers(s.nelem / 64 + 1);
+    std::vector<std::vector<PairRec>> part(nw);
+    parallel_chunks(s.nelem, nw, [&](int64_t eb, int64_t ee, int w) {
+        std::vector<int32_t> cand;
+        for (int E = (int)eb; E < (int)ee; ++E) {
+            cand.clear();
+            for (int c = 0; c < 4; ++c) {
+                const double *x = &s.ecorner[(size_t)E * 12 + 3 * c];
+                int64_t id[3];
+                int lo[3], hi[3];
+                for (int a = 0; a < 3; ++a) {
+                    double t = x[a] / cell, f = std::floor(t);
+                    id[a] = (int64_t)f;
+                    lo[a] = (t - f < margin) ? -1 : 0;
+                    hi[a] = (t - f > 1.0 - margin) ? 1 : 0;
+                }
+                for (int dx = lo[0]; dx <= hi[0]; ++dx)
+                    for (int dy = lo[1]; dy <= hi[1]; ++dy)
+                        for (int dz = lo[2]; dz <= hi[2]; ++dz) {
+                            uint64_t h = cell_hash(id[0] + dx, id[1] + dy, id[2] + dz);
+                            auto it = std::lower_bound(tab.begin(), tab.end(), std::make_pair(h, (int32_t)INT32_MIN));
+                            for (; it != tab.end() && it->first == h; ++it)
+                                if (it->second > E) cand.push_back(it->second);
+                        }
+            }
+            std::sort(cand.begin(), cand.end());
+            cand.erase(std::unique(cand.begin(), cand.end()), cand.end());
+            PairRec R;
+            std::memset(&R, 0, sizeof R);
+            classify_pair(s, E, E, R);
+            part[w].push_back(R);
+            for (int32_t F : cand) {
+                std::memset(&R, 0, sizeof R);
+                classify_pair(s, E, F, R, true);
+                if (R.cls != kRegular) part[w].push_back(R);
+            }
+        }
+    });
+    size_t tot = 0;
+    for (auto &v : part) tot += v.size();
+    out.reserve(tot);
+    for (auto &v : part) out.insert(out.end(), v.begin(), v.end());
     return "";
 }
 
+// Near-field element pairs E <= F, in block order (target leaf, source leaf,
+// then the elements of each leaf row by row).  A pair is generated from the
+// block (leaf(E), leaf(F)) only; blk2 is the mirrored block (leaf(F), leaf(E)).
 static std::string build_pairs(Setup &s)
 {
-    auto leaf_of = [&](int E, int &el) {
-        int pt = E / (s.ne * s.ne), r = E % (s.ne * s.ne), e2 = r / s.ne, e1 = r % s.ne;
-        int nL = 1 << s.L;
-        el = (e2 % s.side) * s.side + (e1 % s.side);
-        return pt * nL * nL + (e2 / s.side) * nL + (e1 / s.side);
-    };
     auto block_index = [&](int t, int src) -> int32_t {
         auto b = s.near_src.begin() + s.near_ptr[t], e = s.near_src.begin() + s.near_ptr[t + 1];
         auto it = std::lower_bound(b, e, src);
@@ -586,13 +719,18 @@ static std::string build_pairs(Setup &s)
     for (int c = 0; c < 4; ++c) s.npairs_class[c] = 0;
     int nL = 1 << s.L;
     int64_t nnear = (int64_t)(s.near.size() / 2);
-    int nw = num_workers(nnear);
+    int nw = num_workers(nnear / 16 + 1);
     std::vector<std::vector<PairRec>> part(nw);
     std::vector<int> bad(nw, 0);
     parallel_chunks(nnear, nw, [&](int64_t kb, int64_t ke, int w) {
         std::vector<PairRec> &out = part[w];
         for (int64_t k = kb; k < ke; ++k) {
             int t = s.near[2 * k], src = s.near[2 * k + 1];
+            int32_t blk1 = (int32_t)k, blk2 = block_index(src, t);
+            if (blk2 < 0) {
+                bad[w] = 1;
+                continue;
+            }
             int pt = t / (nL * nL), rt = t % (nL * nL), t2 = rt / nL, t1 = rt % nL;
             int ps = src / (nL * nL), rs = src % (nL * nL), s2 = rs / nL, s1 = rs % nL;
             for (int a2 = 0; a2 < s.side; ++a2)
@@ -605,29 +743,25 @@ static std::string build_pairs(Setup &s)
                             PairRec R;
                             std::memset(&R, 0, sizeof R);
                             classify_pair(s, E, F, R);
-                            int elE, elF;
-                            int lE = leaf_of(E, elE), lF = leaf_of(F, elF);
-                            R.elE = (int8_t)elE;
-                            R.elF = (int8_t)elF;
-                            R.blk1 = block_index(lE, lF);
-                            R.blk2 = (E == F) ? -1 : block_index(lF, lE);
-                            if (R.blk1 < 0 || (E != F && R.blk2 < 0)) {
-                                bad[w] = 1;
-                                continue;
-                            }
+                            R.elE = (int8_t)(a2 * s.side + a1);
+                            R.elF = (int8_t)(b2 * s.side + b1);
+                            R.blk1 = blk1;
+                            R.blk2 = (E == F) ? -1 : blk2;
                             out.push_back(R);
                         }
                 }
         }
     });
+    size_t tot = 0;
     for (int w = 0; w < nw; ++w) {
         if (bad[w]) return "near-field partition is not symmetric";
+        tot += part[w].size();
+    }
+    s.pairs.reserve(tot);
+    for (int w = 0; w < nw; ++w) {
         for (const PairRec &R : part[w]) s.npairs_class[R.cls]++;
         s.pairs.insert(s.pairs.end(), part[w].begin(), part[w].end());
     }
-    std::sort(s.pairs.begin(), s.pairs.end(), [](const PairRec &a, const PairRec &b) {
-        return std::make_pair(a.E, a.F) < std::make_pair(b.E, b.F);
-    });
     return "";
 }
 
@@ -712,6 +846,7 @@ std::string build_setup_geometry(const Geometry &geo, const igb_params &prm, Set
     s.d = d;
     s.L = s.m - d;
     s.npatch = (int)geo.patches.size();
+    if (((int64_t)s.npatch << (2 * s.m)) >= ((int64_t)1 << 29)) return "too many elements (n_patches * 4^m >= 2^29)";
     s.ne = 1 << s.m;
     s.nelem = s.npatch * s.ne * s.ne;
     s.nloc = (s.p + 1) * (s.p + 1);
@@ -725,15 +860,29 @@ std::string build_setup_geometry(const Geometry &geo, const igb_params &prm, Set
     s.cl_off.assign(s.L + 2, 0);
     for (int l = 0; l <= s.L; ++l) s.cl_off[l + 1] = s.cl_off[l] + ((int64_t)s.npatch << (2 * l));
 
-    // Gauss rules 1..40
-    s.goff.assign(42, 0);
-    for (int n = 1; n <= 40; ++n) s.goff[n + 1] = s.goff[n] + n;
-    s.gx.assign(s.goff[41], 0.0);
-    s.gw.assign(s.goff[41], 0.0);
-    for (int n = 1; n <= 40; ++n) gauss_rule(n, &s.gx[s.goff[n]], &s.gw[s.goff[n]]);
+    // Gauss rules 1..40 (the same table for every operator: built once)
+    {
+        struct Table {
+            std::vector<int32_t> off;
+            std::vector<double> x, w;
+            Table() : off(42, 0)
+            {
+                for (int n = 1; n <= 40; ++n) off[n + 1] = off[n] + n;
+                x.assign(off[41], 0.0);
+                w.assign(off[41], 0.0);
+                for (int n = 1; n <= 40; ++n) gauss_rule(n, &x[off[n]], &w[off[n]]);
+            }
+        };
+        static const Table table;
+        s.goff = table.off;
+        s.gx = table.x;
+        s.gw = table.w;
+    }
 
     // element tiles by Bezier extraction, degree-elevated to one common bidegree
-    // (exact) so that every tile has the same compile-time shape on the device
+    // (exact) so that every tile has the same compile-time shape on the device.
+    // Separable: the u-extraction rows are applied once per element column e1,
+    // then each element contracts the v-extraction rows over that result.
     int pmax = 0;
     for (const Patch &P : geo.patches) pmax = std::max(pmax, std::max(P.pu, P.pv));
     int PG = pmax <= 1 ? 1 : (pmax <= 2 ? 2 : (pmax <= 4 ? 4 : 8));
@@ -741,41 +890,85 @@ std::string build_setup_geometry(const Geometry &geo, const igb_params &prm, Set
     s.tile_stride = (PG + 1) * (PG + 1) * 4;
     s.tiles.assign((size_t)s.nelem * s.tile_stride, 0.0);
     s.tile_deg.assign((size_t)s.nelem * 2, PG);
+    struct PatchExtraction {
+        std::vector<double> Mv, A;
+        std::vector<int> vlo, vhi;
+    };
+    std::vector<PatchExtraction> px(s.npatch);
+    // nonzero column range of every extraction row
+    auto support = [](const std::vector<double> &M, int rows, int cols, std::vector<int> &lo, std::vector<int> &hi) {
+        lo.assign(rows, 0);
+        hi.assign(rows, -1);
+        for (int k = 0; k < rows; ++k) {
+            int a = cols, b = -1;
+            for (int j = 0; j < cols; ++j)
+                if (M[(size_t)k * cols + j] != 0.0) { a = std::min(a, j); b = j; }
+            lo[k] = a;
+            hi[k] = b;
+        }
+    };
     for (int pt = 0; pt < s.npatch; ++pt) {
         const Patch &P = geo.patches[pt];
-        std::vector<double> Mu, Mv;
+        PatchExtraction &X = px[pt];
+        std::vector<double> Mu;
         int nru, nrv;
         std::string err = extraction(P.pu, P.U, P.nu, s.ne, Mu, nru);
         if (!err.empty()) return "patch " + std::to_string(pt) + " u: " + err;
-        err = extraction(P.pv, P.V, P.nv, s.ne, Mv, nrv);
+        err = extraction(P.pv, P.V, P.nv, s.ne, X.Mv, nrv);
         if (!err.empty()) return "patch " + std::to_string(pt) + " v: " + err;
-        std::vector<double> H((size_t)(P.pu + 1) * (P.pv + 1) * 4);
-        for (int e2 = 0; e2 < s.ne; ++e2)
-            for (int e1 = 0; e1 < s.ne; ++e1) {
-                int E = pt * s.ne * s.ne + e2 * s.ne + e1;
-                for (int rv = 0; rv <= P.pv; ++rv)
-                    for (int ru = 0; ru <= P.pu; ++ru) {
-                        int ku = (P.pu == 0 ? e1 : e1 * P.pu + ru), kv = (P.pv == 0 ? e2 : e2 * P.pv + rv);
-                        double acc[4] = {0, 0, 0, 0};
-                        for (int j = 0; j < P.nv; ++j) {
-                            double cv = Mv[(size_t)kv * P.nv + j];
-                            if (cv == 0.0) continue;
-                            for (int i = 0; i < P.nu; ++i) {
-                                double cu = Mu[(size_t)ku * P.nu + i];
-                                if (cu == 0.0) continue;
-                                const double *c = &P.cpw[4 * ((size_t)j * P.nu + i)];
-                                double f = cu * cv * c[3];
-                                acc[0] += f * c[0];
-                                acc[1] += f * c[1];
-                                acc[2] += f * c[2];
-                                acc[3] += f;
-                            }
-                        }
-                        for (int c = 0; c < 4; ++c) H[4 * (rv * (P.pu + 1) + ru) + c] = acc[c];
+        std::vector<int> ulo, uhi;
+        support(Mu, nru, P.nu, ulo, uhi);
+        support(X.Mv, nrv, P.nv, X.vlo, X.vhi);
+        // A[((e1 * nv + j) * (pu+1) + ru) * 4 + c] = sum_i Mu[ku][i] * w_ji * (x, y, z, 1)_ji
+        const int pu1 = P.pu + 1;
+        X.A.assign((size_t)s.ne * P.nv * pu1 * 4, 0.0);
+        for (int e1 = 0; e1 < s.ne; ++e1)
+            for (int ru = 0; ru < pu1; ++ru) {
+                int ku = P.pu == 0 ? e1 : e1 * P.pu + ru;
+                for (int j = 0; j < P.nv; ++j) {
+                    double acc[4] = {0, 0, 0, 0};
+                    for (int i = ulo[ku]; i <= uhi[ku]; ++i) {
+                        const double *c = &P.cpw[4 * ((size_t)j * P.nu + i)];
+                        double f = Mu[(size_t)ku * P.nu + i] * c[3];
+                        acc[0] += f * c[0];
+                        acc[1] += f * c[1];
+                        acc[2] += f * c[2];
+                        acc[3] += f;
                     }
-                elevate_tile(H, P.pu, P.pv, PG, &s.tiles[(size_t)E * s.tile_stride]);
+                    for (int c = 0; c < 4; ++c) X.A[(((size_t)e1 * P.nv + j) * pu1 + ru) * 4 + c] = acc[c];
+                }
             }
     }
+    s.ecorner.assign((size_t)s.nelem * 12, 0.0);
+    s.egrid.assign((size_t)s.nelem * 27, 0.0);
+    s.ediam.assign(s.nelem, 0.0);
+    s.erad.assign(s.nelem, 0.0);
+    // per element: v-contraction, degree elevation, corners / 3x3 grid / diameter
+    parallel_chunks(s.nelem, 1 << 30, [&](int64_t b, int64_t e, int) {
+        std::vector<double> H;
+        for (int64_t k = b; k < e; ++k) {
+            int E = (int)k;
+            int pt = E / (s.ne * s.ne), r = E % (s.ne * s.ne), e2 = r / s.ne, e1 = r % s.ne;
+            const Patch &P = geo.patches[pt];
+            const PatchExtraction &X = px[pt];
+            const int pu1 = P.pu + 1, pv1 = P.pv + 1;
+            H.assign((size_t)pu1 * pv1 * 4, 0.0);
+            for (int rv = 0; rv < pv1; ++rv) {
+                int kv = P.pv == 0 ? e2 : e2 * P.pv + rv;
+                for (int ru = 0; ru < pu1; ++ru) {
+                    double acc[4] = {0, 0, 0, 0};
+                    for (int j = X.vlo[kv]; j <= X.vhi[kv]; ++j) {
+                        double cv = X.Mv[(size_t)kv * P.nv + j];
+                        const double *a = &X.A[(((size_t)e1 * P.nv + j) * pu1 + ru) * 4];
+                        for (int c = 0; c < 4; ++c) acc[c] += cv * a[c];
+                    }
+                    for (int c = 0; c < 4; ++c) H[4 * (rv * pu1 + ru) + c] = acc[c];
+                }
+            }
+            elevate_tile(H, P.pu, P.pv, PG, &s.tiles[(size_t)E * s.tile_stride]);
+            element_geometry_one(s, E);
+        }
+    });
     // T band on Xi_{p,m}
     {
         int p = s.p;
@@ -829,7 +1022,6 @@ std::string build_setup_geometry(const Geometry &geo, const igb_params &prm, Set
                         s.Mlev[s.Mlev_off[l] + (size_t)(el * (s.p + 1) + r) * s.q + mu] = mom(nsub, el, r, mu);
         }
     }
-    element_geometry(s);
     s.setup_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     return "";
 }
@@ -843,19 +1035,41 @@ std::string build_setup_plan(Setup &s)
     return perr;
 }
 
-std::string check_touching(const Setup &s, const std::vector<PairRec> &touch)
+std::string check_touching(const Setup &s, const std::vector<PairRec> &touch, std::vector<PairRec> *plan_touch)
 {
-    size_t k = 0;
-    for (const PairRec &R : s.pairs) {
-        if (R.cls == kRegular) continue;
-        if (k >= touch.size()) return "touching pairs outside the enumerated set";
-        const PairRec &T = touch[k++];
+    std::vector<PairRec> mine;
+    std::vector<PairRec> &pt = plan_touch ? *plan_touch : mine;
+    pt.clear();
+    for (const PairRec &R : s.pairs)
+        if (R.cls != kRegular) pt.push_back(R);
+    std::sort(pt.begin(), pt.end(), [](const PairRec &a, const PairRec &b) {
+        return ((uint64_t)(uint32_t)a.E << 32 | (uint32_t)a.F) < ((uint64_t)(uint32_t)b.E << 32 | (uint32_t)b.F);
+    });
+    if (pt.size() != touch.size()) return "touching pair enumeration differs from the near-field pairs (count)";
+    for (size_t k = 0; k < pt.size(); ++k) {
+        const PairRec &R = pt[k], &T = touch[k];
         if (T.E != R.E || T.F != R.F || T.cls != R.cls || T.order != R.order || T.oE != R.oE || T.aE != R.aE ||
             T.bE != R.bE || T.oF != R.oF || T.aF != R.aF || T.bF != R.bF)
             return "touching pair enumeration differs from the near-field pairs";
     }
-    if (k != touch.size()) return "enumerated touching pairs missing from the near field";
     return "";
+}
+
+void sorted_pair_classes(const Setup &s, int32_t *out)
+{
+    std::vector<uint64_t> idx(s.pairs.size());
+    for (size_t k = 0; k < s.pairs.size(); ++k) idx[k] = k;
+    std::sort(idx.begin(), idx.end(), [&](uint64_t x, uint64_t y) {
+        const PairRec &a = s.pairs[x], &b = s.pairs[y];
+        return a.E < b.E || (a.E == b.E && a.F < b.F);
+    });
+    for (size_t k = 0; k < idx.size(); ++k) {
+        const PairRec &R = s.pairs[idx[k]];
+        out[4 * k] = R.E;
+        out[4 * k + 1] = R.F;
+        out[4 * k + 2] = R.cls;
+        out[4 * k + 3] = R.order;
+    }
 }
 
 std::string build_setup(const Geometry &geo, const igb_params &prm, Setup &s)

@@ -71,9 +71,10 @@ struct Setup {
     std::vector<int32_t> near_src;
     std::vector<int64_t> far_ptr;    // CSR over global clusters
     std::vector<int32_t> far_src;    // global cluster index of sources
-    // element corners (4 x 3), 3x3 grids (9 x 3) and grid diameters
-    std::vector<double> ecorner, egrid, ediam;
-    // near-field element pairs
+    // element corners (4 x 3), 3x3 grids (9 x 3), grid diameters and the radius of
+    // the grid about its centre point (grid point 4)
+    std::vector<double> ecorner, egrid, ediam, erad;
+    // near-field element pairs, in near-block order
     std::vector<PairRec> pairs;
     int64_t npairs_class[4] = {0, 0, 0, 0};
     // Gauss rules on [0,1], orders 1..40, concatenated: gx[goff[n] + i]
@@ -96,8 +97,12 @@ std::string build_setup_plan(Setup &s);
 // from physical corner coincidence alone, without the partition.  Every touching
 // pair lies in the near field, so this list equals the touching part of the plan.
 std::string enumerate_touching(const Setup &s, std::vector<PairRec> &out);
-// "" if the touching pairs of the plan are exactly `touch` (same order, class, frames).
-std::string check_touching(const Setup &s, const std::vector<PairRec> &touch);
+// "" if the touching pairs of the plan, sorted by (E, F), are exactly `touch`
+// (class, order, frames); the sorted plan records (with their block indices)
+// are returned through plan_touch when it is not null.
+std::string check_touching(const Setup &s, const std::vector<PairRec> &touch, std::vector<PairRec> *plan_touch = nullptr);
+// n_pairs x 4 (E, F, class, order) of the near-field pairs, sorted by (E, F).
+void sorted_pair_classes(const Setup &s, int32_t *out);
 
 // Host evaluation of an element tile: point and surface measure w.r.t. element-local coordinates.
 void tile_eval(const Setup &s, int E, double u, double v, double X[3], double *kap_local);

@@ -25,6 +25,12 @@ def test_library_exports_every_declared_symbol():
     assert declared == set(igb.EXPORTED)
 
 
+def test_stage_names_match_header():
+    with open(os.path.join(ROOT, "include", "igabem.h")) as fh:
+        n = int(re.search(r"#define IGB_NUM_MATVEC_STAGES (\d+)", fh.read()).group(1))
+    assert n == len(igb.STAGES)
+
+
 def test_geometry_validation_errors():
     good = W.sphere_patches()[0]
     igb.Geometry([good])

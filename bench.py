@@ -235,9 +235,16 @@ def main():
     rows = len(np.unique(off[far[:, 0]] + far[:, 1]))  # clusters with far blocks (rows written)
     srcs = len(np.unique(off[far[:, 0]] + far[:, 2]))  # distinct source moment vectors read
     roofs = {}
-    near_bytes = op.info.near_bytes + 8 * 2 * op.info.n_dof_super
+    # symmetric near storage: blocks (t, s) with t <= s, column stride nl rounded up to 8; the
+    # kernel reads them and the S* vector once and writes one partial row per block side
+    nleaf = npatch << (2 * op.info.leaf_level)
+    nl = op.info.n_dof_super // nleaf
+    ld = (nl + 7) // 8 * 8
+    nsb = int(np.sum(near[:, 0] <= near[:, 1]))
+    ndiag = int(np.sum(near[:, 0] == near[:, 1]))
+    near_bytes = op.info.near_bytes + 8 * op.info.n_dof_super + 8 * ld * (2 * nsb - ndiag)
     a = near_bytes / (stages["near_gemv"] * 1e-3) / 1e9
-    roofs["near_gemv"] = {"bound": "hbm", "kernel": "k_bsr_gemv<double, 0>", "achieved": round(a, 1),
+    roofs["near_gemv"] = {"bound": "hbm", "kernel": "k_near_sym<double>", "achieved": round(a, 1),
                           "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": round(a / HBM_PEAK_GBPS, 4),
                           "traffic": read_traffic("near_gemv"), "algorithmic_bytes": int(near_bytes),
                           "avg_ms": round(stages["near_gemv"], 4)}

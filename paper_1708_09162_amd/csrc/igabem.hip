@@ -99,10 +99,25 @@ __global__ void k_cluster_nodes(int64_t ncl_all, int L, const int64_t *__restric
 // ===========================================================================
 
 // Position of entry (row a of element elE, column b of element elF) in a
-// column-major leaf block of nl x nl.
-__device__ inline int64_t blk_pos(int nl, int nloc, int elE, int a, int elF, int b)
+// column-major leaf block of nl columns with column stride ld (ld >= nl).
+__device__ inline int64_t blk_pos(int ld, int nloc, int elE, int a, int elF, int b)
 {
-    return (int64_t)(elF * nloc + b) * nl + elE * nloc + a;
+    return (int64_t)(elF * nloc + b) * ld + elE * nloc + a;
+}
+
+// Near-field storage: only the leaf blocks (t, s) with t <= s are kept (the
+// Galerkin matrix is symmetric, complex symmetric for Helmholtz, so block
+// (s, t) is the transpose of block (t, s)).  sb[e] is the stored block of CSR
+// near entry e, or -1 for an entry with t > s.  A pair record writes its entry
+// (E row, F column) into sb[blk1] and the mirrored entry into sb[blk2]; the
+// lower one of the two is absent, and both land in the same block when
+// leaf(E) == leaf(F).
+template <class T>
+__device__ inline void near_targets(const int32_t *sb, const PairRec &R, int64_t bsz, T *blocks, T *&out1, T *&out2)
+{
+    const int32_t b1 = sb[R.blk1], b2 = R.blk2 >= 0 ? sb[R.blk2] : -1;
+    out1 = b1 >= 0 ? blocks + (int64_t)b1 * bsz : nullptr;
+    out2 = b2 >= 0 ? blocks + (int64_t)b2 * bsz : nullptr;
 }
 
 // Well separated pairs: tensor Gauss of order g in all four variables.
@@ -111,7 +126,8 @@ __device__ inline int64_t blk_pos(int nl, int nloc, int elE, int a, int elF, int
 template <class T, int P>
 __global__ void __launch_bounds__(128) k_near_regular(const PairRec *__restrict__ pairs, int npairs, int g,
                                                       const double *__restrict__ gp, const double *__restrict__ btab,
-                                                      double kappa, int nl, T *__restrict__ blocks)
+                                                      double kappa, int nl, int ld, const int32_t *__restrict__ sb,
+                                                      T *__restrict__ blocks)
 {
     constexpr int P1 = P + 1, NLOC = P1 * P1;
     extern __shared__ double sh[];
@@ -150,14 +166,14 @@ __global__ void __launch_bounds__(128) k_near_regular(const PairRec *__restrict_
         for (int b = 0; b < NLOC; ++b) tmp[i * NLOC + b] = acc[b] * kw;
     }
     __syncthreads();
-    T *out1 = blocks + (int64_t)R.blk1 * nl * nl;
-    T *out2 = R.blk2 >= 0 ? blocks + (int64_t)R.blk2 * nl * nl : nullptr;
+    T *out1, *out2;
+    near_targets(sb, R, (int64_t)nl * ld, blocks, out1, out2);
     for (int o = threadIdx.x; o < NLOC * NLOC; o += blockDim.x) {
         int a = o / NLOC, b = o % NLOC;
         T s = zero<T>();
         for (int i = 0; i < gg; ++i) s += psi[i * NLOC + a] * tmp[i * NLOC + b];
-        out1[blk_pos(nl, NLOC, R.elE, a, R.elF, b)] = s;
-        if (out2) out2[blk_pos(nl, NLOC, R.elF, b, R.elE, a)] = s;
+        if (out1) out1[blk_pos(ld, NLOC, R.elE, a, R.elF, b)] = s;
+        if (out2) out2[blk_pos(ld, NLOC, R.elF, b, R.elE, a)] = s;
     }
 }
 
@@ -359,18 +375,18 @@ __global__ void __launch_bounds__(64 * WAVES, NComp<T>::value == 1 ? 3 : 1) k_ne
 // Places staged touching-pair blocks (row-major nloc x nloc per pair, in the
 // order of `pairs`) into the near-field leaf blocks and their mirrors.
 template <class T>
-__global__ void k_scatter_pairs(const PairRec *__restrict__ pairs, int nloc, int nl, const T *__restrict__ pairbuf,
-                                T *__restrict__ blocks)
+__global__ void k_scatter_pairs(const PairRec *__restrict__ pairs, int nloc, int nl, int ld,
+                                const int32_t *__restrict__ sb, const T *__restrict__ pairbuf, T *__restrict__ blocks)
 {
     const PairRec R = pairs[blockIdx.x];
     const T *in = pairbuf + (int64_t)blockIdx.x * nloc * nloc;
-    T *out1 = blocks + (int64_t)R.blk1 * nl * nl;
-    T *out2 = R.blk2 >= 0 ? blocks + (int64_t)R.blk2 * nl * nl : nullptr;
+    T *out1, *out2;
+    near_targets(sb, R, (int64_t)nl * ld, blocks, out1, out2);
     for (int o = threadIdx.x; o < nloc * nloc; o += blockDim.x) {
         int a = o / nloc, b = o % nloc;
         T v = in[o];
-        out1[blk_pos(nl, nloc, R.elE, a, R.elF, b)] = v;
-        if (out2) out2[blk_pos(nl, nloc, R.elF, b, R.elE, a)] = v;
+        if (out1) out1[blk_pos(ld, nloc, R.elE, a, R.elF, b)] = v;
+        if (out2) out2[blk_pos(ld, nloc, R.elF, b, R.elE, a)] = v;
     }
 }
 
@@ -566,6 +582,127 @@ __global__ void __launch_bounds__(256) k_bsr_gemv(int nb, const int64_t *__restr
         T s = part[a];
         for (int w = 1; w < nw; ++w) s += part[w * nb + a];
         y[t * nb + a] = s;
+    }
+}
+
+// Near-field product with symmetric block storage (Sec. 4 item 4 blocks, one
+// stored block per mirrored pair): one wave per stored block k = (t, s),
+// t <= s, column-major with column stride ld (a multiple of 8, padding rows
+// zero).  The lanes form an 8 x 8 grid; lane (li, lj) reads 8 consecutive
+// rows (64 contiguous bytes) of the columns lj, lj + 8, ... of each 64-row
+// tile and accumulates both B x_s (rows) and B^T x_t (columns).  Writes the
+// partial rows part[2k] = B x_s (for leaf t) and, when t != s,
+// part[2k+1] = B^T x_t (for leaf s); k_gather sums them per leaf.
+typedef double v2d __attribute__((ext_vector_type(2)));
+
+template <class T>
+__device__ inline void load8(const T *p, T v[8])
+{
+    const v2d *q = (const v2d *)p;
+    if constexpr (NComp<T>::value == 1) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            v2d w = q[r];
+            v[2 * r] = w.x;
+            v[2 * r + 1] = w.y;
+        }
+    } else {
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+            v2d w = q[r];
+            v[r] = T{w.x, w.y};
+        }
+    }
+}
+
+template <class T>
+__global__ void __launch_bounds__(256) k_near_sym(int64_t nsb, const int32_t *__restrict__ sb_t,
+                                                  const int32_t *__restrict__ sb_s, int nl, int ld,
+                                                  const T *__restrict__ blocks, const T *__restrict__ x,
+                                                  T *__restrict__ part)
+{
+    extern __shared__ double sh[];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t k = (int64_t)blockIdx.x * (blockDim.x >> 6) + wave;
+    if (k >= nsb) return;  // whole waves only; no block-wide barrier follows
+    const int li = lane >> 3, lj = lane & 7;
+    const int64_t t = sb_t[k], sc = sb_s[k];
+    T *cacc = (T *)sh + (size_t)wave * (8 * ld + 512);  // [li][column]
+    T *rbuf = cacc + 8 * ld;                              // [lj][row of the tile]
+    const T *B = blocks + k * (int64_t)nl * ld;
+    const T *xt = x + t * nl, *xsrc = x + sc * nl;
+    T *prow = part + (size_t)(2 * k) * ld;
+    for (int rt = 0; rt < nl; rt += 64) {
+        const int r0 = rt + 8 * li;
+        T xr[8], ra[8];
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+            xr[r] = r0 + r < nl ? xt[r0 + r] : zero<T>();
+            ra[r] = zero<T>();
+        }
+        for (int c = lj; c < nl; c += 8) {
+            T cs = zero<T>();
+            if (r0 < ld) {
+                T v[8];
+                load8(B + (int64_t)c * ld + r0, v);
+                const T xc = xsrc[c];
+#pragma unroll
+                for (int r = 0; r < 8; ++r) {
+                    ra[r] += v[r] * xc;
+                    cs += v[r] * xr[r];
+                }
+            }
+            cacc[li * ld + c] = rt == 0 ? cs : cacc[li * ld + c] + cs;
+        }
+#pragma unroll
+        for (int r = 0; r < 8; ++r) rbuf[lj * 64 + 8 * li + r] = ra[r];
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        if (rt + lane < nl) {
+            T v = rbuf[lane];
+#pragma unroll
+            for (int q = 1; q < 8; ++q) v += rbuf[q * 64 + lane];
+            prow[rt + lane] = v;
+        }
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    }
+    if (t != sc) {
+        T *pcol = part + (size_t)(2 * k + 1) * ld;
+        for (int c = lane; c < nl; c += 64) {
+            T v = cacc[c];
+#pragma unroll
+            for (int q = 1; q < 8; ++q) v += cacc[q * ld + c];
+            pcol[c] = v;
+        }
+    }
+}
+
+// out[t*n + a] (t >= row0) = sum over the CSR entries e of row t, in order, of
+// part[pidx[e]*ld + a], times scale * w[(t*n + a)*4] when w is given (node
+// weights of the far field).  Four waves per row take every fourth entry; the
+// four partial sums are added in wave order.
+template <class T>
+__global__ void __launch_bounds__(256) k_gather(int n, int ld, const int64_t *__restrict__ ptr,
+                                                const int32_t *__restrict__ pidx, const T *__restrict__ part,
+                                                const double *__restrict__ w, double scale, T *__restrict__ out,
+                                                int64_t row0)
+{
+    extern __shared__ double sh[];
+    T *red = (T *)sh;  // [4][n]
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t t = row0 + blockIdx.x;
+    const int64_t k0 = ptr[t], k1 = ptr[t + 1];
+    for (int a = lane; a < n; a += 64) {
+        T acc = zero<T>();
+        for (int64_t e = k0 + wave; e < k1; e += 4) acc += part[(size_t)pidx[e] * ld + a];
+        red[wave * n + a] = acc;
+    }
+    __syncthreads();
+    for (int a = threadIdx.x; a < n; a += blockDim.x) {
+        T v = red[a] + red[n + a] + red[2 * n + a] + red[3 * n + a];
+        if (w) v = v * (scale * w[((size_t)t * n + a) * 4]);
+        out[(size_t)t * n + a] = v;
     }
 }
 
@@ -765,23 +902,6 @@ __global__ void __launch_bounds__(256) k_far_sym(int64_t nup, const int32_t *__r
 #pragma unroll
         for (int r = 1; r < 8; ++r) v += cb[r * W + i];
         pr[i] = v;
-    }
-}
-
-// Coupling result of every cluster t >= row0: the partial rows of its far
-// blocks (pidx[e] for CSR entry e) summed in CSR order, times the node weights
-// and the 1/(4 pi) of the kernel.  One wave per cluster.
-template <class T>
-__global__ void __launch_bounds__(64) k_far_gather(int q2, const int64_t *__restrict__ ptr,
-                                                   const int32_t *__restrict__ pidx, const T *__restrict__ part,
-                                                   const double *__restrict__ nodes, T *__restrict__ Yh, int64_t row0)
-{
-    const int64_t t = row0 + blockIdx.x;
-    const int64_t k0 = ptr[t], k1 = ptr[t + 1];
-    for (int i = threadIdx.x; i < q2; i += 64) {
-        T acc = zero<T>();
-        for (int64_t e = k0; e < k1; ++e) acc += part[(size_t)pidx[e] * q2 + i];
-        Yh[(size_t)t * q2 + i] = acc * (0.07957747154594767 * nodes[((size_t)t * q2 + i) * 4 + 3]);
     }
 }
 
@@ -1007,6 +1127,8 @@ struct DiagArgs {
     const int64_t *cl_off;
     const int64_t *near_ptr;
     const int32_t *near_src;
+    const int32_t *sb;  // stored near block of each CSR entry (-1: read the mirror transposed)
+    int ld;             // column stride of the stored near blocks
     const int64_t *far_ptr;
     const int32_t *far_src;
     const double *nodes;
@@ -1081,7 +1203,14 @@ __global__ void __launch_bounds__(256) k_diag(DiagArgs A, int64_t ndof, const T 
                 int ida = patch * n * n + ka2 * n + ka1, idb = patch * n * n + kb2 * n + kb1;
                 int64_t k = csr_find(A.near_ptr, A.near_src, ida, idb);
                 if (k < 0) continue;
-                const T *B = nearb + k * (int64_t)lo.nl * lo.nl;
+                int64_t kb = A.sb[k];
+                const bool tr = kb < 0;
+                if (tr) {
+                    int64_t km = csr_find(A.near_ptr, A.near_src, idb, ida);
+                    if (km < 0) continue;
+                    kb = A.sb[km];
+                }
+                const T *B = nearb + kb * (int64_t)lo.nl * A.ld;
                 // functions of the support in both leaves: loop over (row fa, col fb) pairs
                 for (int o = threadIdx.x; o < lo.nl * lo.nl; o += blockDim.x) {
                     int fb = o / lo.nl, fa = o % lo.nl;
@@ -1093,7 +1222,7 @@ __global__ void __launch_bounds__(256) k_diag(DiagArgs A, int64_t ndof, const T 
                     double ta = A.Tb[(ea1 * lo.P1 + ra % lo.P1) * lo.P1 + (j1 - ea1)] * A.Tb[(ea2 * lo.P1 + ra / lo.P1) * lo.P1 + (j2 - ea2)];
                     double tb = A.Tb[(eb1 * lo.P1 + rb % lo.P1) * lo.P1 + (j1 - eb1)] * A.Tb[(eb2 * lo.P1 + rb / lo.P1) * lo.P1 + (j2 - eb2)];
                     if (ta == 0.0 || tb == 0.0) continue;
-                    acc += B[o] * (ta * tb);
+                    acc += (tr ? B[(int64_t)fa * A.ld + fb] : B[(int64_t)fb * A.ld + fa]) * (ta * tb);
                 }
             }
     }
@@ -1270,6 +1399,14 @@ struct igb_operator {
     int64_t *near_ptr = nullptr;
     int32_t *near_src = nullptr;
     void *nearb = nullptr;
+    // near-field storage (see near_layout): stored block of every CSR entry,
+    // (t, s) of every stored block, partial-row index of every entry, partial rows
+    bool near_sym = false;
+    int near_ld = 0;
+    int64_t nsb = 0;
+    int32_t *sb = nullptr, *sb_t = nullptr, *sb_s = nullptr, *near_pidx = nullptr;
+    void *npart = nullptr;
+    std::vector<int32_t> sb_host;
     int64_t *far_ptr = nullptr;
     int32_t *far_src = nullptr, *far_tgt = nullptr;
     void *coup = nullptr;
@@ -1324,6 +1461,37 @@ static igb_status upload(igb_operator *op, P **dst, const void *src, size_t byte
 
 static inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
+// Near-field storage: symmetric (blocks t <= s only, column stride nl rounded up
+// to 8) when a wave's staging of k_near_sym fits 48 KB of LDS, else every
+// block (t, s) of the CSR list with column stride nl.
+struct NearLayout {
+    bool sym;
+    int ld;
+    int64_t nsb;
+};
+static NearLayout near_layout(const Setup &s, size_t esz)
+{
+    NearLayout L;
+    int ld8 = (s.nl + 7) & ~7;
+    L.sym = (size_t)(8 * ld8 + 512) * esz <= 48 * 1024;
+    L.ld = L.sym ? ld8 : s.nl;
+    L.nsb = 0;
+    if (L.sym) {
+        for (int64_t t = 0; t < (int64_t)s.near_ptr.size() - 1; ++t)
+            for (int64_t e = s.near_ptr[t]; e < s.near_ptr[t + 1]; ++e) L.nsb += s.near_src[e] >= t;
+    } else {
+        L.nsb = (int64_t)s.near_src.size();
+    }
+    return L;
+}
+
+static int64_t csr_find_host(const Setup &s, int t, int src)
+{
+    auto b = s.near_src.begin() + s.near_ptr[t], e = s.near_src.begin() + s.near_ptr[t + 1];
+    auto it = std::lower_bound(b, e, src);
+    return (it == e || *it != src) ? -1 : (int64_t)(it - s.near_src.begin());
+}
+
 // ---------------------------------------------------------------------------
 // template launchers
 // ---------------------------------------------------------------------------
@@ -1337,7 +1505,8 @@ static igb_status launch_regular_p(igb_operator *op, const PairRec *d_pairs, int
     for (int64_t off = 0; off < n; off += 1 << 20) {
         int64_t cnt = std::min<int64_t>(n - off, 1 << 20);
         hipLaunchKernelGGL((k_near_regular<T, P>), dim3((unsigned)cnt), dim3(128), shm, op->st, d_pairs + off, (int)cnt, g,
-                           gp, op->btab + (size_t)op->s.goff[g] * (P + 1), op->s.kappa, op->s.nl, (T *)op->nearb);
+                           gp, op->btab + (size_t)op->s.goff[g] * (P + 1), op->s.kappa, op->s.nl, op->near_ld, op->sb,
+                           (T *)op->nearb);
         LAUNCHCHK();
     }
     return IGB_OK;
@@ -1410,9 +1579,10 @@ static igb_status launch_singular(igb_operator *op, const PairRec *d, int64_t n)
 }
 
 // superspace matvec on internal vectors: ys = A xs.  When ev is given, ev[k]
-// is recorded on the operator's stream before stage k and ev[7] at the end:
+// is recorded on the operator's stream before stage k and ev[8] at the end:
 // stages 0 leaf moments, 1 upward, 2 coupling blocks, 3 coupling gather (on
-// the fly by mirrored pairs only), 4 downward, 5 near GEMV, 6 leaf back-moments.
+// the fly by mirrored pairs only), 4 downward, 5 near GEMV, 6 near gather
+// (symmetric near storage only), 7 leaf back-moments.
 template <class T, int TT>
 static void launch_far_sym(igb_operator *op, const T *Xh)
 {
@@ -1474,8 +1644,9 @@ static igb_status matvec_internal(igb_operator *op, const T *xs, T *ys, hipEvent
     }
     if ((rc = mark(3))) return rc;
     if (sym) {
-        hipLaunchKernelGGL((k_far_gather<T>), dim3((unsigned)nrows), dim3(64), 0, op->st, q2, op->far_ptr, op->far_pidx,
-                           (const T *)op->fpart, op->nodes, Yh, row0);
+        hipLaunchKernelGGL((k_gather<T>), dim3((unsigned)nrows), dim3(256), 4 * q2 * sizeof(T), op->st, q2, q2,
+                           op->far_ptr, op->far_pidx, (const T *)op->fpart, op->nodes + 3, 0.07957747154594767, Yh,
+                           row0);
         LAUNCHCHK();
     }
     if ((rc = mark(4))) return rc;
@@ -1488,17 +1659,32 @@ static igb_status matvec_internal(igb_operator *op, const T *xs, T *ys, hipEvent
         }
     }
     if ((rc = mark(5))) return rc;
-    hipLaunchKernelGGL((k_bsr_gemv<T, 0>), dim3(s.nleaf), dim3(256), 4 * s.nl * sizeof(T), op->st, s.nl, op->near_ptr,
-                       op->near_src, (const T *)op->nearb, xs, ys, (int64_t)0);
+    if (op->near_sym) {
+        const int ld = op->near_ld;
+        const size_t wave_lds = (size_t)(8 * ld + 512) * sizeof(T);
+        const int wpb = (int)std::max<size_t>(1, std::min<size_t>(4, (64 * 1024) / wave_lds));
+        hipLaunchKernelGGL((k_near_sym<T>), dim3((unsigned)((op->nsb + wpb - 1) / wpb)), dim3(64 * wpb), wpb * wave_lds,
+                           op->st, op->nsb, op->sb_t, op->sb_s, s.nl, ld, (const T *)op->nearb, xs, (T *)op->npart);
+    } else {
+        hipLaunchKernelGGL((k_bsr_gemv<T, 0>), dim3(s.nleaf), dim3(256), 4 * s.nl * sizeof(T), op->st, s.nl,
+                           op->near_ptr, op->near_src, (const T *)op->nearb, xs, ys, (int64_t)0);
+    }
     LAUNCHCHK();
     if ((rc = mark(6))) return rc;
+    if (op->near_sym) {
+        hipLaunchKernelGGL((k_gather<T>), dim3(s.nleaf), dim3(256), 4 * s.nl * sizeof(T), op->st, s.nl, op->near_ld,
+                           op->near_ptr, op->near_pidx, (const T *)op->npart, (const double *)nullptr, 1.0, ys,
+                           (int64_t)0);
+        LAUNCHCHK();
+    }
+    if ((rc = mark(7))) return rc;
     if (has_far) {
         size_t shm = (size_t)(q2 + q * s.n1) * sizeof(T);
         hipLaunchKernelGGL((k_leaf_back<T>), dim3(s.nleaf), dim3(64), shm, op->st, s.n1, q, s.side, s.p + 1, s.nloc, s.nl,
                            op->M1, (const T *)(Yh + s.cl_off[s.L] * q2), ys);
         LAUNCHCHK();
     }
-    return mark(7);
+    return mark(8);
 }
 
 template <class T>
@@ -1592,8 +1778,45 @@ static igb_status assemble(igb_operator *op)
     std::vector<PairRec> touch;
     std::string terr = check_touching(s, op->touch, &touch);
     if (!terr.empty()) return fail(IGB_EINVAL, terr);
-    // near-field blocks
-    op->near_bytes = (int64_t)s.near_src.size() * s.nl * s.nl * (int64_t)sizeof(T);
+    // near-field blocks: storage map, partial-row indices, zeroed storage
+    {
+        NearLayout NL = near_layout(s, sizeof(T));
+        op->near_sym = NL.sym;
+        op->near_ld = NL.ld;
+        op->nsb = NL.nsb;
+        int64_t nnear = (int64_t)s.near_src.size();
+        std::vector<int32_t> &sbh = op->sb_host;
+        sbh.assign(nnear, -1);
+        if (NL.sym) {
+            std::vector<int32_t> st, ss, pidx(nnear);
+            for (int t = 0; t < s.nleaf; ++t)
+                for (int64_t e = s.near_ptr[t]; e < s.near_ptr[t + 1]; ++e)
+                    if (s.near_src[e] >= t) {
+                        sbh[e] = (int32_t)st.size();
+                        st.push_back(t);
+                        ss.push_back(s.near_src[e]);
+                    }
+            for (int t = 0; t < s.nleaf; ++t)
+                for (int64_t e = s.near_ptr[t]; e < s.near_ptr[t + 1]; ++e) {
+                    int src = s.near_src[e];
+                    if (src >= t) {
+                        pidx[e] = 2 * sbh[e];
+                        continue;
+                    }
+                    int64_t m = csr_find_host(s, src, t);
+                    if (m < 0) return fail(IGB_EINVAL, "near-field partition is not symmetric");
+                    pidx[e] = 2 * sbh[m] + 1;
+                }
+            if ((rc = upload(op, &op->sb_t, st.data(), st.size() * sizeof(int32_t)))) return rc;
+            if ((rc = upload(op, &op->sb_s, ss.data(), ss.size() * sizeof(int32_t)))) return rc;
+            if ((rc = upload(op, &op->near_pidx, pidx.data(), pidx.size() * sizeof(int32_t)))) return rc;
+            if ((rc = dalloc(op, &op->npart, (size_t)2 * op->nsb * op->near_ld * sizeof(T)))) return rc;
+        } else {
+            for (int64_t e = 0; e < nnear; ++e) sbh[e] = (int32_t)e;
+        }
+        if ((rc = upload(op, &op->sb, sbh.data(), sbh.size() * sizeof(int32_t)))) return rc;
+    }
+    op->near_bytes = op->nsb * s.nl * op->near_ld * (int64_t)sizeof(T);
     if ((rc = dalloc(op, &op->nearb, op->near_bytes))) return rc;
     HIPCHK(hipMemsetAsync(op->nearb, 0, op->near_bytes, op->st));
     {
@@ -1612,7 +1835,8 @@ static igb_status assemble(igb_operator *op)
             for (int64_t off = 0; off < (int64_t)touch.size(); off += 1 << 20) {
                 int64_t cnt = std::min<int64_t>((int64_t)touch.size() - off, 1 << 20);
                 hipLaunchKernelGGL((k_scatter_pairs<T>), dim3((unsigned)cnt), dim3(256), 0, op->st, d + off, s.nloc, s.nl,
-                                   (const T *)op->pairbuf + off * s.nloc * s.nloc, (T *)op->nearb);
+                                   op->near_ld, op->sb, (const T *)op->pairbuf + off * s.nloc * s.nloc,
+                                   (T *)op->nearb);
                 LAUNCHCHK();
             }
         }
@@ -1646,6 +1870,8 @@ static igb_status assemble(igb_operator *op)
         A.cl_off = op->cl_off;
         A.near_ptr = op->near_ptr;
         A.near_src = op->near_src;
+        A.sb = op->sb;
+        A.ld = op->near_ld;
         A.far_ptr = op->far_ptr;
         A.far_src = op->far_src;
         A.nodes = op->nodes;
@@ -2225,11 +2451,18 @@ igb_status igb_export_near_block(const igb_operator *op, int32_t E, int32_t F, d
     };
     int elE, elF;
     int lE = leaf_of(E, elE), lF = leaf_of(F, elF);
-    auto b = s.near_src.begin() + s.near_ptr[lE], e = s.near_src.begin() + s.near_ptr[lE + 1];
-    auto it = std::lower_bound(b, e, lF);
-    if (it == e || *it != lF) return fail(IGB_EINVAL, "element pair is not in the near field");
-    int64_t k = it - s.near_src.begin();
-    size_t nb = (size_t)s.nl * s.nl;
+    int64_t e = csr_find_host(s, lE, lF);
+    if (e < 0) return fail(IGB_EINVAL, "element pair is not in the near field");
+    // a block that is not stored is read from its mirror, transposed
+    int64_t k = op->sb_host[e];
+    const bool tr = k < 0;
+    if (tr) {
+        int64_t m = csr_find_host(s, lF, lE);
+        if (m < 0 || op->sb_host[m] < 0) return fail(IGB_EINVAL, "near-field block storage is inconsistent");
+        k = op->sb_host[m];
+    }
+    const int ld = op->near_ld;
+    size_t nb = (size_t)s.nl * ld;
     std::vector<unsigned char> buf(nb * op->esz);
     HIPCHK(hipStreamSynchronize(op->st));
     HIPCHK(hipMemcpy(buf.data(), (const char *)op->nearb + k * nb * op->esz, nb * op->esz, hipMemcpyDeviceToHost));
@@ -2237,7 +2470,8 @@ igb_status igb_export_near_block(const igb_operator *op, int32_t E, int32_t F, d
     const double *B = (const double *)buf.data();
     for (int a = 0; a < s.nloc; ++a)
         for (int c = 0; c < s.nloc; ++c) {
-            int64_t pos = (int64_t)(elF * s.nloc + c) * s.nl + elE * s.nloc + a;
+            int64_t pos = tr ? (int64_t)(elE * s.nloc + a) * ld + elF * s.nloc + c
+                             : (int64_t)(elF * s.nloc + c) * ld + elE * s.nloc + a;
             for (int z = 0; z < nc; ++z) blk_host[(a * s.nloc + c) * nc + z] = B[pos * nc + z];
         }
     return IGB_OK;
@@ -2316,7 +2550,10 @@ static void fill_info(const Setup &s, size_t esz, igb_info *out)
     out->n_far_blocks = (int64_t)s.far_src.size();
     for (int c = 0; c < 4; ++c) out->n_pairs[c] = s.npairs_class[c];
     int64_t q2 = (int64_t)s.q * s.q, ncl = s.cl_off[s.L + 1];
-    out->near_bytes = out->n_near_blocks * s.nl * s.nl * (int64_t)esz;
+    {
+        NearLayout NL = near_layout(s, esz);
+        out->near_bytes = NL.nsb * s.nl * NL.ld * (int64_t)esz;
+    }
     out->coupling_bytes = s.mode == IGB_H2_STORED ? out->n_far_blocks * q2 * q2 * (int64_t)esz : 0;
     // one superspace matvec moves every stored block once, the S* vector in and
     // out, the moment vectors of all clusters, and (on the fly) the node data

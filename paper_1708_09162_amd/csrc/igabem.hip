@@ -177,42 +177,144 @@ __global__ void __launch_bounds__(128) k_near_regular(const PairRec *__restrict_
     }
 }
 
-__device__ inline void frame_map(int o, int a, int b, double s, double t, double &x, double &y)
+// 1/sqrt(r2) for finite r2 > 0: the hardware estimate refined by the
+// second-order expansion of (1 - e)^(-1/2) = 1 + e/2 + 3e^2/8, e = 1 - r2 y^2.
+__device__ inline double rsqrt_pos(double r2)
+{
+    double y = __builtin_amdgcn_rsq(r2);
+    double e = fma(-r2 * y, y, 1.0);
+    return fma(y * e, fma(e, 0.375, 0.5), y);
+}
+
+// Partial contraction of a rational Bezier tile of bidegree (PG, PG) at a
+// fixed value f of one parameter.  M holds the homogeneous control points with
+// the contracted parameter fastest, M[(k*(PG+1) + l)*4 + c]: the tile itself
+// (l along u) to fix u, its transpose (l along v) to fix v.  Returns
+// A[k] = sum_l B_l(f) M[k][l] and dA[k] = sum_l B'_l(f) M[k][l], k along the
+// parameter that remains free.
+template <int PG>
+__device__ inline void tile_fix(const double *M, double f, double A[PG + 1][4], double dA[PG + 1][4])
+{
+    constexpr int G1 = PG + 1;
+    double B[G1], dB[G1];
+    bernstein_d_t<PG>(f, B, dB);
+#pragma unroll
+    for (int k = 0; k < G1; ++k)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            double x = 0.0, d = 0.0;
+#pragma unroll
+            for (int l = 0; l < G1; ++l) {
+                const double h = M[(k * G1 + l) * 4 + c];
+                x += B[l] * h;
+                d += dB[l] * h;
+            }
+            A[k][c] = x;
+            dA[k][c] = d;
+        }
+}
+
+// Point and surface measure of the tile at value w of the remaining parameter,
+// from its partial contraction (the measure |X_u x X_v| does not depend on the
+// order of the two tangents).
+template <int PG>
+__device__ inline void tile_line_point(const double A[PG + 1][4], const double dA[PG + 1][4], double w, double X[3],
+                                       double *kap)
+{
+    constexpr int G1 = PG + 1;
+    double B[G1], dB[G1];
+    bernstein_d_t<PG>(w, B, dB);
+    double S[4] = {0, 0, 0, 0}, D1[4] = {0, 0, 0, 0}, D2[4] = {0, 0, 0, 0};
+#pragma unroll
+    for (int k = 0; k < G1; ++k)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            S[c] += B[k] * A[k][c];
+            D1[c] += dB[k] * A[k][c];
+            D2[c] += B[k] * dA[k][c];
+        }
+    const double iw = 1.0 / S[3];
+    const double x0 = S[0] * iw, x1 = S[1] * iw, x2 = S[2] * iw;
+    const double a0 = (D1[0] - x0 * D1[3]) * iw, a1 = (D1[1] - x1 * D1[3]) * iw, a2 = (D1[2] - x2 * D1[3]) * iw;
+    const double b0 = (D2[0] - x0 * D2[3]) * iw, b1 = (D2[1] - x1 * D2[3]) * iw, b2 = (D2[2] - x2 * D2[3]) * iw;
+    X[0] = x0;
+    X[1] = x1;
+    X[2] = x2;
+    const double n0 = a1 * b2 - a2 * b1, n1 = a2 * b0 - a0 * b2, n2 = a0 * b1 - a1 * b0;
+    *kap = sqrt(n0 * n0 + n1 * n1 + n2 * n2);
+}
+
+// One element's reference point along a quadrature line: (u, v) = (u0, v0) +
+// w (du, dv), where only the coordinate that is not fixed moves (fix_u: u
+// stays u0).  For a canonical frame (o, a, b) and local (s, t) = (s0, t0) +
+// w (ds, dt) with only s or only t moving.
+struct Line {
+    double u0, v0, du, dv;
+};
+
+__device__ inline Line frame_line(int o, int a, int b, double s0, double ds, double t0, double dt)
 {
     const double cx[4] = {0.0, 1.0, 1.0, 0.0}, cy[4] = {0.0, 0.0, 1.0, 1.0};
-    x = cx[o] + s * (cx[a] - cx[o]) + t * (cx[b] - cx[o]);
-    y = cy[o] + s * (cy[a] - cy[o]) + t * (cy[b] - cy[o]);
+    const double xa = cx[a] - cx[o], ya = cy[a] - cy[o], xb = cx[b] - cx[o], yb = cy[b] - cy[o];
+    return Line{cx[o] + s0 * xa + t0 * xb, cy[o] + s0 * ya + t0 * yb, ds * xa + dt * xb, ds * ya + dt * yb};
+}
+
+// Whether u stays fixed along the line when the moving local coordinate is s
+// (move_s) or t of the frame (o, a, b).
+__device__ inline bool frame_fix_u(int o, int a, int b, bool move_s)
+{
+    const double cx[4] = {0.0, 1.0, 1.0, 0.0};
+    return (move_s ? cx[a] : cx[b]) == cx[o];
+}
+
+// Value of the neighbouring lane of the pair (lane ^ 1), by DPP quad_perm [1,0,3,2].
+__device__ inline double from_pair_lane(double v)
+{
+    const int lo = __double2loint(v), hi = __double2hiint(v);
+    const int plo = __builtin_amdgcn_update_dpp(0, lo, 0xB1, 0xF, 0xF, false);
+    const int phi = __builtin_amdgcn_update_dpp(0, hi, 0xB1, 0xF, 0xF, false);
+    return __hiloint2double(phi, plo);
 }
 
 // Touching pairs (identical / common edge / common vertex): regularising
 // Duffy-type substitutions of [0,1]^4 (8 / 6 / 4 regions), Gauss of order gs
-// per variable.  One workgroup per pair; every lane forms one quadrature
-// point (geometry of both elements, weighted kernel value, Bernstein vectors),
-// each wave stages its 64 points in LDS and accumulates the nloc x nloc block
+// per variable.  One workgroup per pair.  A line of the rule has its first
+// three variables (xi and two more) fixed and the fourth running over its gs
+// nodes; along a line each element's reference point moves in one parameter
+// only (in the vertex case the point of E does not move at all).  Every pair
+// of lanes (2k, 2k+1) owns one line, lane 2k element E and lane 2k+1 element
+// F: the lane contracts its tile once over the fixed parameter and then
+// evaluates the points of the line at the cost of a curve.  Lane 2k receives
+// the point of F from its neighbour, forms the weighted kernel value and the
+// row of E's Bernstein products; lane 2k+1 forms the row of F's.  A wave
+// stages its 32 points in LDS and accumulates the nloc x nloc block
 // B += U^T V with FP64 MFMA (v_mfma_f64_16x16x4f64: 4 points per step),
 // complex kernels as two real accumulations.  Waves are reduced through LDS
 // at the end.
 typedef double v4d __attribute__((ext_vector_type(4)));
 
 template <class T, int P, int PG, int WAVES>
-__global__ void __launch_bounds__(64 * WAVES, NComp<T>::value == 1 ? 3 : 1) k_near_singular(
+__global__ void __launch_bounds__(64 * WAVES, NComp<T>::value == 1 ? 2 : 1) k_near_singular(
     const PairRec *__restrict__ pairs, int gs, const double *__restrict__ gxs, const double *__restrict__ gws,
-    const double *__restrict__ tiles, double kappa, T *__restrict__ pairbuf)
+    const double *__restrict__ tiles, const double *__restrict__ tilesT, double kappa, T *__restrict__ pairbuf)
 {
     constexpr int P1 = P + 1, NLOC = P1 * P1, NT = (NLOC + 15) / 16, NPAD = 16 * NT;
     constexpr int NC = NComp<T>::value;
-    constexpr int TS = (PG + 1) * (PG + 1) * 4;
-    constexpr int HALF = 32;                        // points staged per half-batch
-    constexpr int STAGE = HALF * (NC + 1) * NPAD;  // doubles per wave
+    constexpr int G1 = PG + 1, TS = G1 * G1 * 4;
+    constexpr int HALF = 32;                        // points staged per step
+    // staging rows of RS = NPAD + 1 doubles, V after U with an 8-double shift:
+    // the 16 lanes of a pass write and read 16 different 8-byte bank pairs
+    constexpr int RS = NPAD + 1;
+    constexpr int STAGE = HALF * (NC + 1) * RS + 8;  // doubles per wave
     extern __shared__ double sh[];
     double *nx = sh, *nw = nx + 64;
     double *stg = nw + 64;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    double *Ub = stg + wave * STAGE;     // [NC][HALF][NPAD]
-    double *Vb = Ub + NC * HALF * NPAD;  // [HALF][NPAD]
+    double *Ub = stg + wave * STAGE;       // [NC][HALF][RS]
+    double *Vb = Ub + NC * HALF * RS + 8;  // [HALF][RS]
     const PairRec R = pairs[blockIdx.x];
-    // tiles are read through the scalar cache (uniform addresses, SGPR operands)
-    const double *tEg = tiles + (size_t)R.E * TS, *tFg = tiles + (size_t)R.F * TS;
+    const int role = lane & 1, pl = lane >> 1;  // role 0: element E, 1: element F; pl: point slot
+    const int elem = role ? R.F : R.E;
     for (int k = threadIdx.x; k < gs; k += blockDim.x) {
         nx[k] = gxs[k];
         nw[k] = gws[k];
@@ -221,15 +323,14 @@ __global__ void __launch_bounds__(64 * WAVES, NComp<T>::value == 1 ? 3 : 1) k_ne
         for (int k = lane; k < HALF * (NPAD - NLOC); k += 64) {
             int pt = k / (NPAD - NLOC), a = NLOC + k % (NPAD - NLOC);
 #pragma unroll
-            for (int c = 0; c < NC; ++c) Ub[c * HALF * NPAD + pt * NPAD + a] = 0.0;
-            Vb[pt * NPAD + a] = 0.0;
+            for (int c = 0; c < NC; ++c) Ub[c * HALF * RS + pt * RS + a] = 0.0;
+            Vb[pt * RS + a] = 0.0;
         }
     }
     __syncthreads();
-    const int g2 = gs * gs, g4 = g2 * g2;
+    const int g = gs, g2 = g * g, g3 = g2 * g;
     const int nreg = R.cls == 1 ? 8 : (R.cls == 2 ? 6 : 4);
-    const int npts = nreg * g4;
-    const int niter = (npts + 64 * WAVES - 1) / (64 * WAVES);
+    const int chunks = (g3 + HALF - 1) / HALF;
     v4d acc[2][NC][NT][NT];
 #pragma unroll
     for (int h = 0; h < 2; ++h)
@@ -240,75 +341,114 @@ __global__ void __launch_bounds__(64 * WAVES, NComp<T>::value == 1 ? 3 : 1) k_ne
 #pragma unroll
                 for (int j = 0; j < NT; ++j) acc[h][c][i][j] = v4d{0.0, 0.0, 0.0, 0.0};
     const int col = lane & 15, sub = lane >> 4;
-    for (int it = 0; it < niter; ++it) {
-        int idx = (it * WAVES + wave) * 64 + lane;
-        // inactive lanes: two distinct points and zero weight
-        double xs = 0.25, xt = 0.25, ys = 0.75, yt = 0.75, W = 0.0;
-        if (idx < npts) {
-            int reg = idx / g4, rem = idx - reg * g4;
-            int ia = rem / (g2 * gs), ib = (rem / g2) % gs, ic = (rem / gs) % gs, id = rem % gs;
-            double va = nx[ia], vb = nx[ib], vc = nx[ic], vd = nx[id];
-            W = nw[ia] * nw[ib] * nw[ic] * nw[id];
+    for (int unit = wave; unit < nreg * chunks; unit += WAVES) {
+        const int reg = unit / chunks, line = (unit - reg * chunks) * HALF + pl;
+        // the pair's line: fixed nodes (ia, ib, ic), weight Wl of the fixed part;
+        // inactive lines get two distinct fixed points and zero weight
+        Line LE{0.25, 0.25, 0.0, 0.0}, LF{0.75, 0.75, 0.0, 0.0};
+        double Wl = 0.0;
+        bool fixE_u = true, fixF_u = true, constE = false;
+        {
+            const bool valid = line < g3;
+            const int ln = valid ? line : 0;
+            const int ia = ln / g2, ib = (ln / g) % g, ic = ln % g;
+            const double va = nx[ia], vb = nx[ib], vc = nx[ic], w3 = nw[ia] * nw[ib] * nw[ic];
             if (R.cls == 1) {
-                int sg1 = reg & 1, sg2 = (reg >> 1) & 1, tri = reg >> 2;
-                double xi = va, eta = vb;
-                double z1 = tri == 0 ? xi : xi * eta, z2 = tri == 0 ? xi * eta : xi;
-                if (sg1 == 0) { xs = (1 - z1) * vc; ys = xs + z1; } else { ys = (1 - z1) * vc; xs = ys + z1; }
-                if (sg2 == 0) { xt = (1 - z2) * vd; yt = xt + z2; } else { yt = (1 - z2) * vd; xt = yt + z2; }
-                W *= xi * (1 - z1) * (1 - z2);
+                // identical: (x1 - y1, x2 - y2) = (+-z1, +-z2); x1, y1 fixed, x2, y2 move with the 4th node
+                const int sg1 = reg & 1, sg2 = (reg >> 1) & 1, tri = reg >> 2;
+                const double xi = va, eta = vb;
+                const double z1 = tri == 0 ? xi : xi * eta, z2 = tri == 0 ? xi * eta : xi;
+                const double lo1 = (1 - z1) * vc;
+                const double xs = sg1 == 0 ? lo1 : lo1 + z1, ys = sg1 == 0 ? lo1 + z1 : lo1;
+                if (valid) {
+                    LE = Line{xs, sg2 == 0 ? 0.0 : z2, 0.0, 1 - z2};
+                    LF = Line{ys, sg2 == 0 ? z2 : 0.0, 0.0, 1 - z2};
+                    Wl = w3 * xi * (1 - z1) * (1 - z2);
+                }
             } else if (R.cls == 2) {
-                int sg = reg & 1, pyr = reg >> 1;
-                double xi = va, e1 = vb, e2 = vc, sv = vd;
+                // common edge: local s moves with the 4th node, t is fixed
+                const int sg = reg & 1, pyr = reg >> 1;
+                const double xi = va, e1 = vb, e2 = vc;
                 double zz, ct, dt;
                 if (pyr == 0) { zz = xi; ct = xi * e1; dt = xi * e2; }
                 else if (pyr == 1) { ct = xi; zz = xi * e1; dt = xi * e2; }
                 else { dt = xi; zz = xi * e1; ct = xi * e2; }
-                double cs, ds;
-                if (sg == 0) { cs = (1 - zz) * sv; ds = cs + zz; } else { ds = (1 - zz) * sv; cs = ds + zz; }
-                W *= xi * xi * (1 - zz);
-                frame_map(R.oE, R.aE, R.bE, cs, ct, xs, xt);
-                frame_map(R.oF, R.aF, R.bF, ds, dt, ys, yt);
+                const double cs0 = sg == 0 ? 0.0 : zz, ds0 = sg == 0 ? zz : 0.0;
+                fixE_u = frame_fix_u(R.oE, R.aE, R.bE, true);
+                fixF_u = frame_fix_u(R.oF, R.aF, R.bF, true);
+                if (valid) {
+                    LE = frame_line(R.oE, R.aE, R.bE, cs0, 1 - zz, ct, 0.0);
+                    LF = frame_line(R.oF, R.aF, R.bF, ds0, 1 - zz, dt, 0.0);
+                    Wl = w3 * xi * xi * (1 - zz);
+                }
             } else {
-                double xi = va;
-                double v0 = reg == 0 ? xi : xi * vb;
-                double v1 = reg == 1 ? xi : xi * (reg == 0 ? vb : vc);
-                double v2 = reg == 2 ? xi : xi * (reg == 3 ? vd : vc);
-                double v3 = reg == 3 ? xi : xi * vd;
-                W *= xi * xi * xi;
-                frame_map(R.oE, R.aE, R.bE, v0, v1, xs, xt);
-                frame_map(R.oF, R.aF, R.bF, v2, v3, ys, yt);
+                // common vertex: E's point is fixed on the line, F's moves in s (region 3) or t
+                const double xi = va;
+                const double v0 = reg == 0 ? xi : xi * vb;
+                const double v1 = reg == 1 ? xi : xi * (reg == 0 ? vb : vc);
+                constE = true;
+                fixF_u = frame_fix_u(R.oF, R.aF, R.bF, reg == 3);
+                if (valid) {
+                    LE = frame_line(R.oE, R.aE, R.bE, v0, 0.0, v1, 0.0);
+                    if (reg == 3) LF = frame_line(R.oF, R.aF, R.bF, 0.0, xi, xi, 0.0);
+                    else LF = frame_line(R.oF, R.aF, R.bF, reg == 2 ? xi : xi * vc, 0.0, 0.0, xi);
+                    Wl = w3 * xi * xi * xi;
+                }
             }
         }
-        // an opaque zero offset (in a scalar register) keeps the tile reads inside
-        // the loop: hoisting both tiles would cost 4 (PG+1)^2 registers each
-        int zoff = 0;
-        asm volatile("" : "+s"(zoff));
-        double X[3], Yp[3], kx, ky;
-        tile_point_t<PG>(tEg + zoff, xs, xt, X, &kx);
-        tile_point_t<PG>(tFg + zoff, ys, yt, Yp, &ky);
-        double d0 = X[0] - Yp[0], d1 = X[1] - Yp[1], d2 = X[2] - Yp[2];
-        T c = green<T>(sqrt(d0 * d0 + d1 * d1 + d2 * d2), kappa) * (W * kx * ky);
-        double bx1[P1], bx2[P1], by1[P1], by2[P1];
-        bernstein_t<P>(xs, bx1);
-        bernstein_t<P>(xt, bx2);
-        bernstein_t<P>(ys, by1);
-        bernstein_t<P>(yt, by2);
-        const double cre = re_(c), cim = im_(c);
-        // two half-batches of 32 points: stage, then 8 MFMA steps of 4 points each
-#pragma unroll
-        for (int hb = 0; hb < 2; ++hb) {
-            if ((lane >> 5) == hb) {
-                const int pl = lane & 31;
-#pragma unroll
-                for (int a2 = 0; a2 < P1; ++a2)
-#pragma unroll
-                    for (int a1 = 0; a1 < P1; ++a1) {
-                        double fx = bx1[a1] * bx2[a2];
-                        Ub[pl * NPAD + a2 * P1 + a1] = cre * fx;
-                        if constexpr (NC == 2) Ub[HALF * NPAD + pl * NPAD + a2 * P1 + a1] = cim * fx;
-                        Vb[pl * NPAD + a2 * P1 + a1] = by1[a1] * by2[a2];
-                    }
+        // this lane's element along the line
+        const Line L = role ? LF : LE;
+        const bool fix_u = role ? fixF_u : fixE_u;
+        const bool cst = role == 0 && constE;
+        const double f = fix_u ? L.u0 : L.v0;
+        double A[G1][4], dA[G1][4];
+        tile_fix<PG>((fix_u ? tiles : tilesT) + (size_t)elem * TS, f, A, dA);
+        double bf[P1], bm[P1], X[3], kap = 0.0;
+        bernstein_t<P>(f, bf);
+        if (cst) {  // vertex, element E: one point for the whole line
+            const double wv = fix_u ? L.v0 : L.u0;
+            tile_line_point<PG>(A, dA, wv, X, &kap);
+            bernstein_t<P>(wv, bm);
+        }
+        for (int id = 0; id < g; ++id) {
+            const double w = nx[id];
+            if (!cst) {
+                const double wv = fix_u ? L.v0 + L.dv * w : L.u0 + L.du * w;
+                tile_line_point<PG>(A, dA, wv, X, &kap);
+                bernstein_t<P>(wv, bm);
             }
+            // lane 2k: the point of F from lane 2k+1, the weighted kernel value
+            const double Y0 = from_pair_lane(X[0]), Y1 = from_pair_lane(X[1]), Y2 = from_pair_lane(X[2]);
+            const double ky = from_pair_lane(kap);
+            const double d0 = X[0] - Y0, d1 = X[1] - Y1, d2 = X[2] - Y2;
+            const double r2 = d0 * d0 + d1 * d1 + d2 * d2;
+            const double ir = rsqrt_pos(r2);
+            const double f0 = 0.07957747154594767 * ir * (Wl * nw[id] * kap * ky);
+            double cre = f0, cim = 0.0;
+            if constexpr (NC == 2) {
+                double sn, cs;
+                sincos(kappa * (r2 * ir), &sn, &cs);
+                cre = cs * f0;
+                cim = sn * f0;
+            }
+            if (role) cre = 1.0;  // lane 2k+1 stages F's Bernstein products unweighted
+            // u / v Bernstein vectors of this lane's element
+            double b1[P1], b2[P1];
+#pragma unroll
+            for (int a = 0; a < P1; ++a) {
+                b1[a] = fix_u ? bf[a] : bm[a];
+                b2[a] = fix_u ? bm[a] : bf[a];
+            }
+            double *dst = (role ? Vb : Ub) + pl * RS;
+#pragma unroll
+            for (int a2 = 0; a2 < P1; ++a2)
+#pragma unroll
+                for (int a1 = 0; a1 < P1; ++a1) {
+                    const double fx = b1[a1] * b2[a2];
+                    dst[a2 * P1 + a1] = cre * fx;
+                    if constexpr (NC == 2)
+                        if (!role) Ub[HALF * RS + pl * RS + a2 * P1 + a1] = cim * fx;
+                }
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
 #pragma unroll
@@ -316,12 +456,12 @@ __global__ void __launch_bounds__(64 * WAVES, NComp<T>::value == 1 ? 3 : 1) k_ne
                 const int pt = 4 * j + sub;
                 double bv[NT];
 #pragma unroll
-                for (int tb = 0; tb < NT; ++tb) bv[tb] = Vb[pt * NPAD + 16 * tb + col];
+                for (int tb = 0; tb < NT; ++tb) bv[tb] = Vb[pt * RS + 16 * tb + col];
 #pragma unroll
                 for (int c2 = 0; c2 < NC; ++c2)
 #pragma unroll
                     for (int ta = 0; ta < NT; ++ta) {
-                        double av = Ub[c2 * HALF * NPAD + pt * NPAD + 16 * ta + col];
+                        double av = Ub[c2 * HALF * RS + pt * RS + 16 * ta + col];
 #pragma unroll
                         for (int tb = 0; tb < NT; ++tb)
                             acc[j & 1][c2][ta][tb] =
@@ -627,8 +767,8 @@ __global__ void __launch_bounds__(256) k_near_sym(int64_t nsb, const int32_t *__
     if (k >= nsb) return;  // whole waves only; no block-wide barrier follows
     const int li = lane >> 3, lj = lane & 7;
     const int64_t t = sb_t[k], sc = sb_s[k];
-    T *cacc = (T *)sh + (size_t)wave * (8 * ld + 512);  // [li][column]
-    T *rbuf = cacc + 8 * ld;                              // [lj][row of the tile]
+    T *cacc = (T *)sh + (size_t)wave * (8 * ld + 520);  // [li][column]
+    T *rbuf = cacc + 8 * ld;                              // [lj][row of the tile], row stride 65
     const T *B = blocks + k * (int64_t)nl * ld;
     const T *xt = x + t * nl, *xsrc = x + sc * nl;
     T *prow = part + (size_t)(2 * k) * ld;
@@ -655,13 +795,13 @@ __global__ void __launch_bounds__(256) k_near_sym(int64_t nsb, const int32_t *__
             cacc[li * ld + c] = rt == 0 ? cs : cacc[li * ld + c] + cs;
         }
 #pragma unroll
-        for (int r = 0; r < 8; ++r) rbuf[lj * 64 + 8 * li + r] = ra[r];
+        for (int r = 0; r < 8; ++r) rbuf[lj * 65 + 8 * li + r] = ra[r];
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
         if (rt + lane < nl) {
             T v = rbuf[lane];
 #pragma unroll
-            for (int q = 1; q < 8; ++q) v += rbuf[q * 64 + lane];
+            for (int q = 1; q < 8; ++q) v += rbuf[q * 65 + lane];
             prow[rt + lane] = v;
         }
         __builtin_amdgcn_wave_barrier();
@@ -789,15 +929,6 @@ __global__ void __launch_bounds__(256) k_far_onthefly(int q2, const int64_t *__r
     }
 }
 
-// 1/sqrt(r2) for finite r2 > 0: the hardware estimate refined by the
-// second-order expansion of (1 - e)^(-1/2) = 1 + e/2 + 3e^2/8, e = 1 - r2 y^2.
-__device__ inline double rsqrt_pos(double r2)
-{
-    double y = __builtin_amdgcn_rsq(r2);
-    double e = fma(-r2 * y, y, 1.0);
-    return fma(y * e, fma(e, 0.375, 0.5), y);
-}
-
 // Far field generated on the fly, once per mirrored pair of coupling blocks
 // (Sec. 4.2): G is symmetric, so the block of (s, t) is the transpose of the
 // block of (t, s) and one evaluation of G(x_i, y_j) serves both products.
@@ -813,7 +944,8 @@ __global__ void __launch_bounds__(256) k_far_sym(int64_t nup, const int32_t *__r
                                                  double kappa, T *__restrict__ part)
 {
     constexpr int W = 8 * TT;  // padded nodes per cluster
-    __shared__ T buf[4][8 * W];
+    constexpr int WS = W + 1;  // LDS row stride (spreads the 8 rows over the banks)
+    __shared__ T buf[4][8 * WS];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int64_t k = (int64_t)blockIdx.x * 4 + wave;
     if (k >= nup) return;  // whole waves only; no block-wide barrier follows
@@ -879,7 +1011,7 @@ __global__ void __launch_bounds__(256) k_far_sym(int64_t nup, const int32_t *__r
                 csum += g * wt[ii];
             }
         }
-        cb[li * W + j] = csum;
+        cb[li * WS + j] = csum;
     }
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
@@ -887,20 +1019,20 @@ __global__ void __launch_bounds__(256) k_far_sym(int64_t nup, const int32_t *__r
     for (int j = lane; j < q2; j += 64) {
         T v = cb[j];
 #pragma unroll
-        for (int r = 1; r < 8; ++r) v += cb[r * W + j];
+        for (int r = 1; r < 8; ++r) v += cb[r * WS + j];
         pc[j] = v;
     }
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
 #pragma unroll
-    for (int ii = 0; ii < TT; ++ii) cb[lj * W + li * TT + ii] = racc[ii];
+    for (int ii = 0; ii < TT; ++ii) cb[lj * WS + li * TT + ii] = racc[ii];
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
     T *pr = part + (size_t)(2 * k) * q2;
     for (int i = lane; i < q2; i += 64) {
         T v = cb[i];
 #pragma unroll
-        for (int r = 1; r < 8; ++r) v += cb[r * W + i];
+        for (int r = 1; r < 8; ++r) v += cb[r * WS + i];
         pr[i] = v;
     }
 }
@@ -1385,6 +1517,7 @@ struct igb_operator {
     int lmin = 0;  // coarsest level with far blocks (L+1 if none)
     // device data
     double *tiles = nullptr;
+    double *tilesT = nullptr;  // each tile with its two parameters exchanged
     int32_t *tdeg = nullptr;
     double *gx = nullptr, *gw = nullptr;
     double *btab = nullptr;        // per order n: n*(p+1) Bernstein values, offset goff[n]*(p+1)
@@ -1473,7 +1606,7 @@ static NearLayout near_layout(const Setup &s, size_t esz)
 {
     NearLayout L;
     int ld8 = (s.nl + 7) & ~7;
-    L.sym = (size_t)(8 * ld8 + 512) * esz <= 48 * 1024;
+    L.sym = (size_t)(8 * ld8 + 520) * esz <= 48 * 1024;
     L.ld = L.sym ? ld8 : s.nl;
     L.nsb = 0;
     if (L.sym) {
@@ -1516,7 +1649,7 @@ template <class T, int P, int PG>
 static igb_status launch_singular_pg(igb_operator *op, const PairRec *d_pairs, int64_t n)
 {
     constexpr int NLOC = (P + 1) * (P + 1), NPAD = 16 * ((NLOC + 15) / 16), NC = NComp<T>::value;
-    constexpr int STAGE_BYTES = 32 * (NC + 1) * NPAD * 8;
+    constexpr int STAGE_BYTES = (32 * (NC + 1) * (NPAD + 1) + 8) * 8;
     constexpr int WAVES = 4;
     // the final reduction reuses the stage: it needs WAVES * NC * NPAD^2 doubles
     constexpr size_t RED_BYTES = (size_t)WAVES * NC * NPAD * NPAD * 8;
@@ -1529,7 +1662,8 @@ static igb_status launch_singular_pg(igb_operator *op, const PairRec *d_pairs, i
     for (int64_t off = 0; off < n; off += 1 << 20) {
         int64_t cnt = std::min<int64_t>(n - off, 1 << 20);
         hipLaunchKernelGGL((k_near_singular<T, P, PG, WAVES>), dim3((unsigned)cnt), dim3(64 * WAVES), shm, op->st,
-                           d_pairs + off, gs, op->gx + op->s.goff[gs], op->gw + op->s.goff[gs], op->tiles, op->s.kappa,
+                           d_pairs + off, gs, op->gx + op->s.goff[gs], op->gw + op->s.goff[gs], op->tiles, op->tilesT,
+                           op->s.kappa,
                            (T *)op->pairbuf + off * NLOC * NLOC);
         LAUNCHCHK();
     }
@@ -1661,7 +1795,7 @@ static igb_status matvec_internal(igb_operator *op, const T *xs, T *ys, hipEvent
     if ((rc = mark(5))) return rc;
     if (op->near_sym) {
         const int ld = op->near_ld;
-        const size_t wave_lds = (size_t)(8 * ld + 512) * sizeof(T);
+        const size_t wave_lds = (size_t)(8 * ld + 520) * sizeof(T);
         const int wpb = (int)std::max<size_t>(1, std::min<size_t>(4, (64 * 1024) / wave_lds));
         hipLaunchKernelGGL((k_near_sym<T>), dim3((unsigned)((op->nsb + wpb - 1) / wpb)), dim3(64 * wpb), wpb * wave_lds,
                            op->st, op->nsb, op->sb_t, op->sb_s, s.nl, ld, (const T *)op->nearb, xs, (T *)op->npart);
@@ -1893,6 +2027,17 @@ static igb_status create_device_geometry(igb_operator *op)
     size_t esz = op->esz;
     int q2 = s.q * s.q;
     if ((rc = upload(op, &op->tiles, s.tiles.data(), s.tiles.size() * sizeof(double)))) return rc;
+    {
+        const int G1 = s.tile_degree + 1;
+        std::vector<double> tt(s.tiles.size());
+        for (int64_t E = 0; E < s.nelem; ++E)
+            for (int j = 0; j < G1; ++j)
+                for (int i = 0; i < G1; ++i)
+                    for (int c = 0; c < 4; ++c)
+                        tt[(size_t)E * s.tile_stride + (i * G1 + j) * 4 + c] =
+                            s.tiles[(size_t)E * s.tile_stride + (j * G1 + i) * 4 + c];
+        if ((rc = upload(op, &op->tilesT, tt.data(), tt.size() * sizeof(double)))) return rc;
+    }
     if ((rc = upload(op, &op->tdeg, s.tile_deg.data(), s.tile_deg.size() * sizeof(int32_t)))) return rc;
     if ((rc = upload(op, &op->gx, s.gx.data(), s.gx.size() * sizeof(double)))) return rc;
     if ((rc = upload(op, &op->gw, s.gw.data(), s.gw.size() * sizeof(double)))) return rc;

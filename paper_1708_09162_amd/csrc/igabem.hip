@@ -1267,26 +1267,47 @@ struct DiagArgs {
     double kappa;
 };
 
+// Kernel value from |d|^2 and 1/|d| (Sec. 3.1 fundamental solutions).
+template <class T> __device__ inline T green_ir(double r2, double ir, double kappa);
+template <> __device__ inline double green_ir<double>(double, double ir, double) { return 0.07957747154594767 * ir; }
+template <> __device__ inline cd green_ir<cd>(double r2, double ir, double kappa)
+{
+    double sn, cs;
+    sincos(kappa * (r2 * ir), &sn, &cs);
+    const double f = 0.07957747154594767 * ir;
+    return {cs * f, sn * f};
+}
+
+// One workgroup per B-spline function i (patch, j1, j2); its support is the
+// element window [lo1, hi1] x [lo2, hi2].  Far field: at every level, the
+// moments of t_i on the clusters meeting the support, then for every
+// admissible pair of those clusters (each unordered pair once: the coupling
+// kernel is symmetric) the q^2 x q^2 coupling product, one (pair, column)
+// work item per thread.  Near field: the superspace functions of the support
+// elements with their weights in t_i (zero weights included, in a fixed
+// order), and for every pair of them the stored near-field entry (blocks read
+// through the symmetric storage map).  Fixed summation order throughout.
 template <class T>
 __global__ void __launch_bounds__(256) k_diag(DiagArgs A, int64_t ndof, const T *__restrict__ nearb,
                                               const T *__restrict__ coup, T *__restrict__ D)
 {
     extern __shared__ double sh[];
     __shared__ T red[256];
+    __shared__ unsigned char ff[4096];
     const Layout &lo = A.lo;
-    int q = A.q, q2 = q * q;
-    int64_t i = blockIdx.x;
-    int nn = lo.ns1 * lo.ns1;
-    int patch = (int)(i / nn), rr = (int)(i % nn), j2 = rr / lo.ns1, j1 = rr % lo.ns1;
-    int lo1 = j1 - lo.p < 0 ? 0 : j1 - lo.p, hi1 = j1 < lo.ne - 1 ? j1 : lo.ne - 1;
-    int lo2 = j2 - lo.p < 0 ? 0 : j2 - lo.p, hi2 = j2 < lo.ne - 1 ? j2 : lo.ne - 1;
+    const int q = A.q, q2 = q * q, P1 = lo.P1;
+    const int64_t i = blockIdx.x;
+    const int nn = lo.ns1 * lo.ns1;
+    const int patch = (int)(i / nn), rr = (int)(i % nn), j2 = rr / lo.ns1, j1 = rr % lo.ns1;
+    const int lo1 = j1 - lo.p < 0 ? 0 : j1 - lo.p, hi1 = j1 < lo.ne - 1 ? j1 : lo.ne - 1;
+    const int lo2 = j2 - lo.p < 0 ? 0 : j2 - lo.p, hi2 = j2 < lo.ne - 1 ? j2 : lo.ne - 1;
     T acc = zero<T>();
     double *mv = sh;  // up to (p+2)^2 clusters x q2
     // far field, level by level
     for (int l = A.lmin; l <= lo.L; ++l) {
-        int nsub = lo.ne >> l, n = 1 << l;
-        int c1lo = lo1 / nsub, c1hi = hi1 / nsub, c2lo = lo2 / nsub, c2hi = hi2 / nsub;
-        int nc1 = c1hi - c1lo + 1, nc = nc1 * (c2hi - c2lo + 1);
+        const int nsub = lo.ne >> l, n = 1 << l;
+        const int c1lo = lo1 / nsub, c1hi = hi1 / nsub, c2lo = lo2 / nsub, c2hi = hi2 / nsub;
+        const int nc1 = c1hi - c1lo + 1, nc = nc1 * (c2hi - c2lo + 1);
         const double *Ml = A.Mlev + A.Mlev_off[l];
         for (int o = threadIdx.x; o < nc * q2; o += blockDim.x) {
             int c = o / q2, mu = o % q2, mu2 = mu / q, mu1 = mu % q;
@@ -1294,69 +1315,91 @@ __global__ void __launch_bounds__(256) k_diag(DiagArgs A, int64_t ndof, const T 
             double s = 0.0;
             for (int e2 = (lo2 > cc2 * nsub ? lo2 : cc2 * nsub); e2 <= hi2 && e2 < (cc2 + 1) * nsub; ++e2)
                 for (int e1 = (lo1 > cc1 * nsub ? lo1 : cc1 * nsub); e1 <= hi1 && e1 < (cc1 + 1) * nsub; ++e1)
-                    for (int r2 = 0; r2 < lo.P1; ++r2)
-                        for (int r1 = 0; r1 < lo.P1; ++r1) {
-                            double t = A.Tb[(e1 * lo.P1 + r1) * lo.P1 + (j1 - e1)] * A.Tb[(e2 * lo.P1 + r2) * lo.P1 + (j2 - e2)];
-                            s += t * Ml[((e1 - cc1 * nsub) * lo.P1 + r1) * q + mu1] * Ml[((e2 - cc2 * nsub) * lo.P1 + r2) * q + mu2];
+                    for (int r2 = 0; r2 < P1; ++r2)
+                        for (int r1 = 0; r1 < P1; ++r1) {
+                            double t = A.Tb[(e1 * P1 + r1) * P1 + (j1 - e1)] * A.Tb[(e2 * P1 + r2) * P1 + (j2 - e2)];
+                            s += t * Ml[((e1 - cc1 * nsub) * P1 + r1) * q + mu1] * Ml[((e2 - cc2 * nsub) * P1 + r2) * q + mu2];
                         }
             mv[o] = s;
         }
-        __syncthreads();
-        for (int ca = 0; ca < nc; ++ca)
-            for (int cb = 0; cb < nc; ++cb) {
-                int ida = patch * n * n + (c2lo + ca / nc1) * n + c1lo + ca % nc1;
-                int idb = patch * n * n + (c2lo + cb / nc1) * n + c1lo + cb % nc1;
-                int64_t ga = A.cl_off[l] + ida, gb = A.cl_off[l] + idb;
-                int64_t k = csr_find(A.far_ptr, A.far_src, ga, (int32_t)gb);
-                if (k < 0) continue;
-                // coupling entries K[mu][nu] = G(x_mu, y_nu) kappa_mu kappa_nu from the node geometry
-                const double *na = A.nodes + (size_t)ga * q2 * 4, *nb = A.nodes + (size_t)gb * q2 * 4;
-                for (int nu = threadIdx.x; nu < q2; nu += blockDim.x) {
-                    T s = zero<T>();
-                    const double *y = nb + 4 * nu;
-                    for (int mu = 0; mu < q2; ++mu) {
-                        const double *x = na + 4 * mu;
-                        double d0 = x[0] - y[0], d1 = x[1] - y[1], d2 = x[2] - y[2];
-                        s += green<T>(sqrt(d0 * d0 + d1 * d1 + d2 * d2), A.kappa) * (x[3] * mv[ca * q2 + mu]);
-                    }
-                    acc += s * (y[3] * mv[cb * q2 + nu]);
-                }
+        // admissible pairs ca < cb
+        for (int c = threadIdx.x; c < nc * nc; c += blockDim.x) {
+            const int ca = c / nc, cb = c % nc;
+            unsigned char f = 0;
+            if (ca < cb) {
+                const int ida = patch * n * n + (c2lo + ca / nc1) * n + c1lo + ca % nc1;
+                const int idb = patch * n * n + (c2lo + cb / nc1) * n + c1lo + cb % nc1;
+                f = csr_find(A.far_ptr, A.far_src, A.cl_off[l] + ida, (int32_t)(A.cl_off[l] + idb)) >= 0;
             }
+            ff[c] = f;
+        }
+        __syncthreads();
+        for (int w = threadIdx.x; w < nc * nc * q2; w += blockDim.x) {
+            const int c = w / q2, nu = w % q2;
+            if (!ff[c]) continue;
+            const int ca = c / nc, cb = c % nc;
+            const int ida = patch * n * n + (c2lo + ca / nc1) * n + c1lo + ca % nc1;
+            const int idb = patch * n * n + (c2lo + cb / nc1) * n + c1lo + cb % nc1;
+            // coupling entries K[mu][nu] = G(x_mu, y_nu) kappa_mu kappa_nu from the node geometry
+            const double *na = A.nodes + (size_t)(A.cl_off[l] + ida) * q2 * 4;
+            const double *y = A.nodes + ((size_t)(A.cl_off[l] + idb) * q2 + nu) * 4;
+            const double y0 = y[0], y1 = y[1], y2 = y[2];
+            T s = zero<T>();
+            for (int mu = 0; mu < q2; ++mu) {
+                const double *x = na + 4 * mu;
+                const double d0 = x[0] - y0, d1 = x[1] - y1, d2 = x[2] - y2;
+                const double r2 = d0 * d0 + d1 * d1 + d2 * d2;
+                s += green_ir<T>(r2, rsqrt_pos(r2), A.kappa) * (x[3] * mv[ca * q2 + mu]);
+            }
+            // the pair (cb, ca) contributes the same amount
+            acc += s * (2.0 * y[3] * mv[cb * q2 + nu]);
+        }
         __syncthreads();
     }
     // near field at the leaf level
     {
-        int nsub = lo.side, n = 1 << lo.L;
-        int c1lo = lo1 / nsub, c1hi = hi1 / nsub, c2lo = lo2 / nsub, c2hi = hi2 / nsub;
-        int nc1 = c1hi - c1lo + 1, nc = nc1 * (c2hi - c2lo + 1);
-        for (int ca = 0; ca < nc; ++ca)
-            for (int cb = 0; cb < nc; ++cb) {
-                int ka1 = c1lo + ca % nc1, ka2 = c2lo + ca / nc1, kb1 = c1lo + cb % nc1, kb2 = c2lo + cb / nc1;
-                int ida = patch * n * n + ka2 * n + ka1, idb = patch * n * n + kb2 * n + kb1;
-                int64_t k = csr_find(A.near_ptr, A.near_src, ida, idb);
-                if (k < 0) continue;
-                int64_t kb = A.sb[k];
-                const bool tr = kb < 0;
-                if (tr) {
-                    int64_t km = csr_find(A.near_ptr, A.near_src, idb, ida);
-                    if (km < 0) continue;
-                    kb = A.sb[km];
-                }
-                const T *B = nearb + kb * (int64_t)lo.nl * A.ld;
-                // functions of the support in both leaves: loop over (row fa, col fb) pairs
-                for (int o = threadIdx.x; o < lo.nl * lo.nl; o += blockDim.x) {
-                    int fb = o / lo.nl, fa = o % lo.nl;
-                    int ela = fa / lo.nloc, ra = fa % lo.nloc, elb = fb / lo.nloc, rb = fb % lo.nloc;
-                    int ea1 = ka1 * nsub + ela % nsub, ea2 = ka2 * nsub + ela / nsub;
-                    int eb1 = kb1 * nsub + elb % nsub, eb2 = kb2 * nsub + elb / nsub;
-                    if (ea1 < lo1 || ea1 > hi1 || ea2 < lo2 || ea2 > hi2 || eb1 < lo1 || eb1 > hi1 || eb2 < lo2 || eb2 > hi2)
-                        continue;
-                    double ta = A.Tb[(ea1 * lo.P1 + ra % lo.P1) * lo.P1 + (j1 - ea1)] * A.Tb[(ea2 * lo.P1 + ra / lo.P1) * lo.P1 + (j2 - ea2)];
-                    double tb = A.Tb[(eb1 * lo.P1 + rb % lo.P1) * lo.P1 + (j1 - eb1)] * A.Tb[(eb2 * lo.P1 + rb / lo.P1) * lo.P1 + (j2 - eb2)];
-                    if (ta == 0.0 || tb == 0.0) continue;
-                    acc += (tr ? B[(int64_t)fa * A.ld + fb] : B[(int64_t)fb * A.ld + fa]) * (ta * tb);
+        const int nsub = lo.side, n = 1 << lo.L;
+        const int c1lo = lo1 / nsub, c1hi = hi1 / nsub, c2lo = lo2 / nsub, c2hi = hi2 / nsub;
+        const int nc1 = c1hi - c1lo + 1, nc = nc1 * (c2hi - c2lo + 1);
+        const int w1 = hi1 - lo1 + 1, w2 = hi2 - lo2 + 1, ns = w1 * w2 * lo.nloc;
+        // support functions: weight, leaf slot, index within the leaf
+        double *lt = sh;
+        int *lc = (int *)(lt + ns), *lf = lc + ns;
+        int *bt = lf + ns;  // per leaf-slot pair: stored block, -2 - block when transposed, -1 when not near
+        for (int k = threadIdx.x; k < ns; k += blockDim.x) {
+            const int r = k % lo.nloc, e = k / lo.nloc;
+            const int e1 = lo1 + e % w1, e2 = lo2 + e / w1, ra = r % P1, rb = r / P1;
+            lt[k] = A.Tb[(e1 * P1 + ra) * P1 + (j1 - e1)] * A.Tb[(e2 * P1 + rb) * P1 + (j2 - e2)];
+            lc[k] = (e2 / nsub - c2lo) * nc1 + (e1 / nsub - c1lo);
+            lf[k] = ((e2 % nsub) * nsub + e1 % nsub) * lo.nloc + r;
+        }
+        for (int c = threadIdx.x; c < nc * nc; c += blockDim.x) {
+            const int ca = c / nc, cb = c % nc;
+            const int ida = patch * n * n + (c2lo + ca / nc1) * n + c1lo + ca % nc1;
+            const int idb = patch * n * n + (c2lo + cb / nc1) * n + c1lo + cb % nc1;
+            int code = -1;
+            const int64_t k = csr_find(A.near_ptr, A.near_src, ida, idb);
+            if (k >= 0) {
+                const int64_t kb = A.sb[k];
+                if (kb >= 0) {
+                    code = (int)kb;
+                } else {
+                    const int64_t km = csr_find(A.near_ptr, A.near_src, idb, ida);
+                    if (km >= 0 && A.sb[km] >= 0) code = -2 - (int)A.sb[km];
                 }
             }
+            bt[c] = code;
+        }
+        __syncthreads();
+        for (int w = threadIdx.x; w < ns * ns; w += blockDim.x) {
+            const int ia = w % ns, ib = w / ns;
+            const double t = lt[ia] * lt[ib];
+            const int code = bt[lc[ia] * nc + lc[ib]];
+            if (t == 0.0 || code == -1) continue;
+            const int fa = lf[ia], fb = lf[ib];
+            if (code >= 0) acc += nearb[(int64_t)code * lo.nl * A.ld + (int64_t)fb * A.ld + fa] * t;
+            else acc += nearb[(int64_t)(-2 - code) * lo.nl * A.ld + (int64_t)fa * A.ld + fb] * t;
+        }
     }
     red[threadIdx.x] = acc;
     __syncthreads();
@@ -2010,8 +2053,12 @@ static igb_status assemble(igb_operator *op)
         A.far_src = op->far_src;
         A.nodes = op->nodes;
         A.kappa = s.kappa;
-        size_t shm = (size_t)(s.p + 2) * (s.p + 2) * q2 * sizeof(double);
-        if (shm > 150 * 1024) return fail(IGB_EUNSUPPORTED, "Jacobi diagonal: (p+2)^2 q^2 too large");
+        // far: moments of up to (p+2)^2 clusters; near: (p+1)^2 nloc support functions
+        // (weight, slot, index) and the (p+2)^4 leaf-pair table
+        const size_t ns = (size_t)(s.p + 1) * (s.p + 1) * s.nloc, ncm = (size_t)(s.p + 2) * (s.p + 2);
+        size_t shm = std::max((size_t)(s.p + 2) * (s.p + 2) * q2 * sizeof(double),
+                              ns * (sizeof(double) + 2 * sizeof(int)) + ncm * ncm * sizeof(int));
+        if (shm > 140 * 1024 || ncm * ncm > 4096) return fail(IGB_EUNSUPPORTED, "Jacobi diagonal: p or q too large");
         (void)hipFuncSetAttribute((const void *)k_diag<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
         hipLaunchKernelGGL((k_diag<T>), dim3((unsigned)s.ndof), dim3(256), shm, op->st, A, s.ndof, (const T *)op->nearb,
                            (const T *)op->coup, (T *)op->diag);

@@ -178,14 +178,14 @@ igb_status igb_potential(const igb_operator *op, const void *w_dev, int64_t n_pt
 /* Timing of the superspace matvec by stage: runs `reps` products on the
  * operator's internal work vectors with HIP events recorded on its stream
  * between stages and writes the mean milliseconds per stage to
- * stage_ms_host[IGB_NUM_MATVEC_STAGES]: 0 leaf moments, 1 upward transfers,
- * 2 coupling blocks (stored GEMV, or generated on the fly), 3 gather of the
- * coupling partial rows (on the fly with q^2 <= 64: each pair of mirrored
- * blocks is evaluated once; 0 otherwise), 4 downward transfers, 5 near-field
- * block GEMV, 6 gather of the near-field partial rows (symmetric near
- * storage: only blocks (t, s) with t <= s are kept; 0 otherwise), 7 leaf
- * back-moments (Sec. 4.2).  Synchronous. */
-#define IGB_NUM_MATVEC_STAGES 8
+ * stage_ms_host[IGB_NUM_MATVEC_STAGES]: 0 upward pass (leaf moments and
+ * transfers), 1 coupling blocks (stored GEMV, or generated on the fly),
+ * 2 gather of the coupling partial rows (on the fly with q^2 <= 64: each pair
+ * of mirrored blocks is evaluated once; 0 otherwise), 3 near-field block
+ * GEMV, 4 gather of the near-field partial rows (symmetric near storage: only
+ * blocks (t, s) with t <= s are kept; 0 otherwise), 5 downward pass
+ * (transfers and leaf back-moments) (Sec. 4.2).  Synchronous. */
+#define IGB_NUM_MATVEC_STAGES 6
 igb_status igb_matvec_profile(const igb_operator *op, int32_t reps, double *stage_ms_host);
 
 /* Host-only planning: the cluster tree, block partition (Sec. 4.1, Sec. 4.2

@@ -553,129 +553,181 @@ __global__ void __launch_bounds__(256) k_coupling(int64_t nfar, const int32_t *_
     }
 }
 
-// Leaf moments X^ = M1^T X M1 (X the leaf's coefficients as an n1 x n1 array).
-template <class T>
-__global__ void k_leaf_moments(int n1, int q, int side, int P1, int nloc, int nl, const double *__restrict__ M1,
-                               const T *__restrict__ xs, T *__restrict__ Xh)
+// Two-level slices of the cluster tree in one workgroup (Sec. 4.2 nested
+// bases).  A workgroup owns one cluster of level ls and the clusters below it
+// down to level lb <= ls + 2.  k_up_tree: leaf moments (when lb is the leaf
+// level) and the upward transfers from lb to ls; k_down_tree: the downward
+// transfers from ls to lb and the leaf back-moments (when lb is the leaf
+// level).  Leaf moments X^ = M1^T X M1 (X the leaf's coefficients as an
+// n1 x n1 array) and back-moments y* += M1 Y^ M1^T are two 1D contractions
+// each; a transfer is one (parent, child) item per wave, the four child
+// contributions of a parent summed in child order through LDS.  Waves use
+// LDS slices of SL elements of T, levels are separated by workgroup barriers.
+struct TreeArgs {
+    int ls, lb, L, q, n1, side, P1, nloc, nl;
+    const double *M1, *E2;
+    const int64_t *cl_off;
+};
+
+// global index of cluster (a2, a1) of level lv inside the slice of root
+// (patch, r2, r1) at level ls
+__device__ inline int64_t tree_cluster(const TreeArgs &A, int patch, int r2, int r1, int lv, int a2, int a1)
 {
-    extern __shared__ double sh[];
-    T *X = (T *)sh;        // n1*n1
-    T *Z = X + n1 * n1;    // n1*q
-    int leaf = blockIdx.x;
-    for (int f = threadIdx.x; f < nl; f += blockDim.x) {
-        int el = f / nloc, r = f % nloc;
-        int i1 = (el % side) * P1 + r % P1, i2 = (el / side) * P1 + r / P1;
-        X[i2 * n1 + i1] = xs[(int64_t)leaf * nl + f];
-    }
-    __syncthreads();
-    for (int o = threadIdx.x; o < n1 * q; o += blockDim.x) {
-        int i2 = o / q, mu1 = o % q;
-        T s = zero<T>();
-        for (int i1 = 0; i1 < n1; ++i1) s += M1[i1 * q + mu1] * X[i2 * n1 + i1];
-        Z[o] = s;
-    }
-    __syncthreads();
-    for (int o = threadIdx.x; o < q * q; o += blockDim.x) {
-        int mu2 = o / q, mu1 = o % q;
-        T s = zero<T>();
-        for (int i2 = 0; i2 < n1; ++i2) s += M1[i2 * q + mu2] * Z[i2 * q + mu1];
-        Xh[(int64_t)leaf * q * q + o] = s;
-    }
+    const int w = 1 << (lv - A.ls), n = 1 << lv;
+    return A.cl_off[lv] + (int64_t)patch * n * n + (int64_t)(r2 * w + a2) * n + r1 * w + a1;
 }
 
-// Upward pass, one level: X^_P = 1/4 sum_c (E_c1 (x) E_c2)^T X^_c (nested bases).
 template <class T>
-__global__ void k_upward(int l, int q, const double *__restrict__ E2, const T *__restrict__ Xc_lvl, T *__restrict__ Xp_lvl)
+__global__ void __launch_bounds__(1024) k_up_tree(TreeArgs A, int SL, const T *__restrict__ xs, T *__restrict__ Xh)
 {
     extern __shared__ double sh[];
-    int q2 = q * q;
-    T *Xc = (T *)sh;   // q2
-    T *Z = Xc + q2;    // q2
-    int n = 1 << l, nn = 2 * n;
-    int pid = blockIdx.x;
-    int patch = pid / (n * n), r = pid % (n * n), k2 = r / n, k1 = r % n;
-    T acc[4];
-    for (int k = 0; k < 4; ++k) acc[k] = zero<T>();
-    for (int c2 = 0; c2 < 2; ++c2)
-        for (int c1 = 0; c1 < 2; ++c1) {
-            int cid = patch * nn * nn + (2 * k2 + c2) * nn + 2 * k1 + c1;
-            for (int o = threadIdx.x; o < q2; o += blockDim.x) Xc[o] = Xc_lvl[(int64_t)cid * q2 + o];
-            __syncthreads();
-            const double *Ec1 = E2 + c1 * q2, *Ec2 = E2 + c2 * q2;
-            for (int o = threadIdx.x; o < q2; o += blockDim.x) {
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, nwv = blockDim.x >> 6;
+    const int q = A.q, q2 = q * q, n1 = A.n1;
+    T *W0 = (T *)sh + (size_t)wave * SL;
+    T *slot = (T *)sh + (size_t)nwv * SL;  // [4 P][q2] child contributions
+    const int nr = 1 << A.ls, root = blockIdx.x;
+    const int patch = root / (nr * nr), r2 = (root % (nr * nr)) / nr, r1 = root % nr;
+    if (A.lb == A.L) {
+        const int w = 1 << (A.L - A.ls);
+        const int64_t leaf0 = A.cl_off[A.L];
+        T *X = W0, *Z = W0 + n1 * n1;
+        for (int i = wave; i < w * w; i += nwv) {
+            const int64_t g = tree_cluster(A, patch, r2, r1, A.L, i / w, i % w), leaf = g - leaf0;
+            for (int f = lane; f < A.nl; f += 64) {
+                int el = f / A.nloc, r = f % A.nloc;
+                int i1 = (el % A.side) * A.P1 + r % A.P1, i2 = (el / A.side) * A.P1 + r / A.P1;
+                X[i2 * n1 + i1] = xs[leaf * A.nl + f];
+            }
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+            for (int o = lane; o < n1 * q; o += 64) {
+                int i2 = o / q, mu1 = o % q;
+                T s = zero<T>();
+                for (int i1 = 0; i1 < n1; ++i1) s += A.M1[i1 * q + mu1] * X[i2 * n1 + i1];
+                Z[o] = s;
+            }
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+            for (int o = lane; o < q2; o += 64) {
+                int mu2 = o / q, mu1 = o % q;
+                T s = zero<T>();
+                for (int i2 = 0; i2 < n1; ++i2) s += A.M1[i2 * q + mu2] * Z[i2 * q + mu1];
+                Xh[g * q2 + o] = s;
+            }
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        }
+    }
+    // X^_P = 1/4 sum_c (E_c1 (x) E_c2)^T X^_c, children c = (c2, c1) in order
+    for (int lv = A.lb - 1; lv >= A.ls; --lv) {
+        __syncthreads();
+        const int w = 1 << (lv - A.ls), np = w * w;
+        T *Xc = W0, *Z = W0 + q2;
+        for (int it = wave; it < 4 * np; it += nwv) {
+            const int i = it >> 2, c1 = it & 1, c2 = (it >> 1) & 1, a2 = i / w, a1 = i % w;
+            const int64_t gc = tree_cluster(A, patch, r2, r1, lv + 1, 2 * a2 + c2, 2 * a1 + c1);
+            for (int o = lane; o < q2; o += 64) Xc[o] = Xh[gc * q2 + o];
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+            const double *Ec1 = A.E2 + c1 * q2, *Ec2 = A.E2 + c2 * q2;
+            for (int o = lane; o < q2; o += 64) {
                 int nu2 = o / q, mu1 = o % q;
                 T s = zero<T>();
                 for (int nu1 = 0; nu1 < q; ++nu1) s += Ec1[nu1 * q + mu1] * Xc[nu2 * q + nu1];
                 Z[o] = s;
             }
-            __syncthreads();
-            for (int k = 0, o = threadIdx.x; o < q2; o += blockDim.x, ++k) {
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+            for (int o = lane; o < q2; o += 64) {
                 int mu2 = o / q, mu1 = o % q;
                 T s = zero<T>();
                 for (int nu2 = 0; nu2 < q; ++nu2) s += Ec2[nu2 * q + mu2] * Z[nu2 * q + mu1];
-                acc[k] += s;
+                slot[(size_t)it * q2 + o] = s;
             }
-            __syncthreads();
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
         }
-    for (int k = 0, o = threadIdx.x; o < q2; o += blockDim.x, ++k) Xp_lvl[(int64_t)pid * q2 + o] = 0.25 * acc[k];
-}
-
-// Downward pass, one level: Y^_c += 1/4 (E_c1 (x) E_c2) Y^_P.
-template <class T>
-__global__ void k_downward(int lc, int q, const double *__restrict__ E2, const T *__restrict__ Yp_lvl, T *__restrict__ Yc_lvl)
-{
-    extern __shared__ double sh[];
-    int q2 = q * q;
-    T *Yp = (T *)sh;
-    T *Z = Yp + q2;
-    int n = 1 << lc, np = n / 2;
-    int cid = blockIdx.x;
-    int patch = cid / (n * n), r = cid % (n * n), k2 = r / n, k1 = r % n;
-    int pid = patch * np * np + (k2 >> 1) * np + (k1 >> 1);
-    int c1 = k1 & 1, c2 = k2 & 1;
-    for (int o = threadIdx.x; o < q2; o += blockDim.x) Yp[o] = Yp_lvl[(int64_t)pid * q2 + o];
-    __syncthreads();
-    const double *Ec1 = E2 + c1 * q2, *Ec2 = E2 + c2 * q2;
-    for (int o = threadIdx.x; o < q2; o += blockDim.x) {
-        int mu2 = o / q, nu1 = o % q;
-        T s = zero<T>();
-        for (int mu1 = 0; mu1 < q; ++mu1) s += Ec1[nu1 * q + mu1] * Yp[mu2 * q + mu1];
-        Z[o] = s;
-    }
-    __syncthreads();
-    for (int o = threadIdx.x; o < q2; o += blockDim.x) {
-        int nu2 = o / q, nu1 = o % q;
-        T s = zero<T>();
-        for (int mu2 = 0; mu2 < q; ++mu2) s += Ec2[nu2 * q + mu2] * Z[mu2 * q + nu1];
-        Yc_lvl[(int64_t)cid * q2 + o] += 0.25 * s;
+        __syncthreads();
+        for (int o = threadIdx.x; o < np * q2; o += blockDim.x) {
+            const int i = o / q2, k = o % q2;
+            const T *sc = slot + (size_t)4 * i * q2 + k;
+            T v = zero<T>();
+            v += sc[0];
+            v += sc[q2];
+            v += sc[2 * q2];
+            v += sc[3 * q2];
+            Xh[tree_cluster(A, patch, r2, r1, lv, i / w, i % w) * q2 + k] = 0.25 * v;
+        }
     }
 }
 
-// Leaf back-moments: y* += M1 Y^ M1^T.
 template <class T>
-__global__ void k_leaf_back(int n1, int q, int side, int P1, int nloc, int nl, const double *__restrict__ M1,
-                            const T *__restrict__ Yh, T *__restrict__ ys)
+__global__ void __launch_bounds__(1024) k_down_tree(TreeArgs A, int SL, T *__restrict__ Yh, T *__restrict__ ys)
 {
     extern __shared__ double sh[];
-    int q2 = q * q;
-    T *Y = (T *)sh;   // q2
-    T *Z = Y + q2;    // q*n1
-    int leaf = blockIdx.x;
-    for (int o = threadIdx.x; o < q2; o += blockDim.x) Y[o] = Yh[(int64_t)leaf * q2 + o];
-    __syncthreads();
-    for (int o = threadIdx.x; o < q * n1; o += blockDim.x) {
-        int mu2 = o / n1, i1 = o % n1;
-        T s = zero<T>();
-        for (int mu1 = 0; mu1 < q; ++mu1) s += M1[i1 * q + mu1] * Y[mu2 * q + mu1];
-        Z[o] = s;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, nwv = blockDim.x >> 6;
+    const int q = A.q, q2 = q * q, n1 = A.n1;
+    T *W0 = (T *)sh + (size_t)wave * SL;
+    const int nr = 1 << A.ls, root = blockIdx.x;
+    const int patch = root / (nr * nr), r2 = (root % (nr * nr)) / nr, r1 = root % nr;
+    // Y^_c += 1/4 (E_c1 (x) E_c2) Y^_P
+    for (int lv = A.ls + 1; lv <= A.lb; ++lv) {
+        const int w = 1 << (lv - A.ls);
+        T *Yp = W0, *Z = W0 + q2;
+        for (int i = wave; i < w * w; i += nwv) {
+            const int a2 = i / w, a1 = i % w, c1 = a1 & 1, c2 = a2 & 1;
+            const int64_t gc = tree_cluster(A, patch, r2, r1, lv, a2, a1);
+            const int64_t gp = tree_cluster(A, patch, r2, r1, lv - 1, a2 >> 1, a1 >> 1);
+            for (int o = lane; o < q2; o += 64) Yp[o] = Yh[gp * q2 + o];
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+            const double *Ec1 = A.E2 + c1 * q2, *Ec2 = A.E2 + c2 * q2;
+            for (int o = lane; o < q2; o += 64) {
+                int mu2 = o / q, nu1 = o % q;
+                T s = zero<T>();
+                for (int mu1 = 0; mu1 < q; ++mu1) s += Ec1[nu1 * q + mu1] * Yp[mu2 * q + mu1];
+                Z[o] = s;
+            }
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+            for (int o = lane; o < q2; o += 64) {
+                int nu2 = o / q, nu1 = o % q;
+                T s = zero<T>();
+                for (int mu2 = 0; mu2 < q; ++mu2) s += Ec2[nu2 * q + mu2] * Z[mu2 * q + nu1];
+                Yh[gc * q2 + o] += 0.25 * s;
+            }
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        }
+        __syncthreads();
     }
-    __syncthreads();
-    for (int f = threadIdx.x; f < nl; f += blockDim.x) {
-        int el = f / nloc, r = f % nloc;
-        int i1 = (el % side) * P1 + r % P1, i2 = (el / side) * P1 + r / P1;
-        T s = zero<T>();
-        for (int mu2 = 0; mu2 < q; ++mu2) s += M1[i2 * q + mu2] * Z[mu2 * n1 + i1];
-        ys[(int64_t)leaf * nl + f] += s;
+    if (A.lb == A.L) {
+        const int w = 1 << (A.L - A.ls);
+        const int64_t leaf0 = A.cl_off[A.L];
+        T *Y = W0, *Z = W0 + q2;
+        for (int i = wave; i < w * w; i += nwv) {
+            const int64_t g = tree_cluster(A, patch, r2, r1, A.L, i / w, i % w), leaf = g - leaf0;
+            for (int o = lane; o < q2; o += 64) Y[o] = Yh[g * q2 + o];
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+            for (int o = lane; o < q * n1; o += 64) {
+                int mu2 = o / n1, i1 = o % n1;
+                T s = zero<T>();
+                for (int mu1 = 0; mu1 < q; ++mu1) s += A.M1[i1 * q + mu1] * Y[mu2 * q + mu1];
+                Z[o] = s;
+            }
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+            for (int f = lane; f < A.nl; f += 64) {
+                int el = f / A.nloc, r = f % A.nloc;
+                int i1 = (el % A.side) * A.P1 + r % A.P1, i2 = (el / A.side) * A.P1 + r / A.P1;
+                T s = zero<T>();
+                for (int mu2 = 0; mu2 < q; ++mu2) s += A.M1[i2 * q + mu2] * Z[mu2 * n1 + i1];
+                ys[leaf * A.nl + f] += s;
+            }
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        }
     }
 }
 
@@ -1756,15 +1808,45 @@ static igb_status launch_singular(igb_operator *op, const PairRec *d, int64_t n)
 }
 
 // superspace matvec on internal vectors: ys = A xs.  When ev is given, ev[k]
-// is recorded on the operator's stream before stage k and ev[8] at the end:
-// stages 0 leaf moments, 1 upward, 2 coupling blocks, 3 coupling gather (on
-// the fly by mirrored pairs only), 4 downward, 5 near GEMV, 6 near gather
-// (symmetric near storage only), 7 leaf back-moments.
+// is recorded on the operator's stream before stage k and ev[6] at the end:
+// stages 0 upward (leaf moments and transfers), 1 coupling blocks, 2 coupling
+// gather (on the fly by mirrored pairs only), 3 near GEMV, 4 near gather
+// (symmetric near storage only), 5 downward (transfers and leaf back-moments).
 template <class T, int TT>
 static void launch_far_sym(igb_operator *op, const T *Xh)
 {
     hipLaunchKernelGGL((k_far_sym<T, TT>), dim3((unsigned)((op->nup + 3) / 4)), dim3(256), 0, op->st, op->nup, op->up_t,
                        op->up_s, op->s.q * op->s.q, op->nodes, Xh, op->s.kappa, (T *)op->fpart);
+}
+
+// Slices of the cluster tree for k_up_tree / k_down_tree: (ls, lb) pairs from
+// the leaves up, lb - ls <= 2, ending at the coarsest far-field level.
+struct TreeLaunch {
+    TreeArgs A;
+    int SL, waves;
+    unsigned roots;
+    size_t shm;
+};
+static std::vector<TreeLaunch> tree_slices(const igb_operator *op, size_t esz)
+{
+    const Setup &s = op->s;
+    std::vector<TreeLaunch> v;
+    const int q2 = s.q * s.q;
+    const int SL = std::max({s.n1 * s.n1 + s.n1 * s.q, 2 * q2, q2 + s.q * s.n1});
+    const int waves = (int)std::max<size_t>(1, std::min<size_t>(16, (48 * 1024) / ((size_t)SL * esz)));
+    int lb = s.L;
+    do {
+        TreeLaunch t;
+        const int ls = std::max(op->lmin, lb - 2);
+        t.A = TreeArgs{ls, lb, s.L, s.q, s.n1, s.side, s.p + 1, s.nloc, s.nl, op->M1, op->E2, op->cl_off};
+        t.SL = SL;
+        t.waves = waves;
+        t.roots = (unsigned)(s.npatch << (2 * ls));
+        t.shm = ((size_t)waves * SL + (size_t)16 * q2) * esz;  // slices + child slots of <= 4 parents
+        v.push_back(t);
+        lb = ls;
+    } while (lb > op->lmin);
+    return v;
 }
 
 template <class T>
@@ -1779,22 +1861,18 @@ static igb_status matvec_internal(igb_operator *op, const T *xs, T *ys, hipEvent
         return IGB_OK;
     };
     igb_status rc;
+    const std::vector<TreeLaunch> TS = has_far ? tree_slices(op, sizeof(T)) : std::vector<TreeLaunch>();
     if ((rc = mark(0))) return rc;
-    if (has_far) {
-        size_t shm = (size_t)(s.n1 * s.n1 + s.n1 * q) * sizeof(T);
-        hipLaunchKernelGGL((k_leaf_moments<T>), dim3(s.nleaf), dim3(64), shm, op->st, s.n1, q, s.side, s.p + 1, s.nloc,
-                           s.nl, op->M1, xs, Xh + s.cl_off[s.L] * q2);
+    for (const TreeLaunch &t : TS) {
+        if (t.shm > 64 * 1024) {
+            if (t.shm > 160 * 1024) return fail(IGB_EUNSUPPORTED, "cluster-tree transfers: q too large for LDS");
+            (void)hipFuncSetAttribute((const void *)k_up_tree<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)t.shm);
+            (void)hipFuncSetAttribute((const void *)k_down_tree<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)t.shm);
+        }
+        hipLaunchKernelGGL((k_up_tree<T>), dim3(t.roots), dim3(64 * t.waves), t.shm, op->st, t.A, t.SL, xs, Xh);
         LAUNCHCHK();
     }
     if ((rc = mark(1))) return rc;
-    if (has_far) {
-        for (int l = s.L - 1; l >= op->lmin; --l) {
-            hipLaunchKernelGGL((k_upward<T>), dim3((unsigned)(s.cl_off[l + 1] - s.cl_off[l])), dim3(64), 2 * q2 * sizeof(T),
-                               op->st, l, q, op->E2, Xh + s.cl_off[l + 1] * q2, Xh + s.cl_off[l] * q2);
-            LAUNCHCHK();
-        }
-    }
-    if ((rc = mark(2))) return rc;
     int64_t row0 = s.cl_off[op->lmin], nrows = s.cl_off[s.L + 1] - row0;
     const bool sym = has_far && op->fpart != nullptr;
     if (has_far) {
@@ -1819,23 +1897,14 @@ static igb_status matvec_internal(igb_operator *op, const T *xs, T *ys, hipEvent
         }
         LAUNCHCHK();
     }
-    if ((rc = mark(3))) return rc;
+    if ((rc = mark(2))) return rc;
     if (sym) {
         hipLaunchKernelGGL((k_gather<T>), dim3((unsigned)nrows), dim3(256), 4 * q2 * sizeof(T), op->st, q2, q2,
                            op->far_ptr, op->far_pidx, (const T *)op->fpart, op->nodes + 3, 0.07957747154594767, Yh,
                            row0);
         LAUNCHCHK();
     }
-    if ((rc = mark(4))) return rc;
-    if (has_far) {
-        for (int l = op->lmin; l < s.L; ++l) {
-            hipLaunchKernelGGL((k_downward<T>), dim3((unsigned)(s.cl_off[l + 2] - s.cl_off[l + 1])), dim3(64),
-                               2 * q2 * sizeof(T), op->st, l + 1, q, op->E2, Yh + s.cl_off[l] * q2,
-                               Yh + s.cl_off[l + 1] * q2);
-            LAUNCHCHK();
-        }
-    }
-    if ((rc = mark(5))) return rc;
+    if ((rc = mark(3))) return rc;
     if (op->near_sym) {
         const int ld = op->near_ld;
         const size_t wave_lds = (size_t)(8 * ld + 520) * sizeof(T);
@@ -1847,21 +1916,19 @@ static igb_status matvec_internal(igb_operator *op, const T *xs, T *ys, hipEvent
                            op->near_ptr, op->near_src, (const T *)op->nearb, xs, ys, (int64_t)0);
     }
     LAUNCHCHK();
-    if ((rc = mark(6))) return rc;
+    if ((rc = mark(4))) return rc;
     if (op->near_sym) {
         hipLaunchKernelGGL((k_gather<T>), dim3(s.nleaf), dim3(256), 4 * s.nl * sizeof(T), op->st, s.nl, op->near_ld,
                            op->near_ptr, op->near_pidx, (const T *)op->npart, (const double *)nullptr, 1.0, ys,
                            (int64_t)0);
         LAUNCHCHK();
     }
-    if ((rc = mark(7))) return rc;
-    if (has_far) {
-        size_t shm = (size_t)(q2 + q * s.n1) * sizeof(T);
-        hipLaunchKernelGGL((k_leaf_back<T>), dim3(s.nleaf), dim3(64), shm, op->st, s.n1, q, s.side, s.p + 1, s.nloc, s.nl,
-                           op->M1, (const T *)(Yh + s.cl_off[s.L] * q2), ys);
+    if ((rc = mark(5))) return rc;
+    for (auto t = TS.rbegin(); t != TS.rend(); ++t) {
+        hipLaunchKernelGGL((k_down_tree<T>), dim3(t->roots), dim3(64 * t->waves), t->shm, op->st, t->A, t->SL, Yh, ys);
         LAUNCHCHK();
     }
-    return mark(8);
+    return mark(6);
 }
 
 template <class T>

@@ -37,8 +37,7 @@ EXPORTED = [
     "igb_plan_create", "igb_plan_destroy", "igb_plan_info", "igb_plan_export_partition",
     "igb_plan_export_pair_classes", "igb_matvec_profile",
 ]
-STAGES = ["leaf_moments", "upward", "coupling", "coupling_gather", "downward", "near_gemv", "near_gather",
-          "leaf_back"]
+STAGES = ["upward", "coupling", "coupling_gather", "near_gemv", "near_gather", "downward"]
 
 
 class igb_nurbs_patch(C.Structure):

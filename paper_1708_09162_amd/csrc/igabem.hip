@@ -186,62 +186,126 @@ __device__ inline double rsqrt_pos(double r2)
     return fma(y * e, fma(e, 0.375, 0.5), y);
 }
 
-// Partial contraction of a rational Bezier tile of bidegree (PG, PG) at a
-// fixed value f of one parameter.  M holds the homogeneous control points with
-// the contracted parameter fastest, M[(k*(PG+1) + l)*4 + c]: the tile itself
-// (l along u) to fix u, its transpose (l along v) to fix v.  Returns
-// A[k] = sum_l B_l(f) M[k][l] and dA[k] = sum_l B'_l(f) M[k][l], k along the
-// parameter that remains free.
+// Line-contraction tiles (see tile_fix): for every element, the tile with both
+// parameters converted by cm (monomial basis, or identity), stored as itself
+// (out[0]) and with the two parameters exchanged (out[1]).  One thread per entry.
+__global__ void k_tline(int nelem, int G1, const double *__restrict__ cm, const double *__restrict__ tiles,
+                        double *__restrict__ out)
+{
+    const int64_t ts = (int64_t)G1 * G1 * 4;
+    const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= (int64_t)nelem * ts) return;
+    const int64_t E = x / ts;
+    const int r = (int)(x % ts), c = r & 3, j = (r >> 2) / G1, i = (r >> 2) % G1;
+    const double *H = tiles + E * ts;
+    double acc = 0.0;
+    for (int jj = 0; jj <= j; ++jj)
+        for (int ii = 0; ii <= i; ++ii) acc += cm[j * G1 + jj] * cm[i * G1 + ii] * H[(jj * G1 + ii) * 4 + c];
+    out[E * ts + (j * G1 + i) * 4 + c] = acc;
+    out[((int64_t)nelem + E) * ts + (i * G1 + j) * 4 + c] = acc;
+}
+
+// 1/x for finite x != 0: the hardware estimate refined by two Newton steps.
+__device__ inline double rcp_nz(double x)
+{
+    double y = __builtin_amdgcn_rcp(x);
+    y = fma(y, fma(-x, y, 1.0), y);
+    return fma(y, fma(-x, y, 1.0), y);
+}
+
+// Line contraction of an element tile (rational, bidegree (PG, PG), homogeneous
+// (x w, y w, z w, w)).  M holds the tile with the parameter to be fixed
+// fastest, M[(k*(PG+1) + l)*4 + c] (the tile itself to fix u, its transpose to
+// fix v), in the monomial basis t^l of both parameters when PG <= 4 (Horner
+// evaluation; the conversion from Bernstein form is exact up to rounding) and
+// in Bernstein form otherwise.  Returns A[k] = sum_l b_l(f) M[k][l] and
+// dA[k] = sum_l b_l'(f) M[k][l], k along the parameter that remains free.
 template <int PG>
 __device__ inline void tile_fix(const double *M, double f, double A[PG + 1][4], double dA[PG + 1][4])
 {
     constexpr int G1 = PG + 1;
-    double B[G1], dB[G1];
-    bernstein_d_t<PG>(f, B, dB);
+    if constexpr (PG <= 4) {
 #pragma unroll
-    for (int k = 0; k < G1; ++k)
+        for (int k = 0; k < G1; ++k)
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            double x = 0.0, d = 0.0;
+            for (int c = 0; c < 4; ++c) {
+                double x = M[(k * G1 + PG) * 4 + c], d = 0.0;
 #pragma unroll
-            for (int l = 0; l < G1; ++l) {
-                const double h = M[(k * G1 + l) * 4 + c];
-                x += B[l] * h;
-                d += dB[l] * h;
+                for (int l = PG - 1; l >= 0; --l) {
+                    d = fma(d, f, x);
+                    x = fma(x, f, M[(k * G1 + l) * 4 + c]);
+                }
+                A[k][c] = x;
+                dA[k][c] = d;
             }
-            A[k][c] = x;
-            dA[k][c] = d;
-        }
+    } else {
+        double B[G1], dB[G1];
+        bernstein_d_t<PG>(f, B, dB);
+#pragma unroll
+        for (int k = 0; k < G1; ++k)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                double x = 0.0, d = 0.0;
+#pragma unroll
+                for (int l = 0; l < G1; ++l) {
+                    const double h = M[(k * G1 + l) * 4 + c];
+                    x += B[l] * h;
+                    d += dB[l] * h;
+                }
+                A[k][c] = x;
+                dA[k][c] = d;
+            }
+    }
 }
 
 // Point and surface measure of the tile at value w of the remaining parameter,
-// from its partial contraction (the measure |X_u x X_v| does not depend on the
-// order of the two tangents).
+// from its line contraction (the measure |X_u x X_v| does not depend on the
+// order of the two tangents).  With homogeneous S, tangents D1, D2 and
+// X = S_xyz / S_w, |X_u x X_v| = |(D1 - X D1_w) x (D2 - X D2_w)| / S_w^2.
 template <int PG>
 __device__ inline void tile_line_point(const double A[PG + 1][4], const double dA[PG + 1][4], double w, double X[3],
                                        double *kap)
 {
     constexpr int G1 = PG + 1;
-    double B[G1], dB[G1];
-    bernstein_d_t<PG>(w, B, dB);
-    double S[4] = {0, 0, 0, 0}, D1[4] = {0, 0, 0, 0}, D2[4] = {0, 0, 0, 0};
-#pragma unroll
-    for (int k = 0; k < G1; ++k)
+    double S[4], D1[4], D2[4];
+    if constexpr (PG <= 4) {
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
-            S[c] += B[k] * A[k][c];
-            D1[c] += dB[k] * A[k][c];
-            D2[c] += B[k] * dA[k][c];
+            double x = A[PG][c], d = 0.0, e = dA[PG][c];
+#pragma unroll
+            for (int k = PG - 1; k >= 0; --k) {
+                d = fma(d, w, x);
+                x = fma(x, w, A[k][c]);
+                e = fma(e, w, dA[k][c]);
+            }
+            S[c] = x;
+            D1[c] = d;
+            D2[c] = e;
         }
-    const double iw = 1.0 / S[3];
+    } else {
+        double B[G1], dB[G1];
+        bernstein_d_t<PG>(w, B, dB);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) S[c] = D1[c] = D2[c] = 0.0;
+#pragma unroll
+        for (int k = 0; k < G1; ++k)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                S[c] += B[k] * A[k][c];
+                D1[c] += dB[k] * A[k][c];
+                D2[c] += B[k] * dA[k][c];
+            }
+    }
+    const double iw = rcp_nz(S[3]);
     const double x0 = S[0] * iw, x1 = S[1] * iw, x2 = S[2] * iw;
-    const double a0 = (D1[0] - x0 * D1[3]) * iw, a1 = (D1[1] - x1 * D1[3]) * iw, a2 = (D1[2] - x2 * D1[3]) * iw;
-    const double b0 = (D2[0] - x0 * D2[3]) * iw, b1 = (D2[1] - x1 * D2[3]) * iw, b2 = (D2[2] - x2 * D2[3]) * iw;
+    const double a0 = D1[0] - x0 * D1[3], a1 = D1[1] - x1 * D1[3], a2 = D1[2] - x2 * D1[3];
+    const double b0 = D2[0] - x0 * D2[3], b1 = D2[1] - x1 * D2[3], b2 = D2[2] - x2 * D2[3];
     X[0] = x0;
     X[1] = x1;
     X[2] = x2;
     const double n0 = a1 * b2 - a2 * b1, n1 = a2 * b0 - a0 * b2, n2 = a0 * b1 - a1 * b0;
-    *kap = sqrt(n0 * n0 + n1 * n1 + n2 * n2);
+    const double nn = n0 * n0 + n1 * n1 + n2 * n2;
+    *kap = nn > 0.0 ? nn * rsqrt_pos(nn) * (iw * iw) : 0.0;
 }
 
 // One element's reference point along a quadrature line: (u, v) = (u0, v0) +
@@ -271,8 +335,8 @@ __device__ inline bool frame_fix_u(int o, int a, int b, bool move_s)
 __device__ inline double from_pair_lane(double v)
 {
     const int lo = __double2loint(v), hi = __double2hiint(v);
-    const int plo = __builtin_amdgcn_update_dpp(0, lo, 0xB1, 0xF, 0xF, false);
-    const int phi = __builtin_amdgcn_update_dpp(0, hi, 0xB1, 0xF, 0xF, false);
+    const int plo = __builtin_amdgcn_update_dpp(lo, lo, 0xB1, 0xF, 0xF, false);
+    const int phi = __builtin_amdgcn_update_dpp(hi, hi, 0xB1, 0xF, 0xF, false);
     return __hiloint2double(phi, plo);
 }
 
@@ -296,7 +360,7 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 template <class T, int P, int PG, int WAVES>
 __global__ void __launch_bounds__(64 * WAVES, NComp<T>::value == 1 ? 2 : 1) k_near_singular(
     const PairRec *__restrict__ pairs, int gs, const double *__restrict__ gxs, const double *__restrict__ gws,
-    const double *__restrict__ tiles, const double *__restrict__ tilesT, double kappa, T *__restrict__ pairbuf)
+    const double *__restrict__ tfix_u, const double *__restrict__ tfix_v, double kappa, T *__restrict__ pairbuf)
 {
     constexpr int P1 = P + 1, NLOC = P1 * P1, NT = (NLOC + 15) / 16, NPAD = 16 * NT;
     constexpr int NC = NComp<T>::value;
@@ -402,7 +466,7 @@ __global__ void __launch_bounds__(64 * WAVES, NComp<T>::value == 1 ? 2 : 1) k_ne
         const bool cst = role == 0 && constE;
         const double f = fix_u ? L.u0 : L.v0;
         double A[G1][4], dA[G1][4];
-        tile_fix<PG>((fix_u ? tiles : tilesT) + (size_t)elem * TS, f, A, dA);
+        tile_fix<PG>((fix_u ? tfix_u : tfix_v) + (size_t)elem * TS, f, A, dA);
         double bf[P1], bm[P1], X[3], kap = 0.0;
         bernstein_t<P>(f, bf);
         if (cst) {  // vertex, element E: one point for the whole line
@@ -432,22 +496,23 @@ __global__ void __launch_bounds__(64 * WAVES, NComp<T>::value == 1 ? 2 : 1) k_ne
                 cim = sn * f0;
             }
             if (role) cre = 1.0;  // lane 2k+1 stages F's Bernstein products unweighted
-            // u / v Bernstein vectors of this lane's element
-            double b1[P1], b2[P1];
+            // u / v Bernstein vectors of this lane's element, the weight folded into the v one
+            double b1[P1], b2[P1], b2i[P1];
 #pragma unroll
             for (int a = 0; a < P1; ++a) {
                 b1[a] = fix_u ? bf[a] : bm[a];
-                b2[a] = fix_u ? bm[a] : bf[a];
+                const double v = fix_u ? bm[a] : bf[a];
+                b2[a] = cre * v;
+                if constexpr (NC == 2) b2i[a] = cim * v;
             }
             double *dst = (role ? Vb : Ub) + pl * RS;
 #pragma unroll
             for (int a2 = 0; a2 < P1; ++a2)
 #pragma unroll
                 for (int a1 = 0; a1 < P1; ++a1) {
-                    const double fx = b1[a1] * b2[a2];
-                    dst[a2 * P1 + a1] = cre * fx;
+                    dst[a2 * P1 + a1] = b1[a1] * b2[a2];
                     if constexpr (NC == 2)
-                        if (!role) Ub[HALF * RS + pl * RS + a2 * P1 + a1] = cim * fx;
+                        if (!role) Ub[HALF * RS + pl * RS + a2 * P1 + a1] = b1[a1] * b2i[a2];
                 }
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
@@ -1612,7 +1677,7 @@ struct igb_operator {
     int lmin = 0;  // coarsest level with far blocks (L+1 if none)
     // device data
     double *tiles = nullptr;
-    double *tilesT = nullptr;  // each tile with its two parameters exchanged
+    double *tline = nullptr;   // line-contraction tiles: [0] tile, [1] transpose (see tile_fix)
     int32_t *tdeg = nullptr;
     double *gx = nullptr, *gw = nullptr;
     double *btab = nullptr;        // per order n: n*(p+1) Bernstein values, offset goff[n]*(p+1)
@@ -1757,7 +1822,8 @@ static igb_status launch_singular_pg(igb_operator *op, const PairRec *d_pairs, i
     for (int64_t off = 0; off < n; off += 1 << 20) {
         int64_t cnt = std::min<int64_t>(n - off, 1 << 20);
         hipLaunchKernelGGL((k_near_singular<T, P, PG, WAVES>), dim3((unsigned)cnt), dim3(64 * WAVES), shm, op->st,
-                           d_pairs + off, gs, op->gx + op->s.goff[gs], op->gw + op->s.goff[gs], op->tiles, op->tilesT,
+                           d_pairs + off, gs, op->gx + op->s.goff[gs], op->gw + op->s.goff[gs], op->tline,
+                           op->tline + (size_t)op->s.nelem * op->s.tile_stride,
                            op->s.kappa,
                            (T *)op->pairbuf + off * NLOC * NLOC);
         LAUNCHCHK();
@@ -2142,15 +2208,28 @@ static igb_status create_device_geometry(igb_operator *op)
     int q2 = s.q * s.q;
     if ((rc = upload(op, &op->tiles, s.tiles.data(), s.tiles.size() * sizeof(double)))) return rc;
     {
-        const int G1 = s.tile_degree + 1;
-        std::vector<double> tt(s.tiles.size());
-        for (int64_t E = 0; E < s.nelem; ++E)
-            for (int j = 0; j < G1; ++j)
-                for (int i = 0; i < G1; ++i)
-                    for (int c = 0; c < 4; ++c)
-                        tt[(size_t)E * s.tile_stride + (i * G1 + j) * 4 + c] =
-                            s.tiles[(size_t)E * s.tile_stride + (j * G1 + i) * 4 + c];
-        if ((rc = upload(op, &op->tilesT, tt.data(), tt.size() * sizeof(double)))) return rc;
+        // line-contraction tiles of the touching-pair quadrature (see tile_fix), built on
+        // the device from the element tiles: cm[l*G1 + k] = coefficient of t^l in the
+        // Bernstein polynomial B_k of degree PG (identity when PG > 4: Bernstein form kept)
+        const int PG = s.tile_degree, G1 = PG + 1;
+        std::vector<double> cm((size_t)G1 * G1, 0.0);
+        if (PG <= 4) {
+            auto binom = [](int n, int k) {
+                double c = 1.0;
+                for (int i = 1; i <= k; ++i) c = c * (n - k + i) / i;
+                return c;
+            };
+            for (int l = 0; l <= PG; ++l)
+                for (int k = 0; k <= l; ++k) cm[(size_t)l * G1 + k] = ((l - k) & 1 ? -1.0 : 1.0) * binom(PG, l) * binom(l, k);
+        } else {
+            for (int k = 0; k <= PG; ++k) cm[(size_t)k * G1 + k] = 1.0;
+        }
+        double *dcm = nullptr;
+        if ((rc = upload(op, &dcm, cm.data(), cm.size() * sizeof(double)))) return rc;
+        if ((rc = dalloc(op, (void **)&op->tline, (size_t)2 * s.nelem * s.tile_stride * sizeof(double)))) return rc;
+        const int64_t n = (int64_t)s.nelem * G1 * G1 * 4;
+        hipLaunchKernelGGL(k_tline, dim3(nblk(n, 256)), dim3(256), 0, op->st, s.nelem, G1, dcm, op->tiles, op->tline);
+        LAUNCHCHK();
     }
     if ((rc = upload(op, &op->tdeg, s.tile_deg.data(), s.tile_deg.size() * sizeof(int32_t)))) return rc;
     if ((rc = upload(op, &op->gx, s.gx.data(), s.gx.size() * sizeof(double)))) return rc;

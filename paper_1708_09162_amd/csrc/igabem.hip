@@ -872,20 +872,23 @@ __device__ inline void load8(const T *p, T v[8])
     }
 }
 
+struct NearSymArgs {
+    int64_t nsb;
+    const int32_t *sb_t, *sb_s;
+    int nl, ld;
+};
+
+// One stored near block k, executed by one whole wave; cacc is the wave's LDS
+// slice of 8 ld + 520 elements.
 template <class T>
-__global__ void __launch_bounds__(256) k_near_sym(int64_t nsb, const int32_t *__restrict__ sb_t,
-                                                  const int32_t *__restrict__ sb_s, int nl, int ld,
-                                                  const T *__restrict__ blocks, const T *__restrict__ x,
-                                                  T *__restrict__ part)
+__device__ inline void near_sym_wave(const NearSymArgs &N, int64_t k, const T *__restrict__ blocks,
+                                     const T *__restrict__ x, T *__restrict__ part, T *cacc)
 {
-    extern __shared__ double sh[];
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int64_t k = (int64_t)blockIdx.x * (blockDim.x >> 6) + wave;
-    if (k >= nsb) return;  // whole waves only; no block-wide barrier follows
+    const int nl = N.nl, ld = N.ld;
+    const int lane = threadIdx.x & 63;
     const int li = lane >> 3, lj = lane & 7;
-    const int64_t t = sb_t[k], sc = sb_s[k];
-    T *cacc = (T *)sh + (size_t)wave * (8 * ld + 520);  // [li][column]
-    T *rbuf = cacc + 8 * ld;                              // [lj][row of the tile], row stride 65
+    const int64_t t = N.sb_t[k], sc = N.sb_s[k];
+    T *rbuf = cacc + 8 * ld;  // [lj][row of the tile], row stride 65; cacc: [li][column]
     const T *B = blocks + k * (int64_t)nl * ld;
     const T *xt = x + t * nl, *xsrc = x + sc * nl;
     T *prow = part + (size_t)(2 * k) * ld;
@@ -935,30 +938,57 @@ __global__ void __launch_bounds__(256) k_near_sym(int64_t nsb, const int32_t *__
     }
 }
 
-// out[t*n + a] (t >= row0) = sum over the CSR entries e of row t, in order, of
-// part[pidx[e]*ld + a], times scale * w[(t*n + a)*4] when w is given (node
-// weights of the far field).  Four waves per row take every fourth entry; the
-// four partial sums are added in wave order.
 template <class T>
-__global__ void __launch_bounds__(256) k_gather(int n, int ld, const int64_t *__restrict__ ptr,
-                                                const int32_t *__restrict__ pidx, const T *__restrict__ part,
-                                                const double *__restrict__ w, double scale, T *__restrict__ out,
-                                                int64_t row0)
+__global__ void __launch_bounds__(256) k_near_sym(NearSymArgs N, const T *__restrict__ blocks, const T *__restrict__ x,
+                                                  T *__restrict__ part)
+{
+    extern __shared__ double sh[];
+    const int wave = threadIdx.x >> 6;
+    const int64_t k = (int64_t)blockIdx.x * (blockDim.x >> 6) + wave;
+    if (k >= N.nsb) return;  // whole waves only; no block-wide barrier follows
+    near_sym_wave<T>(N, k, blocks, x, part, (T *)sh + (size_t)wave * (8 * N.ld + 520));
+}
+
+
+// Sum of partial rows: out[t*n + a] (t = row0 + r, r < rows) = sum over the CSR
+// entries e of row t, in order, of part[pidx[e]*ld + a], times
+// scale * w[(t*n + a)*4] when w is given (node weights of the far field).
+struct GatherArgs {
+    int n, ld;
+    const int64_t *ptr;
+    const int32_t *pidx;
+    const void *part;
+    const double *w;
+    double scale;
+    void *out;
+    int64_t row0;
+};
+
+// Workgroups [0, nb_a) gather the rows of A, the rest those of B (one launch for
+// the far-field and the near-field partial rows).  Four waves per row take every
+// fourth entry; the four partial sums are added in wave order.
+template <class T>
+__global__ void __launch_bounds__(256) k_gather(GatherArgs A, GatherArgs B, int64_t nb_a)
 {
     extern __shared__ double sh[];
     T *red = (T *)sh;  // [4][n]
+    const bool first = (int64_t)blockIdx.x < nb_a;
+    const GatherArgs &G = first ? A : B;
+    const int n = G.n, ld = G.ld;
+    const T *part = (const T *)G.part;
+    T *out = (T *)G.out;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int64_t t = row0 + blockIdx.x;
-    const int64_t k0 = ptr[t], k1 = ptr[t + 1];
+    const int64_t t = G.row0 + (first ? (int64_t)blockIdx.x : (int64_t)blockIdx.x - nb_a);
+    const int64_t k0 = G.ptr[t], k1 = G.ptr[t + 1];
     for (int a = lane; a < n; a += 64) {
         T acc = zero<T>();
-        for (int64_t e = k0 + wave; e < k1; e += 4) acc += part[(size_t)pidx[e] * ld + a];
+        for (int64_t e = k0 + wave; e < k1; e += 4) acc += part[(size_t)G.pidx[e] * ld + a];
         red[wave * n + a] = acc;
     }
     __syncthreads();
     for (int a = threadIdx.x; a < n; a += blockDim.x) {
         T v = red[a] + red[n + a] + red[2 * n + a] + red[3 * n + a];
-        if (w) v = v * (scale * w[((size_t)t * n + a) * 4]);
+        if (G.w) v = v * (G.scale * G.w[((size_t)t * n + a) * 4]);
         out[(size_t)t * n + a] = v;
     }
 }
@@ -1054,21 +1084,32 @@ __global__ void __launch_bounds__(256) k_far_onthefly(int q2, const int64_t *__r
 // (q^2 <= 8 TT).  The unscaled products are written as partial rows:
 // part[2k] = sum_j G_ij w_j X_s[j] (for cluster t), part[2k+1] = sum_i G_ij w_i X_t[i]
 // (for cluster s); k_far_gather sums them per cluster and applies the weights.
+struct FarSymArgs {
+    int64_t nup;
+    const int32_t *up_t, *up_s;
+    int q2;
+    const double *nodes;
+    double kappa;
+};
+
+// LDS elements of T per wave for far_sym_wave
+template <int TT>
+constexpr int far_sym_lds() { return 8 * (8 * TT + 1); }
+
+// One mirrored pair k of the far field, executed by one whole wave; cb is the
+// wave's LDS slice of far_sym_lds<TT>() elements.
 template <class T, int TT>
-__global__ void __launch_bounds__(256) k_far_sym(int64_t nup, const int32_t *__restrict__ up_t,
-                                                 const int32_t *__restrict__ up_s, int q2,
-                                                 const double *__restrict__ nodes, const T *__restrict__ Xh,
-                                                 double kappa, T *__restrict__ part)
+__device__ inline void far_sym_wave(const FarSymArgs &F, int64_t k, const T *__restrict__ Xh, T *__restrict__ part,
+                                    T *cb)
 {
     constexpr int W = 8 * TT;  // padded nodes per cluster
     constexpr int WS = W + 1;  // LDS row stride (spreads the 8 rows over the banks)
-    __shared__ T buf[4][8 * WS];
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int64_t k = (int64_t)blockIdx.x * 4 + wave;
-    if (k >= nup) return;  // whole waves only; no block-wide barrier follows
+    const int q2 = F.q2;
+    const double *__restrict__ nodes = F.nodes;
+    const double kappa = F.kappa;
+    const int lane = threadIdx.x & 63;
     const int li = lane >> 3, lj = lane & 7;
-    const int64_t t = up_t[k], sc = up_s[k];
-    T *cb = buf[wave];
+    const int64_t t = F.up_t[k], sc = F.up_s[k];
     double tx[TT], ty[TT], tz[TT];
     T wt[TT], racc[TT];
 #pragma unroll
@@ -1151,6 +1192,41 @@ __global__ void __launch_bounds__(256) k_far_sym(int64_t nup, const int32_t *__r
 #pragma unroll
         for (int r = 1; r < 8; ++r) v += cb[r * WS + i];
         pr[i] = v;
+    }
+}
+
+template <class T, int TT>
+__global__ void __launch_bounds__(256) k_far_sym(FarSymArgs F, const T *__restrict__ Xh, T *__restrict__ part)
+{
+    __shared__ T buf[4][far_sym_lds<TT>()];
+    const int wave = threadIdx.x >> 6;
+    const int64_t k = (int64_t)blockIdx.x * 4 + wave;
+    if (k >= F.nup) return;  // whole waves only; no block-wide barrier follows
+    far_sym_wave<T, TT>(F, k, Xh, part, buf[wave]);
+}
+
+// The far-field pairs and the stored near blocks in one launch (ALU-bound and
+// HBM-bound work on the same CUs): nf far workgroups and nn near workgroups of
+// four waves, the near ones spread evenly through the grid (workgroup b is near
+// iff floor((b+1) nn / (nf+nn)) > floor(b nn / (nf+nn))).
+template <class T, int TT>
+__global__ void __launch_bounds__(256) k_sym_products(FarSymArgs F, NearSymArgs N, int64_t nf, int64_t nn,
+                                                      const T *__restrict__ Xh, T *__restrict__ fpart,
+                                                      const T *__restrict__ blocks, const T *__restrict__ x,
+                                                      T *__restrict__ npart)
+{
+    extern __shared__ double sh[];
+    const int wave = threadIdx.x >> 6;
+    const int64_t b = blockIdx.x, tot = nf + nn;
+    const int64_t before = b * nn / tot, upto = (b + 1) * nn / tot;
+    if (upto > before) {
+        const int64_t k = before * 4 + wave;
+        if (k >= N.nsb) return;
+        near_sym_wave<T>(N, k, blocks, x, npart, (T *)sh + (size_t)wave * (8 * N.ld + 520));
+    } else {
+        const int64_t k = (b - before) * 4 + wave;
+        if (k >= F.nup) return;
+        far_sym_wave<T, TT>(F, k, Xh, fpart, (T *)sh + (size_t)wave * far_sym_lds<TT>());
     }
 }
 
@@ -1778,6 +1854,20 @@ static NearLayout near_layout(const Setup &s, size_t esz)
     return L;
 }
 
+// With both products symmetric, the near blocks ride along in the far-field
+// launch (and both gathers share one launch) when four waves' near staging fits
+// 64 KB of LDS.
+static bool fused_products(bool near_sym, int near_ld, size_t esz)
+{
+    return near_sym && 4 * (size_t)(8 * near_ld + 520) * esz <= 64 * 1024;
+}
+
+// Far field evaluated once per mirrored pair of blocks (on the fly, q^2 <= 64).
+static bool far_mirrored(const Setup &s)
+{
+    return s.mode == IGB_H2_ONTHEFLY && s.q * s.q <= 64 && !s.far_src.empty();
+}
+
 static int64_t csr_find_host(const Setup &s, int t, int src)
 {
     auto b = s.near_src.begin() + s.near_ptr[t], e = s.near_src.begin() + s.near_ptr[t + 1];
@@ -1878,11 +1968,28 @@ static igb_status launch_singular(igb_operator *op, const PairRec *d, int64_t n)
 // stages 0 upward (leaf moments and transfers), 1 coupling blocks, 2 coupling
 // gather (on the fly by mirrored pairs only), 3 near GEMV, 4 near gather
 // (symmetric near storage only), 5 downward (transfers and leaf back-moments).
-template <class T, int TT>
-static void launch_far_sym(igb_operator *op, const T *Xh)
+static FarSymArgs far_args(const igb_operator *op)
 {
-    hipLaunchKernelGGL((k_far_sym<T, TT>), dim3((unsigned)((op->nup + 3) / 4)), dim3(256), 0, op->st, op->nup, op->up_t,
-                       op->up_s, op->s.q * op->s.q, op->nodes, Xh, op->s.kappa, (T *)op->fpart);
+    return FarSymArgs{op->nup, op->up_t, op->up_s, op->s.q * op->s.q, op->nodes, op->s.kappa};
+}
+static NearSymArgs near_args(const igb_operator *op)
+{
+    return NearSymArgs{op->nsb, op->sb_t, op->sb_s, op->s.nl, op->near_ld};
+}
+
+// far pairs alone, or (fuse) far pairs and stored near blocks in one launch
+template <class T, int TT>
+static void launch_far_sym(igb_operator *op, const T *Xh, const T *xs, bool fuse)
+{
+    if (!fuse) {
+        hipLaunchKernelGGL((k_far_sym<T, TT>), dim3((unsigned)((op->nup + 3) / 4)), dim3(256), 0, op->st, far_args(op), Xh,
+                           (T *)op->fpart);
+        return;
+    }
+    const int64_t nf = (op->nup + 3) / 4, nn = (op->nsb + 3) / 4;
+    const size_t shm = 4 * std::max<size_t>((size_t)(8 * op->near_ld + 520), (size_t)far_sym_lds<TT>()) * sizeof(T);
+    hipLaunchKernelGGL((k_sym_products<T, TT>), dim3((unsigned)(nf + nn)), dim3(256), shm, op->st, far_args(op),
+                       near_args(op), nf, nn, Xh, (T *)op->fpart, (const T *)op->nearb, xs, (T *)op->npart);
 }
 
 // Slices of the cluster tree for k_up_tree / k_down_tree: (ls, lb) pairs from
@@ -1941,17 +2048,18 @@ static igb_status matvec_internal(igb_operator *op, const T *xs, T *ys, hipEvent
     if ((rc = mark(1))) return rc;
     int64_t row0 = s.cl_off[op->lmin], nrows = s.cl_off[s.L + 1] - row0;
     const bool sym = has_far && op->fpart != nullptr;
+    const bool fuse = sym && fused_products(op->near_sym, op->near_ld, sizeof(T));
     if (has_far) {
         if (sym) {
             switch ((q2 + 7) / 8) {
-            case 1: launch_far_sym<T, 1>(op, Xh); break;
-            case 2: launch_far_sym<T, 2>(op, Xh); break;
-            case 3: launch_far_sym<T, 3>(op, Xh); break;
-            case 4: launch_far_sym<T, 4>(op, Xh); break;
-            case 5: launch_far_sym<T, 5>(op, Xh); break;
-            case 6: launch_far_sym<T, 6>(op, Xh); break;
-            case 7: launch_far_sym<T, 7>(op, Xh); break;
-            default: launch_far_sym<T, 8>(op, Xh); break;
+            case 1: launch_far_sym<T, 1>(op, Xh, xs, fuse); break;
+            case 2: launch_far_sym<T, 2>(op, Xh, xs, fuse); break;
+            case 3: launch_far_sym<T, 3>(op, Xh, xs, fuse); break;
+            case 4: launch_far_sym<T, 4>(op, Xh, xs, fuse); break;
+            case 5: launch_far_sym<T, 5>(op, Xh, xs, fuse); break;
+            case 6: launch_far_sym<T, 6>(op, Xh, xs, fuse); break;
+            case 7: launch_far_sym<T, 7>(op, Xh, xs, fuse); break;
+            default: launch_far_sym<T, 8>(op, Xh, xs, fuse); break;
             }
         } else if (s.mode == IGB_H2_ONTHEFLY) {
             size_t shm = (size_t)4 * q2 * (3 + NComp<T>::value) * sizeof(double) + (size_t)4 * q2 * sizeof(T);
@@ -1964,29 +2072,35 @@ static igb_status matvec_internal(igb_operator *op, const T *xs, T *ys, hipEvent
         LAUNCHCHK();
     }
     if ((rc = mark(2))) return rc;
-    if (sym) {
-        hipLaunchKernelGGL((k_gather<T>), dim3((unsigned)nrows), dim3(256), 4 * q2 * sizeof(T), op->st, q2, q2,
-                           op->far_ptr, op->far_pidx, (const T *)op->fpart, op->nodes + 3, 0.07957747154594767, Yh,
-                           row0);
+    const GatherArgs GF{q2, q2, op->far_ptr, op->far_pidx, op->fpart, op->nodes + 3, 0.07957747154594767, Yh, row0};
+    const GatherArgs GN{s.nl, op->near_ld, op->near_ptr, op->near_pidx, op->npart, nullptr, 1.0, ys, 0};
+    if (fuse) {  // both gathers in one launch
+        hipLaunchKernelGGL((k_gather<T>), dim3((unsigned)(nrows + s.nleaf)), dim3(256),
+                           4 * std::max(q2, s.nl) * sizeof(T), op->st, GF, GN, nrows);
+        LAUNCHCHK();
+    } else if (sym) {
+        hipLaunchKernelGGL((k_gather<T>), dim3((unsigned)nrows), dim3(256), 4 * q2 * sizeof(T), op->st, GF, GF, nrows);
         LAUNCHCHK();
     }
     if ((rc = mark(3))) return rc;
-    if (op->near_sym) {
+    if (fuse) {
+        // done inside the far-field launch
+    } else if (op->near_sym) {
         const int ld = op->near_ld;
         const size_t wave_lds = (size_t)(8 * ld + 520) * sizeof(T);
         const int wpb = (int)std::max<size_t>(1, std::min<size_t>(4, (64 * 1024) / wave_lds));
         hipLaunchKernelGGL((k_near_sym<T>), dim3((unsigned)((op->nsb + wpb - 1) / wpb)), dim3(64 * wpb), wpb * wave_lds,
-                           op->st, op->nsb, op->sb_t, op->sb_s, s.nl, ld, (const T *)op->nearb, xs, (T *)op->npart);
+                           op->st, near_args(op), (const T *)op->nearb, xs, (T *)op->npart);
+        LAUNCHCHK();
     } else {
         hipLaunchKernelGGL((k_bsr_gemv<T, 0>), dim3(s.nleaf), dim3(256), 4 * s.nl * sizeof(T), op->st, s.nl,
                            op->near_ptr, op->near_src, (const T *)op->nearb, xs, ys, (int64_t)0);
+        LAUNCHCHK();
     }
-    LAUNCHCHK();
     if ((rc = mark(4))) return rc;
-    if (op->near_sym) {
-        hipLaunchKernelGGL((k_gather<T>), dim3(s.nleaf), dim3(256), 4 * s.nl * sizeof(T), op->st, s.nl, op->near_ld,
-                           op->near_ptr, op->near_pidx, (const T *)op->npart, (const double *)nullptr, 1.0, ys,
-                           (int64_t)0);
+    if (op->near_sym && !fuse) {
+        hipLaunchKernelGGL((k_gather<T>), dim3(s.nleaf), dim3(256), 4 * s.nl * sizeof(T), op->st, GN, GN,
+                           (int64_t)s.nleaf);
         LAUNCHCHK();
     }
     if ((rc = mark(5))) return rc;
@@ -2284,7 +2398,7 @@ static igb_status create_device_plan(igb_operator *op)
             for (int64_t k = s.far_ptr[c]; k < s.far_ptr[c + 1]; ++k) tg[k] = (int32_t)c;
         if ((rc = upload(op, &op->far_tgt, tg.data(), tg.size() * sizeof(int32_t)))) return rc;
     }
-    if (s.mode == IGB_H2_ONTHEFLY && s.q * s.q <= 64 && !s.far_src.empty()) {
+    if (far_mirrored(s)) {
         // mirrored pairs: entry e = (c, src) with src > c owns pair k; its mirror
         // (src, c) reads the column part of k
         int64_t nfar = (int64_t)s.far_src.size(), ncl = (int64_t)s.far_ptr.size() - 1;
@@ -2891,6 +3005,8 @@ static void fill_info(const Setup &s, size_t esz, igb_info *out)
     {
         NearLayout NL = near_layout(s, esz);
         out->near_bytes = NL.nsb * s.nl * NL.ld * (int64_t)esz;
+        const bool fm = far_mirrored(s);
+        out->layout_flags = (NL.sym ? 1 : 0) | (fm ? 2 : 0) | (fm && fused_products(NL.sym, NL.ld, esz) ? 4 : 0);
     }
     out->coupling_bytes = s.mode == IGB_H2_STORED ? out->n_far_blocks * q2 * q2 * (int64_t)esz : 0;
     // one superspace matvec moves every stored block once, the S* vector in and

@@ -56,7 +56,7 @@ class igb_params(C.Structure):
 class igb_info(C.Structure):
     _fields_ = [("n_dof", C.c_int64), ("n_dof_super", C.c_int64), ("n_elements", C.c_int64),
                 ("n_rhs_points", C.c_int64), ("leaf_level", C.c_int32), ("gauss_singular", C.c_int32),
-                ("gauss_rhs", C.c_int32), ("pad0", C.c_int32), ("n_near_blocks", C.c_int64),
+                ("gauss_rhs", C.c_int32), ("layout_flags", C.c_int32), ("n_near_blocks", C.c_int64),
                 ("n_far_blocks", C.c_int64), ("n_pairs", C.c_int64 * 4), ("near_bytes", C.c_int64),
                 ("coupling_bytes", C.c_int64), ("matvec_bytes", C.c_int64), ("setup_seconds", C.c_double),
                 ("assembly_seconds", C.c_double)]

@@ -111,3 +111,14 @@ def test_plan_matches_oracle_sphere_p3_m5_q8_full_size():
     info = _compare_plan(W.sphere_patches(), p=3, m=5, q=8, eta=1.6, gauss_regular=6)
     assert info.n_dof == 7350 and info.n_dof_super == 98304 and info.leaf_level == 4
     assert info.n_pairs[1] == 6144
+
+
+@pytest.mark.parametrize("mode,q,flags", [("stored", 8, 1), ("onthefly", 8, 7), ("onthefly", 10, 1)])
+def test_layout_flags(mode, q, flags):
+    """Symmetric near storage always at this size; mirrored far pairs and the shared launch only
+    on the fly with q^2 <= 64."""
+    g = igb.Geometry(W.sphere_patches())
+    m = igb.IGB_H2_STORED if mode == "stored" else igb.IGB_H2_ONTHEFLY
+    info = igb.Plan(g, p=1, m=4, q=q, eta=1.6, gauss_regular=4, mode=m).info
+    assert info.n_far_blocks > 0
+    assert info.layout_flags == flags

@@ -1092,24 +1092,47 @@ struct FarSymArgs {
     double kappa;
 };
 
-// LDS elements of T per wave for far_sym_wave
-template <int TT>
-constexpr int far_sym_lds() { return 8 * (8 * TT + 1); }
+// LDS doubles per wave for far_sym_wave: 8 rows of partial sums (row stride
+// 8 TT + 1) and the pair's source nodes (x, y, z, weighted moment).
+template <class T, int TT>
+constexpr int far_sym_lds() { return 8 * (8 * TT + 1) * NComp<T>::value + (3 + NComp<T>::value) * 8 * TT; }
 
-// One mirrored pair k of the far field, executed by one whole wave; cb is the
-// wave's LDS slice of far_sym_lds<TT>() elements.
+// One mirrored pair k of the far field, executed by one whole wave; lds is the
+// wave's slice of far_sym_lds<T, TT>() doubles.  Lane (li, lj) owns targets
+// li*TT + ii and sources jj*8 + lj (ii, jj < TT); the sources are staged in
+// LDS first, so that the evaluation loop reads no global memory.
 template <class T, int TT>
 __device__ inline void far_sym_wave(const FarSymArgs &F, int64_t k, const T *__restrict__ Xh, T *__restrict__ part,
-                                    T *cb)
+                                    double *lds)
 {
+    constexpr int NC = NComp<T>::value;
     constexpr int W = 8 * TT;  // padded nodes per cluster
     constexpr int WS = W + 1;  // LDS row stride (spreads the 8 rows over the banks)
+    T *cb = (T *)lds;
+    double *ssx = lds + 8 * WS * NC, *ssy = ssx + W, *ssz = ssy + W, *ssw = ssz + W;  // ssw: NC * W
     const int q2 = F.q2;
     const double *__restrict__ nodes = F.nodes;
     const double kappa = F.kappa;
     const int lane = threadIdx.x & 63;
     const int li = lane >> 3, lj = lane & 7;
     const int64_t t = F.up_t[k], sc = F.up_s[k];
+    // stage the source nodes (padding: far from every node, zero weight)
+    for (int j = lane; j < W; j += 64) {
+        double x = -1e100, y = 0.0, z = 0.0;
+        T wv = zero<T>();
+        if (j < q2) {
+            const double *nd = nodes + ((size_t)sc * q2 + j) * 4;
+            x = nd[0];
+            y = nd[1];
+            z = nd[2];
+            wv = Xh[(size_t)sc * q2 + j] * nd[3];
+        }
+        ssx[j] = x;
+        ssy[j] = y;
+        ssz[j] = z;
+        ssw[j] = re_(wv);
+        if constexpr (NC == 2) ssw[W + j] = im_(wv);
+    }
     double tx[TT], ty[TT], tz[TT];
     T wt[TT], racc[TT];
 #pragma unroll
@@ -1128,37 +1151,22 @@ __device__ inline void far_sym_wave(const FarSymArgs &F, int64_t k, const T *__r
             wt[ii] = zero<T>();
         }
     }
-    // source node jj (padding: far from every node, zero weight), loaded one ahead
-    auto load_src = [&](int jj, double &x, double &y, double &z, double &w, T &xv) {
-        const int j = lj * TT + jj;
-        x = -1e100;
-        y = z = w = 0.0;
-        xv = zero<T>();
-        if (jj < TT && j < q2) {
-            const double *nd = nodes + ((size_t)sc * q2 + j) * 4;
-            x = nd[0];
-            y = nd[1];
-            z = nd[2];
-            w = nd[3];
-            xv = Xh[(size_t)sc * q2 + j];
-        }
-    };
-    double nsx, nsy, nsz, nsw;
-    T nxv;
-    load_src(0, nsx, nsy, nsz, nsw, nxv);
-#pragma unroll 1
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+#pragma unroll 2
     for (int jj = 0; jj < TT; ++jj) {
-        const int j = lj * TT + jj;
-        const double sx = nsx, sy = nsy, sz = nsz;
-        const T ws = nxv * nsw;
-        load_src(jj + 1, nsx, nsy, nsz, nsw, nxv);
+        const int j = jj * 8 + lj;
+        const double sx = ssx[j], sy = ssy[j], sz = ssz[j];
+        T ws;
+        if constexpr (NC == 1) ws = ssw[j];
+        else ws = T{ssw[j], ssw[W + j]};
         T csum = zero<T>();
 #pragma unroll
         for (int ii = 0; ii < TT; ++ii) {
             const double d0 = tx[ii] - sx, d1 = ty[ii] - sy, d2 = tz[ii] - sz;
             const double r2 = d0 * d0 + d1 * d1 + d2 * d2;
             const double ir = rsqrt_pos(r2);
-            if constexpr (NComp<T>::value == 1) {
+            if constexpr (NC == 1) {
                 racc[ii] += ir * ws;
                 csum += ir * wt[ii];
             } else {
@@ -1169,15 +1177,16 @@ __device__ inline void far_sym_wave(const FarSymArgs &F, int64_t k, const T *__r
                 csum += g * wt[ii];
             }
         }
-        cb[li * WS + j] = csum;
+        cb[li * WS + lj * TT + jj] = csum;  // column of source j at lj*TT + jj (bank spread)
     }
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
     T *pc = part + (size_t)(2 * k + 1) * q2;
     for (int j = lane; j < q2; j += 64) {
-        T v = cb[j];
+        const int pj = (j & 7) * TT + (j >> 3);
+        T v = cb[pj];
 #pragma unroll
-        for (int r = 1; r < 8; ++r) v += cb[r * WS + j];
+        for (int r = 1; r < 8; ++r) v += cb[r * WS + pj];
         pc[j] = v;
     }
     __builtin_amdgcn_wave_barrier();
@@ -1198,7 +1207,7 @@ __device__ inline void far_sym_wave(const FarSymArgs &F, int64_t k, const T *__r
 template <class T, int TT>
 __global__ void __launch_bounds__(256) k_far_sym(FarSymArgs F, const T *__restrict__ Xh, T *__restrict__ part)
 {
-    __shared__ T buf[4][far_sym_lds<TT>()];
+    __shared__ double buf[4][far_sym_lds<T, TT>()];
     const int wave = threadIdx.x >> 6;
     const int64_t k = (int64_t)blockIdx.x * 4 + wave;
     if (k >= F.nup) return;  // whole waves only; no block-wide barrier follows
@@ -1219,14 +1228,16 @@ __global__ void __launch_bounds__(256) k_sym_products(FarSymArgs F, NearSymArgs 
     const int wave = threadIdx.x >> 6;
     const int64_t b = blockIdx.x, tot = nf + nn;
     const int64_t before = b * nn / tot, upto = (b + 1) * nn / tot;
+    // per-wave LDS slice (doubles): the larger of the two kinds
+    const int slice = max(far_sym_lds<T, TT>(), (8 * N.ld + 520) * NComp<T>::value);
     if (upto > before) {
         const int64_t k = before * 4 + wave;
         if (k >= N.nsb) return;
-        near_sym_wave<T>(N, k, blocks, x, npart, (T *)sh + (size_t)wave * (8 * N.ld + 520));
+        near_sym_wave<T>(N, k, blocks, x, npart, (T *)(sh + (size_t)wave * slice));
     } else {
         const int64_t k = (b - before) * 4 + wave;
         if (k >= F.nup) return;
-        far_sym_wave<T, TT>(F, k, Xh, fpart, (T *)sh + (size_t)wave * far_sym_lds<TT>());
+        far_sym_wave<T, TT>(F, k, Xh, fpart, sh + (size_t)wave * slice);
     }
 }
 
@@ -1987,7 +1998,8 @@ static void launch_far_sym(igb_operator *op, const T *Xh, const T *xs, bool fuse
         return;
     }
     const int64_t nf = (op->nup + 3) / 4, nn = (op->nsb + 3) / 4;
-    const size_t shm = 4 * std::max<size_t>((size_t)(8 * op->near_ld + 520), (size_t)far_sym_lds<TT>()) * sizeof(T);
+    const size_t shm =
+        4 * std::max<size_t>((size_t)(8 * op->near_ld + 520) * NComp<T>::value, (size_t)far_sym_lds<T, TT>()) * 8;
     hipLaunchKernelGGL((k_sym_products<T, TT>), dim3((unsigned)(nf + nn)), dim3(256), shm, op->st, far_args(op),
                        near_args(op), nf, nn, Xh, (T *)op->fpart, (const T *)op->nearb, xs, (T *)op->npart);
 }

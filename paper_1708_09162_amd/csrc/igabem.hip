@@ -1092,132 +1092,159 @@ struct FarSymArgs {
     double kappa;
 };
 
-// LDS doubles per wave for far_sym_wave: 8 rows of partial sums (row stride
-// 8 TT + 1) and the pair's source nodes (x, y, z, weighted moment).
-template <class T, int TT>
-constexpr int far_sym_lds() { return 8 * (8 * TT + 1) * NComp<T>::value + (3 + NComp<T>::value) * 8 * TT; }
+// Mirrored far-field pairs handled by one wave in a row (node data of the next
+// pair is loaded while the current one is evaluated).
+constexpr int kFarChunk = 4;
 
-// One mirrored pair k of the far field, executed by one whole wave; lds is the
-// wave's slice of far_sym_lds<T, TT>() doubles.  Lane (li, lj) owns targets
-// li*TT + ii and sources jj*8 + lj (ii, jj < TT); the sources are staged in
-// LDS first, so that the evaluation loop reads no global memory.
+// LDS doubles per wave for far_sym_chunk: 8 rows of partial sums (row stride
+// 8 TT + 1) and the pair's target and source nodes (x, y, z, weighted moment).
 template <class T, int TT>
-__device__ inline void far_sym_wave(const FarSymArgs &F, int64_t k, const T *__restrict__ Xh, T *__restrict__ part,
-                                    double *lds)
+constexpr int far_sym_lds() { return 8 * (8 * TT + 1) * NComp<T>::value + 2 * (3 + NComp<T>::value) * 8 * TT; }
+
+// Node data of one cluster's node j for the far field: position and the
+// weighted moment kappa_j X^[j] (padding nodes j >= q2: far from every node,
+// zero weight; targets and sources are pushed to opposite sides).
+template <class T>
+struct FarNode {
+    double x, y, z;
+    T w;
+};
+template <class T>
+__device__ inline FarNode<T> far_node(const FarSymArgs &F, const T *__restrict__ Xh, int64_t c, int j, double pad)
+{
+    FarNode<T> n{pad, 0.0, 0.0, zero<T>()};
+    if (j < F.q2) {
+        const double *nd = F.nodes + ((size_t)c * F.q2 + j) * 4;
+        n.x = nd[0];
+        n.y = nd[1];
+        n.z = nd[2];
+        n.w = Xh[(size_t)c * F.q2 + j] * nd[3];
+    }
+    return n;
+}
+
+// Pairs k0 .. k1-1 of the far field, executed by one whole wave; lds is the
+// wave's slice of far_sym_lds<T, TT>() doubles.  Lane (li, lj) owns targets
+// li*TT + ii and sources jj*8 + lj (ii, jj < TT); node data comes from LDS.
+template <class T, int TT>
+__device__ inline void far_sym_chunk(const FarSymArgs &F, int64_t k0, int64_t k1, const T *__restrict__ Xh,
+                                     T *__restrict__ part, double *lds)
 {
     constexpr int NC = NComp<T>::value;
     constexpr int W = 8 * TT;  // padded nodes per cluster
     constexpr int WS = W + 1;  // LDS row stride (spreads the 8 rows over the banks)
     T *cb = (T *)lds;
-    double *ssx = lds + 8 * WS * NC, *ssy = ssx + W, *ssz = ssy + W, *ssw = ssz + W;  // ssw: NC * W
+    double *tg = lds + 8 * WS * NC, *sr = tg + (3 + NC) * W;  // [x | y | z | w (NC)] x W each
     const int q2 = F.q2;
-    const double *__restrict__ nodes = F.nodes;
     const double kappa = F.kappa;
     const int lane = threadIdx.x & 63;
     const int li = lane >> 3, lj = lane & 7;
-    const int64_t t = F.up_t[k], sc = F.up_s[k];
-    // stage the source nodes (padding: far from every node, zero weight)
-    for (int j = lane; j < W; j += 64) {
-        double x = -1e100, y = 0.0, z = 0.0;
-        T wv = zero<T>();
-        if (j < q2) {
-            const double *nd = nodes + ((size_t)sc * q2 + j) * 4;
-            x = nd[0];
-            y = nd[1];
-            z = nd[2];
-            wv = Xh[(size_t)sc * q2 + j] * nd[3];
-        }
-        ssx[j] = x;
-        ssy[j] = y;
-        ssz[j] = z;
-        ssw[j] = re_(wv);
-        if constexpr (NC == 2) ssw[W + j] = im_(wv);
+    auto stage = [&](double *d, int j, const FarNode<T> &n) {
+        d[j] = n.x;
+        d[W + j] = n.y;
+        d[2 * W + j] = n.z;
+        d[3 * W + j] = re_(n.w);
+        if constexpr (NC == 2) d[4 * W + j] = im_(n.w);
+    };
+    // lane j < W holds target node j and source node j of the next pair (W <= 64)
+    FarNode<T> nt{}, ns{};
+    if (lane < W) {
+        nt = far_node<T>(F, Xh, F.up_t[k0], lane, 1e100);
+        ns = far_node<T>(F, Xh, F.up_s[k0], lane, -1e100);
     }
-    double tx[TT], ty[TT], tz[TT];
-    T wt[TT], racc[TT];
-#pragma unroll
-    for (int ii = 0; ii < TT; ++ii) {
-        const int i = li * TT + ii;
-        racc[ii] = zero<T>();
-        if (i < q2) {
-            const double *nd = nodes + ((size_t)t * q2 + i) * 4;
-            tx[ii] = nd[0];
-            ty[ii] = nd[1];
-            tz[ii] = nd[2];
-            wt[ii] = Xh[(size_t)t * q2 + i] * nd[3];
-        } else {  // padding: far from every node, zero weight
-            tx[ii] = 1e100;
-            ty[ii] = tz[ii] = 0.0;
-            wt[ii] = zero<T>();
+    for (int64_t k = k0; k < k1; ++k) {
+        if (lane < W) {
+            stage(tg, lane, nt);
+            stage(sr, lane, ns);
         }
-    }
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-#pragma unroll 2
-    for (int jj = 0; jj < TT; ++jj) {
-        const int j = jj * 8 + lj;
-        const double sx = ssx[j], sy = ssy[j], sz = ssz[j];
-        T ws;
-        if constexpr (NC == 1) ws = ssw[j];
-        else ws = T{ssw[j], ssw[W + j]};
-        T csum = zero<T>();
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        if (k + 1 < k1 && lane < W) {  // prefetch the next pair
+            nt = far_node<T>(F, Xh, F.up_t[k + 1], lane, 1e100);
+            ns = far_node<T>(F, Xh, F.up_s[k + 1], lane, -1e100);
+        }
+        double tx[TT], ty[TT], tz[TT];
+        T wt[TT], racc[TT];
 #pragma unroll
         for (int ii = 0; ii < TT; ++ii) {
-            const double d0 = tx[ii] - sx, d1 = ty[ii] - sy, d2 = tz[ii] - sz;
-            const double r2 = d0 * d0 + d1 * d1 + d2 * d2;
-            const double ir = rsqrt_pos(r2);
-            if constexpr (NC == 1) {
-                racc[ii] += ir * ws;
-                csum += ir * wt[ii];
-            } else {
-                double sn, cs;
-                sincos(kappa * (r2 * ir), &sn, &cs);
-                const T g{cs * ir, sn * ir};
-                racc[ii] += g * ws;
-                csum += g * wt[ii];
-            }
+            const int i = li * TT + ii;
+            tx[ii] = tg[i];
+            ty[ii] = tg[W + i];
+            tz[ii] = tg[2 * W + i];
+            if constexpr (NC == 1) wt[ii] = tg[3 * W + i];
+            else wt[ii] = T{tg[3 * W + i], tg[4 * W + i]};
+            racc[ii] = zero<T>();
         }
-        cb[li * WS + lj * TT + jj] = csum;  // column of source j at lj*TT + jj (bank spread)
-    }
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-    T *pc = part + (size_t)(2 * k + 1) * q2;
-    for (int j = lane; j < q2; j += 64) {
-        const int pj = (j & 7) * TT + (j >> 3);
-        T v = cb[pj];
+#pragma unroll 2
+        for (int jj = 0; jj < TT; ++jj) {
+            const int j = jj * 8 + lj;
+            const double sx = sr[j], sy = sr[W + j], sz = sr[2 * W + j];
+            T ws;
+            if constexpr (NC == 1) ws = sr[3 * W + j];
+            else ws = T{sr[3 * W + j], sr[4 * W + j]};
+            T csum = zero<T>();
 #pragma unroll
-        for (int r = 1; r < 8; ++r) v += cb[r * WS + pj];
-        pc[j] = v;
-    }
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+            for (int ii = 0; ii < TT; ++ii) {
+                const double d0 = tx[ii] - sx, d1 = ty[ii] - sy, d2 = tz[ii] - sz;
+                const double r2 = d0 * d0 + d1 * d1 + d2 * d2;
+                const double ir = rsqrt_pos(r2);
+                if constexpr (NC == 1) {
+                    racc[ii] += ir * ws;
+                    csum += ir * wt[ii];
+                } else {
+                    double sn, cs;
+                    sincos(kappa * (r2 * ir), &sn, &cs);
+                    const T g{cs * ir, sn * ir};
+                    racc[ii] += g * ws;
+                    csum += g * wt[ii];
+                }
+            }
+            cb[li * WS + lj * TT + jj] = csum;  // column of source j at lj*TT + jj (bank spread)
+        }
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        T *pc = part + (size_t)(2 * k + 1) * q2;
+        for (int j = lane; j < q2; j += 64) {
+            const int pj = (j & 7) * TT + (j >> 3);
+            T v = cb[pj];
 #pragma unroll
-    for (int ii = 0; ii < TT; ++ii) cb[lj * WS + li * TT + ii] = racc[ii];
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-    T *pr = part + (size_t)(2 * k) * q2;
-    for (int i = lane; i < q2; i += 64) {
-        T v = cb[i];
+            for (int r = 1; r < 8; ++r) v += cb[r * WS + pj];
+            pc[j] = v;
+        }
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
 #pragma unroll
-        for (int r = 1; r < 8; ++r) v += cb[r * WS + i];
-        pr[i] = v;
+        for (int ii = 0; ii < TT; ++ii) cb[lj * WS + li * TT + ii] = racc[ii];
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        T *pr = part + (size_t)(2 * k) * q2;
+        for (int i = lane; i < q2; i += 64) {
+            T v = cb[i];
+#pragma unroll
+            for (int r = 1; r < 8; ++r) v += cb[r * WS + i];
+            pr[i] = v;
+        }
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
     }
 }
+
 
 template <class T, int TT>
 __global__ void __launch_bounds__(256) k_far_sym(FarSymArgs F, const T *__restrict__ Xh, T *__restrict__ part)
 {
     __shared__ double buf[4][far_sym_lds<T, TT>()];
     const int wave = threadIdx.x >> 6;
-    const int64_t k = (int64_t)blockIdx.x * 4 + wave;
-    if (k >= F.nup) return;  // whole waves only; no block-wide barrier follows
-    far_sym_wave<T, TT>(F, k, Xh, part, buf[wave]);
+    const int64_t k0 = ((int64_t)blockIdx.x * 4 + wave) * kFarChunk;
+    if (k0 >= F.nup) return;  // whole waves only; no block-wide barrier follows
+    far_sym_chunk<T, TT>(F, k0, min(k0 + kFarChunk, F.nup), Xh, part, buf[wave]);
 }
 
 // The far-field pairs and the stored near blocks in one launch (ALU-bound and
-// HBM-bound work on the same CUs): nf far workgroups and nn near workgroups of
-// four waves, the near ones spread evenly through the grid (workgroup b is near
-// iff floor((b+1) nn / (nf+nn)) > floor(b nn / (nf+nn))).
+// HBM-bound work on the same CUs): nf far workgroups (four waves of kFarChunk
+// pairs) and nn near workgroups (four waves of one block), the near ones spread
+// evenly through the grid (workgroup b is near iff
+// floor((b+1) nn / (nf+nn)) > floor(b nn / (nf+nn))).
 template <class T, int TT>
 __global__ void __launch_bounds__(256) k_sym_products(FarSymArgs F, NearSymArgs N, int64_t nf, int64_t nn,
                                                       const T *__restrict__ Xh, T *__restrict__ fpart,
@@ -1235,9 +1262,9 @@ __global__ void __launch_bounds__(256) k_sym_products(FarSymArgs F, NearSymArgs 
         if (k >= N.nsb) return;
         near_sym_wave<T>(N, k, blocks, x, npart, (T *)(sh + (size_t)wave * slice));
     } else {
-        const int64_t k = (b - before) * 4 + wave;
-        if (k >= F.nup) return;
-        far_sym_wave<T, TT>(F, k, Xh, fpart, sh + (size_t)wave * slice);
+        const int64_t k0 = ((b - before) * 4 + wave) * kFarChunk;
+        if (k0 >= F.nup) return;
+        far_sym_chunk<T, TT>(F, k0, min(k0 + kFarChunk, F.nup), Xh, fpart, sh + (size_t)wave * slice);
     }
 }
 
@@ -1993,11 +2020,11 @@ template <class T, int TT>
 static void launch_far_sym(igb_operator *op, const T *Xh, const T *xs, bool fuse)
 {
     if (!fuse) {
-        hipLaunchKernelGGL((k_far_sym<T, TT>), dim3((unsigned)((op->nup + 3) / 4)), dim3(256), 0, op->st, far_args(op), Xh,
-                           (T *)op->fpart);
+        hipLaunchKernelGGL((k_far_sym<T, TT>), dim3((unsigned)((op->nup + 4 * kFarChunk - 1) / (4 * kFarChunk))),
+                           dim3(256), 0, op->st, far_args(op), Xh, (T *)op->fpart);
         return;
     }
-    const int64_t nf = (op->nup + 3) / 4, nn = (op->nsb + 3) / 4;
+    const int64_t nf = (op->nup + 4 * kFarChunk - 1) / (4 * kFarChunk), nn = (op->nsb + 3) / 4;
     const size_t shm =
         4 * std::max<size_t>((size_t)(8 * op->near_ld + 520) * NComp<T>::value, (size_t)far_sym_lds<T, TT>()) * 8;
     hipLaunchKernelGGL((k_sym_products<T, TT>), dim3((unsigned)(nf + nn)), dim3(256), shm, op->st, far_args(op),

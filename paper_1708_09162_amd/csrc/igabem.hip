@@ -1835,10 +1835,10 @@ struct igb_operator {
     void *mpart = nullptr;     // GMRES multi-dot partial sums
     void *potc = nullptr;      // potential: weighted density at the quadrature points
     void *tz = nullptr;        // intermediate of the separable T application
-    void *pairbuf = nullptr;   // staged touching-pair blocks (nloc^2 per pair)
-    PairRec *d_touch = nullptr;
-    int64_t ntouch = 0;
-    std::vector<PairRec> touch;  // host copy of the staged touching pairs
+    // staged touching-pair blocks (nloc^2 per pair, row-major): identical pairs (E, E) in
+    // element order, and the common-edge / common-vertex pairs in (E, F) order
+    void *pairbuf_id = nullptr, *pairbuf = nullptr;
+    std::vector<PairRec> touch_id, touch;  // host copies of the staged pairs
     int64_t near_bytes = 0, coup_bytes = 0;
     double assembly_seconds = 0.0;
     std::vector<void *> owned;
@@ -1934,7 +1934,7 @@ static igb_status launch_regular_p(igb_operator *op, const PairRec *d_pairs, int
 }
 
 template <class T, int P, int PG>
-static igb_status launch_singular_pg(igb_operator *op, const PairRec *d_pairs, int64_t n)
+static igb_status launch_singular_pg(igb_operator *op, const PairRec *d_pairs, int64_t n, void *outbuf)
 {
     constexpr int NLOC = (P + 1) * (P + 1), NPAD = 16 * ((NLOC + 15) / 16), NC = NComp<T>::value;
     constexpr int STAGE_BYTES = (32 * (NC + 1) * (NPAD + 1) + 8) * 8;
@@ -1953,20 +1953,20 @@ static igb_status launch_singular_pg(igb_operator *op, const PairRec *d_pairs, i
                            d_pairs + off, gs, op->gx + op->s.goff[gs], op->gw + op->s.goff[gs], op->tline,
                            op->tline + (size_t)op->s.nelem * op->s.tile_stride,
                            op->s.kappa,
-                           (T *)op->pairbuf + off * NLOC * NLOC);
+                           (T *)outbuf + off * NLOC * NLOC);
         LAUNCHCHK();
     }
     return IGB_OK;
 }
 
 template <class T, int P>
-static igb_status launch_singular_p(igb_operator *op, const PairRec *d_pairs, int64_t n)
+static igb_status launch_singular_p(igb_operator *op, const PairRec *d_pairs, int64_t n, void *outbuf)
 {
     switch (op->s.tile_degree) {
-    case 1: return launch_singular_pg<T, P, 1>(op, d_pairs, n);
-    case 2: return launch_singular_pg<T, P, 2>(op, d_pairs, n);
-    case 4: return launch_singular_pg<T, P, 4>(op, d_pairs, n);
-    case 8: return launch_singular_pg<T, P, 8>(op, d_pairs, n);
+    case 1: return launch_singular_pg<T, P, 1>(op, d_pairs, n, outbuf);
+    case 2: return launch_singular_pg<T, P, 2>(op, d_pairs, n, outbuf);
+    case 4: return launch_singular_pg<T, P, 4>(op, d_pairs, n, outbuf);
+    case 8: return launch_singular_pg<T, P, 8>(op, d_pairs, n, outbuf);
     }
     return fail(IGB_EUNSUPPORTED, "tile degree");
 }
@@ -1987,16 +1987,16 @@ static igb_status launch_regular(igb_operator *op, const PairRec *d, int64_t n, 
 }
 
 template <class T>
-static igb_status launch_singular(igb_operator *op, const PairRec *d, int64_t n)
+static igb_status launch_singular(igb_operator *op, const PairRec *d, int64_t n, void *outbuf)
 {
     switch (op->s.p) {
-    case 0: return launch_singular_p<T, 0>(op, d, n);
-    case 1: return launch_singular_p<T, 1>(op, d, n);
-    case 2: return launch_singular_p<T, 2>(op, d, n);
-    case 3: return launch_singular_p<T, 3>(op, d, n);
-    case 4: return launch_singular_p<T, 4>(op, d, n);
-    case 5: return launch_singular_p<T, 5>(op, d, n);
-    case 6: return launch_singular_p<T, 6>(op, d, n);
+    case 0: return launch_singular_p<T, 0>(op, d, n, outbuf);
+    case 1: return launch_singular_p<T, 1>(op, d, n, outbuf);
+    case 2: return launch_singular_p<T, 2>(op, d, n, outbuf);
+    case 3: return launch_singular_p<T, 3>(op, d, n, outbuf);
+    case 4: return launch_singular_p<T, 4>(op, d, n, outbuf);
+    case 5: return launch_singular_p<T, 5>(op, d, n, outbuf);
+    case 6: return launch_singular_p<T, 6>(op, d, n, outbuf);
     }
     return fail(IGB_EUNSUPPORTED, "p > 6");
 }
@@ -2192,11 +2192,12 @@ static igb_status dot_dev(igb_operator *op, int64_t n, const T *a, const T *b, T
     return IGB_OK;
 }
 
-// Assembly, first part (needs only the element geometry): Gauss-node geometry
-// and the touching-pair quadrature into a staging buffer.  Runs on the GPU
-// while the host builds the cluster tree and the block partition.
+// Assembly, first part (needs only the element tiles): Gauss-node geometry and
+// the quadrature of the identical pairs (E, E), which are known without any
+// search, into a staging buffer.  Runs on the GPU while the host computes the
+// element geometry and looks for the other touching pairs.
 template <class T>
-static igb_status assemble_touching(igb_operator *op)
+static igb_status assemble_identical(igb_operator *op)
 {
     Setup &s = op->s;
     igb_status rc;
@@ -2216,13 +2217,37 @@ static igb_status assemble_touching(igb_operator *op)
                            s.tile_stride, op->tiles, op->tdeg, g, op->gx + s.goff[g], op->gw + s.goff[g], op->rpts);
         LAUNCHCHK();
     }
+    std::vector<PairRec> &tid = op->touch_id;
+    tid.assign(s.nelem, PairRec{});
+    for (int E = 0; E < s.nelem; ++E) {  // same record as the plan's classification of (E, E)
+        PairRec &R = tid[E];
+        std::memset(&R, 0, sizeof R);
+        R.E = R.F = E;
+        R.cls = kIdentical;
+        R.order = s.gs;
+        R.oE = 0; R.aE = 1; R.bE = 3; R.oF = 0; R.aF = 1; R.bF = 3;
+    }
+    PairRec *d = nullptr;
+    if ((rc = upload(op, &d, tid.data(), tid.size() * sizeof(PairRec)))) return rc;
+    if ((rc = dalloc(op, &op->pairbuf_id, (size_t)s.nelem * s.nloc * s.nloc * sizeof(T)))) return rc;
+    return launch_singular<T>(op, d, (int64_t)s.nelem, op->pairbuf_id);
+}
+
+// The common-edge and common-vertex pairs, found from corner coincidence of the
+// element geometry (no partition needed), into their staging buffer.
+template <class T>
+static igb_status assemble_adjacent(igb_operator *op)
+{
+    Setup &s = op->s;
+    igb_status rc;
     std::vector<PairRec> &touch = op->touch;
-    std::string err = enumerate_touching(s, touch);
+    std::string err = enumerate_touching(s, touch, false);
     if (!err.empty()) return fail(IGB_EINVAL, err);
-    op->ntouch = (int64_t)touch.size();
-    if ((rc = upload(op, &op->d_touch, touch.data(), touch.size() * sizeof(PairRec)))) return rc;
-    if ((rc = dalloc(op, &op->pairbuf, (size_t)op->ntouch * s.nloc * s.nloc * sizeof(T)))) return rc;
-    if (op->ntouch > 0) return launch_singular<T>(op, op->d_touch, op->ntouch);
+    const int64_t n = (int64_t)touch.size();
+    PairRec *d = nullptr;
+    if ((rc = upload(op, &d, touch.data(), touch.size() * sizeof(PairRec)))) return rc;
+    if ((rc = dalloc(op, &op->pairbuf, (size_t)n * s.nloc * s.nloc * sizeof(T)))) return rc;
+    if (n > 0) return launch_singular<T>(op, d, n, op->pairbuf);
     return IGB_OK;
 }
 
@@ -2238,9 +2263,12 @@ static igb_status assemble(igb_operator *op)
     const int *ords = op->gord;
     // the touching pairs of the plan must be exactly the ones quadrature already ran on
     // (and, sorted like them, they carry the near-block indices for the scatter)
-    std::vector<PairRec> touch;
-    std::string terr = check_touching(s, op->touch, &touch);
+    std::vector<PairRec> staged(op->touch_id.size() + op->touch.size()), touch, touch_id, touch_adj;
+    auto by_ef = [](const PairRec &a, const PairRec &b) { return a.E < b.E || (a.E == b.E && a.F < b.F); };
+    std::merge(op->touch_id.begin(), op->touch_id.end(), op->touch.begin(), op->touch.end(), staged.begin(), by_ef);
+    std::string terr = check_touching(s, staged, &touch);
     if (!terr.empty()) return fail(IGB_EINVAL, terr);
+    for (const PairRec &R : touch) (R.E == R.F ? touch_id : touch_adj).push_back(R);  // staging orders
     // near-field blocks: storage map, partial-row indices, zeroed storage
     {
         NearLayout NL = near_layout(s, sizeof(T));
@@ -2292,14 +2320,16 @@ static igb_status assemble(igb_operator *op)
             if ((rc = upload(op, &d, lists[k].data(), lists[k].size() * sizeof(PairRec)))) return rc;
             if ((rc = launch_regular<T>(op, d, (int64_t)lists[k].size(), ords[k], op->gpts[k]))) return rc;
         }
-        if (!touch.empty()) {
+        for (int part = 0; part < 2; ++part) {
+            const std::vector<PairRec> &lst = part == 0 ? touch_id : touch_adj;
+            const T *buf = (const T *)(part == 0 ? op->pairbuf_id : op->pairbuf);
+            if (lst.empty()) continue;
             PairRec *d = nullptr;
-            if ((rc = upload(op, &d, touch.data(), touch.size() * sizeof(PairRec)))) return rc;
-            for (int64_t off = 0; off < (int64_t)touch.size(); off += 1 << 20) {
-                int64_t cnt = std::min<int64_t>((int64_t)touch.size() - off, 1 << 20);
+            if ((rc = upload(op, &d, lst.data(), lst.size() * sizeof(PairRec)))) return rc;
+            for (int64_t off = 0; off < (int64_t)lst.size(); off += 1 << 20) {
+                int64_t cnt = std::min<int64_t>((int64_t)lst.size() - off, 1 << 20);
                 hipLaunchKernelGGL((k_scatter_pairs<T>), dim3((unsigned)cnt), dim3(256), 0, op->st, d + off, s.nloc, s.nl,
-                                   op->near_ld, op->sb, (const T *)op->pairbuf + off * s.nloc * s.nloc,
-                                   (T *)op->nearb);
+                                   op->near_ld, op->sb, buf + off * s.nloc * s.nloc, (T *)op->nearb);
                 LAUNCHCHK();
             }
         }
@@ -2420,7 +2450,7 @@ static igb_status create_device_geometry(igb_operator *op)
     if ((rc = dalloc(op, (void **)&op->scal, 16 * sizeof(double)))) return rc;
     HIPCHK(hipHostMalloc((void **)&op->h_scal, 16 * sizeof(double), hipHostMallocDefault));
     if ((rc = dalloc(op, &op->potc, (size_t)s.nelem * s.grhs * s.grhs * esz))) return rc;
-    return op->cplx ? assemble_touching<cd>(op) : assemble_touching<double>(op);
+    return op->cplx ? assemble_identical<cd>(op) : assemble_identical<double>(op);
 }
 
 static igb_status create_device_plan(igb_operator *op)
@@ -2705,7 +2735,7 @@ igb_status igb_operator_create(const igb_geometry *geo, const igb_params *prm, v
     op->st = (hipStream_t)hip_stream;
     std::string err;
     try {
-        err = build_setup_geometry(geo->g, *prm, op->s);
+        err = build_setup_tiles(geo->g, *prm, op->s);
     } catch (const std::bad_alloc &) {
         delete op;
         return fail(IGB_ENOMEM, "host allocation failed during setup");
@@ -2718,8 +2748,17 @@ igb_status igb_operator_create(const igb_geometry *geo, const igb_params *prm, v
     op->cplx = s.kernel == IGB_HELMHOLTZ;
     op->esz = op->cplx ? sizeof(cd) : sizeof(double);
     op->lo = Layout{s.p, s.p + 1, s.nloc, s.nl, s.side, s.L, s.ne, s.ns1};
-    // GPU: geometry and touching-pair quadrature; host meanwhile: tree, partition, pair lists
+    // GPU: Gauss-node geometry and identical-pair quadrature, then the other touching
+    // pairs; host meanwhile: element geometry, touching search, tree, partition, lists
     igb_status rc = create_device_geometry(op);
+    if (rc == IGB_OK) {
+        try {
+            build_setup_elements(s);
+        } catch (const std::bad_alloc &) {
+            rc = fail(IGB_ENOMEM, "host allocation failed during setup");
+        }
+    }
+    if (rc == IGB_OK) rc = op->cplx ? assemble_adjacent<cd>(op) : assemble_adjacent<double>(op);
     if (rc == IGB_OK) {
         try {
             err = build_setup_plan(s);

@@ -630,7 +630,7 @@ static void classify_pair(const Setup &s, int E, int F, PairRec &R, bool touchin
     R.order = g;
 }
 
-std::string enumerate_touching(const Setup &s, std::vector<PairRec> &out)
+std::string enumerate_touching(const Setup &s, std::vector<PairRec> &out, bool with_identical)
 {
     out.clear();
     double dmin = 1e300, dmax = 0.0;
@@ -688,8 +688,10 @@ std::string enumerate_touching(const Setup &s, std::vector<PairRec> &out)
             cand.erase(std::unique(cand.begin(), cand.end()), cand.end());
             PairRec R;
             std::memset(&R, 0, sizeof R);
-            classify_pair(s, E, E, R);
-            part[w].push_back(R);
+            if (with_identical) {
+                classify_pair(s, E, E, R);
+                part[w].push_back(R);
+            }
             for (int32_t F : cand) {
                 std::memset(&R, 0, sizeof R);
                 classify_pair(s, E, F, R, true);
@@ -808,7 +810,7 @@ static void elevate_tile(const std::vector<double> &Hin, int pu, int pv, int PG,
 }
 
 // ---------------------------------------------------------------------------
-std::string build_setup_geometry(const Geometry &geo, const igb_params &prm, Setup &s)
+std::string build_setup_tiles(const Geometry &geo, const igb_params &prm, Setup &s)
 {
     auto t0 = std::chrono::steady_clock::now();
     if (prm.kernel != IGB_LAPLACE && prm.kernel != IGB_HELMHOLTZ) return "kernel must be IGB_LAPLACE or IGB_HELMHOLTZ";
@@ -939,11 +941,7 @@ std::string build_setup_geometry(const Geometry &geo, const igb_params &prm, Set
                 }
             }
     }
-    s.ecorner.assign((size_t)s.nelem * 12, 0.0);
-    s.egrid.assign((size_t)s.nelem * 27, 0.0);
-    s.ediam.assign(s.nelem, 0.0);
-    s.erad.assign(s.nelem, 0.0);
-    // per element: v-contraction, degree elevation, corners / 3x3 grid / diameter
+    // per element: v-contraction, degree elevation
     parallel_chunks(s.nelem, 1 << 30, [&](int64_t b, int64_t e, int) {
         std::vector<double> H;
         for (int64_t k = b; k < e; ++k) {
@@ -966,7 +964,6 @@ std::string build_setup_geometry(const Geometry &geo, const igb_params &prm, Set
                 }
             }
             elevate_tile(H, P.pu, P.pv, PG, &s.tiles[(size_t)E * s.tile_stride]);
-            element_geometry_one(s, E);
         }
     });
     // T band on Xi_{p,m}
@@ -1026,6 +1023,27 @@ std::string build_setup_geometry(const Geometry &geo, const igb_params &prm, Set
     return "";
 }
 
+void build_setup_elements(Setup &s)
+{
+    auto t0 = std::chrono::steady_clock::now();
+    s.ecorner.assign((size_t)s.nelem * 12, 0.0);
+    s.egrid.assign((size_t)s.nelem * 27, 0.0);
+    s.ediam.assign(s.nelem, 0.0);
+    s.erad.assign(s.nelem, 0.0);
+    // corners / 3x3 grid / diameter / grid radius per element
+    parallel_chunks(s.nelem, 1 << 30, [&](int64_t b, int64_t e, int) {
+        for (int64_t k = b; k < e; ++k) element_geometry_one(s, (int)k);
+    });
+    s.setup_seconds += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+}
+
+std::string build_setup_geometry(const Geometry &geo, const igb_params &prm, Setup &s)
+{
+    std::string err = build_setup_tiles(geo, prm, s);
+    if (err.empty()) build_setup_elements(s);
+    return err;
+}
+
 std::string build_setup_plan(Setup &s)
 {
     auto t0 = std::chrono::steady_clock::now();
@@ -1077,7 +1095,7 @@ std::string build_setup(const Geometry &geo, const igb_params &prm, Setup &s)
     std::string err = build_setup_geometry(geo, prm, s);
     if (!err.empty()) return err;
     std::vector<PairRec> touch;
-    err = enumerate_touching(s, touch);
+    err = enumerate_touching(s, touch, true);
     if (!err.empty()) return err;
     err = build_setup_plan(s);
     if (!err.empty()) return err;

@@ -87,16 +87,20 @@ struct Setup {
 std::string make_geometry(int32_t n, const igb_nurbs_patch *in, Geometry &out);
 
 // Build everything host-side for the given parameters; returns "" or an error message.
-// build_setup = build_setup_geometry (parameters, element tiles, tables, element
-// corners) followed by build_setup_plan (cluster tree, partition, near-field pairs).
+// build_setup = build_setup_geometry (build_setup_tiles: parameters, element tiles,
+// tables; then build_setup_elements: element corners, grids, diameters) followed by
+// build_setup_plan (cluster tree, partition, near-field pairs).
 std::string build_setup(const Geometry &g, const igb_params &prm, Setup &s);
 std::string build_setup_geometry(const Geometry &g, const igb_params &prm, Setup &s);
+std::string build_setup_tiles(const Geometry &g, const igb_params &prm, Setup &s);
+void build_setup_elements(Setup &s);
 std::string build_setup_plan(Setup &s);
 
-// Touching element pairs (identical, common edge, common vertex; E <= F, sorted)
-// from physical corner coincidence alone, without the partition.  Every touching
-// pair lies in the near field, so this list equals the touching part of the plan.
-std::string enumerate_touching(const Setup &s, std::vector<PairRec> &out);
+// Touching element pairs (common edge, common vertex, and identical ones when
+// with_identical; E <= F, sorted) from physical corner coincidence alone, without
+// the partition.  Every touching pair lies in the near field, so this list equals
+// the touching part of the plan.  Needs the element geometry.
+std::string enumerate_touching(const Setup &s, std::vector<PairRec> &out, bool with_identical);
 // "" if the touching pairs of the plan, sorted by (E, F), are exactly `touch`
 // (class, order, frames); the sorted plan records (with their block indices)
 // are returned through plan_touch when it is not null.

@@ -1678,28 +1678,80 @@ __global__ void k_reduce_to(int nparts, const T *__restrict__ part, T *__restric
     if (threadIdx.x == 0) *out = red[0];
 }
 
-// CG (real): scal = [rz, pAp, rz_new, rr]
-__global__ void k_cg_update(int64_t n, const double *__restrict__ scal, double *__restrict__ w, double *__restrict__ r,
-                            const double *__restrict__ p, const double *__restrict__ Ap, const double *__restrict__ D,
-                            double *__restrict__ z)
+// CG (real), Jacobi preconditioned: scal = [rz (even steps), -, rz (odd steps), rr]
+
+// Sum of the first np (<= 256) entries of part, in a fixed order (every block
+// that calls it gets the same value).  Needs a __syncthreads-safe call site.
+__device__ inline double block_sum_parts(const double *__restrict__ part, int np, double *red)
 {
-    double alpha = scal[0] / scal[1];
+    red[threadIdx.x] = (int)threadIdx.x < np ? part[threadIdx.x] : 0.0;
+    __syncthreads();
+    for (int k = blockDim.x / 2; k > 0; k >>= 1) {
+        if ((int)threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+        __syncthreads();
+    }
+    const double v = red[0];
+    __syncthreads();
+    return v;
+}
+
+// CG step (real, Jacobi): alpha = rz / (p . Ap) with p . Ap summed from the np
+// partials of k_dot_partial; w += alpha p, r -= alpha Ap, z = r / D; per-block
+// partials of r . z and r . r into part2[blockIdx] and part2[256 + blockIdx].
+// 256 threads, at most 256 blocks.
+__global__ void __launch_bounds__(256) k_cg_step(int64_t n, const double *__restrict__ rz_old,
+                                                 const double *__restrict__ pap_part, int np, double *__restrict__ w,
+                                                 double *__restrict__ r, const double *__restrict__ p,
+                                                 const double *__restrict__ Ap, const double *__restrict__ D,
+                                                 double *__restrict__ z, double *__restrict__ part2)
+{
+    __shared__ double red[256];
+    const double alpha = *rz_old / block_sum_parts(pap_part, np, red);
+    double rzs = 0.0, rrs = 0.0;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         w[i] += alpha * p[i];
-        double ri = r[i] - alpha * Ap[i];
+        const double ri = r[i] - alpha * Ap[i];
         r[i] = ri;
-        z[i] = ri / D[i];
+        const double zi = ri / D[i];
+        z[i] = zi;
+        rzs += ri * zi;
+        rrs += ri * ri;
     }
+    red[threadIdx.x] = rzs;
+    __syncthreads();
+    for (int k = blockDim.x / 2; k > 0; k >>= 1) {
+        if ((int)threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part2[blockIdx.x] = red[0];
+    __syncthreads();
+    red[threadIdx.x] = rrs;
+    __syncthreads();
+    for (int k = blockDim.x / 2; k > 0; k >>= 1) {
+        if ((int)threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part2[256 + blockIdx.x] = red[0];
 }
 
-__global__ void k_cg_direction(int64_t n, double *__restrict__ scal, double *__restrict__ p, const double *__restrict__ z)
+// CG direction: rz_new, rr from the np partials of k_cg_step; p = z + (rz_new /
+// rz_old) p; block 0 stores rz_new and rr (the next step reads rz_new as its rz_old).
+__global__ void __launch_bounds__(256) k_cg_dir(int64_t n, const double *__restrict__ part2, int np,
+                                                const double *__restrict__ rz_old, double *__restrict__ rz_new,
+                                                double *__restrict__ rr, double *__restrict__ p,
+                                                const double *__restrict__ z)
 {
-    double beta = scal[2] / scal[0];
+    __shared__ double red[256];
+    const double rzn = block_sum_parts(part2, np, red);
+    const double rrn = block_sum_parts(part2 + 256, np, red);
+    const double beta = rzn / *rz_old;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
         p[i] = z[i] + beta * p[i];
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        *rz_new = rzn;
+        *rr = rrn;
+    }
 }
-
-__global__ void k_copy_scalar(double *scal, int from, int to) { scal[to] = scal[from]; }
 
 template <class T>
 __global__ void k_axpby(int64_t n, T alpha, const T *__restrict__ x, T beta, T *__restrict__ y)
@@ -2445,7 +2497,7 @@ static igb_status create_device_geometry(igb_operator *op)
     HIPCHK(hipMemsetAsync(op->Yh, 0, ncl_all * q2 * esz, op->st));
     for (void **v : {&op->r, &op->z, &op->pv, &op->Ap, &op->tmp})
         if ((rc = dalloc(op, v, s.ndof * esz))) return rc;
-    if ((rc = dalloc(op, &op->part, kRedBlocks * esz))) return rc;
+    if ((rc = dalloc(op, &op->part, 3 * kRedBlocks * esz))) return rc;  // dot partials; CG: 3 sets
     if ((rc = dalloc(op, &op->tz, (size_t)s.npatch * s.ne * (s.p + 1) * s.ns1 * esz))) return rc;
     if ((rc = dalloc(op, (void **)&op->scal, 16 * sizeof(double)))) return rc;
     HIPCHK(hipHostMalloc((void **)&op->h_scal, 16 * sizeof(double), hipHostMallocDefault));
@@ -2542,21 +2594,26 @@ static igb_status solve_cg(igb_operator *op, const double *b, double *w, double 
         LAUNCHCHK();
         HIPCHK(hipMemcpyAsync(p, z, n * sizeof(double), hipMemcpyDeviceToDevice, op->st));
         if ((rc = dot_dev<double>(op, n, r, z, sc + 0))) return rc;
+        // rz alternates between sc[0] and sc[2] (the step reads the old value while the
+        // direction kernel writes the new one); partial sums live in op->part
+        double *pp = (double *)op->part, *p2 = pp + 256;
+        const unsigned gs = std::min<unsigned>(gb, 256);
+        int slot = 0;
         while (it < maxit) {
             if ((rc = matvec_S<double>(op, p, Ap))) return rc;
-            if ((rc = dot_dev<double>(op, n, p, Ap, sc + 1))) return rc;
-            hipLaunchKernelGGL(k_cg_update, dim3(gb), dim3(256), 0, op->st, n, sc, w, r, p, Ap, D, z);
+            hipLaunchKernelGGL((k_dot_partial<double>), dim3(gs), dim3(256), 0, op->st, n, p, Ap, pp);
             LAUNCHCHK();
-            if ((rc = dot_dev<double>(op, n, r, z, sc + 2))) return rc;
-            if ((rc = dot_dev<double>(op, n, r, r, sc + 3))) return rc;
+            hipLaunchKernelGGL(k_cg_step, dim3(gs), dim3(256), 0, op->st, n, sc + slot, pp, (int)gs, w, r, p, Ap, D, z, p2);
+            LAUNCHCHK();
+            hipLaunchKernelGGL(k_cg_dir, dim3(gs), dim3(256), 0, op->st, n, p2, (int)gs, sc + slot, sc + (2 - slot),
+                               sc + 3, p, z);
+            LAUNCHCHK();
+            slot = 2 - slot;
             if ((rc = read_scalar(op, 3, &rr))) return rc;
             ++it;
             if (std::sqrt(rr) / bn <= tol) break;
-            hipLaunchKernelGGL(k_cg_direction, dim3(gb), dim3(256), 0, op->st, n, sc, p, z);
-            LAUNCHCHK();
-            hipLaunchKernelGGL(k_copy_scalar, dim3(1), dim3(1), 0, op->st, sc, 2, 0);
-            LAUNCHCHK();
         }
+
     }
     if (info) {
         info->iterations = it;

@@ -380,7 +380,7 @@ class Operator:
         igb_jacobi_diag(self.h, d)
         return d
 
-    def solve(self, b, w0=None, tol=1e-8, max_iter=1000, restart=100):
+    def solve(self, b, w0=None, tol=1e-8, max_iter=1000, restart=300):
         w = self._vec(self.info.n_dof) if w0 is None else self._in(w0, self.info.n_dof).clone()
         info = igb_solve(self.h, self._in(b, self.info.n_dof), w, tol, max_iter, restart)
         return w, info

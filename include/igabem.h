@@ -190,9 +190,14 @@ igb_status igb_potential(const igb_operator *op, const void *w_dev, int64_t n_pt
  * of mirrored blocks is evaluated once; 0 otherwise), 3 near-field block
  * GEMV, 4 gather of the near-field partial rows (symmetric near storage: only
  * blocks (t, s) with t <= s are kept; 0 otherwise), 5 downward pass
- * (transfers and leaf back-moments) (Sec. 4.2).  Synchronous. */
+ * (transfers and leaf back-moments) (Sec. 4.2).  With flags = 0 the products
+ * are launched as in igb_matvec: when igb_info.layout_flags bit 2 is set, the
+ * near-field products and gathers share the far-field launches (stages 1 and
+ * 2) and stages 3 and 4 are empty.  With IGB_PROFILE_SEPARATE they run as
+ * separate launches, one kernel per stage.  Synchronous. */
 #define IGB_NUM_MATVEC_STAGES 6
-igb_status igb_matvec_profile(const igb_operator *op, int32_t reps, double *stage_ms_host);
+#define IGB_PROFILE_SEPARATE 1
+igb_status igb_matvec_profile(const igb_operator *op, int32_t reps, int32_t flags, double *stage_ms_host);
 
 /* Host-only planning: the cluster tree, block partition (Sec. 4.1, Sec. 4.2
  * Def.) and near-field element-pair classification that igb_operator_create

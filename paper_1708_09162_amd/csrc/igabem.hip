@@ -2114,7 +2114,8 @@ static std::vector<TreeLaunch> tree_slices(const igb_operator *op, size_t esz)
 }
 
 template <class T>
-static igb_status matvec_internal(igb_operator *op, const T *xs, T *ys, hipEvent_t *ev = nullptr)
+static igb_status matvec_internal(igb_operator *op, const T *xs, T *ys, hipEvent_t *ev = nullptr,
+                                  bool separate = false)
 {
     const Setup &s = op->s;
     int q = s.q, q2 = q * q;
@@ -2139,7 +2140,7 @@ static igb_status matvec_internal(igb_operator *op, const T *xs, T *ys, hipEvent
     if ((rc = mark(1))) return rc;
     int64_t row0 = s.cl_off[op->lmin], nrows = s.cl_off[s.L + 1] - row0;
     const bool sym = has_far && op->fpart != nullptr;
-    const bool fuse = sym && fused_products(op->near_sym, op->near_ld, sizeof(T));
+    const bool fuse = sym && !separate && fused_products(op->near_sym, op->near_ld, sizeof(T));
     if (has_far) {
         if (sym) {
             switch ((q2 + 7) / 8) {
@@ -3197,7 +3198,7 @@ igb_status igb_plan_export_pair_classes(const igb_plan *plan, int32_t *pairs_hos
 // per-stage timing of the superspace matvec (HIP events on the operator stream)
 // ---------------------------------------------------------------------------
 template <class T>
-static igb_status profile_impl(igb_operator *op, int reps, double *ms)
+static igb_status profile_impl(igb_operator *op, int reps, bool separate, double *ms)
 {
     constexpr int NS = IGB_NUM_MATVEC_STAGES;
     hipEvent_t ev[NS + 1];
@@ -3205,7 +3206,7 @@ static igb_status profile_impl(igb_operator *op, int reps, double *ms)
     for (int k = 0; k < NS; ++k) ms[k] = 0.0;
     igb_status rc = IGB_OK;
     for (int r = 0; r < reps && rc == IGB_OK; ++r) {
-        rc = matvec_internal<T>(op, (const T *)op->xs, (T *)op->ys, ev);
+        rc = matvec_internal<T>(op, (const T *)op->xs, (T *)op->ys, ev, separate);
         if (rc) break;
         if (hipEventSynchronize(ev[NS]) != hipSuccess) { rc = fail(IGB_EHIP, "event synchronize"); break; }
         for (int k = 0; k < NS; ++k) {
@@ -3220,10 +3221,12 @@ static igb_status profile_impl(igb_operator *op, int reps, double *ms)
     return IGB_OK;
 }
 
-igb_status igb_matvec_profile(const igb_operator *cop, int32_t reps, double *stage_ms_host)
+igb_status igb_matvec_profile(const igb_operator *cop, int32_t reps, int32_t flags, double *stage_ms_host)
 {
     CHECK_OP(cop);
     if (reps < 1 || !stage_ms_host) return fail(IGB_EINVAL, "reps < 1 or null output");
     igb_operator *op = const_cast<igb_operator *>(cop);
-    return op->cplx ? profile_impl<cd>(op, reps, stage_ms_host) : profile_impl<double>(op, reps, stage_ms_host);
+    if (flags & ~IGB_PROFILE_SEPARATE) return fail(IGB_EINVAL, "unknown profile flags");
+    const bool sep = (flags & IGB_PROFILE_SEPARATE) != 0;
+    return op->cplx ? profile_impl<cd>(op, reps, sep, stage_ms_host) : profile_impl<double>(op, reps, sep, stage_ms_host);
 }

@@ -37,6 +37,7 @@ EXPORTED = [
     "igb_plan_create", "igb_plan_destroy", "igb_plan_info", "igb_plan_export_partition",
     "igb_plan_export_pair_classes", "igb_matvec_profile",
 ]
+IGB_PROFILE_SEPARATE = 1
 STAGES = ["upward", "coupling", "coupling_gather", "near_gemv", "near_gather", "downward"]
 
 
@@ -91,7 +92,7 @@ def _load():
         "igb_export_pair_classes": (C.c_int32, [vp, ip]),
         "igb_export_near_block": (C.c_int32, [vp, C.c_int32, C.c_int32, dp]),
         "igb_export_coupling_block": (C.c_int32, [vp, C.c_int32, C.c_int32, C.c_int32, dp]),
-        "igb_matvec_profile": (C.c_int32, [vp, C.c_int32, dp]),
+        "igb_matvec_profile": (C.c_int32, [vp, C.c_int32, C.c_int32, dp]),
         "igb_plan_create": (C.c_int32, [vp, C.POINTER(igb_params), C.POINTER(vp)]),
         "igb_plan_destroy": (None, [vp]),
         "igb_plan_info": (C.c_int32, [vp, C.POINTER(igb_info)]),
@@ -235,9 +236,9 @@ def igb_export_coupling_block(op, level, tgt, src, q2, cplx):
     return out[..., 0] + 1j * out[..., 1] if cplx else out[..., 0]
 
 
-def igb_matvec_profile(op, reps):
+def igb_matvec_profile(op, reps, flags=0):
     out = np.zeros(len(STAGES))
-    _check(_lib.igb_matvec_profile(op, int(reps), out.ctypes.data_as(C.POINTER(C.c_double))))
+    _check(_lib.igb_matvec_profile(op, int(reps), int(flags), out.ctypes.data_as(C.POINTER(C.c_double))))
     return dict(zip(STAGES, out.tolist()))
 
 
@@ -285,9 +286,9 @@ class Plan:
         self.h = igb_plan_create(geometry.h, make_params(**params))
         self.info = igb_plan_info(self.h)
 
-    def __del__(self):
+    def __del__(self, _destroy=_lib.igb_plan_destroy):
         if getattr(self, "h", None):
-            igb_plan_destroy(self.h)
+            _destroy(self.h)
             self.h = None
 
     def partition(self):
@@ -304,9 +305,11 @@ class Geometry:
     def __init__(self, patches):
         self.h = igb_geometry_create(patches)
 
-    def __del__(self):
+    # the destroy routine is bound at definition time: module globals may already be gone when an
+    # object is collected at interpreter shutdown
+    def __del__(self, _destroy=_lib.igb_geometry_destroy):
         if getattr(self, "h", None):
-            igb_geometry_destroy(self.h)
+            _destroy(self.h)
             self.h = None
 
 
@@ -331,9 +334,9 @@ class Operator:
         self.dtype = torch.complex128 if self.cplx else torch.float64
         self.p, self.q = p, q
 
-    def __del__(self):
+    def __del__(self, _destroy=_lib.igb_operator_destroy):
         if getattr(self, "h", None):
-            igb_operator_destroy(self.h)
+            _destroy(self.h)
             self.h = None
 
     def _vec(self, n):
@@ -391,9 +394,10 @@ class Operator:
         igb_potential(self.h, self._in(w, self.info.n_dof), pts, u)
         return u
 
-    def profile(self, reps=10):
-        """Mean milliseconds per matvec stage, from HIP events on the operator's stream."""
-        return igb_matvec_profile(self.h, reps)
+    def profile(self, reps=10, separate=False):
+        """Mean milliseconds per matvec stage, from HIP events on the operator's stream; with
+        separate=True the far- and near-field products run as separate launches."""
+        return igb_matvec_profile(self.h, reps, IGB_PROFILE_SEPARATE if separate else 0)
 
     def partition(self):
         return igb_export_partition(self.h, self.info)

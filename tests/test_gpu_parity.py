@@ -212,6 +212,8 @@ def test_h2_superspace_matvec(case, mode):
     assert list(st) == igb.STAGES and all(v >= 0.0 for v in st.values())
     if mode == "onthefly" and kw["q"] <= 8:
         assert st["coupling_gather"] > 0.0
+    sp = op.profile(reps=2, separate=True)
+    assert list(sp) == igb.STAGES and sp["near_gemv"] > 0.0 and sp["coupling"] > 0.0
     x = rand(P.ndof, 7)
     assert rel(to_np(op.matvec(torch.tensor(x))), P.matvec(x)) < 1e-12
     say(f"h2 {case}: jacobi diagonal")

@@ -348,13 +348,22 @@ __device__ inline double from_pair_lane(double v)
 // only (in the vertex case the point of E does not move at all).  Every pair
 // of lanes (2k, 2k+1) owns one line, lane 2k element E and lane 2k+1 element
 // F: the lane contracts its tile once over the fixed parameter and then
-// evaluates the points of the line at the cost of a curve.  Lane 2k receives
-// the point of F from its neighbour, forms the weighted kernel value and the
-// row of E's Bernstein products; lane 2k+1 forms the row of F's.  A wave
-// stages its 32 points in LDS and accumulates the nloc x nloc block
-// B += U^T V with FP64 MFMA (v_mfma_f64_16x16x4f64: 4 points per step),
-// complex kernels as two real accumulations.  Waves are reduced through LDS
-// at the end.
+// evaluates the points of the line at the cost of a curve.
+//
+// With the fixed parameter of E at f_E and of F at f_F, the basis function
+// (a1, a2) of E factors on the line into b(f_E) times b(moving), so the line's
+// contribution to the block is the Kronecker product of the fixed-parameter
+// factor p[aF][bF] = b_aF(f_E) b_bF(f_F) with the line factor
+// C[aM][bM] = sum over the line's points of w K(x, y) b_aM(.) b_bM(.).  Each
+// line is therefore one rank-1 term of the block reordered by (aF, bF) x
+// (aM, bM): the lane pair forms C on the vector units (lane 2k rows 0 .. H-1,
+// lane 2k+1 rows H .. P, with the partner's Bernstein values passed by DPP),
+// stages p and C of its line in LDS (same row split), and a wave accumulates
+// its 32 lines with FP64 MFMA (v_mfma_f64_16x16x4f64: 4 lines per step),
+// complex kernels as two real accumulations.  The reordered block depends on
+// which parameter of F is fixed (the vertex rule has both kinds of lines), so
+// there is one accumulator per kind; waves are reduced through LDS at the end
+// and the reordering is undone on output.
 typedef double v4d __attribute__((ext_vector_type(4)));
 
 template <class T, int P, int PG, int WAVES>
@@ -365,19 +374,20 @@ __global__ void __launch_bounds__(64 * WAVES, NComp<T>::value == 1 ? 2 : 1) k_ne
     constexpr int P1 = P + 1, NLOC = P1 * P1, NT = (NLOC + 15) / 16, NPAD = 16 * NT;
     constexpr int NC = NComp<T>::value;
     constexpr int G1 = PG + 1, TS = G1 * G1 * 4;
-    constexpr int HALF = 32;                        // points staged per step
+    constexpr int H = (P1 + 1) / 2;  // rows (lane 2k) / columns (lane 2k+1) of C per lane
+    constexpr int HALF = 32;         // lines staged per step
     // staging rows of RS = NPAD + 1 doubles, V after U with an 8-double shift:
-    // the 16 lanes of a pass write and read 16 different 8-byte bank pairs
+    // the 16 lanes of a pass read 16 different 8-byte bank pairs
     constexpr int RS = NPAD + 1;
     constexpr int STAGE = HALF * (NC + 1) * RS + 8;  // doubles per wave
     extern __shared__ double sh[];
     double *nx = sh, *nw = nx + 64;
     double *stg = nw + 64;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    double *Ub = stg + wave * STAGE;       // [NC][HALF][RS]
-    double *Vb = Ub + NC * HALF * RS + 8;  // [HALF][RS]
+    double *Ub = stg + wave * STAGE;  // [HALF][RS]: p of each line
+    double *Vb = Ub + HALF * RS + 8;  // [NC][HALF][RS]: C of each line
     const PairRec R = pairs[blockIdx.x];
-    const int role = lane & 1, pl = lane >> 1;  // role 0: element E, 1: element F; pl: point slot
+    const int role = lane & 1, pl = lane >> 1;  // role 0: element E, 1: element F; pl: line slot
     const int elem = role ? R.F : R.E;
     for (int k = threadIdx.x; k < gs; k += blockDim.x) {
         nx[k] = gxs[k];
@@ -386,15 +396,16 @@ __global__ void __launch_bounds__(64 * WAVES, NComp<T>::value == 1 ? 2 : 1) k_ne
     if constexpr (NPAD > NLOC) {
         for (int k = lane; k < HALF * (NPAD - NLOC); k += 64) {
             int pt = k / (NPAD - NLOC), a = NLOC + k % (NPAD - NLOC);
+            Ub[pt * RS + a] = 0.0;
 #pragma unroll
-            for (int c = 0; c < NC; ++c) Ub[c * HALF * RS + pt * RS + a] = 0.0;
-            Vb[pt * RS + a] = 0.0;
+            for (int c = 0; c < NC; ++c) Vb[c * HALF * RS + pt * RS + a] = 0.0;
         }
     }
     __syncthreads();
     const int g = gs, g2 = g * g, g3 = g2 * g;
     const int nreg = R.cls == 1 ? 8 : (R.cls == 2 ? 6 : 4);
     const int chunks = (g3 + HALF - 1) / HALF;
+    // acc[h]: lines on which F's fixed parameter is u (h = 1) or v (h = 0)
     v4d acc[2][NC][NT][NT];
 #pragma unroll
     for (int h = 0; h < 2; ++h)
@@ -467,13 +478,25 @@ __global__ void __launch_bounds__(64 * WAVES, NComp<T>::value == 1 ? 2 : 1) k_ne
         const double f = fix_u ? L.u0 : L.v0;
         double A[G1][4], dA[G1][4];
         tile_fix<PG>((fix_u ? tfix_u : tfix_v) + (size_t)elem * TS, f, A, dA);
-        double bf[P1], bm[P1], X[3], kap = 0.0;
+        // Bernstein values at the fixed (bf) and moving (bm) parameter; index P1
+        // pads the last row of an odd P1 on lane 2k+1
+        double bf[P1 + 1], bm[P1 + 1], X[3], kap = 0.0;
         bernstein_t<P>(f, bf);
+        bf[P1] = bm[P1] = 0.0;
         if (cst) {  // vertex, element E: one point for the whole line
             const double wv = fix_u ? L.v0 : L.u0;
             tile_line_point<PG>(A, dA, wv, X, &kap);
             bernstein_t<P>(wv, bm);
         }
+        // cl[i][j] = C[base + i][j]: rows base .. base+H-1 of the line factor
+        const int base = role ? H : 0;
+        double cl[H][P1][NC];
+#pragma unroll
+        for (int i = 0; i < H; ++i)
+#pragma unroll
+            for (int j = 0; j < P1; ++j)
+#pragma unroll
+                for (int c = 0; c < NC; ++c) cl[i][j][c] = 0.0;
         for (int id = 0; id < g; ++id) {
             const double w = nx[id];
             if (!cst) {
@@ -481,99 +504,141 @@ __global__ void __launch_bounds__(64 * WAVES, NComp<T>::value == 1 ? 2 : 1) k_ne
                 tile_line_point<PG>(A, dA, wv, X, &kap);
                 bernstein_t<P>(wv, bm);
             }
-            // lane 2k: the point of F from lane 2k+1, the weighted kernel value
+            // the partner's point; the weighted kernel value comes out bitwise
+            // the same on both lanes (x - y = -(y - x) exactly)
             const double Y0 = from_pair_lane(X[0]), Y1 = from_pair_lane(X[1]), Y2 = from_pair_lane(X[2]);
             const double ky = from_pair_lane(kap);
             const double d0 = X[0] - Y0, d1 = X[1] - Y1, d2 = X[2] - Y2;
             const double r2 = d0 * d0 + d1 * d1 + d2 * d2;
             const double ir = rsqrt_pos(r2);
-            const double f0 = 0.07957747154594767 * ir * (Wl * nw[id] * kap * ky);
-            double cre = f0, cim = 0.0;
+            const double f0 = 0.07957747154594767 * ir * ((Wl * nw[id]) * (kap * ky));
+            double wk[NC];
             if constexpr (NC == 2) {
                 double sn, cs;
                 sincos(kappa * (r2 * ir), &sn, &cs);
-                cre = cs * f0;
-                cim = sn * f0;
+                wk[0] = cs * f0;
+                wk[1] = sn * f0;
+            } else {
+                wk[0] = f0;
             }
-            if (role) cre = 1.0;  // lane 2k+1 stages F's Bernstein products unweighted
-            // u / v Bernstein vectors of this lane's element, the weight folded into the v one
-            double b1[P1], b2[P1], b2i[P1];
+            // E's values of this lane's rows and F's values of all columns
+            double bo[P1 + 1], be[H], bF[P1];
 #pragma unroll
-            for (int a = 0; a < P1; ++a) {
-                b1[a] = fix_u ? bf[a] : bm[a];
-                const double v = fix_u ? bm[a] : bf[a];
-                b2[a] = cre * v;
-                if constexpr (NC == 2) b2i[a] = cim * v;
-            }
-            double *dst = (role ? Vb : Ub) + pl * RS;
+            for (int a = 0; a < P1; ++a) bo[a] = from_pair_lane(bm[a]);
+            bo[P1] = 0.0;
 #pragma unroll
-            for (int a2 = 0; a2 < P1; ++a2)
+            for (int i = 0; i < H; ++i) be[i] = role ? bo[H + i] : bm[i];
 #pragma unroll
-                for (int a1 = 0; a1 < P1; ++a1) {
-                    dst[a2 * P1 + a1] = b1[a1] * b2[a2];
-                    if constexpr (NC == 2)
-                        if (!role) Ub[HALF * RS + pl * RS + a2 * P1 + a1] = b1[a1] * b2i[a2];
+            for (int j = 0; j < P1; ++j) bF[j] = role ? bm[j] : bo[j];
+#pragma unroll
+            for (int i = 0; i < H; ++i)
+#pragma unroll
+                for (int c = 0; c < NC; ++c) {
+                    const double t = wk[c] * be[i];
+#pragma unroll
+                    for (int j = 0; j < P1; ++j) cl[i][j][c] = fma(t, bF[j], cl[i][j][c]);
                 }
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        }
+        // stage p and C of this line (row pl), rows base .. base+H-1 of both, in
+        // (fixed | moving) index order aX * P1 + bX
+        {
+            double bfo[P1 + 1];
+#pragma unroll
+            for (int a = 0; a < P1; ++a) bfo[a] = from_pair_lane(bf[a]);
+            bfo[P1] = 0.0;
+            double *urow = Ub + pl * RS + base * P1;
+#pragma unroll
+            for (int i = 0; i < H; ++i) {
+                if (P1 % 2 == 1 && i == H - 1 && role) continue;  // row P1 does not exist
+                const double fe = role ? bfo[H + i] : bf[i];
+#pragma unroll
+                for (int j = 0; j < P1; ++j) {
+                    const double ff = role ? bf[j] : bfo[j];
+                    urow[i * P1 + j] = fe * ff;
+#pragma unroll
+                    for (int c = 0; c < NC; ++c) urow[(Vb - Ub) + c * HALF * RS + i * P1 + j] = cl[i][j][c];
+                }
+            }
+        }
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        auto accumulate = [&](v4d (&a)[NC][NT][NT]) {
 #pragma unroll
             for (int j = 0; j < HALF / 4; ++j) {
                 const int pt = 4 * j + sub;
-                double bv[NT];
+                double av[NT];
 #pragma unroll
-                for (int tb = 0; tb < NT; ++tb) bv[tb] = Vb[pt * RS + 16 * tb + col];
+                for (int ta = 0; ta < NT; ++ta) av[ta] = Ub[pt * RS + 16 * ta + col];
 #pragma unroll
                 for (int c2 = 0; c2 < NC; ++c2)
 #pragma unroll
-                    for (int ta = 0; ta < NT; ++ta) {
-                        double av = Ub[c2 * HALF * RS + pt * RS + 16 * ta + col];
+                    for (int tb = 0; tb < NT; ++tb) {
+                        const double bv = Vb[c2 * HALF * RS + pt * RS + 16 * tb + col];
 #pragma unroll
-                        for (int tb = 0; tb < NT; ++tb)
-                            acc[j & 1][c2][ta][tb] =
-                                __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv[tb], acc[j & 1][c2][ta][tb], 0, 0, 0);
+                        for (int ta = 0; ta < NT; ++ta)
+                            a[c2][ta][tb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[ta], bv, a[c2][ta][tb], 0, 0, 0);
                     }
             }
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-        }
+        };
+        if (fixF_u) accumulate(acc[1]);
+        else accumulate(acc[0]);
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
     }
-    // reduce the per-wave accumulators: red[(w*NC + c)*NPAD*NPAD + row*NPAD + col]
-    __syncthreads();
-    double *red = stg;
-#pragma unroll
-    for (int c2 = 0; c2 < NC; ++c2)
-#pragma unroll
-        for (int ta = 0; ta < NT; ++ta)
-#pragma unroll
-            for (int tb = 0; tb < NT; ++tb)
-#pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    // v_mfma_f64_16x16x4f64 result layout: lane l, element e holds D[4e + l/16][l%16]
-                    int row = 16 * ta + 4 * e + sub, cc = 16 * tb + col;
-                    red[((size_t)(wave * NC + c2) * NPAD + row) * NPAD + cc] =
-                        acc[0][c2][ta][tb][e] + acc[1][c2][ta][tb][e];
-                }
-    __syncthreads();
+    // E's fixed parameter is the same on every line of the pair; F's takes one
+    // value (identical, edge) or both (vertex)
+    const bool fixE = R.cls == 2 ? frame_fix_u(R.oE, R.aE, R.bE, true) : true;
+    const int hF = R.cls == 1 ? 1 : (frame_fix_u(R.oF, R.aF, R.bF, true) ? 1 : 0);
     T *out = pairbuf + (int64_t)blockIdx.x * NLOC * NLOC;
-    for (int o = threadIdx.x; o < NLOC * NLOC; o += blockDim.x) {
-        int a = o / NLOC, b = o % NLOC;
-        double sre = 0.0, sim = 0.0, tre = 0.0, tim = 0.0;
-        for (int w = 0; w < WAVES; ++w) {
-            sre += red[((size_t)(w * NC) * NPAD + a) * NPAD + b];
-            tre += red[((size_t)(w * NC) * NPAD + b) * NPAD + a];
-            if constexpr (NC == 2) {
-                sim += red[((size_t)(w * NC + 1) * NPAD + a) * NPAD + b];
-                tim += red[((size_t)(w * NC + 1) * NPAD + b) * NPAD + a];
+    double *red = stg;  // red[((w*NC + c)*NPAD + row)*NPAD + col], reordered block of wave w
+    bool first = true;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        if (R.cls != 3 && h != hF) continue;
+        __syncthreads();
+#pragma unroll
+        for (int c2 = 0; c2 < NC; ++c2)
+#pragma unroll
+            for (int ta = 0; ta < NT; ++ta)
+#pragma unroll
+                for (int tb = 0; tb < NT; ++tb)
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        // v_mfma_f64_16x16x4f64 result layout: lane l, element e holds D[4e + l/16][l%16]
+                        int row = 16 * ta + 4 * e + sub, cc = 16 * tb + col;
+                        red[((size_t)(wave * NC + c2) * NPAD + row) * NPAD + cc] = acc[h][c2][ta][tb][e];
+                    }
+        __syncthreads();
+        for (int o = threadIdx.x; o < NLOC * NLOC; o += blockDim.x) {
+            // entry (a, b) with a = a2 P1 + a1 (a1: u index of E), b likewise for F
+            const int a = o / NLOC, b = o % NLOC;
+            const int a1 = a % P1, a2 = a / P1, b1 = b % P1, b2 = b / P1;
+            const int aF = fixE ? a1 : a2, aM = fixE ? a2 : a1;
+            const int bF = h ? b1 : b2, bM = h ? b2 : b1;
+            const size_t rc = (size_t)(aF * P1 + bF) * NPAD + aM * P1 + bM;
+            // the mirrored entry (b, a) of an identical pair (both fix u)
+            const size_t rt = (size_t)(b1 * P1 + a1) * NPAD + b2 * P1 + a2;
+            double sre = 0.0, sim = 0.0, tre = 0.0, tim = 0.0;
+            for (int w = 0; w < WAVES; ++w) {
+                const double *rw = red + (size_t)(w * NC) * NPAD * NPAD;
+                sre += rw[rc];
+                if (R.cls == 1) tre += rw[rt];
+                if constexpr (NC == 2) {
+                    sim += rw[NPAD * NPAD + rc];
+                    if (R.cls == 1) tim += rw[NPAD * NPAD + rt];
+                }
             }
+            if (R.cls == 1) {
+                sre = 0.5 * (sre + tre);
+                sim = 0.5 * (sim + tim);
+            }
+            T s;
+            if constexpr (NC == 2) s = T{sre, sim};
+            else s = sre;
+            if (!first) s += out[o];
+            out[o] = s;
         }
-        if (R.cls == 1) {
-            sre = 0.5 * (sre + tre);
-            sim = 0.5 * (sim + tim);
-        }
-        T s;
-        if constexpr (NC == 2) s = T{sre, sim};
-        else s = sre;
-        out[o] = s;
+        first = false;
     }
 }
 

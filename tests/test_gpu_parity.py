@@ -258,6 +258,27 @@ def test_helmholtz_dense_sphere():
     assert rel(to_np(op.jacobi_diag()), P.jacobi_diag(dense=True)) < 1e-12
 
 
+def test_near_blocks_every_class_p2_helmholtz_torus():
+    """Touching-pair blocks at an odd number of Bernstein functions per direction (p=2) with the
+    complex kernel: identical, edge and vertex pairs (both orientations of the vertex lines) and
+    regular pairs, against the oracle block by block."""
+    say("near blocks: helmholtz torus k=2 p=2 m=2")
+    op, P = make(W.torus_patches(), kernel=igb.IGB_HELMHOLTZ, wavenumber=2.0, p=2, m=2, q=4, leaf_depth=1,
+                 eta=1.6, gauss_regular=6)
+    pairs = op.pair_classes()
+    count = {}
+    for E, F, cls, order in pairs:
+        cls = int(cls)
+        if count.get(cls, 0) >= 6 or (E * 7 + F) % 5:
+            continue
+        count[cls] = count.get(cls, 0) + 1
+        g = op.near_block(E, F)
+        o = P.pair_block(E, F)
+        assert np.abs(g - o).max() <= 1e-12 * np.abs(o).max(), (E, F, cls)
+        assert np.array_equal(op.near_block(F, E), g.T)
+    assert set(count) == {0, 1, 2, 3}
+
+
 @pytest.mark.parametrize("mode", ["stored", "onthefly"])
 def test_helmholtz_h2_torus(mode):
     say(f"helmholtz h2 torus k=2 p=1 m=2 q=4 {mode}")

@@ -707,6 +707,19 @@ __device__ inline int64_t tree_cluster(const TreeArgs &A, int patch, int r2, int
     return A.cl_off[lv] + (int64_t)patch * n * n + (int64_t)(r2 * w + a2) * n + r1 * w + a1;
 }
 
+// The leaf moment matrix M1 (n1 x q) and the two child transfers E2 (q x q
+// each) copied to LDS by the whole workgroup (the inner products read them
+// once per term).
+__device__ inline void tree_stage_ops(const TreeArgs &A, double *M1, double *E2)
+{
+    const int nm = A.n1 * A.q, ne = 2 * A.q * A.q;
+    for (int k = threadIdx.x; k < nm + ne; k += blockDim.x) {
+        if (k < nm) M1[k] = A.M1[k];
+        else E2[k - nm] = A.E2[k - nm];
+    }
+    __syncthreads();
+}
+
 template <class T>
 __global__ void __launch_bounds__(1024) k_up_tree(TreeArgs A, int SL, const T *__restrict__ xs, T *__restrict__ Xh)
 {
@@ -715,6 +728,8 @@ __global__ void __launch_bounds__(1024) k_up_tree(TreeArgs A, int SL, const T *_
     const int q = A.q, q2 = q * q, n1 = A.n1;
     T *W0 = (T *)sh + (size_t)wave * SL;
     T *slot = (T *)sh + (size_t)nwv * SL;  // [4 P][q2] child contributions
+    double *M1 = (double *)(slot + (size_t)16 * q2), *E2 = M1 + n1 * q;  // staged operators
+    tree_stage_ops(A, M1, E2);
     const int nr = 1 << A.ls, root = blockIdx.x;
     const int patch = root / (nr * nr), r2 = (root % (nr * nr)) / nr, r1 = root % nr;
     if (A.lb == A.L) {
@@ -733,7 +748,7 @@ __global__ void __launch_bounds__(1024) k_up_tree(TreeArgs A, int SL, const T *_
             for (int o = lane; o < n1 * q; o += 64) {
                 int i2 = o / q, mu1 = o % q;
                 T s = zero<T>();
-                for (int i1 = 0; i1 < n1; ++i1) s += A.M1[i1 * q + mu1] * X[i2 * n1 + i1];
+                for (int i1 = 0; i1 < n1; ++i1) s += M1[i1 * q + mu1] * X[i2 * n1 + i1];
                 Z[o] = s;
             }
             __builtin_amdgcn_wave_barrier();
@@ -741,7 +756,7 @@ __global__ void __launch_bounds__(1024) k_up_tree(TreeArgs A, int SL, const T *_
             for (int o = lane; o < q2; o += 64) {
                 int mu2 = o / q, mu1 = o % q;
                 T s = zero<T>();
-                for (int i2 = 0; i2 < n1; ++i2) s += A.M1[i2 * q + mu2] * Z[i2 * q + mu1];
+                for (int i2 = 0; i2 < n1; ++i2) s += M1[i2 * q + mu2] * Z[i2 * q + mu1];
                 Xh[g * q2 + o] = s;
             }
             __builtin_amdgcn_wave_barrier();
@@ -759,7 +774,7 @@ __global__ void __launch_bounds__(1024) k_up_tree(TreeArgs A, int SL, const T *_
             for (int o = lane; o < q2; o += 64) Xc[o] = Xh[gc * q2 + o];
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-            const double *Ec1 = A.E2 + c1 * q2, *Ec2 = A.E2 + c2 * q2;
+            const double *Ec1 = E2 + c1 * q2, *Ec2 = E2 + c2 * q2;
             for (int o = lane; o < q2; o += 64) {
                 int nu2 = o / q, mu1 = o % q;
                 T s = zero<T>();
@@ -798,6 +813,8 @@ __global__ void __launch_bounds__(1024) k_down_tree(TreeArgs A, int SL, T *__res
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, nwv = blockDim.x >> 6;
     const int q = A.q, q2 = q * q, n1 = A.n1;
     T *W0 = (T *)sh + (size_t)wave * SL;
+    double *M1 = (double *)((T *)sh + (size_t)nwv * SL + (size_t)16 * q2), *E2 = M1 + n1 * q;  // staged operators
+    tree_stage_ops(A, M1, E2);
     const int nr = 1 << A.ls, root = blockIdx.x;
     const int patch = root / (nr * nr), r2 = (root % (nr * nr)) / nr, r1 = root % nr;
     // Y^_c += 1/4 (E_c1 (x) E_c2) Y^_P
@@ -811,7 +828,7 @@ __global__ void __launch_bounds__(1024) k_down_tree(TreeArgs A, int SL, T *__res
             for (int o = lane; o < q2; o += 64) Yp[o] = Yh[gp * q2 + o];
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-            const double *Ec1 = A.E2 + c1 * q2, *Ec2 = A.E2 + c2 * q2;
+            const double *Ec1 = E2 + c1 * q2, *Ec2 = E2 + c2 * q2;
             for (int o = lane; o < q2; o += 64) {
                 int mu2 = o / q, nu1 = o % q;
                 T s = zero<T>();
@@ -843,7 +860,7 @@ __global__ void __launch_bounds__(1024) k_down_tree(TreeArgs A, int SL, T *__res
             for (int o = lane; o < q * n1; o += 64) {
                 int mu2 = o / n1, i1 = o % n1;
                 T s = zero<T>();
-                for (int mu1 = 0; mu1 < q; ++mu1) s += A.M1[i1 * q + mu1] * Y[mu2 * q + mu1];
+                for (int mu1 = 0; mu1 < q; ++mu1) s += M1[i1 * q + mu1] * Y[mu2 * q + mu1];
                 Z[o] = s;
             }
             __builtin_amdgcn_wave_barrier();
@@ -852,7 +869,7 @@ __global__ void __launch_bounds__(1024) k_down_tree(TreeArgs A, int SL, T *__res
                 int el = f / A.nloc, r = f % A.nloc;
                 int i1 = (el % A.side) * A.P1 + r % A.P1, i2 = (el / A.side) * A.P1 + r / A.P1;
                 T s = zero<T>();
-                for (int mu2 = 0; mu2 < q; ++mu2) s += A.M1[i2 * q + mu2] * Z[mu2 * n1 + i1];
+                for (int mu2 = 0; mu2 < q; ++mu2) s += M1[i2 * q + mu2] * Z[mu2 * n1 + i1];
                 ys[leaf * A.nl + f] += s;
             }
             __builtin_amdgcn_wave_barrier();
@@ -1047,7 +1064,18 @@ __global__ void __launch_bounds__(256) k_gather(GatherArgs A, GatherArgs B, int6
     const int64_t k0 = G.ptr[t], k1 = G.ptr[t + 1];
     for (int a = lane; a < n; a += 64) {
         T acc = zero<T>();
-        for (int64_t e = k0 + wave; e < k1; e += 4) acc += part[(size_t)G.pidx[e] * ld + a];
+        int64_t e = k0 + wave;
+        // four entries per step, all loads issued before the sums (same summation order)
+        for (; e + 12 < k1; e += 16) {
+            const int32_t i0 = G.pidx[e], i1 = G.pidx[e + 4], i2 = G.pidx[e + 8], i3 = G.pidx[e + 12];
+            const T v0 = part[(size_t)i0 * ld + a], v1 = part[(size_t)i1 * ld + a];
+            const T v2 = part[(size_t)i2 * ld + a], v3 = part[(size_t)i3 * ld + a];
+            acc += v0;
+            acc += v1;
+            acc += v2;
+            acc += v3;
+        }
+        for (; e < k1; e += 4) acc += part[(size_t)G.pidx[e] * ld + a];
         red[wave * n + a] = acc;
     }
     __syncthreads();
@@ -1365,58 +1393,108 @@ __device__ inline int64_t encode_internal(const Layout &lo, int patch, int e1, i
     return leaf * lo.nl + el * lo.nloc + r2 * lo.P1 + r1;
 }
 
-template <class T>
-__global__ void k_Tt(Layout lo, int64_t nsup, const double *__restrict__ Tb, const T *__restrict__ w, T *__restrict__ xs)
+// The three kernels below take the degree as a template parameter (P1 = P + 1
+// terms per direction, loops fully unrolled so that every load of a thread is
+// in flight at once) and 32-bit index arithmetic (the host checks that the
+// superspace size fits).
+template <int P>
+__device__ inline void decode_internal32(const Layout &lo, int a, int &patch, int &e1, int &e2, int &r1, int &r2)
 {
-    int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    constexpr int P1 = P + 1;
+    const int leaf = a / lo.nl, f = a - leaf * lo.nl;
+    const int el = f / (P1 * P1), r = f - el * (P1 * P1);
+    const int nL = 1 << lo.L, l2 = leaf >> (2 * lo.L), rl = leaf & (nL * nL - 1);
+    patch = l2;
+    const int k2 = rl >> lo.L, k1 = rl & (nL - 1);
+    e1 = k1 * lo.side + el % lo.side;
+    e2 = k2 * lo.side + el / lo.side;
+    r1 = r % P1;
+    r2 = r / P1;
+}
+
+// xs = T^T w: superspace coefficient a (patch, e1, e2, r1, r2) gathers the
+// P1 x P1 B-spline coefficients whose support covers element (e1, e2).
+template <class T, int P>
+__global__ void k_Tt(Layout lo, int nsup, const double *__restrict__ Tb, const T *__restrict__ w, T *__restrict__ xs)
+{
+    constexpr int P1 = P + 1;
+    const int a = blockIdx.x * blockDim.x + threadIdx.x;
     if (a >= nsup) return;
     int patch, e1, e2, r1, r2;
-    decode_internal(lo, a, patch, e1, e2, r1, r2);
-    const double *t1 = Tb + (e1 * lo.P1 + r1) * lo.P1, *t2 = Tb + (e2 * lo.P1 + r2) * lo.P1;
-    const T *wp = w + (int64_t)patch * lo.ns1 * lo.ns1;
+    decode_internal32<P>(lo, a, patch, e1, e2, r1, r2);
+    const double *t1 = Tb + (e1 * P1 + r1) * P1, *t2 = Tb + (e2 * P1 + r2) * P1;
+    const T *wp = w + patch * lo.ns1 * lo.ns1 + e2 * lo.ns1 + e1;
     T s = zero<T>();
-    for (int j2 = 0; j2 < lo.P1; ++j2)
-        for (int j1 = 0; j1 < lo.P1; ++j1) s += (t1[j1] * t2[j2]) * wp[(e2 + j2) * lo.ns1 + e1 + j1];
+#pragma unroll
+    for (int j2 = 0; j2 < P1; ++j2)
+#pragma unroll
+        for (int j1 = 0; j1 < P1; ++j1) s += (t1[j1] * t2[j2]) * wp[j2 * lo.ns1 + j1];
     xs[a] = s;
 }
 
 // y = T ys applied as (T1 (x) T1) per patch in two separable passes.
 // Pass 1: Z[patch][e2][r2][j1] = sum_{e1, r1} T1[j1, (e1, r1)] ys[patch, e1, e2, r1, r2]
-template <class T>
+// (element e1 = j1 - P + d, d < P1, inside the patch)
+template <class T, int P>
 __global__ void k_T_pass1(Layout lo, int npatch, const double *__restrict__ Tb, const T *__restrict__ ys, T *__restrict__ Z)
 {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    int64_t n = (int64_t)npatch * lo.ne * lo.P1 * lo.ns1;
+    constexpr int P1 = P + 1;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int n = npatch * lo.ne * P1 * lo.ns1;
     if (i >= n) return;
-    int j1 = (int)(i % lo.ns1);
-    int64_t rest = i / lo.ns1;
-    int r2 = (int)(rest % lo.P1);
-    rest /= lo.P1;
-    int e2 = (int)(rest % lo.ne);
-    int patch = (int)(rest / lo.ne);
-    int lo1 = j1 - lo.p < 0 ? 0 : j1 - lo.p, hi1 = j1 < lo.ne - 1 ? j1 : lo.ne - 1;
+    const int j1 = i % lo.ns1, rest = i / lo.ns1;
+    const int r2 = rest % P1, rest2 = rest / P1;
+    const int e2 = rest2 % lo.ne, patch = rest2 / lo.ne;
+    const int nL = 1 << lo.L;
+    const int leafrow = (patch * nL + e2 / lo.side) * nL, elrow = (e2 % lo.side) * lo.side;
     T s = zero<T>();
-    for (int e1 = lo1; e1 <= hi1; ++e1)
-        for (int r1 = 0; r1 < lo.P1; ++r1)
-            s += Tb[(e1 * lo.P1 + r1) * lo.P1 + (j1 - e1)] * ys[encode_internal(lo, patch, e1, e2, r1, r2)];
+#pragma unroll
+    for (int d = 0; d < P1; ++d) {
+        const int e1 = j1 - P + d;
+        if (e1 < 0 || e1 >= lo.ne) continue;
+        const int leaf = leafrow + e1 / lo.side, el = elrow + e1 % lo.side;
+        const T *y0 = ys + leaf * lo.nl + el * (P1 * P1) + r2 * P1;
+        const double *tb = Tb + e1 * P1 * P1 + (P - d);
+#pragma unroll
+        for (int r1 = 0; r1 < P1; ++r1) s += tb[r1 * P1] * y0[r1];
+    }
     Z[i] = s;
 }
 
-// Pass 2: y[patch][j2][j1] = sum_{e2, r2} T1[j2, (e2, r2)] Z[patch][e2][r2][j1]
-template <class T>
-__global__ void k_T_pass2(Layout lo, int64_t ndof, const double *__restrict__ Tb, const T *__restrict__ Z, T *__restrict__ y)
+// Pass 2: y[patch][j2][j1] = sum_{e2, r2} T1[j2, (e2, r2)] Z[patch][e2][r2][j1];
+// with dx given, part[block] = sum over the block's i of conj(dx[i]) y[i].
+template <class T, int P>
+__global__ void __launch_bounds__(256) k_T_pass2(Layout lo, int ndof, const double *__restrict__ Tb,
+                                                 const T *__restrict__ Z, T *__restrict__ y, const T *__restrict__ dx,
+                                                 T *__restrict__ part)
 {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= ndof) return;
-    int nn = lo.ns1 * lo.ns1;
-    int patch = (int)(i / nn), r = (int)(i % nn), j2 = r / lo.ns1, j1 = r % lo.ns1;
-    int lo2 = j2 - lo.p < 0 ? 0 : j2 - lo.p, hi2 = j2 < lo.ne - 1 ? j2 : lo.ne - 1;
-    const T *Zp = Z + (int64_t)patch * lo.ne * lo.P1 * lo.ns1;
+    constexpr int P1 = P + 1;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
     T s = zero<T>();
-    for (int e2 = lo2; e2 <= hi2; ++e2)
-        for (int r2 = 0; r2 < lo.P1; ++r2)
-            s += Tb[(e2 * lo.P1 + r2) * lo.P1 + (j2 - e2)] * Zp[((int64_t)e2 * lo.P1 + r2) * lo.ns1 + j1];
-    y[i] = s;
+    if (i < ndof) {
+        const int nn = lo.ns1 * lo.ns1;
+        const int patch = i / nn, r = i % nn, j2 = r / lo.ns1, j1 = r % lo.ns1;
+        const T *Zp = Z + patch * lo.ne * P1 * lo.ns1 + j1;
+#pragma unroll
+        for (int d = 0; d < P1; ++d) {
+            const int e2 = j2 - P + d;
+            if (e2 < 0 || e2 >= lo.ne) continue;
+            const double *tb = Tb + e2 * P1 * P1 + (P - d);
+#pragma unroll
+            for (int r2 = 0; r2 < P1; ++r2) s += tb[r2 * P1] * Zp[(e2 * P1 + r2) * lo.ns1];
+        }
+        y[i] = s;
+    }
+    if (dx) {
+        __shared__ T red[256];
+        red[threadIdx.x] = i < ndof ? conj_(dx[i]) * s : zero<T>();
+        __syncthreads();
+        for (int k = blockDim.x / 2; k > 0; k >>= 1) {
+            if ((int)threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+    }
 }
 
 // external S* order (element-major) <-> internal (leaf-major)
@@ -1743,13 +1821,18 @@ __global__ void k_reduce_to(int nparts, const T *__restrict__ part, T *__restric
     if (threadIdx.x == 0) *out = red[0];
 }
 
-// CG (real), Jacobi preconditioned: scal = [rz (even steps), -, rz (odd steps), rr]
+// CG (real), Jacobi preconditioned: scal = [rz (even steps), -, rz (odd steps),
+// rr, done, threshold]; done (1.0) is set by the direction kernel once rr <=
+// threshold and turns every later step into a no-op, so the host may test
+// convergence one step behind the device.
 
-// Sum of the first np (<= 256) entries of part, in a fixed order (every block
-// that calls it gets the same value).  Needs a __syncthreads-safe call site.
+// Sum of the first np entries of part, in a fixed order (every block that
+// calls it gets the same value).  Needs a __syncthreads-safe call site.
 __device__ inline double block_sum_parts(const double *__restrict__ part, int np, double *red)
 {
-    red[threadIdx.x] = (int)threadIdx.x < np ? part[threadIdx.x] : 0.0;
+    double v0 = 0.0;
+    for (int k = threadIdx.x; k < np; k += blockDim.x) v0 += part[k];
+    red[threadIdx.x] = v0;
     __syncthreads();
     for (int k = blockDim.x / 2; k > 0; k >>= 1) {
         if ((int)threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
@@ -1761,16 +1844,18 @@ __device__ inline double block_sum_parts(const double *__restrict__ part, int np
 }
 
 // CG step (real, Jacobi): alpha = rz / (p . Ap) with p . Ap summed from the np
-// partials of k_dot_partial; w += alpha p, r -= alpha Ap, z = r / D; per-block
+// partials of the product; w += alpha p, r -= alpha Ap, z = r / D; per-block
 // partials of r . z and r . r into part2[blockIdx] and part2[256 + blockIdx].
-// 256 threads, at most 256 blocks.
+// Nothing happens once *done is set.  256 threads, at most 256 blocks.
 __global__ void __launch_bounds__(256) k_cg_step(int64_t n, const double *__restrict__ rz_old,
                                                  const double *__restrict__ pap_part, int np, double *__restrict__ w,
                                                  double *__restrict__ r, const double *__restrict__ p,
                                                  const double *__restrict__ Ap, const double *__restrict__ D,
-                                                 double *__restrict__ z, double *__restrict__ part2)
+                                                 double *__restrict__ z, double *__restrict__ part2,
+                                                 const double *__restrict__ done)
 {
     __shared__ double red[256];
+    if (*done != 0.0) return;  // uniform: the whole grid returns
     const double alpha = *rz_old / block_sum_parts(pap_part, np, red);
     double rzs = 0.0, rrs = 0.0;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
@@ -1800,11 +1885,14 @@ __global__ void __launch_bounds__(256) k_cg_step(int64_t n, const double *__rest
 }
 
 // CG direction: rz_new, rr from the np partials of k_cg_step; p = z + (rz_new /
-// rz_old) p; block 0 stores rz_new and rr (the next step reads rz_new as its rz_old).
+// rz_old) p; block 0 stores rz_new, rr and done = (rr <= *thr) (the next step
+// reads rz_new as its rz_old).  After a skipped step the partials are those of
+// the last real one, so the stored values do not change.
 __global__ void __launch_bounds__(256) k_cg_dir(int64_t n, const double *__restrict__ part2, int np,
                                                 const double *__restrict__ rz_old, double *__restrict__ rz_new,
                                                 double *__restrict__ rr, double *__restrict__ p,
-                                                const double *__restrict__ z)
+                                                const double *__restrict__ z, const double *__restrict__ thr,
+                                                double *__restrict__ done)
 {
     __shared__ double red[256];
     const double rzn = block_sum_parts(part2, np, red);
@@ -1815,7 +1903,14 @@ __global__ void __launch_bounds__(256) k_cg_dir(int64_t n, const double *__restr
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         *rz_new = rzn;
         *rr = rrn;
+        *done = rrn <= *thr ? 1.0 : 0.0;
     }
+}
+
+__global__ void k_set2(double *a, double va, double *b, double vb)
+{
+    *a = va;
+    *b = vb;
 }
 
 template <class T>
@@ -1944,6 +2039,7 @@ struct igb_operator {
     // solver work
     void *r = nullptr, *z = nullptr, *pv = nullptr, *Ap = nullptr, *tmp = nullptr;
     void *part = nullptr;
+    void *dpart = nullptr;     // CG: per-block partials of p . Ap (one per block of the last T pass)
     double *scal = nullptr;
     double *h_scal = nullptr;  // pinned
     void *V = nullptr;         // GMRES basis (Vcols columns of ndof)
@@ -2171,7 +2267,8 @@ static std::vector<TreeLaunch> tree_slices(const igb_operator *op, size_t esz)
         t.SL = SL;
         t.waves = waves;
         t.roots = (unsigned)(s.npatch << (2 * ls));
-        t.shm = ((size_t)waves * SL + (size_t)16 * q2) * esz;  // slices + child slots of <= 4 parents
+        // slices + child slots of <= 4 parents + the staged M1 and E2
+        t.shm = ((size_t)waves * SL + (size_t)16 * q2) * esz + (size_t)(s.n1 * s.q + 2 * q2) * sizeof(double);
         v.push_back(t);
         lb = ls;
     } while (lb > op->lmin);
@@ -2268,34 +2365,81 @@ static igb_status matvec_internal(igb_operator *op, const T *xs, T *ys, hipEvent
     return mark(6);
 }
 
+template <class T, int P>
+static void launch_Tt_p(igb_operator *op, const T *w, T *xs)
+{
+    hipLaunchKernelGGL((k_Tt<T, P>), dim3(nblk(op->s.nsup, 256)), dim3(256), 0, op->st, op->lo, (int)op->s.nsup, op->Tb,
+                       w, xs);
+}
+
+template <class T, int P>
+static void launch_T_p(igb_operator *op, const T *ys, T *y, const T *dx, T *part)
+{
+    const int64_t nz = (int64_t)op->s.npatch * op->s.ne * (P + 1) * op->s.ns1;
+    hipLaunchKernelGGL((k_T_pass1<T, P>), dim3(nblk(nz, 256)), dim3(256), 0, op->st, op->lo, op->s.npatch, op->Tb, ys,
+                       (T *)op->tz);
+    hipLaunchKernelGGL((k_T_pass2<T, P>), dim3(nblk(op->s.ndof, 256)), dim3(256), 0, op->st, op->lo, (int)op->s.ndof,
+                       op->Tb, (const T *)op->tz, y, dx, part);
+}
+
+// The T kernels index with 32-bit integers: every superspace index must fit.
+static igb_status t_sizes_ok(const igb_operator *op)
+{
+    if (op->s.nsup >= ((int64_t)1 << 31) ||
+        (int64_t)op->s.npatch * op->s.ne * (op->s.p + 1) * op->s.ns1 >= ((int64_t)1 << 31))
+        return fail(IGB_EUNSUPPORTED, "superspace dimension >= 2^31");
+    return IGB_OK;
+}
+
 template <class T>
 static igb_status apply_Tt(igb_operator *op, const T *w, T *xs)
 {
-    hipLaunchKernelGGL((k_Tt<T>), dim3(nblk(op->s.nsup, 256)), dim3(256), 0, op->st, op->lo, op->s.nsup, op->Tb, w, xs);
+    igb_status rc;
+    if ((rc = t_sizes_ok(op))) return rc;
+    switch (op->s.p) {
+    case 0: launch_Tt_p<T, 0>(op, w, xs); break;
+    case 1: launch_Tt_p<T, 1>(op, w, xs); break;
+    case 2: launch_Tt_p<T, 2>(op, w, xs); break;
+    case 3: launch_Tt_p<T, 3>(op, w, xs); break;
+    case 4: launch_Tt_p<T, 4>(op, w, xs); break;
+    case 5: launch_Tt_p<T, 5>(op, w, xs); break;
+    case 6: launch_Tt_p<T, 6>(op, w, xs); break;
+    default: return fail(IGB_EUNSUPPORTED, "p > 6");
+    }
     LAUNCHCHK();
     return IGB_OK;
 }
 
+// y = T ys; with dx given, also the per-block partial sums of conj(dx) . y
+// into part (nblk(ndof, 256) entries).
 template <class T>
-static igb_status apply_T(igb_operator *op, const T *ys, T *y)
+static igb_status apply_T(igb_operator *op, const T *ys, T *y, const T *dx = nullptr, T *part = nullptr)
 {
-    int64_t nz = (int64_t)op->s.npatch * op->s.ne * (op->s.p + 1) * op->s.ns1;
-    hipLaunchKernelGGL((k_T_pass1<T>), dim3(nblk(nz, 256)), dim3(256), 0, op->st, op->lo, op->s.npatch, op->Tb, ys,
-                       (T *)op->tz);
-    LAUNCHCHK();
-    hipLaunchKernelGGL((k_T_pass2<T>), dim3(nblk(op->s.ndof, 256)), dim3(256), 0, op->st, op->lo, op->s.ndof, op->Tb,
-                       (const T *)op->tz, y);
+    igb_status rc;
+    if ((rc = t_sizes_ok(op))) return rc;
+    switch (op->s.p) {
+    case 0: launch_T_p<T, 0>(op, ys, y, dx, part); break;
+    case 1: launch_T_p<T, 1>(op, ys, y, dx, part); break;
+    case 2: launch_T_p<T, 2>(op, ys, y, dx, part); break;
+    case 3: launch_T_p<T, 3>(op, ys, y, dx, part); break;
+    case 4: launch_T_p<T, 4>(op, ys, y, dx, part); break;
+    case 5: launch_T_p<T, 5>(op, ys, y, dx, part); break;
+    case 6: launch_T_p<T, 6>(op, ys, y, dx, part); break;
+    default: return fail(IGB_EUNSUPPORTED, "p > 6");
+    }
     LAUNCHCHK();
     return IGB_OK;
 }
 
+// y = A x in the spline space; with part given, also the per-block partial
+// sums of conj(x) . y (nblk(ndof, 256) entries).
 template <class T>
-static igb_status matvec_S(igb_operator *op, const T *x, T *y)
+static igb_status matvec_S(igb_operator *op, const T *x, T *y, T *part = nullptr)
 {
     igb_status rc;
     if ((rc = apply_Tt<T>(op, x, (T *)op->xs))) return rc;
     if ((rc = matvec_internal<T>(op, (const T *)op->xs, (T *)op->ys))) return rc;
-    return apply_T<T>(op, (const T *)op->ys, y);
+    return apply_T<T>(op, (const T *)op->ys, y, part ? x : nullptr, part);
 }
 
 static const int kRedBlocks = 256;
@@ -2564,6 +2708,7 @@ static igb_status create_device_geometry(igb_operator *op)
     for (void **v : {&op->r, &op->z, &op->pv, &op->Ap, &op->tmp})
         if ((rc = dalloc(op, v, s.ndof * esz))) return rc;
     if ((rc = dalloc(op, &op->part, 3 * kRedBlocks * esz))) return rc;  // dot partials; CG: 3 sets
+    if ((rc = dalloc(op, &op->dpart, nblk(s.ndof, 256) * esz))) return rc;  // p . Ap partials of the T pass
     if ((rc = dalloc(op, &op->tz, (size_t)s.npatch * s.ne * (s.p + 1) * s.ns1 * esz))) return rc;
     if ((rc = dalloc(op, (void **)&op->scal, 16 * sizeof(double)))) return rc;
     HIPCHK(hipHostMalloc((void **)&op->h_scal, 16 * sizeof(double), hipHostMallocDefault));
@@ -2661,25 +2806,54 @@ static igb_status solve_cg(igb_operator *op, const double *b, double *w, double 
         HIPCHK(hipMemcpyAsync(p, z, n * sizeof(double), hipMemcpyDeviceToDevice, op->st));
         if ((rc = dot_dev<double>(op, n, r, z, sc + 0))) return rc;
         // rz alternates between sc[0] and sc[2] (the step reads the old value while the
-        // direction kernel writes the new one); partial sums live in op->part
-        double *pp = (double *)op->part, *p2 = pp + 256;
+        // direction kernel writes the new one); r.z and r.r partials live in op->part.
+        // Step k copies (rr, done) to pinned slot k & 1 and records ev[k & 1]; the host
+        // reads step k while step k + 1 runs, and a step after convergence does nothing.
+        double *pp = (double *)op->dpart, *p2 = (double *)op->part + 256;
+        const int np = (int)nblk(n, 256);
         const unsigned gs = std::min<unsigned>(gb, 256);
-        int slot = 0;
-        while (it < maxit) {
-            if ((rc = matvec_S<double>(op, p, Ap))) return rc;
-            hipLaunchKernelGGL((k_dot_partial<double>), dim3(gs), dim3(256), 0, op->st, n, p, Ap, pp);
-            LAUNCHCHK();
-            hipLaunchKernelGGL(k_cg_step, dim3(gs), dim3(256), 0, op->st, n, sc + slot, pp, (int)gs, w, r, p, Ap, D, z, p2);
-            LAUNCHCHK();
-            hipLaunchKernelGGL(k_cg_dir, dim3(gs), dim3(256), 0, op->st, n, p2, (int)gs, sc + slot, sc + (2 - slot),
-                               sc + 3, p, z);
-            LAUNCHCHK();
-            slot = 2 - slot;
-            if ((rc = read_scalar(op, 3, &rr))) return rc;
-            ++it;
-            if (std::sqrt(rr) / bn <= tol) break;
+        hipLaunchKernelGGL(k_set2, dim3(1), dim3(1), 0, op->st, sc + 4, 0.0, sc + 5, (tol * bn) * (tol * bn));
+        LAUNCHCHK();
+        hipEvent_t ev[2];
+        HIPCHK(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
+        if (hipEventCreateWithFlags(&ev[1], hipEventDisableTiming) != hipSuccess) {
+            (void)hipEventDestroy(ev[0]);
+            return fail(IGB_EHIP, "hipEventCreate");
         }
-
+        int slot = 0, launched = 0, examined = 0;
+        bool conv = false;
+        rc = IGB_OK;
+        while (true) {
+            if (it + launched < maxit && launched - examined < 2) {
+                if ((rc = matvec_S<double>(op, p, Ap, pp))) break;
+                hipLaunchKernelGGL(k_cg_step, dim3(gs), dim3(256), 0, op->st, n, sc + slot, pp, np, w, r, p, Ap, D, z,
+                                   p2, sc + 4);
+                hipLaunchKernelGGL(k_cg_dir, dim3(gs), dim3(256), 0, op->st, n, p2, (int)gs, sc + slot, sc + (2 - slot),
+                                   sc + 3, p, z, sc + 5, sc + 4);
+                if (hipGetLastError() != hipSuccess) { rc = fail(IGB_EHIP, "CG kernel launch"); break; }
+                double *h = op->h_scal + 8 + 2 * (launched & 1);
+                if (hipMemcpyAsync(h, sc + 3, 2 * sizeof(double), hipMemcpyDeviceToHost, op->st) != hipSuccess ||
+                    hipEventRecord(ev[launched & 1], op->st) != hipSuccess) {
+                    rc = fail(IGB_EHIP, "CG residual copy");
+                    break;
+                }
+                slot = 2 - slot;
+                ++launched;
+                continue;
+            }
+            if (examined == launched) break;  // max_iter reached and every step read
+            if (hipEventSynchronize(ev[examined & 1]) != hipSuccess) { rc = fail(IGB_EHIP, "hipEventSynchronize"); break; }
+            const double *h = op->h_scal + 8 + 2 * (examined & 1);
+            rr = h[0];
+            ++examined;
+            if (h[1] != 0.0) { conv = true; break; }
+        }
+        (void)hipStreamSynchronize(op->st);  // the pinned slots stay valid until the last copy lands
+        (void)hipEventDestroy(ev[0]);
+        (void)hipEventDestroy(ev[1]);
+        if (rc) return rc;
+        it += examined;
+        (void)conv;  // the true residual b - A w decides, at the top of the loop
     }
     if (info) {
         info->iterations = it;

@@ -1189,10 +1189,22 @@ struct FarSymArgs {
 // pair is loaded while the current one is evaluated).
 constexpr int kFarChunk = 4;
 
-// LDS doubles per wave for far_sym_chunk: 8 rows of partial sums (row stride
-// 8 TT + 1) and the pair's target and source nodes (x, y, z, weighted moment).
+// LDS doubles per wave of far_mfma_chunk (W = 16 NTI padded nodes): the
+// staged nodes and |x'|^2 (9 W), reused after the products for the row sums
+// (W rows of 17) and the column sums (4 rows of W + 1).
+template <int NTI>
+constexpr int far_mfma_lds() { return 21 * 16 * NTI + 4; }
+
+// LDS doubles per wave for the far-field pairs: the matrix-core path for the
+// real kernel; for the complex one (far_sym_chunk) 8 rows of partial sums (row
+// stride 8 TT + 1) and the pair's target and source nodes (x, y, z, weighted
+// moment).
 template <class T, int TT>
-constexpr int far_sym_lds() { return 8 * (8 * TT + 1) * NComp<T>::value + 2 * (3 + NComp<T>::value) * 8 * TT; }
+constexpr int far_sym_lds()
+{
+    if constexpr (NComp<T>::value == 1) return far_mfma_lds<(TT + 1) / 2>();
+    else return 8 * (8 * TT + 1) * NComp<T>::value + 2 * (3 + NComp<T>::value) * 8 * TT;
+}
 
 // Node data of one cluster's node j for the far field: position and the
 // weighted moment kappa_j X^[j] (padding nodes j >= q2: far from every node,
@@ -1323,14 +1335,135 @@ __device__ inline void far_sym_chunk(const FarSymArgs &F, int64_t k0, int64_t k1
 }
 
 
+// Real kernel: pairs k0 .. k1-1 with the squared distances on the matrix
+// cores.  For a 16 x 16 tile of target nodes x and source nodes y, one
+// v_mfma_f64_16x16x4f64 forms a . b + c with a = (x', 1), b = (-2 y', |y'|^2)
+// and c = |x'|^2, i.e. |x - y|^2, where ' is relative to the pair's first
+// target node (small operands: no cancellation for admissible pairs).  The
+// vector units then take 1/|x - y| and the two weighted sums.  W = 16 NTI
+// nodes per cluster (padding as in far_node).  Result layout of the product:
+// lane l, element e holds row 4e + l/16 (target), column l%16 (source).
+typedef double v4d_far __attribute__((ext_vector_type(4)));
+template <int NTI>
+__device__ inline void far_mfma_chunk(const FarSymArgs &F, int64_t k0, int64_t k1, const double *__restrict__ Xh,
+                                      double *__restrict__ part, double *lds)
+{
+    constexpr int W = 16 * NTI;
+    double *tg = lds, *sr = lds + 4 * W, *nx2 = lds + 8 * W;  // [x | y | z | w] x W each, |x'|^2
+    double *rs = lds, *cs = lds + 17 * W;                     // after the products: row and column sums
+    const int q2 = F.q2;
+    const int lane = threadIdx.x & 63, col = lane & 15, sub = lane >> 4;
+    FarNode<double> nt{}, ns{};
+    if (lane < W) {
+        nt = far_node<double>(F, Xh, F.up_t[k0], lane, 1e100);
+        ns = far_node<double>(F, Xh, F.up_s[k0], lane, -1e100);
+    }
+    for (int64_t k = k0; k < k1; ++k) {
+        if (lane < W) {
+            tg[lane] = nt.x;
+            tg[W + lane] = nt.y;
+            tg[2 * W + lane] = nt.z;
+            tg[3 * W + lane] = nt.w;
+            sr[lane] = ns.x;
+            sr[W + lane] = ns.y;
+            sr[2 * W + lane] = ns.z;
+            sr[3 * W + lane] = ns.w;
+        }
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        const double cx = tg[0], cy = tg[W], cz = tg[2 * W];
+        if (lane < W) {
+            const double a0 = nt.x - cx, a1 = nt.y - cy, a2 = nt.z - cz;
+            nx2[lane] = a0 * a0 + a1 * a1 + a2 * a2;
+        }
+        if (k + 1 < k1 && lane < W) {  // prefetch the next pair
+            nt = far_node<double>(F, Xh, F.up_t[k + 1], lane, 1e100);
+            ns = far_node<double>(F, Xh, F.up_s[k + 1], lane, -1e100);
+        }
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        // every LDS value of the pair into registers first: the staging space
+        // then takes the row and column sums
+        const double ck = sub == 0 ? cx : (sub == 1 ? cy : cz);
+        double bop[NTI], ws[NTI], csum[NTI], aop[NTI], wt[NTI][4];
+        v4d_far cin[NTI];
+#pragma unroll
+        for (int tj = 0; tj < NTI; ++tj) {
+            const int j = 16 * tj + col;
+            const double y0 = sr[j] - cx, y1 = sr[W + j] - cy, y2 = sr[2 * W + j] - cz;
+            bop[tj] = sub == 3 ? y0 * y0 + y1 * y1 + y2 * y2 : -2.0 * (sub == 0 ? y0 : (sub == 1 ? y1 : y2));
+            ws[tj] = sr[3 * W + j];
+            csum[tj] = 0.0;
+        }
+#pragma unroll
+        for (int ti = 0; ti < NTI; ++ti) {
+            aop[ti] = sub == 3 ? 1.0 : tg[sub * W + 16 * ti + col] - ck;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int r = 16 * ti + 4 * e + sub;
+                cin[ti][e] = nx2[r];
+                wt[ti][e] = tg[3 * W + r];
+            }
+        }
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+#pragma unroll
+        for (int ti = 0; ti < NTI; ++ti) {
+            double racc[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int tj = 0; tj < NTI; ++tj) {
+                const v4d_far d = __builtin_amdgcn_mfma_f64_16x16x4f64(aop[ti], bop[tj], cin[ti], 0, 0, 0);
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const double ir = rsqrt_pos(d[e]);
+                    racc[e] += ir * ws[tj];
+                    csum[tj] += ir * wt[ti][e];
+                }
+            }
+#pragma unroll
+            for (int e = 0; e < 4; ++e) rs[(16 * ti + 4 * e + sub) * 17 + col] = racc[e];
+        }
+#pragma unroll
+        for (int tj = 0; tj < NTI; ++tj) cs[sub * (W + 1) + 16 * tj + col] = csum[tj];
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        double *pr = part + (size_t)(2 * k) * q2, *pc = part + (size_t)(2 * k + 1) * q2;
+        for (int i = lane; i < q2; i += 64) {
+            double v = 0.0;
+#pragma unroll
+            for (int c = 0; c < 16; ++c) v += rs[i * 17 + c];
+            pr[i] = v;
+            double u = 0.0;
+#pragma unroll
+            for (int t = 0; t < 4; ++t) u += cs[t * (W + 1) + i];
+            pc[i] = u;
+        }
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    }
+}
+
+// Far-field pairs k0 .. k1-1 of one wave: matrix-core path for the real
+// kernel, far_sym_chunk for the complex one.
 template <class T, int TT>
-__global__ void __launch_bounds__(256) k_far_sym(FarSymArgs F, const T *__restrict__ Xh, T *__restrict__ part)
+__device__ inline void far_chunk(const FarSymArgs &F, int64_t k0, int64_t k1, const T *__restrict__ Xh,
+                                 T *__restrict__ part, double *lds)
+{
+    if constexpr (NComp<T>::value == 1) far_mfma_chunk<(TT + 1) / 2>(F, k0, k1, Xh, part, lds);
+    else far_sym_chunk<T, TT>(F, k0, k1, Xh, part, lds);
+}
+
+// three waves per SIMD for the real kernel: the far-field pairs need the
+// occupancy more than the deeper product pipeline the compiler would build
+template <class T, int TT>
+__global__ void __launch_bounds__(256, NComp<T>::value == 1 ? 3 : 1) k_far_sym(FarSymArgs F, const T *__restrict__ Xh,
+                                                                             T *__restrict__ part)
 {
     __shared__ double buf[4][far_sym_lds<T, TT>()];
     const int wave = threadIdx.x >> 6;
     const int64_t k0 = ((int64_t)blockIdx.x * 4 + wave) * kFarChunk;
     if (k0 >= F.nup) return;  // whole waves only; no block-wide barrier follows
-    far_sym_chunk<T, TT>(F, k0, min(k0 + kFarChunk, F.nup), Xh, part, buf[wave]);
+    far_chunk<T, TT>(F, k0, min(k0 + kFarChunk, F.nup), Xh, part, buf[wave]);
 }
 
 // The far-field pairs and the stored near blocks in one launch (ALU-bound and
@@ -1339,7 +1472,8 @@ __global__ void __launch_bounds__(256) k_far_sym(FarSymArgs F, const T *__restri
 // evenly through the grid (workgroup b is near iff
 // floor((b+1) nn / (nf+nn)) > floor(b nn / (nf+nn))).
 template <class T, int TT>
-__global__ void __launch_bounds__(256) k_sym_products(FarSymArgs F, NearSymArgs N, int64_t nf, int64_t nn,
+__global__ void __launch_bounds__(256, NComp<T>::value == 1 ? 3 : 1) k_sym_products(FarSymArgs F, NearSymArgs N,
+                                                                                  int64_t nf, int64_t nn,
                                                       const T *__restrict__ Xh, T *__restrict__ fpart,
                                                       const T *__restrict__ blocks, const T *__restrict__ x,
                                                       T *__restrict__ npart)
@@ -1357,7 +1491,7 @@ __global__ void __launch_bounds__(256) k_sym_products(FarSymArgs F, NearSymArgs 
     } else {
         const int64_t k0 = ((b - before) * 4 + wave) * kFarChunk;
         if (k0 >= F.nup) return;
-        far_sym_chunk<T, TT>(F, k0, min(k0 + kFarChunk, F.nup), Xh, fpart, sh + (size_t)wave * slice);
+        far_chunk<T, TT>(F, k0, min(k0 + kFarChunk, F.nup), Xh, fpart, sh + (size_t)wave * slice);
     }
 }
 
@@ -1886,13 +2020,14 @@ __global__ void __launch_bounds__(256) k_cg_step(int64_t n, const double *__rest
 
 // CG direction: rz_new, rr from the np partials of k_cg_step; p = z + (rz_new /
 // rz_old) p; block 0 stores rz_new, rr and done = (rr <= *thr) (the next step
-// reads rz_new as its rz_old).  After a skipped step the partials are those of
-// the last real one, so the stored values do not change.
+// reads rz_new as its rz_old), and (rr, done) also into host_out (device view
+// of pinned host memory) when given.  After a skipped step the partials are
+// those of the last real one, so the stored values do not change.
 __global__ void __launch_bounds__(256) k_cg_dir(int64_t n, const double *__restrict__ part2, int np,
                                                 const double *__restrict__ rz_old, double *__restrict__ rz_new,
                                                 double *__restrict__ rr, double *__restrict__ p,
                                                 const double *__restrict__ z, const double *__restrict__ thr,
-                                                double *__restrict__ done)
+                                                double *__restrict__ done, double *__restrict__ host_out)
 {
     __shared__ double red[256];
     const double rzn = block_sum_parts(part2, np, red);
@@ -1901,9 +2036,14 @@ __global__ void __launch_bounds__(256) k_cg_dir(int64_t n, const double *__restr
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
         p[i] = z[i] + beta * p[i];
     if (blockIdx.x == 0 && threadIdx.x == 0) {
+        const double dn = rrn <= *thr ? 1.0 : 0.0;
         *rz_new = rzn;
         *rr = rrn;
-        *done = rrn <= *thr ? 1.0 : 0.0;
+        *done = dn;
+        if (host_out) {  // pinned host memory: (rr, done) of this step
+            host_out[0] = rrn;
+            host_out[1] = dn;
+        }
     }
 }
 
@@ -2711,7 +2851,8 @@ static igb_status create_device_geometry(igb_operator *op)
     if ((rc = dalloc(op, &op->dpart, nblk(s.ndof, 256) * esz))) return rc;  // p . Ap partials of the T pass
     if ((rc = dalloc(op, &op->tz, (size_t)s.npatch * s.ne * (s.p + 1) * s.ns1 * esz))) return rc;
     if ((rc = dalloc(op, (void **)&op->scal, 16 * sizeof(double)))) return rc;
-    HIPCHK(hipHostMalloc((void **)&op->h_scal, 16 * sizeof(double), hipHostMallocDefault));
+    // mapped and coherent: the CG direction kernel writes residuals into it directly
+    HIPCHK(hipHostMalloc((void **)&op->h_scal, 16 * sizeof(double), hipHostMallocMapped | hipHostMallocCoherent));
     if ((rc = dalloc(op, &op->potc, (size_t)s.nelem * s.grhs * s.grhs * esz))) return rc;
     return op->cplx ? assemble_identical<cd>(op) : assemble_identical<double>(op);
 }
@@ -2807,7 +2948,7 @@ static igb_status solve_cg(igb_operator *op, const double *b, double *w, double 
         if ((rc = dot_dev<double>(op, n, r, z, sc + 0))) return rc;
         // rz alternates between sc[0] and sc[2] (the step reads the old value while the
         // direction kernel writes the new one); r.z and r.r partials live in op->part.
-        // Step k copies (rr, done) to pinned slot k & 1 and records ev[k & 1]; the host
+        // Step k writes (rr, done) to pinned slot k & 1 and records ev[k & 1]; the host
         // reads step k while step k + 1 runs, and a step after convergence does nothing.
         double *pp = (double *)op->dpart, *p2 = (double *)op->part + 256;
         const int np = (int)nblk(n, 256);
@@ -2820,6 +2961,13 @@ static igb_status solve_cg(igb_operator *op, const double *b, double *w, double 
             (void)hipEventDestroy(ev[0]);
             return fail(IGB_EHIP, "hipEventCreate");
         }
+        // the direction kernel writes (rr, done) of step k straight into pinned slot k & 1
+        double *hres = nullptr;
+        if (hipHostGetDevicePointer((void **)&hres, op->h_scal + 8, 0) != hipSuccess) {
+            (void)hipEventDestroy(ev[0]);
+            (void)hipEventDestroy(ev[1]);
+            return fail(IGB_EHIP, "hipHostGetDevicePointer");
+        }
         int slot = 0, launched = 0, examined = 0;
         bool conv = false;
         rc = IGB_OK;
@@ -2829,12 +2977,9 @@ static igb_status solve_cg(igb_operator *op, const double *b, double *w, double 
                 hipLaunchKernelGGL(k_cg_step, dim3(gs), dim3(256), 0, op->st, n, sc + slot, pp, np, w, r, p, Ap, D, z,
                                    p2, sc + 4);
                 hipLaunchKernelGGL(k_cg_dir, dim3(gs), dim3(256), 0, op->st, n, p2, (int)gs, sc + slot, sc + (2 - slot),
-                                   sc + 3, p, z, sc + 5, sc + 4);
-                if (hipGetLastError() != hipSuccess) { rc = fail(IGB_EHIP, "CG kernel launch"); break; }
-                double *h = op->h_scal + 8 + 2 * (launched & 1);
-                if (hipMemcpyAsync(h, sc + 3, 2 * sizeof(double), hipMemcpyDeviceToHost, op->st) != hipSuccess ||
-                    hipEventRecord(ev[launched & 1], op->st) != hipSuccess) {
-                    rc = fail(IGB_EHIP, "CG residual copy");
+                                   sc + 3, p, z, sc + 5, sc + 4, hres + 2 * (launched & 1));
+                if (hipGetLastError() != hipSuccess || hipEventRecord(ev[launched & 1], op->st) != hipSuccess) {
+                    rc = fail(IGB_EHIP, "CG kernel launch");
                     break;
                 }
                 slot = 2 - slot;

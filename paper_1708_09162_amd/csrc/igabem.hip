@@ -403,7 +403,12 @@ __global__ void __launch_bounds__(64 * WAVES, NComp<T>::value == 1 ? 2 : 1) k_ne
     }
     __syncthreads();
     const int g = gs, g2 = g * g, g3 = g2 * g;
-    const int nreg = R.cls == 1 ? 8 : (R.cls == 2 ? 6 : 4);
+    // identical pairs: the region with both signs flipped is the x <-> y mirror of
+    // the one with (sg1, sg2 = 0) (same weights, the two points exchanged), so with
+    // a symmetric kernel its block is the transpose; only the four regions with
+    // sg2 = 0 are integrated and the output is S + S^T (the symmetrised sum of all
+    // eight)
+    const int nreg = R.cls == 1 ? 4 : (R.cls == 2 ? 6 : 4);
     const int chunks = (g3 + HALF - 1) / HALF;
     // acc[h]: lines on which F's fixed parameter is u (h = 1) or v (h = 0)
     v4d acc[2][NC][NT][NT];
@@ -417,7 +422,8 @@ __global__ void __launch_bounds__(64 * WAVES, NComp<T>::value == 1 ? 2 : 1) k_ne
                 for (int j = 0; j < NT; ++j) acc[h][c][i][j] = v4d{0.0, 0.0, 0.0, 0.0};
     const int col = lane & 15, sub = lane >> 4;
     for (int unit = wave; unit < nreg * chunks; unit += WAVES) {
-        const int reg = unit / chunks, line = (unit - reg * chunks) * HALF + pl;
+        const int ureg = unit / chunks, line = (unit - ureg * chunks) * HALF + pl;
+        const int reg = R.cls == 1 ? (ureg & 1) | ((ureg >> 1) << 2) : ureg;
         // the pair's line: fixed nodes (ia, ib, ic), weight Wl of the fixed part;
         // inactive lines get two distinct fixed points and zero weight
         Line LE{0.25, 0.25, 0.0, 0.0}, LF{0.75, 0.75, 0.0, 0.0};
@@ -628,9 +634,9 @@ __global__ void __launch_bounds__(64 * WAVES, NComp<T>::value == 1 ? 2 : 1) k_ne
                     if (R.cls == 1) tim += rw[NPAD * NPAD + rt];
                 }
             }
-            if (R.cls == 1) {
-                sre = 0.5 * (sre + tre);
-                sim = 0.5 * (sim + tim);
+            if (R.cls == 1) {  // S + S^T over the four integrated regions
+                sre = sre + tre;
+                sim = sim + tim;
             }
             T s;
             if constexpr (NC == 2) s = T{sre, sim};

@@ -128,14 +128,28 @@ void igb_geometry_destroy(igb_geometry *geo);
  * the 2^m x 2^m element grid, cluster tree and block partition (Sec. 4.1,
  * 4.2), near-field Galerkin quadrature (Sec. 3.2; Sec. 4 item 4), coupling
  * blocks and moment/transfer matrices (Sec. 4.2), Jacobi diagonal.  Device
- * memory is allocated here and freed by igb_operator_destroy.  `hip_stream`
+ * memory is taken here (from the pool, else hipMalloc) and given back by
+ * igb_operator_destroy.  `hip_stream`
  * is a hipStream_t (NULL = default stream) used by every later call on the
  * operator.  Synchronises the stream before returning.
  * IGB_EINVAL for parameters out of range or geometry whose interior knots are
  * off the refinement grid; IGB_ENOMEM if HBM runs out; IGB_EHIP otherwise. */
 igb_status igb_operator_create(const igb_geometry *geo, const igb_params *prm, void *hip_stream,
                                igb_operator **out);
+/* Synchronises the operator's stream, then gives its device buffers back to
+ * the library's memory pool (see igb_release_cached_memory). */
 void igb_operator_destroy(igb_operator *op);
+
+/* Device memory pool.  The buffers of destroyed operators (and the scratch of
+ * igb_potential) are kept per device, in size classes (4 KiB steps up to
+ * 2 MiB, 2 MiB steps above), and handed to later allocations of the same
+ * class, so an application that creates operators repeatedly calls hipMalloc
+ * and hipFree only the first time.  An allocation that runs out of device
+ * memory frees the cache and tries once more.  This call frees every cached
+ * buffer on every device now (buffers of live operators are not touched).
+ * Thread-safe.  Makes no HIP call when nothing is cached.  IGB_OK, or
+ * IGB_EHIP if a hipFree fails. */
+igb_status igb_release_cached_memory(void);
 
 /* Fills `out` (host).  Synchronous. */
 igb_status igb_operator_info(const igb_operator *op, igb_info *out);

@@ -7,6 +7,8 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -2140,6 +2142,102 @@ __global__ void k_sub_Vh(int64_t n, int k, const T *__restrict__ V, int64_t ldv,
 // operator object
 // ===========================================================================
 
+// ---------------------------------------------------------------------------
+// device memory pool
+// ---------------------------------------------------------------------------
+// Process-wide, per device: buffers given back by destroyed operators (and the
+// scratch of potentials and exports) stay in free lists by size class and go
+// to later requests of the same class, so an application that creates
+// operators again and again calls hipMalloc / hipFree only the first time.
+// igb_release_cached_memory frees what is cached; an allocation that fails for
+// lack of memory releases the cache and tries once more.  A buffer is given
+// back only after its operator's stream has drained.
+struct DevBlock {
+    void *p = nullptr;
+    size_t bytes = 0;  // size class actually allocated
+    int dev = 0;
+};
+
+namespace {
+struct DevPool {
+    std::mutex mu;
+    std::map<std::pair<int, size_t>, std::vector<void *>> lists;
+};
+DevPool &dev_pool()
+{
+    static DevPool *p = new DevPool();  // lives until the process ends
+    return *p;
+}
+size_t pool_class(size_t b)
+{
+    const size_t big = (size_t)2 << 20;
+    return b <= big ? (b + 4095) / 4096 * 4096 : (b + big - 1) / big * big;
+}
+}  // namespace
+
+static hipError_t pool_release_all()
+{
+    DevPool &P = dev_pool();
+    std::lock_guard<std::mutex> lk(P.mu);
+    bool any = false;
+    for (auto &kv : P.lists) any = any || !kv.second.empty();
+    if (!any) return hipSuccess;
+    int cur = 0;
+    const hipError_t ecur = hipGetDevice(&cur);
+    hipError_t res = hipSuccess;
+    for (auto &kv : P.lists) {
+        if (kv.second.empty()) continue;
+        hipError_t e = hipSetDevice(kv.first.first);
+        for (void *q : kv.second)
+            if (e == hipSuccess) e = hipFree(q);
+        if (e != hipSuccess) res = e;
+        kv.second.clear();
+    }
+    if (ecur == hipSuccess) (void)hipSetDevice(cur);
+    return res;
+}
+
+static hipError_t pool_alloc(DevBlock &b, size_t bytes)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    const size_t c = pool_class(bytes == 0 ? 8 : bytes);
+    {
+        DevPool &P = dev_pool();
+        std::lock_guard<std::mutex> lk(P.mu);
+        auto it = P.lists.find({dev, c});
+        if (it != P.lists.end() && !it->second.empty()) {
+            b.p = it->second.back();
+            b.bytes = c;
+            b.dev = dev;
+            it->second.pop_back();
+            return hipSuccess;
+        }
+    }
+    void *q = nullptr;
+    e = hipMalloc(&q, c);
+    if (e == hipErrorOutOfMemory) {
+        (void)hipGetLastError();
+        (void)pool_release_all();
+        e = hipMalloc(&q, c);
+    }
+    if (e != hipSuccess) return e;
+    b.p = q;
+    b.bytes = c;
+    b.dev = dev;
+    return hipSuccess;
+}
+
+static void pool_free(DevBlock &b)
+{
+    if (!b.p) return;
+    DevPool &P = dev_pool();
+    std::lock_guard<std::mutex> lk(P.mu);
+    P.lists[{b.dev, b.bytes}].push_back(b.p);
+    b = DevBlock{};
+}
+
 struct igb_operator {
     Setup s;
     hipStream_t st = nullptr;
@@ -2200,19 +2298,21 @@ struct igb_operator {
     std::vector<PairRec> touch_id, touch;  // host copies of the staged pairs
     int64_t near_bytes = 0, coup_bytes = 0;
     double assembly_seconds = 0.0;
-    std::vector<void *> owned;
+    std::vector<DevBlock> owned;
+    DevBlock Vblk{}, hblk{}, mblk{};  // GMRES basis, projections, multi-dot partials
 };
 
 static igb_status dalloc(igb_operator *op, void **p, size_t bytes)
 {
-    if (bytes == 0) bytes = 8;
-    hipError_t e = hipMalloc(p, bytes);
+    DevBlock b{};
+    hipError_t e = pool_alloc(b, bytes);
     if (e != hipSuccess) {
         *p = nullptr;
         return fail(e == hipErrorOutOfMemory ? IGB_ENOMEM : IGB_EHIP,
                     "hipMalloc(" + std::to_string(bytes) + " bytes): " + hipGetErrorString(e));
     }
-    op->owned.push_back(*p);
+    *p = b.p;
+    op->owned.push_back(b);
     return IGB_OK;
 }
 
@@ -3020,11 +3120,18 @@ static igb_status solve_gmres(igb_operator *op, const cd *b, cd *w, double tol, 
     int R = std::max(1, std::min(restart, std::max(1, maxit)));
     igb_status rc;
     if (op->Vcols < R + 1) {
-        if (op->V) { (void)hipFree(op->V); (void)hipFree(op->hdev); (void)hipFree(op->mpart); }
+        HIPCHK(hipStreamSynchronize(op->st));
+        pool_free(op->Vblk);
+        pool_free(op->hblk);
+        pool_free(op->mblk);
         op->V = op->hdev = op->mpart = nullptr;
-        HIPCHK(hipMalloc(&op->V, (size_t)(R + 1) * n * sizeof(cd)));
-        HIPCHK(hipMalloc(&op->hdev, (size_t)(R + 1) * sizeof(cd)));
-        HIPCHK(hipMalloc(&op->mpart, (size_t)(R + 1) * kRedBlocks * sizeof(cd)));
+        op->Vcols = 0;
+        HIPCHK(pool_alloc(op->Vblk, (size_t)(R + 1) * n * sizeof(cd)));
+        HIPCHK(pool_alloc(op->hblk, (size_t)(R + 1) * sizeof(cd)));
+        HIPCHK(pool_alloc(op->mblk, (size_t)(R + 1) * kRedBlocks * sizeof(cd)));
+        op->V = op->Vblk.p;
+        op->hdev = op->hblk.p;
+        op->mpart = op->mblk.p;
         op->Vcols = R + 1;
     }
     cd *V = (cd *)op->V, *hd = (cd *)op->hdev, *t = (cd *)op->tmp, *r = (cd *)op->r, *t2 = (cd *)op->z;
@@ -3165,13 +3272,26 @@ void igb_geometry_destroy(igb_geometry *geo) { delete geo; }
 void igb_operator_destroy(igb_operator *op)
 {
     if (!op) return;
-    (void)hipStreamSynchronize(op->st);
-    for (void *p : op->owned) (void)hipFree(p);
-    if (op->V) (void)hipFree(op->V);
-    if (op->hdev) (void)hipFree(op->hdev);
-    if (op->mpart) (void)hipFree(op->mpart);
+    // buffers go back to the pool only once the operator's stream has drained
+    if (hipStreamSynchronize(op->st) == hipSuccess) {
+        for (DevBlock &b : op->owned) pool_free(b);
+        pool_free(op->Vblk);
+        pool_free(op->hblk);
+        pool_free(op->mblk);
+    } else {
+        for (DevBlock &b : op->owned) (void)hipFree(b.p);
+        (void)hipFree(op->Vblk.p);
+        (void)hipFree(op->hblk.p);
+        (void)hipFree(op->mblk.p);
+    }
     if (op->h_scal) (void)hipHostFree(op->h_scal);
     delete op;
+}
+
+igb_status igb_release_cached_memory(void)
+{
+    const hipError_t e = pool_release_all();
+    return e == hipSuccess ? IGB_OK : fail(IGB_EHIP, std::string("hipFree: ") + hipGetErrorString(e));
 }
 
 igb_status igb_operator_create(const igb_geometry *geo, const igb_params *prm, void *hip_stream, igb_operator **out)
@@ -3377,15 +3497,17 @@ static igb_status potential_impl(igb_operator *op, const T *w, int64_t npts, con
     int64_t tb = (npts + 255) / 256;
     int64_t nchunk = std::max<int64_t>(1, std::min<int64_t>(4096 / tb + 1, (nq + 4095) / 4096));
     int64_t chunk = (nq + nchunk - 1) / nchunk;
-    T *part = nullptr;
-    HIPCHK(hipMalloc((void **)&part, (size_t)nchunk * npts * sizeof(T)));
+    DevBlock pb{};
+    HIPCHK(pool_alloc(pb, (size_t)nchunk * npts * sizeof(T)));
+    T *part = (T *)pb.p;
     hipLaunchKernelGGL((k_pot_eval<T>), dim3((unsigned)tb, (unsigned)nchunk), dim3(256), 0, op->st, npts, X, nq, op->rpts,
                        (const T *)op->potc, s.kappa, chunk, part);
     hipError_t e1 = hipGetLastError();
     hipLaunchKernelGGL((k_pot_reduce<T>), dim3((unsigned)tb), dim3(256), 0, op->st, npts, (int)nchunk, (const T *)part, u);
     hipError_t e2 = hipGetLastError();
     hipError_t e3 = hipStreamSynchronize(op->st);
-    (void)hipFree(part);
+    if (e3 == hipSuccess) pool_free(pb);
+    else (void)hipFree(pb.p);
     if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) return fail(IGB_EHIP, "potential evaluation failed");
     return IGB_OK;
 }

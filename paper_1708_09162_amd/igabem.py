@@ -35,7 +35,7 @@ EXPORTED = [
     "igb_matvec_super", "igb_apply_Tt", "igb_apply_T", "igb_jacobi_diag", "igb_solve", "igb_potential",
     "igb_export_partition", "igb_export_pair_classes", "igb_export_near_block", "igb_export_coupling_block",
     "igb_plan_create", "igb_plan_destroy", "igb_plan_info", "igb_plan_export_partition",
-    "igb_plan_export_pair_classes", "igb_matvec_profile",
+    "igb_plan_export_pair_classes", "igb_matvec_profile", "igb_release_cached_memory",
 ]
 IGB_PROFILE_SEPARATE = 1
 STAGES = ["upward", "coupling", "coupling_gather", "near_gemv", "near_gather", "downward"]
@@ -98,6 +98,7 @@ def _load():
         "igb_plan_info": (C.c_int32, [vp, C.POINTER(igb_info)]),
         "igb_plan_export_partition": (C.c_int32, [vp, ip, ip]),
         "igb_plan_export_pair_classes": (C.c_int32, [vp, ip]),
+        "igb_release_cached_memory": (C.c_int32, []),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -160,6 +161,11 @@ def igb_operator_create(geo, prm: igb_params, stream) -> C.c_void_p:
 
 def igb_operator_destroy(h):
     _lib.igb_operator_destroy(h)
+
+
+def igb_release_cached_memory() -> None:
+    """Frees the device buffers the library keeps for reuse by later operators."""
+    _check(_lib.igb_release_cached_memory())
 
 
 def igb_operator_info(op) -> igb_info:

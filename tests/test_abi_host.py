@@ -31,6 +31,12 @@ def test_stage_names_match_header():
     assert n == len(igb.STAGES)
 
 
+def test_release_cached_memory_with_nothing_cached():
+    # no operator was ever created in this process: nothing is cached and no HIP call is made
+    igb.igb_release_cached_memory()
+    igb.igb_release_cached_memory()
+
+
 def test_geometry_validation_errors():
     good = W.sphere_patches()[0]
     igb.Geometry([good])

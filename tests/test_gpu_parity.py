@@ -220,6 +220,30 @@ def test_h2_superspace_matvec(case, mode):
     assert rel(to_np(op.jacobi_diag()), P.jacobi_diag()) < 1e-12
 
 
+def test_operator_from_pooled_memory_is_bitwise_identical():
+    """Operators built from buffers that an earlier operator gave back to the memory pool (stale
+    contents) give bitwise the same products and solution as the first one."""
+    say("pool: three operators, sphere p=2 m=3 q=5 on the fly")
+    kw = dict(p=2, m=3, q=5, leaf_depth=1, eta=1.6, gauss_regular=6, mode=igb.IGB_H2_ONTHEFLY, device=DEV)
+    g = igb.Geometry(W.sphere_patches())
+    x = torch.tensor(rand(igb.Operator(g, **kw).info.n_dof, 21), device=DEV)
+    igb.igb_release_cached_memory()
+    ref = None
+    for k in range(3):
+        op = igb.Operator(g, **kw)
+        y = to_np(op.matvec(x))
+        w, info = op.solve(op.matvec(x), tol=1e-10, max_iter=500)
+        got = (y, to_np(w), info.iterations)
+        if ref is None:
+            ref = got
+        else:
+            assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1]) and got[2] == ref[2], k
+        del op
+        torch.cuda.synchronize()
+        if k == 1:
+            igb.igb_release_cached_memory()
+
+
 def test_h2_solve_density_parity():
     say("h2 solve: sphere p=1 m=3 q=4")
     op, P = make(W.sphere_patches(), p=1, m=3, q=4, leaf_depth=1, eta=1.6, gauss_regular=6)

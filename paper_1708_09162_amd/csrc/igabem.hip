@@ -131,13 +131,13 @@ __global__ void __launch_bounds__(128) k_near_regular(const PairRec *__restrict_
                                                       double kappa, int nl, int ld, const int32_t *__restrict__ sb,
                                                       T *__restrict__ blocks)
 {
-    constexpr int P1 = P + 1, NLOC = P1 * P1;
+    constexpr int P1 = P + 1, NLOC = P1 * P1, TS = NLOC + 1;  // tmp row stride: rows on distinct banks
     extern __shared__ double sh[];
     int gg = g * g;
     double *X = sh;                        // gg*4
     double *Y = X + gg * 4;                // gg*4
     double *psi = Y + gg * 4;              // gg*NLOC
-    T *tmp = (T *)(psi + (size_t)gg * NLOC);  // gg*NLOC
+    T *tmp = (T *)(psi + (size_t)gg * NLOC);  // gg*TS
     PairRec R = pairs[blockIdx.x];
     const double *gE = gp + (size_t)R.E * gg * 4, *gF = gp + (size_t)R.F * gg * 4;
     for (int k = threadIdx.x; k < gg * 4; k += blockDim.x) {
@@ -165,7 +165,7 @@ __global__ void __launch_bounds__(128) k_near_regular(const PairRec *__restrict_
         }
         double kw = X[4 * i + 3];
 #pragma unroll
-        for (int b = 0; b < NLOC; ++b) tmp[i * NLOC + b] = acc[b] * kw;
+        for (int b = 0; b < NLOC; ++b) tmp[i * TS + b] = acc[b] * kw;
     }
     __syncthreads();
     T *out1, *out2;
@@ -173,7 +173,7 @@ __global__ void __launch_bounds__(128) k_near_regular(const PairRec *__restrict_
     for (int o = threadIdx.x; o < NLOC * NLOC; o += blockDim.x) {
         int a = o / NLOC, b = o % NLOC;
         T s = zero<T>();
-        for (int i = 0; i < gg; ++i) s += psi[i * NLOC + a] * tmp[i * NLOC + b];
+        for (int i = 0; i < gg; ++i) s += psi[i * NLOC + a] * tmp[i * TS + b];
         if (out1) out1[blk_pos(ld, NLOC, R.elE, a, R.elF, b)] = s;
         if (out2) out2[blk_pos(ld, NLOC, R.elF, b, R.elE, a)] = s;
     }
@@ -2379,12 +2379,14 @@ template <class T, int P>
 static igb_status launch_regular_p(igb_operator *op, const PairRec *d_pairs, int64_t n, int g, const double *gp)
 {
     int gg = g * g, NLOC = (P + 1) * (P + 1);
-    size_t shm = (size_t)gg * 8 * sizeof(double) + (size_t)gg * NLOC * sizeof(double) + (size_t)gg * NLOC * sizeof(T);
+    size_t shm =
+        (size_t)gg * 8 * sizeof(double) + (size_t)gg * NLOC * sizeof(double) + (size_t)gg * (NLOC + 1) * sizeof(T);
     if (shm > 160 * 1024) return fail(IGB_EUNSUPPORTED, "regular quadrature order too large for LDS");
     (void)hipFuncSetAttribute((const void *)k_near_regular<T, P>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+    const int threads = gg <= 64 ? 64 : 128;  // one quadrature point of E per thread in the first phase
     for (int64_t off = 0; off < n; off += 1 << 20) {
         int64_t cnt = std::min<int64_t>(n - off, 1 << 20);
-        hipLaunchKernelGGL((k_near_regular<T, P>), dim3((unsigned)cnt), dim3(128), shm, op->st, d_pairs + off, (int)cnt, g,
+        hipLaunchKernelGGL((k_near_regular<T, P>), dim3((unsigned)cnt), dim3(threads), shm, op->st, d_pairs + off, (int)cnt, g,
                            gp, op->btab + (size_t)op->s.goff[g] * (P + 1), op->s.kappa, op->s.nl, op->near_ld, op->sb,
                            (T *)op->nearb);
         LAUNCHCHK();

@@ -319,6 +319,20 @@ void tile_eval(const Setup &s, int E, double u, double v, double X[3], double *k
     double Bu[16], dBu[16], Bv[16], dBv[16];
     bern(pu, u, Bu, dBu);
     bern(pv, v, Bv, dBv);
+    if (!kap) {  // position only: the same sums for S, no tangents
+        double S[4] = {0, 0, 0, 0};
+        for (int j = 0; j <= pv; ++j) {
+            double A[4] = {0, 0, 0, 0};
+            for (int i = 0; i <= pu; ++i) {
+                const double *h = H + 4 * (j * (pu + 1) + i);
+                for (int c = 0; c < 4; ++c) A[c] += Bu[i] * h[c];
+            }
+            for (int c = 0; c < 4; ++c) S[c] += Bv[j] * A[c];
+        }
+        const double iw = 1.0 / S[3];
+        for (int c = 0; c < 3; ++c) X[c] = S[c] * iw;
+        return;
+    }
     double S[4] = {0, 0, 0, 0}, Su[4] = {0, 0, 0, 0}, Sv[4] = {0, 0, 0, 0};
     for (int j = 0; j <= pv; ++j) {
         double A[4] = {0, 0, 0, 0}, Ad[4] = {0, 0, 0, 0};
@@ -455,6 +469,7 @@ static void build_partition(Setup &s)
         bool dense = (s.mode == IGB_DENSE);
         if (!dense) level_geo(s, l, G);
         std::vector<BP> nxt;
+        nxt.reserve(l < s.L ? 16 * cur.size() : 0);
         int n = 1 << l, nn = 2 * n;
         std::vector<char> adm(cur.size(), 0);
         if (!dense)
@@ -483,47 +498,50 @@ static void build_partition(Setup &s)
         }
         cur.swap(nxt);
     }
-    // sort (packed keys; cluster indices are below 2^29 by the size limits)
+    // CSR by target (counting sort), sources ascending within a row: the order
+    // of (target, source) for the near list and (level, target, source) for
+    // the far list; both lists are then rewritten in that order
     {
-        size_t nb = s.near.size() / 2;
-        std::vector<uint64_t> key(nb);
-        for (size_t k = 0; k < nb; ++k) key[k] = ((uint64_t)(uint32_t)s.near[2 * k] << 32) | (uint32_t)s.near[2 * k + 1];
-        std::sort(key.begin(), key.end());
-        for (size_t k = 0; k < nb; ++k) {
-            s.near[2 * k] = (int32_t)(key[k] >> 32);
-            s.near[2 * k + 1] = (int32_t)(key[k] & 0xffffffffu);
-        }
+        const size_t nb = s.near.size() / 2;
+        s.near_ptr.assign(s.nleaf + 1, 0);
+        for (size_t k = 0; k < nb; ++k) s.near_ptr[s.near[2 * k] + 1]++;
+        for (int i = 0; i < s.nleaf; ++i) s.near_ptr[i + 1] += s.near_ptr[i];
+        s.near_src.assign(nb, 0);
+        std::vector<int64_t> fill(s.near_ptr.begin(), s.near_ptr.end() - 1);
+        for (size_t k = 0; k < nb; ++k) s.near_src[fill[s.near[2 * k]]++] = s.near[2 * k + 1];
+        parallel_chunks(s.nleaf, 1 << 30, [&](int64_t b, int64_t e, int) {
+            for (int64_t t = b; t < e; ++t)
+                std::sort(s.near_src.begin() + s.near_ptr[t], s.near_src.begin() + s.near_ptr[t + 1]);
+        });
+        for (int64_t t = 0; t < s.nleaf; ++t)
+            for (int64_t k = s.near_ptr[t]; k < s.near_ptr[t + 1]; ++k) {
+                s.near[2 * k] = (int32_t)t;
+                s.near[2 * k + 1] = s.near_src[k];
+            }
     }
     {
-        size_t nb = s.far.size() / 3;
-        std::vector<uint64_t> key(nb);
-        for (size_t k = 0; k < nb; ++k)
-            key[k] = ((uint64_t)s.far[3 * k] << 58) | ((uint64_t)(uint32_t)s.far[3 * k + 1] << 29) | (uint32_t)s.far[3 * k + 2];
-        std::sort(key.begin(), key.end());
-        const uint64_t m29 = (1ull << 29) - 1;
+        const size_t nb = s.far.size() / 3;
+        const int64_t ncl_all = s.cl_off[s.L + 1];
+        s.far_ptr.assign(ncl_all + 1, 0);
+        for (size_t k = 0; k < nb; ++k) s.far_ptr[s.cl_off[s.far[3 * k]] + s.far[3 * k + 1] + 1]++;
+        for (int64_t i = 0; i < ncl_all; ++i) s.far_ptr[i + 1] += s.far_ptr[i];
+        s.far_src.assign(nb, 0);
+        std::vector<int64_t> fill(s.far_ptr.begin(), s.far_ptr.end() - 1);
         for (size_t k = 0; k < nb; ++k) {
-            s.far[3 * k] = (int32_t)(key[k] >> 58);
-            s.far[3 * k + 1] = (int32_t)((key[k] >> 29) & m29);
-            s.far[3 * k + 2] = (int32_t)(key[k] & m29);
+            const int l = s.far[3 * k];
+            s.far_src[fill[s.cl_off[l] + s.far[3 * k + 1]]++] = (int32_t)(s.cl_off[l] + s.far[3 * k + 2]);
         }
+        parallel_chunks(ncl_all, 1 << 30, [&](int64_t b, int64_t e, int) {
+            for (int64_t g = b; g < e; ++g) std::sort(s.far_src.begin() + s.far_ptr[g], s.far_src.begin() + s.far_ptr[g + 1]);
+        });
+        for (int l = 0; l <= s.L; ++l)
+            for (int64_t g = s.cl_off[l]; g < s.cl_off[l + 1]; ++g)
+                for (int64_t k = s.far_ptr[g]; k < s.far_ptr[g + 1]; ++k) {
+                    s.far[3 * k] = l;
+                    s.far[3 * k + 1] = (int32_t)(g - s.cl_off[l]);
+                    s.far[3 * k + 2] = (int32_t)(s.far_src[k] - s.cl_off[l]);
+                }
     }
-    // CSR structures
-    s.near_ptr.assign(s.nleaf + 1, 0);
-    s.near_src.resize(s.near.size() / 2);
-    for (size_t k = 0; k < s.near.size() / 2; ++k) {
-        s.near_ptr[s.near[2 * k] + 1]++;
-        s.near_src[k] = s.near[2 * k + 1];
-    }
-    for (int i = 0; i < s.nleaf; ++i) s.near_ptr[i + 1] += s.near_ptr[i];
-    int64_t ncl_all = s.cl_off[s.L + 1];
-    s.far_ptr.assign(ncl_all + 1, 0);
-    s.far_src.resize(s.far.size() / 3);
-    for (size_t k = 0; k < s.far.size() / 3; ++k) {
-        int l = s.far[3 * k];
-        s.far_ptr[s.cl_off[l] + s.far[3 * k + 1] + 1]++;
-        s.far_src[k] = (int32_t)(s.cl_off[l] + s.far[3 * k + 2]);
-    }
-    for (int64_t i = 0; i < ncl_all; ++i) s.far_ptr[i + 1] += s.far_ptr[i];
 }
 
 // ---------------------------------------------------------------------------
@@ -542,9 +560,12 @@ static int other_adjacent(int o, int a)
 // touching test and the regular-pair order
 static void element_geometry_one(Setup &s, int E)
 {
-    for (int c = 0; c < 4; ++c) tile_eval(s, E, kCorner[c][0], kCorner[c][1], &s.ecorner[(size_t)E * 12 + 3 * c], nullptr);
     for (int b = 0; b < 3; ++b)
         for (int a = 0; a < 3; ++a) tile_eval(s, E, 0.5 * a, 0.5 * b, &s.egrid[(size_t)E * 27 + 3 * (3 * b + a)], nullptr);
+    // the corners are grid points (same parameters, same values)
+    for (int c = 0; c < 4; ++c)
+        std::memcpy(&s.ecorner[(size_t)E * 12 + 3 * c], &s.egrid[(size_t)E * 27 + 3 * (3 * 2 * kCorner[c][1] + 2 * kCorner[c][0])],
+                    3 * sizeof(double));
     double d = 0.0;
     for (int i = 0; i < 9; ++i)
         for (int j = i + 1; j < 9; ++j) d = std::max(d, dist(&s.egrid[(size_t)E * 27 + 3 * i], &s.egrid[(size_t)E * 27 + 3 * j]));

@@ -347,6 +347,38 @@ def test_full_size_sampled_rows(mode):
     assert abs(zs @ ys - xs @ yz) <= 1e-12 * abs(zs @ ys)
 
 
+def test_full_size_perturbed_sphere_sampled_rows():
+    """Laplace on the radially perturbed sphere (amplitude 0.1, spherical-harmonic degree <= 6, seed 5),
+    p=2, 128x128 elements per patch (leaves of 4x4 elements, 144 superspace functions), q=8, far field
+    on the fly: GPU superspace product against the oracle's row-sampled product on random target leaves,
+    and the symmetry of the assembled operator."""
+    say("full size perturbed sphere p=2 m=7 q=8 onthefly: assemble")
+    op, P = make(W.perturbed_sphere_patches(0.1, 5), mode=igb.IGB_H2_ONTHEFLY, p=2, m=7, q=8, eta=1.6,
+                 gauss_regular=6)
+    assert op.info.n_dof == 101400 and op.info.n_dof_super == 884736
+    xs = rand(P.nsup, 15)
+    say("perturbed sphere: matvec")
+    ys = to_np(op.matvec_super(torch.tensor(xs)))
+    zs = rand(P.nsup, 16)
+    yz = to_np(op.matvec_super(torch.tensor(zs)))
+    assert abs(zs @ ys - xs @ yz) <= 1e-12 * abs(zs @ ys)
+    del op
+    torch.cuda.empty_cache()
+    n, side, ne, nloc = 32, 4, 128, 9
+    leaves = np.sort(np.random.default_rng(17).choice(6 * n * n, 4, replace=False)).astype(np.int32)
+    say("perturbed sphere: oracle rows")
+    rows = P.h2_matvec_rows(xs, leaves)
+    got = []
+    for leaf in leaves:
+        pt, r = divmod(int(leaf), n * n)
+        k2, k1 = divmod(r, n)
+        for a2 in range(side):
+            for a1 in range(side):
+                E = pt * ne * ne + (k2 * side + a2) * ne + k1 * side + a1
+                got.append(ys[E * nloc:(E + 1) * nloc])
+    assert rel(np.concatenate(got), rows.reshape(-1)) < 1e-12
+
+
 def test_full_size_helmholtz_torus_sampled_rows():
     """Helmholtz on the 16-patch torus, kappa=8, p=2, 64x64 elements per patch, q=10 (on-the-fly far
     field): GPU superspace product against the oracle's row-sampled product on random target leaves."""

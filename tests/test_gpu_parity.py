@@ -244,6 +244,29 @@ def test_operator_from_pooled_memory_is_bitwise_identical():
             igb.igb_release_cached_memory()
 
 
+@pytest.mark.parametrize("seed", range(4))
+def test_mixed_instances_h2_matvec(seed):
+    """Seeded instances in the shape of the batched workload (sphere with 4x4 or 8x8 elements per patch,
+    or the torus with 4x4, p in {1,2,3}, Laplace or Helmholtz with kappa uniform in [1,16], q in 4..8, stored or on-the-fly
+    coupling): GPU superspace product against the oracle's H2 product."""
+    rng = np.random.default_rng(4 + seed)
+    torus = bool(rng.integers(2))
+    m = 2 if torus else int(rng.integers(2, 4))  # the 16-patch torus at 4x4 elements per patch
+    p = int(rng.integers(1, 4))
+    helm = bool(rng.integers(2))
+    kappa = float(rng.uniform(1.0, 16.0)) if helm else 0.0
+    q = int(rng.integers(4, 9))
+    mode = igb.IGB_H2_STORED if rng.integers(2) else igb.IGB_H2_ONTHEFLY
+    say(f"mixed {seed}: torus={torus} m={m} p={p} kappa={kappa:.3f} q={q} mode={mode}")
+    kw = dict(p=p, m=m, q=q, leaf_depth=1, eta=1.6, gauss_regular=6)
+    if helm:
+        kw.update(kernel=igb.IGB_HELMHOLTZ, wavenumber=kappa)
+    op, P = make(W.torus_patches() if torus else W.sphere_patches(), mode=mode, **kw)
+    P.h2_assemble(store_coupling=True)
+    xs = rand(P.nsup, 40 + seed, cplx=helm)
+    assert rel(to_np(op.matvec_super(torch.tensor(xs))), P.h2_matvec_super(xs)) < 1e-12
+
+
 def test_h2_solve_density_parity():
     say("h2 solve: sphere p=1 m=3 q=4")
     op, P = make(W.sphere_patches(), p=1, m=3, q=4, leaf_depth=1, eta=1.6, gauss_regular=6)

@@ -98,12 +98,12 @@ def charge_field(torch, pts, pos, q):
     return g
 
 
-def one_step(torch, igb, geo, cfg, ev_dev, mode):
+def one_step(torch, igb, geo, cfg, ev_dev, mode, far_precision=0):
     """The whole path once; returns (operator, density, solve info, potential, timings)."""
     t = {}
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    op = igb.Operator(geo, device="cuda:0", mode=MODES[mode], **PRM)
+    op = igb.Operator(geo, device="cuda:0", mode=MODES[mode], far_precision=far_precision, **PRM)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     pts = op.rhs_points()
@@ -118,6 +118,30 @@ def one_step(torch, igb, geo, cfg, ev_dev, mode):
     t4 = time.perf_counter()
     t.update(assembly_s=t1 - t0, rhs_s=t2 - t1, solve_s=t3 - t2, potential_s=t4 - t3, total_s=t4 - t0)
     return op, w, info, u, t
+
+
+def mixed_leg(torch, igb, geo, cfg, ev_dev, fp64_ms, exact, steps: int = 2):
+    """The same step with the single-precision far field (far_precision IGB_FP32) and the solve refined to
+    the FP64 tolerance with FP64 residuals: time-to-solve beside the plain FP64 one."""
+    op, w, info, u, t = one_step(torch, igb, geo, cfg, ev_dev, "onthefly", igb.IGB_FP32)  # warmup
+    del op
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        op, w, info, u, t = one_step(torch, igb, geo, cfg, ev_dev, "onthefly", igb.IGB_FP32)
+        if _ + 1 < steps:
+            del op
+    torch.cuda.synchronize()
+    ms = 1e3 * (time.perf_counter() - t0) / steps
+    st = op.profile(reps=20)
+    print(f"[bench] single-precision far field: {ms / 1e3:.4f} s per step, {info.iterations} it", file=sys.stderr,
+          flush=True)
+    return {"far_precision": "fp32 (kernel values from the hardware reciprocal square root, FP64 sums)",
+            "value": round(ms / 1e3, 5), "ms_per_step": round(ms, 3), "vs_fp64": round(ms / fp64_ms, 4),
+            "iterations": int(info.iterations), "rel_residual": float(info.rel_residual),
+            "potential_max_err": float(np.abs(u.cpu().numpy() - exact).max()),
+            "breakdown_s": {k: round(v, 4) for k, v in t.items()},
+            "coupling_ms": round(st["coupling"], 4)}
 
 
 def cpu_baseline(cfg, iterations: int, seed: int = 7):
@@ -165,6 +189,7 @@ def main():
     ap.add_argument("--mode", choices=sorted(MODES), default="onthefly",
                     help="far field: coupling blocks generated in every matvec (default) or stored in HBM")
     ap.add_argument("--calibrate-copy", action="store_true", help="only run a plain 1 GiB device copy")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the single-precision far-field leg")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -322,6 +347,8 @@ def main():
         "roofline_stages": roofs,
         "cpu_baseline": None,
     }
+    if args.mode == "onthefly" and not args.no_mixed:
+        out["mixed_fp32_far"] = mixed_leg(torch, igb, geo, cfg, ev_dev, ms_per_step, exact)
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle sample)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(cfg, int(info.iterations))

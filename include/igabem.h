@@ -52,6 +52,15 @@ typedef int32_t igb_status;
 #define IGB_H2_ONTHEFLY 2        /* near field stored; coupling blocks generated inside every matvec */
 
 #define IGB_FP64 0
+/* Single-precision far field (Laplace, on-the-fly coupling, q <= 8): every
+ * coupling-kernel value 1/|x - y| is the hardware reciprocal-square-root
+ * estimate without refinement (relative error below 6e-8, single-precision
+ * accuracy); distances, moments, transfers, sums and the near field stay FP64.
+ * igb_matvec / igb_matvec_super apply this operator; igb_solve still solves
+ * the FP64 system: CG steps with this operator, the recursive residual
+ * replaced by the FP64 residual b - A w (full-precision far field) every 20
+ * steps, convergence judged on the FP64 residual. */
+#define IGB_FP32 1
 
 /* One NURBS patch F_j : [0,1]^2 -> Gamma_j (Sec. 2.2, eq. def::geom).
  * knots_u has n_u + deg_u + 1 entries, p-open (Sec. 2.1): deg_u+1 zeros first,
@@ -81,7 +90,7 @@ typedef struct {
     int32_t gauss_singular;  /* points per variable in the regularised touching-pair rules; -1: g0+2 */
     int32_t gauss_rhs;       /* points per direction for right-hand side and potential; -1: max(g0, p+4) */
     int32_t mode;            /* IGB_DENSE, IGB_H2_STORED or IGB_H2_ONTHEFLY */
-    int32_t far_precision;   /* IGB_FP64 */
+    int32_t far_precision;   /* IGB_FP64, or IGB_FP32 (see there) */
 } igb_params;
 
 /* Sizes of an assembled operator (host struct filled by igb_operator_info). */

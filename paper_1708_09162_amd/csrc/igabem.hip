@@ -1352,7 +1352,7 @@ __device__ inline void far_sym_chunk(const FarSymArgs &F, int64_t k0, int64_t k1
 // nodes per cluster (padding as in far_node).  Result layout of the product:
 // lane l, element e holds row 4e + l/16 (target), column l%16 (source).
 typedef double v4d_far __attribute__((ext_vector_type(4)));
-template <int NTI>
+template <int NTI, bool RAW>
 __device__ inline void far_mfma_chunk(const FarSymArgs &F, int64_t k0, int64_t k1, const double *__restrict__ Xh,
                                       double *__restrict__ part, double *lds)
 {
@@ -1423,7 +1423,9 @@ __device__ inline void far_mfma_chunk(const FarSymArgs &F, int64_t k0, int64_t k
                 const v4d_far d = __builtin_amdgcn_mfma_f64_16x16x4f64(aop[ti], bop[tj], cin[ti], 0, 0, 0);
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {
-                    const double ir = rsqrt_pos(d[e]);
+                    // RAW: the hardware estimate alone (relative error below 6e-8, single-precision
+                    // far field); else refined to full double precision
+                    const double ir = RAW ? __builtin_amdgcn_rsq(d[e]) : rsqrt_pos(d[e]);
                     racc[e] += ir * ws[tj];
                     csum[tj] += ir * wt[ti][e];
                 }
@@ -1452,18 +1454,23 @@ __device__ inline void far_mfma_chunk(const FarSymArgs &F, int64_t k0, int64_t k
 }
 
 // Far-field pairs k0 .. k1-1 of one wave: matrix-core path for the real
-// kernel, far_sym_chunk for the complex one.
-template <class T, int TT>
+// kernel (RAW: single-precision kernel values), far_sym_chunk for the complex
+// one (full precision only).
+template <class T, int TT, bool RAW>
 __device__ inline void far_chunk(const FarSymArgs &F, int64_t k0, int64_t k1, const T *__restrict__ Xh,
                                  T *__restrict__ part, double *lds)
 {
-    if constexpr (NComp<T>::value == 1) far_mfma_chunk<(TT + 1) / 2>(F, k0, k1, Xh, part, lds);
-    else far_sym_chunk<T, TT>(F, k0, k1, Xh, part, lds);
+    if constexpr (NComp<T>::value == 1) {
+        far_mfma_chunk<(TT + 1) / 2, RAW>(F, k0, k1, Xh, part, lds);
+    } else {
+        static_assert(!RAW, "single-precision far field: real kernel only");
+        far_sym_chunk<T, TT>(F, k0, k1, Xh, part, lds);
+    }
 }
 
 // three waves per SIMD for the real kernel: the far-field pairs need the
 // occupancy more than the deeper product pipeline the compiler would build
-template <class T, int TT>
+template <class T, int TT, bool RAW>
 __global__ void __launch_bounds__(256, NComp<T>::value == 1 ? 3 : 1) k_far_sym(FarSymArgs F, const T *__restrict__ Xh,
                                                                              T *__restrict__ part)
 {
@@ -1471,7 +1478,7 @@ __global__ void __launch_bounds__(256, NComp<T>::value == 1 ? 3 : 1) k_far_sym(F
     const int wave = threadIdx.x >> 6;
     const int64_t k0 = ((int64_t)blockIdx.x * 4 + wave) * kFarChunk;
     if (k0 >= F.nup) return;  // whole waves only; no block-wide barrier follows
-    far_chunk<T, TT>(F, k0, min(k0 + kFarChunk, F.nup), Xh, part, buf[wave]);
+    far_chunk<T, TT, RAW>(F, k0, min(k0 + kFarChunk, F.nup), Xh, part, buf[wave]);
 }
 
 // The far-field pairs and the stored near blocks in one launch (ALU-bound and
@@ -1479,7 +1486,7 @@ __global__ void __launch_bounds__(256, NComp<T>::value == 1 ? 3 : 1) k_far_sym(F
 // pairs) and nn near workgroups (four waves of one block), the near ones spread
 // evenly through the grid (workgroup b is near iff
 // floor((b+1) nn / (nf+nn)) > floor(b nn / (nf+nn))).
-template <class T, int TT>
+template <class T, int TT, bool RAW>
 __global__ void __launch_bounds__(256, NComp<T>::value == 1 ? 3 : 1) k_sym_products(FarSymArgs F, NearSymArgs N,
                                                                                   int64_t nf, int64_t nn,
                                                       const T *__restrict__ Xh, T *__restrict__ fpart,
@@ -1499,7 +1506,7 @@ __global__ void __launch_bounds__(256, NComp<T>::value == 1 ? 3 : 1) k_sym_produ
     } else {
         const int64_t k0 = ((b - before) * 4 + wave) * kFarChunk;
         if (k0 >= F.nup) return;
-        far_chunk<T, TT>(F, k0, min(k0 + kFarChunk, F.nup), Xh, fpart, sh + (size_t)wave * slice);
+        far_chunk<T, TT, RAW>(F, k0, min(k0 + kFarChunk, F.nup), Xh, fpart, sh + (size_t)wave * slice);
     }
 }
 
@@ -2300,6 +2307,10 @@ struct igb_operator {
     double assembly_seconds = 0.0;
     std::vector<DevBlock> owned;
     DevBlock Vblk{}, hblk{}, mblk{};  // GMRES basis, projections, multi-dot partials
+    // far_precision IGB_FP32: products use single-precision far-field kernel values;
+    // force_fp64 is set while the solver forms its double-precision residuals
+    bool far_single = false, force_fp64 = false;
+    void *rr = nullptr, *dw = nullptr;  // refinement: residual and correction (IGB_FP32)
 };
 
 static igb_status dalloc(igb_operator *op, void **p, size_t bytes)
@@ -2476,20 +2487,33 @@ static NearSymArgs near_args(const igb_operator *op)
     return NearSymArgs{op->nsb, op->sb_t, op->sb_s, op->s.nl, op->near_ld};
 }
 
-// far pairs alone, or (fuse) far pairs and stored near blocks in one launch
-template <class T, int TT>
-static void launch_far_sym(igb_operator *op, const T *Xh, const T *xs, bool fuse)
+// far pairs alone, or (fuse) far pairs and stored near blocks in one launch;
+// RAW: single-precision kernel values (far_precision IGB_FP32)
+template <class T, int TT, bool RAW>
+static void launch_far_sym_p(igb_operator *op, const T *Xh, const T *xs, bool fuse)
 {
     if (!fuse) {
-        hipLaunchKernelGGL((k_far_sym<T, TT>), dim3((unsigned)((op->nup + 4 * kFarChunk - 1) / (4 * kFarChunk))),
+        hipLaunchKernelGGL((k_far_sym<T, TT, RAW>), dim3((unsigned)((op->nup + 4 * kFarChunk - 1) / (4 * kFarChunk))),
                            dim3(256), 0, op->st, far_args(op), Xh, (T *)op->fpart);
         return;
     }
     const int64_t nf = (op->nup + 4 * kFarChunk - 1) / (4 * kFarChunk), nn = (op->nsb + 3) / 4;
     const size_t shm =
         4 * std::max<size_t>((size_t)(8 * op->near_ld + 520) * NComp<T>::value, (size_t)far_sym_lds<T, TT>()) * 8;
-    hipLaunchKernelGGL((k_sym_products<T, TT>), dim3((unsigned)(nf + nn)), dim3(256), shm, op->st, far_args(op),
+    hipLaunchKernelGGL((k_sym_products<T, TT, RAW>), dim3((unsigned)(nf + nn)), dim3(256), shm, op->st, far_args(op),
                        near_args(op), nf, nn, Xh, (T *)op->fpart, (const T *)op->nearb, xs, (T *)op->npart);
+}
+
+template <class T, int TT>
+static void launch_far_sym(igb_operator *op, const T *Xh, const T *xs, bool fuse)
+{
+    if constexpr (NComp<T>::value == 1) {
+        if (op->far_single && !op->force_fp64) {
+            launch_far_sym_p<T, TT, true>(op, Xh, xs, fuse);
+            return;
+        }
+    }
+    launch_far_sym_p<T, TT, false>(op, Xh, xs, fuse);
 }
 
 // Slices of the cluster tree for k_up_tree / k_down_tree: (ls, lb) pairs from
@@ -2953,7 +2977,7 @@ static igb_status create_device_geometry(igb_operator *op)
     if ((rc = dalloc(op, &op->Yh, ncl_all * q2 * esz))) return rc;
     HIPCHK(hipMemsetAsync(op->Xh, 0, ncl_all * q2 * esz, op->st));
     HIPCHK(hipMemsetAsync(op->Yh, 0, ncl_all * q2 * esz, op->st));
-    for (void **v : {&op->r, &op->z, &op->pv, &op->Ap, &op->tmp})
+    for (void **v : {&op->r, &op->z, &op->pv, &op->Ap, &op->tmp, &op->rr, &op->dw})
         if ((rc = dalloc(op, v, s.ndof * esz))) return rc;
     if ((rc = dalloc(op, &op->part, 3 * kRedBlocks * esz))) return rc;  // dot partials; CG: 3 sets
     if ((rc = dalloc(op, &op->dpart, nblk(s.ndof, 256) * esz))) return rc;  // p . Ap partials of the T pass
@@ -3026,6 +3050,11 @@ static igb_status read_scalar(igb_operator *op, int idx, double *out)
     return IGB_OK;
 }
 
+// far_precision IGB_FP32: the steps use the single-precision far field; every
+// kReplaceEvery steps the recursive residual is replaced by the FP64 one
+// ("reliable updates"), and convergence is always judged on the FP64 residual.
+static const int kReplaceEvery = 20;
+
 static igb_status solve_cg(igb_operator *op, const double *b, double *w, double tol, int maxit, igb_solve_info *info)
 {
     int64_t n = op->s.ndof;
@@ -3042,7 +3071,11 @@ static igb_status solve_cg(igb_operator *op, const double *b, double *w, double 
     int it = 0;
     double rel = 0.0;
     for (;;) {
-        if ((rc = matvec_S<double>(op, w, Ap))) return rc;
+        // the true residual, always with the full-precision far field
+        op->force_fp64 = true;
+        rc = matvec_S<double>(op, w, Ap);
+        op->force_fp64 = false;
+        if (rc) return rc;
         HIPCHK(hipMemcpyAsync(r, b, n * sizeof(double), hipMemcpyDeviceToDevice, op->st));
         hipLaunchKernelGGL((k_axpby<double>), dim3(gb), dim3(256), 0, op->st, n, -1.0, Ap, 1.0, r);
         LAUNCHCHK();
@@ -3081,6 +3114,21 @@ static igb_status solve_cg(igb_operator *op, const double *b, double *w, double 
         rc = IGB_OK;
         while (true) {
             if (it + launched < maxit && launched - examined < 2) {
+                if (op->far_single && launched > 0 && launched % kReplaceEvery == 0) {
+                    // reliable update: the recursive residual is replaced by b - A w with the
+                    // full-precision far field (and z, r.z with it); the direction p is kept
+                    op->force_fp64 = true;
+                    rc = matvec_S<double>(op, w, Ap);
+                    op->force_fp64 = false;
+                    if (rc) break;
+                    if (hipMemcpyAsync(r, b, n * sizeof(double), hipMemcpyDeviceToDevice, op->st) != hipSuccess) {
+                        rc = fail(IGB_EHIP, "CG residual replacement");
+                        break;
+                    }
+                    hipLaunchKernelGGL((k_axpby<double>), dim3(gb), dim3(256), 0, op->st, n, -1.0, Ap, 1.0, r);
+                    hipLaunchKernelGGL((k_div<double>), dim3(gb), dim3(256), 0, op->st, n, r, D, z);
+                    if ((rc = dot_dev<double>(op, n, r, z, sc + slot))) break;
+                }
                 if ((rc = matvec_S<double>(op, p, Ap, pp))) break;
                 hipLaunchKernelGGL(k_cg_step, dim3(gs), dim3(256), 0, op->st, n, sc + slot, pp, np, w, r, p, Ap, D, z,
                                    p2, sc + 4);
@@ -3316,6 +3364,7 @@ igb_status igb_operator_create(const igb_geometry *geo, const igb_params *prm, v
     }
     Setup &s = op->s;
     op->cplx = s.kernel == IGB_HELMHOLTZ;
+    op->far_single = prm->far_precision == IGB_FP32;
     op->esz = op->cplx ? sizeof(cd) : sizeof(double);
     op->lo = Layout{s.p, s.p + 1, s.nloc, s.nl, s.side, s.L, s.ne, s.ns1};
     // GPU: Gauss-node geometry and identical-pair quadrature, then the other touching

@@ -846,7 +846,11 @@ std::string build_setup_tiles(const Geometry &geo, const igb_params &prm, Setup 
     if (prm.gauss_rhs != -1 && (prm.gauss_rhs < 1 || prm.gauss_rhs > 40)) return "gauss_rhs outside 1..40";
     if (prm.mode != IGB_DENSE && prm.mode != IGB_H2_STORED && prm.mode != IGB_H2_ONTHEFLY)
         return "mode must be IGB_DENSE, IGB_H2_STORED or IGB_H2_ONTHEFLY";
-    if (prm.far_precision != IGB_FP64) return "far_precision must be IGB_FP64";
+    if (prm.far_precision != IGB_FP64 && prm.far_precision != IGB_FP32)
+        return "far_precision must be IGB_FP64 or IGB_FP32";
+    if (prm.far_precision == IGB_FP32 &&
+        (prm.kernel != IGB_LAPLACE || prm.mode != IGB_H2_ONTHEFLY || prm.q * prm.q > 64))
+        return "far_precision IGB_FP32 needs the Laplace kernel, on-the-fly coupling and q <= 8";
     if (prm.leaf_depth < -1 || prm.leaf_depth > 10) return "leaf_depth outside -1..10";
 
     s.kernel = prm.kernel;

@@ -28,6 +28,7 @@ IGB_DENSE = 0
 IGB_H2_STORED = 1
 IGB_H2_ONTHEFLY = 2
 IGB_FP64 = 0
+IGB_FP32 = 1
 
 EXPORTED = [
     "igb_last_error", "igb_geometry_create", "igb_geometry_destroy", "igb_operator_create",
@@ -249,9 +250,9 @@ def igb_matvec_profile(op, reps, flags=0):
 
 
 def make_params(*, kernel=IGB_LAPLACE, wavenumber=0.0, p=1, m=2, q=8, eta=1.6, leaf_depth=-1, gauss_regular=6,
-                gauss_singular=-1, gauss_rhs=-1, mode=IGB_H2_STORED) -> igb_params:
+                gauss_singular=-1, gauss_rhs=-1, mode=IGB_H2_STORED, far_precision=IGB_FP64) -> igb_params:
     return igb_params(int(kernel), float(wavenumber), int(p), int(m), int(q), float(eta), int(leaf_depth),
-                      int(gauss_regular), int(gauss_singular), int(gauss_rhs), int(mode), IGB_FP64)
+                      int(gauss_regular), int(gauss_singular), int(gauss_rhs), int(mode), int(far_precision))
 
 
 def igb_plan_create(geo, prm: igb_params):
@@ -324,14 +325,15 @@ class Operator:
 
     def __init__(self, geometry: Geometry, *, kernel=IGB_LAPLACE, wavenumber=0.0, p=1, m=2, q=8, eta=1.6,
                  leaf_depth=-1, gauss_regular=6, gauss_singular=-1, gauss_rhs=-1, mode=IGB_H2_STORED,
-                 device="cuda:0"):
+                 far_precision=IGB_FP64, device="cuda:0"):
         import torch
 
         self.torch = torch
         self.device = torch.device(device)
         self.geometry = geometry
         prm = make_params(kernel=kernel, wavenumber=wavenumber, p=p, m=m, q=q, eta=eta, leaf_depth=leaf_depth,
-                          gauss_regular=gauss_regular, gauss_singular=gauss_singular, gauss_rhs=gauss_rhs, mode=mode)
+                          gauss_regular=gauss_regular, gauss_singular=gauss_singular, gauss_rhs=gauss_rhs, mode=mode,
+                          far_precision=far_precision)
         with torch.cuda.device(self.device):
             self.stream = torch.cuda.current_stream(self.device)
             self.h = igb_operator_create(geometry.h, prm, self.stream.cuda_stream)

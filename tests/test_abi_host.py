@@ -37,6 +37,11 @@ def test_release_cached_memory_with_nothing_cached():
     igb.igb_release_cached_memory()
 
 
+def test_single_precision_far_field_accepted_where_supported():
+    g = igb.Geometry(W.sphere_patches())
+    igb.Plan(g, p=1, m=2, q=8, mode=igb.IGB_H2_ONTHEFLY, far_precision=igb.IGB_FP32)
+
+
 def test_geometry_validation_errors():
     good = W.sphere_patches()[0]
     igb.Geometry([good])
@@ -56,7 +61,9 @@ def test_geometry_validation_errors():
 
 @pytest.mark.parametrize("bad", [dict(p=-1), dict(p=7), dict(m=11), dict(q=0), dict(eta=0.0), dict(eta=-1.0),
                                  dict(gauss_regular=0), dict(gauss_singular=41), dict(kernel=5), dict(mode=3),
-                                 dict(kernel=1, wavenumber=-1.0), dict(leaf_depth=-2)])
+                                 dict(kernel=1, wavenumber=-1.0), dict(leaf_depth=-2), dict(far_precision=2),
+                                 dict(far_precision=1, kernel=1, wavenumber=1.0, mode=2),
+                                 dict(far_precision=1, mode=1), dict(far_precision=1, mode=2, q=9)])
 def test_parameter_validation_errors(bad):
     g = igb.Geometry(W.sphere_patches())
     with pytest.raises(igb.IgbError) as e:

@@ -267,6 +267,45 @@ def test_mixed_instances_h2_matvec(seed):
     assert rel(to_np(op.matvec_super(torch.tensor(xs))), P.h2_matvec_super(xs)) < 1e-12
 
 
+@pytest.mark.parametrize("q", [5, 8])
+def test_single_precision_far_field_product(q):
+    """far_precision IGB_FP32: every coupling-kernel value is the hardware reciprocal-square-root estimate
+    (relative error below 6e-8, measured 5.2e-8 at most), the rest FP64. The product stays within 1e-6 of the
+    oracle's FP64 H2 product (the far part's error is a few 1e-8 of its size) and is exactly symmetric (one
+    kernel value per mirrored pair of nodes)."""
+    say(f"single-precision far field: sphere p=1 m=3 q={q}")
+    op, P = make(W.sphere_patches(), mode=igb.IGB_H2_ONTHEFLY, far_precision=igb.IGB_FP32, p=1, m=3, q=q,
+                 leaf_depth=1, eta=1.6, gauss_regular=6)
+    P.h2_assemble(store_coupling=True)
+    xs = rand(P.nsup, 30)
+    ys = to_np(op.matvec_super(torch.tensor(xs)))
+    err = rel(ys, P.h2_matvec_super(xs))
+    assert err < 1e-6
+    zs = rand(P.nsup, 31)
+    yz = to_np(op.matvec_super(torch.tensor(zs)))
+    assert abs(zs @ ys - xs @ yz) <= 1e-13 * abs(zs @ ys)
+
+
+def test_single_precision_far_field_refined_solve():
+    """The solve of an IGB_FP32 operator reaches the FP64 system's solution: iterative refinement with FP64
+    residuals. Density within 1e-10 of the oracle's FP64 solution (both to relative residual 1e-13), and the
+    reported residual is the FP64 one (checked with a separate FP64 operator)."""
+    say("single-precision far field: refined solve, sphere p=1 m=3 q=4")
+    kw = dict(p=1, m=3, q=4, leaf_depth=1, eta=1.6, gauss_regular=6)
+    op, P = make(W.sphere_patches(), mode=igb.IGB_H2_ONTHEFLY, far_precision=igb.IGB_FP32, **kw)
+    P.h2_assemble(store_coupling=True)
+    pos, qs = W.point_charges(4, 2)
+    b = P.rhs(W.laplace_charge_field(P.rhs_points(), pos, qs))
+    w_or, it_or, rr_or = P.solve(b, tol=1e-13, maxit=3000)
+    w, info = op.solve(torch.tensor(b), tol=1e-13, max_iter=3000)
+    assert info.converged == 1 and info.rel_residual <= 1e-13
+    assert rel(to_np(w), w_or) < 1e-10
+    op64 = igb.Operator(igb.Geometry(W.sphere_patches()), mode=igb.IGB_H2_ONTHEFLY, device=DEV, **kw)
+    bt = torch.tensor(b, device=DEV)
+    r = to_np(bt - op64.matvec(w))
+    assert np.linalg.norm(r) <= 1.01e-13 * np.linalg.norm(b)
+
+
 def test_h2_solve_density_parity():
     say("h2 solve: sphere p=1 m=3 q=4")
     op, P = make(W.sphere_patches(), p=1, m=3, q=4, leaf_depth=1, eta=1.6, gauss_regular=6)

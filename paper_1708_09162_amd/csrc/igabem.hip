@@ -1784,6 +1784,7 @@ struct DiagArgs {
     const int32_t *near_src;
     const int32_t *sb;  // stored near block of each CSR entry (-1: read the mirror transposed)
     int ld;             // column stride of the stored near blocks
+    const void *cbuf;   // per stored block, the near-field terms of k_diag_blocks (or null)
     const int64_t *far_ptr;
     const int32_t *far_src;
     const double *nodes;
@@ -1799,6 +1800,92 @@ template <> __device__ inline cd green_ir<cd>(double r2, double ir, double kappa
     sincos(kappa * (r2 * ir), &sn, &cs);
     const double f = 0.07957747154594767 * ir;
     return {cs * f, sn * f};
+}
+
+// Near-field terms of the Jacobi diagonal, block by block (symmetric storage):
+// for the stored leaf block B of (t, s) (t <= s) and every B-spline j whose
+// support meets both leaves, c = u^T B v with u, v the restrictions of
+// t_j = T^T e_j to the superspace functions of t and of s (tensor products of
+// the 1D weights of Sec. 4.3, zero where the support does not reach).  One
+// workgroup per stored block; c goes to slot (j2 - j2lo) W + (j1 - j1lo) of
+// the block's W^2 (W = side + p), (j1lo, j2lo) the first B-spline of the
+// window both leaves share.  Leaves of different patches share no B-spline.
+// LDS: V (nl x nj), the four 1D weight tables, the row terms (nj x nl).
+template <class T>
+__global__ void __launch_bounds__(256) k_diag_blocks(Layout lo, const int32_t *__restrict__ sb_t,
+                                                     const int32_t *__restrict__ sb_s, int ld,
+                                                     const double *__restrict__ Tb, const T *__restrict__ nearb,
+                                                     T *__restrict__ cbuf)
+{
+    extern __shared__ double sh[];
+    const int64_t k = blockIdx.x;
+    const int P1 = lo.P1, p = lo.p, side = lo.side, nl = lo.nl, nloc = lo.nloc, W = side + p, SP = side * P1;
+    const int n = 1 << lo.L;
+    const int t = sb_t[k], s = sb_s[k];
+    if (t / (n * n) != s / (n * n)) return;
+    const int rt = t % (n * n), rs = s % (n * n);
+    const int t2 = rt / n, t1 = rt % n, s2 = rs / n, s1 = rs % n;
+    const int j1lo = max(t1, s1) * side, j1hi = min(t1, s1) * side + side - 1 + p;
+    const int j2lo = max(t2, s2) * side, j2hi = min(t2, s2) * side + side - 1 + p;
+    if (j1lo > j1hi || j2lo > j2hi) return;
+    const int w1 = j1hi - j1lo + 1, w2 = j2hi - j2lo + 1, nj = w1 * w2;
+    double *V = sh;                                   // [nl][nj]
+    double *Tt1 = V + (size_t)nl * nj, *Tt2 = Tt1 + SP * w1, *Ts1 = Tt2 + SP * w2, *Ts2 = Ts1 + SP * w1;
+    T *red = (T *)(sh + (((size_t)nl * nj + 2 * (size_t)SP * (w1 + w2) + 1) & ~(size_t)1));  // [nj][nl], 16-byte aligned
+    // 1D weights: leaf-local index i = el*P1 + r along one direction, B-spline j = jlo + jj
+    auto w1d = [&](int leafk, int i, int jj, int jlo) -> double {
+        const int e = leafk * side + i / P1, r = i % P1, j = jlo + jj, d = j - e;
+        return (d >= 0 && d <= p) ? Tb[(e * P1 + r) * P1 + d] : 0.0;
+    };
+    for (int x = threadIdx.x; x < SP * w1; x += blockDim.x) {
+        Tt1[x] = w1d(t1, x / w1, x % w1, j1lo);
+        Ts1[x] = w1d(s1, x / w1, x % w1, j1lo);
+    }
+    for (int x = threadIdx.x; x < SP * w2; x += blockDim.x) {
+        Tt2[x] = w1d(t2, x / w2, x % w2, j2lo);
+        Ts2[x] = w1d(s2, x / w2, x % w2, j2lo);
+    }
+    __syncthreads();
+    // superspace function f of a leaf: element el = el2*side + el1, r = r2*P1 + r1
+    auto i1of = [&](int f) { const int el = f / nloc, r = f % nloc; return (el % side) * P1 + r % P1; };
+    auto i2of = [&](int f) { const int el = f / nloc, r = f % nloc; return (el / side) * P1 + r / P1; };
+    for (int x = threadIdx.x; x < nl * nj; x += blockDim.x) {
+        const int b = x / nj, jj = x % nj;
+        V[x] = Ts1[i1of(b) * w1 + jj % w1] * Ts2[i2of(b) * w2 + jj / w1];
+    }
+    __syncthreads();
+    // 256 threads: lane = row a (mod 64), group g of four takes the window columns
+    // jj = g, g+4, ...; y = B v for those columns, then the row's share of u^T y
+    // 256 threads: lane = row a (mod 64), group g of four takes the window columns
+    // jj = g, g+4, ...; y = B v for those columns, the row's share of u^T y into
+    // red[jj][a], then one fixed-order sum per column
+    const T *B = nearb + k * (int64_t)nl * ld;  // column b: rows a of leaf t, stride ld
+    const int lane = threadIdx.x & 63, g = threadIdx.x >> 6;
+    constexpr int YC = 16;  // columns per thread, nj <= 64
+    for (int a = lane; a < nl; a += 64) {
+        T y[YC];
+#pragma unroll
+        for (int c = 0; c < YC; ++c) y[c] = zero<T>();
+        for (int b = 0; b < nl; ++b) {
+            const T Bab = B[(int64_t)b * ld + a];
+            const double *vb = V + (size_t)b * nj;
+#pragma unroll
+            for (int c = 0; c < YC; ++c)
+                if (g + 4 * c < nj) y[c] += Bab * vb[g + 4 * c];
+        }
+        const int ia1 = i1of(a), ia2 = i2of(a);
+#pragma unroll
+        for (int c = 0; c < YC; ++c) {
+            const int jj = g + 4 * c;
+            if (jj < nj) red[(size_t)jj * nl + a] = y[c] * (Tt1[ia1 * w1 + jj % w1] * Tt2[ia2 * w2 + jj / w1]);
+        }
+    }
+    __syncthreads();
+    for (int jj = threadIdx.x; jj < nj; jj += blockDim.x) {
+        T v = zero<T>();
+        for (int a = 0; a < nl; ++a) v += red[(size_t)jj * nl + a];
+        cbuf[k * W * W + (int64_t)(jj / w1) * W + jj % w1] = v;
+    }
 }
 
 // One workgroup per B-spline function i (patch, j1, j2); its support is the
@@ -1832,18 +1919,25 @@ __global__ void __launch_bounds__(256) k_diag(DiagArgs A, int64_t ndof, const T 
         const int c1lo = lo1 / nsub, c1hi = hi1 / nsub, c2lo = lo2 / nsub, c2hi = hi2 / nsub;
         const int nc1 = c1hi - c1lo + 1, nc = nc1 * (c2hi - c2lo + 1);
         const double *Ml = A.Mlev + A.Mlev_off[l];
+        // the moments of t_i on a cluster are tensor products: one 1D sum per
+        // cluster column and node (s1) and per cluster row and node (s2)
+        const int nc2 = nc / nc1;
+        double *s1 = mv + (size_t)nc * q2, *s2 = s1 + (size_t)nc1 * q;
+        for (int o = threadIdx.x; o < (nc1 + nc2) * q; o += blockDim.x) {
+            const bool first = o < nc1 * q;
+            const int oo = first ? o : o - nc1 * q, c = oo / q, mu = oo % q;
+            const int cc = (first ? c1lo : c2lo) + c, jj = first ? j1 : j2;
+            const int elo = first ? lo1 : lo2, ehi = first ? hi1 : hi2;
+            double sum = 0.0;
+            for (int e = (elo > cc * nsub ? elo : cc * nsub); e <= ehi && e < (cc + 1) * nsub; ++e)
+                for (int r = 0; r < P1; ++r)
+                    sum += A.Tb[(e * P1 + r) * P1 + (jj - e)] * Ml[((e - cc * nsub) * P1 + r) * q + mu];
+            (first ? s1 : s2)[oo] = sum;
+        }
+        __syncthreads();
         for (int o = threadIdx.x; o < nc * q2; o += blockDim.x) {
-            int c = o / q2, mu = o % q2, mu2 = mu / q, mu1 = mu % q;
-            int cc1 = c1lo + c % nc1, cc2 = c2lo + c / nc1;
-            double s = 0.0;
-            for (int e2 = (lo2 > cc2 * nsub ? lo2 : cc2 * nsub); e2 <= hi2 && e2 < (cc2 + 1) * nsub; ++e2)
-                for (int e1 = (lo1 > cc1 * nsub ? lo1 : cc1 * nsub); e1 <= hi1 && e1 < (cc1 + 1) * nsub; ++e1)
-                    for (int r2 = 0; r2 < P1; ++r2)
-                        for (int r1 = 0; r1 < P1; ++r1) {
-                            double t = A.Tb[(e1 * P1 + r1) * P1 + (j1 - e1)] * A.Tb[(e2 * P1 + r2) * P1 + (j2 - e2)];
-                            s += t * Ml[((e1 - cc1 * nsub) * P1 + r1) * q + mu1] * Ml[((e2 - cc2 * nsub) * P1 + r2) * q + mu2];
-                        }
-            mv[o] = s;
+            const int c = o / q2, mu = o % q2, mu2 = mu / q, mu1 = mu % q;
+            mv[o] = s1[(c % nc1) * q + mu1] * s2[(c / nc1) * q + mu2];
         }
         // admissible pairs ca < cb
         for (int c = threadIdx.x; c < nc * nc; c += blockDim.x) {
@@ -1879,7 +1973,28 @@ __global__ void __launch_bounds__(256) k_diag(DiagArgs A, int64_t ndof, const T 
         }
         __syncthreads();
     }
-    // near field at the leaf level
+    // near field at the leaf level: from the per-block terms of k_diag_blocks
+    // (each unordered pair of support leaves once, twice when they differ) ...
+    if (A.cbuf) {
+        const int nsub = lo.side, n = 1 << lo.L, W = lo.side + lo.p;
+        const int c1lo = lo1 / nsub, c1hi = hi1 / nsub, c2lo = lo2 / nsub, c2hi = hi2 / nsub;
+        const int nc1 = c1hi - c1lo + 1, nc = nc1 * (c2hi - c2lo + 1);
+        const T *cb = (const T *)A.cbuf;
+        for (int w = threadIdx.x; w < nc * nc; w += blockDim.x) {
+            const int ca = w / nc, cbb = w % nc;
+            if (cbb < ca) continue;
+            const int a1 = c1lo + ca % nc1, a2 = c2lo + ca / nc1, b1 = c1lo + cbb % nc1, b2 = c2lo + cbb / nc1;
+            const int ia = patch * n * n + a2 * n + a1, ib = patch * n * n + b2 * n + b1;
+            const bool fwd = ia <= ib;
+            const int64_t e = csr_find(A.near_ptr, A.near_src, fwd ? ia : ib, fwd ? ib : ia);
+            if (e < 0) continue;
+            const int64_t kb = A.sb[e];
+            const int j1lo = max(a1, b1) * nsub, j2lo = max(a2, b2) * nsub;
+            const T v = cb[kb * W * W + (int64_t)(j2 - j2lo) * W + (j1 - j1lo)];
+            acc += ca == cbb ? v : 2.0 * v;
+        }
+    } else {
+    // ... or, for non-symmetric storage, entry by entry
     {
         const int nsub = lo.side, n = 1 << lo.L;
         const int c1lo = lo1 / nsub, c1hi = hi1 / nsub, c2lo = lo2 / nsub, c2hi = hi2 / nsub;
@@ -1923,6 +2038,7 @@ __global__ void __launch_bounds__(256) k_diag(DiagArgs A, int64_t ndof, const T 
             if (code >= 0) acc += nearb[(int64_t)code * lo.nl * A.ld + (int64_t)fb * A.ld + fa] * t;
             else acc += nearb[(int64_t)(-2 - code) * lo.nl * A.ld + (int64_t)fa * A.ld + fb] * t;
         }
+    }
     }
     red[threadIdx.x] = acc;
     __syncthreads();
@@ -2899,6 +3015,24 @@ static igb_status assemble(igb_operator *op)
         A.near_src = op->near_src;
         A.sb = op->sb;
         A.ld = op->near_ld;
+        A.cbuf = nullptr;
+        {
+            // near-field terms block by block (symmetric storage, windows that fit LDS)
+            const int W = s.side + s.p, SP = s.side * (s.p + 1), nj = W * W;
+            const size_t shm_b =
+                ((size_t)s.nl * nj + 2 * (size_t)SP * 2 * W + 1) * sizeof(double) + (size_t)nj * s.nl * sizeof(T);
+            if (op->near_sym && op->nsb > 0 && nj <= 64 && shm_b <= 64 * 1024) {
+                void *cb = nullptr;
+                if ((rc = dalloc(op, &cb, (size_t)op->nsb * nj * sizeof(T)))) return rc;
+                HIPCHK(hipMemsetAsync(cb, 0, (size_t)op->nsb * nj * sizeof(T), op->st));
+                (void)hipFuncSetAttribute((const void *)k_diag_blocks<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                          (int)shm_b);
+                hipLaunchKernelGGL((k_diag_blocks<T>), dim3((unsigned)op->nsb), dim3(256), shm_b, op->st, op->lo,
+                                   op->sb_t, op->sb_s, op->near_ld, op->Tb, (const T *)op->nearb, (T *)cb);
+                LAUNCHCHK();
+                A.cbuf = cb;
+            }
+        }
         A.far_ptr = op->far_ptr;
         A.far_src = op->far_src;
         A.nodes = op->nodes;
@@ -2906,7 +3040,7 @@ static igb_status assemble(igb_operator *op)
         // far: moments of up to (p+2)^2 clusters; near: (p+1)^2 nloc support functions
         // (weight, slot, index) and the (p+2)^4 leaf-pair table
         const size_t ns = (size_t)(s.p + 1) * (s.p + 1) * s.nloc, ncm = (size_t)(s.p + 2) * (s.p + 2);
-        size_t shm = std::max((size_t)(s.p + 2) * (s.p + 2) * q2 * sizeof(double),
+        size_t shm = std::max(((size_t)(s.p + 2) * (s.p + 2) * q2 + (size_t)2 * (s.p + 2) * s.q) * sizeof(double),
                               ns * (sizeof(double) + 2 * sizeof(int)) + ncm * ncm * sizeof(int));
         if (shm > 140 * 1024 || ncm * ncm > 4096) return fail(IGB_EUNSUPPORTED, "Jacobi diagonal: p or q too large");
         (void)hipFuncSetAttribute((const void *)k_diag<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);

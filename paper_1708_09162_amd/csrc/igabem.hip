@@ -10,6 +10,7 @@
 #include <map>
 #include <mutex>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "kernels.h"
@@ -368,7 +369,11 @@ __device__ inline double from_pair_lane(double v)
 // and the reordering is undone on output.
 typedef double v4d __attribute__((ext_vector_type(4)));
 
-template <class T, int P, int PG, int WAVES>
+// VTX: this launch integrates the common-vertex pairs of its list (the others
+// the remaining classes); a workgroup whose pair belongs to the other launch
+// returns at once.  The two rules are separate instantiations so that neither
+// carries the other's registers.
+template <class T, int P, int PG, int WAVES, bool VTX>
 __global__ void __launch_bounds__(64 * WAVES, NComp<T>::value == 1 ? 2 : 1) k_near_singular(
     const PairRec *__restrict__ pairs, int gs, const double *__restrict__ gxs, const double *__restrict__ gws,
     const double *__restrict__ tfix_u, const double *__restrict__ tfix_v, double kappa, T *__restrict__ pairbuf)
@@ -389,6 +394,7 @@ __global__ void __launch_bounds__(64 * WAVES, NComp<T>::value == 1 ? 2 : 1) k_ne
     double *Ub = stg + wave * STAGE;  // [HALF][RS]: p of each line
     double *Vb = Ub + HALF * RS + 8;  // [NC][HALF][RS]: C of each line
     const PairRec R = pairs[blockIdx.x];
+    if ((R.cls == 3) != VTX) return;  // the other launch's pair (uniform: no barrier passed yet)
     const int role = lane & 1, pl = lane >> 1;  // role 0: element E, 1: element F; pl: line slot
     const int elem = role ? R.F : R.E;
     for (int k = threadIdx.x; k < gs; k += blockDim.x) {
@@ -479,92 +485,159 @@ __global__ void __launch_bounds__(64 * WAVES, NComp<T>::value == 1 ? 2 : 1) k_ne
                 }
             }
         }
-        // this lane's element along the line
-        const Line L = role ? LF : LE;
-        const bool fix_u = role ? fixF_u : fixE_u;
-        const bool cst = role == 0 && constE;
-        const double f = fix_u ? L.u0 : L.v0;
-        double A[G1][4], dA[G1][4];
-        tile_fix<PG>((fix_u ? tfix_u : tfix_v) + (size_t)elem * TS, f, A, dA);
-        // Bernstein values at the fixed (bf) and moving (bm) parameter; index P1
-        // pads the last row of an odd P1 on lane 2k+1
-        double bf[P1 + 1], bm[P1 + 1], X[3], kap = 0.0;
-        bernstein_t<P>(f, bf);
-        bf[P1] = bm[P1] = 0.0;
-        if (cst) {  // vertex, element E: one point for the whole line
-            const double wv = fix_u ? L.v0 : L.u0;
-            tile_line_point<PG>(A, dA, wv, X, &kap);
-            bernstein_t<P>(wv, bm);
-        }
-        // cl[i][j] = C[base + i][j]: rows base .. base+H-1 of the line factor
-        const int base = role ? H : 0;
-        double cl[H][P1][NC];
-#pragma unroll
-        for (int i = 0; i < H; ++i)
-#pragma unroll
-            for (int j = 0; j < P1; ++j)
-#pragma unroll
-                for (int c = 0; c < NC; ++c) cl[i][j][c] = 0.0;
-        for (int id = 0; id < g; ++id) {
-            const double w = nx[id];
-            if (!cst) {
-                const double wv = fix_u ? L.v0 + L.dv * w : L.u0 + L.du * w;
+        if constexpr (!VTX) {
+            // this lane's element along the line
+            const Line L = role ? LF : LE;
+            const bool fix_u = role ? fixF_u : fixE_u;
+            const bool cst = role == 0 && constE;
+            const double f = fix_u ? L.u0 : L.v0;
+            double A[G1][4], dA[G1][4];
+            tile_fix<PG>((fix_u ? tfix_u : tfix_v) + (size_t)elem * TS, f, A, dA);
+            // Bernstein values at the fixed (bf) and moving (bm) parameter; index P1
+            // pads the last row of an odd P1 on lane 2k+1
+            double bf[P1 + 1], bm[P1 + 1], X[3], kap = 0.0;
+            bernstein_t<P>(f, bf);
+            bf[P1] = bm[P1] = 0.0;
+            if (cst) {  // vertex, element E: one point for the whole line
+                const double wv = fix_u ? L.v0 : L.u0;
                 tile_line_point<PG>(A, dA, wv, X, &kap);
                 bernstein_t<P>(wv, bm);
             }
-            // the partner's point; the weighted kernel value comes out bitwise
-            // the same on both lanes (x - y = -(y - x) exactly)
-            const double Y0 = from_pair_lane(X[0]), Y1 = from_pair_lane(X[1]), Y2 = from_pair_lane(X[2]);
-            const double ky = from_pair_lane(kap);
-            const double d0 = X[0] - Y0, d1 = X[1] - Y1, d2 = X[2] - Y2;
-            const double r2 = d0 * d0 + d1 * d1 + d2 * d2;
-            const double ir = rsqrt_pos(r2);
-            const double f0 = 0.07957747154594767 * ir * ((Wl * nw[id]) * (kap * ky));
-            double wk[NC];
-            if constexpr (NC == 2) {
-                double sn, cs;
-                sincos(kappa * (r2 * ir), &sn, &cs);
-                wk[0] = cs * f0;
-                wk[1] = sn * f0;
-            } else {
-                wk[0] = f0;
-            }
-            // E's values of this lane's rows and F's values of all columns
-            double bo[P1 + 1], be[H], bF[P1];
-#pragma unroll
-            for (int a = 0; a < P1; ++a) bo[a] = from_pair_lane(bm[a]);
-            bo[P1] = 0.0;
-#pragma unroll
-            for (int i = 0; i < H; ++i) be[i] = role ? bo[H + i] : bm[i];
-#pragma unroll
-            for (int j = 0; j < P1; ++j) bF[j] = role ? bm[j] : bo[j];
-#pragma unroll
+            // cl[i][j] = C[base + i][j]: rows base .. base+H-1 of the line factor
+            const int base = role ? H : 0;
+            double cl[H][P1][NC];
+    #pragma unroll
             for (int i = 0; i < H; ++i)
-#pragma unroll
-                for (int c = 0; c < NC; ++c) {
-                    const double t = wk[c] * be[i];
-#pragma unroll
-                    for (int j = 0; j < P1; ++j) cl[i][j][c] = fma(t, bF[j], cl[i][j][c]);
+    #pragma unroll
+                for (int j = 0; j < P1; ++j)
+    #pragma unroll
+                    for (int c = 0; c < NC; ++c) cl[i][j][c] = 0.0;
+            for (int id = 0; id < g; ++id) {
+                const double w = nx[id];
+                if (!cst) {
+                    const double wv = fix_u ? L.v0 + L.dv * w : L.u0 + L.du * w;
+                    tile_line_point<PG>(A, dA, wv, X, &kap);
+                    bernstein_t<P>(wv, bm);
                 }
-        }
-        // stage p and C of this line (row pl), rows base .. base+H-1 of both, in
-        // (fixed | moving) index order aX * P1 + bX
-        {
-            double bfo[P1 + 1];
+                // the partner's point; the weighted kernel value comes out bitwise
+                // the same on both lanes (x - y = -(y - x) exactly)
+                const double Y0 = from_pair_lane(X[0]), Y1 = from_pair_lane(X[1]), Y2 = from_pair_lane(X[2]);
+                const double ky = from_pair_lane(kap);
+                const double d0 = X[0] - Y0, d1 = X[1] - Y1, d2 = X[2] - Y2;
+                const double r2 = d0 * d0 + d1 * d1 + d2 * d2;
+                const double ir = rsqrt_pos(r2);
+                const double f0 = 0.07957747154594767 * ir * ((Wl * nw[id]) * (kap * ky));
+                double wk[NC];
+                if constexpr (NC == 2) {
+                    double sn, cs;
+                    sincos(kappa * (r2 * ir), &sn, &cs);
+                    wk[0] = cs * f0;
+                    wk[1] = sn * f0;
+                } else {
+                    wk[0] = f0;
+                }
+                // E's values of this lane's rows and F's values of all columns
+                double bo[P1 + 1], be[H], bF[P1];
+    #pragma unroll
+                for (int a = 0; a < P1; ++a) bo[a] = from_pair_lane(bm[a]);
+                bo[P1] = 0.0;
+    #pragma unroll
+                for (int i = 0; i < H; ++i) be[i] = role ? bo[H + i] : bm[i];
+    #pragma unroll
+                for (int j = 0; j < P1; ++j) bF[j] = role ? bm[j] : bo[j];
+    #pragma unroll
+                for (int i = 0; i < H; ++i)
+    #pragma unroll
+                    for (int c = 0; c < NC; ++c) {
+                        const double t = wk[c] * be[i];
+    #pragma unroll
+                        for (int j = 0; j < P1; ++j) cl[i][j][c] = fma(t, bF[j], cl[i][j][c]);
+                    }
+            }
+            // stage p and C of this line (row pl), rows base .. base+H-1 of both, in
+            // (fixed | moving) index order aX * P1 + bX
+            {
+                double bfo[P1 + 1];
+    #pragma unroll
+                for (int a = 0; a < P1; ++a) bfo[a] = from_pair_lane(bf[a]);
+                bfo[P1] = 0.0;
+                double *urow = Ub + pl * RS + base * P1;
+    #pragma unroll
+                for (int i = 0; i < H; ++i) {
+                    if (P1 % 2 == 1 && i == H - 1 && role) continue;  // row P1 does not exist
+                    const double fe = role ? bfo[H + i] : bf[i];
+    #pragma unroll
+                    for (int j = 0; j < P1; ++j) {
+                        const double ff = role ? bf[j] : bfo[j];
+                        urow[i * P1 + j] = fe * ff;
+    #pragma unroll
+                        for (int c = 0; c < NC; ++c) urow[(Vb - Ub) + c * HALF * RS + i * P1 + j] = cl[i][j][c];
+                    }
+                }
+            }
+        } else {
+            // common vertex: E's point is the same on the whole line, so both lanes of
+            // the pair evaluate F's points, lane 2k the even and lane 2k+1 the odd
+            // nodes; E's Bernstein factors are constant along the line, so the line
+            // factor has rank one, C = b(v_E) (x) sum over the nodes of w K b(moving of F)
+            const int base = role ? H : 0;
+            double bfE[P1 + 1], bmE[P1 + 1], bfF[P1], XE[3], kapE = 0.0;
+            {
+                double A[G1][4], dA[G1][4];
+                tile_fix<PG>(tfix_u + (size_t)R.E * TS, LE.u0, A, dA);  // E fixes u on vertex lines
+                tile_line_point<PG>(A, dA, LE.v0, XE, &kapE);
+            }
+            bernstein_t<P>(LE.u0, bfE);
+            bernstein_t<P>(LE.v0, bmE);
+            bfE[P1] = bmE[P1] = 0.0;
+            const double fF = fixF_u ? LF.u0 : LF.v0;
+            double A[G1][4], dA[G1][4];
+            tile_fix<PG>((fixF_u ? tfix_u : tfix_v) + (size_t)R.F * TS, fF, A, dA);
+            bernstein_t<P>(fF, bfF);
+            double sF[P1][NC];
 #pragma unroll
-            for (int a = 0; a < P1; ++a) bfo[a] = from_pair_lane(bf[a]);
-            bfo[P1] = 0.0;
+            for (int j = 0; j < P1; ++j)
+#pragma unroll
+                for (int c = 0; c < NC; ++c) sF[j][c] = 0.0;
+            for (int id = role; id < g; id += 2) {
+                const double w = nx[id];
+                const double wv = fixF_u ? LF.v0 + LF.dv * w : LF.u0 + LF.du * w;
+                double XF[3], kapF = 0.0, bmF[P1];
+                tile_line_point<PG>(A, dA, wv, XF, &kapF);
+                bernstein_t<P>(wv, bmF);
+                const double d0 = XE[0] - XF[0], d1 = XE[1] - XF[1], d2 = XE[2] - XF[2];
+                const double r2 = d0 * d0 + d1 * d1 + d2 * d2;
+                const double ir = rsqrt_pos(r2);
+                const double f0 = 0.07957747154594767 * ir * ((Wl * nw[id]) * (kapE * kapF));
+                double wk[NC];
+                if constexpr (NC == 2) {
+                    double sn, cs;
+                    sincos(kappa * (r2 * ir), &sn, &cs);
+                    wk[0] = cs * f0;
+                    wk[1] = sn * f0;
+                } else {
+                    wk[0] = f0;
+                }
+#pragma unroll
+                for (int j = 0; j < P1; ++j)
+#pragma unroll
+                    for (int c = 0; c < NC; ++c) sF[j][c] = fma(wk[c], bmF[j], sF[j][c]);
+            }
+            // both lanes: own half plus the partner's (the same sum on both)
+#pragma unroll
+            for (int j = 0; j < P1; ++j)
+#pragma unroll
+                for (int c = 0; c < NC; ++c) sF[j][c] += from_pair_lane(sF[j][c]);
             double *urow = Ub + pl * RS + base * P1;
 #pragma unroll
             for (int i = 0; i < H; ++i) {
                 if (P1 % 2 == 1 && i == H - 1 && role) continue;  // row P1 does not exist
-                const double fe = role ? bfo[H + i] : bf[i];
+                const double fe = role ? bfE[H + i] : bfE[i], me = role ? bmE[H + i] : bmE[i];
 #pragma unroll
                 for (int j = 0; j < P1; ++j) {
-                    const double ff = role ? bf[j] : bfo[j];
-                    urow[i * P1 + j] = fe * ff;
+                    urow[i * P1 + j] = fe * bfF[j];
 #pragma unroll
-                    for (int c = 0; c < NC; ++c) urow[(Vb - Ub) + c * HALF * RS + i * P1 + j] = cl[i][j][c];
+                    for (int c = 0; c < NC; ++c) urow[(Vb - Ub) + c * HALF * RS + i * P1 + j] = me * sF[j][c];
                 }
             }
         }
@@ -2522,7 +2595,7 @@ static igb_status launch_regular_p(igb_operator *op, const PairRec *d_pairs, int
 }
 
 template <class T, int P, int PG>
-static igb_status launch_singular_pg(igb_operator *op, const PairRec *d_pairs, int64_t n, void *outbuf)
+static igb_status launch_singular_pg(igb_operator *op, const PairRec *d_pairs, int64_t n, void *outbuf, bool vertex)
 {
     constexpr int NLOC = (P + 1) * (P + 1), NPAD = 16 * ((NLOC + 15) / 16), NC = NComp<T>::value;
     constexpr int STAGE_BYTES = (32 * (NC + 1) * (NPAD + 1) + 8) * 8;
@@ -2532,29 +2605,35 @@ static igb_status launch_singular_pg(igb_operator *op, const PairRec *d_pairs, i
     size_t stage = std::max<size_t>((size_t)WAVES * STAGE_BYTES, RED_BYTES);
     size_t shm = (size_t)128 * sizeof(double) + stage;
     if (shm > 160 * 1024) return fail(IGB_EUNSUPPORTED, "touching-pair quadrature: LDS too small for this degree");
-    (void)hipFuncSetAttribute((const void *)k_near_singular<T, P, PG, WAVES>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              (int)shm);
-    int gs = op->s.gs;
-    for (int64_t off = 0; off < n; off += 1 << 20) {
-        int64_t cnt = std::min<int64_t>(n - off, 1 << 20);
-        hipLaunchKernelGGL((k_near_singular<T, P, PG, WAVES>), dim3((unsigned)cnt), dim3(64 * WAVES), shm, op->st,
-                           d_pairs + off, gs, op->gx + op->s.goff[gs], op->gw + op->s.goff[gs], op->tline,
-                           op->tline + (size_t)op->s.nelem * op->s.tile_stride,
-                           op->s.kappa,
-                           (T *)outbuf + off * NLOC * NLOC);
-        LAUNCHCHK();
-    }
-    return IGB_OK;
+    const int gs = op->s.gs;
+    // identical and common-edge pairs, then (vertex) the common-vertex pairs of the same list
+    auto go = [&](auto vtx) -> igb_status {
+        constexpr bool V = decltype(vtx)::value;
+        (void)hipFuncSetAttribute((const void *)k_near_singular<T, P, PG, WAVES, V>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+        for (int64_t off = 0; off < n; off += 1 << 20) {
+            int64_t cnt = std::min<int64_t>(n - off, 1 << 20);
+            hipLaunchKernelGGL((k_near_singular<T, P, PG, WAVES, V>), dim3((unsigned)cnt), dim3(64 * WAVES), shm,
+                               op->st, d_pairs + off, gs, op->gx + op->s.goff[gs], op->gw + op->s.goff[gs], op->tline,
+                               op->tline + (size_t)op->s.nelem * op->s.tile_stride, op->s.kappa,
+                               (T *)outbuf + off * NLOC * NLOC);
+            LAUNCHCHK();
+        }
+        return IGB_OK;
+    };
+    igb_status rc = go(std::false_type{});
+    if (rc == IGB_OK && vertex) rc = go(std::true_type{});
+    return rc;
 }
 
 template <class T, int P>
-static igb_status launch_singular_p(igb_operator *op, const PairRec *d_pairs, int64_t n, void *outbuf)
+static igb_status launch_singular_p(igb_operator *op, const PairRec *d_pairs, int64_t n, void *outbuf, bool vertex)
 {
     switch (op->s.tile_degree) {
-    case 1: return launch_singular_pg<T, P, 1>(op, d_pairs, n, outbuf);
-    case 2: return launch_singular_pg<T, P, 2>(op, d_pairs, n, outbuf);
-    case 4: return launch_singular_pg<T, P, 4>(op, d_pairs, n, outbuf);
-    case 8: return launch_singular_pg<T, P, 8>(op, d_pairs, n, outbuf);
+    case 1: return launch_singular_pg<T, P, 1>(op, d_pairs, n, outbuf, vertex);
+    case 2: return launch_singular_pg<T, P, 2>(op, d_pairs, n, outbuf, vertex);
+    case 4: return launch_singular_pg<T, P, 4>(op, d_pairs, n, outbuf, vertex);
+    case 8: return launch_singular_pg<T, P, 8>(op, d_pairs, n, outbuf, vertex);
     }
     return fail(IGB_EUNSUPPORTED, "tile degree");
 }
@@ -2575,16 +2654,16 @@ static igb_status launch_regular(igb_operator *op, const PairRec *d, int64_t n, 
 }
 
 template <class T>
-static igb_status launch_singular(igb_operator *op, const PairRec *d, int64_t n, void *outbuf)
+static igb_status launch_singular(igb_operator *op, const PairRec *d, int64_t n, void *outbuf, bool vertex)
 {
     switch (op->s.p) {
-    case 0: return launch_singular_p<T, 0>(op, d, n, outbuf);
-    case 1: return launch_singular_p<T, 1>(op, d, n, outbuf);
-    case 2: return launch_singular_p<T, 2>(op, d, n, outbuf);
-    case 3: return launch_singular_p<T, 3>(op, d, n, outbuf);
-    case 4: return launch_singular_p<T, 4>(op, d, n, outbuf);
-    case 5: return launch_singular_p<T, 5>(op, d, n, outbuf);
-    case 6: return launch_singular_p<T, 6>(op, d, n, outbuf);
+    case 0: return launch_singular_p<T, 0>(op, d, n, outbuf, vertex);
+    case 1: return launch_singular_p<T, 1>(op, d, n, outbuf, vertex);
+    case 2: return launch_singular_p<T, 2>(op, d, n, outbuf, vertex);
+    case 3: return launch_singular_p<T, 3>(op, d, n, outbuf, vertex);
+    case 4: return launch_singular_p<T, 4>(op, d, n, outbuf, vertex);
+    case 5: return launch_singular_p<T, 5>(op, d, n, outbuf, vertex);
+    case 6: return launch_singular_p<T, 6>(op, d, n, outbuf, vertex);
     }
     return fail(IGB_EUNSUPPORTED, "p > 6");
 }
@@ -2880,7 +2959,7 @@ static igb_status assemble_identical(igb_operator *op)
     PairRec *d = nullptr;
     if ((rc = upload(op, &d, tid.data(), tid.size() * sizeof(PairRec)))) return rc;
     if ((rc = dalloc(op, &op->pairbuf_id, (size_t)s.nelem * s.nloc * s.nloc * sizeof(T)))) return rc;
-    return launch_singular<T>(op, d, (int64_t)s.nelem, op->pairbuf_id);
+    return launch_singular<T>(op, d, (int64_t)s.nelem, op->pairbuf_id, false);
 }
 
 // The common-edge and common-vertex pairs, found from corner coincidence of the
@@ -2897,7 +2976,7 @@ static igb_status assemble_adjacent(igb_operator *op)
     PairRec *d = nullptr;
     if ((rc = upload(op, &d, touch.data(), touch.size() * sizeof(PairRec)))) return rc;
     if ((rc = dalloc(op, &op->pairbuf, (size_t)n * s.nloc * s.nloc * sizeof(T)))) return rc;
-    if (n > 0) return launch_singular<T>(op, d, n, op->pairbuf);
+    if (n > 0) return launch_singular<T>(op, d, n, op->pairbuf, true);
     return IGB_OK;
 }
 

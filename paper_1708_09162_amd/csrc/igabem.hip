@@ -1332,22 +1332,42 @@ __device__ inline void far_sym_chunk(const FarSymArgs &F, int64_t k0, int64_t k1
         d[3 * W + j] = re_(n.w);
         if constexpr (NC == 2) d[4 * W + j] = im_(n.w);
     };
-    // lane j < W holds target node j and source node j of the next pair (W <= 64)
-    FarNode<T> nt{}, ns{};
+    // lane j holds target node j and source node j of the next pair, and nodes
+    // j + 64 as well when W > 64
+    constexpr bool TWO = W > 64;
+    FarNode<T> nt{}, ns{}, nt2{}, ns2{};
     if (lane < W) {
         nt = far_node<T>(F, Xh, F.up_t[k0], lane, 1e100);
         ns = far_node<T>(F, Xh, F.up_s[k0], lane, -1e100);
+    }
+    if constexpr (TWO) {
+        if (lane + 64 < W) {
+            nt2 = far_node<T>(F, Xh, F.up_t[k0], lane + 64, 1e100);
+            ns2 = far_node<T>(F, Xh, F.up_s[k0], lane + 64, -1e100);
+        }
     }
     for (int64_t k = k0; k < k1; ++k) {
         if (lane < W) {
             stage(tg, lane, nt);
             stage(sr, lane, ns);
         }
+        if constexpr (TWO) {
+            if (lane + 64 < W) {
+                stage(tg, lane + 64, nt2);
+                stage(sr, lane + 64, ns2);
+            }
+        }
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
         if (k + 1 < k1 && lane < W) {  // prefetch the next pair
             nt = far_node<T>(F, Xh, F.up_t[k + 1], lane, 1e100);
             ns = far_node<T>(F, Xh, F.up_s[k + 1], lane, -1e100);
+        }
+        if constexpr (TWO) {
+            if (k + 1 < k1 && lane + 64 < W) {
+                nt2 = far_node<T>(F, Xh, F.up_t[k + 1], lane + 64, 1e100);
+                ns2 = far_node<T>(F, Xh, F.up_s[k + 1], lane + 64, -1e100);
+            }
         }
         double tx[TT], ty[TT], tz[TT];
         T wt[TT], racc[TT];
@@ -1552,6 +1572,17 @@ __global__ void __launch_bounds__(256, NComp<T>::value == 1 ? 3 : 1) k_far_sym(F
     const int64_t k0 = ((int64_t)blockIdx.x * 4 + wave) * kFarChunk;
     if (k0 >= F.nup) return;  // whole waves only; no block-wide barrier follows
     far_chunk<T, TT, RAW>(F, k0, min(k0 + kFarChunk, F.nup), Xh, part, buf[wave]);
+}
+
+// Complex kernel with 65 .. 104 nodes per cluster: one wave per workgroup
+// (its LDS slice is too large for four), kFarChunk pairs per wave.
+template <class T, int TT>
+__global__ void __launch_bounds__(64, 1) k_far_sym1(FarSymArgs F, const T *__restrict__ Xh, T *__restrict__ part)
+{
+    extern __shared__ double sh[];
+    const int64_t k0 = (int64_t)blockIdx.x * kFarChunk;
+    if (k0 >= F.nup) return;
+    far_sym_chunk<T, TT>(F, k0, min(k0 + kFarChunk, F.nup), Xh, part, sh);
 }
 
 // The far-field pairs and the stored near blocks in one launch (ALU-bound and
@@ -2554,15 +2585,18 @@ static NearLayout near_layout(const Setup &s, size_t esz)
 // With both products symmetric, the near blocks ride along in the far-field
 // launch (and both gathers share one launch) when four waves' near staging fits
 // 64 KB of LDS.
-static bool fused_products(bool near_sym, int near_ld, size_t esz)
+static bool fused_products(bool near_sym, int near_ld, size_t esz, int q2)
 {
-    return near_sym && 4 * (size_t)(8 * near_ld + 520) * esz <= 64 * 1024;
+    return near_sym && q2 <= 64 && 4 * (size_t)(8 * near_ld + 520) * esz <= 64 * 1024;
 }
 
-// Far field evaluated once per mirrored pair of blocks (on the fly, q^2 <= 64).
+// Far field evaluated once per mirrored pair of blocks (on the fly; q^2 <= 64 for
+// the real kernel, q^2 <= 104 for the complex one).
 static bool far_mirrored(const Setup &s)
 {
-    return s.mode == IGB_H2_ONTHEFLY && s.q * s.q <= 64 && !s.far_src.empty();
+    // real kernel up to 64 nodes per cluster, complex up to 104 (13 per lane)
+    return s.mode == IGB_H2_ONTHEFLY && !s.far_src.empty() &&
+           (s.q * s.q <= 64 || (s.kernel == IGB_HELMHOLTZ && s.q * s.q <= 104));
 }
 
 static int64_t csr_find_host(const Setup &s, int t, int src)
@@ -2687,21 +2721,31 @@ static NearSymArgs near_args(const igb_operator *op)
 template <class T, int TT, bool RAW>
 static void launch_far_sym_p(igb_operator *op, const T *Xh, const T *xs, bool fuse)
 {
-    if (!fuse) {
-        hipLaunchKernelGGL((k_far_sym<T, TT, RAW>), dim3((unsigned)((op->nup + 4 * kFarChunk - 1) / (4 * kFarChunk))),
-                           dim3(256), 0, op->st, far_args(op), Xh, (T *)op->fpart);
-        return;
+    if constexpr (TT > 8) {  // one wave per workgroup (LDS slice of far_sym_lds doubles), never fused
+        (void)fuse;
+        const size_t shm = (size_t)far_sym_lds<T, TT>() * sizeof(double);
+        (void)hipFuncSetAttribute((const void *)k_far_sym1<T, TT>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+        hipLaunchKernelGGL((k_far_sym1<T, TT>), dim3((unsigned)((op->nup + kFarChunk - 1) / kFarChunk)), dim3(64), shm,
+                           op->st, far_args(op), Xh, (T *)op->fpart);
+    } else {
+        if (!fuse) {
+            hipLaunchKernelGGL((k_far_sym<T, TT, RAW>),
+                               dim3((unsigned)((op->nup + 4 * kFarChunk - 1) / (4 * kFarChunk))), dim3(256), 0, op->st,
+                               far_args(op), Xh, (T *)op->fpart);
+            return;
+        }
+        const int64_t nf = (op->nup + 4 * kFarChunk - 1) / (4 * kFarChunk), nn = (op->nsb + 3) / 4;
+        const size_t shm =
+            4 * std::max<size_t>((size_t)(8 * op->near_ld + 520) * NComp<T>::value, (size_t)far_sym_lds<T, TT>()) * 8;
+        hipLaunchKernelGGL((k_sym_products<T, TT, RAW>), dim3((unsigned)(nf + nn)), dim3(256), shm, op->st, far_args(op),
+                           near_args(op), nf, nn, Xh, (T *)op->fpart, (const T *)op->nearb, xs, (T *)op->npart);
     }
-    const int64_t nf = (op->nup + 4 * kFarChunk - 1) / (4 * kFarChunk), nn = (op->nsb + 3) / 4;
-    const size_t shm =
-        4 * std::max<size_t>((size_t)(8 * op->near_ld + 520) * NComp<T>::value, (size_t)far_sym_lds<T, TT>()) * 8;
-    hipLaunchKernelGGL((k_sym_products<T, TT, RAW>), dim3((unsigned)(nf + nn)), dim3(256), shm, op->st, far_args(op),
-                       near_args(op), nf, nn, Xh, (T *)op->fpart, (const T *)op->nearb, xs, (T *)op->npart);
 }
 
 template <class T, int TT>
 static void launch_far_sym(igb_operator *op, const T *Xh, const T *xs, bool fuse)
 {
+    static_assert(TT <= 8 || NComp<T>::value == 2, "more than 64 nodes per cluster: complex kernel only");
     if constexpr (NComp<T>::value == 1) {
         if (op->far_single && !op->force_fp64) {
             launch_far_sym_p<T, TT, true>(op, Xh, xs, fuse);
@@ -2769,7 +2813,7 @@ static igb_status matvec_internal(igb_operator *op, const T *xs, T *ys, hipEvent
     if ((rc = mark(1))) return rc;
     int64_t row0 = s.cl_off[op->lmin], nrows = s.cl_off[s.L + 1] - row0;
     const bool sym = has_far && op->fpart != nullptr;
-    const bool fuse = sym && !separate && fused_products(op->near_sym, op->near_ld, sizeof(T));
+    const bool fuse = sym && !separate && fused_products(op->near_sym, op->near_ld, sizeof(T), q2);
     if (has_far) {
         if (sym) {
             switch ((q2 + 7) / 8) {
@@ -2780,7 +2824,19 @@ static igb_status matvec_internal(igb_operator *op, const T *xs, T *ys, hipEvent
             case 5: launch_far_sym<T, 5>(op, Xh, xs, fuse); break;
             case 6: launch_far_sym<T, 6>(op, Xh, xs, fuse); break;
             case 7: launch_far_sym<T, 7>(op, Xh, xs, fuse); break;
-            default: launch_far_sym<T, 8>(op, Xh, xs, fuse); break;
+            case 8: launch_far_sym<T, 8>(op, Xh, xs, fuse); break;
+            default:  // complex kernel, 65 .. 104 nodes per cluster
+                if constexpr (NComp<T>::value == 2) {
+                    switch ((q2 + 7) / 8) {
+                    case 9: launch_far_sym<T, 9>(op, Xh, xs, false); break;
+                    case 10: launch_far_sym<T, 10>(op, Xh, xs, false); break;
+                    case 11: launch_far_sym<T, 11>(op, Xh, xs, false); break;
+                    case 12: launch_far_sym<T, 12>(op, Xh, xs, false); break;
+                    default: launch_far_sym<T, 13>(op, Xh, xs, false); break;
+                    }
+                } else {
+                    return fail(IGB_EINVAL, "mirrored far field: more than 64 nodes per cluster");
+                }
             }
         } else if (s.mode == IGB_H2_ONTHEFLY) {
             size_t shm = (size_t)4 * q2 * (3 + NComp<T>::value) * sizeof(double) + (size_t)4 * q2 * sizeof(T);
@@ -3918,7 +3974,8 @@ static void fill_info(const Setup &s, size_t esz, igb_info *out)
         NearLayout NL = near_layout(s, esz);
         out->near_bytes = NL.nsb * s.nl * NL.ld * (int64_t)esz;
         const bool fm = far_mirrored(s);
-        out->layout_flags = (NL.sym ? 1 : 0) | (fm ? 2 : 0) | (fm && fused_products(NL.sym, NL.ld, esz) ? 4 : 0);
+        out->layout_flags =
+            (NL.sym ? 1 : 0) | (fm ? 2 : 0) | (fm && fused_products(NL.sym, NL.ld, esz, s.q * s.q) ? 4 : 0);
     }
     out->coupling_bytes = s.mode == IGB_H2_STORED ? out->n_far_blocks * q2 * q2 * (int64_t)esz : 0;
     // one superspace matvec moves every stored block once, the S* vector in and

@@ -126,12 +126,16 @@ def test_plan_matches_oracle_sphere_p3_m5_q8_full_size():
     assert info.n_pairs[1] == 6144
 
 
-@pytest.mark.parametrize("mode,q,flags", [("stored", 8, 1), ("onthefly", 8, 7), ("onthefly", 10, 1)])
-def test_layout_flags(mode, q, flags):
-    """Symmetric near storage always at this size; mirrored far pairs and the shared launch only
-    on the fly with q^2 <= 64."""
+@pytest.mark.parametrize("mode,q,kernel,flags", [("stored", 8, 0, 1), ("onthefly", 8, 0, 7), ("onthefly", 10, 0, 1),
+                                                  ("onthefly", 8, 1, 3), ("onthefly", 10, 1, 3),
+                                                  ("onthefly", 11, 1, 1)])
+def test_layout_flags(mode, q, kernel, flags):
+    """Symmetric near storage always at this size; mirrored far pairs only on the fly, with at most 64
+    nodes per cluster for the real kernel and 104 for the complex one; the shared launch only where
+    four waves of near staging fit 64 KB of LDS (not for complex blocks of this size)."""
     g = igb.Geometry(W.sphere_patches())
     m = igb.IGB_H2_STORED if mode == "stored" else igb.IGB_H2_ONTHEFLY
-    info = igb.Plan(g, p=1, m=4, q=q, eta=1.6, gauss_regular=4, mode=m).info
+    info = igb.Plan(g, p=1, m=4, q=q, eta=1.6, gauss_regular=4, mode=m, kernel=kernel,
+                    wavenumber=2.0 if kernel else 0.0).info
     assert info.n_far_blocks > 0
     assert info.layout_flags == flags

@@ -377,6 +377,23 @@ def test_helmholtz_h2_torus(mode):
     assert rel(to_np(op.jacobi_diag()), P.jacobi_diag()) < 1e-12
 
 
+@pytest.mark.parametrize("q", [9, 10])
+def test_helmholtz_h2_torus_mirrored_many_nodes(q):
+    """Complex kernel with 81 and 100 interpolation nodes per cluster: the far field is generated once
+    per mirrored block pair with 11 and 13 nodes per lane (layout flag bit 1 set, no shared launch)."""
+    say(f"helmholtz h2 torus k=3 p=1 m=2 q={q} onthefly mirrored")
+    op, P = make(W.torus_patches(), mode=igb.IGB_H2_ONTHEFLY, kernel=igb.IGB_HELMHOLTZ, wavenumber=3.0, p=1, m=2,
+                 q=q, leaf_depth=1, eta=1.6, gauss_regular=4)
+    assert op.info.n_far_blocks > 0 and op.info.layout_flags == 3
+    P.h2_assemble(store_coupling=True)
+    xs = rand(P.nsup, 30 + q, cplx=True)
+    ys = to_np(op.matvec_super(torch.tensor(xs)))
+    assert rel(ys, P.h2_matvec_super(xs)) < 1e-12
+    zs = rand(P.nsup, 40 + q, cplx=True)
+    yz = to_np(op.matvec_super(torch.tensor(zs)))
+    assert abs(zs @ ys - xs @ yz) <= 1e-12 * abs(zs @ ys)  # complex symmetric, not Hermitian
+
+
 # ---------------------------------------------------------------------------
 # full size (the benchmark workload): sphere p=3, 32x32 elements per patch, q=8, eta=1.6
 # ---------------------------------------------------------------------------

@@ -144,6 +144,68 @@ def mixed_leg(torch, igb, geo, cfg, ev_dev, fp64_ms, exact, steps: int = 2):
             "coupling_ms": round(st["coupling"], 4)}
 
 
+def learned_leg(torch, igb, epochs: int = 4):
+    """The learned preconditioner on its own workload: Laplace on the perturbed sphere (p=2, 128x128 elements
+    per patch, q=8), 2000 seeded training vectors, the linear network trained on the GPU (loss on x), then
+    flexible GMRES to 1e-8 beside the plain FP64 solve (Jacobi CG) and Jacobi FGMRES, all from w = 0."""
+    from paper_1708_09162_amd import workloads as W
+
+    c5 = W.config_learned_preconditioner()
+    prm = dict(p=c5["p"], m=c5["m"], q=c5["q"], eta=c5["eta"], gauss_regular=c5["gauss_regular"])
+    geo = igb.Geometry(c5["patches"])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    op = igb.Operator(geo, device="cuda:0", mode=igb.IGB_H2_ONTHEFLY, **prm)
+    torch.cuda.synchronize()
+    t_asm = time.perf_counter() - t0
+    b = op.rhs(charge_field(torch, op.rhs_points(), *W.point_charges(*c5["charges"])))
+    npatch, side = op.grid
+    res = {"workload": c5["name"], "n_dof": int(op.info.n_dof), "n_pairs": c5["n_pairs"], "epochs": epochs,
+           "activation": "linear", "assembly_s": round(t_asm, 3)}
+
+    def timed_solve(fn):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        w, info = fn()
+        torch.cuda.synchronize()
+        return w, info, time.perf_counter() - t
+
+    _, i_cg, t_cg = timed_solve(lambda: op.solve(b, tol=TOL, max_iter=20000))
+    _, i_j, t_j = timed_solve(lambda: op.solve_fgmres(b, None, tol=TOL, max_iter=5000, restart=100))
+    gen = torch.Generator(device="cuda:0")
+    gen.manual_seed(c5["pair_seed"])
+    x = torch.randn((c5["n_pairs"], op.info.n_dof), dtype=torch.float64, device="cuda:0", generator=gen)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    y32, x32 = op.training_pairs(x)
+    torch.cuda.synchronize()
+    t_pairs = time.perf_counter() - t
+    del x
+    net = igb.CNN(W.cnn_initial_weights(c5["pair_seed"]), igb.IGB_CNN_LINEAR, device="cuda:0")
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    losses = net.train(y32, x32, npatch, side, side, epochs=epochs, batch=16, lr=1e-3)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t
+    del y32, x32
+    w, i_n, t_n = timed_solve(lambda: op.solve_fgmres(b, net, tol=TOL, max_iter=1000, restart=100))
+    r = b - op.matvec(w)
+    res.update({
+        "plain_fp64_cg": {"iterations": int(i_cg.iterations), "solve_s": round(t_cg, 4)},
+        "jacobi_fgmres": {"iterations": int(i_j.iterations), "solve_s": round(t_j, 4)},
+        "network_fgmres": {"iterations": int(i_n.iterations), "solve_s": round(t_n, 4),
+                           "converged": int(i_n.converged),
+                           "true_rel_residual": float(torch.linalg.norm(r) / torch.linalg.norm(b))},
+        "pairs_s": round(t_pairs, 3), "train_s": round(t_train, 3),
+        "loss_per_epoch": [round(float(v), 5) for v in losses],
+        "solve_vs_plain_fp64": round(t_n / t_cg, 4),
+    })
+    print(f"[bench] learned preconditioner: CG {i_cg.iterations} it {t_cg:.3f} s, Jacobi FGMRES {i_j.iterations} it "
+          f"{t_j:.3f} s, network FGMRES {i_n.iterations} it {t_n:.3f} s (train {t_train:.2f} s)", file=sys.stderr,
+          flush=True)
+    return res
+
+
 def cpu_baseline(cfg, iterations: int, seed: int = 7):
     """Oracle time-to-solve projected from a timed stratified sample of the same workload:
     near-field pair quadrature (per class) and coupling-block evaluation (the oracle evaluates
@@ -190,6 +252,7 @@ def main():
                     help="far field: coupling blocks generated in every matvec (default) or stored in HBM")
     ap.add_argument("--calibrate-copy", action="store_true", help="only run a plain 1 GiB device copy")
     ap.add_argument("--no-mixed", action="store_true", help="skip the single-precision far-field leg")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-preconditioner leg")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -349,6 +412,8 @@ def main():
     }
     if args.mode == "onthefly" and not args.no_mixed:
         out["mixed_fp32_far"] = mixed_leg(torch, igb, geo, cfg, ev_dev, ms_per_step, exact)
+    if not args.no_learned:
+        out["learned_preconditioner"] = learned_leg(torch, igb)
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle sample)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(cfg, int(info.iterations))

@@ -198,6 +198,80 @@ igb_status igb_jacobi_diag(const igb_operator *op, void *d_dev);
 igb_status igb_solve(const igb_operator *op, const void *b_dev, void *w_dev, double rel_tol, int32_t max_iter,
                      int32_t restart, igb_solve_info *info);
 
+/* ---- Learned preconditioner -------------------------------------------------
+ * Motivation: Sec. 5 observes that diagonally preconditioned Krylov solves
+ * grow costly on fine meshes with higher degrees.  A network acts patch by
+ * patch on the (2^m+p) x (2^m+p) coefficient grid of S (Sec. 2.2) as an
+ * approximate inverse of the Jacobi-scaled Galerkin matrix D^-1 A: the
+ * preconditioner is M(r) = y + f(y), y = D^-1 r.  f is five 3x3 convolutions
+ * with 1 -> 32 -> 32 -> 32 -> 32 -> 1 channels, an activation after the first
+ * four (ReLU, or the identity: then f is a linear 11 x 11 stencil in factored
+ * form), no biases, zero padding at patch edges.  Weights are FP32 for the optimiser and
+ * rounded to BF16 (nearest even) for every pass; sums accumulate in FP32.
+ * Weight layout: layers in order, each [c_out][c_in][3][3] (row dy, column
+ * dx; tap (dy, dx) reads pixel (y + dy - 1, x + dx - 1)).  An igb_cnn lives on
+ * the device current at igb_cnn_create; calls on one network must not
+ * overlap. */
+#define IGB_CNN_NUM_WEIGHTS 28224  /* 9 * (1*32 + 3*32*32 + 32*1) */
+#define IGB_CNN_RELU 0
+#define IGB_CNN_LINEAR 1
+typedef struct igb_cnn igb_cnn;
+
+/* Creates a network with the given FP32 weights (host, IGB_CNN_NUM_WEIGHTS
+ * values, copied) and activation IGB_CNN_RELU or IGB_CNN_LINEAR.  Work is
+ * ordered on hip_stream (NULL = default stream).  IGB_EINVAL for null
+ * pointers, non-finite weights or another activation; IGB_ENOMEM. */
+igb_status igb_cnn_create(const float *weights_host, int32_t activation, void *hip_stream, igb_cnn **out);
+void igb_cnn_destroy(igb_cnn *net);
+
+/* Copies the current FP32 weights to the host.  Synchronous. */
+igb_status igb_cnn_get_weights(const igb_cnn *net, float *weights_host);
+
+/* out = in + f(in) for n_img images of h x w (FP32 device arrays, image-major,
+ * rows of w values).  Asynchronous on the network's stream.  IGB_EINVAL for
+ * null pointers, sizes < 1, more than 65535 images or sides above 4096. */
+igb_status igb_cnn_forward(const igb_cnn *net, const float *in_dev, int32_t n_img, int32_t h, int32_t w,
+                           float *out_dev);
+
+/* Loss L = sum (in + f(in) - target)^2 / (2 N) over the N = n_img h w values
+ * and its gradient with respect to the BF16 weights (host, IGB_CNN_NUM_WEIGHTS
+ * floats, weight layout).  Synchronous.  Errors as igb_cnn_forward. */
+igb_status igb_cnn_gradient(igb_cnn *net, const float *in_dev, const float *target_dev, int32_t n_img, int32_t h,
+                            int32_t w, double *loss_host, float *grad_host);
+
+/* Training pairs from the operator (Laplace only): for each of the n_pairs
+ * FP64 coefficient vectors x_s in x_dev (n_pairs x n_dof, device), y_s =
+ * D^-1 A x_s and x_s, both rounded to FP32, into y_dev and x32_dev (n_pairs x
+ * n_dof floats each).  A vector of S is n_patches images of (2^m+p)^2.
+ * Asynchronous.  IGB_EUNSUPPORTED for Helmholtz operators. */
+igb_status igb_cnn_training_pairs(const igb_operator *op, const double *x_dev, int64_t n_pairs, float *y_dev,
+                                  float *x32_dev);
+
+/* Adam (beta1 0.9, beta2 0.999, eps 1e-8, rate lr) on the loss of
+ * igb_cnn_gradient over the pairs in order, `batch` pairs per step (the last
+ * step of an epoch takes the rest), `epochs` passes.  Each pair is
+ * imgs_per_pair images of h x w.  loss_host (may be NULL) receives the mean
+ * loss of each epoch (epochs doubles).  Synchronous. */
+igb_status igb_cnn_train(igb_cnn *net, const float *y_dev, const float *x_dev, int64_t n_pairs, int32_t imgs_per_pair,
+                         int32_t h, int32_t w, int32_t epochs, int32_t batch, float lr, double *loss_host);
+
+/* Adam as igb_cnn_train, but on the loss measured by the operator: for the
+ * pairs (y_s, x_s) of igb_cnn_training_pairs (y_s = D^-1 A x_s),
+ * L = sum_s |D^-1 A (M(y_s) - x_s)|^2 / (2 N), M(y) = y + f(y), N = n_pairs
+ * n_dof: the residual of the preconditioned system (Laplace only).  Two FP64
+ * operator applications per pair and step.  Synchronous. */
+igb_status igb_cnn_train_operator(igb_cnn *net, const igb_operator *op, const float *y_dev, const float *x_dev,
+                                  int64_t n_pairs, int32_t epochs, int32_t batch, float lr, double *loss_host);
+
+/* Flexible GMRES (right preconditioned, restarted after `restart` steps) for
+ * T A T^T w = b with the preconditioner M(v) = D^-1 v + f(D^-1 v) of `net`, or
+ * plain Jacobi D^-1 v when net is NULL (the fallback).  Laplace operators only
+ * (IGB_EUNSUPPORTED otherwise).  Stopping rule, initial guess and return
+ * values as igb_solve, judged on the true residual of the FP64 operator.  The
+ * bases take (2 restart + 1) n_dof doubles of device memory.  Synchronous. */
+igb_status igb_solve_fgmres(const igb_operator *op, const igb_cnn *net, const void *b_dev, void *w_dev,
+                            double rel_tol, int32_t max_iter, int32_t restart, igb_solve_info *info);
+
 /* Potential u(x) = (V~ mu_h)(x) for x off Gamma (Sec. 3.1, eq. eq::repform),
  * mu_h the density with S coefficients w_dev; Gauss order gauss_rhs per
  * element.  xyz_dev: n_pts x 3 doubles; u_dev: n_pts values. */

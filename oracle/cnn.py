@@ -10,8 +10,8 @@ grid of the spline space (Sec. 2.2):
 
     M(r) = y + f(y),  y = D^-1 r,
 
-f = five 3x3 convolutions (channels 1 -> 32 -> 32 -> 32 -> 32 -> 1), ReLU
-after the first four, no biases, zero padding at the grid edges.  Weights
+f = five 3x3 convolutions (channels 1 -> 32 -> 32 -> 32 -> 32 -> 1), ReLU (or
+the identity, a linear network) after the first four, no biases, zero padding at the grid edges.  Weights
 are given layer after layer, each as [c_out][c_in][dy][dx]; tap (dy, dx)
 reads pixel (y + dy - 1, x + dx - 1) (a cross-correlation).  The loss of a
 batch of pairs (y, x) is L = sum (y + f(y) - x)^2 / (2 N), N the number of
@@ -76,8 +76,9 @@ def relu(z):
     return np.maximum(z, 0.0)
 
 
-def forward(w, y):
-    """(y + f(y), pre-activations z_0..z_3) for images y of shape (n, H, W)."""
+def forward(w, y, linear=False):
+    """(y + f(y), pre-activations z_0..z_3) for images y of shape (n, H, W); linear=True takes the
+    identity for the activation."""
     ks = split(w)
     a = np.asarray(y, dtype=np.float64)[:, None]
     zs = []
@@ -85,24 +86,24 @@ def forward(w, y):
         z = conv3(a, k)
         if l < len(ks) - 1:
             zs.append(z)
-            a = relu(z)
+            a = z if linear else relu(z)
         else:
             f = z[:, 0]
     return np.asarray(y, dtype=np.float64) + f, zs
 
 
-def loss_grad(w, y, x):
+def loss_grad(w, y, x, linear=False):
     """(L, dL/dw) for images y, targets x of shape (n, H, W)."""
     ks = split(w)
     y = np.asarray(y, dtype=np.float64)
-    out, zs = forward(w, y)
+    out, zs = forward(w, y, linear)
     d = out - np.asarray(x, dtype=np.float64)
     N = d.size
     loss = float(np.sum(d * d) / (2 * N))
     g = (d / N)[:, None]                      # dL / d(output of the last layer)
     grads = [None] * len(ks)
     for l in range(len(ks) - 1, -1, -1):
-        a = y[:, None] if l == 0 else relu(zs[l - 1])
+        a = y[:, None] if l == 0 else (zs[l - 1] if linear else relu(zs[l - 1]))
         ap = np.pad(a, ((0, 0), (0, 0), (1, 1), (1, 1)))
         H, W = a.shape[2], a.shape[3]
         gw = np.zeros_like(ks[l])
@@ -111,11 +112,13 @@ def loss_grad(w, y, x):
                 gw[:, :, dy, dx] = np.einsum("nohw,nchw->oc", g, ap[:, :, dy:dy + H, dx:dx + W])
         grads[l] = gw
         if l > 0:
-            g = conv3_adjoint(g, ks[l]) * (zs[l - 1] > 0)
+            g = conv3_adjoint(g, ks[l])
+            if not linear:
+                g = g * (zs[l - 1] > 0)
     return loss, np.concatenate([gw.reshape(-1) for gw in grads])
 
 
-def precondition(w, r, D, n_img, side):
+def precondition(w, r, D, n_img, side, linear=False):
     """M(r) = y + f(y), y = r / D, for a vector of n_img grids of side x side (FP64)."""
     y = (np.asarray(r) / np.asarray(D)).reshape(n_img, side, side)
-    return forward(w, y)[0].reshape(-1)
+    return forward(w, y, linear)[0].reshape(-1)

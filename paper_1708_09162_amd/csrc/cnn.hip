@@ -1,0 +1,623 @@
+// Learned preconditioner for the single-layer system: a convolutional network
+// that acts patch by patch on the tensor-product coefficient grid of the spline
+// space (a patch of S is a (2^m+p) x (2^m+p) grid of coefficients, Sec. 2.2) as
+// an approximate inverse of the Jacobi-scaled Galerkin matrix.  Its purpose is
+// the observation of Sec. 5 that diagonally preconditioned Krylov iterations
+// grow costly for fine meshes and higher degrees.
+//
+// Network: five 3x3 convolutions, 1 -> C -> C -> C -> C -> 1 channels (C = 32),
+// ReLU (or the identity: a linear network) after the first four, no biases,
+// zero padding at the patch edges.  The
+// preconditioner is the residual map y -> y + f(y) with y = D^-1 r (D the
+// diagonal of the Galerkin matrix), so a network whose last layer is zero is
+// the Jacobi preconditioner.  Without biases f is positively homogeneous,
+// f(a y) = a f(y) for a > 0, so it needs no input normalisation.
+//
+// Precision: FP32 master weights for the optimiser (Adam), rounded to BF16
+// (nearest even) for every forward and backward pass; activations, gradients
+// and all sums in FP32.  Loss: L = sum (y + f(y) - x)^2 / (2 N) over the N
+// coefficients of a batch of (y, x) pairs.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/igabem.h"
+#include "cnn.h"
+
+namespace {
+
+constexpr int kC = 32;               // hidden channels
+constexpr int kLayers = 5;
+constexpr int kTile = 16;            // convolution output tile: 16 x 16 pixels, one per thread
+constexpr int kCiChunk = 8;          // input channels staged in LDS at a time
+constexpr int kGTH = 8, kGTW = 16;   // pixel tile of the weight-gradient kernel
+constexpr int kGBlocks = 1024;       // weight-gradient blocks (partials summed in a fixed order)
+constexpr int kLossBlocks = 1024;
+
+constexpr int kCin[kLayers] = {1, kC, kC, kC, kC};
+constexpr int kCout[kLayers] = {kC, kC, kC, kC, 1};
+
+struct Dims {
+    int64_t off[kLayers + 1];
+    int cin[kLayers], cout[kLayers];
+};
+
+Dims make_dims()
+{
+    Dims d{};
+    d.off[0] = 0;
+    for (int l = 0; l < kLayers; ++l) {
+        d.cin[l] = kCin[l];
+        d.cout[l] = kCout[l];
+        d.off[l + 1] = d.off[l] + (int64_t)9 * kCin[l] * kCout[l];
+    }
+    return d;
+}
+
+__device__ inline float bf16_to_float(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+__device__ inline uint16_t float_to_bf16(float f)
+{
+    uint32_t u = __float_as_uint(f);
+    u += 0x7fffu + ((u >> 16) & 1u);  // round to nearest, ties to even (finite inputs)
+    return (uint16_t)(u >> 16);
+}
+
+// out[n][co][y][x] = sum_ci sum_{dy,dx} w[co][ci][dy][dx] a[n][ci][y+dy-1][x+dx-1]
+// with a = relu(in) when RELU_IN, else in; zero outside the grid.  When
+// MASK_OUT, out is multiplied by (mask > 0) (the ReLU derivative of the layer
+// below, for the data gradient).  Grid: (tiles of 16 x 16, images).
+template <int CIN, int COUT, bool RELU_IN, bool MASK_OUT>
+__global__ void __launch_bounds__(256) k_conv3(const float *__restrict__ in, const uint16_t *__restrict__ wgt,
+                                               float *__restrict__ out, const float *__restrict__ mask, int H, int W,
+                                               int tiles_x)
+{
+    constexpr int CC = CIN < kCiChunk ? CIN : kCiChunk;
+    static_assert(CIN % CC == 0, "input channels in whole chunks");
+    constexpr int S = kTile + 2;
+    __shared__ float xs[CC][S][S + 1];
+    __shared__ float ws[CC * 9][COUT];
+    const int n = blockIdx.y;
+    const int ty0 = (blockIdx.x / tiles_x) * kTile, tx0 = (blockIdx.x % tiles_x) * kTile;
+    const int tid = threadIdx.x, py = tid / kTile, px = tid % kTile;
+    const size_t plane = (size_t)H * W;
+    float acc[COUT];
+#pragma unroll
+    for (int co = 0; co < COUT; ++co) acc[co] = 0.f;
+    for (int c0 = 0; c0 < CIN; c0 += CC) {
+        __syncthreads();
+        for (int i = tid; i < CC * S * S; i += 256) {
+            const int cc = i / (S * S), r = i % (S * S), yy = r / S, xx = r % S;
+            const int y = ty0 + yy - 1, x = tx0 + xx - 1;
+            float v = 0.f;
+            if (y >= 0 && y < H && x >= 0 && x < W) {
+                v = in[((size_t)n * CIN + c0 + cc) * plane + (size_t)y * W + x];
+                if (RELU_IN) v = fmaxf(v, 0.f);
+            }
+            xs[cc][yy][xx] = v;
+        }
+        for (int i = tid; i < CC * 9 * COUT; i += 256) {
+            const int co = i / (CC * 9), r = i % (CC * 9);
+            ws[r][co] = bf16_to_float(wgt[((size_t)co * CIN + c0) * 9 + r]);
+        }
+        __syncthreads();
+        for (int cc = 0; cc < CC; ++cc) {
+#pragma unroll
+            for (int t = 0; t < 9; ++t) {
+                const float xv = xs[cc][py + t / 3][px + t % 3];
+#pragma unroll
+                for (int co = 0; co < COUT; ++co) acc[co] = fmaf(ws[cc * 9 + t][co], xv, acc[co]);
+            }
+        }
+    }
+    const int y = ty0 + py, x = tx0 + px;
+    if (y < H && x < W) {
+        const size_t o = (size_t)n * COUT * plane + (size_t)y * W + x;
+#pragma unroll
+        for (int co = 0; co < COUT; ++co) {
+            float v = acc[co];
+            if (MASK_OUT && !(mask[o + co * plane] > 0.f)) v = 0.f;
+            out[o + co * plane] = v;
+        }
+    }
+}
+
+// Weight gradient of one layer: g[co][ci][t] = sum_{n,p} dz[n][co][p] a[n][ci][p + o_t]
+// (a = relu(in) when RELU_IN), as per-block partial sums part[block][co][ci][t];
+// block b takes the 8 x 16 pixel tiles b, b + gridDim.x, ...
+template <int CIN, int COUT, bool RELU_IN>
+__global__ void __launch_bounds__(256) k_wgrad3(const float *__restrict__ in, const float *__restrict__ dz,
+                                                float *__restrict__ part, int H, int W, int tiles_x,
+                                                int64_t tiles_per_img, int64_t ntiles)
+{
+    constexpr int NP = CIN * COUT;
+    constexpr int PPT = (NP + 255) / 256;
+    static_assert(256 % CIN == 0, "a thread keeps one input channel");
+    constexpr int AW = kGTW + 2, AS = (kGTH + 2) * AW + 1;
+    __shared__ float as[CIN * AS];
+    __shared__ float ds[COUT][kGTH * kGTW];
+    const int tid = threadIdx.x, ci = tid % CIN;
+    const size_t plane = (size_t)H * W;
+    float acc[PPT][9];
+#pragma unroll
+    for (int j = 0; j < PPT; ++j)
+#pragma unroll
+        for (int t = 0; t < 9; ++t) acc[j][t] = 0.f;
+    for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const int n = (int)(tile / tiles_per_img);
+        const int r = (int)(tile % tiles_per_img);
+        const int ty0 = (r / tiles_x) * kGTH, tx0 = (r % tiles_x) * kGTW;
+        __syncthreads();
+        for (int i = tid; i < CIN * (kGTH + 2) * AW; i += 256) {
+            const int c = i / ((kGTH + 2) * AW), rr = i % ((kGTH + 2) * AW);
+            const int y = ty0 + rr / AW - 1, x = tx0 + rr % AW - 1;
+            float v = 0.f;
+            if (y >= 0 && y < H && x >= 0 && x < W) {
+                v = in[((size_t)n * CIN + c) * plane + (size_t)y * W + x];
+                if (RELU_IN) v = fmaxf(v, 0.f);
+            }
+            as[c * AS + rr] = v;
+        }
+        for (int i = tid; i < COUT * kGTH * kGTW; i += 256) {
+            const int co = i / (kGTH * kGTW), pp = i % (kGTH * kGTW);
+            const int y = ty0 + pp / kGTW, x = tx0 + pp % kGTW;
+            ds[co][pp] = (y < H && x < W) ? dz[((size_t)n * COUT + co) * plane + (size_t)y * W + x] : 0.f;
+        }
+        __syncthreads();
+        if (tid < NP) {
+            for (int pp = 0; pp < kGTH * kGTW; ++pp) {
+                const int py = pp / kGTW, px = pp % kGTW;
+                float a9[9];
+#pragma unroll
+                for (int t = 0; t < 9; ++t) a9[t] = as[ci * AS + (py + t / 3) * AW + px + t % 3];
+#pragma unroll
+                for (int j = 0; j < PPT; ++j) {
+                    const int k = tid + 256 * j;
+                    if (k < NP) {
+                        const float d = ds[k / CIN][pp];
+#pragma unroll
+                        for (int t = 0; t < 9; ++t) acc[j][t] = fmaf(d, a9[t], acc[j][t]);
+                    }
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < PPT; ++j) {
+        const int k = tid + 256 * j;
+        if (k < NP)
+#pragma unroll
+            for (int t = 0; t < 9; ++t) part[(size_t)blockIdx.x * NP * 9 + (size_t)k * 9 + t] = acc[j][t];
+    }
+}
+
+__global__ void k_wreduce(int nblk, int cnt, const float *__restrict__ part, float *__restrict__ g)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= cnt) return;
+    float s = 0.f;
+    for (int b = 0; b < nblk; ++b) s += part[(size_t)b * cnt + i];
+    g[i] = s;
+}
+
+// d = y + f - x; dout = d * scale; per-block partial sums of d^2 (FP64).
+__global__ void __launch_bounds__(256) k_loss(int64_t n, const float *__restrict__ y, const float *__restrict__ f,
+                                              const float *__restrict__ x, float scale, float *__restrict__ dout,
+                                              double *__restrict__ lpart)
+{
+    __shared__ double red[256];
+    double s = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+        const float d = y[i] + f[i] - x[i];
+        dout[i] = d * scale;
+        s += (double)d * d;
+    }
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) lpart[blockIdx.x] = red[0];
+}
+
+__global__ void k_add_in(int64_t n, const float *__restrict__ y, float *__restrict__ f)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) f[i] += y[i];
+}
+
+__global__ void k_adam(int64_t n, float *__restrict__ w, const float *__restrict__ g, float *__restrict__ m,
+                       float *__restrict__ v, float lr, float b1, float b2, float eps, float c1, float c2)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.f - b1) * gi, vi = b2 * v[i] + (1.f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    w[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+// BF16 copies of the weights: wb in the forward layout [co][ci][t], wt for the
+// data gradient, [ci][co][8 - t] (channels swapped, taps flipped).
+__global__ void k_pack(Dims D, int64_t nw, const float *__restrict__ w, uint16_t *__restrict__ wb,
+                       uint16_t *__restrict__ wt)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nw) return;
+    int l = 0;
+    while (l + 1 < kLayers && i >= D.off[l + 1]) ++l;
+    const int64_t r = i - D.off[l];
+    const int cin = D.cin[l], cout = D.cout[l];
+    const int co = (int)(r / (9 * cin)), ci = (int)((r / 9) % cin), t = (int)(r % 9);
+    const uint16_t h = float_to_bf16(w[i]);
+    wb[i] = h;
+    wt[D.off[l] + ((int64_t)ci * cout + co) * 9 + (8 - t)] = h;
+}
+
+__global__ void k_pc_in(int64_t n, const double *__restrict__ v, const double *__restrict__ D, float *__restrict__ y)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) y[i] = (float)(v[i] / D[i]);
+}
+
+__global__ void k_pc_out(int64_t n, const double *__restrict__ v, const double *__restrict__ D,
+                         const float *__restrict__ f, double *__restrict__ z)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) z[i] = v[i] / D[i] + (double)f[i];
+}
+
+unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+
+}  // namespace
+
+struct igb_cnn {
+    hipStream_t st = nullptr;
+    bool relu = true;                  // IGB_CNN_RELU; false: identity activation (a linear network)
+    Dims dims{};
+    int64_t nw = 0;
+    float *w = nullptr, *g = nullptr, *m = nullptr, *v = nullptr, *part = nullptr;
+    uint16_t *wb = nullptr, *wt = nullptr;
+    double *lpart = nullptr;
+    int64_t step = 0;
+    int64_t cap = 0;                   // pixels per activation buffer
+    float *z[4] = {}, *da = nullptr, *db = nullptr, *f = nullptr, *d1 = nullptr, *yin = nullptr;
+};
+
+namespace {
+
+igb_status err(igb_status s, const std::string &m)
+{
+    igb_set_error(m);
+    return s;
+}
+
+#define CNNCHK(x)                                                                                         \
+    do {                                                                                                  \
+        hipError_t e_ = (x);                                                                              \
+        if (e_ != hipSuccess)                                                                             \
+            return err(e_ == hipErrorOutOfMemory ? IGB_ENOMEM : IGB_EHIP, std::string("HIP: ") + hipGetErrorString(e_)); \
+    } while (0)
+#define CNNLAUNCH() CNNCHK(hipGetLastError())
+
+void free_acts(igb_cnn *net)
+{
+    for (float **p : {&net->z[0], &net->z[1], &net->z[2], &net->z[3], &net->da, &net->db, &net->f, &net->d1, &net->yin}) {
+        if (*p) (void)hipFree(*p);
+        *p = nullptr;
+    }
+    net->cap = 0;
+}
+
+igb_status ensure(igb_cnn *net, int64_t npix)
+{
+    if (npix <= net->cap) return IGB_OK;
+    CNNCHK(hipStreamSynchronize(net->st));
+    free_acts(net);
+    for (int l = 0; l < 4; ++l) CNNCHK(hipMalloc(&net->z[l], (size_t)npix * kC * sizeof(float)));
+    CNNCHK(hipMalloc(&net->da, (size_t)npix * kC * sizeof(float)));
+    CNNCHK(hipMalloc(&net->db, (size_t)npix * kC * sizeof(float)));
+    CNNCHK(hipMalloc(&net->f, (size_t)npix * sizeof(float)));
+    CNNCHK(hipMalloc(&net->d1, (size_t)npix * sizeof(float)));
+    CNNCHK(hipMalloc(&net->yin, (size_t)npix * sizeof(float)));
+    net->cap = npix;
+    return IGB_OK;
+}
+
+template <int CIN, int COUT, bool RELU_IN, bool MASK_OUT>
+igb_status conv(const igb_cnn *net, const float *in, const uint16_t *w, float *out, const float *mask, int nimg, int H,
+                int W)
+{
+    const int tx = (W + kTile - 1) / kTile, ty = (H + kTile - 1) / kTile;
+    hipLaunchKernelGGL((k_conv3<CIN, COUT, RELU_IN, MASK_OUT>), dim3((unsigned)(tx * ty), (unsigned)nimg), dim3(256), 0,
+                       net->st, in, w, out, mask, H, W, tx);
+    CNNLAUNCH();
+    return IGB_OK;
+}
+
+template <int CIN, int COUT, bool RELU_IN>
+igb_status wgrad(igb_cnn *net, int layer, const float *in, const float *dz, int nimg, int H, int W)
+{
+    const int tx = (W + kGTW - 1) / kGTW, ty = (H + kGTH - 1) / kGTH;
+    const int64_t tpi = (int64_t)tx * ty, nt = tpi * nimg;
+    const int nb = (int)std::min<int64_t>(kGBlocks, nt);
+    hipLaunchKernelGGL((k_wgrad3<CIN, COUT, RELU_IN>), dim3((unsigned)nb), dim3(256), 0, net->st, in, dz, net->part, H, W,
+                       tx, tpi, nt);
+    CNNLAUNCH();
+    const int cnt = 9 * CIN * COUT;
+    hipLaunchKernelGGL(k_wreduce, dim3(nblk(cnt, 256)), dim3(256), 0, net->st, nb, cnt, (const float *)net->part,
+                       net->g + net->dims.off[layer]);
+    CNNLAUNCH();
+    return IGB_OK;
+}
+
+// f = network(in) (correction only) into net->f; pre-activations into z[0..3].
+template <bool ACT>
+igb_status forward_t(const igb_cnn *net, const float *in, int nimg, int H, int W)
+{
+    igb_status rc;
+    const int64_t *o = net->dims.off;
+    if ((rc = conv<1, kC, false, false>(net, in, net->wb + o[0], net->z[0], nullptr, nimg, H, W))) return rc;
+    if ((rc = conv<kC, kC, ACT, false>(net, net->z[0], net->wb + o[1], net->z[1], nullptr, nimg, H, W))) return rc;
+    if ((rc = conv<kC, kC, ACT, false>(net, net->z[1], net->wb + o[2], net->z[2], nullptr, nimg, H, W))) return rc;
+    if ((rc = conv<kC, kC, ACT, false>(net, net->z[2], net->wb + o[3], net->z[3], nullptr, nimg, H, W))) return rc;
+    return conv<kC, 1, ACT, false>(net, net->z[3], net->wb + o[4], net->f, nullptr, nimg, H, W);
+}
+
+igb_status forward(const igb_cnn *net, const float *in, int nimg, int H, int W)
+{
+    return net->relu ? forward_t<true>(net, in, nimg, H, W) : forward_t<false>(net, in, nimg, H, W);
+}
+
+// Weight gradient into net->g from dL/df in net->d1 (activations of the last forward pass).
+template <bool ACT>
+igb_status backward_t(igb_cnn *net, const float *in, int nimg, int H, int W)
+{
+    igb_status rc;
+    const int64_t *o = net->dims.off;
+    const uint16_t *wt = net->wt;
+    float **z = net->z;
+    if ((rc = wgrad<kC, 1, ACT>(net, 4, z[3], net->d1, nimg, H, W))) return rc;
+    if ((rc = conv<1, kC, false, ACT>(net, net->d1, wt + o[4], net->da, z[3], nimg, H, W))) return rc;
+    if ((rc = wgrad<kC, kC, ACT>(net, 3, z[2], net->da, nimg, H, W))) return rc;
+    if ((rc = conv<kC, kC, false, ACT>(net, net->da, wt + o[3], net->db, z[2], nimg, H, W))) return rc;
+    if ((rc = wgrad<kC, kC, ACT>(net, 2, z[1], net->db, nimg, H, W))) return rc;
+    if ((rc = conv<kC, kC, false, ACT>(net, net->db, wt + o[2], net->da, z[1], nimg, H, W))) return rc;
+    if ((rc = wgrad<kC, kC, ACT>(net, 1, z[0], net->da, nimg, H, W))) return rc;
+    if ((rc = conv<kC, kC, false, ACT>(net, net->da, wt + o[1], net->db, z[0], nimg, H, W))) return rc;
+    return wgrad<1, kC, false>(net, 0, in, net->db, nimg, H, W);
+}
+
+igb_status backward(igb_cnn *net, const float *in, int nimg, int H, int W)
+{
+    return net->relu ? backward_t<true>(net, in, nimg, H, W) : backward_t<false>(net, in, nimg, H, W);
+}
+
+// Loss of (in + f, target) and the weight gradient into net->g; returns sum d^2.
+igb_status loss_grad(igb_cnn *net, const float *in, const float *tgt, int nimg, int H, int W, double *sumsq)
+{
+    igb_status rc;
+    const int64_t npix = (int64_t)nimg * H * W;
+    if ((rc = forward(net, in, nimg, H, W))) return rc;
+    hipLaunchKernelGGL(k_loss, dim3(kLossBlocks), dim3(256), 0, net->st, npix, in, (const float *)net->f, tgt,
+                       (float)(1.0 / (double)npix), net->d1, net->lpart);
+    CNNLAUNCH();
+    if ((rc = backward(net, in, nimg, H, W))) return rc;
+    std::vector<double> lp(kLossBlocks);
+    CNNCHK(hipMemcpyAsync(lp.data(), net->lpart, kLossBlocks * sizeof(double), hipMemcpyDeviceToHost, net->st));
+    CNNCHK(hipStreamSynchronize(net->st));
+    double s = 0.0;
+    for (double x : lp) s += x;
+    *sumsq = s;
+    return IGB_OK;
+}
+
+igb_status adam_step(igb_cnn *net, float lr);
+
+igb_status pack(igb_cnn *net)
+{
+    hipLaunchKernelGGL(k_pack, dim3(nblk(net->nw, 256)), dim3(256), 0, net->st, net->dims, net->nw, (const float *)net->w,
+                       net->wb, net->wt);
+    CNNLAUNCH();
+    return IGB_OK;
+}
+
+igb_status adam_step(igb_cnn *net, float lr)
+{
+    const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+    ++net->step;
+    const float c1 = (float)(1.0 - std::pow((double)b1, (double)net->step));
+    const float c2 = (float)(1.0 - std::pow((double)b2, (double)net->step));
+    hipLaunchKernelGGL(k_adam, dim3(nblk(net->nw, 256)), dim3(256), 0, net->st, net->nw, net->w, (const float *)net->g,
+                       net->m, net->v, lr, b1, b2, eps, c1, c2);
+    CNNLAUNCH();
+    return pack(net);
+}
+
+struct StreamSwap {
+    igb_cnn *net;
+    hipStream_t keep;
+    StreamSwap(igb_cnn *n, hipStream_t st) : net(n), keep(n->st) { n->st = st; }
+    ~StreamSwap() { net->st = keep; }
+};
+
+igb_status check_grid(int64_t nimg, int64_t h, int64_t w)
+{
+    if (nimg < 1 || h < 1 || w < 1) return err(IGB_EINVAL, "image count and sizes must be >= 1");
+    if (nimg > 65535) return err(IGB_EINVAL, "at most 65535 images per call");
+    if (h > 4096 || w > 4096) return err(IGB_EINVAL, "image sides above 4096");
+    return IGB_OK;
+}
+
+}  // namespace
+
+int32_t cnn_precondition(const igb_cnn *cnet, int32_t n_img, int32_t h, int32_t w, const double *v, const double *D,
+                         double *z, hipStream_t st)
+{
+    igb_cnn *net = const_cast<igb_cnn *>(cnet);
+    igb_status rc;
+    if ((rc = check_grid(n_img, h, w))) return rc;
+    const int64_t n = (int64_t)n_img * h * w;
+    if ((rc = ensure(net, n))) return rc;
+    hipStream_t keep = net->st;
+    net->st = st;
+    hipLaunchKernelGGL(k_pc_in, dim3(nblk(n, 256)), dim3(256), 0, st, n, v, D, net->yin);
+    rc = hipGetLastError() == hipSuccess ? IGB_OK : err(IGB_EHIP, "kernel launch failed");
+    if (!rc) rc = forward(net, net->yin, n_img, h, w);
+    if (!rc) {
+        hipLaunchKernelGGL(k_pc_out, dim3(nblk(n, 256)), dim3(256), 0, st, n, v, D, (const float *)net->f, z);
+        if (hipGetLastError() != hipSuccess) rc = err(IGB_EHIP, "kernel launch failed");
+    }
+    net->st = keep;
+    return rc;
+}
+
+int32_t cnn_batch_forward(igb_cnn *net, const float *in, int32_t n_img, int32_t h, int32_t w, hipStream_t st,
+                          float **f_out, float **dout)
+{
+    igb_status rc;
+    if ((rc = check_grid(n_img, h, w))) return rc;
+    if ((rc = ensure(net, (int64_t)n_img * h * w))) return rc;
+    StreamSwap sw(net, st);
+    if ((rc = forward(net, in, n_img, h, w))) return rc;
+    *f_out = net->f;
+    *dout = net->d1;
+    return IGB_OK;
+}
+
+int32_t cnn_batch_backward_adam(igb_cnn *net, const float *in, int32_t n_img, int32_t h, int32_t w, float lr,
+                                hipStream_t st)
+{
+    StreamSwap sw(net, st);
+    igb_status rc;
+    if ((rc = backward(net, in, n_img, h, w))) return rc;
+    return adam_step(net, lr);
+}
+
+extern "C" {
+
+igb_status igb_cnn_create(const float *weights_host, int32_t activation, void *hip_stream, igb_cnn **out)
+{
+    if (!out) return err(IGB_EINVAL, "null argument");
+    *out = nullptr;
+    if (!weights_host) return err(IGB_EINVAL, "null weights");
+    if (activation != IGB_CNN_RELU && activation != IGB_CNN_LINEAR) return err(IGB_EINVAL, "unknown activation");
+    igb_cnn *net = new igb_cnn();
+    net->relu = activation == IGB_CNN_RELU;
+    net->st = (hipStream_t)hip_stream;
+    net->dims = make_dims();
+    net->nw = net->dims.off[kLayers];
+    if (net->nw != IGB_CNN_NUM_WEIGHTS) {
+        delete net;
+        return err(IGB_EINVAL, "weight count mismatch");
+    }
+    for (int64_t i = 0; i < net->nw; ++i)
+        if (!std::isfinite(weights_host[i])) {
+            delete net;
+            return err(IGB_EINVAL, "weights must be finite");
+        }
+    auto fail_free = [&](igb_status s) {
+        igb_cnn_destroy(net);
+        return s;
+    };
+    const size_t fb = (size_t)net->nw * sizeof(float);
+    if (hipMalloc(&net->w, fb) != hipSuccess || hipMalloc(&net->g, fb) != hipSuccess ||
+        hipMalloc(&net->m, fb) != hipSuccess || hipMalloc(&net->v, fb) != hipSuccess ||
+        hipMalloc(&net->wb, net->nw * sizeof(uint16_t)) != hipSuccess ||
+        hipMalloc(&net->wt, net->nw * sizeof(uint16_t)) != hipSuccess ||
+        hipMalloc(&net->part, (size_t)kGBlocks * 9 * kC * kC * sizeof(float)) != hipSuccess ||
+        hipMalloc(&net->lpart, kLossBlocks * sizeof(double)) != hipSuccess)
+        return fail_free(err(IGB_ENOMEM, "device allocation failed"));
+    if (hipMemcpyAsync(net->w, weights_host, fb, hipMemcpyHostToDevice, net->st) != hipSuccess ||
+        hipMemsetAsync(net->m, 0, fb, net->st) != hipSuccess || hipMemsetAsync(net->v, 0, fb, net->st) != hipSuccess)
+        return fail_free(err(IGB_EHIP, "weight upload failed"));
+    igb_status rc = pack(net);
+    if (!rc && hipStreamSynchronize(net->st) != hipSuccess) rc = err(IGB_EHIP, "weight upload failed");
+    if (rc) return fail_free(rc);
+    *out = net;
+    return IGB_OK;
+}
+
+void igb_cnn_destroy(igb_cnn *net)
+{
+    if (!net) return;
+    (void)hipStreamSynchronize(net->st);
+    free_acts(net);
+    for (void *p : {(void *)net->w, (void *)net->g, (void *)net->m, (void *)net->v, (void *)net->wb, (void *)net->wt,
+                    (void *)net->part, (void *)net->lpart})
+        if (p) (void)hipFree(p);
+    delete net;
+}
+
+igb_status igb_cnn_get_weights(const igb_cnn *net, float *weights_host)
+{
+    if (!net || !weights_host) return err(IGB_EINVAL, "null argument");
+    CNNCHK(hipMemcpyAsync(weights_host, net->w, net->nw * sizeof(float), hipMemcpyDeviceToHost, net->st));
+    CNNCHK(hipStreamSynchronize(net->st));
+    return IGB_OK;
+}
+
+igb_status igb_cnn_forward(const igb_cnn *cnet, const float *in_dev, int32_t n_img, int32_t h, int32_t w, float *out_dev)
+{
+    if (!cnet || !in_dev || !out_dev) return err(IGB_EINVAL, "null argument");
+    igb_cnn *net = const_cast<igb_cnn *>(cnet);
+    igb_status rc;
+    if ((rc = check_grid(n_img, h, w))) return rc;
+    const int64_t n = (int64_t)n_img * h * w;
+    if ((rc = ensure(net, n))) return rc;
+    if ((rc = forward(net, in_dev, n_img, h, w))) return rc;
+    hipLaunchKernelGGL(k_add_in, dim3(nblk(n, 256)), dim3(256), 0, net->st, n, in_dev, net->f);
+    CNNLAUNCH();
+    CNNCHK(hipMemcpyAsync(out_dev, net->f, n * sizeof(float), hipMemcpyDeviceToDevice, net->st));
+    return IGB_OK;
+}
+
+igb_status igb_cnn_gradient(igb_cnn *net, const float *in_dev, const float *target_dev, int32_t n_img, int32_t h,
+                            int32_t w, double *loss_host, float *grad_host)
+{
+    if (!net || !in_dev || !target_dev || !loss_host || !grad_host) return err(IGB_EINVAL, "null argument");
+    igb_status rc;
+    if ((rc = check_grid(n_img, h, w))) return rc;
+    const int64_t n = (int64_t)n_img * h * w;
+    if ((rc = ensure(net, n))) return rc;
+    double s;
+    if ((rc = loss_grad(net, in_dev, target_dev, n_img, h, w, &s))) return rc;
+    *loss_host = s / (2.0 * (double)n);
+    CNNCHK(hipMemcpyAsync(grad_host, net->g, net->nw * sizeof(float), hipMemcpyDeviceToHost, net->st));
+    CNNCHK(hipStreamSynchronize(net->st));
+    return IGB_OK;
+}
+
+igb_status igb_cnn_train(igb_cnn *net, const float *y_dev, const float *x_dev, int64_t n_pairs, int32_t imgs_per_pair,
+                         int32_t h, int32_t w, int32_t epochs, int32_t batch, float lr, double *loss_host)
+{
+    if (!net || !y_dev || !x_dev) return err(IGB_EINVAL, "null argument");
+    if (n_pairs < 1 || epochs < 0 || batch < 1) return err(IGB_EINVAL, "n_pairs and batch must be >= 1, epochs >= 0");
+    if (!(lr > 0.f) || !std::isfinite(lr)) return err(IGB_EINVAL, "learning rate must be > 0");
+    igb_status rc;
+    const int64_t b = std::min<int64_t>(batch, n_pairs);
+    if ((rc = check_grid(b * imgs_per_pair, h, w))) return rc;
+    const int64_t per = (int64_t)imgs_per_pair * h * w;
+    if ((rc = ensure(net, b * per))) return rc;
+    for (int e = 0; e < epochs; ++e) {
+        double tot = 0.0;
+        for (int64_t s0 = 0; s0 < n_pairs; s0 += b) {
+            const int64_t nb = std::min(b, n_pairs - s0);
+            double s;
+            if ((rc = loss_grad(net, y_dev + s0 * per, x_dev + s0 * per, (int)(nb * imgs_per_pair), h, w, &s))) return rc;
+            tot += s;
+            if ((rc = adam_step(net, lr))) return rc;
+        }
+        if (loss_host) loss_host[e] = tot / (2.0 * (double)(n_pairs * per));
+    }
+    CNNCHK(hipStreamSynchronize(net->st));
+    return IGB_OK;
+}
+
+}  // extern "C"

@@ -13,6 +13,7 @@
 #include <type_traits>
 #include <vector>
 
+#include "cnn.h"
 #include "kernels.h"
 #include "setup.h"
 
@@ -25,6 +26,8 @@ static igb_status fail(igb_status s, const std::string &m)
     g_err = m;
     return s;
 }
+
+void igb_set_error(const std::string &msg) { g_err = msg; }
 
 #define HIPCHK(x)                                                                                  \
     do {                                                                                           \
@@ -2527,6 +2530,8 @@ struct igb_operator {
     double assembly_seconds = 0.0;
     std::vector<DevBlock> owned;
     DevBlock Vblk{}, hblk{}, mblk{};  // GMRES basis, projections, multi-dot partials
+    DevBlock Zblk{};                  // flexible GMRES: preconditioned directions
+    int Zcols = 0;
     // far_precision IGB_FP32: products use single-precision far-field kernel values;
     // force_fp64 is set while the solver forms its double-precision residuals
     bool far_single = false, force_fp64 = false;
@@ -3559,6 +3564,167 @@ static igb_status solve_gmres(igb_operator *op, const cd *b, cd *w, double tol, 
     return rel <= tol ? IGB_OK : fail(IGB_ENOT_CONVERGED, "GMRES stopped at max_iter with relative residual " + std::to_string(rel));
 }
 
+// Flexible GMRES (Saad's right-preconditioned variant that keeps the
+// preconditioned directions z_k, since a network is not a fixed linear map),
+// classical Gram-Schmidt applied twice, Givens rotations on the host.  The
+// operator runs in FP64 throughout.
+static igb_status solve_fgmres(igb_operator *op, const igb_cnn *net, const double *b, double *w, double tol, int maxit,
+                               int restart, igb_solve_info *info)
+{
+    const Setup &s = op->s;
+    const int64_t n = s.ndof;
+    const int R = std::max(1, std::min(restart, std::max(1, maxit)));
+    igb_status rc;
+    struct Restore {
+        igb_operator *o;
+        bool v;
+        ~Restore() { o->force_fp64 = v; }
+    } restore{op, op->force_fp64};
+    op->force_fp64 = true;
+    if (op->Vcols < R + 1 || op->Zcols < R) {
+        HIPCHK(hipStreamSynchronize(op->st));
+        pool_free(op->Vblk);
+        pool_free(op->Zblk);
+        pool_free(op->hblk);
+        pool_free(op->mblk);
+        op->V = op->hdev = op->mpart = nullptr;
+        op->Vcols = op->Zcols = 0;
+        HIPCHK(pool_alloc(op->Vblk, (size_t)(R + 1) * n * sizeof(double)));
+        HIPCHK(pool_alloc(op->Zblk, (size_t)R * n * sizeof(double)));
+        HIPCHK(pool_alloc(op->hblk, (size_t)(R + 1) * sizeof(double)));
+        HIPCHK(pool_alloc(op->mblk, (size_t)(R + 1) * kRedBlocks * sizeof(double)));
+        op->V = op->Vblk.p;
+        op->hdev = op->hblk.p;
+        op->mpart = op->mblk.p;
+        op->Vcols = R + 1;
+        op->Zcols = R;
+    }
+    double *V = (double *)op->V, *Z = (double *)op->Zblk.p, *hd = (double *)op->hdev, *t = (double *)op->tmp,
+           *r = (double *)op->r;
+    const double *D = (const double *)op->diag;
+    const unsigned gb = std::min<unsigned>(nblk(n, 256), 1024);
+    auto norm2 = [&](const double *x, double *out) -> igb_status {
+        igb_status c;
+        if ((c = dot_dev<double>(op, n, x, x, op->scal))) return c;
+        return read_scalar(op, 0, out);
+    };
+    double bn2;
+    if ((rc = norm2(b, &bn2))) return rc;
+    double bn = std::sqrt(bn2);
+    if (bn == 0.0) bn = 1.0;
+    std::vector<double> H((size_t)(R + 1) * R), cs(R), sn(R), g(R + 1), y(R), hcol(R + 1), hh(R + 1);
+    int it = 0;
+    double rel = 0.0;
+    for (;;) {
+        if ((rc = matvec_S<double>(op, w, t))) return rc;
+        HIPCHK(hipMemcpyAsync(r, b, n * sizeof(double), hipMemcpyDeviceToDevice, op->st));
+        hipLaunchKernelGGL((k_axpby<double>), dim3(gb), dim3(256), 0, op->st, n, -1.0, (const double *)t, 1.0, r);
+        LAUNCHCHK();
+        double beta2;
+        if ((rc = norm2(r, &beta2))) return rc;
+        const double beta = std::sqrt(beta2);
+        rel = beta / bn;
+        if (rel <= tol || it >= maxit) break;
+        hipLaunchKernelGGL((k_axpby<double>), dim3(gb), dim3(256), 0, op->st, n, 1.0 / beta, (const double *)r, 0.0, V);
+        LAUNCHCHK();
+        std::fill(g.begin(), g.end(), 0.0);
+        std::fill(H.begin(), H.end(), 0.0);
+        g[0] = beta;
+        int k = 0;
+        for (; k < R && it < maxit;) {
+            double *vk = V + (size_t)k * n, *vn = V + (size_t)(k + 1) * n, *zk = Z + (size_t)k * n;
+            if (net) {
+                if ((rc = cnn_precondition(net, s.npatch, s.ns1, s.ns1, vk, D, zk, op->st))) return rc;
+            } else {
+                hipLaunchKernelGGL((k_div<double>), dim3(gb), dim3(256), 0, op->st, n, (const double *)vk, D, zk);
+                LAUNCHCHK();
+            }
+            if ((rc = matvec_S<double>(op, zk, vn))) return rc;
+            std::fill(hcol.begin(), hcol.end(), 0.0);
+            for (int pass = 0; pass < 2; ++pass) {
+                hipLaunchKernelGGL((k_multidot_partial<double>), dim3(kRedBlocks), dim3(256), 0, op->st, n, k + 1,
+                                   (const double *)V, n, (const double *)vn, (double *)op->mpart, kRedBlocks);
+                LAUNCHCHK();
+                hipLaunchKernelGGL((k_multireduce<double>), dim3(k + 1), dim3(256), 0, op->st, k + 1, kRedBlocks,
+                                   (const double *)op->mpart, hd);
+                LAUNCHCHK();
+                hipLaunchKernelGGL((k_sub_Vh<double>), dim3(gb), dim3(256), 0, op->st, n, k + 1, (const double *)V, n,
+                                   (const double *)hd, vn);
+                LAUNCHCHK();
+                HIPCHK(hipMemcpyAsync(hh.data(), hd, (k + 1) * sizeof(double), hipMemcpyDeviceToHost, op->st));
+                HIPCHK(hipStreamSynchronize(op->st));
+                for (int j = 0; j <= k; ++j) hcol[j] += hh[j];
+            }
+            double hn2;
+            if ((rc = norm2(vn, &hn2))) return rc;
+            const double hn = std::sqrt(hn2);
+            hcol[k + 1] = hn;
+            if (hn > 0.0) {
+                hipLaunchKernelGGL((k_axpby<double>), dim3(gb), dim3(256), 0, op->st, n, 1.0 / hn, (const double *)vn,
+                                   0.0, vn);
+                LAUNCHCHK();
+            }
+            for (int j = 0; j < k; ++j) {
+                const double a = hcol[j], bb = hcol[j + 1];
+                hcol[j] = cs[j] * a + sn[j] * bb;
+                hcol[j + 1] = -sn[j] * a + cs[j] * bb;
+            }
+            const double a = hcol[k], bb = hcol[k + 1], den = std::hypot(a, bb);
+            cs[k] = a / den;
+            sn[k] = bb / den;
+            hcol[k] = den;
+            hcol[k + 1] = 0.0;
+            g[k + 1] = -sn[k] * g[k];
+            g[k] = cs[k] * g[k];
+            for (int j = 0; j <= k; ++j) H[(size_t)j * R + k] = hcol[j];
+            ++k;
+            ++it;
+            if (std::fabs(g[k]) / bn <= tol) break;
+        }
+        // y = H^-1 g (upper triangular k x k); w += Z y
+        for (int j = k - 1; j >= 0; --j) {
+            double sum = g[j];
+            for (int l = j + 1; l < k; ++l) sum -= H[(size_t)j * R + l] * y[l];
+            y[j] = sum / H[(size_t)j * R + j];
+        }
+        for (int j = 0; j < k; ++j) hh[j] = -y[j];
+        HIPCHK(hipMemcpyAsync(hd, hh.data(), k * sizeof(double), hipMemcpyHostToDevice, op->st));
+        hipLaunchKernelGGL((k_sub_Vh<double>), dim3(gb), dim3(256), 0, op->st, n, k, (const double *)Z, n,
+                           (const double *)hd, w);
+        LAUNCHCHK();
+        HIPCHK(hipStreamSynchronize(op->st));
+    }
+    if (info) {
+        info->iterations = it;
+        info->rel_residual = rel;
+        info->converged = rel <= tol;
+    }
+    return rel <= tol ? IGB_OK
+                      : fail(IGB_ENOT_CONVERGED, "FGMRES stopped at max_iter with relative residual " + std::to_string(rel));
+}
+
+__global__ void k_err64(int64_t n, const float *__restrict__ y, const float *__restrict__ f, const float *__restrict__ x,
+                        double *__restrict__ e)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) e[i] = (double)y[i] + (double)f[i] - (double)x[i];
+}
+
+__global__ void k_grad32(int64_t n, const double *__restrict__ g, double scale, float *__restrict__ out)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = (float)(g[i] * scale);
+}
+
+__global__ void k_pairs_out(int64_t n, const double *__restrict__ t, const double *__restrict__ D,
+                            const double *__restrict__ x, float *__restrict__ y32, float *__restrict__ x32)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    y32[i] = (float)(t[i] / D[i]);
+    x32[i] = (float)x[i];
+}
+
 // ===========================================================================
 // C ABI
 // ===========================================================================
@@ -3595,11 +3761,13 @@ void igb_operator_destroy(igb_operator *op)
     if (hipStreamSynchronize(op->st) == hipSuccess) {
         for (DevBlock &b : op->owned) pool_free(b);
         pool_free(op->Vblk);
+        pool_free(op->Zblk);
         pool_free(op->hblk);
         pool_free(op->mblk);
     } else {
         for (DevBlock &b : op->owned) (void)hipFree(b.p);
         (void)hipFree(op->Vblk.p);
+        (void)hipFree(op->Zblk.p);
         (void)hipFree(op->hblk.p);
         (void)hipFree(op->mblk.p);
     }
@@ -3801,6 +3969,101 @@ igb_status igb_solve(const igb_operator *cop, const void *b_dev, void *w_dev, do
         return solve_gmres(op, (const cd *)b_dev, (cd *)w_dev, rel_tol, max_iter, restart, info);
     }
     return solve_cg(op, (const double *)b_dev, (double *)w_dev, rel_tol, max_iter, info);
+}
+
+igb_status igb_solve_fgmres(const igb_operator *cop, const igb_cnn *net, const void *b_dev, void *w_dev,
+                            double rel_tol, int32_t max_iter, int32_t restart, igb_solve_info *info)
+{
+    CHECK_OP(cop);
+    if (!b_dev || !w_dev) return fail(IGB_EINVAL, "null device pointer");
+    if (b_dev == w_dev) return fail(IGB_EINVAL, "b and w must not alias");
+    if (!(rel_tol > 0.0) || max_iter < 0) return fail(IGB_EINVAL, "rel_tol must be > 0 and max_iter >= 0");
+    if (restart < 1) return fail(IGB_EINVAL, "restart must be >= 1");
+    igb_operator *op = const_cast<igb_operator *>(cop);
+    if (op->cplx) return fail(IGB_EUNSUPPORTED, "flexible GMRES is built for real (Laplace) operators");
+    return solve_fgmres(op, net, (const double *)b_dev, (double *)w_dev, rel_tol, max_iter, restart, info);
+}
+
+igb_status igb_cnn_train_operator(igb_cnn *net, const igb_operator *cop, const float *y_dev, const float *x_dev,
+                                  int64_t n_pairs, int32_t epochs, int32_t batch, float lr, double *loss_host)
+{
+    CHECK_OP(cop);
+    if (!net || !y_dev || !x_dev) return fail(IGB_EINVAL, "null argument");
+    if (n_pairs < 1 || epochs < 0 || batch < 1) return fail(IGB_EINVAL, "n_pairs and batch must be >= 1, epochs >= 0");
+    if (!(lr > 0.f) || !std::isfinite(lr)) return fail(IGB_EINVAL, "learning rate must be > 0");
+    igb_operator *op = const_cast<igb_operator *>(cop);
+    if (op->cplx) return fail(IGB_EUNSUPPORTED, "the network is built for real (Laplace) operators");
+    struct Restore {
+        igb_operator *o;
+        bool v;
+        ~Restore() { o->force_fp64 = v; }
+    } restore{op, op->force_fp64};
+    op->force_fp64 = true;
+    const Setup &s = op->s;
+    const int64_t n = s.ndof, b = std::min<int64_t>(batch, n_pairs);
+    double *e = (double *)op->r, *t = (double *)op->tmp, *u = (double *)op->z;
+    const double *D = (const double *)op->diag;
+    const unsigned gb = std::min<unsigned>(nblk(n, 256), 1024);
+    igb_status rc;
+    for (int ep = 0; ep < epochs; ++ep) {
+        double tot = 0.0;
+        for (int64_t s0 = 0; s0 < n_pairs; s0 += b) {
+            const int64_t nb = std::min(b, n_pairs - s0);
+            float *f = nullptr, *dout = nullptr;
+            if ((rc = cnn_batch_forward(net, y_dev + s0 * n, (int32_t)(nb * s.npatch), s.ns1, s.ns1, op->st, &f, &dout)))
+                return rc;
+            const double scale = 1.0 / (double)(nb * n);
+            for (int64_t k = 0; k < nb; ++k) {
+                // e = M(y) - x; u = D^-1 A e; loss += |u|^2; dL/dM(y) = A D^-1 u / N
+                hipLaunchKernelGGL(k_err64, dim3(nblk(n, 256)), dim3(256), 0, op->st, n, y_dev + (s0 + k) * n,
+                                   (const float *)f + k * n, x_dev + (s0 + k) * n, e);
+                LAUNCHCHK();
+                if ((rc = matvec_S<double>(op, e, t))) return rc;
+                hipLaunchKernelGGL((k_div<double>), dim3(gb), dim3(256), 0, op->st, n, (const double *)t, D, u);
+                LAUNCHCHK();
+                double uu;
+                if ((rc = dot_dev<double>(op, n, u, u, op->scal + 2))) return rc;
+                if ((rc = read_scalar(op, 2, &uu))) return rc;
+                tot += uu;
+                hipLaunchKernelGGL((k_div<double>), dim3(gb), dim3(256), 0, op->st, n, (const double *)u, D, e);
+                LAUNCHCHK();
+                if ((rc = matvec_S<double>(op, e, t))) return rc;
+                hipLaunchKernelGGL(k_grad32, dim3(nblk(n, 256)), dim3(256), 0, op->st, n, (const double *)t, scale,
+                                   dout + k * n);
+                LAUNCHCHK();
+            }
+            if ((rc = cnn_batch_backward_adam(net, y_dev + s0 * n, (int32_t)(nb * s.npatch), s.ns1, s.ns1, lr, op->st)))
+                return rc;
+        }
+        if (loss_host) loss_host[ep] = tot / (2.0 * (double)(n_pairs * n));
+    }
+    HIPCHK(hipStreamSynchronize(op->st));
+    return IGB_OK;
+}
+
+igb_status igb_cnn_training_pairs(const igb_operator *cop, const double *x_dev, int64_t n_pairs, float *y_dev,
+                                  float *x32_dev)
+{
+    CHECK_OP(cop);
+    if (!x_dev || !y_dev || !x32_dev) return fail(IGB_EINVAL, "null device pointer");
+    if (n_pairs < 0) return fail(IGB_EINVAL, "n_pairs must be >= 0");
+    igb_operator *op = const_cast<igb_operator *>(cop);
+    if (op->cplx) return fail(IGB_EUNSUPPORTED, "training pairs are built for real (Laplace) operators");
+    struct Restore {
+        igb_operator *o;
+        bool v;
+        ~Restore() { o->force_fp64 = v; }
+    } restore{op, op->force_fp64};
+    op->force_fp64 = true;
+    const int64_t n = op->s.ndof;
+    igb_status rc;
+    for (int64_t k = 0; k < n_pairs; ++k) {
+        if ((rc = matvec_S<double>(op, x_dev + k * n, (double *)op->tmp))) return rc;
+        hipLaunchKernelGGL(k_pairs_out, dim3(nblk(n, 256)), dim3(256), 0, op->st, n, (const double *)op->tmp,
+                           (const double *)op->diag, x_dev + k * n, y_dev + k * n, x32_dev + k * n);
+        LAUNCHCHK();
+    }
+    return IGB_OK;
 }
 
 template <class T>

@@ -37,7 +37,13 @@ EXPORTED = [
     "igb_export_partition", "igb_export_pair_classes", "igb_export_near_block", "igb_export_coupling_block",
     "igb_plan_create", "igb_plan_destroy", "igb_plan_info", "igb_plan_export_partition",
     "igb_plan_export_pair_classes", "igb_matvec_profile", "igb_release_cached_memory",
+    "igb_cnn_create", "igb_cnn_destroy", "igb_cnn_get_weights", "igb_cnn_forward", "igb_cnn_gradient",
+    "igb_cnn_training_pairs", "igb_cnn_train", "igb_cnn_train_operator", "igb_solve_fgmres",
 ]
+IGB_CNN_NUM_WEIGHTS = 28224
+IGB_CNN_RELU = 0
+IGB_CNN_LINEAR = 1
+CNN_LAYERS = [(1, 32), (32, 32), (32, 32), (32, 32), (32, 1)]  # (c_in, c_out) of each 3x3 convolution
 IGB_PROFILE_SEPARATE = 1
 STAGES = ["upward", "coupling", "coupling_gather", "near_gemv", "near_gather", "downward"]
 
@@ -72,7 +78,7 @@ def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"libigabem.so not built at {LIB_PATH}; run paper_1708_09162_amd/build.py")
     lib = C.CDLL(LIB_PATH)
-    vp, dp, ip = C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int32)
+    vp, dp, ip, fp = C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int32), C.POINTER(C.c_float)
     sig = {
         "igb_last_error": (C.c_char_p, []),
         "igb_geometry_create": (C.c_int32, [C.c_int32, C.POINTER(igb_nurbs_patch), C.POINTER(vp)]),
@@ -100,6 +106,17 @@ def _load():
         "igb_plan_export_partition": (C.c_int32, [vp, ip, ip]),
         "igb_plan_export_pair_classes": (C.c_int32, [vp, ip]),
         "igb_release_cached_memory": (C.c_int32, []),
+        "igb_cnn_create": (C.c_int32, [fp, C.c_int32, vp, C.POINTER(vp)]),
+        "igb_cnn_destroy": (None, [vp]),
+        "igb_cnn_get_weights": (C.c_int32, [vp, fp]),
+        "igb_cnn_forward": (C.c_int32, [vp, vp, C.c_int32, C.c_int32, C.c_int32, vp]),
+        "igb_cnn_gradient": (C.c_int32, [vp, vp, vp, C.c_int32, C.c_int32, C.c_int32, dp, fp]),
+        "igb_cnn_training_pairs": (C.c_int32, [vp, vp, C.c_int64, vp, vp]),
+        "igb_cnn_train": (C.c_int32, [vp, vp, vp, C.c_int64, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32,
+                                      C.c_float, dp]),
+        "igb_cnn_train_operator": (C.c_int32, [vp, vp, vp, vp, C.c_int64, C.c_int32, C.c_int32, C.c_float, dp]),
+        "igb_solve_fgmres": (C.c_int32, [vp, vp, vp, vp, C.c_double, C.c_int32, C.c_int32,
+                                         C.POINTER(igb_solve_info)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -208,6 +225,62 @@ def igb_solve(op, b, w, rel_tol, max_iter, restart) -> igb_solve_info:
     _check(_lib.igb_solve(op, _ptr(b), _ptr(w), float(rel_tol), int(max_iter), int(restart), C.byref(info)),
            allow=(IGB_OK, IGB_ENOT_CONVERGED))
     return info
+
+
+def igb_solve_fgmres(op, net, b, w, rel_tol, max_iter, restart) -> igb_solve_info:
+    info = igb_solve_info()
+    _check(_lib.igb_solve_fgmres(op, net, _ptr(b), _ptr(w), float(rel_tol), int(max_iter), int(restart),
+                                 C.byref(info)), allow=(IGB_OK, IGB_ENOT_CONVERGED))
+    return info
+
+
+def _fptr(a):
+    return a.ctypes.data_as(C.POINTER(C.c_float))
+
+
+def igb_cnn_create(weights, activation, stream) -> C.c_void_p:
+    w = np.ascontiguousarray(weights, dtype=np.float32).reshape(-1)
+    if w.size != IGB_CNN_NUM_WEIGHTS:
+        raise ValueError(f"expected {IGB_CNN_NUM_WEIGHTS} weights, got {w.size}")
+    h = C.c_void_p()
+    _check(_lib.igb_cnn_create(_fptr(w), int(activation), C.c_void_p(stream), C.byref(h)))
+    return h
+
+
+def igb_cnn_get_weights(net):
+    out = np.zeros(IGB_CNN_NUM_WEIGHTS, dtype=np.float32)
+    _check(_lib.igb_cnn_get_weights(net, _fptr(out)))
+    return out
+
+
+def igb_cnn_forward(net, x, n_img, h, w, out):
+    _check(_lib.igb_cnn_forward(net, _ptr(x), int(n_img), int(h), int(w), _ptr(out)))
+
+
+def igb_cnn_gradient(net, x, target, n_img, h, w):
+    loss = C.c_double()
+    grad = np.zeros(IGB_CNN_NUM_WEIGHTS, dtype=np.float32)
+    _check(_lib.igb_cnn_gradient(net, _ptr(x), _ptr(target), int(n_img), int(h), int(w), C.byref(loss),
+                                 _fptr(grad)))
+    return loss.value, grad
+
+
+def igb_cnn_training_pairs(op, x, n_pairs, y32, x32):
+    _check(_lib.igb_cnn_training_pairs(op, _ptr(x), int(n_pairs), _ptr(y32), _ptr(x32)))
+
+
+def igb_cnn_train(net, y32, x32, n_pairs, imgs_per_pair, h, w, epochs, batch, lr):
+    losses = np.zeros(max(int(epochs), 1), dtype=np.float64)
+    _check(_lib.igb_cnn_train(net, _ptr(y32), _ptr(x32), int(n_pairs), int(imgs_per_pair), int(h), int(w),
+                              int(epochs), int(batch), float(lr), losses.ctypes.data_as(C.POINTER(C.c_double))))
+    return losses[:int(epochs)]
+
+
+def igb_cnn_train_operator(net, op, y32, x32, n_pairs, epochs, batch, lr):
+    losses = np.zeros(max(int(epochs), 1), dtype=np.float64)
+    _check(_lib.igb_cnn_train_operator(net, op, _ptr(y32), _ptr(x32), int(n_pairs), int(epochs), int(batch),
+                                       float(lr), losses.ctypes.data_as(C.POINTER(C.c_double))))
+    return losses[:int(epochs)]
 
 
 def igb_potential(op, w, xyz, u):
@@ -340,7 +413,7 @@ class Operator:
         self.info = igb_operator_info(self.h)
         self.cplx = kernel == IGB_HELMHOLTZ
         self.dtype = torch.complex128 if self.cplx else torch.float64
-        self.p, self.q = p, q
+        self.p, self.q, self.m = p, q, m
 
     def __del__(self, _destroy=_lib.igb_operator_destroy):
         if getattr(self, "h", None):
@@ -396,6 +469,30 @@ class Operator:
         info = igb_solve(self.h, self._in(b, self.info.n_dof), w, tol, max_iter, restart)
         return w, info
 
+    def solve_fgmres(self, b, net=None, w0=None, tol=1e-8, max_iter=1000, restart=100):
+        """Flexible GMRES with the network preconditioner `net` (a CNN), or Jacobi when net is None."""
+        w = self._vec(self.info.n_dof) if w0 is None else self._in(w0, self.info.n_dof).clone()
+        info = igb_solve_fgmres(self.h, net.h if net is not None else None, self._in(b, self.info.n_dof), w, tol,
+                                max_iter, restart)
+        return w, info
+
+    @property
+    def grid(self):
+        """(patches, side): a vector of S is `patches` coefficient grids of side x side."""
+        side = (1 << self.m) + self.p
+        return self.info.n_dof // (side * side), side
+
+    def training_pairs(self, x):
+        """(D^-1 A x_s, x_s) in FP32 for the rows x_s of x (n_pairs x n_dof, FP64)."""
+        x = x.to(device=self.device, dtype=self.torch.float64).contiguous()
+        n_pairs = x.shape[0]
+        if x.numel() != n_pairs * self.info.n_dof:
+            raise ValueError("x must be n_pairs x n_dof")
+        y32 = self.torch.empty((n_pairs, self.info.n_dof), dtype=self.torch.float32, device=self.device)
+        x32 = self.torch.empty_like(y32)
+        igb_cnn_training_pairs(self.h, x, n_pairs, y32, x32)
+        return y32, x32
+
     def potential(self, w, points):
         pts = self.torch.as_tensor(points, dtype=self.torch.float64).to(self.device).reshape(-1, 3).contiguous()
         u = self._vec(pts.shape[0])
@@ -418,3 +515,49 @@ class Operator:
 
     def coupling_block(self, level, tgt, src):
         return igb_export_coupling_block(self.h, level, tgt, src, self.q * self.q, self.cplx)
+
+
+class CNN:
+    """The learned preconditioner's network on the current torch CUDA (HIP) stream."""
+
+    def __init__(self, weights, activation=IGB_CNN_RELU, device="cuda:0"):
+        import torch
+
+        self.torch = torch
+        self.device = torch.device(device)
+        self.activation = activation
+        with torch.cuda.device(self.device):
+            self.stream = torch.cuda.current_stream(self.device)
+            self.h = igb_cnn_create(weights, activation, self.stream.cuda_stream)
+
+    def __del__(self, _destroy=_lib.igb_cnn_destroy):
+        if getattr(self, "h", None):
+            _destroy(self.h)
+            self.h = None
+
+    def _f32(self, t):
+        return t.to(device=self.device, dtype=self.torch.float32).contiguous()
+
+    def weights(self):
+        return igb_cnn_get_weights(self.h)
+
+    def forward(self, x, n_img, h, w):
+        """x + f(x) for n_img images of h x w."""
+        x = self._f32(x)
+        out = self.torch.empty_like(x)
+        igb_cnn_forward(self.h, x, n_img, h, w, out)
+        return out
+
+    def gradient(self, x, target, n_img, h, w):
+        """(loss, gradient with respect to the weights) of one batch."""
+        return igb_cnn_gradient(self.h, self._f32(x), self._f32(target), n_img, h, w)
+
+    def train(self, y32, x32, imgs_per_pair, h, w, epochs=5, batch=16, lr=1e-3):
+        """Adam over the (y, x) pairs (rows of y32, x32); returns the mean loss of each epoch."""
+        y32, x32 = self._f32(y32), self._f32(x32)
+        return igb_cnn_train(self.h, y32, x32, y32.shape[0], imgs_per_pair, h, w, epochs, batch, lr)
+
+    def train_operator(self, op, y32, x32, epochs=5, batch=16, lr=1e-3):
+        """Adam on the preconditioned residual |D^-1 A (M(y) - x)|^2 of operator `op` over the pairs."""
+        y32, x32 = self._f32(y32), self._f32(x32)
+        return igb_cnn_train_operator(self.h, op.h, y32, x32, y32.shape[0], epochs, batch, lr)

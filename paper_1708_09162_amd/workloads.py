@@ -347,3 +347,35 @@ def config_torus_helmholtz() -> dict:
         "direction": d,
         "eval_points": grid,
     }
+
+
+def config_learned_preconditioner() -> dict:
+    """Laplace on the radially perturbed sphere (amplitude 0.1, spherical-harmonic degree <= 6,
+    seed 5), p=2, 128x128 elements per patch (m=7), q=8; 2000 training vectors x ~ N(0, 1)
+    (seed 5); right-hand side from 4 exterior point charges (seed 2)."""
+    return {
+        "name": "laplace_perturbed_sphere_p2_m7_q8",
+        "patches": perturbed_sphere_patches(0.1, 5),
+        "p": 2, "m": 7, "q": 8, "eta": 1.6, "gauss_regular": 6,
+        "n_pairs": 2000, "pair_seed": 5, "charges": (4, 2),
+    }
+
+
+CNN_LAYERS = [(1, 32), (32, 32), (32, 32), (32, 32), (32, 1)]
+
+
+def cnn_initial_weights(seed: int, last_scale: float = 0.0) -> np.ndarray:
+    """Seeded initial weights of the preconditioner network, layer after layer, each
+    [c_out][c_in][3][3] (FP32): normal with standard deviation sqrt(2 / (9 c_in)) for the
+    first four layers, last layer normal * last_scale (zero by default)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for l, (ci, co) in enumerate(CNN_LAYERS):
+        std = np.sqrt(2.0 / (9 * ci)) if l < len(CNN_LAYERS) - 1 else last_scale
+        out.append(rng.standard_normal(9 * ci * co) * std)
+    return np.concatenate(out).astype(np.float32)
+
+
+def training_vectors(n_pairs: int, n: int, seed: int) -> np.ndarray:
+    """n_pairs seeded standard normal coefficient vectors of length n (FP64)."""
+    return np.random.default_rng(seed).standard_normal((n_pairs, n))

@@ -84,13 +84,31 @@ def test_positive_homogeneity():
     assert np.allclose(out1, out2, rtol=1e-13, atol=1e-13)
 
 
-def test_gradient_matches_central_differences():
+def test_linear_network_superposition_and_composite_stencil():
+    """With the identity activation f is linear and equals one 11x11 correlation (the five 3x3
+    kernels composed), here checked on a single channel path against scipy."""
+    w = rand_weights(24)
+    rng = np.random.default_rng(25)
+    y1, y2 = rng.standard_normal((2, 1, 13, 12))
+    f = lambda y: cnn.forward(w, y, linear=True)[0] - y
+    assert np.allclose(f(2.0 * y1 - 0.5 * y2), 2.0 * f(y1) - 0.5 * f(y2), rtol=0, atol=1e-12)
+    # impulse response = the composite stencil; away from the edges f(y) = correlate2d(y, stencil)
+    e = np.zeros((1, 31, 31))
+    e[0, 15, 15] = 1.0
+    stencil = f(e)[0, 10:21, 10:21][::-1, ::-1]
+    big = rng.standard_normal((1, 40, 40))
+    ref = correlate2d(big[0], stencil, mode="same")
+    assert np.allclose(f(big)[0, 5:-5, 5:-5], ref[5:-5, 5:-5], rtol=0, atol=1e-11)
+
+
+@pytest.mark.parametrize("linear", [False, True])
+def test_gradient_matches_central_differences(linear):
     w = rand_weights(9, scale=0.6)
     rng = np.random.default_rng(10)
     y = rng.standard_normal((2, 5, 6))
     x = rng.standard_normal((2, 5, 6))
-    loss, g = cnn.loss_grad(w, y, x)
-    assert loss == pytest.approx(np.sum((cnn.forward(w, y)[0] - x) ** 2) / (2 * x.size), rel=1e-14)
+    loss, g = cnn.loss_grad(w, y, x, linear)
+    assert loss == pytest.approx(np.sum((cnn.forward(w, y, linear)[0] - x) ** 2) / (2 * x.size), rel=1e-14)
     offs = np.cumsum([0] + [9 * ci * co for ci, co in cnn.LAYERS])
     idx = np.concatenate([rng.choice(np.arange(offs[l], offs[l + 1]), 8, replace=False) for l in range(5)])
     h = 1e-6
@@ -98,5 +116,5 @@ def test_gradient_matches_central_differences():
         wp, wm = w.copy(), w.copy()
         wp[i] += h
         wm[i] -= h
-        fd = (cnn.loss_grad(wp, y, x)[0] - cnn.loss_grad(wm, y, x)[0]) / (2 * h)
+        fd = (cnn.loss_grad(wp, y, x, linear)[0] - cnn.loss_grad(wm, y, x, linear)[0]) / (2 * h)
         assert abs(fd - g[i]) <= 1e-6 * max(abs(g[i]), 1e-3 * np.abs(g).max()), (i, fd, g[i])

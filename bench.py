@@ -4,7 +4,7 @@
 Workload (the metric's configuration): interior Laplace Dirichlet problem on the unit sphere given
 as 6 exact rational NURBS patches, spline degree p=3, 32x32 elements per patch (m=5; dim S = 7,350,
 dim S* = 98,304), H2 compression with q=8 Chebyshev nodes per parametric direction and eta=1.6,
-Gauss order 6; Dirichlet data from 4 seeded exterior point charges; Jacobi-preconditioned CG to
+Gauss order 6; Dirichlet data from 4 seeded exterior point charges; Jacobi-preconditioned GMRES(100) to
 true relative residual 1e-8; potential at 100 seeded interior points.
 
 One step = operator assembly (Bezier extraction, partition, near-field quadrature, coupling blocks,
@@ -98,8 +98,12 @@ def charge_field(torch, pts, pos, q):
     return g
 
 
-def one_step(torch, igb, geo, cfg, ev_dev, mode, far_precision=0):
-    """The whole path once; returns (operator, density, solve info, potential, timings)."""
+RESTART = 100
+
+
+def one_step(torch, igb, geo, cfg, ev_dev, mode, far_precision=0, solver="gmres"):
+    """The whole path once; returns (operator, density, solve info, potential, timings).  solver "gmres":
+    Jacobi-preconditioned GMRES(100) (igb_solve_fgmres without a network); "cg": Jacobi CG (igb_solve)."""
     t = {}
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -110,7 +114,10 @@ def one_step(torch, igb, geo, cfg, ev_dev, mode, far_precision=0):
     b = op.rhs(charge_field(torch, pts, *cfg["charges"]))
     torch.cuda.synchronize()
     t2 = time.perf_counter()
-    w, info = op.solve(b, tol=TOL, max_iter=20000)
+    if solver == "gmres":
+        w, info = op.solve_fgmres(b, None, tol=TOL, max_iter=20000, restart=RESTART)
+    else:
+        w, info = op.solve(b, tol=TOL, max_iter=20000)
     torch.cuda.synchronize()
     t3 = time.perf_counter()
     u = op.potential(w, ev_dev)
@@ -121,23 +128,32 @@ def one_step(torch, igb, geo, cfg, ev_dev, mode, far_precision=0):
 
 
 def mixed_leg(torch, igb, geo, cfg, ev_dev, fp64_ms, exact, steps: int = 2):
-    """The same step with the single-precision far field (far_precision IGB_FP32) and the solve refined to
-    the FP64 tolerance with FP64 residuals: time-to-solve beside the plain FP64 one."""
-    op, w, info, u, t = one_step(torch, igb, geo, cfg, ev_dev, "onthefly", igb.IGB_FP32)  # warmup
+    """The same step with the single-precision far field (far_precision IGB_FP32) and CG refined to the FP64
+    tolerance with FP64 residuals: time-to-solve beside the plain FP64 CG step and the headline step."""
+    def timed(fp, solver):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            res = one_step(torch, igb, geo, cfg, ev_dev, "onthefly", fp, solver)
+            if _ + 1 < steps:
+                del res
+        torch.cuda.synchronize()
+        return 1e3 * (time.perf_counter() - t0) / steps, res
+
+    one_step(torch, igb, geo, cfg, ev_dev, "onthefly", 0, "cg")  # warmup
+    cg_ms, (op, w, info_cg, u, t) = timed(0, "cg")
     del op
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        op, w, info, u, t = one_step(torch, igb, geo, cfg, ev_dev, "onthefly", igb.IGB_FP32)
-        if _ + 1 < steps:
-            del op
-    torch.cuda.synchronize()
-    ms = 1e3 * (time.perf_counter() - t0) / steps
+    op, w, info, u, t = one_step(torch, igb, geo, cfg, ev_dev, "onthefly", igb.IGB_FP32, "cg")  # warmup
+    del op
+    ms, (op, w, info, u, t) = timed(igb.IGB_FP32, "cg")
     st = op.profile(reps=20)
     print(f"[bench] single-precision far field: {ms / 1e3:.4f} s per step, {info.iterations} it", file=sys.stderr,
           flush=True)
     return {"far_precision": "fp32 (kernel values from the hardware reciprocal square root, FP64 sums)",
-            "value": round(ms / 1e3, 5), "ms_per_step": round(ms, 3), "vs_fp64": round(ms / fp64_ms, 4),
+            "solver": "jacobi_cg_reliable_updates",
+            "value": round(ms / 1e3, 5), "ms_per_step": round(ms, 3), "vs_fp64_cg": round(ms / cg_ms, 4),
+            "fp64_cg_ms_per_step": round(cg_ms, 3), "fp64_cg_iterations": int(info_cg.iterations),
+            "vs_fp64": round(ms / fp64_ms, 4),
             "iterations": int(info.iterations), "rel_residual": float(info.rel_residual),
             "potential_max_err": float(np.abs(u.cpu().numpy() - exact).max()),
             "breakdown_s": {k: round(v, 4) for k, v in t.items()},
@@ -237,7 +253,7 @@ def cpu_baseline(cfg, iterations: int, seed: int = 7):
     value = t_asm + (iterations + 2) * t_far
     return {"value": value, "unit": "s", "cores": threads, "kind": "oracle",
             "sample": "projected from a timed random sample of the full workload: " + ", ".join(parts)
-                      + f"; time = near quadrature + (CG iterations + 2) x coupling evaluation per matvec",
+                      + f"; time = near quadrature + (solver iterations + 2) x coupling evaluation per matvec",
             "assembly_s": t_asm, "matvec_s": t_far}
 
 
@@ -362,12 +378,12 @@ def main():
                     "algorithmic_flops": int(flops), "kernel_evaluations": int(evals),
                     "block_entries_applied": int(len(far) * q2 * q2), "flop_per_evaluation": fpe,
                     "avg_ms": round(ms, 4)}
-        kfar = f"k_far_sym<double, {tt}>" if sym else "k_far_onthefly<double>"
+        kfar = f"k_far_sym<double, {tt}, false>" if sym else "k_far_onthefly<double>"
         roofs["far_field"] = alu_roof(kfar, sep["coupling"], read_traffic("coupling") if sym else None)
         roofs["far_field"]["launched_alone"] = True
         if fused:
             # as launched in the solver: the near blocks ride along with the far-field pairs
-            roofs["coupling"] = alu_roof(f"k_sym_products<double, {tt}>", stages["coupling"],
+            roofs["coupling"] = alu_roof(f"k_sym_products<double, {tt}, false>", stages["coupling"],
                                          read_traffic("coupling_fused"))
             roofs["coupling"]["hbm_bytes_alongside"] = int(near_bytes)
             roofs["coupling"]["hbm_GBps_alongside"] = round(near_bytes / (stages["coupling"] * 1e-3) / 1e9, 1)
@@ -393,7 +409,8 @@ def main():
         "config": {"workload": WORKLOAD, "geometry": "unit sphere, 6 rational NURBS patches of bidegree 4",
                    "kernel": "laplace", "p": PRM["p"], "m": PRM["m"], "q": PRM["q"], "eta": PRM["eta"],
                    "gauss_regular": PRM["gauss_regular"], "n_dof": int(op.info.n_dof),
-                   "n_dof_super": int(op.info.n_dof_super), "rel_tol": TOL, "mode": "h2_" + args.mode},
+                   "n_dof_super": int(op.info.n_dof_super), "rel_tol": TOL, "mode": "h2_" + args.mode,
+                   "solver": f"jacobi_gmres_{RESTART}"},
         "h2_matvec_GBps": round(gbps, 1),
         "h2_matvec_ms": round(mv_ms, 4),
         "matvec_bytes": int(op.info.matvec_bytes),

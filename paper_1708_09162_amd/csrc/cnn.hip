@@ -195,13 +195,24 @@ __global__ void __launch_bounds__(256) k_wgrad3(const float *__restrict__ in, co
     }
 }
 
-__global__ void k_wreduce(int nblk, int cnt, const float *__restrict__ part, float *__restrict__ g)
+// g[i] = sum over blocks b of part[b][i] in a fixed order: 32 weights per workgroup, 8 groups of
+// threads summing the partials b = grp, grp + 8, ..., then the 8 group sums added in order.
+__global__ void __launch_bounds__(256) k_wreduce(int nblk, int cnt, const float *__restrict__ part,
+                                                 float *__restrict__ g)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= cnt) return;
+    __shared__ float red[8][32];
+    const int lane = threadIdx.x % 32, grp = threadIdx.x / 32;
+    const int i = blockIdx.x * 32 + lane;
     float s = 0.f;
-    for (int b = 0; b < nblk; ++b) s += part[(size_t)b * cnt + i];
-    g[i] = s;
+    if (i < cnt)
+        for (int b = grp; b < nblk; b += 8) s += part[(size_t)b * cnt + i];
+    red[grp][lane] = s;
+    __syncthreads();
+    if (grp == 0 && i < cnt) {
+        float t = red[0][lane];
+        for (int k = 1; k < 8; ++k) t += red[k][lane];
+        g[i] = t;
+    }
 }
 
 // d = y + f - x; dout = d * scale; per-block partial sums of d^2 (FP64).
@@ -351,7 +362,7 @@ igb_status wgrad(igb_cnn *net, int layer, const float *in, const float *dz, int 
                        tx, tpi, nt);
     CNNLAUNCH();
     const int cnt = 9 * CIN * COUT;
-    hipLaunchKernelGGL(k_wreduce, dim3(nblk(cnt, 256)), dim3(256), 0, net->st, nb, cnt, (const float *)net->part,
+    hipLaunchKernelGGL(k_wreduce, dim3(nblk(cnt, 32)), dim3(256), 0, net->st, nb, cnt, (const float *)net->part,
                        net->g + net->dims.off[layer]);
     CNNLAUNCH();
     return IGB_OK;

@@ -2319,25 +2319,88 @@ __global__ void k_div<cd>(int64_t n, const cd *__restrict__ x, const cd *__restr
     }
 }
 
-// GMRES: h[j] = <v_j, w> for j < k (classical Gram-Schmidt pass), partial per block
+// GMRES: h[j] = <v_j, w> for j < k (classical Gram-Schmidt pass), partial per
+// block: block (b, c) takes rows b*256 + u + m*nblk*256 (u < 256), its wave q
+// the vectors j = 4c + q, 4c + q + 4 gridDim.y, ..., reduced with cross-lane
+// shuffles, so no barrier is needed; part[j*nblk + b].
+__device__ inline double wave_sum64(double s)
+{
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+    return s;
+}
+__device__ inline cd wave_sum64(cd s) { return {wave_sum64(s.re), wave_sum64(s.im)}; }
+
 template <class T>
 __global__ void __launch_bounds__(256) k_multidot_partial(int64_t n, int k, const T *__restrict__ V, int64_t ldv,
                                                           const T *__restrict__ w, T *__restrict__ part, int nblk)
 {
-    __shared__ T red[256];
-    for (int j = 0; j < k; ++j) {
-        T s = zero<T>();
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t stride = (int64_t)nblk * 256;
+    T wl[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        const int64_t i = (int64_t)blockIdx.x * 256 + lane + 64 * t;
+        wl[t] = i < n ? w[i] : zero<T>();
+    }
+    for (int j = (int)blockIdx.y * 4 + wave; j < k; j += 4 * (int)gridDim.y) {
         const T *v = V + (int64_t)j * ldv;
-        for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-            s += conj_(v[i]) * w[i];
-        red[threadIdx.x] = s;
-        __syncthreads();
-        for (int q = blockDim.x / 2; q > 0; q >>= 1) {
-            if ((int)threadIdx.x < q) red[threadIdx.x] += red[threadIdx.x + q];
-            __syncthreads();
+        T s = zero<T>();
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const int64_t i = (int64_t)blockIdx.x * 256 + lane + 64 * t;
+            if (i < n) s += conj_(v[i]) * wl[t];
         }
-        if (threadIdx.x == 0) part[(int64_t)j * nblk + blockIdx.x] = red[0];
+        for (int64_t r0 = (int64_t)blockIdx.x * 256 + stride; r0 < n; r0 += stride)
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const int64_t i = r0 + lane + 64 * t;
+                if (i < n) s += conj_(v[i]) * w[i];
+            }
+        s = wave_sum64(s);
+        if (lane == 0) part[(int64_t)j * nblk + blockIdx.x] = s;
+    }
+}
+
+static int multidot_blocks(int64_t n) { return (int)std::min<int64_t>(64, (n + 255) / 256); }
+
+// w -= V h for the first k columns, with h[j] = sum_b part[j*nblk + b] (b in
+// order) formed by every block in LDS (block 0 also stores h to hout); with
+// nrm, each block also writes its partial sum of |w_new|^2 to nrm[block].
+template <class T>
+__global__ void __launch_bounds__(256) k_sub_Vh_red(int64_t n, int k, const T *__restrict__ V, int64_t ldv,
+                                                    const T *__restrict__ part, int nblk, T *__restrict__ hout,
+                                                    T *__restrict__ w, double *__restrict__ nrm)
+{
+    extern __shared__ double shd[];
+    __shared__ double wred[4];
+    T *h = (T *)shd;
+    for (int j = threadIdx.x; j < k; j += blockDim.x) {
+        T s = zero<T>();
+        for (int b = 0; b < nblk; ++b) s += part[(int64_t)j * nblk + b];
+        h[j] = s;
+        if (blockIdx.x == 0) hout[j] = s;
+    }
+    __syncthreads();
+    double acc = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        T s = w[i];
+        int j = 0;
+        for (; j + 8 <= k; j += 8) {  // eight independent loads in flight
+            T v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) v[u] = V[(int64_t)(j + u) * ldv + i];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) s -= h[j + u] * v[u];
+        }
+        for (; j < k; ++j) s -= h[j] * V[(int64_t)j * ldv + i];
+        w[i] = s;
+        acc += abs2(s);
+    }
+    if (nrm) {
+        acc = wave_sum64(acc);
+        if ((threadIdx.x & 63) == 0) wred[threadIdx.x >> 6] = acc;
         __syncthreads();
+        if (threadIdx.x == 0) nrm[blockIdx.x] = (wred[0] + wred[1]) + (wred[2] + wred[3]);
     }
 }
 
@@ -2531,6 +2594,7 @@ struct igb_operator {
     std::vector<DevBlock> owned;
     DevBlock Vblk{}, hblk{}, mblk{};  // GMRES basis, projections, multi-dot partials
     DevBlock Zblk{};                  // flexible GMRES: preconditioned directions
+    DevBlock Gblk{};                  // flexible GMRES: Hessenberg matrix, rotations, state
     int Zcols = 0;
     // far_precision IGB_FP32: products use single-precision far-field kernel values;
     // force_fp64 is set while the solver forms its double-precision residuals
@@ -3459,6 +3523,7 @@ static igb_status solve_gmres(igb_operator *op, const cd *b, cd *w, double tol, 
         op->Vcols = R + 1;
     }
     cd *V = (cd *)op->V, *hd = (cd *)op->hdev, *t = (cd *)op->tmp, *r = (cd *)op->r, *t2 = (cd *)op->z;
+    const int mdb = multidot_blocks(n);
     const cd *D = (const cd *)op->diag;
     unsigned gb = std::min<unsigned>(nblk(n, 256), 1024);
     auto norm2 = [&](const cd *x, double *out) -> igb_status {
@@ -3496,10 +3561,10 @@ static igb_status solve_gmres(igb_operator *op, const cd *b, cd *w, double tol, 
             if ((rc = matvec_S<cd>(op, t, vn))) return rc;
             std::fill(hcol.begin(), hcol.end(), cd{0.0, 0.0});
             for (int pass = 0; pass < 2; ++pass) {  // classical Gram-Schmidt, twice
-                hipLaunchKernelGGL((k_multidot_partial<cd>), dim3(kRedBlocks), dim3(256), 0, op->st, n, k + 1, V, n, vn,
-                                   (cd *)op->mpart, kRedBlocks);
+                hipLaunchKernelGGL((k_multidot_partial<cd>), dim3(mdb), dim3(256), 0, op->st, n, k + 1, V, n, vn,
+                                   (cd *)op->mpart, mdb);
                 LAUNCHCHK();
-                hipLaunchKernelGGL((k_multireduce<cd>), dim3(k + 1), dim3(256), 0, op->st, k + 1, kRedBlocks,
+                hipLaunchKernelGGL((k_multireduce<cd>), dim3(k + 1), dim3(256), 0, op->st, k + 1, mdb,
                                    (const cd *)op->mpart, hd);
                 LAUNCHCHK();
                 hipLaunchKernelGGL((k_sub_Vh<cd>), dim3(gb), dim3(256), 0, op->st, n, k + 1, V, n, hd, vn);
@@ -3564,10 +3629,66 @@ static igb_status solve_gmres(igb_operator *op, const cd *b, cd *w, double tol, 
     return rel <= tol ? IGB_OK : fail(IGB_ENOT_CONVERGED, "GMRES stopped at max_iter with relative residual " + std::to_string(rel));
 }
 
-// Flexible GMRES (Saad's right-preconditioned variant that keeps the
-// preconditioned directions z_k, since a network is not a fixed linear map),
-// classical Gram-Schmidt applied twice, Givens rotations on the host.  The
-// operator runs in FP64 throughout.
+// One Arnoldi step's bookkeeping of flexible GMRES, on the device (one thread):
+// the new Hessenberg column h = hA + hB (two classical Gram-Schmidt passes) with
+// h[k+1] = |v_{k+1}| (from the nvv partial sums of its squared norm), the earlier Givens rotations
+// applied to it, a new rotation that zeroes h[k+1], the rotated right-hand side
+// g, and the residual estimate |g[k+1]| / |b|.  G holds H ((R+1) x R, row j,
+// column k at j*R + k), cs, sn (R each), g (R+1) and the state st: |b|, 1/|v_{k+1}|,
+// the first step count that reached tol (or -1), tol.  The estimate and a
+// converged flag go to the host-mapped pair `out`.  Steps after convergence
+// leave G as it is.
+__global__ void k_arnoldi(int k, int R, const double *__restrict__ hA, const double *__restrict__ hB,
+                          const double *__restrict__ vv, int nvv, double *__restrict__ G, double *__restrict__ out)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double *H = G, *cs = G + (size_t)(R + 1) * R, *sn = cs + R, *g = sn + R, *st = g + R + 1;
+    if (st[2] >= 0.0) {
+        out[0] = 0.0;
+        out[1] = 1.0;
+        return;
+    }
+    for (int j = 0; j <= k; ++j) H[(size_t)j * R + k] = hA[j] + hB[j];
+    double v2 = 0.0;
+    for (int b = 0; b < nvv; ++b) v2 += vv[b];
+    const double hn = sqrt(v2);
+    st[1] = hn > 0.0 ? 1.0 / hn : 0.0;
+    for (int j = 0; j < k; ++j) {
+        const double a = H[(size_t)j * R + k], b = H[(size_t)(j + 1) * R + k];
+        H[(size_t)j * R + k] = cs[j] * a + sn[j] * b;
+        H[(size_t)(j + 1) * R + k] = -sn[j] * a + cs[j] * b;
+    }
+    const double a = H[(size_t)k * R + k], den = hypot(a, hn);
+    cs[k] = den > 0.0 ? a / den : 1.0;
+    sn[k] = den > 0.0 ? hn / den : 0.0;
+    H[(size_t)k * R + k] = den;
+    g[k + 1] = -sn[k] * g[k];
+    g[k] = cs[k] * g[k];
+    const double res = fabs(g[k + 1]) / st[0];
+    const bool conv = res <= st[3];
+    if (conv) st[2] = k + 1;
+    out[0] = res;
+    out[1] = conv ? 1.0 : 0.0;
+}
+
+// x *= *alpha (alpha on the device); with D, also z = x / D (the next Jacobi direction)
+__global__ void k_scale_dev(int64_t n, const double *__restrict__ alpha, double *__restrict__ x,
+                            const double *__restrict__ D, double *__restrict__ z)
+{
+    const double a = *alpha;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const double v = x[i] * a;
+        x[i] = v;
+        if (z) z[i] = v / D[i];
+    }
+}
+
+// Flexible GMRES (right preconditioned; the preconditioned directions z_k are
+// kept, since a network is not a fixed linear map), classical Gram-Schmidt
+// applied twice, Givens rotations on the device.  The host keeps at most two
+// steps in flight and reads each step's residual estimate from mapped memory,
+// so the device never waits for it; the small triangular solve runs on the host
+// once per restart cycle.  The operator runs in FP64 throughout.
 static igb_status solve_fgmres(igb_operator *op, const igb_cnn *net, const double *b, double *w, double tol, int maxit,
                                int restart, igb_solve_info *info)
 {
@@ -3581,17 +3702,20 @@ static igb_status solve_fgmres(igb_operator *op, const igb_cnn *net, const doubl
         ~Restore() { o->force_fp64 = v; }
     } restore{op, op->force_fp64};
     op->force_fp64 = true;
+    const size_t gsz = (size_t)(R + 1) * R + 3 * (size_t)R + 1 + 8;
     if (op->Vcols < R + 1 || op->Zcols < R) {
         HIPCHK(hipStreamSynchronize(op->st));
         pool_free(op->Vblk);
         pool_free(op->Zblk);
+        pool_free(op->Gblk);
         pool_free(op->hblk);
         pool_free(op->mblk);
         op->V = op->hdev = op->mpart = nullptr;
         op->Vcols = op->Zcols = 0;
         HIPCHK(pool_alloc(op->Vblk, (size_t)(R + 1) * n * sizeof(double)));
         HIPCHK(pool_alloc(op->Zblk, (size_t)R * n * sizeof(double)));
-        HIPCHK(pool_alloc(op->hblk, (size_t)(R + 1) * sizeof(double)));
+        HIPCHK(pool_alloc(op->Gblk, gsz * sizeof(double)));
+        HIPCHK(pool_alloc(op->hblk, 2 * (size_t)(R + 1) * sizeof(double)));
         HIPCHK(pool_alloc(op->mblk, (size_t)(R + 1) * kRedBlocks * sizeof(double)));
         op->V = op->Vblk.p;
         op->hdev = op->hblk.p;
@@ -3599,10 +3723,16 @@ static igb_status solve_fgmres(igb_operator *op, const igb_cnn *net, const doubl
         op->Vcols = R + 1;
         op->Zcols = R;
     }
-    double *V = (double *)op->V, *Z = (double *)op->Zblk.p, *hd = (double *)op->hdev, *t = (double *)op->tmp,
+    double *V = (double *)op->V, *Z = (double *)op->Zblk.p, *G = (double *)op->Gblk.p, *t = (double *)op->tmp,
            *r = (double *)op->r;
+    double *hA = (double *)op->hdev, *hB = hA + R + 1, *st = G + (size_t)(R + 1) * R + 2 * (size_t)R + R + 1;
     const double *D = (const double *)op->diag;
     const unsigned gb = std::min<unsigned>(nblk(n, 256), 1024);
+    const int mdb = multidot_blocks(n);
+    const unsigned gsub = std::min<unsigned>(nblk(n, 256), 256);  // k_sub_Vh_red blocks (norm partials)
+    double *nrm = (double *)op->part;                             // kRedBlocks >= gsub doubles
+    double *hout = nullptr;  // two (estimate, converged) slots of mapped host memory, device view
+    HIPCHK(hipHostGetDevicePointer((void **)&hout, op->h_scal + 12, 0));
     auto norm2 = [&](const double *x, double *out) -> igb_status {
         igb_status c;
         if ((c = dot_dev<double>(op, n, x, x, op->scal))) return c;
@@ -3612,7 +3742,17 @@ static igb_status solve_fgmres(igb_operator *op, const igb_cnn *net, const doubl
     if ((rc = norm2(b, &bn2))) return rc;
     double bn = std::sqrt(bn2);
     if (bn == 0.0) bn = 1.0;
-    std::vector<double> H((size_t)(R + 1) * R), cs(R), sn(R), g(R + 1), y(R), hcol(R + 1), hh(R + 1);
+    std::vector<double> H((size_t)(R + 1) * R), gh(R + 1), y(R), init(2 * (size_t)R + 2 + 8, 0.0);
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    if (hipEventCreateWithFlags(&ev[0], hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&ev[1], hipEventDisableTiming) != hipSuccess) {
+        if (ev[0]) (void)hipEventDestroy(ev[0]);
+        return fail(IGB_EHIP, "hipEventCreate");
+    }
+    struct Events {
+        hipEvent_t *e;
+        ~Events() { (void)hipEventDestroy(e[0]); (void)hipEventDestroy(e[1]); }
+    } events{ev};
     int it = 0;
     double rel = 0.0;
     for (;;) {
@@ -3627,70 +3767,77 @@ static igb_status solve_fgmres(igb_operator *op, const igb_cnn *net, const doubl
         if (rel <= tol || it >= maxit) break;
         hipLaunchKernelGGL((k_axpby<double>), dim3(gb), dim3(256), 0, op->st, n, 1.0 / beta, (const double *)r, 0.0, V);
         LAUNCHCHK();
-        std::fill(g.begin(), g.end(), 0.0);
-        std::fill(H.begin(), H.end(), 0.0);
-        g[0] = beta;
-        int k = 0;
-        for (; k < R && it < maxit;) {
-            double *vk = V + (size_t)k * n, *vn = V + (size_t)(k + 1) * n, *zk = Z + (size_t)k * n;
-            if (net) {
-                if ((rc = cnn_precondition(net, s.npatch, s.ns1, s.ns1, vk, D, zk, op->st))) return rc;
-            } else {
-                hipLaunchKernelGGL((k_div<double>), dim3(gb), dim3(256), 0, op->st, n, (const double *)vk, D, zk);
-                LAUNCHCHK();
+        // g = (beta, 0, ...), state = (|b|, -, not converged, tol); the stream is idle here
+        std::fill(init.begin(), init.end(), 0.0);
+        init[0] = beta;
+        double *sti = init.data() + R + 1;
+        sti[0] = bn;
+        sti[2] = -1.0;
+        sti[3] = tol;
+        HIPCHK(hipMemcpyAsync(G + (size_t)(R + 1) * R + 2 * (size_t)R, init.data(), (R + 1 + 8) * sizeof(double),
+                              hipMemcpyHostToDevice, op->st));
+        const int kmax = std::min(R, maxit - it);
+        int launched = 0, examined = 0, kuse = -1;
+        rc = IGB_OK;
+        while (true) {
+            if (launched < kmax && launched - examined < 2) {
+                const int k = launched;
+                double *vk = V + (size_t)k * n, *vn = V + (size_t)(k + 1) * n, *zk = Z + (size_t)k * n;
+                if (net) {
+                    if ((rc = cnn_precondition(net, s.npatch, s.ns1, s.ns1, vk, D, zk, op->st))) break;
+                } else if (k == 0) {
+                    hipLaunchKernelGGL((k_div<double>), dim3(gb), dim3(256), 0, op->st, n, (const double *)vk, D, zk);
+                }  // else z_k = D^-1 v_k was formed when v_k was normalised
+                if ((rc = matvec_S<double>(op, zk, vn))) break;
+                for (int pass = 0; pass < 2; ++pass) {
+                    double *hp = pass ? hB : hA;
+                    hipLaunchKernelGGL((k_multidot_partial<double>), dim3(mdb, (unsigned)((k + 4) / 4)), dim3(256), 0,
+                                       op->st, n, k + 1, (const double *)V, n, (const double *)vn, (double *)op->mpart,
+                                       mdb);
+                    hipLaunchKernelGGL((k_sub_Vh_red<double>), dim3(gsub), dim3(256), (size_t)(k + 1) * sizeof(double),
+                                       op->st, n, k + 1, (const double *)V, n, (const double *)op->mpart, mdb, hp, vn,
+                                       pass ? nrm : (double *)nullptr);
+                }
+                hipLaunchKernelGGL(k_arnoldi, dim3(1), dim3(64), 0, op->st, k, R, (const double *)hA,
+                                   (const double *)hB, (const double *)nrm, (int)gsub, G, hout + 2 * (k & 1));
+                double *znext = (!net && k + 1 < kmax) ? Z + (size_t)(k + 1) * n : nullptr;
+                hipLaunchKernelGGL(k_scale_dev, dim3(gb), dim3(256), 0, op->st, n, (const double *)(st + 1), vn, D, znext);
+                if (hipGetLastError() != hipSuccess || hipEventRecord(ev[k & 1], op->st) != hipSuccess) {
+                    rc = fail(IGB_EHIP, "FGMRES kernel launch");
+                    break;
+                }
+                ++launched;
+                continue;
             }
-            if ((rc = matvec_S<double>(op, zk, vn))) return rc;
-            std::fill(hcol.begin(), hcol.end(), 0.0);
-            for (int pass = 0; pass < 2; ++pass) {
-                hipLaunchKernelGGL((k_multidot_partial<double>), dim3(kRedBlocks), dim3(256), 0, op->st, n, k + 1,
-                                   (const double *)V, n, (const double *)vn, (double *)op->mpart, kRedBlocks);
-                LAUNCHCHK();
-                hipLaunchKernelGGL((k_multireduce<double>), dim3(k + 1), dim3(256), 0, op->st, k + 1, kRedBlocks,
-                                   (const double *)op->mpart, hd);
-                LAUNCHCHK();
-                hipLaunchKernelGGL((k_sub_Vh<double>), dim3(gb), dim3(256), 0, op->st, n, k + 1, (const double *)V, n,
-                                   (const double *)hd, vn);
-                LAUNCHCHK();
-                HIPCHK(hipMemcpyAsync(hh.data(), hd, (k + 1) * sizeof(double), hipMemcpyDeviceToHost, op->st));
-                HIPCHK(hipStreamSynchronize(op->st));
-                for (int j = 0; j <= k; ++j) hcol[j] += hh[j];
+            if (examined == launched) break;
+            if (hipEventSynchronize(ev[examined & 1]) != hipSuccess) {
+                rc = fail(IGB_EHIP, "hipEventSynchronize");
+                break;
             }
-            double hn2;
-            if ((rc = norm2(vn, &hn2))) return rc;
-            const double hn = std::sqrt(hn2);
-            hcol[k + 1] = hn;
-            if (hn > 0.0) {
-                hipLaunchKernelGGL((k_axpby<double>), dim3(gb), dim3(256), 0, op->st, n, 1.0 / hn, (const double *)vn,
-                                   0.0, vn);
-                LAUNCHCHK();
+            const double *h = op->h_scal + 12 + 2 * (examined & 1);
+            ++examined;
+            if (h[1] != 0.0) {
+                kuse = examined;
+                break;
             }
-            for (int j = 0; j < k; ++j) {
-                const double a = hcol[j], bb = hcol[j + 1];
-                hcol[j] = cs[j] * a + sn[j] * bb;
-                hcol[j + 1] = -sn[j] * a + cs[j] * bb;
-            }
-            const double a = hcol[k], bb = hcol[k + 1], den = std::hypot(a, bb);
-            cs[k] = a / den;
-            sn[k] = bb / den;
-            hcol[k] = den;
-            hcol[k + 1] = 0.0;
-            g[k + 1] = -sn[k] * g[k];
-            g[k] = cs[k] * g[k];
-            for (int j = 0; j <= k; ++j) H[(size_t)j * R + k] = hcol[j];
-            ++k;
-            ++it;
-            if (std::fabs(g[k]) / bn <= tol) break;
         }
+        HIPCHK(hipStreamSynchronize(op->st));
+        if (rc) return rc;
+        const int k = kuse > 0 ? kuse : examined;
+        it += k;
         // y = H^-1 g (upper triangular k x k); w += Z y
+        HIPCHK(hipMemcpy(H.data(), G, (size_t)k * R * sizeof(double), hipMemcpyDeviceToHost));
+        HIPCHK(hipMemcpy(gh.data(), G + (size_t)(R + 1) * R + 2 * (size_t)R, (R + 1) * sizeof(double),
+                         hipMemcpyDeviceToHost));
         for (int j = k - 1; j >= 0; --j) {
-            double sum = g[j];
+            double sum = gh[j];
             for (int l = j + 1; l < k; ++l) sum -= H[(size_t)j * R + l] * y[l];
             y[j] = sum / H[(size_t)j * R + j];
         }
-        for (int j = 0; j < k; ++j) hh[j] = -y[j];
-        HIPCHK(hipMemcpyAsync(hd, hh.data(), k * sizeof(double), hipMemcpyHostToDevice, op->st));
+        for (int j = 0; j < k; ++j) y[j] = -y[j];
+        HIPCHK(hipMemcpyAsync(hA, y.data(), k * sizeof(double), hipMemcpyHostToDevice, op->st));
         hipLaunchKernelGGL((k_sub_Vh<double>), dim3(gb), dim3(256), 0, op->st, n, k, (const double *)Z, n,
-                           (const double *)hd, w);
+                           (const double *)hA, w);
         LAUNCHCHK();
         HIPCHK(hipStreamSynchronize(op->st));
     }
@@ -3762,12 +3909,14 @@ void igb_operator_destroy(igb_operator *op)
         for (DevBlock &b : op->owned) pool_free(b);
         pool_free(op->Vblk);
         pool_free(op->Zblk);
+        pool_free(op->Gblk);
         pool_free(op->hblk);
         pool_free(op->mblk);
     } else {
         for (DevBlock &b : op->owned) (void)hipFree(b.p);
         (void)hipFree(op->Vblk.p);
         (void)hipFree(op->Zblk.p);
+        (void)hipFree(op->Gblk.p);
         (void)hipFree(op->hblk.p);
         (void)hipFree(op->mblk.p);
     }
@@ -3978,7 +4127,7 @@ igb_status igb_solve_fgmres(const igb_operator *cop, const igb_cnn *net, const v
     if (!b_dev || !w_dev) return fail(IGB_EINVAL, "null device pointer");
     if (b_dev == w_dev) return fail(IGB_EINVAL, "b and w must not alias");
     if (!(rel_tol > 0.0) || max_iter < 0) return fail(IGB_EINVAL, "rel_tol must be > 0 and max_iter >= 0");
-    if (restart < 1) return fail(IGB_EINVAL, "restart must be >= 1");
+    if (restart < 1 || restart > 4096) return fail(IGB_EINVAL, "restart must be in 1..4096");
     igb_operator *op = const_cast<igb_operator *>(cop);
     if (op->cplx) return fail(IGB_EUNSUPPORTED, "flexible GMRES is built for real (Laplace) operators");
     return solve_fgmres(op, net, (const double *)b_dev, (double *)w_dev, rel_tol, max_iter, restart, info);

@@ -160,10 +160,12 @@ def mixed_leg(torch, igb, geo, cfg, ev_dev, fp64_ms, exact, steps: int = 2):
             "coupling_ms": round(st["coupling"], 4)}
 
 
-def learned_leg(torch, igb, epochs: int = 4):
+def learned_leg(torch, igb, epochs: int = 4, seeds=(5, 6, 7, 8)):
     """The learned preconditioner on its own workload: Laplace on the perturbed sphere (p=2, 128x128 elements
-    per patch, q=8), 2000 seeded training vectors, the linear network trained on the GPU (loss on x), then
-    flexible GMRES to 1e-8 beside the plain FP64 solve (Jacobi CG) and Jacobi FGMRES, all from w = 0."""
+    per patch, q=8), 2000 seeded training vectors, the linear network trained on the GPU (loss on x) from four
+    seeded initial weights, each then used in flexible GMRES to 1e-8 (at most 300 steps), beside the plain FP64
+    solve (Jacobi CG) and Jacobi FGMRES, all from w = 0.  Every seed is reported: the network's effect depends
+    on its initial weights."""
     from paper_1708_09162_amd import workloads as W
 
     c5 = W.config_learned_preconditioner()
@@ -197,28 +199,34 @@ def learned_leg(torch, igb, epochs: int = 4):
     torch.cuda.synchronize()
     t_pairs = time.perf_counter() - t
     del x
-    net = igb.CNN(W.cnn_initial_weights(c5["pair_seed"]), igb.IGB_CNN_LINEAR, device="cuda:0")
-    torch.cuda.synchronize()
-    t = time.perf_counter()
-    losses = net.train(y32, x32, npatch, side, side, epochs=epochs, batch=16, lr=1e-3)
-    torch.cuda.synchronize()
-    t_train = time.perf_counter() - t
-    del y32, x32
-    w, i_n, t_n = timed_solve(lambda: op.solve_fgmres(b, net, tol=TOL, max_iter=1000, restart=100))
-    r = b - op.matvec(w)
+    runs = []
+    for seed in seeds:
+        net = igb.CNN(W.cnn_initial_weights(seed), igb.IGB_CNN_LINEAR, device="cuda:0")
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        losses = net.train(y32, x32, npatch, side, side, epochs=epochs, batch=16, lr=1e-3)
+        torch.cuda.synchronize()
+        t_train = time.perf_counter() - t
+        w, i_n, t_n = timed_solve(lambda: op.solve_fgmres(b, net, tol=TOL, max_iter=300, restart=100))
+        r = b - op.matvec(w)
+        runs.append({"init_seed": seed, "train_s": round(t_train, 3),
+                     "loss_per_epoch": [round(float(v), 5) for v in losses],
+                     "iterations": int(i_n.iterations), "converged": int(i_n.converged), "solve_s": round(t_n, 4),
+                     "true_rel_residual": float(torch.linalg.norm(r) / torch.linalg.norm(b))})
+        del net
+    conv = [rr for rr in runs if rr["converged"]]
     res.update({
         "plain_fp64_cg": {"iterations": int(i_cg.iterations), "solve_s": round(t_cg, 4)},
         "jacobi_fgmres": {"iterations": int(i_j.iterations), "solve_s": round(t_j, 4)},
-        "network_fgmres": {"iterations": int(i_n.iterations), "solve_s": round(t_n, 4),
-                           "converged": int(i_n.converged),
-                           "true_rel_residual": float(torch.linalg.norm(r) / torch.linalg.norm(b))},
-        "pairs_s": round(t_pairs, 3), "train_s": round(t_train, 3),
-        "loss_per_epoch": [round(float(v), 5) for v in losses],
-        "solve_vs_plain_fp64": round(t_n / t_cg, 4),
+        "network_fgmres_per_seed": runs,
+        "network_converged_within_300": f"{len(conv)}/{len(runs)}",
+        "network_median_iterations": float(np.median([rr["iterations"] for rr in runs])),
+        "network_best_solve_vs_plain_fp64": round(min(rr["solve_s"] for rr in conv) / t_cg, 4) if conv else None,
+        "pairs_s": round(t_pairs, 3),
     })
     print(f"[bench] learned preconditioner: CG {i_cg.iterations} it {t_cg:.3f} s, Jacobi FGMRES {i_j.iterations} it "
-          f"{t_j:.3f} s, network FGMRES {i_n.iterations} it {t_n:.3f} s (train {t_train:.2f} s)", file=sys.stderr,
-          flush=True)
+          f"{t_j:.3f} s, network FGMRES per seed {[(rr['iterations'], rr['converged']) for rr in runs]}",
+          file=sys.stderr, flush=True)
     return res
 
 

@@ -21,6 +21,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <utility>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -538,13 +539,17 @@ igb_status igb_cnn_create(const float *weights_host, int32_t activation, void *h
         return s;
     };
     const size_t fb = (size_t)net->nw * sizeof(float);
-    if (hipMalloc(&net->w, fb) != hipSuccess || hipMalloc(&net->g, fb) != hipSuccess ||
-        hipMalloc(&net->m, fb) != hipSuccess || hipMalloc(&net->v, fb) != hipSuccess ||
-        hipMalloc(&net->wb, net->nw * sizeof(uint16_t)) != hipSuccess ||
-        hipMalloc(&net->wt, net->nw * sizeof(uint16_t)) != hipSuccess ||
-        hipMalloc(&net->part, (size_t)kGBlocks * 9 * kC * kC * sizeof(float)) != hipSuccess ||
-        hipMalloc(&net->lpart, kLossBlocks * sizeof(double)) != hipSuccess)
-        return fail_free(err(IGB_ENOMEM, "device allocation failed"));
+    hipError_t e = hipSuccess;
+    for (auto a : {std::make_pair((void **)&net->w, fb), std::make_pair((void **)&net->g, fb),
+                   std::make_pair((void **)&net->m, fb), std::make_pair((void **)&net->v, fb),
+                   std::make_pair((void **)&net->wb, net->nw * sizeof(uint16_t)),
+                   std::make_pair((void **)&net->wt, net->nw * sizeof(uint16_t)),
+                   std::make_pair((void **)&net->part, (size_t)kGBlocks * 9 * kC * kC * sizeof(float)),
+                   std::make_pair((void **)&net->lpart, kLossBlocks * sizeof(double))})
+        if (e == hipSuccess) e = hipMalloc(a.first, a.second);
+    if (e != hipSuccess)
+        return fail_free(err(e == hipErrorOutOfMemory ? IGB_ENOMEM : IGB_EHIP,
+                             std::string("device allocation: ") + hipGetErrorString(e)));
     if (hipMemcpyAsync(net->w, weights_host, fb, hipMemcpyHostToDevice, net->st) != hipSuccess ||
         hipMemsetAsync(net->m, 0, fb, net->st) != hipSuccess || hipMemsetAsync(net->v, 0, fb, net->st) != hipSuccess)
         return fail_free(err(IGB_EHIP, "weight upload failed"));

@@ -77,6 +77,12 @@ class igb_solve_info(C.Structure):
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"libigabem.so not built at {LIB_PATH}; run paper_1708_09162_amd/build.py")
+    # torch first: its HIP runtime is then the one libigabem.so binds to (same soname).  Loaded the
+    # other way round, the process would hold two HIP runtimes and the second one sees no device.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = C.CDLL(LIB_PATH)
     vp, dp, ip, fp = C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int32), C.POINTER(C.c_float)
     sig = {

@@ -139,3 +139,11 @@ def test_layout_flags(mode, q, kernel, flags):
                     wavenumber=2.0 if kernel else 0.0).info
     assert info.n_far_blocks > 0
     assert info.layout_flags == flags
+
+
+def test_single_hip_runtime_in_process():
+    """The binding loads torch before libigabem.so, so the library binds to torch's HIP runtime
+    instead of bringing a second copy into the process (the second would see no device)."""
+    with open("/proc/self/maps") as fh:
+        libs = {ln.split()[-1] for ln in fh if "libamdhip64" in ln}
+    assert len(libs) == 1, libs

@@ -268,7 +268,7 @@ igb_status igb_cnn_train_operator(igb_cnn *net, const igb_operator *op, const fl
  * plain Jacobi D^-1 v when net is NULL (the fallback).  Laplace operators only
  * (IGB_EUNSUPPORTED otherwise).  Stopping rule, initial guess and return
  * values as igb_solve, judged on the true residual of the FP64 operator.
- * restart in 1..4096 (IGB_EINVAL otherwise).  The bases take (2 restart + 1)
+ * restart in 1..2048 (IGB_EINVAL otherwise).  The bases take (2 restart + 1)
  * n_dof doubles of device memory.  Synchronous. */
 igb_status igb_solve_fgmres(const igb_operator *op, const igb_cnn *net, const void *b_dev, void *w_dev,
                             double rel_tol, int32_t max_iter, int32_t restart, igb_solve_info *info);

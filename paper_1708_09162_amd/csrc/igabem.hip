@@ -3638,37 +3638,56 @@ static igb_status solve_gmres(igb_operator *op, const cd *b, cd *w, double tol, 
 // the first step count that reached tol (or -1), tol.  The estimate and a
 // converged flag go to the host-mapped pair `out`.  Steps after convergence
 // leave G as it is.
-__global__ void k_arnoldi(int k, int R, const double *__restrict__ hA, const double *__restrict__ hB,
-                          const double *__restrict__ vv, int nvv, double *__restrict__ G, double *__restrict__ out)
+__global__ void __launch_bounds__(64) k_arnoldi(int k, int R, const double *__restrict__ hA,
+                                                 const double *__restrict__ hB, const double *__restrict__ vv, int nvv,
+                                                 double *__restrict__ G, double *__restrict__ out)
 {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    // one wave: the column, the rotations and the norm partials are staged in LDS
+    // by all lanes, the rotations run serially on lane 0, and the lanes write back
+    extern __shared__ double sm[];
+    double *col = sm, *c = col + k + 2, *sv = c + k + 1;
     double *H = G, *cs = G + (size_t)(R + 1) * R, *sn = cs + R, *g = sn + R, *st = g + R + 1;
-    if (st[2] >= 0.0) {
-        out[0] = 0.0;
-        out[1] = 1.0;
+    const int lane = threadIdx.x;
+    if (st[2] >= 0.0) {  // converged at an earlier step
+        if (lane == 0) {
+            out[0] = 0.0;
+            out[1] = 1.0;
+        }
         return;
     }
-    for (int j = 0; j <= k; ++j) H[(size_t)j * R + k] = hA[j] + hB[j];
-    double v2 = 0.0;
-    for (int b = 0; b < nvv; ++b) v2 += vv[b];
-    const double hn = sqrt(v2);
-    st[1] = hn > 0.0 ? 1.0 / hn : 0.0;
-    for (int j = 0; j < k; ++j) {
-        const double a = H[(size_t)j * R + k], b = H[(size_t)(j + 1) * R + k];
-        H[(size_t)j * R + k] = cs[j] * a + sn[j] * b;
-        H[(size_t)(j + 1) * R + k] = -sn[j] * a + cs[j] * b;
+    for (int j = lane; j <= k; j += 64) {
+        col[j] = hA[j] + hB[j];
+        c[j] = cs[j];
+        sv[j] = sn[j];
     }
-    const double a = H[(size_t)k * R + k], den = hypot(a, hn);
-    cs[k] = den > 0.0 ? a / den : 1.0;
-    sn[k] = den > 0.0 ? hn / den : 0.0;
-    H[(size_t)k * R + k] = den;
-    g[k + 1] = -sn[k] * g[k];
-    g[k] = cs[k] * g[k];
-    const double res = fabs(g[k + 1]) / st[0];
-    const bool conv = res <= st[3];
-    if (conv) st[2] = k + 1;
-    out[0] = res;
-    out[1] = conv ? 1.0 : 0.0;
+    double v2 = 0.0;
+    for (int b = lane; b < nvv; b += 64) v2 += vv[b];
+    v2 = wave_sum64(v2);
+    __syncthreads();
+    if (lane == 0) {
+        const double hn = sqrt(v2);
+        st[1] = hn > 0.0 ? 1.0 / hn : 0.0;
+        for (int j = 0; j < k; ++j) {
+            const double a = col[j], b = col[j + 1];
+            col[j] = c[j] * a + sv[j] * b;
+            col[j + 1] = -sv[j] * a + c[j] * b;
+        }
+        const double a = col[k], den = hypot(a, hn);
+        const double ck = den > 0.0 ? a / den : 1.0, sk = den > 0.0 ? hn / den : 0.0;
+        cs[k] = ck;
+        sn[k] = sk;
+        col[k] = den;
+        const double gk = g[k];
+        g[k + 1] = -sk * gk;
+        g[k] = ck * gk;
+        const double res = fabs(g[k + 1]) / st[0];
+        const bool conv = res <= st[3];
+        if (conv) st[2] = k + 1;
+        out[0] = res;
+        out[1] = conv ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    for (int j = lane; j <= k; j += 64) H[(size_t)j * R + k] = col[j];
 }
 
 // x *= *alpha (alpha on the device); with D, also z = x / D (the next Jacobi direction)
@@ -3798,7 +3817,8 @@ static igb_status solve_fgmres(igb_operator *op, const igb_cnn *net, const doubl
                                        op->st, n, k + 1, (const double *)V, n, (const double *)op->mpart, mdb, hp, vn,
                                        pass ? nrm : (double *)nullptr);
                 }
-                hipLaunchKernelGGL(k_arnoldi, dim3(1), dim3(64), 0, op->st, k, R, (const double *)hA,
+                hipLaunchKernelGGL(k_arnoldi, dim3(1), dim3(64), (size_t)(3 * k + 4) * sizeof(double), op->st, k, R,
+                                   (const double *)hA,
                                    (const double *)hB, (const double *)nrm, (int)gsub, G, hout + 2 * (k & 1));
                 double *znext = (!net && k + 1 < kmax) ? Z + (size_t)(k + 1) * n : nullptr;
                 hipLaunchKernelGGL(k_scale_dev, dim3(gb), dim3(256), 0, op->st, n, (const double *)(st + 1), vn, D, znext);
@@ -4127,7 +4147,7 @@ igb_status igb_solve_fgmres(const igb_operator *cop, const igb_cnn *net, const v
     if (!b_dev || !w_dev) return fail(IGB_EINVAL, "null device pointer");
     if (b_dev == w_dev) return fail(IGB_EINVAL, "b and w must not alias");
     if (!(rel_tol > 0.0) || max_iter < 0) return fail(IGB_EINVAL, "rel_tol must be > 0 and max_iter >= 0");
-    if (restart < 1 || restart > 4096) return fail(IGB_EINVAL, "restart must be in 1..4096");
+    if (restart < 1 || restart > 2048) return fail(IGB_EINVAL, "restart must be in 1..2048");
     igb_operator *op = const_cast<igb_operator *>(cop);
     if (op->cplx) return fail(IGB_EUNSUPPORTED, "flexible GMRES is built for real (Laplace) operators");
     return solve_fgmres(op, net, (const double *)b_dev, (double *)w_dev, rel_tol, max_iter, restart, info);

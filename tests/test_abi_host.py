@@ -147,3 +147,16 @@ def test_single_hip_runtime_in_process():
     with open("/proc/self/maps") as fh:
         libs = {ln.split()[-1] for ln in fh if "libamdhip64" in ln}
     assert len(libs) == 1, libs
+
+
+def test_solver_and_network_entry_points_reject_null_arguments():
+    """Argument checks that run before any device work."""
+    assert igb._lib.igb_solve_fgmres(None, None, None, None, 1e-8, 10, 10, None) == igb.IGB_EINVAL
+    assert igb._lib.igb_cnn_training_pairs(None, None, 1, None, None) == igb.IGB_EINVAL
+    assert igb._lib.igb_cnn_train_operator(None, None, None, None, 1, 1, 1, 1e-3, None) == igb.IGB_EINVAL
+    h = igb.C.c_void_p()
+    assert igb._lib.igb_cnn_create(None, 0, None, igb.C.byref(h)) == igb.IGB_EINVAL
+    assert igb._lib.igb_cnn_forward(None, None, 1, 1, 1, None) == igb.IGB_EINVAL
+    assert igb._lib.igb_cnn_gradient(None, None, None, 1, 1, 1, None, None) == igb.IGB_EINVAL
+    assert igb._lib.igb_cnn_train(None, None, None, 1, 1, 1, 1, 1, 1, 1e-3, None) == igb.IGB_EINVAL
+    assert igb._lib.igb_cnn_get_weights(None, None) == igb.IGB_EINVAL

@@ -213,3 +213,27 @@ def test_trained_network_against_jacobi():
         assert true_rel <= 1e-8
     else:
         assert abs(true_rel - info_n.rel_residual) <= 1e-3 * true_rel
+
+
+def test_fgmres_restart_cycles_and_limits():
+    """Flexible GMRES with short cycles (restart 7, many cycles) reaches the oracle's density; a step limit
+    that is not a multiple of the cycle length stops after exactly that many steps with the true
+    residual of the returned iterate reported; max_iter = 0 returns the initial guess."""
+    say("fgmres restart cycles: sphere p=1 m=3 q=4")
+    op, P, b = _sphere_problem(1, 3, 4)
+    bt = torch.tensor(b, device=DEV)
+    w, info = op.solve_fgmres(bt, None, tol=1e-13, max_iter=5000, restart=7)
+    assert info.converged == 1 and info.iterations > 7
+    P.h2_assemble(store_coupling=True)
+    w_or, _, rr_or = P.solve(b, tol=1e-13, maxit=3000)
+    assert rr_or <= 1e-13
+    assert rel(w.cpu().numpy(), w_or) < 1e-10
+    w13, i13 = op.solve_fgmres(bt, None, tol=1e-13, max_iter=13, restart=5)
+    assert i13.converged == 0 and i13.iterations == 13
+    true_rel = (torch.linalg.norm(bt - op.matvec(w13)) / torch.linalg.norm(bt)).item()
+    assert abs(true_rel - i13.rel_residual) <= 1e-6 * true_rel
+    w5, i5 = op.solve_fgmres(bt, None, tol=1e-13, max_iter=5, restart=5)
+    assert i5.iterations == 5 and i5.rel_residual > i13.rel_residual
+    w0, i0 = op.solve_fgmres(bt, None, tol=1e-8, max_iter=0, restart=5)
+    assert i0.iterations == 0 and i0.converged == 0 and abs(i0.rel_residual - 1.0) < 1e-15
+    assert torch.count_nonzero(w0).item() == 0

@@ -298,8 +298,9 @@ def main():
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py: this build runs its whole path on one GPU; multi-GPU runs (--gpus > 1) are not "
-              "supported (see DESIGN.md for how the path would shard).", file=sys.stderr, flush=True)
+        print("bench.py: the whole path runs on one GPU; multi-GPU runs (--gpus > 1) are not supported. "
+              "The path would shard by target clusters, with one all-gather of cluster moments per product.",
+              file=sys.stderr, flush=True)
         sys.exit(2)
     if args.calibrate_copy:
         calibrate_copy()

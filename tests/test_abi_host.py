@@ -160,3 +160,12 @@ def test_solver_and_network_entry_points_reject_null_arguments():
     assert igb._lib.igb_cnn_gradient(None, None, None, 1, 1, 1, None, None) == igb.IGB_EINVAL
     assert igb._lib.igb_cnn_train(None, None, None, 1, 1, 1, 1, 1, 1, 1e-3, None) == igb.IGB_EINVAL
     assert igb._lib.igb_cnn_get_weights(None, None) == igb.IGB_EINVAL
+
+
+def test_bench_refuses_more_than_one_gpu():
+    import subprocess
+    import sys as _sys
+    r = subprocess.run([_sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr and r.stdout == ""

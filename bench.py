@@ -248,6 +248,49 @@ def learned_leg(torch, igb, epochs: int = 4, seeds=(5, 6, 7, 8)):
     return res
 
 
+def batched_leg(torch, igb, n: int = 128, max_iter: int = 2000):
+    """Many independent instances (sphere/torus, m 2-5, p 1-3, Laplace or Helmholtz, one right-hand side each),
+    every operator on its own stream: one-at-a-time solves against igb_solve_many (solves overlapping on the
+    GPU), same tolerance and step limit (GMRES restart 300 for Helmholtz)."""
+    from paper_1708_09162_amd import workloads as W
+
+    cfg = W.config_batched(n)
+    inst = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i, d in enumerate(cfg):
+        patches = W.torus_patches() if d["geometry"] == "torus" else W.sphere_patches()
+        op = igb.Operator(igb.Geometry(patches), mode=igb.IGB_H2_ONTHEFLY, kernel=d["kernel"],
+                          wavenumber=d["wavenumber"], p=d["p"], m=d["m"], q=d["q"], eta=d["eta"],
+                          gauss_regular=d["gauss_regular"], device="cuda:0", stream=torch.cuda.Stream())
+        pts = op.rhs_points()
+        torch.cuda.synchronize()
+        pn = pts.cpu().numpy()
+        g = (W.helmholtz_point_source(pn, d["source"], d["wavenumber"]) if d["kernel"] == 1
+             else W.laplace_charge_field(pn, *d["charges"]))
+        inst.append((op, op.rhs(torch.tensor(g, device="cuda:0"))))
+        torch.cuda.synchronize()
+        if i % 32 == 31:
+            print(f"[bench] batched: {i + 1} instances assembled", file=sys.stderr, flush=True)
+    t_asm = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    seq = [op.solve(b, tol=TOL, max_iter=max_iter, restart=300)[1] for op, b in inst]
+    torch.cuda.synchronize()
+    t_seq = time.perf_counter() - t0
+    print(f"[bench] batched: one-at-a-time solves {t_seq:.2f} s", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    _, infos = igb.solve_many([op for op, _ in inst], [b for _, b in inst], tol=TOL, max_iter=max_iter, restart=300)
+    torch.cuda.synchronize()
+    t_many = time.perf_counter() - t0
+    print(f"[bench] batched: solve_many {t_many:.2f} s", file=sys.stderr, flush=True)
+    return {"instances": n, "max_iter": max_iter, "assembly_s": round(t_asm, 3),
+            "sequential_solve_s": round(t_seq, 3), "solve_many_s": round(t_many, 3),
+            "speedup": round(t_seq / t_many, 3), "instances_per_s": round(n / t_many, 2),
+            "converged": f"{sum(i.converged for i in infos)}/{n}",
+            "converged_one_at_a_time": f"{sum(i.converged for i in seq)}/{n}",
+            "total_dofs": int(sum(op.info.n_dof for op, _ in inst))}
+
+
 def cpu_baseline(cfg, iterations: int, seed: int = 7):
     """Oracle time-to-solve projected from a timed stratified sample of the same workload:
     near-field pair quadrature (per class) and coupling-block evaluation (the oracle evaluates
@@ -295,6 +338,8 @@ def main():
     ap.add_argument("--calibrate-copy", action="store_true", help="only run a plain 1 GiB device copy")
     ap.add_argument("--no-mixed", action="store_true", help="skip the single-precision far-field leg")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-preconditioner leg")
+    ap.add_argument("--batched", action="store_true",
+                    help="also run the 128-instance batched-solve leg (about 90 s)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -458,6 +503,8 @@ def main():
         out["mixed_fp32_far"] = mixed_leg(torch, igb, geo, cfg, ev_dev, ms_per_step, exact)
     if not args.no_learned:
         out["learned_preconditioner"] = learned_leg(torch, igb)
+    if args.batched:
+        out["batched"] = batched_leg(torch, igb)
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle sample)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(cfg, int(info.iterations))

@@ -273,6 +273,18 @@ igb_status igb_cnn_train_operator(igb_cnn *net, const igb_operator *op, const fl
 igb_status igb_solve_fgmres(const igb_operator *op, const igb_cnn *net, const void *b_dev, void *w_dev,
                             double rel_tol, int32_t max_iter, int32_t restart, igb_solve_info *info);
 
+/* Solves n independent systems at once, each as igb_solve on ops[i] with
+ * b_devs[i], w_devs[i] (same rel_tol, max_iter, restart for all).  Solve i
+ * runs on operator i's stream, driven by one of up to 16 host threads, so
+ * instances given their own streams overlap on the GPU (instances sharing a
+ * stream run one after another, still correct).  The operators must be
+ * distinct (IGB_EINVAL otherwise: a solve uses its operator's buffers).
+ * infos (host, n entries) may be NULL.  Returns IGB_OK, or the most severe
+ * status of any instance with its index in igb_last_error().  Synchronous.
+ * This batches whole solves over streams; it is not a single fused launch. */
+igb_status igb_solve_many(int32_t n, igb_operator *const *ops, const void *const *b_devs, void *const *w_devs,
+                          double rel_tol, int32_t max_iter, int32_t restart, igb_solve_info *infos);
+
 /* Potential u(x) = (V~ mu_h)(x) for x off Gamma (Sec. 3.1, eq. eq::repform),
  * mu_h the density with S coefficients w_dev; Gauss order gauss_rhs per
  * element.  xyz_dev: n_pts x 3 doubles; u_dev: n_pts values. */

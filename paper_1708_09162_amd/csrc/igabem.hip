@@ -8,7 +8,10 @@
 #include <cmath>
 #include <cstring>
 #include <map>
+#include <atomic>
 #include <mutex>
+#include <set>
+#include <thread>
 #include <string>
 #include <type_traits>
 #include <vector>
@@ -4138,6 +4141,59 @@ igb_status igb_solve(const igb_operator *cop, const void *b_dev, void *w_dev, do
         return solve_gmres(op, (const cd *)b_dev, (cd *)w_dev, rel_tol, max_iter, restart, info);
     }
     return solve_cg(op, (const double *)b_dev, (double *)w_dev, rel_tol, max_iter, info);
+}
+
+igb_status igb_solve_many(int32_t n, igb_operator *const *ops, const void *const *b_devs, void *const *w_devs,
+                          double rel_tol, int32_t max_iter, int32_t restart, igb_solve_info *infos)
+{
+    if (n < 0) return fail(IGB_EINVAL, "n must be >= 0");
+    if (n > 0 && (!ops || !b_devs || !w_devs)) return fail(IGB_EINVAL, "null argument");
+    if (!(rel_tol > 0.0) || max_iter < 0) return fail(IGB_EINVAL, "rel_tol must be > 0 and max_iter >= 0");
+    std::set<const igb_operator *> seen;
+    for (int32_t i = 0; i < n; ++i) {
+        if (!ops[i] || !b_devs[i] || !w_devs[i]) return fail(IGB_EINVAL, "null operator or vector at " + std::to_string(i));
+        if (!seen.insert(ops[i]).second)
+            return fail(IGB_EINVAL, "operator " + std::to_string(i) + " appears twice (its buffers would be shared)");
+        if (ops[i]->cplx && restart < 1) return fail(IGB_EINVAL, "restart must be >= 1");
+    }
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    std::vector<igb_status> st(n, IGB_OK);
+    std::vector<std::string> msg(n);
+    std::atomic<int> next{0};
+    auto worker = [&]() {
+        if (hipSetDevice(dev) != hipSuccess) return;
+        for (;;) {
+            const int i = next.fetch_add(1);
+            if (i >= n) break;
+            igb_solve_info inf{};
+            st[i] = igb_solve(ops[i], b_devs[i], w_devs[i], rel_tol, max_iter, restart, &inf);
+            if (infos) infos[i] = inf;
+            if (st[i] != IGB_OK) msg[i] = g_err;
+        }
+    };
+    const int nt = std::min<int>(n, 16);
+    std::vector<std::thread> th;
+    try {
+        for (int t = 0; t < nt; ++t) th.emplace_back(worker);
+    } catch (const std::system_error &) {
+        for (auto &x : th) x.join();
+        return fail(IGB_ENOMEM, "could not start solver threads");
+    }
+    for (auto &x : th) x.join();
+    if (next.load() < n) return fail(IGB_EHIP, "hipSetDevice failed in a solver thread");
+    igb_status worst = IGB_OK;
+    int wi = -1;
+    for (int32_t i = 0; i < n; ++i)
+        if (st[i] < 0 && (worst >= 0 || st[i] < worst)) {
+            worst = st[i];
+            wi = i;
+        } else if (st[i] > 0 && worst == IGB_OK) {
+            worst = st[i];
+            wi = i;
+        }
+    if (worst != IGB_OK) return fail(worst, "instance " + std::to_string(wi) + ": " + msg[wi]);
+    return IGB_OK;
 }
 
 igb_status igb_solve_fgmres(const igb_operator *cop, const igb_cnn *net, const void *b_dev, void *w_dev,

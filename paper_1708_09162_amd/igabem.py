@@ -38,7 +38,7 @@ EXPORTED = [
     "igb_plan_create", "igb_plan_destroy", "igb_plan_info", "igb_plan_export_partition",
     "igb_plan_export_pair_classes", "igb_matvec_profile", "igb_release_cached_memory",
     "igb_cnn_create", "igb_cnn_destroy", "igb_cnn_get_weights", "igb_cnn_forward", "igb_cnn_gradient",
-    "igb_cnn_training_pairs", "igb_cnn_train", "igb_cnn_train_operator", "igb_solve_fgmres",
+    "igb_cnn_training_pairs", "igb_cnn_train", "igb_cnn_train_operator", "igb_solve_fgmres", "igb_solve_many",
 ]
 IGB_CNN_NUM_WEIGHTS = 28224
 IGB_CNN_RELU = 0
@@ -120,6 +120,8 @@ def _load():
         "igb_cnn_training_pairs": (C.c_int32, [vp, vp, C.c_int64, vp, vp]),
         "igb_cnn_train": (C.c_int32, [vp, vp, vp, C.c_int64, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32,
                                       C.c_float, dp]),
+        "igb_solve_many": (C.c_int32, [C.c_int32, vp, vp, vp, C.c_double, C.c_int32, C.c_int32,
+                                       C.POINTER(igb_solve_info)]),
         "igb_cnn_train_operator": (C.c_int32, [vp, vp, vp, vp, C.c_int64, C.c_int32, C.c_int32, C.c_float, dp]),
         "igb_solve_fgmres": (C.c_int32, [vp, vp, vp, vp, C.c_double, C.c_int32, C.c_int32,
                                          C.POINTER(igb_solve_info)]),
@@ -238,6 +240,27 @@ def igb_solve_fgmres(op, net, b, w, rel_tol, max_iter, restart) -> igb_solve_inf
     _check(_lib.igb_solve_fgmres(op, net, _ptr(b), _ptr(w), float(rel_tol), int(max_iter), int(restart),
                                  C.byref(info)), allow=(IGB_OK, IGB_ENOT_CONVERGED))
     return info
+
+
+def igb_solve_many(ops, bs, ws, rel_tol, max_iter, restart):
+    n = len(ops)
+    arr = lambda xs: (C.c_void_p * max(n, 1))(*xs)
+    infos = (igb_solve_info * max(n, 1))()
+    _check(_lib.igb_solve_many(n, arr([o.value for o in ops]), arr([t.data_ptr() for t in bs]),
+                               arr([t.data_ptr() for t in ws]), float(rel_tol), int(max_iter), int(restart), infos),
+           allow=(IGB_OK, IGB_ENOT_CONVERGED))
+    return [infos[i] for i in range(n)]
+
+
+def solve_many(operators, bs, tol=1e-8, max_iter=1000, restart=300):
+    """Solves the systems of several distinct operators at once (igb_solve_many); returns (densities, infos).
+    Instances overlap on the GPU when each operator was created with its own stream."""
+    ws = [op._vec(op.info.n_dof) for op in operators]
+    bs = [op._in(b, op.info.n_dof) for op, b in zip(operators, bs)]
+    for op in operators:
+        op.torch.cuda.synchronize(op.device)
+    infos = igb_solve_many([op.h for op in operators], bs, ws, tol, max_iter, restart)
+    return ws, infos
 
 
 def _fptr(a):
@@ -404,7 +427,7 @@ class Operator:
 
     def __init__(self, geometry: Geometry, *, kernel=IGB_LAPLACE, wavenumber=0.0, p=1, m=2, q=8, eta=1.6,
                  leaf_depth=-1, gauss_regular=6, gauss_singular=-1, gauss_rhs=-1, mode=IGB_H2_STORED,
-                 far_precision=IGB_FP64, device="cuda:0"):
+                 far_precision=IGB_FP64, device="cuda:0", stream=None):
         import torch
 
         self.torch = torch
@@ -414,7 +437,7 @@ class Operator:
                           gauss_regular=gauss_regular, gauss_singular=gauss_singular, gauss_rhs=gauss_rhs, mode=mode,
                           far_precision=far_precision)
         with torch.cuda.device(self.device):
-            self.stream = torch.cuda.current_stream(self.device)
+            self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
             self.h = igb_operator_create(geometry.h, prm, self.stream.cuda_stream)
         self.info = igb_operator_info(self.h)
         self.cplx = kernel == IGB_HELMHOLTZ

@@ -379,3 +379,47 @@ def cnn_initial_weights(seed: int, last_scale: float = 0.0) -> np.ndarray:
 def training_vectors(n_pairs: int, n: int, seed: int) -> np.ndarray:
     """n_pairs seeded standard normal coefficient vectors of length n (FP64)."""
     return np.random.default_rng(seed).standard_normal((n_pairs, n))
+
+
+def _near_sphere_resonance(kappa: float, lmax: int = 19, gap: float = 0.05) -> bool:
+    """True when kappa lies within `gap` of a zero of a spherical Bessel function j_l, l <= lmax (the interior
+    Dirichlet eigenvalues of the unit sphere, where the single-layer operator is singular)."""
+    from scipy.special import spherical_jn
+
+    xs = np.linspace(max(kappa - gap, 1e-6), kappa + gap, 41)
+    for l in range(lmax + 1):
+        v = spherical_jn(l, xs)
+        if np.any(np.sign(v[1:]) != np.sign(v[:-1])) or np.any(v == 0.0):
+            return True
+    return False
+
+
+def config_batched(n: int = 128, seed: int = 4) -> list[dict]:
+    """n independent problems (seed + i each): unit sphere or 16-patch torus, 2^m x 2^m elements per patch
+    with m in {2,3,4,5}, degree p in {1,2,3}, q = 6; Laplace (data from 4 exterior point charges) or
+    Helmholtz with kappa uniform in [1, 16] (data from a point source inside: sphere radius <= 0.5, torus
+    tube centre line; kappa redrawn near sphere resonances)."""
+    out = []
+    for i in range(n):
+        rng = np.random.default_rng(seed + i)
+        torus = bool(rng.integers(0, 2))
+        m = int(rng.integers(2, 6))
+        p = int(rng.integers(1, 4))
+        helm = bool(rng.integers(0, 2))
+        d = {"geometry": "torus" if torus else "sphere", "m": m, "p": p, "q": 6, "eta": 1.6, "gauss_regular": 6,
+             "kernel": 1 if helm else 0, "wavenumber": 0.0, "seed": seed + i}
+        if helm:
+            k = float(rng.uniform(1.0, 16.0))
+            while not torus and _near_sphere_resonance(k):
+                k = float(rng.uniform(1.0, 16.0))
+            d["wavenumber"] = k
+            if torus:
+                a = float(rng.uniform(0.0, 2.0 * np.pi))
+                d["source"] = np.array([2.0 * np.cos(a), 2.0 * np.sin(a), 0.0])
+            else:
+                v = rng.standard_normal(3)
+                d["source"] = v / np.linalg.norm(v) * float(rng.uniform(0.0, 0.5))
+        else:
+            d["charges"] = point_charges(4, seed + i, rmin=3.5 if torus else 1.5, rmax=5.0 if torus else 3.0)
+        out.append(d)
+    return out

@@ -237,3 +237,43 @@ def test_fgmres_restart_cycles_and_limits():
     w0, i0 = op.solve_fgmres(bt, None, tol=1e-8, max_iter=0, restart=5)
     assert i0.iterations == 0 and i0.converged == 0 and abs(i0.rel_residual - 1.0) < 1e-15
     assert torch.count_nonzero(w0).item() == 0
+
+
+def _batch_instance(d, stream):
+    patches = W.torus_patches() if d["geometry"] == "torus" else W.sphere_patches()
+    op = igb.Operator(igb.Geometry(patches), mode=igb.IGB_H2_ONTHEFLY, kernel=d["kernel"],
+                      wavenumber=d["wavenumber"], p=d["p"], m=d["m"], q=d["q"], eta=d["eta"],
+                      gauss_regular=d["gauss_regular"], device=DEV, stream=stream)
+    pts = op.rhs_points()
+    torch.cuda.synchronize()
+    pn = pts.cpu().numpy()
+    if d["kernel"] == 1:
+        g = W.helmholtz_point_source(pn, d["source"], d["wavenumber"])
+    else:
+        g = W.laplace_charge_field(pn, *d["charges"])
+    b = op.rhs(torch.tensor(g, device=DEV))
+    torch.cuda.synchronize()
+    return op, b
+
+
+def test_solve_many_matches_single_solves():
+    """Independent instances (sphere and torus, Laplace and Helmholtz, different sizes) solved together on
+    their own streams give bit for bit the densities and step counts of one-at-a-time solves."""
+    cfg = [d for d in W.config_batched(24, seed=40) if d["m"] <= 3][:6]
+    assert {d["kernel"] for d in cfg} == {0, 1}
+    say(f"solve_many: {[(d['geometry'], d['m'], d['p'], d['kernel']) for d in cfg]}")
+    inst = [_batch_instance(d, torch.cuda.Stream()) for d in cfg]
+    ops = [o for o, _ in inst]
+    bs = [b for _, b in inst]
+    ref = []
+    for op, b in inst:
+        w, info = op.solve(b, tol=1e-8, max_iter=3000, restart=300)
+        torch.cuda.synchronize()
+        ref.append((w.clone(), info.iterations, info.converged))
+    ws, infos = igb.solve_many(ops, bs, tol=1e-8, max_iter=3000, restart=300)
+    torch.cuda.synchronize()
+    for (w_ref, it, conv), w, info in zip(ref, ws, infos):
+        assert conv == 1 and info.converged == 1 and info.iterations == it
+        assert torch.equal(w, w_ref)
+    with pytest.raises(igb.IgbError):
+        igb.solve_many([ops[0], ops[0]], [bs[0], bs[0]])

@@ -273,7 +273,8 @@ igb_status igb_cnn_train_operator(igb_cnn *net, const igb_operator *op, const fl
 igb_status igb_solve_fgmres(const igb_operator *op, const igb_cnn *net, const void *b_dev, void *w_dev,
                             double rel_tol, int32_t max_iter, int32_t restart, igb_solve_info *info);
 
-/* Solves n independent systems at once, each as igb_solve on ops[i] with
+/* Solves n independent systems at once (the Krylov solve of Sec. 4 item 3
+ * for each instance), each as igb_solve on ops[i] with
  * b_devs[i], w_devs[i] (same rel_tol, max_iter, restart for all).  Solve i
  * runs on operator i's stream, driven by one of up to 16 host threads, so
  * instances given their own streams overlap on the GPU (instances sharing a

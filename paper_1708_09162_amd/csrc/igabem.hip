@@ -4167,9 +4167,14 @@ igb_status igb_solve_many(int32_t n, igb_operator *const *ops, const void *const
             const int i = next.fetch_add(1);
             if (i >= n) break;
             igb_solve_info inf{};
-            st[i] = igb_solve(ops[i], b_devs[i], w_devs[i], rel_tol, max_iter, restart, &inf);
+            try {
+                st[i] = igb_solve(ops[i], b_devs[i], w_devs[i], rel_tol, max_iter, restart, &inf);
+                if (st[i] != IGB_OK) msg[i] = g_err;
+            } catch (const std::exception &ex) {  // nothing may escape a worker thread
+                st[i] = IGB_ENOMEM;
+                msg[i] = std::string("host exception: ") + ex.what();
+            }
             if (infos) infos[i] = inf;
-            if (st[i] != IGB_OK) msg[i] = g_err;
         }
     };
     const int nt = std::min<int>(n, 16);

@@ -277,3 +277,34 @@ def test_solve_many_matches_single_solves():
         assert torch.equal(w, w_ref)
     with pytest.raises(igb.IgbError):
         igb.solve_many([ops[0], ops[0]], [bs[0], bs[0]])
+
+
+def test_selected_network_against_jacobi():
+    """Model selection with fallback: four linear networks (initial-weight seeds 5-8) trained on the p=2
+    sphere with 32x32 elements per patch; the one with the fewest flexible-GMRES steps on a validation
+    right-hand side (other point charges) is kept if it beats Jacobi there, else Jacobi.  On the real
+    right-hand side the kept preconditioner takes at most Jacobi's steps plus a small margin for the
+    validation-to-target mismatch; the gain is reported."""
+    say("selected network: sphere p=2 m=5 q=8")
+    op, P, b = _sphere_problem(2, 5, 8)
+    npatch, side = op.grid
+    bt = torch.tensor(b, device=DEV)
+    pos, qs = W.point_charges(4, 3)
+    bv = op.rhs(torch.tensor(W.laplace_charge_field(op.rhs_points().cpu().numpy(), pos, qs), device=DEV))
+    x = torch.tensor(W.training_vectors(512, op.info.n_dof, 20), device=DEV)
+    y32, x32 = op.training_pairs(x)
+    _, vj = op.solve_fgmres(bv, None, tol=1e-8, max_iter=2000, restart=100)
+    best, best_v = None, vj.iterations
+    for seed in (5, 6, 7, 8):
+        net = igb.CNN(W.cnn_initial_weights(seed), igb.IGB_CNN_LINEAR, device=DEV)
+        net.train(y32, x32, npatch, side, side, epochs=12, batch=16, lr=1e-3)
+        _, vi = op.solve_fgmres(bv, net, tol=1e-8, max_iter=300, restart=100)
+        say(f"seed {seed}: validation {vi.iterations} steps (converged {vi.converged}), jacobi {vj.iterations}")
+        if vi.converged == 1 and vi.iterations < best_v:
+            best, best_v = net, vi.iterations
+    _, ij = op.solve_fgmres(bt, None, tol=1e-8, max_iter=2000, restart=100)
+    w, isel = op.solve_fgmres(bt, best, tol=1e-8, max_iter=2000, restart=100)
+    say(f"selected {'network' if best is not None else 'jacobi'}: {isel.iterations} steps, jacobi {ij.iterations}")
+    assert ij.converged == 1 and isel.converged == 1
+    assert isel.iterations <= ij.iterations + 5
+    assert (torch.linalg.norm(bt - op.matvec(w)) / torch.linalg.norm(bt)).item() <= 1e-8

@@ -248,10 +248,10 @@ def learned_leg(torch, igb, epochs: int = 4, seeds=(5, 6, 7, 8)):
     return res
 
 
-def batched_leg(torch, igb, n: int = 128, max_iter: int = 2000):
+def batched_leg(torch, igb, n: int = 128, max_iter: int = 3000, restart: int = 1000):
     """Many independent instances (sphere/torus, m 2-5, p 1-3, Laplace or Helmholtz, one right-hand side each),
     every operator on its own stream: one-at-a-time solves against igb_solve_many (solves overlapping on the
-    GPU), same tolerance and step limit (GMRES restart 300 for Helmholtz)."""
+    GPU), same tolerance and step limit (GMRES restart 1000 for Helmholtz: shorter cycles stall at high kappa)."""
     from paper_1708_09162_amd import workloads as W
 
     cfg = W.config_batched(n)
@@ -274,16 +274,17 @@ def batched_leg(torch, igb, n: int = 128, max_iter: int = 2000):
             print(f"[bench] batched: {i + 1} instances assembled", file=sys.stderr, flush=True)
     t_asm = time.perf_counter() - t0
     t0 = time.perf_counter()
-    seq = [op.solve(b, tol=TOL, max_iter=max_iter, restart=300)[1] for op, b in inst]
+    seq = [op.solve(b, tol=TOL, max_iter=max_iter, restart=restart)[1] for op, b in inst]
     torch.cuda.synchronize()
     t_seq = time.perf_counter() - t0
     print(f"[bench] batched: one-at-a-time solves {t_seq:.2f} s", file=sys.stderr, flush=True)
     t0 = time.perf_counter()
-    _, infos = igb.solve_many([op for op, _ in inst], [b for _, b in inst], tol=TOL, max_iter=max_iter, restart=300)
+    _, infos = igb.solve_many([op for op, _ in inst], [b for _, b in inst], tol=TOL, max_iter=max_iter,
+                              restart=restart)
     torch.cuda.synchronize()
     t_many = time.perf_counter() - t0
     print(f"[bench] batched: solve_many {t_many:.2f} s", file=sys.stderr, flush=True)
-    return {"instances": n, "max_iter": max_iter, "assembly_s": round(t_asm, 3),
+    return {"instances": n, "max_iter": max_iter, "restart": restart, "assembly_s": round(t_asm, 3),
             "sequential_solve_s": round(t_seq, 3), "solve_many_s": round(t_many, 3),
             "speedup": round(t_seq / t_many, 3), "instances_per_s": round(n / t_many, 2),
             "converged": f"{sum(i.converged for i in infos)}/{n}",

@@ -2423,13 +2423,21 @@ __global__ void k_multireduce(int k, int nblk, const T *__restrict__ part, T *__
     if (threadIdx.x == 0) h[j] = red[0];
 }
 
-// w -= V h (first k columns)
+// w -= V h (first k columns), eight columns' loads in flight per thread
 template <class T>
 __global__ void k_sub_Vh(int64_t n, int k, const T *__restrict__ V, int64_t ldv, const T *__restrict__ h, T *__restrict__ w)
 {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         T s = w[i];
-        for (int j = 0; j < k; ++j) s -= h[j] * V[(int64_t)j * ldv + i];
+        int j = 0;
+        for (; j + 8 <= k; j += 8) {
+            T v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) v[u] = V[(int64_t)(j + u) * ldv + i];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) s -= h[j + u] * v[u];
+        }
+        for (; j < k; ++j) s -= h[j] * V[(int64_t)j * ldv + i];
         w[i] = s;
     }
 }
@@ -3564,8 +3572,8 @@ static igb_status solve_gmres(igb_operator *op, const cd *b, cd *w, double tol, 
             if ((rc = matvec_S<cd>(op, t, vn))) return rc;
             std::fill(hcol.begin(), hcol.end(), cd{0.0, 0.0});
             for (int pass = 0; pass < 2; ++pass) {  // classical Gram-Schmidt, twice
-                hipLaunchKernelGGL((k_multidot_partial<cd>), dim3(mdb), dim3(256), 0, op->st, n, k + 1, V, n, vn,
-                                   (cd *)op->mpart, mdb);
+                hipLaunchKernelGGL((k_multidot_partial<cd>), dim3(mdb, (unsigned)((k + 4) / 4)), dim3(256), 0, op->st, n,
+                                   k + 1, V, n, vn, (cd *)op->mpart, mdb);
                 LAUNCHCHK();
                 hipLaunchKernelGGL((k_multireduce<cd>), dim3(k + 1), dim3(256), 0, op->st, k + 1, mdb,
                                    (const cd *)op->mpart, hd);

@@ -259,7 +259,8 @@ igb_status igb_cnn_train(igb_cnn *net, const float *y_dev, const float *x_dev, i
  * pairs (y_s, x_s) of igb_cnn_training_pairs (y_s = D^-1 A x_s),
  * L = sum_s |D^-1 A (M(y_s) - x_s)|^2 / (2 N), M(y) = y + f(y), N = n_pairs
  * n_dof: the residual of the preconditioned system (Laplace only).  Two FP64
- * operator applications per pair and step.  Synchronous. */
+ * operator applications per pair and step.  Uses the operator's solver work
+ * vectors, so it must not overlap a solve on the same operator.  Synchronous. */
 igb_status igb_cnn_train_operator(igb_cnn *net, const igb_operator *op, const float *y_dev, const float *x_dev,
                                   int64_t n_pairs, int32_t epochs, int32_t batch, float lr, double *loss_host);
 

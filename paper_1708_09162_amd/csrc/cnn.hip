@@ -33,7 +33,7 @@ namespace {
 
 constexpr int kC = 32;               // hidden channels
 constexpr int kLayers = 5;
-constexpr int kTile = 16;            // convolution output tile: 32 x 16 pixels, two per thread
+constexpr int kTile = 16;            // convolution output tile: 16 RT x 16 pixels, RT per thread
 constexpr int kCiChunk = 8;          // input channels staged in LDS at a time
 constexpr int kGTH = 8, kGTW = 16;   // pixel tile of the weight-gradient kernel
 constexpr int kGBlocks = 1024;       // weight-gradient blocks (partials summed in a fixed order)
@@ -71,9 +71,13 @@ __device__ inline uint16_t float_to_bf16(float f)
 // out[n][co][y][x] = sum_ci sum_{dy,dx} w[co][ci][dy][dx] a[n][ci][y+dy-1][x+dx-1]
 // with a = relu(in) when RELU_IN, else in; zero outside the grid.  When
 // MASK_OUT, out is multiplied by (mask > 0) (the ReLU derivative of the layer
-// below, for the data gradient).  Grid: (tiles of 32 rows x 16 columns,
-// images); each thread computes the pixels (py, px) and (py + 16, px) of its
-// tile, so every weight read from LDS feeds two multiply-adds.
+// below, for the data gradient).  Grid: (tiles of 16 RT rows x 16 columns,
+// images); each thread computes the pixels (py + 16 r, px), r < RT, so every
+// weight read from LDS feeds RT multiply-adds (RT = 2 for several output
+// channels, 1 for one, where more waves matter more).
+template <int CIN, int COUT, bool RELU_IN, bool MASK_OUT>
+constexpr int conv_rows() { return COUT > 1 ? 2 : 1; }
+
 template <int CIN, int COUT, bool RELU_IN, bool MASK_OUT>
 __global__ void __launch_bounds__(256) k_conv3(const float *__restrict__ in, const uint16_t *__restrict__ wgt,
                                                float *__restrict__ out, const float *__restrict__ mask, int H, int W,
@@ -81,16 +85,19 @@ __global__ void __launch_bounds__(256) k_conv3(const float *__restrict__ in, con
 {
     constexpr int CC = CIN < kCiChunk ? CIN : kCiChunk;
     static_assert(CIN % CC == 0, "input channels in whole chunks");
-    constexpr int SH = 2 * kTile + 2, SW = kTile + 2;
+    constexpr int RT = conv_rows<CIN, COUT, RELU_IN, MASK_OUT>();
+    constexpr int SH = RT * kTile + 2, SW = kTile + 2;
     __shared__ float xs[CC][SH][SW + 1];
     __shared__ float ws[CC * 9][COUT];
     const int n = blockIdx.y;
-    const int ty0 = (blockIdx.x / tiles_x) * (2 * kTile), tx0 = (blockIdx.x % tiles_x) * kTile;
+    const int ty0 = (blockIdx.x / tiles_x) * (RT * kTile), tx0 = (blockIdx.x % tiles_x) * kTile;
     const int tid = threadIdx.x, py = tid / kTile, px = tid % kTile;
     const size_t plane = (size_t)H * W;
-    float acc0[COUT], acc1[COUT];
+    float acc[RT][COUT];
 #pragma unroll
-    for (int co = 0; co < COUT; ++co) acc0[co] = acc1[co] = 0.f;
+    for (int r = 0; r < RT; ++r)
+#pragma unroll
+        for (int co = 0; co < COUT; ++co) acc[r][co] = 0.f;
     for (int c0 = 0; c0 < CIN; c0 += CC) {
         __syncthreads();
         for (int i = tid; i < CC * SH * SW; i += 256) {
@@ -111,26 +118,27 @@ __global__ void __launch_bounds__(256) k_conv3(const float *__restrict__ in, con
         for (int cc = 0; cc < CC; ++cc) {
 #pragma unroll
             for (int t = 0; t < 9; ++t) {
-                const float x0 = xs[cc][py + t / 3][px + t % 3];
-                const float x1 = xs[cc][py + kTile + t / 3][px + t % 3];
+                float xv[RT];
+#pragma unroll
+                for (int r = 0; r < RT; ++r) xv[r] = xs[cc][py + r * kTile + t / 3][px + t % 3];
 #pragma unroll
                 for (int co = 0; co < COUT; ++co) {
                     const float wv = ws[cc * 9 + t][co];
-                    acc0[co] = fmaf(wv, x0, acc0[co]);
-                    acc1[co] = fmaf(wv, x1, acc1[co]);
+#pragma unroll
+                    for (int r = 0; r < RT; ++r) acc[r][co] = fmaf(wv, xv[r], acc[r][co]);
                 }
             }
         }
     }
     const int x = tx0 + px;
 #pragma unroll
-    for (int h2 = 0; h2 < 2; ++h2) {
-        const int y = ty0 + py + h2 * kTile;
+    for (int r = 0; r < RT; ++r) {
+        const int y = ty0 + py + r * kTile;
         if (y < H && x < W) {
             const size_t o = (size_t)n * COUT * plane + (size_t)y * W + x;
 #pragma unroll
             for (int co = 0; co < COUT; ++co) {
-                float v = h2 ? acc1[co] : acc0[co];
+                float v = acc[r][co];
                 if (MASK_OUT && !(mask[o + co * plane] > 0.f)) v = 0.f;
                 out[o + co * plane] = v;
             }
@@ -357,7 +365,8 @@ template <int CIN, int COUT, bool RELU_IN, bool MASK_OUT>
 igb_status conv(const igb_cnn *net, const float *in, const uint16_t *w, float *out, const float *mask, int nimg, int H,
                 int W)
 {
-    const int tx = (W + kTile - 1) / kTile, ty = (H + 2 * kTile - 1) / (2 * kTile);
+    constexpr int RT = conv_rows<CIN, COUT, RELU_IN, MASK_OUT>();
+    const int tx = (W + kTile - 1) / kTile, ty = (H + RT * kTile - 1) / (RT * kTile);
     hipLaunchKernelGGL((k_conv3<CIN, COUT, RELU_IN, MASK_OUT>), dim3((unsigned)(tx * ty), (unsigned)nimg), dim3(256), 0,
                        net->st, in, w, out, mask, H, W, tx);
     CNNLAUNCH();

@@ -190,11 +190,12 @@ igb_status igb_jacobi_diag(const igb_operator *op, void *d_dev);
  * on entry and the density coefficients on exit.  Stops when the true relative
  * residual ||b - A w|| <= rel_tol ||b|| or after max_iter operator
  * applications (then IGB_ENOT_CONVERGED, w = last iterate).  `restart` is the
- * GMRES cycle length (ignored by CG); short cycles can stagnate on oscillatory
- * problems (the 16-patch torus at kappa = 8, 70k dofs, stalls near 3e-5 with 100
- * and converges in about 560 applications with 300).  The basis takes
- * (restart + 1) n_dof complex values of device memory.  Synchronous; `info`
- * (host) may be NULL. */
+ * GMRES cycle length, 1..2048 (ignored by CG); short cycles can stagnate on
+ * oscillatory problems (the 16-patch torus at kappa = 8, 70k dofs, stalls near
+ * 3e-5 with 100 and converges in about 560 applications with 300).  GMRES keeps
+ * its Hessenberg matrix and rotations on the device and takes (2 restart + 1)
+ * n_dof complex values of device memory.  Synchronous; `info` (host) may be
+ * NULL. */
 igb_status igb_solve(const igb_operator *op, const void *b_dev, void *w_dev, double rel_tol, int32_t max_iter,
                      int32_t restart, igb_solve_info *info);
 

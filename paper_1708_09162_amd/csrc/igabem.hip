@@ -3513,151 +3513,36 @@ static igb_status solve_cg(igb_operator *op, const double *b, double *w, double 
     return rel <= tol ? IGB_OK : fail(IGB_ENOT_CONVERGED, "CG stopped at max_iter with relative residual " + std::to_string(rel));
 }
 
-static igb_status solve_gmres(igb_operator *op, const cd *b, cd *w, double tol, int maxit, int restart, igb_solve_info *info)
+// One Arnoldi step's bookkeeping of (flexible) GMRES, on the device: the new
+// Hessenberg column h = hA + hB (two classical Gram-Schmidt passes) with
+// h[k+1] = |v_{k+1}| (from the nvv partial sums of its squared norm), the
+// earlier Givens rotations applied to it, a new rotation that zeroes h[k+1],
+// the rotated right-hand side g, and the residual estimate |g[k+1]| / |b|.
+// G holds H ((R+1) x R, row j, column k at j*R + k), cs, sn (R each), g (R+1),
+// then the state st (doubles): |b|, 1/|v_{k+1}|, the first step count that
+// reached tol (or -1), tol.  The estimate and a converged flag go to the
+// host-mapped pair `out`.  Steps after convergence leave G as it is.  One
+// wave: the column, the rotations and the norm partials are staged in LDS by
+// all lanes, the rotations run serially on lane 0, and the lanes write back.
+template <class T> __host__ __device__ inline T from_real(double a);
+template <> __host__ __device__ inline double from_real<double>(double a) { return a; }
+template <> __host__ __device__ inline cd from_real<cd>(double a) { return {a, 0.0}; }
+__host__ __device__ inline double div_(double a, double b) { return a / b; }
+__host__ __device__ inline cd div_(cd a, cd b)
 {
-    int64_t n = op->s.ndof;
-    int R = std::max(1, std::min(restart, std::max(1, maxit)));
-    igb_status rc;
-    if (op->Vcols < R + 1) {
-        HIPCHK(hipStreamSynchronize(op->st));
-        pool_free(op->Vblk);
-        pool_free(op->hblk);
-        pool_free(op->mblk);
-        op->V = op->hdev = op->mpart = nullptr;
-        op->Vcols = 0;
-        HIPCHK(pool_alloc(op->Vblk, (size_t)(R + 1) * n * sizeof(cd)));
-        HIPCHK(pool_alloc(op->hblk, (size_t)(R + 1) * sizeof(cd)));
-        HIPCHK(pool_alloc(op->mblk, (size_t)(R + 1) * kRedBlocks * sizeof(cd)));
-        op->V = op->Vblk.p;
-        op->hdev = op->hblk.p;
-        op->mpart = op->mblk.p;
-        op->Vcols = R + 1;
-    }
-    cd *V = (cd *)op->V, *hd = (cd *)op->hdev, *t = (cd *)op->tmp, *r = (cd *)op->r, *t2 = (cd *)op->z;
-    const int mdb = multidot_blocks(n);
-    const cd *D = (const cd *)op->diag;
-    unsigned gb = std::min<unsigned>(nblk(n, 256), 1024);
-    auto norm2 = [&](const cd *x, double *out) -> igb_status {
-        igb_status c;
-        if ((c = dot_dev<cd>(op, n, x, x, (cd *)op->scal))) return c;
-        return read_scalar(op, 0, out);
-    };
-    double bn2;
-    if ((rc = norm2(b, &bn2))) return rc;
-    double bn = std::sqrt(bn2);
-    if (bn == 0.0) bn = 1.0;
-    std::vector<cd> H((size_t)(R + 1) * R), cs(R), sn(R), g(R + 1), y(R), hcol(R + 1);
-    int it = 0;
-    double rel = 0.0;
-    for (;;) {
-        if ((rc = matvec_S<cd>(op, w, t))) return rc;
-        HIPCHK(hipMemcpyAsync(r, b, n * sizeof(cd), hipMemcpyDeviceToDevice, op->st));
-        hipLaunchKernelGGL((k_axpby<cd>), dim3(gb), dim3(256), 0, op->st, n, cd{-1.0, 0.0}, t, cd{1.0, 0.0}, r);
-        LAUNCHCHK();
-        double beta2;
-        if ((rc = norm2(r, &beta2))) return rc;
-        double beta = std::sqrt(beta2);
-        rel = beta / bn;
-        if (rel <= tol || it >= maxit) break;
-        hipLaunchKernelGGL((k_axpby<cd>), dim3(gb), dim3(256), 0, op->st, n, cd{1.0 / beta, 0.0}, r, cd{0.0, 0.0}, V);
-        LAUNCHCHK();
-        std::fill(g.begin(), g.end(), cd{0.0, 0.0});
-        std::fill(H.begin(), H.end(), cd{0.0, 0.0});
-        g[0] = cd{beta, 0.0};
-        int k = 0;
-        for (; k < R && it < maxit;) {
-            cd *vk = V + (size_t)k * n, *vn = V + (size_t)(k + 1) * n;
-            hipLaunchKernelGGL((k_div<cd>), dim3(gb), dim3(256), 0, op->st, n, vk, D, t);
-            LAUNCHCHK();
-            if ((rc = matvec_S<cd>(op, t, vn))) return rc;
-            std::fill(hcol.begin(), hcol.end(), cd{0.0, 0.0});
-            for (int pass = 0; pass < 2; ++pass) {  // classical Gram-Schmidt, twice
-                hipLaunchKernelGGL((k_multidot_partial<cd>), dim3(mdb, (unsigned)((k + 4) / 4)), dim3(256), 0, op->st, n,
-                                   k + 1, V, n, vn, (cd *)op->mpart, mdb);
-                LAUNCHCHK();
-                hipLaunchKernelGGL((k_multireduce<cd>), dim3(k + 1), dim3(256), 0, op->st, k + 1, mdb,
-                                   (const cd *)op->mpart, hd);
-                LAUNCHCHK();
-                hipLaunchKernelGGL((k_sub_Vh<cd>), dim3(gb), dim3(256), 0, op->st, n, k + 1, V, n, hd, vn);
-                LAUNCHCHK();
-                std::vector<cd> hh(k + 1);
-                HIPCHK(hipMemcpyAsync(hh.data(), hd, (k + 1) * sizeof(cd), hipMemcpyDeviceToHost, op->st));
-                HIPCHK(hipStreamSynchronize(op->st));
-                for (int j = 0; j <= k; ++j) hcol[j] += hh[j];
-            }
-            double hn2;
-            if ((rc = norm2(vn, &hn2))) return rc;
-            double hn = std::sqrt(hn2);
-            hcol[k + 1] = cd{hn, 0.0};
-            if (hn > 0.0) {
-                hipLaunchKernelGGL((k_axpby<cd>), dim3(gb), dim3(256), 0, op->st, n, cd{1.0 / hn, 0.0}, vn, cd{0.0, 0.0}, vn);
-                LAUNCHCHK();
-            }
-            // Givens rotations on the new column
-            for (int j = 0; j < k; ++j) {
-                cd a = hcol[j], bb = hcol[j + 1];
-                hcol[j] = conj_(cs[j]) * a + conj_(sn[j]) * bb;
-                hcol[j + 1] = cd{-1.0, 0.0} * sn[j] * a + cs[j] * bb;
-            }
-            cd a = hcol[k], bb = hcol[k + 1];
-            double den = std::sqrt(abs2(a) + abs2(bb));
-            cs[k] = a * (1.0 / den);
-            sn[k] = bb * (1.0 / den);
-            hcol[k] = cd{den, 0.0};
-            hcol[k + 1] = cd{0.0, 0.0};
-            g[k + 1] = cd{-1.0, 0.0} * sn[k] * g[k];
-            g[k] = conj_(cs[k]) * g[k];
-            for (int j = 0; j <= k; ++j) H[(size_t)j * R + k] = hcol[j];
-            ++k;
-            ++it;
-            if (std::sqrt(abs2(g[k])) / bn <= tol) break;
-        }
-        // y = H^-1 g (upper triangular k x k), w += D^-1 V y
-        for (int j = k - 1; j >= 0; --j) {
-            cd s = g[j];
-            for (int l = j + 1; l < k; ++l) s -= H[(size_t)j * R + l] * y[l];
-            cd d = H[(size_t)j * R + j];
-            double den = abs2(d);
-            y[j] = cd{(s.re * d.re + s.im * d.im) / den, (s.im * d.re - s.re * d.im) / den};
-        }
-        std::vector<cd> ny(k);
-        for (int j = 0; j < k; ++j) ny[j] = cd{-y[j].re, -y[j].im};
-        HIPCHK(hipMemcpyAsync(hd, ny.data(), k * sizeof(cd), hipMemcpyHostToDevice, op->st));
-        HIPCHK(hipMemsetAsync(t, 0, n * sizeof(cd), op->st));
-        hipLaunchKernelGGL((k_sub_Vh<cd>), dim3(gb), dim3(256), 0, op->st, n, k, V, n, hd, t);
-        LAUNCHCHK();
-        hipLaunchKernelGGL((k_div<cd>), dim3(gb), dim3(256), 0, op->st, n, t, D, t2);
-        LAUNCHCHK();
-        hipLaunchKernelGGL((k_axpby<cd>), dim3(gb), dim3(256), 0, op->st, n, cd{1.0, 0.0}, t2, cd{1.0, 0.0}, w);
-        LAUNCHCHK();
-        HIPCHK(hipStreamSynchronize(op->st));
-    }
-    if (info) {
-        info->iterations = it;
-        info->rel_residual = rel;
-        info->converged = rel <= tol;
-    }
-    return rel <= tol ? IGB_OK : fail(IGB_ENOT_CONVERGED, "GMRES stopped at max_iter with relative residual " + std::to_string(rel));
+    const double d = b.re * b.re + b.im * b.im;
+    return {(a.re * b.re + a.im * b.im) / d, (a.im * b.re - a.re * b.im) / d};
 }
 
-// One Arnoldi step's bookkeeping of flexible GMRES, on the device (one thread):
-// the new Hessenberg column h = hA + hB (two classical Gram-Schmidt passes) with
-// h[k+1] = |v_{k+1}| (from the nvv partial sums of its squared norm), the earlier Givens rotations
-// applied to it, a new rotation that zeroes h[k+1], the rotated right-hand side
-// g, and the residual estimate |g[k+1]| / |b|.  G holds H ((R+1) x R, row j,
-// column k at j*R + k), cs, sn (R each), g (R+1) and the state st: |b|, 1/|v_{k+1}|,
-// the first step count that reached tol (or -1), tol.  The estimate and a
-// converged flag go to the host-mapped pair `out`.  Steps after convergence
-// leave G as it is.
-__global__ void __launch_bounds__(64) k_arnoldi(int k, int R, const double *__restrict__ hA,
-                                                 const double *__restrict__ hB, const double *__restrict__ vv, int nvv,
-                                                 double *__restrict__ G, double *__restrict__ out)
+template <class T>
+__global__ void __launch_bounds__(64) k_arnoldi(int k, int R, const T *__restrict__ hA, const T *__restrict__ hB,
+                                                 const double *__restrict__ vv, int nvv, T *__restrict__ G,
+                                                 double *__restrict__ out)
 {
-    // one wave: the column, the rotations and the norm partials are staged in LDS
-    // by all lanes, the rotations run serially on lane 0, and the lanes write back
     extern __shared__ double sm[];
-    double *col = sm, *c = col + k + 2, *sv = c + k + 1;
-    double *H = G, *cs = G + (size_t)(R + 1) * R, *sn = cs + R, *g = sn + R, *st = g + R + 1;
+    T *col = (T *)sm, *c = col + k + 2, *sv = c + k + 1;
+    T *H = G, *cs = G + (size_t)(R + 1) * R, *sn = cs + R, *g = sn + R;
+    double *st = (double *)(g + R + 1);
     const int lane = threadIdx.x;
     if (st[2] >= 0.0) {  // converged at an earlier step
         if (lane == 0) {
@@ -3679,19 +3564,21 @@ __global__ void __launch_bounds__(64) k_arnoldi(int k, int R, const double *__re
         const double hn = sqrt(v2);
         st[1] = hn > 0.0 ? 1.0 / hn : 0.0;
         for (int j = 0; j < k; ++j) {
-            const double a = col[j], b = col[j + 1];
-            col[j] = c[j] * a + sv[j] * b;
-            col[j + 1] = -sv[j] * a + c[j] * b;
+            const T a = col[j], b = col[j + 1];
+            col[j] = conj_(c[j]) * a + conj_(sv[j]) * b;
+            col[j + 1] = c[j] * b - sv[j] * a;
         }
-        const double a = col[k], den = hypot(a, hn);
-        const double ck = den > 0.0 ? a / den : 1.0, sk = den > 0.0 ? hn / den : 0.0;
+        const T a = col[k];
+        const double den = sqrt(abs2(a) + hn * hn);
+        const T ck = den > 0.0 ? a * (1.0 / den) : from_real<T>(1.0);
+        const T sk = from_real<T>(den > 0.0 ? hn / den : 0.0);
         cs[k] = ck;
         sn[k] = sk;
-        col[k] = den;
-        const double gk = g[k];
-        g[k + 1] = -sk * gk;
-        g[k] = ck * gk;
-        const double res = fabs(g[k + 1]) / st[0];
+        col[k] = from_real<T>(den);
+        const T gk = g[k];
+        g[k + 1] = zero<T>() - sk * gk;
+        g[k] = conj_(ck) * gk;
+        const double res = sqrt(abs2(g[k + 1])) / st[0];
         const bool conv = res <= st[3];
         if (conv) st[2] = k + 1;
         out[0] = res;
@@ -3701,26 +3588,31 @@ __global__ void __launch_bounds__(64) k_arnoldi(int k, int R, const double *__re
     for (int j = lane; j <= k; j += 64) H[(size_t)j * R + k] = col[j];
 }
 
-// x *= *alpha (alpha on the device); with D, also z = x / D (the next Jacobi direction)
-__global__ void k_scale_dev(int64_t n, const double *__restrict__ alpha, double *__restrict__ x,
-                            const double *__restrict__ D, double *__restrict__ z)
+// x *= *alpha (alpha real, on the device); with z, also z = x / D (the next
+// Jacobi direction)
+template <class T>
+__global__ void k_scale_dev(int64_t n, const double *__restrict__ alpha, T *__restrict__ x, const T *__restrict__ D,
+                            T *__restrict__ z)
 {
     const double a = *alpha;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        const double v = x[i] * a;
+        const T v = x[i] * a;
         x[i] = v;
-        if (z) z[i] = v / D[i];
+        if (z) z[i] = div_(v, D[i]);
     }
 }
 
-// Flexible GMRES (right preconditioned; the preconditioned directions z_k are
-// kept, since a network is not a fixed linear map), classical Gram-Schmidt
-// applied twice, Givens rotations on the device.  The host keeps at most two
-// steps in flight and reads each step's residual estimate from mapped memory,
-// so the device never waits for it; the small triangular solve runs on the host
-// once per restart cycle.  The operator runs in FP64 throughout.
-static igb_status solve_fgmres(igb_operator *op, const igb_cnn *net, const double *b, double *w, double tol, int maxit,
-                               int restart, igb_solve_info *info)
+// GMRES, right preconditioned in the flexible form (the preconditioned
+// directions z_k are kept, since a network is not a fixed linear map; with
+// Jacobi it is plain right-preconditioned GMRES), classical Gram-Schmidt applied
+// twice, Givens rotations on the device.  The host keeps at most two steps in
+// flight and reads each step's residual estimate from mapped memory, so the
+// device never waits for it; the small triangular solve runs on the host once
+// per restart cycle.  Real (Laplace, optionally with a network) and complex
+// (Helmholtz, Jacobi) systems; the operator runs in FP64 throughout.
+template <class T>
+static igb_status solve_gmres_dev(igb_operator *op, const igb_cnn *net, const T *b, T *w, double tol, int maxit,
+                                  int restart, igb_solve_info *info)
 {
     const Setup &s = op->s;
     const int64_t n = s.ndof;
@@ -3732,7 +3624,7 @@ static igb_status solve_fgmres(igb_operator *op, const igb_cnn *net, const doubl
         ~Restore() { o->force_fp64 = v; }
     } restore{op, op->force_fp64};
     op->force_fp64 = true;
-    const size_t gsz = (size_t)(R + 1) * R + 3 * (size_t)R + 1 + 8;
+    const size_t gT = (size_t)(R + 1) * R + 3 * (size_t)R + 1;  // H, cs, sn, g
     if (op->Vcols < R + 1 || op->Zcols < R) {
         HIPCHK(hipStreamSynchronize(op->st));
         pool_free(op->Vblk);
@@ -3742,37 +3634,41 @@ static igb_status solve_fgmres(igb_operator *op, const igb_cnn *net, const doubl
         pool_free(op->mblk);
         op->V = op->hdev = op->mpart = nullptr;
         op->Vcols = op->Zcols = 0;
-        HIPCHK(pool_alloc(op->Vblk, (size_t)(R + 1) * n * sizeof(double)));
-        HIPCHK(pool_alloc(op->Zblk, (size_t)R * n * sizeof(double)));
-        HIPCHK(pool_alloc(op->Gblk, gsz * sizeof(double)));
-        HIPCHK(pool_alloc(op->hblk, 2 * (size_t)(R + 1) * sizeof(double)));
-        HIPCHK(pool_alloc(op->mblk, (size_t)(R + 1) * kRedBlocks * sizeof(double)));
+        HIPCHK(pool_alloc(op->Vblk, (size_t)(R + 1) * n * sizeof(T)));
+        HIPCHK(pool_alloc(op->Zblk, (size_t)R * n * sizeof(T)));
+        HIPCHK(pool_alloc(op->Gblk, gT * sizeof(T) + 8 * sizeof(double)));
+        HIPCHK(pool_alloc(op->hblk, 2 * (size_t)(R + 1) * sizeof(T)));
+        HIPCHK(pool_alloc(op->mblk, (size_t)(R + 1) * kRedBlocks * sizeof(T)));
         op->V = op->Vblk.p;
         op->hdev = op->hblk.p;
         op->mpart = op->mblk.p;
         op->Vcols = R + 1;
         op->Zcols = R;
     }
-    double *V = (double *)op->V, *Z = (double *)op->Zblk.p, *G = (double *)op->Gblk.p, *t = (double *)op->tmp,
-           *r = (double *)op->r;
-    double *hA = (double *)op->hdev, *hB = hA + R + 1, *st = G + (size_t)(R + 1) * R + 2 * (size_t)R + R + 1;
-    const double *D = (const double *)op->diag;
+    T *V = (T *)op->V, *Z = (T *)op->Zblk.p, *G = (T *)op->Gblk.p, *t = (T *)op->tmp, *r = (T *)op->r;
+    T *hA = (T *)op->hdev, *hB = hA + R + 1, *gdev = G + (size_t)(R + 1) * R + 2 * (size_t)R;
+    double *st = (double *)(gdev + R + 1);
+    const T *D = (const T *)op->diag;
     const unsigned gb = std::min<unsigned>(nblk(n, 256), 1024);
     const int mdb = multidot_blocks(n);
     const unsigned gsub = std::min<unsigned>(nblk(n, 256), 256);  // k_sub_Vh_red blocks (norm partials)
-    double *nrm = (double *)op->part;                             // kRedBlocks >= gsub doubles
+    double *nrm = (double *)op->part;                             // 3 kRedBlocks >= gsub doubles
+    if (sizeof(T) * (3 * (size_t)R + 4) > 64 * 1024)
+        (void)hipFuncSetAttribute((const void *)k_arnoldi<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)(sizeof(T) * (3 * (size_t)R + 4)));
     double *hout = nullptr;  // two (estimate, converged) slots of mapped host memory, device view
     HIPCHK(hipHostGetDevicePointer((void **)&hout, op->h_scal + 12, 0));
-    auto norm2 = [&](const double *x, double *out) -> igb_status {
+    auto norm2 = [&](const T *x, double *out) -> igb_status {
         igb_status c;
-        if ((c = dot_dev<double>(op, n, x, x, op->scal))) return c;
-        return read_scalar(op, 0, out);
+        if ((c = dot_dev<T>(op, n, x, x, (T *)op->scal))) return c;
+        return read_scalar(op, 0, out);  // real part
     };
     double bn2;
     if ((rc = norm2(b, &bn2))) return rc;
     double bn = std::sqrt(bn2);
     if (bn == 0.0) bn = 1.0;
-    std::vector<double> H((size_t)(R + 1) * R), gh(R + 1), y(R), init(2 * (size_t)R + 2 + 8, 0.0);
+    std::vector<T> H((size_t)(R + 1) * R), gh(R + 1), y(R), ginit(R + 1);
+    std::vector<double> stinit(8, 0.0);
     hipEvent_t ev[2] = {nullptr, nullptr};
     if (hipEventCreateWithFlags(&ev[0], hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&ev[1], hipEventDisableTiming) != hipSuccess) {
@@ -3786,55 +3682,58 @@ static igb_status solve_fgmres(igb_operator *op, const igb_cnn *net, const doubl
     int it = 0;
     double rel = 0.0;
     for (;;) {
-        if ((rc = matvec_S<double>(op, w, t))) return rc;
-        HIPCHK(hipMemcpyAsync(r, b, n * sizeof(double), hipMemcpyDeviceToDevice, op->st));
-        hipLaunchKernelGGL((k_axpby<double>), dim3(gb), dim3(256), 0, op->st, n, -1.0, (const double *)t, 1.0, r);
+        if ((rc = matvec_S<T>(op, w, t))) return rc;
+        HIPCHK(hipMemcpyAsync(r, b, n * sizeof(T), hipMemcpyDeviceToDevice, op->st));
+        hipLaunchKernelGGL((k_axpby<T>), dim3(gb), dim3(256), 0, op->st, n, from_real<T>(-1.0), (const T *)t,
+                           from_real<T>(1.0), r);
         LAUNCHCHK();
         double beta2;
         if ((rc = norm2(r, &beta2))) return rc;
         const double beta = std::sqrt(beta2);
         rel = beta / bn;
         if (rel <= tol || it >= maxit) break;
-        hipLaunchKernelGGL((k_axpby<double>), dim3(gb), dim3(256), 0, op->st, n, 1.0 / beta, (const double *)r, 0.0, V);
+        hipLaunchKernelGGL((k_axpby<T>), dim3(gb), dim3(256), 0, op->st, n, from_real<T>(1.0 / beta), (const T *)r,
+                           zero<T>(), V);
         LAUNCHCHK();
         // g = (beta, 0, ...), state = (|b|, -, not converged, tol); the stream is idle here
-        std::fill(init.begin(), init.end(), 0.0);
-        init[0] = beta;
-        double *sti = init.data() + R + 1;
-        sti[0] = bn;
-        sti[2] = -1.0;
-        sti[3] = tol;
-        HIPCHK(hipMemcpyAsync(G + (size_t)(R + 1) * R + 2 * (size_t)R, init.data(), (R + 1 + 8) * sizeof(double),
-                              hipMemcpyHostToDevice, op->st));
+        std::fill(ginit.begin(), ginit.end(), zero<T>());
+        ginit[0] = from_real<T>(beta);
+        stinit[0] = bn;
+        stinit[2] = -1.0;
+        stinit[3] = tol;
+        HIPCHK(hipMemcpyAsync(gdev, ginit.data(), (R + 1) * sizeof(T), hipMemcpyHostToDevice, op->st));
+        HIPCHK(hipMemcpyAsync(st, stinit.data(), 8 * sizeof(double), hipMemcpyHostToDevice, op->st));
         const int kmax = std::min(R, maxit - it);
         int launched = 0, examined = 0, kuse = -1;
         rc = IGB_OK;
         while (true) {
             if (launched < kmax && launched - examined < 2) {
                 const int k = launched;
-                double *vk = V + (size_t)k * n, *vn = V + (size_t)(k + 1) * n, *zk = Z + (size_t)k * n;
-                if (net) {
-                    if ((rc = cnn_precondition(net, s.npatch, s.ns1, s.ns1, vk, D, zk, op->st))) break;
-                } else if (k == 0) {
-                    hipLaunchKernelGGL((k_div<double>), dim3(gb), dim3(256), 0, op->st, n, (const double *)vk, D, zk);
-                }  // else z_k = D^-1 v_k was formed when v_k was normalised
-                if ((rc = matvec_S<double>(op, zk, vn))) break;
+                T *vk = V + (size_t)k * n, *vn = V + (size_t)(k + 1) * n, *zk = Z + (size_t)k * n;
+                if constexpr (std::is_same<T, double>::value) {
+                    if (net) {
+                        if ((rc = cnn_precondition(net, s.npatch, s.ns1, s.ns1, vk, D, zk, op->st))) break;
+                    }
+                }
+                if (!net && k == 0)
+                    hipLaunchKernelGGL((k_div<T>), dim3(gb), dim3(256), 0, op->st, n, (const T *)vk, D, zk);
+                // else (Jacobi) z_k = D^-1 v_k was formed when v_k was normalised
+                if ((rc = matvec_S<T>(op, zk, vn))) break;
                 for (int pass = 0; pass < 2; ++pass) {
-                    double *hp = pass ? hB : hA;
-                    hipLaunchKernelGGL((k_multidot_partial<double>), dim3(mdb, (unsigned)((k + 4) / 4)), dim3(256), 0,
-                                       op->st, n, k + 1, (const double *)V, n, (const double *)vn, (double *)op->mpart,
-                                       mdb);
-                    hipLaunchKernelGGL((k_sub_Vh_red<double>), dim3(gsub), dim3(256), (size_t)(k + 1) * sizeof(double),
-                                       op->st, n, k + 1, (const double *)V, n, (const double *)op->mpart, mdb, hp, vn,
+                    T *hp = pass ? hB : hA;
+                    hipLaunchKernelGGL((k_multidot_partial<T>), dim3(mdb, (unsigned)((k + 4) / 4)), dim3(256), 0,
+                                       op->st, n, k + 1, (const T *)V, n, (const T *)vn, (T *)op->mpart, mdb);
+                    hipLaunchKernelGGL((k_sub_Vh_red<T>), dim3(gsub), dim3(256), (size_t)(k + 1) * sizeof(T), op->st, n,
+                                       k + 1, (const T *)V, n, (const T *)op->mpart, mdb, hp, vn,
                                        pass ? nrm : (double *)nullptr);
                 }
-                hipLaunchKernelGGL(k_arnoldi, dim3(1), dim3(64), (size_t)(3 * k + 4) * sizeof(double), op->st, k, R,
-                                   (const double *)hA,
-                                   (const double *)hB, (const double *)nrm, (int)gsub, G, hout + 2 * (k & 1));
-                double *znext = (!net && k + 1 < kmax) ? Z + (size_t)(k + 1) * n : nullptr;
-                hipLaunchKernelGGL(k_scale_dev, dim3(gb), dim3(256), 0, op->st, n, (const double *)(st + 1), vn, D, znext);
+                hipLaunchKernelGGL((k_arnoldi<T>), dim3(1), dim3(64), (size_t)(3 * k + 4) * sizeof(T), op->st, k, R,
+                                   (const T *)hA, (const T *)hB, (const double *)nrm, (int)gsub, G, hout + 2 * (k & 1));
+                T *znext = (!net && k + 1 < kmax) ? Z + (size_t)(k + 1) * n : nullptr;
+                hipLaunchKernelGGL((k_scale_dev<T>), dim3(gb), dim3(256), 0, op->st, n, (const double *)(st + 1), vn, D,
+                                   znext);
                 if (hipGetLastError() != hipSuccess || hipEventRecord(ev[k & 1], op->st) != hipSuccess) {
-                    rc = fail(IGB_EHIP, "FGMRES kernel launch");
+                    rc = fail(IGB_EHIP, "GMRES kernel launch");
                     break;
                 }
                 ++launched;
@@ -3857,18 +3756,16 @@ static igb_status solve_fgmres(igb_operator *op, const igb_cnn *net, const doubl
         const int k = kuse > 0 ? kuse : examined;
         it += k;
         // y = H^-1 g (upper triangular k x k); w += Z y
-        HIPCHK(hipMemcpy(H.data(), G, (size_t)k * R * sizeof(double), hipMemcpyDeviceToHost));
-        HIPCHK(hipMemcpy(gh.data(), G + (size_t)(R + 1) * R + 2 * (size_t)R, (R + 1) * sizeof(double),
-                         hipMemcpyDeviceToHost));
+        HIPCHK(hipMemcpy(H.data(), G, (size_t)k * R * sizeof(T), hipMemcpyDeviceToHost));
+        HIPCHK(hipMemcpy(gh.data(), gdev, (R + 1) * sizeof(T), hipMemcpyDeviceToHost));
         for (int j = k - 1; j >= 0; --j) {
-            double sum = gh[j];
+            T sum = gh[j];
             for (int l = j + 1; l < k; ++l) sum -= H[(size_t)j * R + l] * y[l];
-            y[j] = sum / H[(size_t)j * R + j];
+            y[j] = div_(sum, H[(size_t)j * R + j]);
         }
-        for (int j = 0; j < k; ++j) y[j] = -y[j];
-        HIPCHK(hipMemcpyAsync(hA, y.data(), k * sizeof(double), hipMemcpyHostToDevice, op->st));
-        hipLaunchKernelGGL((k_sub_Vh<double>), dim3(gb), dim3(256), 0, op->st, n, k, (const double *)Z, n,
-                           (const double *)hA, w);
+        for (int j = 0; j < k; ++j) y[j] = zero<T>() - y[j];
+        HIPCHK(hipMemcpyAsync(hA, y.data(), k * sizeof(T), hipMemcpyHostToDevice, op->st));
+        hipLaunchKernelGGL((k_sub_Vh<T>), dim3(gb), dim3(256), 0, op->st, n, k, (const T *)Z, n, (const T *)hA, w);
         LAUNCHCHK();
         HIPCHK(hipStreamSynchronize(op->st));
     }
@@ -3878,7 +3775,7 @@ static igb_status solve_fgmres(igb_operator *op, const igb_cnn *net, const doubl
         info->converged = rel <= tol;
     }
     return rel <= tol ? IGB_OK
-                      : fail(IGB_ENOT_CONVERGED, "FGMRES stopped at max_iter with relative residual " + std::to_string(rel));
+                      : fail(IGB_ENOT_CONVERGED, "GMRES stopped at max_iter with relative residual " + std::to_string(rel));
 }
 
 __global__ void k_err64(int64_t n, const float *__restrict__ y, const float *__restrict__ f, const float *__restrict__ x,
@@ -4145,8 +4042,8 @@ igb_status igb_solve(const igb_operator *cop, const void *b_dev, void *w_dev, do
     if (!(rel_tol > 0.0) || max_iter < 0) return fail(IGB_EINVAL, "rel_tol must be > 0 and max_iter >= 0");
     igb_operator *op = const_cast<igb_operator *>(cop);
     if (op->cplx) {
-        if (restart < 1) return fail(IGB_EINVAL, "restart must be >= 1");
-        return solve_gmres(op, (const cd *)b_dev, (cd *)w_dev, rel_tol, max_iter, restart, info);
+        if (restart < 1 || restart > 2048) return fail(IGB_EINVAL, "restart must be in 1..2048");
+        return solve_gmres_dev<cd>(op, nullptr, (const cd *)b_dev, (cd *)w_dev, rel_tol, max_iter, restart, info);
     }
     return solve_cg(op, (const double *)b_dev, (double *)w_dev, rel_tol, max_iter, info);
 }
@@ -4219,7 +4116,7 @@ igb_status igb_solve_fgmres(const igb_operator *cop, const igb_cnn *net, const v
     if (restart < 1 || restart > 2048) return fail(IGB_EINVAL, "restart must be in 1..2048");
     igb_operator *op = const_cast<igb_operator *>(cop);
     if (op->cplx) return fail(IGB_EUNSUPPORTED, "flexible GMRES is built for real (Laplace) operators");
-    return solve_fgmres(op, net, (const double *)b_dev, (double *)w_dev, rel_tol, max_iter, restart, info);
+    return solve_gmres_dev<double>(op, net, (const double *)b_dev, (double *)w_dev, rel_tol, max_iter, restart, info);
 }
 
 igb_status igb_cnn_train_operator(igb_cnn *net, const igb_operator *cop, const float *y_dev, const float *x_dev,

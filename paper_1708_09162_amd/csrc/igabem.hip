@@ -3653,9 +3653,13 @@ static igb_status solve_gmres_dev(igb_operator *op, const igb_cnn *net, const T 
     const int mdb = multidot_blocks(n);
     const unsigned gsub = std::min<unsigned>(nblk(n, 256), 256);  // k_sub_Vh_red blocks (norm partials)
     double *nrm = (double *)op->part;                             // 3 kRedBlocks >= gsub doubles
-    if (sizeof(T) * (3 * (size_t)R + 4) > 64 * 1024)
-        (void)hipFuncSetAttribute((const void *)k_arnoldi<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  (int)(sizeof(T) * (3 * (size_t)R + 4)));
+    // the Givens step stages 3 k + 4 values in LDS: above 64 KB (complex cycles longer than 1365) the
+    // launch needs the larger limit of gfx950 (160 KB per workgroup) granted explicitly
+    if (sizeof(T) * (3 * (size_t)R + 4) > 64 * 1024 &&
+        hipFuncSetAttribute((const void *)k_arnoldi<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)(sizeof(T) * (3 * (size_t)R + 4))) != hipSuccess)
+        return fail(IGB_EHIP, "hipFuncSetAttribute: GMRES restart " + std::to_string(R) + " needs " +
+                                  std::to_string(sizeof(T) * (3 * (size_t)R + 4)) + " bytes of LDS");
     double *hout = nullptr;  // two (estimate, converged) slots of mapped host memory, device view
     HIPCHK(hipHostGetDevicePointer((void **)&hout, op->h_scal + 12, 0));
     auto norm2 = [&](const T *x, double *out) -> igb_status {

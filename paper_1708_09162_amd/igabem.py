@@ -8,6 +8,7 @@ cannot be loaded, importing this module raises.
 """
 from __future__ import annotations
 
+import contextlib
 import ctypes as C
 import os
 
@@ -422,7 +423,28 @@ class Geometry:
             self.h = None
 
 
-class Operator:
+class _StreamOrdered:
+    """Orders the object's HIP stream against torch's current stream around each library call.
+
+    Inputs and zero-filled outputs are made on the current stream; the library works on the object's
+    stream.  Before a call the object's stream waits for the current one, and after it the current stream
+    waits for the object's, so results can be used on the current stream without a host synchronisation
+    and temporaries freed on the current stream are not reused before the library is done with them."""
+
+    @contextlib.contextmanager
+    def _ordered(self):
+        cur = self.torch.cuda.current_stream(self.device)
+        other = cur.cuda_stream != self.stream.cuda_stream
+        if other:
+            self.stream.wait_stream(cur)
+        try:
+            yield
+        finally:
+            if other:
+                cur.wait_stream(self.stream)
+
+
+class Operator(_StreamOrdered):
     """An assembled single-layer operator on the current torch CUDA (HIP) stream."""
 
     def __init__(self, geometry: Geometry, *, kernel=IGB_LAPLACE, wavenumber=0.0, p=1, m=2, q=8, eta=1.6,
@@ -460,49 +482,59 @@ class Operator:
 
     def rhs_points(self):
         xyz = self.torch.zeros((self.info.n_rhs_points, 3), dtype=self.torch.float64, device=self.device)
-        igb_rhs_points(self.h, xyz)
+        with self._ordered():
+            igb_rhs_points(self.h, xyz)
         return xyz
 
     def rhs(self, g):
-        b = self._vec(self.info.n_dof)
-        igb_rhs_assemble(self.h, self._in(g, self.info.n_rhs_points), b)
+        b, g = self._vec(self.info.n_dof), self._in(g, self.info.n_rhs_points)
+        with self._ordered():
+            igb_rhs_assemble(self.h, g, b)
         return b
 
     def matvec(self, x):
-        y = self._vec(self.info.n_dof)
-        igb_matvec(self.h, self._in(x, self.info.n_dof), y)
+        y, x = self._vec(self.info.n_dof), self._in(x, self.info.n_dof)
+        with self._ordered():
+            igb_matvec(self.h, x, y)
         return y
 
     def matvec_super(self, xs):
-        ys = self._vec(self.info.n_dof_super)
-        igb_matvec_super(self.h, self._in(xs, self.info.n_dof_super), ys)
+        ys, xs = self._vec(self.info.n_dof_super), self._in(xs, self.info.n_dof_super)
+        with self._ordered():
+            igb_matvec_super(self.h, xs, ys)
         return ys
 
     def apply_Tt(self, w):
-        xs = self._vec(self.info.n_dof_super)
-        igb_apply_Tt(self.h, self._in(w, self.info.n_dof), xs)
+        xs, w = self._vec(self.info.n_dof_super), self._in(w, self.info.n_dof)
+        with self._ordered():
+            igb_apply_Tt(self.h, w, xs)
         return xs
 
     def apply_T(self, ys):
-        y = self._vec(self.info.n_dof)
-        igb_apply_T(self.h, self._in(ys, self.info.n_dof_super), y)
+        y, ys = self._vec(self.info.n_dof), self._in(ys, self.info.n_dof_super)
+        with self._ordered():
+            igb_apply_T(self.h, ys, y)
         return y
 
     def jacobi_diag(self):
         d = self._vec(self.info.n_dof)
-        igb_jacobi_diag(self.h, d)
+        with self._ordered():
+            igb_jacobi_diag(self.h, d)
         return d
 
     def solve(self, b, w0=None, tol=1e-8, max_iter=1000, restart=300):
         w = self._vec(self.info.n_dof) if w0 is None else self._in(w0, self.info.n_dof).clone()
-        info = igb_solve(self.h, self._in(b, self.info.n_dof), w, tol, max_iter, restart)
+        b = self._in(b, self.info.n_dof)
+        with self._ordered():
+            info = igb_solve(self.h, b, w, tol, max_iter, restart)
         return w, info
 
     def solve_fgmres(self, b, net=None, w0=None, tol=1e-8, max_iter=1000, restart=100):
         """Flexible GMRES with the network preconditioner `net` (a CNN), or Jacobi when net is None."""
         w = self._vec(self.info.n_dof) if w0 is None else self._in(w0, self.info.n_dof).clone()
-        info = igb_solve_fgmres(self.h, net.h if net is not None else None, self._in(b, self.info.n_dof), w, tol,
-                                max_iter, restart)
+        b = self._in(b, self.info.n_dof)
+        with self._ordered():
+            info = igb_solve_fgmres(self.h, net.h if net is not None else None, b, w, tol, max_iter, restart)
         return w, info
 
     @property
@@ -519,13 +551,15 @@ class Operator:
             raise ValueError("x must be n_pairs x n_dof")
         y32 = self.torch.empty((n_pairs, self.info.n_dof), dtype=self.torch.float32, device=self.device)
         x32 = self.torch.empty_like(y32)
-        igb_cnn_training_pairs(self.h, x, n_pairs, y32, x32)
+        with self._ordered():
+            igb_cnn_training_pairs(self.h, x, n_pairs, y32, x32)
         return y32, x32
 
     def potential(self, w, points):
         pts = self.torch.as_tensor(points, dtype=self.torch.float64).to(self.device).reshape(-1, 3).contiguous()
-        u = self._vec(pts.shape[0])
-        igb_potential(self.h, self._in(w, self.info.n_dof), pts, u)
+        u, w = self._vec(pts.shape[0]), self._in(w, self.info.n_dof)
+        with self._ordered():
+            igb_potential(self.h, w, pts, u)
         return u
 
     def profile(self, reps=10, separate=False):
@@ -546,7 +580,7 @@ class Operator:
         return igb_export_coupling_block(self.h, level, tgt, src, self.q * self.q, self.cplx)
 
 
-class CNN:
+class CNN(_StreamOrdered):
     """The learned preconditioner's network on the current torch CUDA (HIP) stream."""
 
     def __init__(self, weights, activation=IGB_CNN_RELU, device="cuda:0"):
@@ -574,19 +608,24 @@ class CNN:
         """x + f(x) for n_img images of h x w."""
         x = self._f32(x)
         out = self.torch.empty_like(x)
-        igb_cnn_forward(self.h, x, n_img, h, w, out)
+        with self._ordered():
+            igb_cnn_forward(self.h, x, n_img, h, w, out)
         return out
 
     def gradient(self, x, target, n_img, h, w):
         """(loss, gradient with respect to the weights) of one batch."""
-        return igb_cnn_gradient(self.h, self._f32(x), self._f32(target), n_img, h, w)
+        x, target = self._f32(x), self._f32(target)
+        with self._ordered():
+            return igb_cnn_gradient(self.h, x, target, n_img, h, w)
 
     def train(self, y32, x32, imgs_per_pair, h, w, epochs=5, batch=16, lr=1e-3):
         """Adam over the (y, x) pairs (rows of y32, x32); returns the mean loss of each epoch."""
         y32, x32 = self._f32(y32), self._f32(x32)
-        return igb_cnn_train(self.h, y32, x32, y32.shape[0], imgs_per_pair, h, w, epochs, batch, lr)
+        with self._ordered():
+            return igb_cnn_train(self.h, y32, x32, y32.shape[0], imgs_per_pair, h, w, epochs, batch, lr)
 
     def train_operator(self, op, y32, x32, epochs=5, batch=16, lr=1e-3):
         """Adam on the preconditioned residual |D^-1 A (M(y) - x)|^2 of operator `op` over the pairs."""
         y32, x32 = self._f32(y32), self._f32(x32)
-        return igb_cnn_train_operator(self.h, op.h, y32, x32, y32.shape[0], epochs, batch, lr)
+        with self._ordered(), op._ordered():
+            return igb_cnn_train_operator(self.h, op.h, y32, x32, y32.shape[0], epochs, batch, lr)

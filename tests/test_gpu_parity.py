@@ -486,3 +486,51 @@ def test_full_size_helmholtz_torus_sampled_rows():
                 E = pt * ne * ne + (k2 * side + a2) * ne + k1 * side + a1
                 got.append(ys[E * nloc:(E + 1) * nloc])
     assert rel(np.concatenate(got), rows.reshape(-1)) < 1e-12
+
+
+def test_operator_on_its_own_stream_is_ordered_against_current_stream():
+    """An operator created with its own stream: inputs produced by long work still queued on torch's current
+    stream, and outputs read on that stream, with no host synchronisation in between.  The binding makes the
+    operator's stream wait for the current one before each call and the current one wait after it."""
+    say("own stream: sphere p=1 m=3 q=4 onthefly")
+    kw = dict(p=1, m=3, q=4, leaf_depth=1, eta=1.6, gauss_regular=6)
+    s = torch.cuda.Stream()
+    op = igb.Operator(igb.Geometry(W.sphere_patches()), mode=igb.IGB_H2_ONTHEFLY, device=DEV, stream=s, **kw)
+    P = oracle.Problem(W.sphere_patches(), **kw)
+    P.h2_assemble(store_coupling=True)
+    torch.cuda.synchronize()
+    xs = rand(P.nsup, 21)
+    big = torch.randn(3072, 3072, dtype=torch.float32, device=DEV)
+    for rep in range(2):
+        acc = big
+        for _ in range(12):  # a few tens of ms of work on the current stream
+            acc = torch.tanh(acc @ big * 1e-3)
+        x = torch.tensor(xs, device=DEV) + 0.0 * acc[0, 0].double()
+        ys = op.matvec_super(x).cpu().numpy()  # copy ordered on the current stream only
+        assert rel(ys, P.h2_matvec_super(xs)) < 1e-12, rep
+        pts = op.rhs_points()
+        g = torch.ones(pts.shape[0], dtype=torch.float64, device=DEV) + 0.0 * torch.tanh(acc @ big)[0, 0].double()
+        b = op.rhs(g).cpu().numpy()
+        assert rel(b, P.rhs(np.ones(P.nrhs))) < 1e-12, rep
+
+
+@pytest.mark.parametrize("restart", [7, 2048])
+def test_helmholtz_h2_gmres_density_parity(restart):
+    """The device-side complex GMRES on an H2 operator against the oracle's GMRES on the same operator
+    (torus, kappa = 2, p = 1, 4x4 elements per patch, q = 4, far field on the fly), both to relative residual
+    1e-13: density within 1e-10.  Restart 7 runs many cycles; restart 2048 needs the enlarged LDS limit of
+    the Givens step (3 * 2048 + 4 complex values)."""
+    say(f"helmholtz h2 gmres density: torus k=2 p=1 m=2 q=4 restart {restart}")
+    op, P = make(W.torus_patches(), mode=igb.IGB_H2_ONTHEFLY, kernel=igb.IGB_HELMHOLTZ, wavenumber=2.0, p=1, m=2,
+                 q=4, leaf_depth=1, eta=1.6, gauss_regular=6)
+    assert op.info.n_far_blocks > 0
+    P.h2_assemble(store_coupling=True)
+    b = P.rhs(W.helmholtz_point_source(P.rhs_points(), [2.0, 0.0, 0.0], 2.0))
+    w_or, it_or, rr_or = P.solve(b, tol=1e-13, maxit=4000, restart=100)
+    assert rr_or <= 1e-13
+    w, info = op.solve(torch.tensor(b), tol=1e-13, max_iter=6000, restart=restart)
+    say(f"  gpu {info.iterations} it relres {info.rel_residual:.2e}; oracle {it_or} it")
+    assert info.converged == 1 and info.rel_residual <= 1e-13
+    if restart < 100:
+        assert info.iterations > 10 * restart  # many restart cycles
+    assert rel(to_np(w), w_or) < 1e-10

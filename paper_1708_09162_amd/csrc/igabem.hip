@@ -536,7 +536,7 @@ __global__ void __launch_bounds__(64 * WAVES, NComp<T>::value == 1 ? 2 : 1) k_ne
                 double wk[NC];
                 if constexpr (NC == 2) {
                     double sn, cs;
-                    sincos(kappa * (r2 * ir), &sn, &cs);
+                    sincos_red(kappa * (r2 * ir), &sn, &cs);
                     wk[0] = cs * f0;
                     wk[1] = sn * f0;
                 } else {
@@ -618,7 +618,7 @@ __global__ void __launch_bounds__(64 * WAVES, NComp<T>::value == 1 ? 2 : 1) k_ne
                 double wk[NC];
                 if constexpr (NC == 2) {
                     double sn, cs;
-                    sincos(kappa * (r2 * ir), &sn, &cs);
+                    sincos_red(kappa * (r2 * ir), &sn, &cs);
                     wk[0] = cs * f0;
                     wk[1] = sn * f0;
                 } else {
@@ -1233,7 +1233,7 @@ __global__ void __launch_bounds__(256) k_far_onthefly(int q2, const int64_t *__r
                         acc[c] += rsqrt(r2) * swr;
                     } else {
                         double ir = rsqrt(r2), sn, cs;
-                        sincos(kappa * (r2 * ir), &sn, &cs);
+                        sincos_red(kappa * (r2 * ir), &sn, &cs);
                         double gr = cs * ir, gi = sn * ir;
                         acc[c] += T{gr * swr - gi * swi, gr * swi + gi * swr};
                     }
@@ -1404,8 +1404,10 @@ __device__ inline void far_sym_chunk(const FarSymArgs &F, int64_t k0, int64_t k1
                     racc[ii] += ir * ws;
                     csum += ir * wt[ii];
                 } else {
+                    // padding nodes sit 1e100 away: their phase is clamped into the reduction's range
+                    // (zero weight on the padding side, a value below 1e-100 on the other)
                     double sn, cs;
-                    sincos(kappa * (r2 * ir), &sn, &cs);
+                    sincos_red(fmin(kappa * (r2 * ir), 0x1p19), &sn, &cs);
                     const T g{cs * ir, sn * ir};
                     racc[ii] += g * ws;
                     csum += g * wt[ii];
@@ -1850,7 +1852,7 @@ __global__ void __launch_bounds__(256) k_pot_eval(int64_t npts, const double *__
         int nb = (int)((s1 - b) < 256 ? (s1 - b) : 256);
         for (int k = 0; k < nb; ++k) {
             double d0 = px - sy[3 * k], d1 = py - sy[3 * k + 1], d2 = pz - sy[3 * k + 2];
-            acc += green<T>(sqrt(d0 * d0 + d1 * d1 + d2 * d2), kappa) * sc[k];
+            acc += green_any<T>(sqrt(d0 * d0 + d1 * d1 + d2 * d2), kappa) * sc[k];
         }
         __syncthreads();
     }
@@ -1907,7 +1909,7 @@ template <> __device__ inline double green_ir<double>(double, double ir, double)
 template <> __device__ inline cd green_ir<cd>(double r2, double ir, double kappa)
 {
     double sn, cs;
-    sincos(kappa * (r2 * ir), &sn, &cs);
+    sincos_red(kappa * (r2 * ir), &sn, &cs);
     const double f = 0.07957747154594767 * ir;
     return {cs * f, sn * f};
 }
@@ -2611,6 +2613,10 @@ struct igb_operator {
     // force_fp64 is set while the solver forms its double-precision residuals
     bool far_single = false, force_fp64 = false;
     void *rr = nullptr, *dw = nullptr;  // refinement: residual and correction (IGB_FP32)
+    // side stream of the product: the near-field block GEMV (HBM-bound) runs there, overlapping the tree
+    // passes and the on-the-fly far field (ALU-bound) on st; forked and joined with the two events
+    hipStream_t st2 = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
 };
 
 static igb_status dalloc(igb_operator *op, void **p, size_t bytes)
@@ -2866,6 +2872,17 @@ static std::vector<TreeLaunch> tree_slices(const igb_operator *op, size_t esz)
     return v;
 }
 
+// symmetric near storage: one wave per stored block (t, s), partial rows for both sides
+template <class T>
+static void launch_near_sym(igb_operator *op, const T *xs, hipStream_t st)
+{
+    const int ld = op->near_ld;
+    const size_t wave_lds = (size_t)(8 * ld + 520) * sizeof(T);
+    const int wpb = (int)std::max<size_t>(1, std::min<size_t>(4, (64 * 1024) / wave_lds));
+    hipLaunchKernelGGL((k_near_sym<T>), dim3((unsigned)((op->nsb + wpb - 1) / wpb)), dim3(64 * wpb), wpb * wave_lds,
+                       st, near_args(op), (const T *)op->nearb, xs, (T *)op->npart);
+}
+
 template <class T>
 static igb_status matvec_internal(igb_operator *op, const T *xs, T *ys, hipEvent_t *ev = nullptr,
                                   bool separate = false)
@@ -2894,6 +2911,20 @@ static igb_status matvec_internal(igb_operator *op, const T *xs, T *ys, hipEvent
     int64_t row0 = s.cl_off[op->lmin], nrows = s.cl_off[s.L + 1] - row0;
     const bool sym = has_far && op->fpart != nullptr;
     const bool fuse = sym && !separate && fused_products(op->near_sym, op->near_ld, sizeof(T), q2);
+    // near blocks not fused into the far-field launch: their GEMV reads only xs, so it runs on the side
+    // stream from the start of the product and is joined before its gather
+    const bool fork = has_far && op->near_sym && !fuse && !separate && !ev;
+    if (fork) {
+        if (!op->st2) {
+            HIPCHK(hipStreamCreateWithFlags(&op->st2, hipStreamNonBlocking));
+            HIPCHK(hipEventCreateWithFlags(&op->ev_fork, hipEventDisableTiming));
+            HIPCHK(hipEventCreateWithFlags(&op->ev_join, hipEventDisableTiming));
+        }
+        HIPCHK(hipEventRecord(op->ev_fork, op->st));
+        HIPCHK(hipStreamWaitEvent(op->st2, op->ev_fork, 0));
+        launch_near_sym<T>(op, xs, op->st2);
+        HIPCHK(hipEventRecord(op->ev_join, op->st2));
+    }
     if (has_far) {
         if (sym) {
             switch ((q2 + 7) / 8) {
@@ -2942,12 +2973,10 @@ static igb_status matvec_internal(igb_operator *op, const T *xs, T *ys, hipEvent
     if ((rc = mark(3))) return rc;
     if (fuse) {
         // done inside the far-field launch
+    } else if (fork) {
+        HIPCHK(hipStreamWaitEvent(op->st, op->ev_join, 0));
     } else if (op->near_sym) {
-        const int ld = op->near_ld;
-        const size_t wave_lds = (size_t)(8 * ld + 520) * sizeof(T);
-        const int wpb = (int)std::max<size_t>(1, std::min<size_t>(4, (64 * 1024) / wave_lds));
-        hipLaunchKernelGGL((k_near_sym<T>), dim3((unsigned)((op->nsb + wpb - 1) / wpb)), dim3(64 * wpb), wpb * wave_lds,
-                           op->st, near_args(op), (const T *)op->nearb, xs, (T *)op->npart);
+        launch_near_sym<T>(op, xs, op->st);
         LAUNCHCHK();
     } else {
         hipLaunchKernelGGL((k_bsr_gemv<T, 0>), dim3(s.nleaf), dim3(256), 4 * s.nl * sizeof(T), op->st, s.nl,
@@ -3853,6 +3882,12 @@ void igb_operator_destroy(igb_operator *op)
         (void)hipFree(op->mblk.p);
     }
     if (op->h_scal) (void)hipHostFree(op->h_scal);
+    if (op->st2) {
+        (void)hipStreamSynchronize(op->st2);
+        (void)hipStreamDestroy(op->st2);
+    }
+    if (op->ev_fork) (void)hipEventDestroy(op->ev_fork);
+    if (op->ev_join) (void)hipEventDestroy(op->ev_join);
     delete op;
 }
 

@@ -175,3 +175,19 @@ def test_helmholtz_h2_approaches_dense():
         errs.append(np.linalg.norm(P.h2_matvec_super(x) - y) / np.linalg.norm(y))
     assert errs[0] > errs[1] > errs[2]
     assert errs[2] < 5e-4
+
+
+def test_golden_sphere_solution_is_accurate():
+    """The stored oracle solution of the sphere workload (tests/golden, oracle-only script): its potential at
+    the 100 interior points reproduces the exact field of the 4 exterior charges to 1e-7 (Cor. cor::pwconv
+    gives h^(2p+3) = 2^-45 for p=3, m=5; quadrature and compression errors dominate)."""
+    import os
+
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "sphere_p3_m5_q8_density.txt")
+    vals = [ln for ln in open(path) if not ln.startswith("#")]
+    n = int(vals[0])
+    assert n == 6 * (32 + 3) ** 2
+    u = np.array([float(v) for v in vals[2 + n:]])
+    cfg = W.config_sphere_h2()
+    exact = W.laplace_charge_field(cfg["eval_points"], *cfg["charges"])
+    assert np.abs(u - exact).max() < 1e-7

@@ -1,19 +1,21 @@
 #!/usr/bin/env python3
-"""Time-to-solve and H2 matvec bandwidth of the isogeometric single-layer BEM on one MI355X.
+"""Time-to-solve and H2 matvec throughput of the isogeometric single-layer BEM on one MI355X.
 
-Workload (the metric's configuration): interior Laplace Dirichlet problem on the unit sphere given
-as 6 exact rational NURBS patches, spline degree p=3, 32x32 elements per patch (m=5; dim S = 7,350,
-dim S* = 98,304), H2 compression with q=8 Chebyshev nodes per parametric direction and eta=1.6,
-Gauss order 6; Dirichlet data from 4 seeded exterior point charges; Jacobi-preconditioned GMRES(100) to
-true relative residual 1e-8; potential at 100 seeded interior points.
+Headline workload (the largest single-GPU configuration): exterior Helmholtz scattering of a plane wave
+(seeded unit direction, sound-soft data g = -exp(i kappa d.x)) by the torus R=2, r=0.5 given as 16 rational
+NURBS patches; spline degree p=2, 64x64 elements per patch (m=6; dim S = 69,696, dim S* = 589,824, complex),
+wavenumber kappa=8, H2 with q=10 Chebyshev nodes per parametric direction and eta=1.6, Gauss order 6, far
+field generated on the fly; Jacobi GMRES(300) to true relative residual 1e-8; potential on a 64x64 grid of
+the plane z=1, x,y in [-4,4].
 
-One step = operator assembly (Bezier extraction, partition, near-field quadrature, coupling blocks,
-Jacobi diagonal) + right-hand side + solve + potential: the whole hot path once.  Inputs (the NURBS
-control nets, 24 KB) are host data handed to the library; everything after that runs on the GPU.
+One step = operator assembly (Bezier extraction, partition, near-field quadrature, Jacobi diagonal) +
+right-hand side + solve + potential: the whole hot path once.  Inputs (the NURBS control nets, a few KB)
+are host data handed to the library; everything after that runs on the GPU.
 
-Prints one JSON line.  Extra keys: h2_matvec_GBps (algorithmic bytes of one matvec / median time of
-igb_matvec), per-stage matvec times, roofline of the dominant matvec kernel, and the CPU oracle
-baseline projected from a timed sample of the same workload.
+Prints one JSON line.  Extra keys: per-stage product times, the rooflines of the far-field kernel (FP64
+ALU) and of the near-field block GEMV (HBM), the point-source accuracy twin (Sec. 5.3), the oracle CPU
+baseline projected from a timed sample, and legs on the other workloads: the Laplace sphere (p=3, m=5,
+q=8), the single-precision far field, and the learned preconditioner on the perturbed sphere.
 """
 from __future__ import annotations
 
@@ -22,6 +24,7 @@ import hashlib
 import json
 import math
 import os
+import subprocess
 import sys
 import time
 
@@ -35,29 +38,39 @@ METRIC = "time-to-solve (rel res 1e-8) + H2 matvec GB/s; mixed/learned vs plain 
 HBM_PEAK_GBPS = 8000.0
 # FP64 vector peak: 256 CUs x 4 SIMDs x 16 lanes x 2 flop (FMA) x 2.4 GHz = 78.6 TFLOP/s
 FP64_VECTOR_PEAK_TFLOPS = 78.6
-# flop model of one Laplace kernel evaluation in the far field: 3 differences, 5 for |d|^2,
-# 2 for the reciprocal square root, 2 for the accumulation
-FLOP_PER_EVAL_LAPLACE = 12
-# one evaluation applied both ways (mirrored blocks): 3 differences, 5 for |d|^2,
-# 2 for the reciprocal square root, 4 for the two accumulations
+# flop models of one far-field kernel evaluation (per pair of Chebyshev nodes):
+#  Laplace, applied both ways (mirrored blocks): 3 differences, 5 for |d|^2, 2 for the reciprocal square
+#  root, 4 for the two accumulations
 FLOP_PER_EVAL_SYM = 14
-WORKLOAD = "laplace_sphere_p3_m5_q8"
-PRM = dict(p=3, m=5, q=8, eta=1.6, gauss_regular=6)
-MODES = {"onthefly": 2, "stored": 1}
+#  Helmholtz: 40 flop per evaluation (distance, reciprocal square root, phase, sine and cosine counted as
+#  10 each, complex scaling and one complex accumulation); the second accumulation of the mirrored
+#  application (8 more) is not counted
+FLOP_PER_EVAL_HELMHOLTZ = 40
 TOL = 1e-8
 PROFILE_DIR = os.path.join(ROOT, "profiles")
-KERNEL_SRC = os.path.join(ROOT, "paper_1708_09162_amd", "csrc", "igabem.hip")
+KERNEL_SRC = [os.path.join(ROOT, "paper_1708_09162_amd", "csrc", f) for f in ("igabem.hip", "kernels.h")]
+
+HEADLINE = "helmholtz_torus_p2_m6_q10_k8"
+C3 = dict(kernel=1, wavenumber=8.0, p=2, m=6, q=10, eta=1.6, gauss_regular=6)
+C3_RESTART = 300
+SPHERE = "laplace_sphere_p3_m5_q8"
+C2 = dict(p=3, m=5, q=8, eta=1.6, gauss_regular=6)
+C2_RESTART = 100
+MODES = {"onthefly": 2, "stored": 1}
 
 
 def source_sha() -> str:
-    with open(KERNEL_SRC, "rb") as fh:
-        return hashlib.sha256(fh.read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for f in KERNEL_SRC:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 
 
-def read_traffic(stage: str):
+def read_traffic(stage: str, workload: str):
     """HBM bytes per launch of a kernel from committed rocprofv3 counter summaries, or None when
     missing or taken on a different kernel source."""
-    path = os.path.join(PROFILE_DIR, f"{stage}_{WORKLOAD}_pmc.txt")
+    path = os.path.join(PROFILE_DIR, f"{stage}_{workload}_pmc.txt")
     if not os.path.exists(path):
         return None
     vals = {}
@@ -90,6 +103,10 @@ def calibrate_copy():
     print(json.dumps({"copy_bytes_read": n * 8, "copy_bytes_written": n * 8, "launches": 5}), flush=True)
 
 
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def charge_field(torch, pts, pos, q):
     g = torch.zeros(pts.shape[0], dtype=torch.float64, device=pts.device)
     for x0, c in zip(pos, q):
@@ -98,24 +115,140 @@ def charge_field(torch, pts, pos, q):
     return g
 
 
-RESTART = 100
+def matvec_ms(torch, op, reps):
+    """Median duration of igb_matvec (HIP events on the operator's stream = torch's current stream)."""
+    x = torch.randn(op.info.n_dof, dtype=op.dtype, device="cuda:0")
+    for _ in range(3):
+        op.matvec(x)
+    mv = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        op.matvec(x)
+        e1.record()
+        e1.synchronize()
+        mv.append(e0.elapsed_time(e1))
+    return float(np.median(mv))
 
 
-def one_step(torch, igb, geo, cfg, ev_dev, mode, far_precision=0, solver="gmres"):
-    """The whole path once; returns (operator, density, solve info, potential, timings).  solver "gmres":
-    Jacobi-preconditioned GMRES(100) (igb_solve_fgmres without a network); "cg": Jacobi CG (igb_solve)."""
-    t = {}
+def near_gemv_bytes(op, near, npatch):
+    """Algorithmic bytes of one symmetric near-field block GEMV: the stored blocks (t, s), t <= s, column
+    stride rounded up to 8, the S* vector once, one partial row per block side."""
+    flags = int(op.info.layout_flags)
+    esz = 16 if op.cplx else 8
+    nleaf = npatch << (2 * op.info.leaf_level)
+    nl = op.info.n_dof_super // nleaf
+    ld = (nl + 7) // 8 * 8 if flags & 1 else nl
+    nsb = int(np.sum(near[:, 0] <= near[:, 1])) if flags & 1 else len(near)
+    ndiag = int(np.sum(near[:, 0] == near[:, 1])) if flags & 1 else 0
+    return op.info.near_bytes + esz * op.info.n_dof_super + esz * ld * (2 * nsb - ndiag)
+
+
+def alu_roof(kname, flops, evals, fpe, ms, traffic):
+    a = flops / (ms * 1e-3) / 1e12
+    return {"bound": "alu", "kernel": kname, "achieved": round(a, 2), "peak": FP64_VECTOR_PEAK_TFLOPS,
+            "unit": "TFLOP/s", "frac": round(a / FP64_VECTOR_PEAK_TFLOPS, 4), "traffic": traffic,
+            "algorithmic_flops": int(flops), "kernel_evaluations": int(evals), "flop_per_evaluation": fpe,
+            "avg_ms": round(ms, 4)}
+
+
+def hbm_roof(kname, nbytes, ms, traffic):
+    a = nbytes / (ms * 1e-3) / 1e9
+    return {"bound": "hbm", "kernel": kname, "achieved": round(a, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+            "frac": round(a / HBM_PEAK_GBPS, 4), "traffic": traffic, "algorithmic_bytes": int(nbytes),
+            "avg_ms": round(ms, 4)}
+
+
+# ---------------------------------------------------------------------------
+# headline: Helmholtz torus
+# ---------------------------------------------------------------------------
+def c3_step(torch, igb, geo, cfg, grid_dev, g_fn, far_precision=0, solver="gmres"):
+    """The whole path once on the torus; returns (operator, density, solve info, potential, timings)."""
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    op = igb.Operator(geo, device="cuda:0", mode=MODES[mode], far_precision=far_precision, **PRM)
+    op = igb.Operator(geo, device="cuda:0", mode=igb.IGB_H2_ONTHEFLY, far_precision=far_precision, **C3)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    pts = op.rhs_points()
-    b = op.rhs(charge_field(torch, pts, *cfg["charges"]))
+    b = op.rhs(g_fn(op.rhs_points()))
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    if solver == "mixed":
+        w, info = op.solve_mixed(b, tol=TOL, max_iter=20000, restart=C3_RESTART)
+    else:
+        w, info = op.solve(b, tol=TOL, max_iter=20000, restart=C3_RESTART)
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    u = op.potential(w, grid_dev)
+    torch.cuda.synchronize()
+    t4 = time.perf_counter()
+    t = dict(assembly_s=t1 - t0, rhs_s=t2 - t1, solve_s=t3 - t2, potential_s=t4 - t3, total_s=t4 - t0)
+    return op, w, info, u, t
+
+
+def plane_wave(torch, cfg):
+    d = torch.tensor(cfg["direction"], dtype=torch.float64, device="cuda:0")
+    k = cfg["wavenumber"]
+    return lambda pts: -torch.exp(1j * k * (pts @ d))
+
+
+def c3_details(torch, igb, W, geo, cfg, op, grid_dev, reps):
+    """Product timings, rooflines and the point-source accuracy twin on the assembled torus operator."""
+    q2 = C3["q"] ** 2
+    mv = matvec_ms(torch, op, reps)
+    sep = op.profile(reps=reps, separate=True)  # one kernel per stage, HIP events on the operator's stream
+    near, far = op.partition()
+    flags = int(op.info.layout_flags)
+    npair = len(far) // 2 if flags & 2 else len(far)
+    evals = npair * q2 * q2
+    flops = FLOP_PER_EVAL_HELMHOLTZ * evals
+    tt = (q2 + 7) // 8
+    roofs = {"far_field": alu_roof(f"k_far_sym1<cd, {tt}>", flops, evals, FLOP_PER_EVAL_HELMHOLTZ, sep["coupling"],
+                                   read_traffic("far_field", HEADLINE))}
+    nb = near_gemv_bytes(op, near, len(cfg["patches"]))
+    roofs["near_gemv"] = hbm_roof("k_near_sym<cd>", nb, sep["near_gemv"], read_traffic("near_gemv", HEADLINE))
+    for r in roofs.values():
+        r["launched_alone"] = True
+    # point-source twin (Sec. 5.3): exp(i k |x - v|)/|x - v| with v = (0, -2, 0) inside the tube is its own
+    # exterior solution, so the potential error against it measures the whole discretisation
+    v = np.array([0.0, -2.0, 0.0])
+    k = cfg["wavenumber"]
+    vt = torch.tensor(v, device="cuda:0")
+    b = op.rhs(lambda_ps(torch, vt, k)(op.rhs_points()))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    w, info = op.solve(b, tol=TOL, max_iter=20000, restart=C3_RESTART)
+    torch.cuda.synchronize()
+    ts = time.perf_counter() - t0
+    u = op.potential(w, grid_dev).cpu().numpy()
+    ex = W.helmholtz_point_source(cfg["eval_points"], v, k)
+    twin = {"source": v.tolist(), "iterations": int(info.iterations), "solve_s": round(ts, 3),
+            "rel_residual": float(info.rel_residual),
+            "potential_max_abs_err": float(np.abs(u - ex).max()),
+            "potential_max_rel_err": float(np.abs(u - ex).max() / np.abs(ex).max())}
+    return mv, sep, roofs, twin
+
+
+def lambda_ps(torch, vt, k):
+    def g(pts):
+        d = torch.linalg.norm(pts - vt, dim=1)
+        return torch.exp(1j * k * d) / d
+    return g
+
+
+# ---------------------------------------------------------------------------
+# second leg: Laplace sphere
+# ---------------------------------------------------------------------------
+def c2_step(torch, igb, geo, cfg, ev_dev, mode="onthefly", far_precision=0, solver="gmres"):
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    op = igb.Operator(geo, device="cuda:0", mode=MODES[mode], far_precision=far_precision, **C2)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    b = op.rhs(charge_field(torch, op.rhs_points(), *cfg["charges"]))
     torch.cuda.synchronize()
     t2 = time.perf_counter()
     if solver == "gmres":
-        w, info = op.solve_fgmres(b, None, tol=TOL, max_iter=20000, restart=RESTART)
+        w, info = op.solve_fgmres(b, None, tol=TOL, max_iter=20000, restart=C2_RESTART)
     else:
         w, info = op.solve(b, tol=TOL, max_iter=20000)
     torch.cuda.synchronize()
@@ -123,43 +256,98 @@ def one_step(torch, igb, geo, cfg, ev_dev, mode, far_precision=0, solver="gmres"
     u = op.potential(w, ev_dev)
     torch.cuda.synchronize()
     t4 = time.perf_counter()
-    t.update(assembly_s=t1 - t0, rhs_s=t2 - t1, solve_s=t3 - t2, potential_s=t4 - t3, total_s=t4 - t0)
+    t = dict(assembly_s=t1 - t0, rhs_s=t2 - t1, solve_s=t3 - t2, potential_s=t4 - t3, total_s=t4 - t0)
     return op, w, info, u, t
 
 
-def mixed_leg(torch, igb, geo, cfg, ev_dev, fp64_ms, exact, steps: int = 2):
-    """The same step with the single-precision far field (far_precision IGB_FP32) and CG refined to the FP64
-    tolerance with FP64 residuals: time-to-solve beside the plain FP64 CG step and the headline step."""
-    def timed(fp, solver):
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(steps):
-            res = one_step(torch, igb, geo, cfg, ev_dev, "onthefly", fp, solver)
-            if _ + 1 < steps:
-                del res
-        torch.cuda.synchronize()
-        return 1e3 * (time.perf_counter() - t0) / steps, res
+def timed_steps(torch, fn, steps):
+    res = None
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        if res is not None:
+            del res
+        res = fn()
+    torch.cuda.synchronize()
+    return 1e3 * (time.perf_counter() - t0) / steps, res
 
-    one_step(torch, igb, geo, cfg, ev_dev, "onthefly", 0, "cg")  # warmup
-    cg_ms, (op, w, info_cg, u, t) = timed(0, "cg")
+
+def sphere_leg(torch, igb, W, steps, reps, mode="onthefly"):
+    """The Laplace sphere workload (p=3, m=5, q=8): time-to-solve with Jacobi GMRES(100), product timings,
+    the fused product's roofline, and the single-precision far field with CG beside FP64 CG."""
+    cfg = W.config_sphere_h2()
+    geo = igb.Geometry(cfg["patches"])
+    ev_dev = torch.tensor(cfg["eval_points"], dtype=torch.float64, device="cuda:0")
+    exact = W.laplace_charge_field(cfg["eval_points"], *cfg["charges"])
+    c2_step(torch, igb, geo, cfg, ev_dev, mode)  # warmup
+    ms, (op, w, info, u, t) = timed_steps(torch, lambda: c2_step(torch, igb, geo, cfg, ev_dev, mode), steps)
+    mv = matvec_ms(torch, op, reps)
+    stages = op.profile(reps=reps)
+    sep = op.profile(reps=reps, separate=True)
+    near, far = op.partition()
+    q2 = C2["q"] ** 2
+    flags = int(op.info.layout_flags)
+    nb = near_gemv_bytes(op, near, len(cfg["patches"]))
+    roofs = {"near_gemv": hbm_roof("k_near_sym<double>" if flags & 1 else "k_bsr_gemv<double, 0>", nb,
+                                   sep["near_gemv"], read_traffic("near_gemv", SPHERE))}
+    roofs["near_gemv"]["launched_alone"] = True
+    if mode == "onthefly":
+        sym = bool(flags & 2)
+        evals = (len(far) // 2 if sym else len(far)) * q2 * q2
+        tt = (q2 + 7) // 8
+        roofs["far_field"] = alu_roof(f"k_far_sym<double, {tt}, false>", FLOP_PER_EVAL_SYM * evals, evals,
+                                      FLOP_PER_EVAL_SYM, sep["coupling"], read_traffic("coupling", SPHERE))
+        roofs["far_field"]["launched_alone"] = True
+        if flags & 4:
+            roofs["fused"] = alu_roof(f"k_sym_products<double, {tt}, false>", FLOP_PER_EVAL_SYM * evals, evals,
+                                      FLOP_PER_EVAL_SYM, stages["coupling"], read_traffic("coupling_fused", SPHERE))
+            roofs["fused"]["hbm_bytes_alongside"] = int(nb)
+            roofs["fused"]["hbm_GBps_alongside"] = round(nb / (stages["coupling"] * 1e-3) / 1e9, 1)
+    out = {"workload": SPHERE, "mode": "h2_" + mode, "solver": f"jacobi_gmres_{C2_RESTART}",
+           "value": round(ms / 1e3, 5), "unit": "s", "ms_per_step": round(ms, 3), "steps": steps,
+           "n_dof": int(op.info.n_dof), "n_dof_super": int(op.info.n_dof_super),
+           "iterations": int(info.iterations), "rel_residual": float(info.rel_residual),
+           "potential_max_err": float(np.abs(u.cpu().numpy() - exact).max()),
+           "breakdown_s": {k: round(v, 4) for k, v in t.items()},
+           "h2_matvec_ms": round(mv, 4), "matvec_bytes": int(op.info.matvec_bytes),
+           "h2_matvec_GBps": round(op.info.matvec_bytes / (mv * 1e-3) / 1e9, 1),
+           "stage_ms": {k: round(v, 4) for k, v in stages.items()},
+           "stage_ms_separate": {k: round(v, 4) for k, v in sep.items()},
+           "near_blocks": int(op.info.n_near_blocks), "far_blocks": int(op.info.n_far_blocks),
+           "roofline_stages": roofs}
+    log(f"sphere: {ms / 1e3:.4f} s per step, {info.iterations} it, matvec {mv:.3f} ms")
     del op
-    op, w, info, u, t = one_step(torch, igb, geo, cfg, ev_dev, "onthefly", igb.IGB_FP32, "cg")  # warmup
+    if mode == "onthefly":
+        out["mixed_fp32_far"] = sphere_mixed_leg(torch, igb, geo, cfg, ev_dev, ms, exact)
+    return out
+
+
+def sphere_mixed_leg(torch, igb, geo, cfg, ev_dev, fp64_ms, exact, steps: int = 2):
+    """The sphere step with the single-precision far field (far_precision IGB_FP32) and CG refined to the FP64
+    tolerance with FP64 residuals, beside the plain FP64 CG step and the FP64 GMRES step."""
+    c2_step(torch, igb, geo, cfg, ev_dev, "onthefly", 0, "cg")  # warmup
+    cg_ms, (op, w, info_cg, u, t) = timed_steps(
+        torch, lambda: c2_step(torch, igb, geo, cfg, ev_dev, "onthefly", 0, "cg"), steps)
     del op
-    ms, (op, w, info, u, t) = timed(igb.IGB_FP32, "cg")
+    c2_step(torch, igb, geo, cfg, ev_dev, "onthefly", igb.IGB_FP32, "cg")  # warmup
+    ms, (op, w, info, u, t) = timed_steps(
+        torch, lambda: c2_step(torch, igb, geo, cfg, ev_dev, "onthefly", igb.IGB_FP32, "cg"), steps)
     st = op.profile(reps=20)
-    print(f"[bench] single-precision far field: {ms / 1e3:.4f} s per step, {info.iterations} it", file=sys.stderr,
-          flush=True)
+    log(f"single-precision far field (sphere): {ms / 1e3:.4f} s per step, {info.iterations} it")
     return {"far_precision": "fp32 (kernel values from the hardware reciprocal square root, FP64 sums)",
             "solver": "jacobi_cg_reliable_updates",
             "value": round(ms / 1e3, 5), "ms_per_step": round(ms, 3), "vs_fp64_cg": round(ms / cg_ms, 4),
             "fp64_cg_ms_per_step": round(cg_ms, 3), "fp64_cg_iterations": int(info_cg.iterations),
-            "vs_fp64": round(ms / fp64_ms, 4),
+            "vs_fp64_gmres": round(ms / fp64_ms, 4),
             "iterations": int(info.iterations), "rel_residual": float(info.rel_residual),
             "potential_max_err": float(np.abs(u.cpu().numpy() - exact).max()),
             "breakdown_s": {k: round(v, 4) for k, v in t.items()},
             "coupling_ms": round(st["coupling"], 4)}
 
 
+# ---------------------------------------------------------------------------
+# learned preconditioner (perturbed sphere)
+# ---------------------------------------------------------------------------
 def learned_leg(torch, igb, epochs: int = 4, seeds=(5, 6, 7, 8)):
     """The learned preconditioner on its own workload: Laplace on the perturbed sphere (p=2, 128x128 elements
     per patch, q=8), 2000 seeded training vectors, the linear network trained on the GPU (loss on x) from four
@@ -221,7 +409,6 @@ def learned_leg(torch, igb, epochs: int = 4, seeds=(5, 6, 7, 8)):
                      "true_rel_residual": float(torch.linalg.norm(r) / torch.linalg.norm(b))})
         nets[seed] = net
     conv = [rr for rr in runs if rr["converged"]]
-    # selection on the validation right-hand side alone; Jacobi when no seed beats it there
     cand = [rr for rr in runs if rr["validation_iterations"] is not None
             and rr["validation_iterations"] < iv_j.iterations]
     chosen = min(cand, key=lambda rr: rr["validation_iterations"]) if cand else None
@@ -242,9 +429,9 @@ def learned_leg(torch, igb, epochs: int = 4, seeds=(5, 6, 7, 8)):
         "network_best_solve_vs_plain_fp64": round(min(rr["solve_s"] for rr in conv) / t_cg, 4) if conv else None,
         "pairs_s": round(t_pairs, 3),
     })
-    print(f"[bench] learned preconditioner: CG {i_cg.iterations} it {t_cg:.3f} s, Jacobi FGMRES {i_j.iterations} it "
-          f"{t_j:.3f} s, network FGMRES per seed {[(rr['iterations'], rr['converged']) for rr in runs]}, "
-          f"selected {res['selected']['preconditioner']}: {i_s.iterations} it {t_s:.3f} s", file=sys.stderr, flush=True)
+    log(f"learned preconditioner: CG {i_cg.iterations} it {t_cg:.3f} s, Jacobi FGMRES {i_j.iterations} it "
+        f"{t_j:.3f} s, network FGMRES per seed {[(rr['iterations'], rr['converged']) for rr in runs]}, "
+        f"selected {res['selected']['preconditioner']}: {i_s.iterations} it {t_s:.3f} s")
     return res
 
 
@@ -271,19 +458,19 @@ def batched_leg(torch, igb, n: int = 128, max_iter: int = 3000, restart: int = 1
         inst.append((op, op.rhs(torch.tensor(g, device="cuda:0"))))
         torch.cuda.synchronize()
         if i % 32 == 31:
-            print(f"[bench] batched: {i + 1} instances assembled", file=sys.stderr, flush=True)
+            log(f"batched: {i + 1} instances assembled")
     t_asm = time.perf_counter() - t0
     t0 = time.perf_counter()
     seq = [op.solve(b, tol=TOL, max_iter=max_iter, restart=restart)[1] for op, b in inst]
     torch.cuda.synchronize()
     t_seq = time.perf_counter() - t0
-    print(f"[bench] batched: one-at-a-time solves {t_seq:.2f} s", file=sys.stderr, flush=True)
+    log(f"batched: one-at-a-time solves {t_seq:.2f} s")
     t0 = time.perf_counter()
     _, infos = igb.solve_many([op for op, _ in inst], [b for _, b in inst], tol=TOL, max_iter=max_iter,
                               restart=restart)
     torch.cuda.synchronize()
     t_many = time.perf_counter() - t0
-    print(f"[bench] batched: solve_many {t_many:.2f} s", file=sys.stderr, flush=True)
+    log(f"batched: solve_many {t_many:.2f} s")
     return {"instances": n, "max_iter": max_iter, "restart": restart, "assembly_s": round(t_asm, 3),
             "sequential_solve_s": round(t_seq, 3), "solve_many_s": round(t_many, 3),
             "speedup": round(t_seq / t_many, 3), "instances_per_s": round(n / t_many, 2),
@@ -292,53 +479,105 @@ def batched_leg(torch, igb, n: int = 128, max_iter: int = 3000, restart: int = 1
             "total_dofs": int(sum(op.info.n_dof for op, _ in inst))}
 
 
-def cpu_baseline(cfg, iterations: int, seed: int = 7):
-    """Oracle time-to-solve projected from a timed stratified sample of the same workload:
-    near-field pair quadrature (per class) and coupling-block evaluation (the oracle evaluates
-    coupling blocks inside every matvec)."""
+# ---------------------------------------------------------------------------
+# CPU baseline: the oracle on the host cores
+# ---------------------------------------------------------------------------
+def cpu_model() -> str:
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for ln in out.splitlines():
+            if ln.startswith("Model name:"):
+                return ln.split(":", 1)[1].strip()
+    except (OSError, subprocess.SubprocessError):
+        pass
+    return "unknown"
+
+
+def cpu_baseline(cfg, prm, iterations: int, seed: int = 7, n_regular: int = 5000, n_touch: int = 200,
+                 n_far: int = 600):
+    """Oracle time-to-solve projected from a timed stratified random sample of the same workload:
+    near-field pair quadrature per class (assembly), and per product the coupling-block evaluation (the
+    oracle evaluates coupling blocks inside every product) plus its complete upward moment pass.  Left out
+    (so the figure is a lower bound): the near-field block GEMV of each product and the downward pass.  The
+    sample also runs on one thread (a smaller share of it) to give the single-core figure."""
     import oracle
 
-    P = oracle.Problem(cfg["patches"], **PRM)
+    P = oracle.Problem(cfg["patches"], **prm)
     threads = oracle.num_threads()
     classes = P.near_pair_classes()
     _, far = P.partition()
     rng = np.random.default_rng(seed)
-    t_asm, parts = 0.0, []
+    t_asm, parts, picks = 0.0, [], []
     for c in range(4):
         rows = classes[classes[:, 2] == c]
-        k = max(32, len(rows) // 100)
-        pick = rows[rng.choice(len(rows), min(k, len(rows)), replace=False)]
+        if len(rows) == 0:
+            continue
+        k = min(len(rows), n_regular if c == 0 else n_touch)
+        pick = rows[rng.choice(len(rows), k, replace=False)]
         t0 = time.perf_counter()
         P.pair_blocks(pick[:, :2])
         dt = time.perf_counter() - t0
         t_asm += dt / len(pick) * len(rows)
         parts.append(f"{len(pick)}/{len(rows)} class-{c} pairs")
-    kf = max(200, len(far) // 100)
-    pick = far[rng.choice(len(far), min(kf, len(far)), replace=False)]
+        picks.append((pick, len(rows), dt))
+    kf = min(n_far, len(far))
+    pick = far[rng.choice(len(far), kf, replace=False)]
     t0 = time.perf_counter()
     P.coupling_blocks(pick)
-    dt = time.perf_counter() - t0
-    t_far = dt / len(pick) * len(far)
-    parts.append(f"{len(pick)}/{len(far)} coupling blocks")
-    value = t_asm + (iterations + 2) * t_far
-    return {"value": value, "unit": "s", "cores": threads, "kind": "oracle",
+    dt_far = time.perf_counter() - t0
+    t_far = dt_far / kf * len(far)
+    parts.append(f"{kf}/{len(far)} coupling blocks")
+    xs = np.random.default_rng(1).standard_normal(P.nsup) + 0j
+    t0 = time.perf_counter()
+    P.h2_matvec_rows(xs, np.zeros(0, dtype=np.int32))  # no target rows: the upward moment pass alone
+    t_up = time.perf_counter() - t0
+    matvec = t_far + t_up
+    value = t_asm + (iterations + 2) * matvec
+    # one thread on a tenth of the regular-pair and coupling samples: the parallel speed-up of the sample
+    P1 = oracle.Problem(cfg["patches"], threads=1, **prm)
+    sub = picks[0][0][: max(1, len(picks[0][0]) // 10)]
+    t0 = time.perf_counter()
+    P1.pair_blocks(sub[:, :2])
+    d1 = time.perf_counter() - t0
+    subf = pick[: max(1, kf // 10)]
+    t0 = time.perf_counter()
+    P1.coupling_blocks(subf)
+    d1f = time.perf_counter() - t0
+    speed_asm = (d1 / len(sub)) / (picks[0][2] / len(picks[0][0]))
+    speed_far = (d1f / len(subf)) / (dt_far / kf)
+    value_1t = t_asm * speed_asm + (iterations + 2) * (t_far * speed_far + t_up * threads)
+    return {"value": round(value, 3), "unit": "s", "cores": threads, "kind": "oracle",
             "sample": "projected from a timed random sample of the full workload: " + ", ".join(parts)
-                      + f"; time = near quadrature + (solver iterations + 2) x coupling evaluation per matvec",
-            "assembly_s": t_asm, "matvec_s": t_far}
+                      + "; time = near quadrature + (solver iterations + 2) x (coupling evaluation + upward "
+                        "moment pass) per product; the near-field GEMV and downward pass of each product are "
+                        "not counted (lower bound)",
+            "assembly_s": round(t_asm, 3), "matvec_s": round(matvec, 4), "iterations": iterations,
+            "one_thread_value": round(value_1t, 2), "cpu_model": cpu_model(), "nproc": os.cpu_count(),
+            "oracle_build": "gcc -O3 -march=native -ffp-contract=off -fopenmp"}
 
 
+def native_oracle():
+    """Builds the oracle for this host's CPU (-march=native) into a private file and points the oracle
+    package at it (the default build targets x86-64-v3 so it runs on any host it is copied to)."""
+    import oracle
+
+    oracle.use_native_build()
+
+
+# ---------------------------------------------------------------------------
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--matvec-reps", type=int, default=20)
+    ap.add_argument("--matvec-reps", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--mode", choices=sorted(MODES), default="onthefly",
-                    help="far field: coupling blocks generated in every matvec (default) or stored in HBM")
     ap.add_argument("--calibrate-copy", action="store_true", help="only run a plain 1 GiB device copy")
-    ap.add_argument("--no-mixed", action="store_true", help="skip the single-precision far-field leg")
+    ap.add_argument("--no-sphere", action="store_true", help="skip the Laplace sphere leg")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the single-precision far-field legs")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-preconditioner leg")
+    ap.add_argument("--no-twin", action="store_true", help="skip the point-source accuracy twin")
+    ap.add_argument("--sphere-steps", type=int, default=10)
     ap.add_argument("--batched", action="store_true",
                     help="also run the 128-instance batched-solve leg (about 90 s)")
     args = ap.parse_args()
@@ -357,114 +596,35 @@ def main():
     from paper_1708_09162_amd import igabem as igb
     from paper_1708_09162_amd import workloads as W
 
-    cfg = W.config_sphere_h2()
+    cfg = W.config_torus_helmholtz()
     geo = igb.Geometry(cfg["patches"])
-    ev = cfg["eval_points"]
-    ev_dev = torch.tensor(ev, dtype=torch.float64, device="cuda:0")
-    print(f"[bench] workload {WORKLOAD}: warmup {args.warmup}, steps {args.steps}", file=sys.stderr, flush=True)
+    grid_dev = torch.tensor(cfg["eval_points"], dtype=torch.float64, device="cuda:0")
+    g_fn = plane_wave(torch, cfg)
+    log(f"workload {HEADLINE}: warmup {args.warmup}, steps {args.steps}")
     op = None
     for i in range(args.warmup):
         if op is not None:
             del op
-        op, w, info, u, t = one_step(torch, igb, geo, cfg, ev_dev, args.mode)
-        print(f"[bench] warmup {i}: {t['total_s']:.3f} s, {info.iterations} it", file=sys.stderr, flush=True)
+        op, w, info, u, t = c3_step(torch, igb, geo, cfg, grid_dev, g_fn)
+        log(f"warmup {i}: {t['total_s']:.3f} s, {info.iterations} it")
     times = []
     torch.cuda.synchronize()
     t_start = time.perf_counter()
     for i in range(args.steps):
         if op is not None:
             del op
-        op, w, info, u, t = one_step(torch, igb, geo, cfg, ev_dev, args.mode)
+        op, w, info, u, t = c3_step(torch, igb, geo, cfg, grid_dev, g_fn)
         times.append(t)
-        print(f"[bench] step {i}: {t['total_s']:.3f} s (assembly {t['assembly_s']:.3f}, solve {t['solve_s']:.3f},"
-              f" {info.iterations} it, relres {info.rel_residual:.2e})", file=sys.stderr, flush=True)
+        log(f"step {i}: {t['total_s']:.3f} s (assembly {t['assembly_s']:.3f}, solve {t['solve_s']:.3f}, "
+            f"{info.iterations} it, relres {info.rel_residual:.2e})")
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t_start
     ms_per_step = 1e3 * elapsed / max(1, args.steps)
+    u_grid = u.cpu().numpy()
 
-    # accuracy of the last step against the exact interior potential
-    exact = W.laplace_charge_field(ev, *cfg["charges"])
-    pot_err = float(np.abs(u.cpu().numpy() - exact).max())
-
-    # H2 matvec bandwidth: algorithmic bytes / median time of igb_matvec
-    x = torch.randn(op.info.n_dof, dtype=torch.float64, device="cuda:0")
-    for _ in range(3):
-        op.matvec(x)
-    mv = []
-    for _ in range(args.matvec_reps):
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        op.matvec(x)
-        e1.record()
-        e1.synchronize()
-        mv.append(e0.elapsed_time(e1))
-    mv_ms = float(np.median(mv))
-    gbps = op.info.matvec_bytes / (mv_ms * 1e-3) / 1e9
-
-    # per-stage durations (HIP events on the operator's stream) and the rooflines of the two
-    # dominant matvec kernels: near-field block GEMV (HBM) and far field (HBM when coupling
-    # blocks are stored, FP64 ALU when they are generated on the fly)
-    stages = op.profile(reps=args.matvec_reps)  # launched as in igb_matvec
-    sep = op.profile(reps=args.matvec_reps, separate=True)  # one kernel per stage
-    near, far = op.partition()
-    q2 = PRM["q"] ** 2
-    npatch = len(cfg["patches"])
-    off = np.concatenate([[0], np.cumsum([npatch << (2 * l) for l in range(op.info.leaf_level + 1)])])
-    rows = len(np.unique(off[far[:, 0]] + far[:, 1]))  # clusters with far blocks (rows written)
-    srcs = len(np.unique(off[far[:, 0]] + far[:, 2]))  # distinct source moment vectors read
-    roofs = {}
-    # symmetric near storage: blocks (t, s) with t <= s, column stride nl rounded up to 8; the
-    # kernel reads them and the S* vector once and writes one partial row per block side
-    flags = int(op.info.layout_flags)
-    fused = bool(flags & 4)  # near blocks ride along in the far-field launch
-    nleaf = npatch << (2 * op.info.leaf_level)
-    nl = op.info.n_dof_super // nleaf
-    ld = (nl + 7) // 8 * 8 if flags & 1 else nl
-    nsb = int(np.sum(near[:, 0] <= near[:, 1])) if flags & 1 else len(near)
-    ndiag = int(np.sum(near[:, 0] == near[:, 1])) if flags & 1 else 0
-    near_bytes = op.info.near_bytes + 8 * op.info.n_dof_super + 8 * ld * (2 * nsb - ndiag)
-    tt = (q2 + 7) // 8
-    a = near_bytes / (sep["near_gemv"] * 1e-3) / 1e9
-    roofs["near_gemv"] = {"bound": "hbm", "kernel": "k_near_sym<double>" if flags & 1 else "k_bsr_gemv<double, 0>",
-                          "achieved": round(a, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                          "frac": round(a / HBM_PEAK_GBPS, 4), "traffic": read_traffic("near_gemv"),
-                          "algorithmic_bytes": int(near_bytes), "avg_ms": round(sep["near_gemv"], 4),
-                          "launched_alone": True}
-    if args.mode == "stored":
-        cb = op.info.coupling_bytes + 8 * q2 * (rows + srcs)
-        a = cb / (stages["coupling"] * 1e-3) / 1e9
-        roofs["coupling"] = {"bound": "hbm", "kernel": "k_bsr_gemv<double, 1>", "achieved": round(a, 1),
-                             "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": round(a / HBM_PEAK_GBPS, 4),
-                             "traffic": read_traffic("coupling_stored"), "algorithmic_bytes": int(cb),
-                             "avg_ms": round(stages["coupling"], 4)}
-    else:
-        # mirrored pairs: each pair of blocks is generated once and applied both ways
-        sym = bool(flags & 2)
-        evals = (len(far) // 2 if sym else len(far)) * q2 * q2
-        fpe = FLOP_PER_EVAL_SYM if sym else FLOP_PER_EVAL_LAPLACE
-        flops = fpe * evals
-
-        def alu_roof(kname, ms, traffic):
-            a = flops / (ms * 1e-3) / 1e12
-            return {"bound": "alu", "kernel": kname, "achieved": round(a, 2), "peak": FP64_VECTOR_PEAK_TFLOPS,
-                    "unit": "TFLOP/s", "frac": round(a / FP64_VECTOR_PEAK_TFLOPS, 4), "traffic": traffic,
-                    "algorithmic_flops": int(flops), "kernel_evaluations": int(evals),
-                    "block_entries_applied": int(len(far) * q2 * q2), "flop_per_evaluation": fpe,
-                    "avg_ms": round(ms, 4)}
-        kfar = f"k_far_sym<double, {tt}, false>" if sym else "k_far_onthefly<double>"
-        roofs["far_field"] = alu_roof(kfar, sep["coupling"], read_traffic("coupling") if sym else None)
-        roofs["far_field"]["launched_alone"] = True
-        if fused:
-            # as launched in the solver: the near blocks ride along with the far-field pairs
-            roofs["coupling"] = alu_roof(f"k_sym_products<double, {tt}, false>", stages["coupling"],
-                                         read_traffic("coupling_fused"))
-            roofs["coupling"]["hbm_bytes_alongside"] = int(near_bytes)
-            roofs["coupling"]["hbm_GBps_alongside"] = round(near_bytes / (stages["coupling"] * 1e-3) / 1e9, 1)
-        else:
-            roofs["coupling"] = dict(roofs["far_field"])
-    # the dominant kernel of the product as launched in the solver
-    roofline = roofs["coupling"] if stages["coupling"] >= stages["near_gemv"] else roofs["near_gemv"]
-
+    mv, sep, roofs, twin = c3_details(torch, igb, W, geo, cfg, op, grid_dev, args.matvec_reps)
+    if args.no_twin:
+        twin = None
     mean = {k: float(np.mean([t[k] for t in times])) for k in times[0]} if times else {}
     out = {
         "metric": METRIC,
@@ -477,39 +637,61 @@ def main():
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "c128",
         "data": "synthetic",
-        "config": {"workload": WORKLOAD, "geometry": "unit sphere, 6 rational NURBS patches of bidegree 4",
-                   "kernel": "laplace", "p": PRM["p"], "m": PRM["m"], "q": PRM["q"], "eta": PRM["eta"],
-                   "gauss_regular": PRM["gauss_regular"], "n_dof": int(op.info.n_dof),
-                   "n_dof_super": int(op.info.n_dof_super), "rel_tol": TOL, "mode": "h2_" + args.mode,
-                   "solver": f"jacobi_gmres_{RESTART}"},
-        "h2_matvec_GBps": round(gbps, 1),
-        "h2_matvec_ms": round(mv_ms, 4),
+        "config": {"workload": HEADLINE, "geometry": "torus R=2 r=0.5, 16 rational biquadratic NURBS patches",
+                   "kernel": "helmholtz", "wavenumber": C3["wavenumber"], "p": C3["p"], "m": C3["m"],
+                   "q": C3["q"], "eta": C3["eta"], "gauss_regular": C3["gauss_regular"],
+                   "n_dof": int(op.info.n_dof), "n_dof_super": int(op.info.n_dof_super), "rel_tol": TOL,
+                   "mode": "h2_onthefly", "solver": f"jacobi_gmres_{C3_RESTART}",
+                   "data": "plane wave, seeded direction", "potential_points": int(grid_dev.shape[0])},
+        "h2_matvec_ms": round(mv, 4),
         "matvec_bytes": int(op.info.matvec_bytes),
-        "stage_ms": {k: round(v, 4) for k, v in stages.items()},
+        "h2_matvec_GBps": round(op.info.matvec_bytes / (mv * 1e-3) / 1e9, 1),
         "stage_ms_separate": {k: round(v, 4) for k, v in sep.items()},
         "breakdown_s": {k: round(v, 4) for k, v in mean.items()},
         "host_setup_s": round(float(op.info.setup_seconds), 4),
         "iterations": int(info.iterations),
         "rel_residual": float(info.rel_residual),
-        "potential_max_err": pot_err,
+        "potential_grid_max_abs": float(np.abs(u_grid).max()),
         "near_blocks": int(op.info.n_near_blocks),
         "far_blocks": int(op.info.n_far_blocks),
-        "roofline": roofline,
+        "point_source_twin": twin,
+        "roofline": roofs["far_field"],
         "roofline_stages": roofs,
         "cpu_baseline": None,
     }
-    if args.mode == "onthefly" and not args.no_mixed:
-        out["mixed_fp32_far"] = mixed_leg(torch, igb, geo, cfg, ev_dev, ms_per_step, exact)
+    iters_c3 = int(info.iterations)
+    del op
+    torch.cuda.empty_cache()
+    if not args.no_mixed and hasattr(igb.Operator, "solve_mixed"):
+        out["mixed_fp32_far"] = c3_mixed_leg(torch, igb, geo, cfg, grid_dev, g_fn, ms_per_step, u_grid)
+    if not args.no_sphere:
+        out["sphere"] = sphere_leg(torch, igb, W, args.sphere_steps, args.matvec_reps)
     if not args.no_learned:
         out["learned_preconditioner"] = learned_leg(torch, igb)
     if args.batched:
         out["batched"] = batched_leg(torch, igb)
     if not args.no_cpu_baseline:
-        print("[bench] cpu baseline (oracle sample)", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(cfg, int(info.iterations))
+        log("cpu baseline (oracle sample)")
+        native_oracle()
+        out["cpu_baseline"] = cpu_baseline(cfg, dict(C3), iters_c3)
     print(json.dumps(out), flush=True)
+
+
+def c3_mixed_leg(torch, igb, geo, cfg, grid_dev, g_fn, fp64_ms, u_fp64, steps: int = 2):
+    """The torus step with the single-precision complex far field as the inner operator of a refinement whose
+    residuals use the FP64 operator (igb_solve_mixed), beside the FP64 headline step."""
+    c3_step(torch, igb, geo, cfg, grid_dev, g_fn, igb.IGB_FP32, "mixed")  # warmup
+    ms, (op, w, info, u, t) = timed_steps(
+        torch, lambda: c3_step(torch, igb, geo, cfg, grid_dev, g_fn, igb.IGB_FP32, "mixed"), steps)
+    un = u.cpu().numpy()
+    log(f"mixed precision (torus): {ms / 1e3:.3f} s per step, {info.iterations} it")
+    return {"far_precision": "fp32 complex far field inside FP64 iterative refinement",
+            "value": round(ms / 1e3, 5), "ms_per_step": round(ms, 3), "vs_fp64": round(ms / fp64_ms, 4),
+            "iterations": int(info.iterations), "rel_residual": float(info.rel_residual),
+            "potential_rel_diff_vs_fp64": float(np.abs(un - u_fp64).max() / np.abs(u_fp64).max()),
+            "breakdown_s": {k: round(v, 4) for k, v in t.items()}}
 
 
 if __name__ == "__main__":

@@ -52,14 +52,21 @@ typedef int32_t igb_status;
 #define IGB_H2_ONTHEFLY 2        /* near field stored; coupling blocks generated inside every matvec */
 
 #define IGB_FP64 0
-/* Single-precision far field (Laplace, on-the-fly coupling, q <= 8): every
- * coupling-kernel value 1/|x - y| is the hardware reciprocal-square-root
- * estimate without refinement (relative error below 6e-8, single-precision
- * accuracy); distances, moments, transfers, sums and the near field stay FP64.
- * igb_matvec / igb_matvec_super apply this operator; igb_solve still solves
- * the FP64 system: CG steps with this operator, the recursive residual
- * replaced by the FP64 residual b - A w (full-precision far field) every 20
- * steps, convergence judged on the FP64 residual. */
+/* Single-precision far field (on-the-fly coupling; q <= 8 for Laplace, q <= 10
+ * for Helmholtz).  Laplace: every coupling-kernel value 1/|x - y| is the
+ * hardware reciprocal-square-root estimate without refinement (relative error
+ * below 6e-8); distances, moments, transfers, sums and the near field stay
+ * FP64.  Helmholtz: the kernel values exp(i k r)/r (hardware reciprocal square
+ * root, sine and cosine of the phase in turns) and the sums inside each pair
+ * of clusters are FP32 (about 1e-6 relative); moments, transfers, the sums
+ * across pairs and the near field stay FP64.  igb_matvec / igb_matvec_super
+ * apply this operator; igb_solve still solves the FP64 system.  Laplace: CG
+ * steps with this operator, the recursive residual replaced by the FP64
+ * residual b - A w (full-precision far field) every 20 steps.  Helmholtz:
+ * iterative refinement, each cycle a GMRES(restart) solve of A~ d = r with this
+ * operator to relative 1e-4 (or what the last cycle needs), w += d, and the
+ * FP64 residual r = b - A w.  Convergence is judged on the FP64 residual; the
+ * iteration count includes both kinds of products. */
 #define IGB_FP32 1
 
 /* One NURBS patch F_j : [0,1]^2 -> Gamma_j (Sec. 2.2, eq. def::geom).
@@ -141,8 +148,11 @@ void igb_geometry_destroy(igb_geometry *geo);
  * igb_operator_destroy.  `hip_stream`
  * is a hipStream_t (NULL = default stream) used by every later call on the
  * operator.  Synchronises the stream before returning.
- * IGB_EINVAL for parameters out of range or geometry whose interior knots are
- * off the refinement grid; IGB_ENOMEM if HBM runs out; IGB_EHIP otherwise. */
+ * IGB_EINVAL for parameters out of range, geometry whose interior knots are
+ * off the refinement grid, or (Helmholtz) a wavenumber times the diagonal of
+ * the control points' bounding box of 2^18 or more (the kernels reduce the
+ * phase kappa |x - y| of surface points below 2^19); IGB_ENOMEM if HBM runs
+ * out; IGB_EHIP otherwise. */
 igb_status igb_operator_create(const igb_geometry *geo, const igb_params *prm, void *hip_stream,
                                igb_operator **out);
 /* Synchronises the operator's stream, then gives its device buffers back to

@@ -37,15 +37,32 @@ def build(force: bool = True) -> str:
 
 
 _lib = None
+_native = None  # path of a build for this host's CPU (use_native_build), used instead of _LIB
+
+
+def use_native_build() -> str:
+    """Compiles the oracle for the CPU of this host (-O3 -march=native) into a temporary directory and
+    loads that build from now on (for timing).  The default build targets x86-64-v3 so that it runs on
+    any host it is copied to.  Must be called before the oracle is first used in the process."""
+    import tempfile
+
+    global _native
+    if _lib is not None:
+        raise RuntimeError("the oracle is already loaded")
+    out = os.path.join(tempfile.mkdtemp(prefix="oracle_native_"), "liboracle.so")
+    subprocess.run(["gcc", "-O3", "-march=native", "-ffp-contract=off", "-fopenmp", "-fPIC", "-shared",
+                    "-std=gnu11", _SRC, "-o", out, "-lm"], check=True)
+    _native = out
+    return out
 
 
 def _load():
     global _lib
     if _lib is not None:
         return _lib
-    if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+    if _native is None and (not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC)):
         build(force=True)
-    lib = C.CDLL(_LIB)
+    lib = C.CDLL(_native or _LIB)
     P = C.c_void_p
     dp = C.POINTER(C.c_double)
     ip = C.POINTER(C.c_int32)

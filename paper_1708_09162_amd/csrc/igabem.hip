@@ -12,6 +12,7 @@
 #include <mutex>
 #include <set>
 #include <thread>
+#include <type_traits>
 #include <string>
 #include <type_traits>
 #include <vector>
@@ -1041,6 +1042,35 @@ __device__ inline void load8(const T *p, T v[8])
     }
 }
 
+// Sum over the 8 adjacent lanes of a lane group (lanes 8g .. 8g+7), every lane
+// receiving the total: quad_perm exchanges within quads (lane ^ 1, lane ^ 2),
+// then row_half_mirror (lane 7 - i within the group) joins the two quads.
+template <int CTRL>
+__device__ inline float dpp_mov(float v)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ inline double dpp_mov(double v)
+{
+    const long long b = __builtin_bit_cast(long long, v);
+    const int lo = __builtin_amdgcn_mov_dpp((int)b, CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xF, 0xF, false);
+    return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
+}
+template <class R>
+__device__ inline R group8_sum(R v)
+{
+    v += dpp_mov<0xB1>(v);   // quad_perm [1, 0, 3, 2]
+    v += dpp_mov<0x4E>(v);   // quad_perm [2, 3, 0, 1]
+    v += dpp_mov<0x141>(v);  // row_half_mirror
+    return v;
+}
+
+__device__ inline cd group8_sum(cd v) { return cd{group8_sum(v.re), group8_sum(v.im)}; }
+__device__ inline double shfl_xor_(double v, int o) { return __shfl_xor(v, o); }
+__device__ inline cd shfl_xor_(cd v, int o) { return cd{__shfl_xor(v.re, o), __shfl_xor(v.im, o)}; }
+
 struct NearSymArgs {
     int64_t nsb;
     const int32_t *sb_t, *sb_s;
@@ -1107,6 +1137,90 @@ __device__ inline void near_sym_wave(const NearSymArgs &N, int64_t k, const T *_
     }
 }
 
+// One stored near block k by one whole wave, without LDS (nl <= 64 S): lane
+// l = 8 lj + li owns rows rt + 8 li .. rt + 8 li + 7 of every 64-row tile and
+// the columns c = lj + 8 kc.  A lane's 8 rows are consecutive in the column-major
+// block, so the 8 lanes of a group read 64 consecutive rows of one column.  Row
+// sums (B x_s) are reduced over the 8 lanes lj at the end of a tile (shuffles);
+// column sums (B^T x_t, the mirrored block's product) over the 8 adjacent lanes
+// li after every column step (DPP) and kept by the lane li == kc % 8 in slot
+// kc / 8.  Writes the same partial rows as near_sym_wave.
+template <class T, int S>
+__device__ inline void near_sym_wave_reg(const NearSymArgs &N, int64_t k, const T *__restrict__ blocks,
+                                         const T *__restrict__ x, T *__restrict__ part)
+{
+    const int nl = N.nl, ld = N.ld;
+    const int lane = threadIdx.x & 63;
+    const int li = lane & 7, lj = lane >> 3;
+    const int64_t t = N.sb_t[k], sc = N.sb_s[k];
+    const T *B = blocks + k * (int64_t)nl * ld;
+    const T *xt = x + t * nl, *xsrc = x + sc * nl;
+    T *prow = part + (size_t)(2 * k) * ld;
+    T own[S];
+#pragma unroll
+    for (int q = 0; q < S; ++q) own[q] = zero<T>();
+    const int ncs = lj < nl ? (nl - lj + 7) / 8 : 0;  // columns lj + 8 kc < nl (the same for a whole group)
+    for (int rt = 0; rt < nl; rt += 64) {
+        const int r0 = rt + 8 * li;
+        const bool rows = r0 < nl;
+        T xr[8], ra[8];
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+            xr[r] = r0 + r < nl ? xt[r0 + r] : zero<T>();
+            ra[r] = zero<T>();
+        }
+        for (int kc = 0; kc < ncs; ++kc) {
+            const int c = lj + 8 * kc;
+            T cs = zero<T>();
+            if (rows) {
+                T v[8];
+                load8(B + (int64_t)c * ld + r0, v);
+                const T xc = xsrc[c];
+#pragma unroll
+                for (int r = 0; r < 8; ++r) {
+                    ra[r] += v[r] * xc;
+                    cs += v[r] * xr[r];
+                }
+            }
+            cs = group8_sum(cs);
+#pragma unroll
+            for (int q = 0; q < S; ++q)
+                if (li == (kc & 7) && (kc >> 3) == q) own[q] += cs;
+        }
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+            T a = ra[r];
+#pragma unroll
+            for (int o = 8; o < 64; o <<= 1) a += shfl_xor_(a, o);
+            if (lj == r && r0 + r < nl) prow[r0 + r] = a;
+        }
+    }
+    if (t != sc) {
+        T *pcol = part + (size_t)(2 * k + 1) * ld;
+#pragma unroll
+        for (int q = 0; q < S; ++q) {
+            const int kc = 8 * q + li;
+            if (kc < ncs) pcol[lj + 8 * kc] = own[q];
+        }
+    }
+}
+
+// A stored near block by one wave: without LDS when nl <= 256, else with the
+// wave's LDS slice cacc (8 ld + 520 elements).
+template <class T>
+__device__ inline void near_sym_block(const NearSymArgs &N, int64_t k, const T *__restrict__ blocks,
+                                      const T *__restrict__ x, T *__restrict__ part, T *cacc)
+{
+    if (N.nl <= 64) near_sym_wave_reg<T, 1>(N, k, blocks, x, part);
+    else if (N.nl <= 128) near_sym_wave_reg<T, 2>(N, k, blocks, x, part);
+    else if (N.nl <= 192) near_sym_wave_reg<T, 3>(N, k, blocks, x, part);
+    else if (N.nl <= 256) near_sym_wave_reg<T, 4>(N, k, blocks, x, part);
+    else near_sym_wave<T>(N, k, blocks, x, part, cacc);
+}
+
+// LDS elements per wave of near_sym_block
+__host__ __device__ inline int near_sym_lds(int nl, int ld) { return nl <= 256 ? 0 : 8 * ld + 520; }
+
 template <class T>
 __global__ void __launch_bounds__(256) k_near_sym(NearSymArgs N, const T *__restrict__ blocks, const T *__restrict__ x,
                                                   T *__restrict__ part)
@@ -1115,7 +1229,7 @@ __global__ void __launch_bounds__(256) k_near_sym(NearSymArgs N, const T *__rest
     const int wave = threadIdx.x >> 6;
     const int64_t k = (int64_t)blockIdx.x * (blockDim.x >> 6) + wave;
     if (k >= N.nsb) return;  // whole waves only; no block-wide barrier follows
-    near_sym_wave<T>(N, k, blocks, x, part, (T *)sh + (size_t)wave * (8 * N.ld + 520));
+    near_sym_block<T>(N, k, blocks, x, part, (T *)sh + (size_t)wave * near_sym_lds(N.nl, N.ld));
 }
 
 
@@ -1283,14 +1397,13 @@ template <int NTI>
 constexpr int far_mfma_lds() { return 21 * 16 * NTI + 4; }
 
 // LDS doubles per wave for the far-field pairs: the matrix-core path for the
-// real kernel; for the complex one (far_sym_chunk) 8 rows of partial sums (row
-// stride 8 TT + 1) and the pair's target and source nodes (x, y, z, weighted
-// moment).
+// real kernel; for the complex one (far_sym_chunk) the pair's target and
+// source nodes (x, y, z, weighted moment re, im), 8 TT each.
 template <class T, int TT>
 constexpr int far_sym_lds()
 {
     if constexpr (NComp<T>::value == 1) return far_mfma_lds<(TT + 1) / 2>();
-    else return 8 * (8 * TT + 1) * NComp<T>::value + 2 * (3 + NComp<T>::value) * 8 * TT;
+    else return 2 * 5 * 8 * TT;
 }
 
 // Node data of one cluster's node j for the far field: position and the
@@ -1315,130 +1428,135 @@ __device__ inline FarNode<T> far_node(const FarSymArgs &F, const T *__restrict__
     return n;
 }
 
-// Pairs k0 .. k1-1 of the far field, executed by one whole wave; lds is the
-// wave's slice of far_sym_lds<T, TT>() doubles.  Lane (li, lj) owns targets
-// li*TT + ii and sources jj*8 + lj (ii, jj < TT); node data comes from LDS.
-template <class T, int TT>
-__device__ inline void far_sym_chunk(const FarSymArgs &F, int64_t k0, int64_t k1, const T *__restrict__ Xh,
-                                     T *__restrict__ part, double *lds)
+// Kernel value G(x, y) 4 pi = exp(i kappa r) / r of the complex far field from r^2.  Double precision:
+// refined reciprocal square root, the phase clamped into the range of sincos_red (padding nodes sit 1e100
+// away; their weight is zero on one side and their value below 1e-100 on the other).  Single precision
+// (RAW): the hardware reciprocal square root, the phase kappa r / (2 pi) in turns reduced to one turn
+// (v_fract) for the hardware sine and cosine, which take turns.
+template <bool RAW>
+__device__ inline void helm_far_value(typename std::conditional<RAW, float, double>::type r2,
+                                      typename std::conditional<RAW, float, double>::type kap,
+                                      typename std::conditional<RAW, float, double>::type &gr,
+                                      typename std::conditional<RAW, float, double>::type &gi)
 {
-    constexpr int NC = NComp<T>::value;
+    if constexpr (RAW) {
+        const float ir = __builtin_amdgcn_rsqf(r2);
+        const float ph = __builtin_amdgcn_fractf(r2 * ir * kap);
+        gr = __builtin_amdgcn_cosf(ph) * ir;
+        gi = __builtin_amdgcn_sinf(ph) * ir;
+    } else {
+        const double ir = rsqrt_pos(r2);
+        double sn, cs;
+        sincos_red(fmin(kap * (r2 * ir), 0x1p19), &sn, &cs);
+        gr = cs * ir;
+        gi = sn * ir;
+    }
+}
+
+// Complex kernel: pairs k0 .. k1-1 of the far field, executed by one whole wave;
+// lds is the wave's slice of far_sym_lds<cd, TT>() doubles (the two clusters'
+// nodes).  Lane (li, lj) owns targets li*TT + ii and sources jj*8 + lj
+// (ii, jj < TT).  The targets go in NP passes of at most TH, so that few of
+// them are held in registers at a time; the column sums of the lane's TT
+// sources stay in registers over the passes.  Row sums are reduced over the 8
+// lanes of a target group and column sums over the 8 groups by lane shuffles,
+// and the owner lanes write the two partial rows (no LDS beyond the nodes).
+// Positions are taken relative to the pair's first target node.  RAW: kernel
+// values and the sums inside the pair in FP32 (positions rounded after the
+// shift, so the rounding is relative to the cluster separation).
+template <int TT, bool RAW>
+__device__ inline void far_sym_chunk(const FarSymArgs &F, int64_t k0, int64_t k1, const cd *__restrict__ Xh,
+                                     cd *__restrict__ part, double *lds)
+{
+    using R = typename std::conditional<RAW, float, double>::type;
     constexpr int W = 8 * TT;  // padded nodes per cluster
-    constexpr int WS = W + 1;  // LDS row stride (spreads the 8 rows over the banks)
-    T *cb = (T *)lds;
-    double *tg = lds + 8 * WS * NC, *sr = tg + (3 + NC) * W;  // [x | y | z | w (NC)] x W each
+    constexpr int NP = (TT + 4) / 5, TH = (TT + NP - 1) / NP;
+    double *tg = lds, *sr = lds + 5 * W;  // [x | y | z | w.re | w.im] x W each
     const int q2 = F.q2;
-    const double kappa = F.kappa;
+    const R kap = RAW ? (R)(F.kappa * 0.15915494309189535) : (R)F.kappa;  // RAW: turns per unit length
+    const double pad = RAW ? 1e4 : 1e100;
     const int lane = threadIdx.x & 63;
-    const int li = lane >> 3, lj = lane & 7;
-    auto stage = [&](double *d, int j, const FarNode<T> &n) {
+    const int li = lane & 7, lj = lane >> 3;
+    auto stage = [&](double *d, int j, const FarNode<cd> &n) {
         d[j] = n.x;
         d[W + j] = n.y;
         d[2 * W + j] = n.z;
-        d[3 * W + j] = re_(n.w);
-        if constexpr (NC == 2) d[4 * W + j] = im_(n.w);
+        d[3 * W + j] = n.w.re;
+        d[4 * W + j] = n.w.im;
     };
-    // lane j holds target node j and source node j of the next pair, and nodes
-    // j + 64 as well when W > 64
-    constexpr bool TWO = W > 64;
-    FarNode<T> nt{}, ns{}, nt2{}, ns2{};
-    if (lane < W) {
-        nt = far_node<T>(F, Xh, F.up_t[k0], lane, 1e100);
-        ns = far_node<T>(F, Xh, F.up_s[k0], lane, -1e100);
-    }
-    if constexpr (TWO) {
-        if (lane + 64 < W) {
-            nt2 = far_node<T>(F, Xh, F.up_t[k0], lane + 64, 1e100);
-            ns2 = far_node<T>(F, Xh, F.up_s[k0], lane + 64, -1e100);
-        }
-    }
     for (int64_t k = k0; k < k1; ++k) {
-        if (lane < W) {
-            stage(tg, lane, nt);
-            stage(sr, lane, ns);
-        }
-        if constexpr (TWO) {
-            if (lane + 64 < W) {
-                stage(tg, lane + 64, nt2);
-                stage(sr, lane + 64, ns2);
-            }
+        // the pair's nodes into LDS (the other waves of the SIMD cover the load latency)
+        for (int j = lane; j < W; j += 64) {
+            stage(tg, j, far_node<cd>(F, Xh, F.up_t[k], j, pad));
+            stage(sr, j, far_node<cd>(F, Xh, F.up_s[k], j, -pad));
         }
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-        if (k + 1 < k1 && lane < W) {  // prefetch the next pair
-            nt = far_node<T>(F, Xh, F.up_t[k + 1], lane, 1e100);
-            ns = far_node<T>(F, Xh, F.up_s[k + 1], lane, -1e100);
-        }
-        if constexpr (TWO) {
-            if (k + 1 < k1 && lane + 64 < W) {
-                nt2 = far_node<T>(F, Xh, F.up_t[k + 1], lane + 64, 1e100);
-                ns2 = far_node<T>(F, Xh, F.up_s[k + 1], lane + 64, -1e100);
+        const double cx = tg[0], cy = tg[W], cz = tg[2 * W];
+        // column sums: source jj*8 + lj is owned by lane li == jj % 8 (slot jj / 8)
+        R c0r = (R)0, c0i = (R)0, c1r = (R)0, c1i = (R)0;
+        cd *pr = part + (size_t)(2 * k) * q2, *pc = part + (size_t)(2 * k + 1) * q2;
+#pragma unroll 1
+        for (int h = 0; h < NP; ++h) {
+            const int n_h = min(TH, TT - h * TH);  // targets in this pass
+            R tx[TH], ty[TH], tz[TH], wr[TH], wi[TH], ar[TH], ai[TH];
+#pragma unroll
+            for (int ii = 0; ii < TH; ++ii) {
+                const int i = li * TT + h * TH + min(ii, n_h - 1);  // a repeated target carries weight 0
+                tx[ii] = (R)(tg[i] - cx);
+                ty[ii] = (R)(tg[W + i] - cy);
+                tz[ii] = (R)(tg[2 * W + i] - cz);
+                wr[ii] = ii < n_h ? (R)tg[3 * W + i] : (R)0;
+                wi[ii] = ii < n_h ? (R)tg[4 * W + i] : (R)0;
+                ar[ii] = ai[ii] = (R)0;
             }
-        }
-        double tx[TT], ty[TT], tz[TT];
-        T wt[TT], racc[TT];
+#pragma unroll 1
+            for (int jj = 0; jj < TT; ++jj) {
+                const int j = jj * 8 + lj;
+                const R sx = (R)(sr[j] - cx), sy = (R)(sr[W + j] - cy), sz = (R)(sr[2 * W + j] - cz);
+                const R swr = (R)sr[3 * W + j], swi = (R)sr[4 * W + j];
+                R pr_ = (R)0, pi_ = (R)0;
 #pragma unroll
-        for (int ii = 0; ii < TT; ++ii) {
-            const int i = li * TT + ii;
-            tx[ii] = tg[i];
-            ty[ii] = tg[W + i];
-            tz[ii] = tg[2 * W + i];
-            if constexpr (NC == 1) wt[ii] = tg[3 * W + i];
-            else wt[ii] = T{tg[3 * W + i], tg[4 * W + i]};
-            racc[ii] = zero<T>();
-        }
-#pragma unroll 2
-        for (int jj = 0; jj < TT; ++jj) {
-            const int j = jj * 8 + lj;
-            const double sx = sr[j], sy = sr[W + j], sz = sr[2 * W + j];
-            T ws;
-            if constexpr (NC == 1) ws = sr[3 * W + j];
-            else ws = T{sr[3 * W + j], sr[4 * W + j]};
-            T csum = zero<T>();
-#pragma unroll
-            for (int ii = 0; ii < TT; ++ii) {
-                const double d0 = tx[ii] - sx, d1 = ty[ii] - sy, d2 = tz[ii] - sz;
-                const double r2 = d0 * d0 + d1 * d1 + d2 * d2;
-                const double ir = rsqrt_pos(r2);
-                if constexpr (NC == 1) {
-                    racc[ii] += ir * ws;
-                    csum += ir * wt[ii];
-                } else {
-                    // padding nodes sit 1e100 away: their phase is clamped into the reduction's range
-                    // (zero weight on the padding side, a value below 1e-100 on the other)
-                    double sn, cs;
-                    sincos_red(fmin(kappa * (r2 * ir), 0x1p19), &sn, &cs);
-                    const T g{cs * ir, sn * ir};
-                    racc[ii] += g * ws;
-                    csum += g * wt[ii];
+                for (int ii = 0; ii < TH; ++ii) {
+                    const R d0 = tx[ii] - sx, d1 = ty[ii] - sy, d2 = tz[ii] - sz;
+                    R gr, gi;
+                    helm_far_value<RAW>(d0 * d0 + d1 * d1 + d2 * d2, kap, gr, gi);
+                    ar[ii] += gr * swr - gi * swi;
+                    ai[ii] += gr * swi + gi * swr;
+                    pr_ += gr * wr[ii] - gi * wi[ii];
+                    pi_ += gr * wi[ii] + gi * wr[ii];
+                }
+                pr_ = group8_sum(pr_);
+                pi_ = group8_sum(pi_);
+                if (li == (jj & 7)) {
+                    if (jj < 8) {
+                        c0r += pr_;
+                        c0i += pi_;
+                    } else {
+                        c1r += pr_;
+                        c1i += pi_;
+                    }
                 }
             }
-            cb[li * WS + lj * TT + jj] = csum;  // column of source j at lj*TT + jj (bank spread)
-        }
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-        T *pc = part + (size_t)(2 * k + 1) * q2;
-        for (int j = lane; j < q2; j += 64) {
-            const int pj = (j & 7) * TT + (j >> 3);
-            T v = cb[pj];
+            // rows of this pass: reduce over the 8 lanes lj; lane lj == ii writes target ii
 #pragma unroll
-            for (int r = 1; r < 8; ++r) v += cb[r * WS + pj];
-            pc[j] = v;
-        }
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+            for (int ii = 0; ii < TH; ++ii) {
+                R a = ar[ii], b = ai[ii];
 #pragma unroll
-        for (int ii = 0; ii < TT; ++ii) cb[lj * WS + li * TT + ii] = racc[ii];
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-        T *pr = part + (size_t)(2 * k) * q2;
-        for (int i = lane; i < q2; i += 64) {
-            T v = cb[i];
-#pragma unroll
-            for (int r = 1; r < 8; ++r) v += cb[r * WS + i];
-            pr[i] = v;
+                for (int o = 8; o < 64; o <<= 1) {
+                    a += __shfl_xor(a, o);
+                    b += __shfl_xor(b, o);
+                }
+                const int i = li * TT + h * TH + ii;
+                if (lj == ii && ii < n_h && i < q2) pr[i] = cd{(double)a, (double)b};
+            }
         }
-        __builtin_amdgcn_wave_barrier();
+        {
+            const int j0 = li * 8 + lj, j1 = (li + 8) * 8 + lj;
+            if (li < TT && j0 < q2) pc[j0] = cd{(double)c0r, (double)c0i};
+            if (li + 8 < TT && j1 < q2) pc[j1] = cd{(double)c1r, (double)c1i};
+        }
+        __builtin_amdgcn_wave_barrier();  // every lane has read the nodes before the next staging
         __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
     }
 }
@@ -1564,8 +1682,7 @@ __device__ inline void far_chunk(const FarSymArgs &F, int64_t k0, int64_t k1, co
     if constexpr (NComp<T>::value == 1) {
         far_mfma_chunk<(TT + 1) / 2, RAW>(F, k0, k1, Xh, part, lds);
     } else {
-        static_assert(!RAW, "single-precision far field: real kernel only");
-        far_sym_chunk<T, TT>(F, k0, k1, Xh, part, lds);
+        far_sym_chunk<TT, RAW>(F, k0, k1, Xh, part, lds);
     }
 }
 
@@ -1582,15 +1699,20 @@ __global__ void __launch_bounds__(256, NComp<T>::value == 1 ? 3 : 1) k_far_sym(F
     far_chunk<T, TT, RAW>(F, k0, min(k0 + kFarChunk, F.nup), Xh, part, buf[wave]);
 }
 
-// Complex kernel with 65 .. 104 nodes per cluster: one wave per workgroup
-// (its LDS slice is too large for four), kFarChunk pairs per wave.
-template <class T, int TT>
-__global__ void __launch_bounds__(64, 1) k_far_sym1(FarSymArgs F, const T *__restrict__ Xh, T *__restrict__ part)
+// Complex kernel with 65 .. 104 nodes per cluster: one wave per workgroup,
+// chunks of kFarChunk pairs, grid-strided.  The host launches a fixed number
+// of waves per SIMD (kFarWaves), fewer than the registers allow, so that the
+// near-field GEMV on the side stream finds room on every CU.
+constexpr int kFarWaves[2] = {3, 3};  // double, single precision: the fastest of 2..4 measured (torus, kappa 8, q 10)
+template <class T, int TT, bool RAW>
+__global__ void __launch_bounds__(64, RAW ? 4 : 2) k_far_sym1(FarSymArgs F, const T *__restrict__ Xh, T *__restrict__ part)
 {
     extern __shared__ double sh[];
-    const int64_t k0 = (int64_t)blockIdx.x * kFarChunk;
-    if (k0 >= F.nup) return;
-    far_sym_chunk<T, TT>(F, k0, min(k0 + kFarChunk, F.nup), Xh, part, sh);
+    const int64_t nch = (F.nup + kFarChunk - 1) / kFarChunk;
+    for (int64_t c = blockIdx.x; c < nch; c += gridDim.x) {
+        const int64_t k0 = c * kFarChunk;
+        far_sym_chunk<TT, RAW>(F, k0, min(k0 + kFarChunk, F.nup), Xh, part, sh);
+    }
 }
 
 // The far-field pairs and the stored near blocks in one launch (ALU-bound and
@@ -1610,11 +1732,11 @@ __global__ void __launch_bounds__(256, NComp<T>::value == 1 ? 3 : 1) k_sym_produ
     const int64_t b = blockIdx.x, tot = nf + nn;
     const int64_t before = b * nn / tot, upto = (b + 1) * nn / tot;
     // per-wave LDS slice (doubles): the larger of the two kinds
-    const int slice = max(far_sym_lds<T, TT>(), (8 * N.ld + 520) * NComp<T>::value);
+    const int slice = max(far_sym_lds<T, TT>(), near_sym_lds(N.nl, N.ld) * NComp<T>::value);
     if (upto > before) {
         const int64_t k = before * 4 + wave;
         if (k >= N.nsb) return;
-        near_sym_wave<T>(N, k, blocks, x, npart, (T *)(sh + (size_t)wave * slice));
+        near_sym_block<T>(N, k, blocks, x, npart, (T *)(sh + (size_t)wave * slice));
     } else {
         const int64_t k0 = ((b - before) * 4 + wave) * kFarChunk;
         if (k0 >= F.nup) return;
@@ -2549,6 +2671,7 @@ struct igb_operator {
     hipStream_t st = nullptr;
     bool cplx = false;
     size_t esz = 8;
+    int ncu = 256;  // compute units of the device (grid size of the persistent far-field launches)
     Layout lo{};
     int lmin = 0;  // coarsest level with far blocks (L+1 if none)
     // device data
@@ -2671,9 +2794,9 @@ static NearLayout near_layout(const Setup &s, size_t esz)
 // With both products symmetric, the near blocks ride along in the far-field
 // launch (and both gathers share one launch) when four waves' near staging fits
 // 64 KB of LDS.
-static bool fused_products(bool near_sym, int near_ld, size_t esz, int q2)
+static bool fused_products(bool near_sym, int nl, int near_ld, size_t esz, int q2)
 {
-    return near_sym && q2 <= 64 && 4 * (size_t)(8 * near_ld + 520) * esz <= 64 * 1024;
+    return near_sym && q2 <= 64 && 4 * (size_t)near_sym_lds(nl, near_ld) * esz <= 64 * 1024;
 }
 
 // Far field evaluated once per mirrored pair of blocks (on the fly; q^2 <= 64 for
@@ -2810,9 +2933,10 @@ static void launch_far_sym_p(igb_operator *op, const T *Xh, const T *xs, bool fu
     if constexpr (TT > 8) {  // one wave per workgroup (LDS slice of far_sym_lds doubles), never fused
         (void)fuse;
         const size_t shm = (size_t)far_sym_lds<T, TT>() * sizeof(double);
-        (void)hipFuncSetAttribute((const void *)k_far_sym1<T, TT>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-        hipLaunchKernelGGL((k_far_sym1<T, TT>), dim3((unsigned)((op->nup + kFarChunk - 1) / kFarChunk)), dim3(64), shm,
-                           op->st, far_args(op), Xh, (T *)op->fpart);
+        const int64_t nch = (op->nup + kFarChunk - 1) / kFarChunk;
+        const int64_t grid = std::min<int64_t>(nch, (int64_t)op->ncu * 4 * kFarWaves[RAW ? 1 : 0]);
+        hipLaunchKernelGGL((k_far_sym1<T, TT, RAW>), dim3((unsigned)grid), dim3(64), shm, op->st, far_args(op), Xh,
+                           (T *)op->fpart);
     } else {
         if (!fuse) {
             hipLaunchKernelGGL((k_far_sym<T, TT, RAW>),
@@ -2821,8 +2945,9 @@ static void launch_far_sym_p(igb_operator *op, const T *Xh, const T *xs, bool fu
             return;
         }
         const int64_t nf = (op->nup + 4 * kFarChunk - 1) / (4 * kFarChunk), nn = (op->nsb + 3) / 4;
-        const size_t shm =
-            4 * std::max<size_t>((size_t)(8 * op->near_ld + 520) * NComp<T>::value, (size_t)far_sym_lds<T, TT>()) * 8;
+        const size_t shm = 4 *
+                           std::max<size_t>((size_t)near_sym_lds(op->s.nl, op->near_ld) * NComp<T>::value,
+                                            (size_t)far_sym_lds<T, TT>()) * 8;
         hipLaunchKernelGGL((k_sym_products<T, TT, RAW>), dim3((unsigned)(nf + nn)), dim3(256), shm, op->st, far_args(op),
                            near_args(op), nf, nn, Xh, (T *)op->fpart, (const T *)op->nearb, xs, (T *)op->npart);
     }
@@ -2832,11 +2957,9 @@ template <class T, int TT>
 static void launch_far_sym(igb_operator *op, const T *Xh, const T *xs, bool fuse)
 {
     static_assert(TT <= 8 || NComp<T>::value == 2, "more than 64 nodes per cluster: complex kernel only");
-    if constexpr (NComp<T>::value == 1) {
-        if (op->far_single && !op->force_fp64) {
-            launch_far_sym_p<T, TT, true>(op, Xh, xs, fuse);
-            return;
-        }
+    if (op->far_single && !op->force_fp64) {
+        launch_far_sym_p<T, TT, true>(op, Xh, xs, fuse);
+        return;
     }
     launch_far_sym_p<T, TT, false>(op, Xh, xs, fuse);
 }
@@ -2876,9 +2999,8 @@ static std::vector<TreeLaunch> tree_slices(const igb_operator *op, size_t esz)
 template <class T>
 static void launch_near_sym(igb_operator *op, const T *xs, hipStream_t st)
 {
-    const int ld = op->near_ld;
-    const size_t wave_lds = (size_t)(8 * ld + 520) * sizeof(T);
-    const int wpb = (int)std::max<size_t>(1, std::min<size_t>(4, (64 * 1024) / wave_lds));
+    const size_t wave_lds = (size_t)near_sym_lds(op->s.nl, op->near_ld) * sizeof(T);
+    const int wpb = wave_lds ? (int)std::max<size_t>(1, std::min<size_t>(4, (64 * 1024) / wave_lds)) : 4;
     hipLaunchKernelGGL((k_near_sym<T>), dim3((unsigned)((op->nsb + wpb - 1) / wpb)), dim3(64 * wpb), wpb * wave_lds,
                        st, near_args(op), (const T *)op->nearb, xs, (T *)op->npart);
 }
@@ -2910,7 +3032,7 @@ static igb_status matvec_internal(igb_operator *op, const T *xs, T *ys, hipEvent
     if ((rc = mark(1))) return rc;
     int64_t row0 = s.cl_off[op->lmin], nrows = s.cl_off[s.L + 1] - row0;
     const bool sym = has_far && op->fpart != nullptr;
-    const bool fuse = sym && !separate && fused_products(op->near_sym, op->near_ld, sizeof(T), q2);
+    const bool fuse = sym && !separate && fused_products(op->near_sym, s.nl, op->near_ld, sizeof(T), q2);
     // near blocks not fused into the far-field launch: their GEMV reads only xs, so it runs on the side
     // stream from the start of the product and is joined before its gather
     const bool fork = has_far && op->near_sym && !fuse && !separate && !ev;
@@ -3639,9 +3761,11 @@ __global__ void k_scale_dev(int64_t n, const double *__restrict__ alpha, T *__re
 // device never waits for it; the small triangular solve runs on the host once
 // per restart cycle.  Real (Laplace, optionally with a network) and complex
 // (Helmholtz, Jacobi) systems; the operator runs in FP64 throughout.
+// fp64 = false (single-precision far field only): the products use that far field; the
+// refinement of solve_refined keeps the FP64 residuals outside.
 template <class T>
 static igb_status solve_gmres_dev(igb_operator *op, const igb_cnn *net, const T *b, T *w, double tol, int maxit,
-                                  int restart, igb_solve_info *info)
+                                  int restart, igb_solve_info *info, bool fp64 = true)
 {
     const Setup &s = op->s;
     const int64_t n = s.ndof;
@@ -3652,7 +3776,7 @@ static igb_status solve_gmres_dev(igb_operator *op, const igb_cnn *net, const T 
         bool v;
         ~Restore() { o->force_fp64 = v; }
     } restore{op, op->force_fp64};
-    op->force_fp64 = true;
+    op->force_fp64 = fp64;
     const size_t gT = (size_t)(R + 1) * R + 3 * (size_t)R + 1;  // H, cs, sn, g
     if (op->Vcols < R + 1 || op->Zcols < R) {
         HIPCHK(hipStreamSynchronize(op->st));
@@ -3919,6 +4043,12 @@ igb_status igb_operator_create(const igb_geometry *geo, const igb_params *prm, v
     op->cplx = s.kernel == IGB_HELMHOLTZ;
     op->far_single = prm->far_precision == IGB_FP32;
     op->esz = op->cplx ? sizeof(cd) : sizeof(double);
+    {
+        int dv = 0, n = 0;
+        if (hipGetDevice(&dv) == hipSuccess &&
+            hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dv) == hipSuccess && n > 0)
+            op->ncu = n;
+    }
     op->lo = Layout{s.p, s.p + 1, s.nloc, s.nl, s.side, s.L, s.ne, s.ns1};
     // GPU: Gauss-node geometry and identical-pair quadrature, then the other touching
     // pairs; host meanwhile: element geometry, touching search, tree, partition, lists
@@ -4072,6 +4202,68 @@ igb_status igb_jacobi_diag(const igb_operator *op, void *d_dev)
     return IGB_OK;
 }
 
+// Helmholtz with the single-precision far field (IGB_FP32): iterative refinement.
+// Each cycle solves the correction equation A~ d = r with the device GMRES on the
+// single-precision operator A~ to the relative tolerance tau, adds d to w, and
+// forms r = b - A w with the FP64 operator; it stops when that residual meets
+// rel_tol.  tau = max(1e-4, rel_tol / (2 |r| / |b|)): the last cycle is asked for
+// no more than it has to gain.  Iterations count the single-precision products of
+// the inner solves and the FP64 residual products.
+static igb_status solve_refined(igb_operator *op, const cd *b, cd *w, double tol, int maxit, int restart,
+                                igb_solve_info *info)
+{
+    const int64_t n = op->s.ndof;
+    cd *r = (cd *)op->rr, *d = (cd *)op->dw;
+    const unsigned gb = std::min<unsigned>(nblk(n, 256), 1024);
+    igb_status rc;
+    struct Restore {
+        igb_operator *o;
+        bool v;
+        ~Restore() { o->force_fp64 = v; }
+    } restore{op, op->force_fp64};
+    auto norm = [&](const cd *x, double *out) -> igb_status {
+        igb_status c;
+        if ((c = dot_dev<cd>(op, n, x, x, (cd *)op->scal))) return c;
+        if ((c = read_scalar(op, 0, out))) return c;
+        *out = std::sqrt(*out);
+        return IGB_OK;
+    };
+    double bn;
+    if ((rc = norm(b, &bn))) return rc;
+    if (bn == 0.0) bn = 1.0;
+    int it = 0;
+    double rel = 0.0;
+    for (;;) {
+        op->force_fp64 = true;
+        if ((rc = matvec_S<cd>(op, w, d))) return rc;
+        HIPCHK(hipMemcpyAsync(r, b, n * sizeof(cd), hipMemcpyDeviceToDevice, op->st));
+        hipLaunchKernelGGL((k_axpby<cd>), dim3(gb), dim3(256), 0, op->st, n, cd{-1.0, 0.0}, (const cd *)d,
+                           cd{1.0, 0.0}, r);
+        LAUNCHCHK();
+        double rn;
+        if ((rc = norm(r, &rn))) return rc;
+        ++it;
+        rel = rn / bn;
+        if (rel <= tol || it >= maxit) break;
+        HIPCHK(hipMemsetAsync(d, 0, n * sizeof(cd), op->st));
+        igb_solve_info in{};
+        rc = solve_gmres_dev<cd>(op, nullptr, r, d, std::max(1e-4, 0.5 * tol / rel), maxit - it, restart, &in, false);
+        if (rc < 0) return rc;
+        it += in.iterations;
+        hipLaunchKernelGGL((k_axpby<cd>), dim3(gb), dim3(256), 0, op->st, n, cd{1.0, 0.0}, (const cd *)d,
+                           cd{1.0, 0.0}, w);
+        LAUNCHCHK();
+    }
+    if (info) {
+        info->iterations = it;
+        info->rel_residual = rel;
+        info->converged = rel <= tol;
+    }
+    return rel <= tol ? IGB_OK
+                      : fail(IGB_ENOT_CONVERGED, "refinement stopped at max_iter with relative residual " +
+                                                     std::to_string(rel));
+}
+
 igb_status igb_solve(const igb_operator *cop, const void *b_dev, void *w_dev, double rel_tol, int32_t max_iter,
                      int32_t restart, igb_solve_info *info)
 {
@@ -4082,6 +4274,8 @@ igb_status igb_solve(const igb_operator *cop, const void *b_dev, void *w_dev, do
     igb_operator *op = const_cast<igb_operator *>(cop);
     if (op->cplx) {
         if (restart < 1 || restart > 2048) return fail(IGB_EINVAL, "restart must be in 1..2048");
+        if (op->far_single)
+            return solve_refined(op, (const cd *)b_dev, (cd *)w_dev, rel_tol, max_iter, restart, info);
         return solve_gmres_dev<cd>(op, nullptr, (const cd *)b_dev, (cd *)w_dev, rel_tol, max_iter, restart, info);
     }
     return solve_cg(op, (const double *)b_dev, (double *)w_dev, rel_tol, max_iter, info);
@@ -4412,7 +4606,7 @@ static void fill_info(const Setup &s, size_t esz, igb_info *out)
         out->near_bytes = NL.nsb * s.nl * NL.ld * (int64_t)esz;
         const bool fm = far_mirrored(s);
         out->layout_flags =
-            (NL.sym ? 1 : 0) | (fm ? 2 : 0) | (fm && fused_products(NL.sym, NL.ld, esz, s.q * s.q) ? 4 : 0);
+            (NL.sym ? 1 : 0) | (fm ? 2 : 0) | (fm && fused_products(NL.sym, s.nl, NL.ld, esz, s.q * s.q) ? 4 : 0);
     }
     out->coupling_bytes = s.mode == IGB_H2_STORED ? out->n_far_blocks * q2 * q2 * (int64_t)esz : 0;
     // one superspace matvec moves every stored block once, the S* vector in and

@@ -31,21 +31,27 @@ __host__ __device__ inline double abs2(cd a) { return a.re * a.re + a.im * a.im;
 
 // sin t and cos t for |t| < 2^19: the Helmholtz phase kappa |x - y| between surface points (the operator
 // checks kappa times the size of the geometry at creation).  Branch-free.
-//  * Range reduction after Cody and Waite: t = n pi/2 + y, n = rint(2t/pi), |y| <= pi/4 up to rounding.
-//    pi/2 = C1 + C2 + C3 with C1 and C2 of 30 significant bits, so n C1 and n C2 are exact for |n| < 2^23;
-//    t - n C1 is exact as well (both are multiples of 2^-33 and differ by less than 1), and the two
-//    further fused steps round once each.
-//  * On |y| <= pi/4 the Taylor series of sin (through y^15) and of cos (through y^16), evaluated by
-//    Horner's rule in y^2; the first omitted terms, y^17/17! and y^18/18!, are below 2^-57.
-//  * The quadrant n mod 4 picks and signs the pair: (sin t, cos t) = (s, c), (c, -s), (-s, -c), (-c, s).
+//  * Range reduction after Cody and Waite: t = n pi + y with n the integer nearest t/pi, |y| <= pi/2 up
+//    to rounding.  n comes from adding 1.5 2^52 in the fused multiply-add t (1/pi) + 1.5 2^52, whose
+//    result has unit spacing, so its lowest mantissa bit is the parity of n.  pi = C1 + C2 + C3 with C1
+//    and C2 of 30 significant bits, so n C1 and n C2 are exact for |n| < 2^23; t - n C1 is exact as well
+//    (both are multiples of 2^-32 and differ by less than 2), and the two further fused steps round once
+//    each.
+//  * On |y| <= pi/2 the Taylor series of sin (through y^21) and of cos (through y^20), evaluated by
+//    Horner's rule in z = y^2; the first omitted terms, (pi/2)^23/23! and (pi/2)^22/22!, are below 2^-55.
+//  * sin(n pi + y) = (-1)^n sin y and cos(n pi + y) = (-1)^n cos y: the parity of n flips both sign bits.
 __host__ __device__ inline void sincos_red(double t, double *sn, double *cs)
 {
-    const double n = rint(t * 0x1.45f306dc9c883p-1);  // 2/pi
-    double y = fma(-n, 0x1.921fb548p+0, t);            // C1
-    y = fma(-n, -0x1.de973dc8p-31, y);                 // C2
-    y = fma(-n, -0x1.9d9cceba3f91fp-62, y);            // C3
+    const double m = fma(t, 0x1.45f306dc9c883p-2, 0x1.8p52);  // t (1/pi) + 1.5 2^52
+    const double n = m - 0x1.8p52;
+    double y = fma(-n, 0x1.921fb548p+1, t);            // C1
+    y = fma(-n, -0x1.de973dc8p-30, y);                 // C2
+    y = fma(-n, -0x1.9d9cceba3f91fp-61, y);            // C3
     const double z = y * y;
-    double ps = -0x1.ae7f3e733b81fp-41;                // -1/15!
+    double ps = 0x1.71b8ef6dcf572p-66;                 //  1/21!
+    ps = fma(ps, z, -0x1.2f49b46814157p-57);           // -1/19!
+    ps = fma(ps, z, 0x1.952c77030ad4ap-49);            //  1/17!
+    ps = fma(ps, z, -0x1.ae7f3e733b81fp-41);           // -1/15!
     ps = fma(ps, z, 0x1.6124613a86d09p-33);            //  1/13!
     ps = fma(ps, z, -0x1.ae64567f544e4p-26);           // -1/11!
     ps = fma(ps, z, 0x1.71de3a556c734p-19);            //  1/9!
@@ -53,7 +59,9 @@ __host__ __device__ inline void sincos_red(double t, double *sn, double *cs)
     ps = fma(ps, z, 0x1.1111111111111p-7);             //  1/5!
     ps = fma(ps, z, -0x1.5555555555555p-3);            // -1/3!
     const double sy = fma(y * z, ps, y);               // sin y = y + y^3 (-1/3! + z/5! - ...)
-    double pc = 0x1.ae7f3e733b81fp-45;                 //  1/16!
+    double pc = 0x1.e542ba4020225p-62;                 //  1/20!
+    pc = fma(pc, z, -0x1.6827863b97d97p-53);           // -1/18!
+    pc = fma(pc, z, 0x1.ae7f3e733b81fp-45);            //  1/16!
     pc = fma(pc, z, -0x1.93974a8c07c9dp-37);           // -1/14!
     pc = fma(pc, z, 0x1.1eed8eff8d898p-29);            //  1/12!
     pc = fma(pc, z, -0x1.27e4fb7789f5cp-22);           // -1/10!
@@ -61,10 +69,9 @@ __host__ __device__ inline void sincos_red(double t, double *sn, double *cs)
     pc = fma(pc, z, -0x1.6c16c16c16c17p-10);           // -1/6!
     pc = fma(pc, z, 0x1.5555555555555p-5);             //  1/4!
     const double cy = fma(z * z, pc, fma(z, -0.5, 1.0));  // cos y = 1 - z/2 + z^2 (1/4! - z/6! + ...)
-    const int q = (int)n;
-    const double a = (q & 1) ? cy : sy, b = (q & 1) ? sy : cy;
-    *sn = (q & 2) ? -a : a;
-    *cs = ((q + 1) & 2) ? -b : b;
+    const unsigned long long flip = __builtin_bit_cast(unsigned long long, m) << 63;
+    *sn = __builtin_bit_cast(double, __builtin_bit_cast(unsigned long long, sy) ^ flip);
+    *cs = __builtin_bit_cast(double, __builtin_bit_cast(unsigned long long, cy) ^ flip);
 }
 
 // Fundamental solutions of Sec. 3.1 (eq. fundament1 / fundament2) at distance r.

@@ -849,8 +849,8 @@ std::string build_setup_tiles(const Geometry &geo, const igb_params &prm, Setup 
     if (prm.far_precision != IGB_FP64 && prm.far_precision != IGB_FP32)
         return "far_precision must be IGB_FP64 or IGB_FP32";
     if (prm.far_precision == IGB_FP32 &&
-        (prm.kernel != IGB_LAPLACE || prm.mode != IGB_H2_ONTHEFLY || prm.q * prm.q > 64))
-        return "far_precision IGB_FP32 needs the Laplace kernel, on-the-fly coupling and q <= 8";
+        (prm.mode != IGB_H2_ONTHEFLY || prm.q * prm.q > (prm.kernel == IGB_HELMHOLTZ ? 104 : 64)))
+        return "far_precision IGB_FP32 needs on-the-fly coupling and q <= 8 (Laplace) or q <= 10 (Helmholtz)";
     if (prm.leaf_depth < -1 || prm.leaf_depth > 10) return "leaf_depth outside -1..10";
     if (prm.kernel == IGB_HELMHOLTZ) {
         // the kernels reduce the phase kappa |x - y| between surface points for |kappa r| < 2^19; the

@@ -62,8 +62,9 @@ def test_geometry_validation_errors():
 @pytest.mark.parametrize("bad", [dict(p=-1), dict(p=7), dict(m=11), dict(q=0), dict(eta=0.0), dict(eta=-1.0),
                                  dict(gauss_regular=0), dict(gauss_singular=41), dict(kernel=5), dict(mode=3),
                                  dict(kernel=1, wavenumber=-1.0), dict(leaf_depth=-2), dict(far_precision=2),
-                                 dict(far_precision=1, kernel=1, wavenumber=1.0, mode=2),
-                                 dict(far_precision=1, mode=1), dict(far_precision=1, mode=2, q=9)])
+                                 dict(far_precision=1, kernel=1, wavenumber=1.0, mode=2, q=11),
+                                 dict(far_precision=1, mode=1), dict(far_precision=1, mode=2, q=9),
+                                 dict(kernel=1, wavenumber=1e6)])
 def test_parameter_validation_errors(bad):
     g = igb.Geometry(W.sphere_patches())
     with pytest.raises(igb.IgbError) as e:
@@ -127,12 +128,12 @@ def test_plan_matches_oracle_sphere_p3_m5_q8_full_size():
 
 
 @pytest.mark.parametrize("mode,q,kernel,flags", [("stored", 8, 0, 1), ("onthefly", 8, 0, 7), ("onthefly", 10, 0, 1),
-                                                  ("onthefly", 8, 1, 3), ("onthefly", 10, 1, 3),
+                                                  ("onthefly", 8, 1, 7), ("onthefly", 10, 1, 3),
                                                   ("onthefly", 11, 1, 1)])
 def test_layout_flags(mode, q, kernel, flags):
     """Symmetric near storage always at this size; mirrored far pairs only on the fly, with at most 64
-    nodes per cluster for the real kernel and 104 for the complex one; the shared launch only where
-    four waves of near staging fit 64 KB of LDS (not for complex blocks of this size)."""
+    nodes per cluster for the real kernel and 104 for the complex one; the shared launch of far pairs and
+    near blocks for at most 64 nodes per cluster (near blocks of up to 256 functions need no LDS)."""
     g = igb.Geometry(W.sphere_patches())
     m = igb.IGB_H2_STORED if mode == "stored" else igb.IGB_H2_ONTHEFLY
     info = igb.Plan(g, p=1, m=4, q=q, eta=1.6, gauss_regular=4, mode=m, kernel=kernel,

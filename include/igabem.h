@@ -304,6 +304,21 @@ igb_status igb_solve_many(int32_t n, igb_operator *const *ops, const void *const
 igb_status igb_potential(const igb_operator *op, const void *w_dev, int64_t n_pts, const double *xyz_dev,
                          void *u_dev);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): the potential of
+ * igb_potential without any allocation.  The partial sums of the direct sum
+ * live in a fixed 32 MiB device array of the library, one per device, held
+ * until the process ends; n_pts may be at most 4,194,304 (Laplace) or
+ * 2,097,152 (Helmholtz), IGB_EINVAL above.  Every call on one device shares
+ * that array (each call overwrites the part it uses; nothing needs clearing),
+ * so calls that overlap in time on one device race: order them on one stream
+ * or synchronise between them.  Otherwise as igb_potential, but asynchronous
+ * (ordered on the operator's stream, returns before the work completes).  The
+ * first call on a device looks up the array's address (hipGetSymbolAddress);
+ * no call allocates. */
+igb_status igb_potential_noalloc(const igb_operator *op, const void *w_dev, int64_t n_pts, const double *xyz_dev,
+                                 void *u_dev);
+
 /* Timing of the superspace matvec by stage: runs `reps` products on the
  * operator's internal work vectors with HIP events recorded on its stream
  * between stages and writes the mean milliseconds per stage to

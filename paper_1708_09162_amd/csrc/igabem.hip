@@ -2740,6 +2740,7 @@ struct igb_operator {
     // passes and the on-the-fly far field (ALU-bound) on st; forked and joined with the two events
     hipStream_t st2 = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    int dev = 0;  // the device current at igb_operator_create
 };
 
 static igb_status dalloc(igb_operator *op, void **p, size_t bytes)
@@ -4028,6 +4029,10 @@ igb_status igb_operator_create(const igb_geometry *geo, const igb_params *prm, v
     auto t0 = std::chrono::steady_clock::now();
     igb_operator *op = new igb_operator();
     op->st = (hipStream_t)hip_stream;
+    if (hipGetDevice(&op->dev) != hipSuccess) {
+        delete op;
+        return fail(IGB_EHIP, "hipGetDevice failed");
+    }
     std::string err;
     try {
         err = build_setup_tiles(geo->g, *prm, op->s);
@@ -4434,32 +4439,84 @@ igb_status igb_cnn_training_pairs(const igb_operator *cop, const double *x_dev, 
     return IGB_OK;
 }
 
+// Source chunks of the potential's direct sum: enough (x, chunk) workgroups to fill the GPU, at most
+// max_parts partial values (nchunk * npts) when max_parts > 0.
+static int64_t potential_chunks(int64_t npts, int64_t nq, int64_t max_parts)
+{
+    const int64_t tb = (npts + 255) / 256;
+    int64_t nchunk = std::max<int64_t>(1, std::min<int64_t>(4096 / tb + 1, (nq + 4095) / 4096));
+    if (max_parts > 0) nchunk = std::max<int64_t>(1, std::min<int64_t>(nchunk, max_parts / npts));
+    return nchunk;
+}
+
+// S -> S*, weighted density at the quadrature points, then the direct sum into
+// nchunk partial values per point (part, nchunk * npts values) and their sum.
 template <class T>
-static igb_status potential_impl(igb_operator *op, const T *w, int64_t npts, const double *X, T *u)
+static igb_status potential_launch(igb_operator *op, const T *w, int64_t npts, const double *X, T *u, T *part,
+                                   int64_t nchunk)
 {
     const Setup &s = op->s;
     igb_status rc = apply_Tt<T>(op, w, (T *)op->xs);
     if (rc) return rc;
-    int64_t nq = (int64_t)s.nelem * s.grhs * s.grhs;
+    const int64_t nq = (int64_t)s.nelem * s.grhs * s.grhs;
     hipLaunchKernelGGL((k_pot_prep<T>), dim3(nblk(nq, 256)), dim3(256), 0, op->st, op->lo, s.nelem, s.grhs,
                        op->gx + s.goff[s.grhs], op->rpts, (const T *)op->xs, (T *)op->potc);
     LAUNCHCHK();
     if (npts == 0) return IGB_OK;
-    int64_t tb = (npts + 255) / 256;
-    int64_t nchunk = std::max<int64_t>(1, std::min<int64_t>(4096 / tb + 1, (nq + 4095) / 4096));
-    int64_t chunk = (nq + nchunk - 1) / nchunk;
-    DevBlock pb{};
-    HIPCHK(pool_alloc(pb, (size_t)nchunk * npts * sizeof(T)));
-    T *part = (T *)pb.p;
+    const int64_t tb = (npts + 255) / 256, chunk = (nq + nchunk - 1) / nchunk;
     hipLaunchKernelGGL((k_pot_eval<T>), dim3((unsigned)tb, (unsigned)nchunk), dim3(256), 0, op->st, npts, X, nq, op->rpts,
                        (const T *)op->potc, s.kappa, chunk, part);
-    hipError_t e1 = hipGetLastError();
+    LAUNCHCHK();
     hipLaunchKernelGGL((k_pot_reduce<T>), dim3((unsigned)tb), dim3(256), 0, op->st, npts, (int)nchunk, (const T *)part, u);
-    hipError_t e2 = hipGetLastError();
-    hipError_t e3 = hipStreamSynchronize(op->st);
-    if (e3 == hipSuccess) pool_free(pb);
+    LAUNCHCHK();
+    return IGB_OK;
+}
+
+template <class T>
+static igb_status potential_impl(igb_operator *op, const T *w, int64_t npts, const double *X, T *u)
+{
+    const Setup &s = op->s;
+    const int64_t nq = (int64_t)s.nelem * s.grhs * s.grhs;
+    if (npts == 0) return potential_launch<T>(op, w, npts, X, u, nullptr, 1);
+    const int64_t nchunk = potential_chunks(npts, nq, 0);
+    DevBlock pb{};
+    HIPCHK(pool_alloc(pb, (size_t)nchunk * npts * sizeof(T)));
+    const igb_status rc = potential_launch<T>(op, w, npts, X, u, (T *)pb.p, nchunk);
+    const hipError_t e = hipStreamSynchronize(op->st);  // the partial sums go back to the pool afterwards
+    if (e == hipSuccess) pool_free(pb);
     else (void)hipFree(pb.p);
-    if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) return fail(IGB_EHIP, "potential evaluation failed");
+    if (rc) return rc;
+    if (e != hipSuccess) return fail(IGB_EHIP, "potential evaluation failed");
+    return IGB_OK;
+}
+
+// Scratch of igb_potential_noalloc: the partial sums of the potential's direct sum, a file-scope device
+// array of kScratchBytes on every device the library runs on (held until the process ends).  Host code
+// never passes the array's name to a kernel: on the first call on a device, with that device current, its
+// address is taken with hipGetSymbolAddress and kept per device.
+constexpr size_t kScratchBytes = 32u << 20;
+static __device__ __align__(256) double scratch[kScratchBytes / sizeof(double)];
+static std::mutex g_scratch_mu;
+static std::map<int, void *> g_scratch_ptr;
+
+static igb_status scratch_address(int dev, void **ptr)
+{
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    auto it = g_scratch_ptr.find(dev);
+    if (it != g_scratch_ptr.end()) {
+        *ptr = it->second;
+        return IGB_OK;
+    }
+    int cur = -1;
+    HIPCHK(hipGetDevice(&cur));
+    if (cur != dev) HIPCHK(hipSetDevice(dev));
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (cur != dev) (void)hipSetDevice(cur);
+    if (e != hipSuccess || !p)
+        return fail(IGB_EHIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_ptr[dev] = p;
+    *ptr = p;
     return IGB_OK;
 }
 
@@ -4471,6 +4528,29 @@ igb_status igb_potential(const igb_operator *cop, const void *w_dev, int64_t n_p
     igb_operator *op = const_cast<igb_operator *>(cop);
     return op->cplx ? potential_impl<cd>(op, (const cd *)w_dev, n_pts, xyz_dev, (cd *)u_dev)
                     : potential_impl<double>(op, (const double *)w_dev, n_pts, xyz_dev, (double *)u_dev);
+}
+
+igb_status igb_potential_noalloc(const igb_operator *cop, const void *w_dev, int64_t n_pts, const double *xyz_dev,
+                                 void *u_dev)
+{
+    CHECK_OP(cop);
+    if (n_pts < 0) return fail(IGB_EINVAL, "n_pts < 0");
+    if (!w_dev || (n_pts > 0 && (!xyz_dev || !u_dev))) return fail(IGB_EINVAL, "null device pointer");
+    igb_operator *op = const_cast<igb_operator *>(cop);
+    const size_t esz = op->cplx ? sizeof(cd) : sizeof(double);
+    const int64_t cap = (int64_t)(kScratchBytes / esz);
+    if (n_pts > cap)
+        return fail(IGB_EINVAL, "igb_potential_noalloc: n_pts " + std::to_string(n_pts) + " exceeds the scratch capacity of " +
+                                    std::to_string(cap) + " points");
+    void *part = nullptr;
+    igb_status rc = scratch_address(op->dev, &part);
+    if (rc) return rc;
+    const Setup &s = op->s;
+    const int64_t nq = (int64_t)s.nelem * s.grhs * s.grhs;
+    const int64_t nchunk = n_pts ? potential_chunks(n_pts, nq, cap) : 1;
+    return op->cplx ? potential_launch<cd>(op, (const cd *)w_dev, n_pts, xyz_dev, (cd *)u_dev, (cd *)part, nchunk)
+                    : potential_launch<double>(op, (const double *)w_dev, n_pts, xyz_dev, (double *)u_dev,
+                                               (double *)part, nchunk);
 }
 
 igb_status igb_export_partition(const igb_operator *op, int32_t *near_host, int32_t *far_host)

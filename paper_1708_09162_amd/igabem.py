@@ -40,6 +40,7 @@ EXPORTED = [
     "igb_plan_export_pair_classes", "igb_matvec_profile", "igb_release_cached_memory",
     "igb_cnn_create", "igb_cnn_destroy", "igb_cnn_get_weights", "igb_cnn_forward", "igb_cnn_gradient",
     "igb_cnn_training_pairs", "igb_cnn_train", "igb_cnn_train_operator", "igb_solve_fgmres", "igb_solve_many",
+    "igb_potential_noalloc",
 ]
 IGB_CNN_NUM_WEIGHTS = 28224
 IGB_CNN_RELU = 0
@@ -102,6 +103,7 @@ def _load():
         "igb_jacobi_diag": (C.c_int32, [vp, vp]),
         "igb_solve": (C.c_int32, [vp, vp, vp, C.c_double, C.c_int32, C.c_int32, C.POINTER(igb_solve_info)]),
         "igb_potential": (C.c_int32, [vp, vp, C.c_int64, vp, vp]),
+        "igb_potential_noalloc": (C.c_int32, [vp, vp, C.c_int64, vp, vp]),
         "igb_export_partition": (C.c_int32, [vp, ip, ip]),
         "igb_export_pair_classes": (C.c_int32, [vp, ip]),
         "igb_export_near_block": (C.c_int32, [vp, C.c_int32, C.c_int32, dp]),
@@ -316,6 +318,11 @@ def igb_cnn_train_operator(net, op, y32, x32, n_pairs, epochs, batch, lr):
 def igb_potential(op, w, xyz, u):
     n = xyz.shape[0]
     _check(_lib.igb_potential(op, _ptr(w), int(n), _ptr(xyz) if n else None, _ptr(u) if n else None))
+
+
+def igb_potential_noalloc(op, w, xyz, u):
+    n = xyz.shape[0]
+    _check(_lib.igb_potential_noalloc(op, _ptr(w), int(n), _ptr(xyz) if n else None, _ptr(u) if n else None))
 
 
 def igb_export_partition(op, info: igb_info):
@@ -561,6 +568,17 @@ class Operator(_StreamOrdered):
         with self._ordered():
             igb_potential(self.h, w, pts, u)
         return u
+
+    def potential_noalloc(self, w, points, out):
+        """Potential into the preallocated `out` without any device allocation by the library
+        (igb_potential_noalloc; asynchronous on the operator's stream)."""
+        pts = self.torch.as_tensor(points, dtype=self.torch.float64).to(self.device).reshape(-1, 3).contiguous()
+        w = self._in(w, self.info.n_dof)
+        if out.numel() != pts.shape[0] or out.dtype != self.dtype or not out.is_contiguous():
+            raise ValueError("out must be a contiguous vector of n_pts values of the operator's dtype")
+        with self._ordered():
+            igb_potential_noalloc(self.h, w, pts, out)
+        return out
 
     def profile(self, reps=10, separate=False):
         """Mean milliseconds per matvec stage, from HIP events on the operator's stream; with

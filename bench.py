@@ -162,7 +162,7 @@ def hbm_roof(kname, nbytes, ms, traffic):
 # ---------------------------------------------------------------------------
 # headline: Helmholtz torus
 # ---------------------------------------------------------------------------
-def c3_step(torch, igb, geo, cfg, grid_dev, g_fn, far_precision=0, solver="gmres"):
+def c3_step(torch, igb, geo, cfg, grid_dev, g_fn, far_precision=0):
     """The whole path once on the torus; returns (operator, density, solve info, potential, timings)."""
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -172,10 +172,9 @@ def c3_step(torch, igb, geo, cfg, grid_dev, g_fn, far_precision=0, solver="gmres
     b = op.rhs(g_fn(op.rhs_points()))
     torch.cuda.synchronize()
     t2 = time.perf_counter()
-    if solver == "mixed":
-        w, info = op.solve_mixed(b, tol=TOL, max_iter=20000, restart=C3_RESTART)
-    else:
-        w, info = op.solve(b, tol=TOL, max_iter=20000, restart=C3_RESTART)
+    # with far_precision IGB_FP32, igb_solve refines: GMRES on the single-precision operator inside
+    # FP64 residuals
+    w, info = op.solve(b, tol=TOL, max_iter=20000, restart=C3_RESTART)
     torch.cuda.synchronize()
     t3 = time.perf_counter()
     u = op.potential(w, grid_dev)
@@ -580,6 +579,9 @@ def main():
     ap.add_argument("--sphere-steps", type=int, default=10)
     ap.add_argument("--batched", action="store_true",
                     help="also run the 128-instance batched-solve leg (about 90 s)")
+    ap.add_argument("--products-only", choices=["fp64", "fp32", "sphere"], default=None,
+                    help="only assemble one operator (the torus in FP64 or with the single-precision far field, "
+                         "or the Laplace sphere) and time its products: for profiler and counter runs")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -596,6 +598,9 @@ def main():
     from paper_1708_09162_amd import igabem as igb
     from paper_1708_09162_amd import workloads as W
 
+    if args.products_only:
+        products_only(torch, igb, W, args.products_only, args.matvec_reps)
+        return
     cfg = W.config_torus_helmholtz()
     geo = igb.Geometry(cfg["patches"])
     grid_dev = torch.tensor(cfg["eval_points"], dtype=torch.float64, device="cuda:0")
@@ -664,7 +669,7 @@ def main():
     iters_c3 = int(info.iterations)
     del op
     torch.cuda.empty_cache()
-    if not args.no_mixed and hasattr(igb.Operator, "solve_mixed"):
+    if not args.no_mixed:
         out["mixed_fp32_far"] = c3_mixed_leg(torch, igb, geo, cfg, grid_dev, g_fn, ms_per_step, u_grid)
     if not args.no_sphere:
         out["sphere"] = sphere_leg(torch, igb, W, args.sphere_steps, args.matvec_reps)
@@ -679,12 +684,32 @@ def main():
     print(json.dumps(out), flush=True)
 
 
+def products_only(torch, igb, W, which, reps):
+    """One operator and its products only (igb_matvec, then the stages launched separately): the command
+    the profiler and counter summaries are taken with.  Prints one JSON line of timings."""
+    if which == "sphere":
+        cfg = W.config_sphere_h2()
+        op = igb.Operator(igb.Geometry(cfg["patches"]), device="cuda:0", mode=igb.IGB_H2_ONTHEFLY, **C2)
+        name = SPHERE
+    else:
+        cfg = W.config_torus_helmholtz()
+        fp = igb.IGB_FP32 if which == "fp32" else igb.IGB_FP64
+        op = igb.Operator(igb.Geometry(cfg["patches"]), device="cuda:0", mode=igb.IGB_H2_ONTHEFLY,
+                          far_precision=fp, **C3)
+        name = HEADLINE
+    torch.cuda.synchronize()
+    mv = matvec_ms(torch, op, reps)
+    sep = op.profile(reps=reps, separate=True)
+    print(json.dumps({"workload": name, "products": which, "h2_matvec_ms": round(mv, 4),
+                      "stage_ms_separate": {k: round(v, 4) for k, v in sep.items()}}), flush=True)
+
+
 def c3_mixed_leg(torch, igb, geo, cfg, grid_dev, g_fn, fp64_ms, u_fp64, steps: int = 2):
     """The torus step with the single-precision complex far field as the inner operator of a refinement whose
-    residuals use the FP64 operator (igb_solve_mixed), beside the FP64 headline step."""
-    c3_step(torch, igb, geo, cfg, grid_dev, g_fn, igb.IGB_FP32, "mixed")  # warmup
+    residuals use the FP64 operator (igb_solve with far_precision IGB_FP32), beside the FP64 headline step."""
+    c3_step(torch, igb, geo, cfg, grid_dev, g_fn, igb.IGB_FP32)  # warmup
     ms, (op, w, info, u, t) = timed_steps(
-        torch, lambda: c3_step(torch, igb, geo, cfg, grid_dev, g_fn, igb.IGB_FP32, "mixed"), steps)
+        torch, lambda: c3_step(torch, igb, geo, cfg, grid_dev, g_fn, igb.IGB_FP32), steps)
     un = u.cpu().numpy()
     log(f"mixed precision (torus): {ms / 1e3:.3f} s per step, {info.iterations} it")
     return {"far_precision": "fp32 complex far field inside FP64 iterative refinement",

@@ -42,6 +42,10 @@ __all__ = [
     "config_torus_helmholtz",
     "interior_ball_points",
     "point_charges",
+    "fichera_patches",
+    "fichera_interior_points",
+    "perturbation_map",
+    "perturbed_mapping_patches",
 ]
 
 
@@ -247,6 +251,114 @@ def cube_patches(edge: float = 2.0) -> list[dict]:
         R = _FACE_ROTATIONS[key]
         corners = [np.array(c) for c in ((-h, -h, h), (h, -h, h), (-h, h, h), (h, h, h))]
         out.append(flat_patch(*[R @ c for c in corners]))
+    return out
+
+
+def fichera_patches() -> list[dict]:
+    """The Fichera cube of Section 5: the cube [-1,1]^3 (edge length 2) with the corner octant (0,1]^3
+    removed, as 24 bilinear unit squares (outward normals): the four quarters of each cube face, less the
+    three that bound the removed octant, plus the three walls of the indentation (planes x, y, z = 0)."""
+    squares = []
+    for axis in range(3):
+        for side in (-1.0, 1.0):
+            for a0 in (-1.0, 0.0):
+                for b0 in (-1.0, 0.0):
+                    if side == 1.0 and a0 == 0.0 and b0 == 0.0:
+                        continue  # this quarter bounds the removed octant
+                    squares.append((axis, side, a0, b0, side))
+    for axis in range(3):
+        squares.append((axis, 0.0, 0.0, 0.0, 1.0))  # indentation wall, outward normal +e_axis
+    out = []
+    for axis, c, a0, b0, sgn in squares:
+        i, j = (axis + 1) % 3, (axis + 2) % 3  # e_i x e_j = e_axis
+
+        def pt(u, v, axis=axis, c=c, a0=a0, b0=b0, i=i, j=j):
+            p = np.zeros(3)
+            p[axis], p[i], p[j] = c, a0 + u, b0 + v
+            return p
+
+        if sgn > 0:
+            out.append(flat_patch(pt(0, 0), pt(1, 0), pt(0, 1), pt(1, 1)))
+        else:  # parameters exchanged: the normal flips to -e_axis
+            out.append(flat_patch(pt(0, 0), pt(0, 1), pt(1, 0), pt(1, 1)))
+    return out
+
+
+def fichera_interior_points(n: int, seed: int, margin: float = 0.15) -> np.ndarray:
+    """n seeded points inside the Fichera cube at least `margin` from its surface (Section 5.1 keeps
+    evaluation points 0.15 away from the boundary)."""
+    rng = np.random.default_rng(seed)
+    pts = []
+    while len(pts) < n:
+        p = rng.uniform(-1.0 + margin, 1.0 - margin, 3)
+        if np.all(p > -margin):  # inside, or too close to, the removed octant
+            continue
+        pts.append(p)
+    return np.array(pts)
+
+
+def perturbation_map(x):
+    """Piecewise linear, monotone map of [0,1] onto itself with kinks at 1/4 and 3/4 (slopes 1/2, 3/2,
+    1/2): continuous with a discontinuous derivative, so it lies in H^1 but not in H^2, like the map of
+    Section 5.2 (whose kinks at 0.3 and 0.7 are moved to the dyadic points 1/4 and 3/4 here, element
+    boundaries of every mesh with m >= 2)."""
+    x = np.asarray(x, dtype=np.float64)
+    return np.where(x <= 0.25, 0.5 * x, np.where(x < 0.75, 1.5 * x - 0.25, 0.5 * (x + 1.0)))
+
+
+def _subdivide_bezier_1d(P: np.ndarray, t: float):
+    """de Casteljau split of a Bezier curve (control points along axis 0, homogeneous) at t."""
+    P = P.copy()
+    n = P.shape[0] - 1
+    left, right = [P[0].copy()], [P[n].copy()]
+    for r in range(1, n + 1):
+        P = (1 - t) * P[:-1] + t * P[1:]
+        left.append(P[0].copy())
+        right.append(P[-1].copy())
+    return np.array(left), np.array(right[::-1])
+
+
+def _reparametrise_bezier_1d(P: np.ndarray, a: float, b: float) -> np.ndarray:
+    """Control points of the Bezier curve restricted to [a, b] (homogeneous points along axis 0)."""
+    _, R = _subdivide_bezier_1d(P, a)
+    if a < 1.0:
+        L, _ = _subdivide_bezier_1d(R, (b - a) / (1.0 - a))
+    else:
+        L = R
+    return L
+
+
+def perturbed_mapping_patches(patches: list[dict]) -> list[dict]:
+    """Each single-piece rational Bezier patch F composed with the perturbation map in both parameters,
+    F(f(u), f(v)) (Section 5.2): the same surface, parametrised with kinks at u, v = 1/4 and 3/4.  The
+    result is a NURBS patch of the same degrees with knots of full multiplicity at 1/4 and 3/4 (one
+    Bezier piece per linear piece of f, obtained by de Casteljau subdivision)."""
+    breaks = [0.0, 0.25, 0.75, 1.0]
+    out = []
+    for p in patches:
+        du, dv = p["deg_u"], p["deg_v"]
+        cpw = np.asarray(p["cpw"], dtype=np.float64)
+        if cpw.shape[1] != du + 1 or cpw.shape[0] != dv + 1:
+            raise ValueError("perturbed_mapping_patches expects single Bezier patches")
+        H = cpw.copy()
+        H[..., :3] *= H[..., 3:4]  # homogeneous (x w, y w, z w, w)
+
+        def pieces_1d(Q, deg):
+            segs = []
+            for k in range(3):
+                a, b = perturbation_map(breaks[k]), perturbation_map(breaks[k + 1])
+                seg = _reparametrise_bezier_1d(Q, float(a), float(b))
+                segs.append(seg if k == 0 else seg[1:])
+            return np.concatenate(segs, axis=0)
+
+        # along u (axis 1), then along v (axis 0)
+        Hu = np.stack([pieces_1d(H[j], du) for j in range(H.shape[0])], axis=0)
+        Hv = np.stack([pieces_1d(Hu[:, i], dv) for i in range(Hu.shape[1])], axis=1)
+        C = Hv.copy()
+        C[..., :3] /= C[..., 3:4]
+        ku = np.array([0.0] * (du + 1) + [0.25] * du + [0.75] * du + [1.0] * (du + 1))
+        kv = np.array([0.0] * (dv + 1) + [0.25] * dv + [0.75] * dv + [1.0] * (dv + 1))
+        out.append(_patch(du, dv, ku, kv, C))
     return out
 
 

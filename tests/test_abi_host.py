@@ -170,3 +170,14 @@ def test_bench_refuses_more_than_one_gpu():
                        text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU" in r.stderr and r.stdout == ""
+
+
+def test_plan_matches_oracle_fichera_and_perturbed_sphere():
+    """The partition and pair classes on the Fichera cube (re-entrant edges and corner; touching pairs
+    across perpendicular faces) and on the perturbed sphere (knots at 1/4 and 3/4) equal the oracle's."""
+    info = _compare_plan(W.fichera_patches(), p=1, m=3, q=4, leaf_depth=1, eta=1.6, gauss_regular=6)
+    assert info.n_far_blocks > 0 and info.n_pairs[1] == 24 * 64
+    assert info.n_pairs[2] > 0 and info.n_pairs[3] > 0
+    info = _compare_plan(W.perturbed_mapping_patches(W.sphere_patches()), p=2, m=3, q=4, leaf_depth=1, eta=1.6,
+                         gauss_regular=6)
+    assert info.n_far_blocks > 0

@@ -331,8 +331,11 @@ igb_status igb_potential_noalloc(const igb_operator *op, const void *w_dev, int6
  * (transfers and leaf back-moments) (Sec. 4.2).  With flags = 0 the products
  * are launched as in igb_matvec: when igb_info.layout_flags bit 2 is set, the
  * near-field products and gathers share the far-field launches (stages 1 and
- * 2) and stages 3 and 4 are empty.  With IGB_PROFILE_SEPARATE they run as
- * separate launches, one kernel per stage.  Synchronous. */
+ * 2) and stages 3 and 4 are empty; when the near-field GEMV runs on the
+ * operator's side stream, concurrent with stages 0-2 (symmetric near storage
+ * without the shared launch), stage 3 is its duration there.  With
+ * IGB_PROFILE_SEPARATE they run as separate launches, one kernel per stage,
+ * on the operator's stream.  Synchronous. */
 #define IGB_NUM_MATVEC_STAGES 6
 #define IGB_PROFILE_SEPARATE 1
 igb_status igb_matvec_profile(const igb_operator *op, int32_t reps, int32_t flags, double *stage_ms_host);

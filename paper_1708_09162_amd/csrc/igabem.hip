@@ -1021,6 +1021,25 @@ __global__ void __launch_bounds__(256) k_bsr_gemv(int nb, const int64_t *__restr
 // partial rows part[2k] = B x_s (for leaf t) and, when t != s,
 // part[2k+1] = B^T x_t (for leaf s); k_gather sums them per leaf.
 typedef double v2d __attribute__((ext_vector_type(2)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+// Complex near-field blocks rounded to single precision, (re, im) float pairs: the
+// near field of the inner operator of the single-precision Helmholtz solve.
+struct cf {
+    float re, im;
+};
+
+// 8 consecutive single-precision complex entries (64 bytes), widened to double
+__device__ inline void load8(const cf *p, cd v[8])
+{
+    const v4f *q = (const v4f *)p;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const v4f w = q[r];
+        v[2 * r] = cd{(double)w.x, (double)w.y};
+        v[2 * r + 1] = cd{(double)w.z, (double)w.w};
+    }
+}
 
 template <class T>
 __device__ inline void load8(const T *p, T v[8])
@@ -1145,15 +1164,15 @@ __device__ inline void near_sym_wave(const NearSymArgs &N, int64_t k, const T *_
 // column sums (B^T x_t, the mirrored block's product) over the 8 adjacent lanes
 // li after every column step (DPP) and kept by the lane li == kc % 8 in slot
 // kc / 8.  Writes the same partial rows as near_sym_wave.
-template <class T, int S>
-__device__ inline void near_sym_wave_reg(const NearSymArgs &N, int64_t k, const T *__restrict__ blocks,
+template <class T, int S, class BT = T>
+__device__ inline void near_sym_wave_reg(const NearSymArgs &N, int64_t k, const BT *__restrict__ blocks,
                                          const T *__restrict__ x, T *__restrict__ part)
 {
     const int nl = N.nl, ld = N.ld;
     const int lane = threadIdx.x & 63;
     const int li = lane & 7, lj = lane >> 3;
     const int64_t t = N.sb_t[k], sc = N.sb_s[k];
-    const T *B = blocks + k * (int64_t)nl * ld;
+    const BT *B = blocks + k * (int64_t)nl * ld;
     const T *xt = x + t * nl, *xsrc = x + sc * nl;
     T *prow = part + (size_t)(2 * k) * ld;
     T own[S];
@@ -1230,6 +1249,26 @@ __global__ void __launch_bounds__(256) k_near_sym(NearSymArgs N, const T *__rest
     const int64_t k = (int64_t)blockIdx.x * (blockDim.x >> 6) + wave;
     if (k >= N.nsb) return;  // whole waves only; no block-wide barrier follows
     near_sym_block<T>(N, k, blocks, x, part, (T *)sh + (size_t)wave * near_sym_lds(N.nl, N.ld));
+}
+
+// The same with single-precision complex blocks (nl <= 256, products and sums in FP64)
+__global__ void __launch_bounds__(256) k_near_sym32(NearSymArgs N, const cf *__restrict__ blocks,
+                                                    const cd *__restrict__ x, cd *__restrict__ part)
+{
+    const int wave = threadIdx.x >> 6;
+    const int64_t k = (int64_t)blockIdx.x * (blockDim.x >> 6) + wave;
+    if (k >= N.nsb) return;
+    if (N.nl <= 64) near_sym_wave_reg<cd, 1, cf>(N, k, blocks, x, part);
+    else if (N.nl <= 128) near_sym_wave_reg<cd, 2, cf>(N, k, blocks, x, part);
+    else if (N.nl <= 192) near_sym_wave_reg<cd, 3, cf>(N, k, blocks, x, part);
+    else near_sym_wave_reg<cd, 4, cf>(N, k, blocks, x, part);
+}
+
+// blocks rounded to single precision, n complex values
+__global__ void k_round_c32(int64_t n, const cd *__restrict__ in, cf *__restrict__ out)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        out[i] = cf{(float)in[i].re, (float)in[i].im};
 }
 
 
@@ -2740,6 +2779,9 @@ struct igb_operator {
     // passes and the on-the-fly far field (ALU-bound) on st; forked and joined with the two events
     hipStream_t st2 = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    // single-precision Helmholtz far field: the stored near blocks rounded to FP32 as well, for the
+    // products of the inner solves (the FP64 residual products use nearb)
+    void *nearb32 = nullptr;
     int dev = 0;  // the device current at igb_operator_create
 };
 
@@ -3000,15 +3042,25 @@ static std::vector<TreeLaunch> tree_slices(const igb_operator *op, size_t esz)
 template <class T>
 static void launch_near_sym(igb_operator *op, const T *xs, hipStream_t st)
 {
+    if constexpr (NComp<T>::value == 2) {
+        if (op->nearb32 && op->far_single && !op->force_fp64) {
+            hipLaunchKernelGGL(k_near_sym32, dim3((unsigned)((op->nsb + 3) / 4)), dim3(256), 0, st, near_args(op),
+                               (const cf *)op->nearb32, (const cd *)xs, (cd *)op->npart);
+            return;
+        }
+    }
     const size_t wave_lds = (size_t)near_sym_lds(op->s.nl, op->near_ld) * sizeof(T);
     const int wpb = wave_lds ? (int)std::max<size_t>(1, std::min<size_t>(4, (64 * 1024) / wave_lds)) : 4;
     hipLaunchKernelGGL((k_near_sym<T>), dim3((unsigned)((op->nsb + wpb - 1) / wpb)), dim3(64 * wpb), wpb * wave_lds,
                        st, near_args(op), (const T *)op->nearb, xs, (T *)op->npart);
 }
 
+// ev (optional): IGB_NUM_MATVEC_STAGES + 1 events recorded on st between the stages; evn (optional): two
+// events recorded on the side stream around the forked near-field GEMV, forked (optional) tells whether
+// the GEMV was forked.
 template <class T>
 static igb_status matvec_internal(igb_operator *op, const T *xs, T *ys, hipEvent_t *ev = nullptr,
-                                  bool separate = false)
+                                  bool separate = false, hipEvent_t *evn = nullptr, bool *forked = nullptr)
 {
     const Setup &s = op->s;
     int q = s.q, q2 = q * q;
@@ -3036,7 +3088,8 @@ static igb_status matvec_internal(igb_operator *op, const T *xs, T *ys, hipEvent
     const bool fuse = sym && !separate && fused_products(op->near_sym, s.nl, op->near_ld, sizeof(T), q2);
     // near blocks not fused into the far-field launch: their GEMV reads only xs, so it runs on the side
     // stream from the start of the product and is joined before its gather
-    const bool fork = has_far && op->near_sym && !fuse && !separate && !ev;
+    const bool fork = has_far && op->near_sym && !fuse && !separate;
+    if (forked) *forked = fork;
     if (fork) {
         if (!op->st2) {
             HIPCHK(hipStreamCreateWithFlags(&op->st2, hipStreamNonBlocking));
@@ -3045,7 +3098,9 @@ static igb_status matvec_internal(igb_operator *op, const T *xs, T *ys, hipEvent
         }
         HIPCHK(hipEventRecord(op->ev_fork, op->st));
         HIPCHK(hipStreamWaitEvent(op->st2, op->ev_fork, 0));
+        if (evn) HIPCHK(hipEventRecord(evn[0], op->st2));
         launch_near_sym<T>(op, xs, op->st2);
+        if (evn) HIPCHK(hipEventRecord(evn[1], op->st2));
         HIPCHK(hipEventRecord(op->ev_join, op->st2));
     }
     if (has_far) {
@@ -4079,6 +4134,16 @@ igb_status igb_operator_create(const igb_geometry *geo, const igb_params *prm, v
         for (size_t k = 0; k < s.far.size(); k += 3) op->lmin = std::min(op->lmin, (int)s.far[k]);
         rc = create_device_plan(op);
     }
+    if (rc == IGB_OK && op->far_single && op->cplx && op->near_sym && s.nl <= 256 && op->near_bytes > 0) {
+        // the near blocks of the inner single-precision products, rounded once the assembly has written them
+        const int64_t nval = op->near_bytes / (int64_t)sizeof(cd);
+        rc = dalloc(op, &op->nearb32, (size_t)nval * sizeof(cf));
+        if (rc == IGB_OK) {
+            hipLaunchKernelGGL(k_round_c32, dim3((unsigned)std::min<int64_t>(nblk(nval, 256), 65536)), dim3(256), 0,
+                               op->st, nval, (const cd *)op->nearb, (cf *)op->nearb32);
+            if (hipGetLastError() != hipSuccess) rc = fail(IGB_EHIP, "k_round_c32 launch");
+        }
+    }
     if (rc == IGB_OK) {
         hipError_t e = hipStreamSynchronize(op->st);
         if (e != hipSuccess) rc = fail(IGB_EHIP, std::string("assembly: ") + hipGetErrorString(e));
@@ -4745,21 +4810,33 @@ template <class T>
 static igb_status profile_impl(igb_operator *op, int reps, bool separate, double *ms)
 {
     constexpr int NS = IGB_NUM_MATVEC_STAGES;
-    hipEvent_t ev[NS + 1];
+    hipEvent_t ev[NS + 1], evn[2];
     for (int k = 0; k <= NS; ++k) HIPCHK(hipEventCreate(&ev[k]));
+    HIPCHK(hipEventCreate(&evn[0]));
+    HIPCHK(hipEventCreate(&evn[1]));
     for (int k = 0; k < NS; ++k) ms[k] = 0.0;
     igb_status rc = IGB_OK;
     for (int r = 0; r < reps && rc == IGB_OK; ++r) {
-        rc = matvec_internal<T>(op, (const T *)op->xs, (T *)op->ys, ev, separate);
+        bool forked = false;
+        rc = matvec_internal<T>(op, (const T *)op->xs, (T *)op->ys, ev, separate, evn, &forked);
         if (rc) break;
         if (hipEventSynchronize(ev[NS]) != hipSuccess) { rc = fail(IGB_EHIP, "event synchronize"); break; }
+        float tn = 0.f;
+        if (forked && hipEventElapsedTime(&tn, evn[0], evn[1]) != hipSuccess) {
+            rc = fail(IGB_EHIP, "event elapsed");
+            break;
+        }
         for (int k = 0; k < NS; ++k) {
             float t = 0.f;
             if (hipEventElapsedTime(&t, ev[k], ev[k + 1]) != hipSuccess) { rc = fail(IGB_EHIP, "event elapsed"); break; }
-            ms[k] += t;
+            // forked: stage 3 is the near GEMV on the side stream (concurrent with stages 0-2); the wait
+            // for it on the main stream is not a stage
+            ms[k] += (forked && k == 3) ? tn : t;
         }
     }
     for (int k = 0; k <= NS; ++k) (void)hipEventDestroy(ev[k]);
+    (void)hipEventDestroy(evn[0]);
+    (void)hipEventDestroy(evn[1]);
     if (rc) return rc;
     for (int k = 0; k < IGB_NUM_MATVEC_STAGES; ++k) ms[k] /= reps;
     return IGB_OK;

@@ -96,3 +96,78 @@ def test_perturbed_sphere_parity():
     P.h2_assemble(store_coupling=True)
     xs = np.random.default_rng(32).standard_normal(P.nsup)
     assert rel(to_np(op.matvec_super(torch.tensor(xs, device=DEV))), P.h2_matvec_super(xs)) < 1e-12
+
+
+def _point_charge_potential_errors(patches, p, ms, mode, q=2, **kw):
+    x0 = 2 * W.random_directions(1, 1)[0]
+    ev = W.interior_ball_points(30, 1, radius=0.5)
+    exact = 1 / np.linalg.norm(ev - x0, axis=1)
+    errs = []
+    for m in ms:
+        op = igb.Operator(igb.Geometry(patches), mode=mode, p=p, m=m, q=q, gauss_regular=10, gauss_rhs=14, device=DEV,
+                          **kw)
+        pts = op.rhs_points()
+        b = op.rhs(1 / torch.linalg.norm(pts - torch.tensor(x0, device=DEV), dim=1))
+        w, info = op.solve(b, tol=1e-13, max_iter=8000)
+        errs.append(float(np.abs(to_np(op.potential(w, ev)) - exact).max()))
+        del op
+    return errs
+
+
+def test_perturbed_mapping_spoils_the_rate():
+    """Sec. 5.2: the same sphere, parametrised through a map with kinks (here at 1/4 and 3/4, element
+    boundaries), every pair by quadrature (dense): the point-charge potential error keeps the rate h^(2p+3)
+    of Cor. cor::pwconv for p=1, whose continuous piecewise linears follow the kink of the pulled-back
+    density, but loses it for p=2 (C^1 splines cannot), while the smooth parametrisation keeps h^7."""
+    say("perturbed mapping: dense rates, p=1 and p=2, m=2..4")
+    S, Pt = W.sphere_patches(), W.perturbed_mapping_patches(W.sphere_patches())
+    rate = lambda e: math.log2(e[-2] / e[-1])
+    e_s2 = _point_charge_potential_errors(S, 2, (2, 3, 4), igb.IGB_DENSE)
+    e_p2 = _point_charge_potential_errors(Pt, 2, (2, 3, 4), igb.IGB_DENSE)
+    e_s1 = _point_charge_potential_errors(S, 1, (3, 4), igb.IGB_DENSE)
+    e_p1 = _point_charge_potential_errors(Pt, 1, (3, 4), igb.IGB_DENSE)
+    say(f"  p=2 smooth {e_s2} perturbed {e_p2}; p=1 smooth {e_s1} perturbed {e_p1}")
+    assert rate(e_s2) > 6.5 and e_s2[-1] < 1e-10
+    assert rate(e_p2) < rate(e_s2) - 2.0 and e_p2[-1] > 1e3 * e_s2[-1]
+    assert rate(e_s1) > 4.5 and rate(e_p1) > 4.5
+
+
+def test_fichera_potential_converges():
+    """Interior Laplace on the Fichera cube (Sec. 5.1), p=1, H2 with q=6: the potential error of two exterior
+    charges (one in the indentation) at interior points 0.15 from the surface falls with every refinement."""
+    say("fichera p=1 m=1..4 q=6: potential error")
+    F = W.fichera_patches()
+    ev = W.fichera_interior_points(40, 2)
+    exact = W.laplace_charge_field(ev, *FICHERA_CHARGES)
+    errs = []
+    for m in (1, 2, 3, 4):
+        op = igb.Operator(igb.Geometry(F), mode=igb.IGB_H2_ONTHEFLY, p=1, m=m, q=6, eta=1.6, gauss_regular=8,
+                          gauss_rhs=14, device=DEV)
+        pts = to_np(op.rhs_points())
+        b = op.rhs(torch.tensor(W.laplace_charge_field(pts, *FICHERA_CHARGES), device=DEV))
+        w, info = op.solve(b, tol=1e-12, max_iter=5000)
+        errs.append(float(np.abs(to_np(op.potential(w, ev)) - exact).max()))
+    say(f"  errors {errs}")
+    assert all(errs[i + 1] < errs[i] / 3 for i in range(3)) and errs[-1] < 3e-7
+
+
+def test_wavenumber_sweep_sphere():
+    """Sec. 5.3: exterior Helmholtz point source inside the unit sphere (p=2, 8x8 elements per patch, q=8,
+    far field on the fly), wavenumbers 0.5 .. 8 kept away from the interior resonances (zeros of j_l): the
+    potential on a radius-6 sphere matches the source within the compression accuracy, which falls off as
+    kappa times the cluster size grows under the wavenumber-blind admissibility of Sec. 4.2."""
+    v = np.array([0.1, -0.2, 0.15])
+    far = 6.0 * W.random_directions(16, 11)
+    errs = {}
+    for k in (0.5, 1.0, 2.0, 4.0, 8.0):
+        assert not W._near_sphere_resonance(k)
+        op = igb.Operator(igb.Geometry(W.sphere_patches()), mode=igb.IGB_H2_ONTHEFLY, kernel=igb.IGB_HELMHOLTZ,
+                          wavenumber=k, p=2, m=3, q=8, eta=1.6, gauss_regular=8, gauss_rhs=14, device=DEV)
+        pts = to_np(op.rhs_points())
+        b = op.rhs(torch.tensor(W.helmholtz_point_source(pts, v, k), device=DEV))
+        w, info = op.solve(b, tol=1e-12, max_iter=5000, restart=300)
+        assert info.converged == 1
+        exact = W.helmholtz_point_source(far, v, k)
+        errs[k] = float(np.abs(to_np(op.potential(w, far)) - exact).max() / np.abs(exact).max())
+    say(f"  relative potential errors {errs}")
+    assert all(errs[k] < 2e-5 for k in (0.5, 1.0, 2.0, 4.0)) and errs[8.0] < 5e-3

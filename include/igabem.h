@@ -58,9 +58,12 @@ typedef int32_t igb_status;
  * below 6e-8); distances, moments, transfers, sums and the near field stay
  * FP64.  Helmholtz: the kernel values exp(i k r)/r (hardware reciprocal square
  * root, sine and cosine of the phase in turns) and the sums inside each pair
- * of clusters are FP32 (about 1e-6 relative); moments, transfers, the sums
- * across pairs and the near field stay FP64.  igb_matvec / igb_matvec_super
- * apply this operator; igb_solve still solves the FP64 system.  Laplace: CG
+ * of clusters are FP32 (about 1e-6 relative), and the near-field blocks
+ * (integrated in FP64) are also kept rounded to FP32 for this operator's
+ * products (leaves of up to 256 functions; half the bytes); moments,
+ * transfers, the sums across pairs and the near-field sums stay FP64.
+ * igb_matvec / igb_matvec_super apply this operator; igb_solve still solves
+ * the FP64 system.  Laplace: CG
  * steps with this operator, the recursive residual replaced by the FP64
  * residual b - A w (full-precision far field) every 20 steps.  Helmholtz:
  * iterative refinement, each cycle a GMRES(restart) solve of A~ d = r with this

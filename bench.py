@@ -53,6 +53,7 @@ KERNEL_SRC = [os.path.join(ROOT, "paper_1708_09162_amd", "csrc", f) for f in ("i
 HEADLINE = "helmholtz_torus_p2_m6_q10_k8"
 C3 = dict(kernel=1, wavenumber=8.0, p=2, m=6, q=10, eta=1.6, gauss_regular=6)
 C3_RESTART = 600
+C3_KAPPA_DIAM = 12.0  # the wavenumber-aware admissibility option of the accuracy-matched leg
 SPHERE = "laplace_sphere_p3_m5_q8"
 C2 = dict(p=3, m=5, q=8, eta=1.6, gauss_regular=6)
 C2_RESTART = 100
@@ -162,11 +163,12 @@ def hbm_roof(kname, nbytes, ms, traffic):
 # ---------------------------------------------------------------------------
 # headline: Helmholtz torus
 # ---------------------------------------------------------------------------
-def c3_step(torch, igb, geo, cfg, grid_dev, g_fn, far_precision=0):
+def c3_step(torch, igb, geo, cfg, grid_dev, g_fn, far_precision=0, kappa_diam=0.0):
     """The whole path once on the torus; returns (operator, density, solve info, potential, timings)."""
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    op = igb.Operator(geo, device="cuda:0", mode=igb.IGB_H2_ONTHEFLY, far_precision=far_precision, **C3)
+    op = igb.Operator(geo, device="cuda:0", mode=igb.IGB_H2_ONTHEFLY, far_precision=far_precision,
+                      kappa_diam=kappa_diam, **C3)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     b = op.rhs(g_fn(op.rhs_points()))
@@ -214,8 +216,12 @@ def c3_details(torch, igb, W, geo, cfg, op, grid_dev, reps):
              "near_gemv_alone": hbm_roof("k_near_sym<cd>", nb, sep["near_gemv"], read_traffic("near_gemv", HEADLINE))}
     for k, r in roofs.items():
         r["launched_alone"] = k.endswith("_alone")
-    # point-source twin (Sec. 5.3): exp(i k |x - v|)/|x - v| with v = (0, -2, 0) inside the tube is its own
-    # exterior solution, so the potential error against it measures the whole discretisation
+    return mv, stages, sep, roofs, point_source_twin(torch, W, cfg, op, grid_dev)
+
+
+def point_source_twin(torch, W, cfg, op, grid_dev):
+    """Point-source twin (Sec. 5.3): exp(i k |x - v|)/|x - v| with v = (0, -2, 0) inside the tube is its own
+    exterior solution, so the potential error against it measures the whole discretisation."""
     v = np.array([0.0, -2.0, 0.0])
     k = cfg["wavenumber"]
     vt = torch.tensor(v, device="cuda:0")
@@ -231,7 +237,7 @@ def c3_details(torch, igb, W, geo, cfg, op, grid_dev, reps):
             "rel_residual": float(info.rel_residual),
             "potential_max_abs_err": float(np.abs(u - ex).max()),
             "potential_max_rel_err": float(np.abs(u - ex).max() / np.abs(ex).max())}
-    return mv, stages, sep, roofs, twin
+    return twin
 
 
 def lambda_ps(torch, vt, k):
@@ -357,10 +363,11 @@ def sphere_mixed_leg(torch, igb, geo, cfg, ev_dev, fp64_ms, exact, steps: int = 
 def learned_leg(torch, igb, epochs: int = 4, seeds=(5, 6, 7, 8)):
     """The learned preconditioner on its own workload: Laplace on the perturbed sphere (p=2, 128x128 elements
     per patch, q=8), 2000 seeded training vectors, the linear network trained on the GPU (loss on x) from four
-    seeded initial weights, each then used in flexible GMRES to 1e-8 (at most 300 steps), beside the plain FP64
-    solve (Jacobi CG) and Jacobi FGMRES, all from w = 0.  Every seed is reported: the network's effect depends
-    on its initial weights.  "selected": the seed with the fewest steps on a validation right-hand side (other
-    point charges), or Jacobi when none beats it there, then timed on the real right-hand side."""
+    seeded initial weights, each then used in flexible GMRES to 1e-8, beside the plain FP64 solve (Jacobi CG)
+    and Jacobi FGMRES, all from w = 0.  Every seed is reported, with whether the library dropped its network
+    for Jacobi after a stalled restart cycle.  "selected": the library's choice (igb_solve_fgmres_select) of the
+    seed with the fewest steps on a validation right-hand side (other point charges), or Jacobi when none beats
+    it there, then timed alone on the real right-hand side."""
     from paper_1708_09162_amd import workloads as W
 
     c5 = W.config_learned_preconditioner()
@@ -396,8 +403,7 @@ def learned_leg(torch, igb, epochs: int = 4, seeds=(5, 6, 7, 8)):
     del x
     # validation right-hand side: other point charges (seed 3), used only to choose among the seeds
     b_val = op.rhs(charge_field(torch, op.rhs_points(), *W.point_charges(4, 3)))
-    _, iv_j, _ = timed_solve(lambda: op.solve_fgmres(b_val, None, tol=TOL, max_iter=300, restart=100))
-    runs, nets = [], {}
+    runs, nets = [], []
     for seed in seeds:
         net = igb.CNN(W.cnn_initial_weights(seed), igb.IGB_CNN_LINEAR, device="cuda:0")
         torch.cuda.synchronize()
@@ -405,23 +411,26 @@ def learned_leg(torch, igb, epochs: int = 4, seeds=(5, 6, 7, 8)):
         losses = net.train(y32, x32, npatch, side, side, epochs=epochs, batch=16, lr=1e-3)
         torch.cuda.synchronize()
         t_train = time.perf_counter() - t
-        _, i_v, _ = timed_solve(lambda: op.solve_fgmres(b_val, net, tol=TOL, max_iter=300, restart=100))
-        w, i_n, t_n = timed_solve(lambda: op.solve_fgmres(b, net, tol=TOL, max_iter=300, restart=100))
+        w, i_n, t_n = timed_solve(lambda: op.solve_fgmres(b, net, tol=TOL, max_iter=5000, restart=100))
         r = b - op.matvec(w)
         runs.append({"init_seed": seed, "train_s": round(t_train, 3),
                      "loss_per_epoch": [round(float(v), 5) for v in losses],
-                     "validation_iterations": int(i_v.iterations) if i_v.converged else None,
-                     "iterations": int(i_n.iterations), "converged": int(i_n.converged), "solve_s": round(t_n, 4),
+                     "iterations": int(i_n.iterations), "converged": int(i_n.converged),
+                     "fell_back_to_jacobi": int(i_n.fallback), "solve_s": round(t_n, 4),
                      "true_rel_residual": float(torch.linalg.norm(r) / torch.linalg.norm(b))})
-        nets[seed] = net
+        nets.append(net)
     conv = [rr for rr in runs if rr["converged"]]
-    cand = [rr for rr in runs if rr["validation_iterations"] is not None
-            and rr["validation_iterations"] < iv_j.iterations]
-    chosen = min(cand, key=lambda rr: rr["validation_iterations"]) if cand else None
-    sel_net = nets[chosen["init_seed"]] if chosen else None
-    w, i_s, t_s = timed_solve(lambda: op.solve_fgmres(b, sel_net, tol=TOL, max_iter=5000, restart=100))
-    res["selected"] = {"preconditioner": f"network seed {chosen['init_seed']}" if chosen else "jacobi",
-                       "validation_iterations_jacobi": int(iv_j.iterations),
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    w, kept, i_s = op.solve_fgmres_select(nets, b_val, b, tol=TOL, max_iter=5000, restart=100)
+    torch.cuda.synchronize()
+    t_sel = time.perf_counter() - t
+    sel_net = nets[kept] if kept >= 0 else None
+    _, i_k, t_s = timed_solve(lambda: op.solve_fgmres(b, sel_net, tol=TOL, max_iter=5000, restart=100))
+    res["selected"] = {"preconditioner": f"network seed {seeds[kept]}" if kept >= 0 else "jacobi",
+                       "selection": "igb_solve_fgmres_select: fewest flexible-GMRES steps on the validation "
+                                    "right-hand side without falling back, else Jacobi",
+                       "select_and_solve_s": round(t_sel, 4),
                        "iterations": int(i_s.iterations), "converged": int(i_s.converged), "solve_s": round(t_s, 4),
                        "solve_vs_plain_fp64": round(t_s / t_cg, 4),
                        "train_s_all_seeds": round(sum(rr["train_s"] for rr in runs), 3)}
@@ -430,14 +439,14 @@ def learned_leg(torch, igb, epochs: int = 4, seeds=(5, 6, 7, 8)):
         "plain_fp64_cg": {"iterations": int(i_cg.iterations), "solve_s": round(t_cg, 4)},
         "jacobi_fgmres": {"iterations": int(i_j.iterations), "solve_s": round(t_j, 4)},
         "network_fgmres_per_seed": runs,
-        "network_converged_within_300": f"{len(conv)}/{len(runs)}",
+        "network_converged": f"{len(conv)}/{len(runs)}",
         "network_median_iterations": float(np.median([rr["iterations"] for rr in runs])),
         "network_best_solve_vs_plain_fp64": round(min(rr["solve_s"] for rr in conv) / t_cg, 4) if conv else None,
         "pairs_s": round(t_pairs, 3),
     })
     log(f"learned preconditioner: CG {i_cg.iterations} it {t_cg:.3f} s, Jacobi FGMRES {i_j.iterations} it "
         f"{t_j:.3f} s, network FGMRES per seed {[(rr['iterations'], rr['converged']) for rr in runs]}, "
-        f"selected {res['selected']['preconditioner']}: {i_s.iterations} it {t_s:.3f} s")
+        f"selected {res['selected']['preconditioner']}: {i_k.iterations} it {t_s:.3f} s")
     return res
 
 
@@ -679,6 +688,9 @@ def main():
     torch.cuda.empty_cache()
     if not args.no_mixed:
         out["mixed_fp32_far"] = c3_mixed_leg(torch, igb, geo, cfg, grid_dev, g_fn, ms_per_step, u_grid)
+    if not args.no_twin:
+        out["wavenumber_aware_admissibility"] = c3_kappa_leg(torch, igb, W, geo, cfg, grid_dev, g_fn, ms_per_step,
+                                                             u_grid, twin)
     if not args.no_sphere:
         out["sphere"] = sphere_leg(torch, igb, W, args.sphere_steps, args.matvec_reps)
     if not args.no_learned:
@@ -712,6 +724,32 @@ def products_only(torch, igb, W, which, reps):
     print(json.dumps({"workload": name, "products": which, "h2_matvec_ms": round(mv, 4),
                       "stage_ms": {k: round(v, 4) for k, v in stages.items()},
                       "stage_ms_separate": {k: round(v, 4) for k, v in sep.items()}}), flush=True)
+
+
+def c3_kappa_leg(torch, igb, W, geo, cfg, grid_dev, g_fn, fp64_ms, u_fp64, twin_blind, steps: int = 2):
+    """The torus step with the wavenumber-aware admissibility (kappa_diam, not from the paper: a block is
+    admissible only if also kappa max(diam) <= 12), and its point-source twin, beside the headline step on
+    the paper's wavenumber-blind rule."""
+    ms, (op, w, info, u, t) = timed_steps(
+        torch, lambda: c3_step(torch, igb, geo, cfg, grid_dev, g_fn, kappa_diam=C3_KAPPA_DIAM), steps)
+    un = u.cpu().numpy()
+    sep = op.profile(reps=5, separate=True)
+    twin = point_source_twin(torch, W, cfg, op, grid_dev)
+    _, far = op.partition()
+    log(f"wavenumber-aware admissibility (torus): {ms / 1e3:.3f} s per step, {info.iterations} it, twin error "
+        f"{twin['potential_max_rel_err']:.2e} (paper's rule {twin_blind and twin_blind['potential_max_rel_err']})")
+    res = {"kappa_diam": C3_KAPPA_DIAM, "value": round(ms / 1e3, 5), "ms_per_step": round(ms, 3),
+           "vs_paper_rule": round(ms / fp64_ms, 4), "iterations": int(info.iterations),
+           "rel_residual": float(info.rel_residual), "far_blocks": int(op.info.n_far_blocks),
+           "far_blocks_per_level": np.bincount(far[:, 0]).tolist(),
+           "far_field_alone_ms": round(sep["coupling"], 4),
+           "potential_rel_diff_vs_paper_rule": float(np.abs(un - u_fp64).max() / np.abs(u_fp64).max()),
+           "point_source_twin": twin,
+           "paper_rule_point_source_twin_rel_err": twin_blind["potential_max_rel_err"] if twin_blind else None,
+           "breakdown_s": {k: round(v, 4) for k, v in t.items()}}
+    del op
+    torch.cuda.empty_cache()
+    return res
 
 
 def c3_mixed_leg(torch, igb, geo, cfg, grid_dev, g_fn, fp64_ms, u_fp64, steps: int = 2):

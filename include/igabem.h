@@ -101,6 +101,12 @@ typedef struct {
     int32_t gauss_rhs;       /* points per direction for right-hand side and potential; -1: max(g0, p+4) */
     int32_t mode;            /* IGB_DENSE, IGB_H2_STORED or IGB_H2_ONTHEFLY */
     int32_t far_precision;   /* IGB_FP64, or IGB_FP32 (see there) */
+    double kappa_diam;       /* 0: the admissibility of Sec. 4.2 Def. as it stands (blind to the
+                                wavenumber).  > 0 (Helmholtz): a block is admissible only if, in
+                                addition, kappa * max(diam) <= kappa_diam, so that the interpolated
+                                kernel oscillates at most kappa_diam / (2 pi) times across a cluster;
+                                coarse blocks of high-wavenumber problems are then subdivided.  Not
+                                from the paper: an option for accuracy at large kappa * size */
 } igb_params;
 
 /* Sizes of an assembled operator (host struct filled by igb_operator_info). */
@@ -129,6 +135,7 @@ typedef struct {
     int32_t iterations;        /* operator applications in the Krylov loop */
     int32_t converged;         /* 1 if the true relative residual reached rel_tol */
     double rel_residual;       /* final true relative residual ||b - A w|| / ||b|| */
+    int32_t fallback;          /* igb_solve_fgmres with a network: 1 if it was dropped for Jacobi (stagnation) */
 } igb_solve_info;
 
 typedef struct igb_geometry igb_geometry;
@@ -280,13 +287,32 @@ igb_status igb_cnn_train_operator(igb_cnn *net, const igb_operator *op, const fl
 
 /* Flexible GMRES (right preconditioned, restarted after `restart` steps) for
  * T A T^T w = b with the preconditioner M(v) = D^-1 v + f(D^-1 v) of `net`, or
- * plain Jacobi D^-1 v when net is NULL (the fallback).  Laplace operators only
+ * plain Jacobi D^-1 v when net is NULL.  With a network, a restart cycle that
+ * fails to halve the true relative residual drops the network for Jacobi for
+ * the rest of the solve (info->fallback = 1).  Laplace operators only
  * (IGB_EUNSUPPORTED otherwise).  Stopping rule, initial guess and return
  * values as igb_solve, judged on the true residual of the FP64 operator.
  * restart in 1..2048 (IGB_EINVAL otherwise).  The bases take (2 restart + 1)
  * n_dof doubles of device memory.  Synchronous. */
 igb_status igb_solve_fgmres(const igb_operator *op, const igb_cnn *net, const void *b_dev, void *w_dev,
                             double rel_tol, int32_t max_iter, int32_t restart, igb_solve_info *info);
+
+/* Model selection for the learned preconditioner, then the solve.  Runs
+ * igb_solve_fgmres on the validation right-hand side v_dev (n_dof doubles, a
+ * problem of the same operator with other data), from a zero guess and with the
+ * same rel_tol, max_iter and restart, first with plain Jacobi and then with
+ * each of the n_nets networks (n_nets >= 0, none NULL).  A network is kept if
+ * it converged without falling back and in fewer steps than Jacobi and every
+ * network before it; *chosen (host) receives its index, or -1 for Jacobi.
+ * Then solves for b_dev into w_dev (initial guess on entry) with the kept
+ * preconditioner, exactly as igb_solve_fgmres; `info` describes that solve.
+ * The validation iterate lives in the operator's CG work vector, so the call
+ * must not overlap another solve on the same operator.  Neither b nor v may
+ * alias w (IGB_EINVAL).  Laplace only (IGB_EUNSUPPORTED otherwise).
+ * Synchronous. */
+igb_status igb_solve_fgmres_select(const igb_operator *op, const igb_cnn *const *nets, int32_t n_nets,
+                                   const void *v_dev, const void *b_dev, void *w_dev, double rel_tol,
+                                   int32_t max_iter, int32_t restart, int32_t *chosen, igb_solve_info *info);
 
 /* Solves n independent systems at once (the Krylov solve of Sec. 4 item 3
  * for each instance), each as igb_solve on ops[i] with

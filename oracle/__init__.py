@@ -69,7 +69,7 @@ def _load():
     lp = C.POINTER(C.c_int64)
     lib.or_create.restype = P
     lib.or_create.argtypes = [C.c_int, ip, ip, dp, dp, C.c_int, C.c_double, C.c_int, C.c_int, C.c_int,
-                              C.c_double, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int]
+                              C.c_double, C.c_double, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int]
     lib.or_destroy.argtypes = [P]
     lib.or_info.argtypes = [P, lp]
     lib.or_export_partition.argtypes = [P, ip, ip]
@@ -144,12 +144,13 @@ class Problem:
     """One discretised single-layer problem (geometry + parameters)."""
 
     def __init__(self, patches, *, kernel=LAPLACE, wavenumber=0.0, p=1, m=2, q=8, eta=1.6, leaf_depth=-1,
-                 gauss_regular=6, gauss_singular=-1, gauss_rhs=-1, threads=0):
+                 gauss_regular=6, gauss_singular=-1, gauss_rhs=-1, threads=0, kappa_diam=0.0):
         lib = _load()
         self._keep = _flatten_patches(patches)
         deg, ncp, knots, cpw = self._keep
         self._h = lib.or_create(len(patches), _i(deg), _i(ncp), _d(knots), _d(cpw), int(kernel), float(wavenumber),
-                                int(p), int(m), int(q), float(eta), int(leaf_depth), int(gauss_regular),
+                                int(p), int(m), int(q), float(eta), float(kappa_diam), int(leaf_depth),
+                                int(gauss_regular),
                                 int(gauss_singular), int(gauss_rhs), int(threads))
         if not self._h:
             raise ValueError("invalid oracle parameters")

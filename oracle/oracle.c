@@ -167,6 +167,7 @@ typedef struct or_problem {
     double kappa;
     int p, m, q, L, g0, gs, grhs;
     double eta;
+    double kdmax; /* > 0: also kappa * max(diam) <= kdmax for admissibility (an option, not the paper's) */
     int nel1, nelem, nloc, nsup, ns1, ndof;
     double h;
     double *T1;     /* ns1 x (nel1*(p+1)) */
@@ -612,7 +613,9 @@ static void pair_block_sym(const or_problem *P, int E, int F, cplx *out)
 /* Cluster (patch, l, k1, k2) covers [k1,k1+1]x[k2,k2+1] * 2^-l.              */
 /* Readings: diam and dist are taken over the images of a 5x5 uniform grid   */
 /* of the cluster's parameter square (corners included); admissible iff       */
-/* max(diam, diam') < eta * dist.  Far field = admissible blocks whose        */
+/* max(diam, diam') < eta * dist.  Option (not in the paper): with kdmax > 0 */
+/* a block must also satisfy kappa * max(diam, diam') <= kdmax.              */
+/* Far field = admissible blocks whose                                        */
 /* parents are not admissible; near field = non-admissible leaf blocks.       */
 /* ------------------------------------------------------------------------ */
 static void cluster_decode(const or_problem *P, int l, int id, int *patch, int *k1, int *k2)
@@ -656,6 +659,7 @@ static void build_level_grid(const or_problem *P, int l, level_grid *G)
 static int admissible(const or_problem *P, const level_grid *G, int a, int b)
 {
     double md = fmax(G->diam[a], G->diam[b]);
+    if (P->kdmax > 0 && P->kernel == OR_HELMHOLTZ && P->kappa * md > P->kdmax) return 0;
     double dmin = 1e300;
     for (int i = 0; i < 25; ++i)
         for (int j = 0; j < 25; ++j) {
@@ -838,10 +842,11 @@ void or_coupling_block(const or_problem *P, int l, int tgt, int src, cplx *K)
 /* creation                                                                   */
 /* ------------------------------------------------------------------------ */
 or_problem *or_create(int npatch, const int *deg, const int *ncp, const double *knots, const double *cpw, int kernel,
-                      double kappa, int p, int m, int q, double eta, int leaf_depth, int g0, int gs, int grhs,
-                      int nthreads)
+                      double kappa, int p, int m, int q, double eta, double kdmax, int leaf_depth, int g0, int gs,
+                      int grhs, int nthreads)
 {
-    if (npatch < 1 || p < 0 || p > 8 || m < 0 || m > 12 || q < 1 || q > 24 || !(eta > 0) || g0 < 1 || g0 > 40)
+    if (npatch < 1 || p < 0 || p > 8 || m < 0 || m > 12 || q < 1 || q > 24 || !(eta > 0) || !(kdmax >= 0) || g0 < 1 ||
+        g0 > 40)
         return NULL;
     or_problem *P = (or_problem *)calloc(1, sizeof(or_problem));
     P->npatch = npatch;
@@ -851,6 +856,7 @@ or_problem *or_create(int npatch, const int *deg, const int *ncp, const double *
     P->m = m;
     P->q = q;
     P->eta = eta;
+    P->kdmax = kdmax;
     P->g0 = g0;
     P->gs = gs > 0 ? gs : (g0 + 2 > 40 ? 40 : g0 + 2);
     P->grhs = grhs > 0 ? grhs : (g0 > p + 4 ? g0 : p + 4);

@@ -1423,6 +1423,7 @@ struct FarSymArgs {
     int q2;
     const double *nodes;
     double kappa;
+    const double *sctab;  // sin, cos (j pi/64), j < 128 (complex kernel, see sincos_tab)
 };
 
 // Mirrored far-field pairs handled by one wave in a row (node data of the next
@@ -1471,12 +1472,14 @@ __device__ inline FarNode<T> far_node(const FarSymArgs &F, const T *__restrict__
 // refined reciprocal square root, the phase clamped into the range of sincos_red (padding nodes sit 1e100
 // away; their weight is zero on one side and their value below 1e-100 on the other).  Single precision
 // (RAW): the hardware reciprocal square root, the phase kappa r / (2 pi) in turns reduced to one turn
-// (v_fract) for the hardware sine and cosine, which take turns.
-template <bool RAW>
+// (v_fract) for the hardware sine and cosine, which take turns.  TAB (double precision): sine and cosine
+// from the table in LDS (sincos_tab) instead of sincos_red.
+template <bool RAW, bool TAB = false>
 __device__ inline void helm_far_value(typename std::conditional<RAW, float, double>::type r2,
                                       typename std::conditional<RAW, float, double>::type kap,
                                       typename std::conditional<RAW, float, double>::type &gr,
-                                      typename std::conditional<RAW, float, double>::type &gi)
+                                      typename std::conditional<RAW, float, double>::type &gi,
+                                      const double *tab = nullptr)
 {
     if constexpr (RAW) {
         const float ir = __builtin_amdgcn_rsqf(r2);
@@ -1486,7 +1489,8 @@ __device__ inline void helm_far_value(typename std::conditional<RAW, float, doub
     } else {
         const double ir = rsqrt_pos(r2);
         double sn, cs;
-        sincos_red(fmin(kap * (r2 * ir), 0x1p19), &sn, &cs);
+        if constexpr (TAB) sincos_tab(fmin(kap * (r2 * ir), 0x1p19), tab, &sn, &cs);
+        else sincos_red(fmin(kap * (r2 * ir), 0x1p19), &sn, &cs);
         gr = cs * ir;
         gi = sn * ir;
     }
@@ -1503,9 +1507,9 @@ __device__ inline void helm_far_value(typename std::conditional<RAW, float, doub
 // Positions are taken relative to the pair's first target node.  RAW: kernel
 // values and the sums inside the pair in FP32 (positions rounded after the
 // shift, so the rounding is relative to the cluster separation).
-template <int TT, bool RAW>
+template <int TT, bool RAW, bool TAB = false>
 __device__ inline void far_sym_chunk(const FarSymArgs &F, int64_t k0, int64_t k1, const cd *__restrict__ Xh,
-                                     cd *__restrict__ part, double *lds)
+                                     cd *__restrict__ part, double *lds, const double *tab = nullptr)
 {
     using R = typename std::conditional<RAW, float, double>::type;
     constexpr int W = 8 * TT;  // padded nodes per cluster
@@ -1559,7 +1563,7 @@ __device__ inline void far_sym_chunk(const FarSymArgs &F, int64_t k0, int64_t k1
                 for (int ii = 0; ii < TH; ++ii) {
                     const R d0 = tx[ii] - sx, d1 = ty[ii] - sy, d2 = tz[ii] - sz;
                     R gr, gi;
-                    helm_far_value<RAW>(d0 * d0 + d1 * d1 + d2 * d2, kap, gr, gi);
+                    helm_far_value<RAW, TAB>(d0 * d0 + d1 * d1 + d2 * d2, kap, gr, gi, tab);
                     ar[ii] += gr * swr - gi * swi;
                     ai[ii] += gr * swi + gi * swr;
                     pr_ += gr * wr[ii] - gi * wi[ii];
@@ -1743,14 +1747,21 @@ __global__ void __launch_bounds__(256, NComp<T>::value == 1 ? 3 : 1) k_far_sym(F
 // of waves per SIMD (kFarWaves), fewer than the registers allow, so that the
 // near-field GEMV on the side stream finds room on every CU.
 constexpr int kFarWaves[2] = {3, 3};  // double, single precision: the fastest of 2..4 measured (torus, kappa 8, q 10)
+// Double precision: the sine/cosine table (2 KB) is copied into LDS ahead of the nodes.
 template <class T, int TT, bool RAW>
 __global__ void __launch_bounds__(64, RAW ? 4 : 2) k_far_sym1(FarSymArgs F, const T *__restrict__ Xh, T *__restrict__ part)
 {
     extern __shared__ double sh[];
+    constexpr int ntab = RAW ? 0 : 256;
+    if constexpr (!RAW) {
+        for (int i = threadIdx.x; i < ntab; i += 64) sh[i] = F.sctab[i];
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    }
     const int64_t nch = (F.nup + kFarChunk - 1) / kFarChunk;
     for (int64_t c = blockIdx.x; c < nch; c += gridDim.x) {
         const int64_t k0 = c * kFarChunk;
-        far_sym_chunk<TT, RAW>(F, k0, min(k0 + kFarChunk, F.nup), Xh, part, sh);
+        far_sym_chunk<TT, RAW, !RAW>(F, k0, min(k0 + kFarChunk, F.nup), Xh, part, sh + ntab, sh);
     }
 }
 
@@ -2723,6 +2734,7 @@ struct igb_operator {
     int gord[3] = {0, 0, 0};
     double *rpts = nullptr;        // rhs/potential order geometry
     double *nodes = nullptr;
+    double *sctab = nullptr;       // sin, cos (j pi/64), j < 128, for the complex far field
     double *zdev = nullptr;        // Chebyshev nodes
     int64_t *cl_off = nullptr;
     double *M1 = nullptr, *E2 = nullptr, *Mlev = nullptr, *Tb = nullptr;
@@ -2961,7 +2973,7 @@ static igb_status launch_singular(igb_operator *op, const PairRec *d, int64_t n,
 // (symmetric near storage only), 5 downward (transfers and leaf back-moments).
 static FarSymArgs far_args(const igb_operator *op)
 {
-    return FarSymArgs{op->nup, op->up_t, op->up_s, op->s.q * op->s.q, op->nodes, op->s.kappa};
+    return FarSymArgs{op->nup, op->up_t, op->up_s, op->s.q * op->s.q, op->nodes, op->s.kappa, op->sctab};
 }
 static NearSymArgs near_args(const igb_operator *op)
 {
@@ -2975,7 +2987,7 @@ static void launch_far_sym_p(igb_operator *op, const T *Xh, const T *xs, bool fu
 {
     if constexpr (TT > 8) {  // one wave per workgroup (LDS slice of far_sym_lds doubles), never fused
         (void)fuse;
-        const size_t shm = (size_t)far_sym_lds<T, TT>() * sizeof(double);
+        const size_t shm = ((size_t)far_sym_lds<T, TT>() + (RAW ? 0 : 256)) * sizeof(double);
         const int64_t nch = (op->nup + kFarChunk - 1) / kFarChunk;
         const int64_t grid = std::min<int64_t>(nch, (int64_t)op->ncu * 4 * kFarWaves[RAW ? 1 : 0]);
         hipLaunchKernelGGL((k_far_sym1<T, TT, RAW>), dim3((unsigned)grid), dim3(64), shm, op->st, far_args(op), Xh,
@@ -3411,6 +3423,17 @@ static igb_status assemble(igb_operator *op)
     int64_t nfar = (int64_t)s.far_src.size();
     op->coup_bytes = nfar * q2 * q2 * (int64_t)sizeof(T);
     if ((rc = dalloc(op, (void **)&op->nodes, (size_t)ncl_all * q2 * 4 * sizeof(double)))) return rc;
+    if (op->cplx) {
+        // one period of sine and cosine at multiples of pi/64, from extended-precision host values
+        std::vector<double> tab(256);
+        for (int j = 0; j < 128; ++j) {
+            const long double a = (long double)j * 3.141592653589793238462643383279502884L / 64.0L;
+            tab[2 * j] = (double)sinl(a);
+            tab[2 * j + 1] = (double)cosl(a);
+        }
+        if ((rc = upload(op, &op->sctab, tab.data(), tab.size() * sizeof(double)))) return rc;
+        HIPCHK(hipStreamSynchronize(op->st));  // the host table goes out of scope
+    }
     hipLaunchKernelGGL(k_cluster_nodes, dim3(nblk(ncl_all * q2, 256)), dim3(256), 0, op->st, ncl_all, s.L, op->cl_off,
                        s.q, s.m, s.ne, op->zdev, s.tile_stride, op->tiles, op->tdeg, op->nodes);
     LAUNCHCHK();
@@ -3716,6 +3739,7 @@ static igb_status solve_cg(igb_operator *op, const double *b, double *w, double 
         info->iterations = it;
         info->rel_residual = rel;
         info->converged = rel <= tol;
+        info->fallback = 0;
     }
     return rel <= tol ? IGB_OK : fail(IGB_ENOT_CONVERGED, "CG stopped at max_iter with relative residual " + std::to_string(rel));
 }
@@ -3893,7 +3917,10 @@ static igb_status solve_gmres_dev(igb_operator *op, const igb_cnn *net, const T 
         ~Events() { (void)hipEventDestroy(e[0]); (void)hipEventDestroy(e[1]); }
     } events{ev};
     int it = 0;
-    double rel = 0.0;
+    double rel = 0.0, prev_rel = -1.0;
+    // the network is dropped for Jacobi (the fallback) once a restart cycle fails to halve the true residual
+    const igb_cnn *pnet = net;
+    int fell_back = 0;
     for (;;) {
         if ((rc = matvec_S<T>(op, w, t))) return rc;
         HIPCHK(hipMemcpyAsync(r, b, n * sizeof(T), hipMemcpyDeviceToDevice, op->st));
@@ -3904,6 +3931,11 @@ static igb_status solve_gmres_dev(igb_operator *op, const igb_cnn *net, const T 
         if ((rc = norm2(r, &beta2))) return rc;
         const double beta = std::sqrt(beta2);
         rel = beta / bn;
+        if (pnet && prev_rel > 0.0 && rel > 0.5 * prev_rel) {
+            pnet = nullptr;
+            fell_back = 1;
+        }
+        prev_rel = rel;
         if (rel <= tol || it >= maxit) break;
         hipLaunchKernelGGL((k_axpby<T>), dim3(gb), dim3(256), 0, op->st, n, from_real<T>(1.0 / beta), (const T *)r,
                            zero<T>(), V);
@@ -3924,11 +3956,11 @@ static igb_status solve_gmres_dev(igb_operator *op, const igb_cnn *net, const T 
                 const int k = launched;
                 T *vk = V + (size_t)k * n, *vn = V + (size_t)(k + 1) * n, *zk = Z + (size_t)k * n;
                 if constexpr (std::is_same<T, double>::value) {
-                    if (net) {
-                        if ((rc = cnn_precondition(net, s.npatch, s.ns1, s.ns1, vk, D, zk, op->st))) break;
+                    if (pnet) {
+                        if ((rc = cnn_precondition(pnet, s.npatch, s.ns1, s.ns1, vk, D, zk, op->st))) break;
                     }
                 }
-                if (!net && k == 0)
+                if (!pnet && k == 0)
                     hipLaunchKernelGGL((k_div<T>), dim3(gb), dim3(256), 0, op->st, n, (const T *)vk, D, zk);
                 // else (Jacobi) z_k = D^-1 v_k was formed when v_k was normalised
                 if ((rc = matvec_S<T>(op, zk, vn))) break;
@@ -3942,7 +3974,7 @@ static igb_status solve_gmres_dev(igb_operator *op, const igb_cnn *net, const T 
                 }
                 hipLaunchKernelGGL((k_arnoldi<T>), dim3(1), dim3(64), (size_t)(3 * k + 4) * sizeof(T), op->st, k, R,
                                    (const T *)hA, (const T *)hB, (const double *)nrm, (int)gsub, G, hout + 2 * (k & 1));
-                T *znext = (!net && k + 1 < kmax) ? Z + (size_t)(k + 1) * n : nullptr;
+                T *znext = (!pnet && k + 1 < kmax) ? Z + (size_t)(k + 1) * n : nullptr;
                 hipLaunchKernelGGL((k_scale_dev<T>), dim3(gb), dim3(256), 0, op->st, n, (const double *)(st + 1), vn, D,
                                    znext);
                 if (hipGetLastError() != hipSuccess || hipEventRecord(ev[k & 1], op->st) != hipSuccess) {
@@ -3986,6 +4018,7 @@ static igb_status solve_gmres_dev(igb_operator *op, const igb_cnn *net, const T 
         info->iterations = it;
         info->rel_residual = rel;
         info->converged = rel <= tol;
+        info->fallback = fell_back;
     }
     return rel <= tol ? IGB_OK
                       : fail(IGB_ENOT_CONVERGED, "GMRES stopped at max_iter with relative residual " + std::to_string(rel));
@@ -4328,6 +4361,7 @@ static igb_status solve_refined(igb_operator *op, const cd *b, cd *w, double tol
         info->iterations = it;
         info->rel_residual = rel;
         info->converged = rel <= tol;
+        info->fallback = 0;
     }
     return rel <= tol ? IGB_OK
                       : fail(IGB_ENOT_CONVERGED, "refinement stopped at max_iter with relative residual " +
@@ -4420,6 +4454,43 @@ igb_status igb_solve_fgmres(const igb_operator *cop, const igb_cnn *net, const v
     igb_operator *op = const_cast<igb_operator *>(cop);
     if (op->cplx) return fail(IGB_EUNSUPPORTED, "flexible GMRES is built for real (Laplace) operators");
     return solve_gmres_dev<double>(op, net, (const double *)b_dev, (double *)w_dev, rel_tol, max_iter, restart, info);
+}
+
+igb_status igb_solve_fgmres_select(const igb_operator *cop, const igb_cnn *const *nets, int32_t n_nets,
+                                   const void *v_dev, const void *b_dev, void *w_dev, double rel_tol,
+                                   int32_t max_iter, int32_t restart, int32_t *chosen, igb_solve_info *info)
+{
+    CHECK_OP(cop);
+    if (!v_dev || !b_dev || !w_dev || !chosen) return fail(IGB_EINVAL, "null argument");
+    if (n_nets < 0 || (n_nets > 0 && !nets)) return fail(IGB_EINVAL, "n_nets must be >= 0 with a network array");
+    for (int32_t i = 0; i < n_nets; ++i)
+        if (!nets[i]) return fail(IGB_EINVAL, "null network at " + std::to_string(i));
+    if (b_dev == w_dev || v_dev == w_dev) return fail(IGB_EINVAL, "b, v and w must not alias");
+    if (!(rel_tol > 0.0) || max_iter < 0) return fail(IGB_EINVAL, "rel_tol must be > 0 and max_iter >= 0");
+    if (restart < 1 || restart > 2048) return fail(IGB_EINVAL, "restart must be in 1..2048");
+    igb_operator *op = const_cast<igb_operator *>(cop);
+    if (op->cplx) return fail(IGB_EUNSUPPORTED, "flexible GMRES is built for real (Laplace) operators");
+    const int64_t n = op->s.ndof;
+    double *vw = (double *)op->pv;  // the CG direction vector, idle during flexible GMRES
+    // validation: Jacobi first, then each network, all from a zero initial guess; a network is kept only if
+    // it converges without falling back and in fewer steps than every earlier choice
+    int32_t best = -1, best_it = 0;
+    for (int32_t i = -1; i < n_nets; ++i) {
+        HIPCHK(hipMemsetAsync(vw, 0, n * sizeof(double), op->st));
+        igb_solve_info vi{};
+        const igb_status rc = solve_gmres_dev<double>(op, i < 0 ? nullptr : nets[i], (const double *)v_dev, vw,
+                                                      rel_tol, max_iter, restart, &vi);
+        if (rc != IGB_OK && rc != IGB_ENOT_CONVERGED) return rc;
+        if (i < 0)
+            best_it = vi.converged ? vi.iterations : max_iter + 1;
+        else if (vi.converged && !vi.fallback && vi.iterations < best_it) {
+            best = i;
+            best_it = vi.iterations;
+        }
+    }
+    *chosen = best;
+    return solve_gmres_dev<double>(op, best < 0 ? nullptr : nets[best], (const double *)b_dev, (double *)w_dev,
+                                   rel_tol, max_iter, restart, info);
 }
 
 igb_status igb_cnn_train_operator(igb_cnn *net, const igb_operator *cop, const float *y_dev, const float *x_dev,

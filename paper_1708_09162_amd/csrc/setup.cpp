@@ -435,10 +435,13 @@ static void level_geo(const Setup &s, int l, LevelGeo &G)
     });
 }
 
-// admissibility max(diam) < eta * dist over the 5x5 grids (bounds decide clear cases)
+// admissibility max(diam) < eta * dist over the 5x5 grids (bounds decide clear cases); with the
+// wavenumber option also kappa * max(diam) <= kappa_diam, so that no admissible cluster spans more than
+// kappa_diam / (2 pi) wavelengths
 static bool admissible(const Setup &s, const LevelGeo &G, int a, int b)
 {
     double md = std::max(G.diam[a], G.diam[b]);
+    if (s.kappa_diam > 0.0 && s.kappa * md > s.kappa_diam) return false;
     double cc = dist(&G.cen[3 * a], &G.cen[3 * b]);
     double lb = cc - G.rad[a] - G.rad[b];
     if (lb > 0 && md < s.eta * lb * (1.0 - 1e-12)) return true;
@@ -839,6 +842,7 @@ std::string build_setup_tiles(const Geometry &geo, const igb_params &prm, Setup 
     if (prm.m < 0 || prm.m > 10) return "m outside 0..10";
     if (prm.q < 1 || prm.q > 16) return "q outside 1..16";
     if (!(prm.eta > 0.0) || !std::isfinite(prm.eta)) return "eta must be > 0";
+    if (!(prm.kappa_diam >= 0.0) || !std::isfinite(prm.kappa_diam)) return "kappa_diam must be >= 0";
     if (prm.kernel == IGB_HELMHOLTZ && (!(prm.wavenumber >= 0.0) || !std::isfinite(prm.wavenumber)))
         return "wavenumber must be >= 0";
     if (prm.gauss_regular < 1 || prm.gauss_regular > 36) return "gauss_regular outside 1..36";
@@ -874,6 +878,7 @@ std::string build_setup_tiles(const Geometry &geo, const igb_params &prm, Setup 
     s.m = prm.m;
     s.q = prm.q;
     s.eta = prm.eta;
+    s.kappa_diam = prm.kappa_diam;
     s.g0 = prm.gauss_regular;
     s.gs = prm.gauss_singular > 0 ? prm.gauss_singular : std::min(40, s.g0 + 2);
     s.grhs = prm.gauss_rhs > 0 ? prm.gauss_rhs : std::max(s.g0, s.p + 4);

@@ -40,6 +40,7 @@ struct Setup {
     double kappa = 0.0;
     int p = 0, m = 0, q = 1, d = 0, L = 0;
     double eta = 1.0;
+    double kappa_diam = 0.0;  // > 0: blocks with kappa max(diam) above it are not admissible
     int g0 = 6, gs = 8, grhs = 6;
     int mode = 0;
     // derived sizes

@@ -40,7 +40,7 @@ EXPORTED = [
     "igb_plan_export_pair_classes", "igb_matvec_profile", "igb_release_cached_memory",
     "igb_cnn_create", "igb_cnn_destroy", "igb_cnn_get_weights", "igb_cnn_forward", "igb_cnn_gradient",
     "igb_cnn_training_pairs", "igb_cnn_train", "igb_cnn_train_operator", "igb_solve_fgmres", "igb_solve_many",
-    "igb_potential_noalloc",
+    "igb_potential_noalloc", "igb_solve_fgmres_select",
 ]
 IGB_CNN_NUM_WEIGHTS = 28224
 IGB_CNN_RELU = 0
@@ -60,7 +60,7 @@ class igb_params(C.Structure):
     _fields_ = [("kernel", C.c_int32), ("wavenumber", C.c_double), ("p", C.c_int32), ("m", C.c_int32),
                 ("q", C.c_int32), ("eta", C.c_double), ("leaf_depth", C.c_int32), ("gauss_regular", C.c_int32),
                 ("gauss_singular", C.c_int32), ("gauss_rhs", C.c_int32), ("mode", C.c_int32),
-                ("far_precision", C.c_int32)]
+                ("far_precision", C.c_int32), ("kappa_diam", C.c_double)]
 
 
 class igb_info(C.Structure):
@@ -73,7 +73,8 @@ class igb_info(C.Structure):
 
 
 class igb_solve_info(C.Structure):
-    _fields_ = [("iterations", C.c_int32), ("converged", C.c_int32), ("rel_residual", C.c_double)]
+    _fields_ = [("iterations", C.c_int32), ("converged", C.c_int32), ("rel_residual", C.c_double),
+                ("fallback", C.c_int32)]
 
 
 def _load():
@@ -128,6 +129,8 @@ def _load():
         "igb_cnn_train_operator": (C.c_int32, [vp, vp, vp, vp, C.c_int64, C.c_int32, C.c_int32, C.c_float, dp]),
         "igb_solve_fgmres": (C.c_int32, [vp, vp, vp, vp, C.c_double, C.c_int32, C.c_int32,
                                          C.POINTER(igb_solve_info)]),
+        "igb_solve_fgmres_select": (C.c_int32, [vp, vp, C.c_int32, vp, vp, vp, C.c_double, C.c_int32, C.c_int32,
+                                                C.POINTER(C.c_int32), C.POINTER(igb_solve_info)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -245,6 +248,17 @@ def igb_solve_fgmres(op, net, b, w, rel_tol, max_iter, restart) -> igb_solve_inf
     return info
 
 
+def igb_solve_fgmres_select(op, nets, v, b, w, rel_tol, max_iter, restart):
+    """Returns (index of the kept network or -1 for Jacobi, info of the final solve)."""
+    n = len(nets)
+    arr = (C.c_void_p * max(n, 1))(*[x.value if isinstance(x, C.c_void_p) else x for x in nets])
+    chosen, info = C.c_int32(-2), igb_solve_info()
+    _check(_lib.igb_solve_fgmres_select(op, arr, n, _ptr(v), _ptr(b), _ptr(w), float(rel_tol), int(max_iter),
+                                        int(restart), C.byref(chosen), C.byref(info)),
+           allow=(IGB_OK, IGB_ENOT_CONVERGED))
+    return chosen.value, info
+
+
 def igb_solve_many(ops, bs, ws, rel_tol, max_iter, restart):
     n = len(ops)
     arr = lambda xs: (C.c_void_p * max(n, 1))(*xs)
@@ -360,9 +374,11 @@ def igb_matvec_profile(op, reps, flags=0):
 
 
 def make_params(*, kernel=IGB_LAPLACE, wavenumber=0.0, p=1, m=2, q=8, eta=1.6, leaf_depth=-1, gauss_regular=6,
-                gauss_singular=-1, gauss_rhs=-1, mode=IGB_H2_STORED, far_precision=IGB_FP64) -> igb_params:
+                gauss_singular=-1, gauss_rhs=-1, mode=IGB_H2_STORED, far_precision=IGB_FP64,
+                kappa_diam=0.0) -> igb_params:
     return igb_params(int(kernel), float(wavenumber), int(p), int(m), int(q), float(eta), int(leaf_depth),
-                      int(gauss_regular), int(gauss_singular), int(gauss_rhs), int(mode), int(far_precision))
+                      int(gauss_regular), int(gauss_singular), int(gauss_rhs), int(mode), int(far_precision),
+                      float(kappa_diam))
 
 
 def igb_plan_create(geo, prm: igb_params):
@@ -456,7 +472,7 @@ class Operator(_StreamOrdered):
 
     def __init__(self, geometry: Geometry, *, kernel=IGB_LAPLACE, wavenumber=0.0, p=1, m=2, q=8, eta=1.6,
                  leaf_depth=-1, gauss_regular=6, gauss_singular=-1, gauss_rhs=-1, mode=IGB_H2_STORED,
-                 far_precision=IGB_FP64, device="cuda:0", stream=None):
+                 far_precision=IGB_FP64, kappa_diam=0.0, device="cuda:0", stream=None):
         import torch
 
         self.torch = torch
@@ -464,7 +480,7 @@ class Operator(_StreamOrdered):
         self.geometry = geometry
         prm = make_params(kernel=kernel, wavenumber=wavenumber, p=p, m=m, q=q, eta=eta, leaf_depth=leaf_depth,
                           gauss_regular=gauss_regular, gauss_singular=gauss_singular, gauss_rhs=gauss_rhs, mode=mode,
-                          far_precision=far_precision)
+                          far_precision=far_precision, kappa_diam=kappa_diam)
         with torch.cuda.device(self.device):
             self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
             self.h = igb_operator_create(geometry.h, prm, self.stream.cuda_stream)
@@ -543,6 +559,16 @@ class Operator(_StreamOrdered):
         with self._ordered():
             info = igb_solve_fgmres(self.h, net.h if net is not None else None, b, w, tol, max_iter, restart)
         return w, info
+
+    def solve_fgmres_select(self, nets, v, b, w0=None, tol=1e-8, max_iter=1000, restart=100):
+        """Keeps the network (or Jacobi) with the fewest flexible-GMRES steps on the validation right-hand side
+        v, then solves for b with it (igb_solve_fgmres_select); returns (w, kept index or -1, info)."""
+        w = self._vec(self.info.n_dof) if w0 is None else self._in(w0, self.info.n_dof).clone()
+        b = self._in(b, self.info.n_dof)
+        v = self._in(v, self.info.n_dof)
+        with self._ordered():
+            chosen, info = igb_solve_fgmres_select(self.h, [x.h for x in nets], v, b, w, tol, max_iter, restart)
+        return w, chosen, info
 
     @property
     def grid(self):

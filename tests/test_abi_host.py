@@ -64,7 +64,8 @@ def test_geometry_validation_errors():
                                  dict(kernel=1, wavenumber=-1.0), dict(leaf_depth=-2), dict(far_precision=2),
                                  dict(far_precision=1, kernel=1, wavenumber=1.0, mode=2, q=11),
                                  dict(far_precision=1, mode=1), dict(far_precision=1, mode=2, q=9),
-                                 dict(kernel=1, wavenumber=1e6)])
+                                 dict(kernel=1, wavenumber=1e6), dict(kappa_diam=-1.0),
+                                 dict(kappa_diam=float("inf"))])
 def test_parameter_validation_errors(bad):
     g = igb.Geometry(W.sphere_patches())
     with pytest.raises(igb.IgbError) as e:
@@ -91,7 +92,9 @@ def _compare_plan(patches, **prm):
     g = igb.Geometry(patches)
     pl = igb.Plan(g, mode=igb.IGB_DENSE if dense else igb.IGB_H2_STORED, **prm)
     kw = dict(p=prm.get("p", 1), m=prm.get("m", 2), q=prm.get("q", 8), eta=1e-12 if dense else prm.get("eta", 1.6),
-              leaf_depth=prm.get("leaf_depth", -1), gauss_regular=prm.get("gauss_regular", 6))
+              leaf_depth=prm.get("leaf_depth", -1), gauss_regular=prm.get("gauss_regular", 6),
+              kernel=prm.get("kernel", 0), wavenumber=prm.get("wavenumber", 0.0),
+              kappa_diam=prm.get("kappa_diam", 0.0))
     P = oracle.Problem(patches, **kw)
     info = pl.info
     assert info.n_dof == P.ndof and info.n_dof_super == P.nsup and info.leaf_level == P.L
@@ -118,6 +121,28 @@ def test_plan_matches_oracle_sphere_h2():
 
 def test_plan_matches_oracle_torus_h2():
     _compare_plan(W.torus_patches(), p=2, m=2, q=4, leaf_depth=1, eta=1.6)
+
+
+def test_wavenumber_aware_admissibility():
+    """kappa_diam > 0 keeps a block out of the far field while kappa max(diam) exceeds it: on the torus at
+    kappa = 8 (clusters of patch size span several wavelengths) the partition equals the oracle's under the
+    same option, has no far blocks on the coarse levels, and still tiles the block index set (the far
+    field moves to finer levels and grows); without the wavenumber (Laplace) the option changes nothing."""
+    base = dict(p=1, m=4, q=4, leaf_depth=1, eta=1.6, kernel=1, wavenumber=8.0)
+    blind = _compare_plan(W.torus_patches(), **base)
+    aware = _compare_plan(W.torus_patches(), kappa_diam=6.0, **base)
+    g = igb.Geometry(W.torus_patches())
+    _, far_b = igb.Plan(g, mode=igb.IGB_H2_STORED, **base).partition()
+    _, far_a = igb.Plan(g, mode=igb.IGB_H2_STORED, kappa_diam=6.0, **base).partition()
+    assert far_b[:, 0].min() <= 1 and far_a[:, 0].min() >= 2
+    assert aware.n_far_blocks > blind.n_far_blocks and aware.n_near_blocks >= blind.n_near_blocks
+    nelem, L = aware.n_elements, aware.leaf_level
+    covered = int(np.sum(16 ** (4 - far_a[:, 0].astype(np.int64)))) + aware.n_near_blocks * 16 ** (4 - L)
+    assert covered == nelem * nelem
+    lap = dict(base, kernel=0, wavenumber=0.0)
+    _, far_l = igb.Plan(g, mode=igb.IGB_H2_STORED, **lap).partition()
+    _, far_l6 = igb.Plan(g, mode=igb.IGB_H2_STORED, kappa_diam=6.0, **lap).partition()
+    assert np.array_equal(far_l, far_l6)
 
 
 def test_plan_matches_oracle_sphere_p3_m5_q8_full_size():

@@ -280,11 +280,13 @@ def test_solve_many_matches_single_solves():
 
 
 def test_selected_network_against_jacobi():
-    """Model selection with fallback: four linear networks (initial-weight seeds 5-8) trained on the p=2
-    sphere with 32x32 elements per patch; the one with the fewest flexible-GMRES steps on a validation
-    right-hand side (other point charges) is kept if it beats Jacobi there, else Jacobi.  On the real
-    right-hand side the kept preconditioner takes at most Jacobi's steps plus a small margin for the
-    validation-to-target mismatch; the gain is reported."""
+    """Model selection and fallback inside the library: four linear networks (initial-weight seeds 5-8)
+    trained on the p=2 sphere with 32x32 elements per patch.  Every seed converges to 1e-8 in flexible GMRES
+    (a network whose restart cycle fails to halve the residual is dropped for Jacobi, reported in
+    info.fallback).  igb_solve_fgmres_select keeps the seed with the fewest steps on a validation right-hand
+    side (other point charges) among those that converged there without falling back and beat Jacobi, else
+    Jacobi; its choice is recomputed here from single solves, and on the real right-hand side the kept
+    preconditioner takes at most Jacobi's steps plus a small margin for the validation-to-target mismatch."""
     say("selected network: sphere p=2 m=5 q=8")
     op, P, b = _sphere_problem(2, 5, 8)
     npatch, side = op.grid
@@ -294,17 +296,26 @@ def test_selected_network_against_jacobi():
     x = torch.tensor(W.training_vectors(512, op.info.n_dof, 20), device=DEV)
     y32, x32 = op.training_pairs(x)
     _, vj = op.solve_fgmres(bv, None, tol=1e-8, max_iter=2000, restart=100)
-    best, best_v = None, vj.iterations
-    for seed in (5, 6, 7, 8):
+    _, ij = op.solve_fgmres(bt, None, tol=1e-8, max_iter=2000, restart=100)
+    assert vj.converged == 1 and ij.converged == 1 and vj.fallback == 0
+    nets, expect, best_v = [], -1, vj.iterations
+    for k, seed in enumerate((5, 6, 7, 8)):
         net = igb.CNN(W.cnn_initial_weights(seed), igb.IGB_CNN_LINEAR, device=DEV)
         net.train(y32, x32, npatch, side, side, epochs=12, batch=16, lr=1e-3)
-        _, vi = op.solve_fgmres(bv, net, tol=1e-8, max_iter=300, restart=100)
-        say(f"seed {seed}: validation {vi.iterations} steps (converged {vi.converged}), jacobi {vj.iterations}")
-        if vi.converged == 1 and vi.iterations < best_v:
-            best, best_v = net, vi.iterations
-    _, ij = op.solve_fgmres(bt, None, tol=1e-8, max_iter=2000, restart=100)
-    w, isel = op.solve_fgmres(bt, best, tol=1e-8, max_iter=2000, restart=100)
-    say(f"selected {'network' if best is not None else 'jacobi'}: {isel.iterations} steps, jacobi {ij.iterations}")
-    assert ij.converged == 1 and isel.converged == 1
-    assert isel.iterations <= ij.iterations + 5
+        nets.append(net)
+        _, vi = op.solve_fgmres(bv, net, tol=1e-8, max_iter=2000, restart=100)
+        w, ti = op.solve_fgmres(bt, net, tol=1e-8, max_iter=2000, restart=100)
+        say(f"seed {seed}: validation {vi.iterations} steps (fallback {vi.fallback}), target {ti.iterations} "
+            f"steps (fallback {ti.fallback}), jacobi {vj.iterations}/{ij.iterations}")
+        assert vi.converged == 1 and ti.converged == 1
+        assert (torch.linalg.norm(bt - op.matvec(w)) / torch.linalg.norm(bt)).item() <= 1e-8
+        if vi.fallback == 0 and vi.iterations < best_v:
+            expect, best_v = k, vi.iterations
+    w, kept, isel = op.solve_fgmres_select(nets, bv, bt, tol=1e-8, max_iter=2000, restart=100)
+    say(f"kept {kept} (expected {expect}): {isel.iterations} steps, jacobi {ij.iterations}")
+    assert kept == expect
+    assert isel.converged == 1 and isel.iterations <= ij.iterations + 5
     assert (torch.linalg.norm(bt - op.matvec(w)) / torch.linalg.norm(bt)).item() <= 1e-8
+    # no candidates: Jacobi, identical to the plain solve
+    w0, kept0, i0 = op.solve_fgmres_select([], bv, bt, tol=1e-8, max_iter=2000, restart=100)
+    assert kept0 == -1 and i0.iterations == ij.iterations and i0.fallback == 0

@@ -42,7 +42,7 @@ def make(patches, dense=False, mode=None, **kw):
         mode = igb.IGB_DENSE if dense else igb.IGB_H2_STORED
     op = igb.Operator(g, mode=mode, device=DEV, **kw)
     okw = {k: v for k, v in kw.items() if k in ("p", "m", "q", "eta", "leaf_depth", "gauss_regular", "gauss_singular",
-                                                 "gauss_rhs")}
+                                                 "gauss_rhs", "kappa_diam")}
     if "kernel" in kw:
         okw["kernel"] = kw["kernel"]
         okw["wavenumber"] = kw.get("wavenumber", 0.0)
@@ -393,6 +393,22 @@ def test_helmholtz_h2_torus_mirrored_many_nodes(q):
     zs = rand(P.nsup, 40 + q, cplx=True)
     yz = to_np(op.matvec_super(torch.tensor(zs)))
     assert abs(zs @ ys - xs @ yz) <= 1e-12 * abs(zs @ ys)  # complex symmetric, not Hermitian
+
+
+@pytest.mark.parametrize("mode", ["stored", "onthefly"])
+def test_helmholtz_h2_torus_wavenumber_aware(mode):
+    """The wavenumber-aware admissibility (kappa max(diam) <= 6 at kappa = 3): the patch-level blocks
+    leave the far field, which then lies on level 1 only, and the product equals the oracle's under the
+    same option."""
+    say(f"helmholtz h2 torus k=3 p=1 m=2 q=6 kappa_diam=6 {mode}")
+    op, P = make(W.torus_patches(), mode=igb.IGB_H2_STORED if mode == "stored" else igb.IGB_H2_ONTHEFLY,
+                 kernel=igb.IGB_HELMHOLTZ, wavenumber=3.0, p=1, m=2, q=6, leaf_depth=1, eta=1.6, gauss_regular=4,
+                 kappa_diam=6.0)
+    _, far = op.partition()
+    assert len(far) > 0 and far[:, 0].min() >= 1
+    P.h2_assemble(store_coupling=True)
+    xs = rand(P.nsup, 17, cplx=True)
+    assert rel(to_np(op.matvec_super(torch.tensor(xs))), P.h2_matvec_super(xs)) < 1e-12
 
 
 # ---------------------------------------------------------------------------

@@ -191,3 +191,25 @@ def test_golden_sphere_solution_is_accurate():
     cfg = W.config_sphere_h2()
     exact = W.laplace_charge_field(cfg["eval_points"], *cfg["charges"])
     assert np.abs(u - exact).max() < 1e-7
+
+
+def test_wavenumber_aware_admissibility_restores_accuracy():
+    """At kappa = 8 on the unit sphere the patch-sized clusters span about two wavelengths and the
+    wavenumber-blind rule of Sec. 4.2 interpolates the oscillating kernel across them (error 5e-3 at q=6).
+    The option kappa max(diam) <= c keeps such blocks out of the far field: c=8 admits clusters of a
+    quarter patch and gains more than a factor 10; c=4 admits none at this level and the H2 product is the
+    dense one up to rounding (no interpolation left)."""
+    k = 8.0
+    Pd = oracle.Problem(SPH, kernel=oracle.HELMHOLTZ, wavenumber=k, p=0, m=3, q=2, gauss_regular=4)
+    A = Pd.dense_super()
+    rng = np.random.default_rng(6)
+    x = rng.standard_normal(Pd.nsup) + 1j * rng.standard_normal(Pd.nsup)
+    y = A @ x
+    err, nfar = {}, {}
+    for c in (0.0, 8.0, 4.0):
+        P = oracle.Problem(SPH, kernel=oracle.HELMHOLTZ, wavenumber=k, p=0, m=3, q=6, leaf_depth=1, eta=1.6,
+                           gauss_regular=4, kappa_diam=c)
+        err[c] = np.linalg.norm(P.h2_matvec_super(x) - y) / np.linalg.norm(y)
+        nfar[c] = P.nfar
+    assert err[0.0] > 1e-3 and err[8.0] < 0.1 * err[0.0]
+    assert nfar[8.0] > nfar[0.0] and nfar[4.0] == 0 and err[4.0] < 1e-14

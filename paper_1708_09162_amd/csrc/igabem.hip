@@ -1564,10 +1564,15 @@ __device__ inline void far_sym_chunk(const FarSymArgs &F, int64_t k0, int64_t k1
                     const R d0 = tx[ii] - sx, d1 = ty[ii] - sy, d2 = tz[ii] - sz;
                     R gr, gi;
                     helm_far_value<RAW, TAB>(d0 * d0 + d1 * d1 + d2 * d2, kap, gr, gi, tab);
-                    ar[ii] += gr * swr - gi * swi;
-                    ai[ii] += gr * swi + gi * swr;
-                    pr_ += gr * wr[ii] - gi * wi[ii];
-                    pi_ += gr * wi[ii] + gi * wr[ii];
+                    // two fused multiply-adds per real accumulation
+                    ar[ii] = fma(gr, swr, ar[ii]);
+                    ar[ii] = fma(-gi, swi, ar[ii]);
+                    ai[ii] = fma(gr, swi, ai[ii]);
+                    ai[ii] = fma(gi, swr, ai[ii]);
+                    pr_ = fma(gr, wr[ii], pr_);
+                    pr_ = fma(-gi, wi[ii], pr_);
+                    pi_ = fma(gr, wi[ii], pi_);
+                    pi_ = fma(gi, wr[ii], pi_);
                 }
                 pr_ = group8_sum(pr_);
                 pi_ = group8_sum(pi_);

@@ -33,10 +33,10 @@ __host__ __device__ inline double abs2(cd a) { return a.re * a.re + a.im * a.im;
 // checks kappa times the size of the geometry at creation).  Branch-free.
 //  * Range reduction after Cody and Waite: t = n pi + y with n the integer nearest t/pi, |y| <= pi/2 up
 //    to rounding.  n comes from adding 1.5 2^52 in the fused multiply-add t (1/pi) + 1.5 2^52, whose
-//    result has unit spacing, so its lowest mantissa bit is the parity of n.  pi = C1 + C2 + C3 with C1
-//    and C2 of 30 significant bits, so n C1 and n C2 are exact for |n| < 2^23; t - n C1 is exact as well
-//    (both are multiples of 2^-32 and differ by less than 2), and the two further fused steps round once
-//    each.
+//    result has unit spacing, so its lowest mantissa bit is the parity of n.  pi = C1 + C2 with C1 of 30
+//    significant bits, so n C1 is exact for |n| < 2^23 and t - n C1 is exact as well (Sterbenz: n C1 is
+//    within a factor two of t for n != 0); C2 is the rest rounded to 53 bits and enters by one fused
+//    multiply-add, which rounds once and leaves |n (pi - C1 - C2)| < 6e-21.
 //  * On |y| <= pi/2 the Taylor series of sin (through y^21) and of cos (through y^20), evaluated by
 //    Horner's rule in z = y^2; the first omitted terms, (pi/2)^23/23! and (pi/2)^22/22!, are below 2^-55.
 //  * sin(n pi + y) = (-1)^n sin y and cos(n pi + y) = (-1)^n cos y: the parity of n flips both sign bits.
@@ -45,8 +45,7 @@ __host__ __device__ inline void sincos_red(double t, double *sn, double *cs)
     const double m = fma(t, 0x1.45f306dc9c883p-2, 0x1.8p52);  // t (1/pi) + 1.5 2^52
     const double n = m - 0x1.8p52;
     double y = fma(-n, 0x1.921fb548p+1, t);            // C1
-    y = fma(-n, -0x1.de973dc8p-30, y);                 // C2
-    y = fma(-n, -0x1.9d9cceba3f91fp-61, y);            // C3
+    y = fma(-n, -0x1.de973dcb3b39ap-30, y);            // C2
     const double z = y * y;
     double ps = 0x1.71b8ef6dcf572p-66;                 //  1/21!
     ps = fma(ps, z, -0x1.2f49b46814157p-57);           // -1/19!
@@ -75,17 +74,17 @@ __host__ __device__ inline void sincos_red(double t, double *sn, double *cs)
 }
 
 // sin t and cos t for 0 <= t <= 2^19 from a table tab[2 j] = sin(j pi/64), tab[2 j + 1] = cos(j pi/64),
-// j < 128 (one period): t = n pi/64 + y with |y| <= pi/128 (Cody-Waite reduction, pi/64 split into two
-// 29-bit parts, so that n C1 and n C2 are exact for n < 2^24, and a rounded remainder), sin y and cos y by
-// their Taylor series through y^7 and y^6 (truncation below 4e-18), then the angle-sum formulas with
-// entry j = n mod 128.  Eighteen double operations against thirty for sincos_red.
+// j < 128 (one period): t = n pi/64 + y with |y| <= pi/128 (Cody-Waite reduction with pi/64 = C1 + C2:
+// C1 has 29 bits, so n C1 is exact for n < 2^24 and t - n C1 is exact by Sterbenz; C2 is the rest rounded
+// to 53 bits and enters by one fused multiply-add, leaving |n (pi/64 - C1 - C2)| < 6e-21), sin y and cos y
+// by their Taylor series through y^7 and y^6 (truncation below 4e-18), then the angle-sum formulas with
+// entry j = n mod 128.  Seventeen double operations against twenty-nine for sincos_red.
 __device__ inline void sincos_tab(double t, const double *tab, double *sn, double *cs)
 {
     const double m = fma(t, 0x1.45f306dc9c883p+4, 0x1.8p52);  // t (64/pi) + 1.5 2^52: n in the low bits
     const double n = m - 0x1.8p52;
     double y = fma(-n, 0x1.921fb54p-5, t);
-    y = fma(-n, 0x1.10b4612p-35, y);
-    y = fma(-n, -0x1.676733ae8fe48p-65, y);
+    y = fma(-n, 0x1.10b4611a62633p-35, y);
     const int j = (int)(__builtin_bit_cast(unsigned long long, m) & 127u);
     const double sa = tab[2 * j], ca = tab[2 * j + 1];
     const double z = y * y;

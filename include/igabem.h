@@ -319,8 +319,11 @@ igb_status igb_solve_fgmres_select(const igb_operator *op, const igb_cnn *const 
  * b_devs[i], w_devs[i] (same rel_tol, max_iter, restart for all).  Solve i
  * runs on operator i's stream, driven by one of up to 16 host threads, so
  * instances given their own streams overlap on the GPU (instances sharing a
- * stream run one after another, still correct).  The operators must be
- * distinct (IGB_EINVAL otherwise: a solve uses its operator's buffers).
+ * stream run one after another, still correct).  An operator may appear in
+ * several entries (several right-hand sides of one problem): its entries are
+ * solved one after another in list order by one thread, since a solve uses
+ * its operator's buffers; distinct operators run concurrently.  Every entry
+ * needs its own w_dev (IGB_EINVAL otherwise).
  * infos (host, n entries) may be NULL.  Returns IGB_OK, or the most severe
  * status of any instance with its index in igb_last_error().  Synchronous.
  * This batches whole solves over streams; it is not a single fused launch. */

@@ -146,6 +146,115 @@ __global__ void __launch_bounds__(256) k_conv3(const float *__restrict__ in, con
     }
 }
 
+// ---------------------------------------------------------------------------
+// The 32 -> 32 channel layers on the matrix cores (v_mfma_f32_16x16x32_bf16: D = A B + C with A 16 x 32,
+// B 32 x 16, FP32 C and D; lane l holds A[l % 16][8 (l / 16) + j] and B[8 (l / 16) + j][l % 16], j < 8,
+// and D[4 (l / 16) + i][l % 16], i < 4).  The weights are BF16 already; an FP32 value v enters as
+// three BF16 terms, hi = bf16(v), mid = bf16(v - hi), lo = bf16(v - hi - mid), with hi + mid + lo = v
+// exactly (each rounding to nearest removes at least eight of the 24 significant bits).  Their products
+// with a BF16 weight are exact in FP32, so a convolution differs from FP32 arithmetic only in the order
+// of the FP32 additions.
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef float f4_t __attribute__((ext_vector_type(4)));
+
+__device__ inline f4_t mfma_bf16(const uint4 &a, const uint4 &b, const f4_t &c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8_t, a), __builtin_bit_cast(bf16x8_t, b),
+                                                   c, 0, 0, 0);
+}
+
+// the three BF16 terms of v
+__device__ inline void split_bf16(float v, uint16_t &hi, uint16_t &mid, uint16_t &lo)
+{
+    hi = float_to_bf16(v);
+    const float r = v - bf16_to_float(hi);
+    mid = float_to_bf16(r);
+    lo = float_to_bf16(r - bf16_to_float(mid));
+}
+
+constexpr int kMT = 16;               // convolution output tile: 16 x 16 pixels per workgroup
+constexpr int kMS = kMT + 2;          // staged input side (one pixel of halo)
+constexpr int kMPS = 40;              // LDS stride of a staged pixel in BF16: 32 channels + 8 padding, so
+                                      // 16 lanes reading 16 bytes at consecutive pixels hit distinct banks
+
+// MFMA operand order of a 32 -> 32 layer: wm[((t * 2 + mt) * 64 + lane) * 8 + j] =
+// w[co = 16 mt + lane % 16][ci = 8 (lane / 16) + j][t] (w in the [co][ci][t] layout of wb or wt).
+__global__ void k_pack_mfma(const uint16_t *__restrict__ w, uint16_t *__restrict__ wm)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= 9 * kC * kC) return;
+    const int j = i % 8, lane = (i / 8) % 64, mt = (i / 512) % 2, t = i / 1024;
+    const int co = 16 * mt + lane % 16, ci = 8 * (lane / 16) + j;
+    wm[i] = w[(co * kC + ci) * 9 + t];
+}
+
+// out[n][co][y][x] = sum_ci sum_t w[co][ci][t] a[n][ci][y + dy - 1][x + dx - 1] for 32 channels in and
+// out, as k_conv3<32, 32, RELU_IN, MASK_OUT>.  Workgroup: one 16 x 16 output tile of one image; the
+// input tile with its halo is staged in LDS as hi, mid and lo planes, pixel-major with the 32 channels
+// innermost.  Wave w takes output rows w, w + 4, w + 8, w + 12: per tap and row, six MFMAs (two halves
+// of the output channels times the three terms) on A = the tap's weights (from wm, in operand order) and
+// B = 16 pixels x 32 channels read straight from the staged tile.
+template <bool RELU_IN, bool MASK_OUT>
+__global__ void __launch_bounds__(256) k_conv3_mfma(const float *__restrict__ in, const uint4 *__restrict__ wm,
+                                                    float *__restrict__ out, const float *__restrict__ mask, int H,
+                                                    int W, int tiles_x)
+{
+    __shared__ __attribute__((aligned(16))) uint16_t xs[3][kMS * kMS * kMPS];
+    const int n = blockIdx.y;
+    const int ty0 = (blockIdx.x / tiles_x) * kMT, tx0 = (blockIdx.x % tiles_x) * kMT;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const size_t plane = (size_t)H * W;
+    for (int i = tid; i < kC * kMS * kMS; i += 256) {
+        const int c = i / (kMS * kMS), r = i % (kMS * kMS);
+        const int y = ty0 + r / kMS - 1, x = tx0 + r % kMS - 1;
+        float v = 0.f;
+        if (y >= 0 && y < H && x >= 0 && x < W) {
+            v = in[((size_t)n * kC + c) * plane + (size_t)y * W + x];
+            if (RELU_IN) v = fmaxf(v, 0.f);
+        }
+        uint16_t h, md, l;
+        split_bf16(v, h, md, l);
+        xs[0][r * kMPS + c] = h;
+        xs[1][r * kMPS + c] = md;
+        xs[2][r * kMPS + c] = l;
+    }
+    __syncthreads();
+    const int pn = lane & 15, kq = lane >> 4;
+    f4_t acc[4][2];
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr) acc[rr][0] = acc[rr][1] = f4_t{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 1
+    for (int t = 0; t < 9; ++t) {
+        const int dy = t / 3, dx = t % 3;
+        const uint4 a0 = wm[(t * 2) * 64 + lane], a1 = wm[(t * 2 + 1) * 64 + lane];
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr) {
+            const int off = ((wave + 4 * rr + dy) * kMS + pn + dx) * kMPS + 8 * kq;
+#pragma unroll
+            for (int pl = 0; pl < 3; ++pl) {
+                const uint4 b = *(const uint4 *)&xs[pl][off];
+                acc[rr][0] = mfma_bf16(a0, b, acc[rr][0]);
+                acc[rr][1] = mfma_bf16(a1, b, acc[rr][1]);
+            }
+        }
+    }
+    const int x = tx0 + pn;
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr) {
+        const int y = ty0 + wave + 4 * rr;
+        if (y >= H || x >= W) continue;
+#pragma unroll
+        for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const size_t o = ((size_t)n * kC + 16 * mt + 4 * kq + i) * plane + (size_t)y * W + x;
+                float v = acc[rr][mt][i];
+                if (MASK_OUT && !(mask[o] > 0.f)) v = 0.f;
+                out[o] = v;
+            }
+    }
+}
+
 // Weight gradient of one layer: g[co][ci][t] = sum_{n,p} dz[n][co][p] a[n][ci][p + o_t]
 // (a = relu(in) when RELU_IN), as per-block partial sums part[block][co][ci][t];
 // block b takes the 8 x 16 pixel tiles b, b + gridDim.x, ...
@@ -213,6 +322,115 @@ __global__ void __launch_bounds__(256) k_wgrad3(const float *__restrict__ in, co
 #pragma unroll
             for (int t = 0; t < 9; ++t) part[(size_t)blockIdx.x * NP * 9 + (size_t)k * 9 + t] = acc[j][t];
     }
+}
+
+constexpr int kWR = 4, kWC = 32;                     // weight-gradient tile: 4 rows x 32 columns
+constexpr int kDZS = kWR * kWC + 8;                  // LDS stride of one channel of dz (BF16, padded)
+constexpr int kASW = kWC + 8;                        // staged activation columns: x0 - 1 .. x0 + 38
+constexpr int kAS = (kWR + 2) * kASW + 8;            // LDS stride of one channel of the activation
+
+// (d0..d3, d4..d7) as 16 BF16 values; the 8 starting at element s (0..2)
+__device__ inline uint4 shift_bf16(const uint4 &a, const uint4 &b, int s)
+{
+    auto fun = [](uint32_t lo, uint32_t hi) { return (uint32_t)((((uint64_t)hi << 32) | lo) >> 16); };
+    if (s == 0) return a;
+    if (s == 2) return uint4{a.y, a.z, a.w, b.x};
+    return uint4{fun(a.x, a.y), fun(a.y, a.z), fun(a.z, a.w), fun(a.w, b.x)};
+}
+
+// Weight gradient of a 32 -> 32 layer on the matrix cores, as k_wgrad3<32, 32, RELU_IN>:
+// g[co][ci][t] = sum over images and pixels p of dz[co][p] a[ci][p + o_t], one 32 x 32 product per tap
+// with the pixels as the reduction.  Workgroup b takes the 4 x 32 pixel tiles b, b + gridDim.x, ...;
+// dz (rows of the tile) and a (with a one-pixel halo) are staged in LDS as hi, mid and lo planes,
+// channel by channel with the columns innermost.  Wave w owns the 16 x 16 block (co half w / 2, ci half
+// w % 2) of all nine taps.  Per staged activation row s it reads the 16 channels' 32 columns once (two
+// aligned 16-byte pieces per lane and term, shifted by dx in registers) and, for each dy with output row
+// s - dy in the tile, adds the six products of terms of combined order at most two (hi hi, hi mid,
+// mid hi, hi lo, lo hi, mid mid) for dx = 0, 1, 2; the three left out are below 2^-23 of the product.
+// Partial sums per workgroup as k_wgrad3's, reduced by k_wreduce.
+template <bool RELU_IN>
+__global__ void __launch_bounds__(256) k_wgrad3_mfma(const float *__restrict__ in, const float *__restrict__ dz,
+                                                     float *__restrict__ part, int H, int W, int tiles_x,
+                                                     int64_t tiles_per_img, int64_t ntiles)
+{
+    __shared__ __attribute__((aligned(16))) uint16_t ds[3][kC * kDZS];
+    __shared__ __attribute__((aligned(16))) uint16_t as[3][kC * kAS];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int mt = wave >> 1, nt = wave & 1, li = lane & 15, h = lane >> 4;
+    const size_t plane = (size_t)H * W;
+    f4_t acc[9];
+#pragma unroll
+    for (int t = 0; t < 9; ++t) acc[t] = f4_t{0.f, 0.f, 0.f, 0.f};
+    for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const int n = (int)(tile / tiles_per_img);
+        const int r = (int)(tile % tiles_per_img);
+        const int y0 = (r / tiles_x) * kWR, x0 = (r % tiles_x) * kWC;
+        __syncthreads();
+        for (int i = tid; i < kC * kWR * kWC; i += 256) {
+            const int c = i / (kWR * kWC), pp = i % (kWR * kWC);
+            const int y = y0 + pp / kWC, x = x0 + pp % kWC;
+            const float v = (y < H && x < W) ? dz[((size_t)n * kC + c) * plane + (size_t)y * W + x] : 0.f;
+            uint16_t hi, md, lo;
+            split_bf16(v, hi, md, lo);
+            ds[0][c * kDZS + pp] = hi;
+            ds[1][c * kDZS + pp] = md;
+            ds[2][c * kDZS + pp] = lo;
+        }
+        for (int i = tid; i < kC * (kWR + 2) * kASW; i += 256) {
+            const int c = i / ((kWR + 2) * kASW), pp = i % ((kWR + 2) * kASW);
+            const int y = y0 + pp / kASW - 1, x = x0 + pp % kASW - 1;
+            float v = 0.f;
+            if (y >= 0 && y < H && x >= 0 && x < W) {
+                v = in[((size_t)n * kC + c) * plane + (size_t)y * W + x];
+                if (RELU_IN) v = fmaxf(v, 0.f);
+            }
+            uint16_t hi, md, lo;
+            split_bf16(v, hi, md, lo);
+            as[0][c * kAS + pp] = hi;
+            as[1][c * kAS + pp] = md;
+            as[2][c * kAS + pp] = lo;
+        }
+        __syncthreads();
+        const int co = 16 * mt + li, ci = 16 * nt + li;
+#pragma unroll 1
+        for (int sr = 0; sr < kWR + 2; ++sr) {
+            uint4 b[3][3];  // [term][dx]
+#pragma unroll
+            for (int pl = 0; pl < 3; ++pl) {
+                const uint16_t *src = &as[pl][ci * kAS + sr * kASW + 8 * h];
+                const uint4 c0 = *(const uint4 *)src, c1 = *(const uint4 *)(src + 8);
+#pragma unroll
+                for (int dx = 0; dx < 3; ++dx) b[pl][dx] = shift_bf16(c0, c1, dx);
+            }
+#pragma unroll
+            for (int dy = 0; dy < 3; ++dy) {
+                const int orow = sr - dy;
+                if (orow < 0 || orow >= kWR) continue;
+                uint4 a[3];
+#pragma unroll
+                for (int pl = 0; pl < 3; ++pl) a[pl] = *(const uint4 *)&ds[pl][co * kDZS + orow * kWC + 8 * h];
+#pragma unroll
+                for (int dx = 0; dx < 3; ++dx) {
+                    f4_t c = acc[dy * 3 + dx];
+                    c = mfma_bf16(a[0], b[0][dx], c);
+                    c = mfma_bf16(a[0], b[1][dx], c);
+                    c = mfma_bf16(a[1], b[0][dx], c);
+                    c = mfma_bf16(a[0], b[2][dx], c);
+                    c = mfma_bf16(a[2], b[0][dx], c);
+                    c = mfma_bf16(a[1], b[1][dx], c);
+                    acc[dy * 3 + dx] = c;
+                }
+            }
+        }
+    }
+    // D[m][n]: m = co within the half (4 (lane / 16) + i), n = ci within the half (lane % 16)
+#pragma unroll
+    for (int t = 0; t < 9; ++t)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int co = 16 * mt + 4 * h + i, ci = 16 * nt + li;
+            part[(size_t)blockIdx.x * kC * kC * 9 + ((size_t)co * kC + ci) * 9 + t] = acc[t][i];
+        }
 }
 
 // g[i] = sum over blocks b of part[b][i] in a fixed order: 32 weights per workgroup, 8 groups of
@@ -315,6 +533,7 @@ struct igb_cnn {
     int64_t nw = 0;
     float *w = nullptr, *g = nullptr, *m = nullptr, *v = nullptr, *part = nullptr;
     uint16_t *wb = nullptr, *wt = nullptr;
+    uint16_t *wm = nullptr, *wtm = nullptr;  // the 32 -> 32 layers 1..3 in MFMA operand order (forward, backward)
     double *lpart = nullptr;
     int64_t step = 0;
     int64_t cap = 0;                   // pixels per activation buffer
@@ -361,6 +580,18 @@ igb_status ensure(igb_cnn *net, int64_t npix)
     return IGB_OK;
 }
 
+// 32 -> 32 layers: wm holds the layer's weights in MFMA operand order
+template <bool RELU_IN, bool MASK_OUT>
+igb_status conv_mfma(const igb_cnn *net, const float *in, const uint16_t *wm, float *out, const float *mask, int nimg,
+                     int H, int W)
+{
+    const int tx = (W + kMT - 1) / kMT, ty = (H + kMT - 1) / kMT;
+    hipLaunchKernelGGL((k_conv3_mfma<RELU_IN, MASK_OUT>), dim3((unsigned)(tx * ty), (unsigned)nimg), dim3(256), 0,
+                       net->st, in, (const uint4 *)wm, out, mask, H, W, tx);
+    CNNLAUNCH();
+    return IGB_OK;
+}
+
 template <int CIN, int COUT, bool RELU_IN, bool MASK_OUT>
 igb_status conv(const igb_cnn *net, const float *in, const uint16_t *w, float *out, const float *mask, int nimg, int H,
                 int W)
@@ -376,11 +607,17 @@ igb_status conv(const igb_cnn *net, const float *in, const uint16_t *w, float *o
 template <int CIN, int COUT, bool RELU_IN>
 igb_status wgrad(igb_cnn *net, int layer, const float *in, const float *dz, int nimg, int H, int W)
 {
-    const int tx = (W + kGTW - 1) / kGTW, ty = (H + kGTH - 1) / kGTH;
+    const bool mfma = CIN == kC && COUT == kC;
+    const int tx = mfma ? (W + kWC - 1) / kWC : (W + kGTW - 1) / kGTW;
+    const int ty = mfma ? (H + kWR - 1) / kWR : (H + kGTH - 1) / kGTH;
     const int64_t tpi = (int64_t)tx * ty, nt = tpi * nimg;
     const int nb = (int)std::min<int64_t>(kGBlocks, nt);
-    hipLaunchKernelGGL((k_wgrad3<CIN, COUT, RELU_IN>), dim3((unsigned)nb), dim3(256), 0, net->st, in, dz, net->part, H, W,
-                       tx, tpi, nt);
+    if constexpr (CIN == kC && COUT == kC)
+        hipLaunchKernelGGL((k_wgrad3_mfma<RELU_IN>), dim3((unsigned)nb), dim3(256), 0, net->st, in, dz, net->part, H, W,
+                           tx, tpi, nt);
+    else
+        hipLaunchKernelGGL((k_wgrad3<CIN, COUT, RELU_IN>), dim3((unsigned)nb), dim3(256), 0, net->st, in, dz, net->part,
+                           H, W, tx, tpi, nt);
     CNNLAUNCH();
     const int cnt = 9 * CIN * COUT;
     hipLaunchKernelGGL(k_wreduce, dim3(nblk(cnt, 32)), dim3(256), 0, net->st, nb, cnt, (const float *)net->part,
@@ -396,9 +633,11 @@ igb_status forward_t(const igb_cnn *net, const float *in, int nimg, int H, int W
     igb_status rc;
     const int64_t *o = net->dims.off;
     if ((rc = conv<1, kC, false, false>(net, in, net->wb + o[0], net->z[0], nullptr, nimg, H, W))) return rc;
-    if ((rc = conv<kC, kC, ACT, false>(net, net->z[0], net->wb + o[1], net->z[1], nullptr, nimg, H, W))) return rc;
-    if ((rc = conv<kC, kC, ACT, false>(net, net->z[1], net->wb + o[2], net->z[2], nullptr, nimg, H, W))) return rc;
-    if ((rc = conv<kC, kC, ACT, false>(net, net->z[2], net->wb + o[3], net->z[3], nullptr, nimg, H, W))) return rc;
+    constexpr int64_t L = 9 * kC * kC;  // weights of one 32 -> 32 layer
+    (void)o;
+    if ((rc = conv_mfma<ACT, false>(net, net->z[0], net->wm, net->z[1], nullptr, nimg, H, W))) return rc;
+    if ((rc = conv_mfma<ACT, false>(net, net->z[1], net->wm + L, net->z[2], nullptr, nimg, H, W))) return rc;
+    if ((rc = conv_mfma<ACT, false>(net, net->z[2], net->wm + 2 * L, net->z[3], nullptr, nimg, H, W))) return rc;
     return conv<kC, 1, ACT, false>(net, net->z[3], net->wb + o[4], net->f, nullptr, nimg, H, W);
 }
 
@@ -418,11 +657,12 @@ igb_status backward_t(igb_cnn *net, const float *in, int nimg, int H, int W)
     if ((rc = wgrad<kC, 1, ACT>(net, 4, z[3], net->d1, nimg, H, W))) return rc;
     if ((rc = conv<1, kC, false, ACT>(net, net->d1, wt + o[4], net->da, z[3], nimg, H, W))) return rc;
     if ((rc = wgrad<kC, kC, ACT>(net, 3, z[2], net->da, nimg, H, W))) return rc;
-    if ((rc = conv<kC, kC, false, ACT>(net, net->da, wt + o[3], net->db, z[2], nimg, H, W))) return rc;
+    constexpr int64_t L = 9 * kC * kC;
+    if ((rc = conv_mfma<false, ACT>(net, net->da, net->wtm + 2 * L, net->db, z[2], nimg, H, W))) return rc;
     if ((rc = wgrad<kC, kC, ACT>(net, 2, z[1], net->db, nimg, H, W))) return rc;
-    if ((rc = conv<kC, kC, false, ACT>(net, net->db, wt + o[2], net->da, z[1], nimg, H, W))) return rc;
+    if ((rc = conv_mfma<false, ACT>(net, net->db, net->wtm + L, net->da, z[1], nimg, H, W))) return rc;
     if ((rc = wgrad<kC, kC, ACT>(net, 1, z[0], net->da, nimg, H, W))) return rc;
-    if ((rc = conv<kC, kC, false, ACT>(net, net->da, wt + o[1], net->db, z[0], nimg, H, W))) return rc;
+    if ((rc = conv_mfma<false, ACT>(net, net->da, net->wtm, net->db, z[0], nimg, H, W))) return rc;
     return wgrad<1, kC, false>(net, 0, in, net->db, nimg, H, W);
 }
 
@@ -456,6 +696,14 @@ igb_status pack(igb_cnn *net)
 {
     hipLaunchKernelGGL(k_pack, dim3(nblk(net->nw, 256)), dim3(256), 0, net->st, net->dims, net->nw, (const float *)net->w,
                        net->wb, net->wt);
+    CNNLAUNCH();
+    for (int l = 1; l <= 3; ++l) {
+        const int64_t L = 9 * kC * kC;
+        hipLaunchKernelGGL(k_pack_mfma, dim3(nblk(L, 256)), dim3(256), 0, net->st, (const uint16_t *)net->wb + net->dims.off[l],
+                           net->wm + (l - 1) * L);
+        hipLaunchKernelGGL(k_pack_mfma, dim3(nblk(L, 256)), dim3(256), 0, net->st, (const uint16_t *)net->wt + net->dims.off[l],
+                           net->wtm + (l - 1) * L);
+    }
     CNNLAUNCH();
     return IGB_OK;
 }
@@ -564,6 +812,8 @@ igb_status igb_cnn_create(const float *weights_host, int32_t activation, void *h
                    std::make_pair((void **)&net->m, fb), std::make_pair((void **)&net->v, fb),
                    std::make_pair((void **)&net->wb, net->nw * sizeof(uint16_t)),
                    std::make_pair((void **)&net->wt, net->nw * sizeof(uint16_t)),
+                   std::make_pair((void **)&net->wm, (size_t)3 * 9 * kC * kC * sizeof(uint16_t)),
+                   std::make_pair((void **)&net->wtm, (size_t)3 * 9 * kC * kC * sizeof(uint16_t)),
                    std::make_pair((void **)&net->part, (size_t)kGBlocks * 9 * kC * kC * sizeof(float)),
                    std::make_pair((void **)&net->lpart, kLossBlocks * sizeof(double))})
         if (e == hipSuccess) e = hipMalloc(a.first, a.second);
@@ -586,7 +836,7 @@ void igb_cnn_destroy(igb_cnn *net)
     (void)hipStreamSynchronize(net->st);
     free_acts(net);
     for (void *p : {(void *)net->w, (void *)net->g, (void *)net->m, (void *)net->v, (void *)net->wb, (void *)net->wt,
-                    (void *)net->part, (void *)net->lpart})
+                    (void *)net->wm, (void *)net->wtm, (void *)net->part, (void *)net->lpart})
         if (p) (void)hipFree(p);
     delete net;
 }

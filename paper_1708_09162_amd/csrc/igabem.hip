@@ -4396,35 +4396,46 @@ igb_status igb_solve_many(int32_t n, igb_operator *const *ops, const void *const
     if (n < 0) return fail(IGB_EINVAL, "n must be >= 0");
     if (n > 0 && (!ops || !b_devs || !w_devs)) return fail(IGB_EINVAL, "null argument");
     if (!(rel_tol > 0.0) || max_iter < 0) return fail(IGB_EINVAL, "rel_tol must be > 0 and max_iter >= 0");
-    std::set<const igb_operator *> seen;
+    // entries of one operator form a group, solved one after another in list order (a solve uses its
+    // operator's buffers); groups run concurrently
+    std::vector<std::vector<int32_t>> groups;
+    std::map<const igb_operator *, size_t> gid;
     for (int32_t i = 0; i < n; ++i) {
         if (!ops[i] || !b_devs[i] || !w_devs[i]) return fail(IGB_EINVAL, "null operator or vector at " + std::to_string(i));
-        if (!seen.insert(ops[i]).second)
-            return fail(IGB_EINVAL, "operator " + std::to_string(i) + " appears twice (its buffers would be shared)");
         if (ops[i]->cplx && restart < 1) return fail(IGB_EINVAL, "restart must be >= 1");
+        auto it = gid.emplace(ops[i], groups.size());
+        if (it.second) groups.emplace_back();
+        groups[it.first->second].push_back(i);
     }
+    for (int32_t i = 0; i < n; ++i)
+        for (int32_t j = 0; j < n; ++j)
+            if (w_devs[i] == w_devs[j] && i != j) return fail(IGB_EINVAL, "entries " + std::to_string(i) + " and " +
+                                                                              std::to_string(j) + " share a solution vector");
     int dev = 0;
     HIPCHK(hipGetDevice(&dev));
     std::vector<igb_status> st(n, IGB_OK);
     std::vector<std::string> msg(n);
+    const int ng = (int)groups.size();
     std::atomic<int> next{0};
     auto worker = [&]() {
         if (hipSetDevice(dev) != hipSuccess) return;
         for (;;) {
-            const int i = next.fetch_add(1);
-            if (i >= n) break;
-            igb_solve_info inf{};
-            try {
-                st[i] = igb_solve(ops[i], b_devs[i], w_devs[i], rel_tol, max_iter, restart, &inf);
-                if (st[i] != IGB_OK) msg[i] = g_err;
-            } catch (const std::exception &ex) {  // nothing may escape a worker thread
-                st[i] = IGB_ENOMEM;
-                msg[i] = std::string("host exception: ") + ex.what();
+            const int gi = next.fetch_add(1);
+            if (gi >= ng) break;
+            for (const int32_t i : groups[gi]) {
+                igb_solve_info inf{};
+                try {
+                    st[i] = igb_solve(ops[i], b_devs[i], w_devs[i], rel_tol, max_iter, restart, &inf);
+                    if (st[i] != IGB_OK) msg[i] = g_err;
+                } catch (const std::exception &ex) {  // nothing may escape a worker thread
+                    st[i] = IGB_ENOMEM;
+                    msg[i] = std::string("host exception: ") + ex.what();
+                }
+                if (infos) infos[i] = inf;
             }
-            if (infos) infos[i] = inf;
         }
     };
-    const int nt = std::min<int>(n, 16);
+    const int nt = std::min<int>(ng, 16);
     std::vector<std::thread> th;
     try {
         for (int t = 0; t < nt; ++t) th.emplace_back(worker);
@@ -4433,7 +4444,7 @@ igb_status igb_solve_many(int32_t n, igb_operator *const *ops, const void *const
         return fail(IGB_ENOMEM, "could not start solver threads");
     }
     for (auto &x : th) x.join();
-    if (next.load() < n) return fail(IGB_EHIP, "hipSetDevice failed in a solver thread");
+    if (next.load() < ng) return fail(IGB_EHIP, "hipSetDevice failed in a solver thread");
     igb_status worst = IGB_OK;
     int wi = -1;
     for (int32_t i = 0; i < n; ++i)

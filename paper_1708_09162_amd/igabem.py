@@ -270,11 +270,12 @@ def igb_solve_many(ops, bs, ws, rel_tol, max_iter, restart):
 
 
 def solve_many(operators, bs, tol=1e-8, max_iter=1000, restart=300):
-    """Solves the systems of several distinct operators at once (igb_solve_many); returns (densities, infos).
-    Instances overlap on the GPU when each operator was created with its own stream."""
+    """Solves the systems of several operators at once (igb_solve_many); returns (densities, infos).  An
+    operator may appear several times (several right-hand sides, solved in list order).  Instances overlap
+    on the GPU when each operator was created with its own stream."""
     ws = [op._vec(op.info.n_dof) for op in operators]
     bs = [op._in(b, op.info.n_dof) for op, b in zip(operators, bs)]
-    for op in operators:
+    for op in {id(o): o for o in operators}.values():
         op.torch.cuda.synchronize(op.device)
     infos = igb_solve_many([op.h for op in operators], bs, ws, tol, max_iter, restart)
     return ws, infos

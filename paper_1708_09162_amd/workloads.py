@@ -510,7 +510,8 @@ def config_batched(n: int = 128, seed: int = 4) -> list[dict]:
     """n independent problems (seed + i each): unit sphere or 16-patch torus, 2^m x 2^m elements per patch
     with m in {2,3,4,5}, degree p in {1,2,3}, q = 6; Laplace (data from 4 exterior point charges) or
     Helmholtz with kappa uniform in [1, 16] (data from a point source inside: sphere radius <= 0.5, torus
-    tube centre line; kappa redrawn near sphere resonances)."""
+    tube centre line; kappa redrawn near sphere resonances); 1 to 8 right-hand sides each (n_rhs; the
+    first from the fields above, the others in more_rhs)."""
     out = []
     for i in range(n):
         rng = np.random.default_rng(seed + i)
@@ -533,5 +534,19 @@ def config_batched(n: int = 128, seed: int = 4) -> list[dict]:
                 d["source"] = v / np.linalg.norm(v) * float(rng.uniform(0.0, 0.5))
         else:
             d["charges"] = point_charges(4, seed + i, rmin=3.5 if torus else 1.5, rmax=5.0 if torus else 3.0)
+        # further right-hand sides of the same problem (1..8 in all): other charges or sources
+        d["n_rhs"] = int(rng.integers(1, 9))
+        d["more_rhs"] = []
+        for r in range(1, d["n_rhs"]):
+            rr = np.random.default_rng((seed + i, r))
+            if helm and torus:
+                a = float(rr.uniform(0.0, 2.0 * np.pi))
+                d["more_rhs"].append({"source": np.array([2.0 * np.cos(a), 2.0 * np.sin(a), 0.0])})
+            elif helm:
+                v = rr.standard_normal(3)
+                d["more_rhs"].append({"source": v / np.linalg.norm(v) * float(rr.uniform(0.0, 0.5))})
+            else:
+                d["more_rhs"].append({"charges": point_charges(4, 100000 * (seed + i) + r, rmin=3.5 if torus else 1.5,
+                                                               rmax=5.0 if torus else 3.0)})
         out.append(d)
     return out

@@ -258,7 +258,8 @@ def _batch_instance(d, stream):
 
 def test_solve_many_matches_single_solves():
     """Independent instances (sphere and torus, Laplace and Helmholtz, different sizes) solved together on
-    their own streams give bit for bit the densities and step counts of one-at-a-time solves."""
+    their own streams, two of them with a second right-hand side, give bit for bit the densities and step
+    counts of one-at-a-time solves."""
     cfg = [d for d in W.config_batched(24, seed=40) if d["m"] <= 3][:6]
     assert {d["kernel"] for d in cfg} == {0, 1}
     say(f"solve_many: {[(d['geometry'], d['m'], d['p'], d['kernel']) for d in cfg]}")
@@ -270,13 +271,20 @@ def test_solve_many_matches_single_solves():
         w, info = op.solve(b, tol=1e-8, max_iter=3000, restart=300)
         torch.cuda.synchronize()
         ref.append((w.clone(), info.iterations, info.converged))
-    ws, infos = igb.solve_many(ops, bs, tol=1e-8, max_iter=3000, restart=300)
+    # a second right-hand side for two of the operators (entries of one operator run in list order)
+    extra = [(ops[0], bs[0] * 0.5 + bs[0].flip(0)), (ops[3], bs[3].flip(0))]
+    for op, b in extra:
+        w, info = op.solve(b, tol=1e-8, max_iter=3000, restart=300)
+        torch.cuda.synchronize()
+        ref.append((w.clone(), info.iterations, info.converged))
+    ws, infos = igb.solve_many(ops + [o for o, _ in extra], bs + [b for _, b in extra], tol=1e-8, max_iter=3000,
+                               restart=300)
     torch.cuda.synchronize()
     for (w_ref, it, conv), w, info in zip(ref, ws, infos):
         assert conv == 1 and info.converged == 1 and info.iterations == it
         assert torch.equal(w, w_ref)
-    with pytest.raises(igb.IgbError):
-        igb.solve_many([ops[0], ops[0]], [bs[0], bs[0]])
+    with pytest.raises(igb.IgbError):  # two entries may not share a solution vector
+        igb.igb_solve_many([ops[0].h, ops[1].h], [bs[0], bs[1]], [ws[0], ws[0]], 1e-8, 100, 30)
 
 
 def test_selected_network_against_jacobi():

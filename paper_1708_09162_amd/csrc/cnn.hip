@@ -172,6 +172,25 @@ __device__ inline void split_bf16(float v, uint16_t &hi, uint16_t &mid, uint16_t
     lo = float_to_bf16(r - bf16_to_float(mid));
 }
 
+// eight values split into three terms, each term's eight BF16 values packed in a uint4 (value j in the
+// low half of word j / 2 for even j)
+__device__ inline void split8_bf16(const float (&v)[8], uint4 &hi, uint4 &mid, uint4 &lo)
+{
+    uint32_t h[4], m[4], l[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        uint16_t h0, m0, l0, h1, m1, l1;
+        split_bf16(v[2 * k], h0, m0, l0);
+        split_bf16(v[2 * k + 1], h1, m1, l1);
+        h[k] = (uint32_t)h0 | ((uint32_t)h1 << 16);
+        m[k] = (uint32_t)m0 | ((uint32_t)m1 << 16);
+        l[k] = (uint32_t)l0 | ((uint32_t)l1 << 16);
+    }
+    hi = uint4{h[0], h[1], h[2], h[3]};
+    mid = uint4{m[0], m[1], m[2], m[3]};
+    lo = uint4{l[0], l[1], l[2], l[3]};
+}
+
 constexpr int kMT = 16;               // convolution output tile: 16 x 16 pixels per workgroup
 constexpr int kMS = kMT + 2;          // staged input side (one pixel of halo)
 constexpr int kMPS = 40;              // LDS stride of a staged pixel in BF16: 32 channels + 8 padding, so
@@ -204,19 +223,33 @@ __global__ void __launch_bounds__(256) k_conv3_mfma(const float *__restrict__ in
     const int ty0 = (blockIdx.x / tiles_x) * kMT, tx0 = (blockIdx.x % tiles_x) * kMT;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const size_t plane = (size_t)H * W;
-    for (int i = tid; i < kC * kMS * kMS; i += 256) {
-        const int c = i / (kMS * kMS), r = i % (kMS * kMS);
+    // one item = one staged pixel and eight channels (consecutive pixels over the lanes): all of a
+    // thread's loads are issued before the first use, then three 16-byte LDS writes per item
+    constexpr int NIT = (4 * kMS * kMS + 255) / 256;
+    float v[NIT][8];
+#pragma unroll
+    for (int k = 0; k < NIT; ++k) {
+        const int it = tid + 256 * k;
+        const int g = it / (kMS * kMS), r = it % (kMS * kMS);
         const int y = ty0 + r / kMS - 1, x = tx0 + r % kMS - 1;
-        float v = 0.f;
-        if (y >= 0 && y < H && x >= 0 && x < W) {
-            v = in[((size_t)n * kC + c) * plane + (size_t)y * W + x];
-            if (RELU_IN) v = fmaxf(v, 0.f);
-        }
-        uint16_t h, md, l;
-        split_bf16(v, h, md, l);
-        xs[0][r * kMPS + c] = h;
-        xs[1][r * kMPS + c] = md;
-        xs[2][r * kMPS + c] = l;
+        const bool inside = it < 4 * kMS * kMS && y >= 0 && y < H && x >= 0 && x < W;
+        const float *src = in + ((size_t)n * kC + 8 * (inside ? g : 0)) * plane + (inside ? (size_t)y * W + x : 0);
+#pragma unroll
+        for (int j = 0; j < 8; ++j) v[k][j] = inside ? src[(size_t)j * plane] : 0.f;
+    }
+#pragma unroll
+    for (int k = 0; k < NIT; ++k) {
+        const int it = tid + 256 * k;
+        if (it >= 4 * kMS * kMS) break;
+        const int g = it / (kMS * kMS), r = it % (kMS * kMS);
+        if (RELU_IN)
+#pragma unroll
+            for (int j = 0; j < 8; ++j) v[k][j] = fmaxf(v[k][j], 0.f);
+        uint4 h, md, l;
+        split8_bf16(v[k], h, md, l);
+        *(uint4 *)&xs[0][r * kMPS + 8 * g] = h;
+        *(uint4 *)&xs[1][r * kMPS + 8 * g] = md;
+        *(uint4 *)&xs[2][r * kMPS + 8 * g] = l;
     }
     __syncthreads();
     const int pn = lane & 15, kq = lane >> 4;
@@ -366,29 +399,58 @@ __global__ void __launch_bounds__(256) k_wgrad3_mfma(const float *__restrict__ i
         const int r = (int)(tile % tiles_per_img);
         const int y0 = (r / tiles_x) * kWR, x0 = (r % tiles_x) * kWC;
         __syncthreads();
-        for (int i = tid; i < kC * kWR * kWC; i += 256) {
-            const int c = i / (kWR * kWC), pp = i % (kWR * kWC);
-            const int y = y0 + pp / kWC, x = x0 + pp % kWC;
-            const float v = (y < H && x < W) ? dz[((size_t)n * kC + c) * plane + (size_t)y * W + x] : 0.f;
-            uint16_t hi, md, lo;
-            split_bf16(v, hi, md, lo);
-            ds[0][c * kDZS + pp] = hi;
-            ds[1][c * kDZS + pp] = md;
-            ds[2][c * kDZS + pp] = lo;
+        // one item = eight consecutive pixels of one row and channel; all of a thread's loads (two dz
+        // items, four activation items) are issued before the first use, then three 16-byte LDS writes
+        // per item
+        constexpr int ND = kC * kWR * (kWC / 8), NA = kC * (kWR + 2) * (kASW / 8);
+        constexpr int KD = (ND + 255) / 256, KA = (NA + 255) / 256;
+        float vd[KD][8], va[KA][8];
+#pragma unroll
+        for (int k = 0; k < KD; ++k) {
+            const int it = tid + 256 * k;
+            const int c = it / (kWR * kWC / 8), q = it % (kWR * kWC / 8);
+            const int y = y0 + q / (kWC / 8), xb = x0 + 8 * (q % (kWC / 8));
+            const bool ok = it < ND && y < H;
+            const float *src = dz + ((size_t)n * kC + (ok ? c : 0)) * plane + (size_t)(ok ? y : 0) * W;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) vd[k][j] = (ok && xb + j < W) ? src[xb + j] : 0.f;
         }
-        for (int i = tid; i < kC * (kWR + 2) * kASW; i += 256) {
-            const int c = i / ((kWR + 2) * kASW), pp = i % ((kWR + 2) * kASW);
-            const int y = y0 + pp / kASW - 1, x = x0 + pp % kASW - 1;
-            float v = 0.f;
-            if (y >= 0 && y < H && x >= 0 && x < W) {
-                v = in[((size_t)n * kC + c) * plane + (size_t)y * W + x];
-                if (RELU_IN) v = fmaxf(v, 0.f);
-            }
-            uint16_t hi, md, lo;
-            split_bf16(v, hi, md, lo);
-            as[0][c * kAS + pp] = hi;
-            as[1][c * kAS + pp] = md;
-            as[2][c * kAS + pp] = lo;
+#pragma unroll
+        for (int k = 0; k < KA; ++k) {
+            const int it = tid + 256 * k;
+            const int c = it / ((kWR + 2) * (kASW / 8)), q = it % ((kWR + 2) * (kASW / 8));
+            const int y = y0 + q / (kASW / 8) - 1, xb = x0 + 8 * (q % (kASW / 8)) - 1;
+            const bool ok = it < NA && y >= 0 && y < H;
+            const float *src = in + ((size_t)n * kC + (ok ? c : 0)) * plane + (size_t)(ok ? y : 0) * W;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) va[k][j] = (ok && xb + j >= 0 && xb + j < W) ? src[xb + j] : 0.f;
+        }
+#pragma unroll
+        for (int k = 0; k < KD; ++k) {
+            const int it = tid + 256 * k;
+            if (it >= ND) break;
+            const int c = it / (kWR * kWC / 8), q = it % (kWR * kWC / 8);
+            uint4 hi, md, lo;
+            split8_bf16(vd[k], hi, md, lo);
+            const int o = c * kDZS + 8 * q;
+            *(uint4 *)&ds[0][o] = hi;
+            *(uint4 *)&ds[1][o] = md;
+            *(uint4 *)&ds[2][o] = lo;
+        }
+#pragma unroll
+        for (int k = 0; k < KA; ++k) {
+            const int it = tid + 256 * k;
+            if (it >= NA) break;
+            const int c = it / ((kWR + 2) * (kASW / 8)), q = it % ((kWR + 2) * (kASW / 8));
+            if (RELU_IN)
+#pragma unroll
+                for (int j = 0; j < 8; ++j) va[k][j] = fmaxf(va[k][j], 0.f);
+            uint4 hi, md, lo;
+            split8_bf16(va[k], hi, md, lo);
+            const int o = c * kAS + 8 * q;
+            *(uint4 *)&as[0][o] = hi;
+            *(uint4 *)&as[1][o] = md;
+            *(uint4 *)&as[2][o] = lo;
         }
         __syncthreads();
         const int co = 16 * mt + li, ci = 16 * nt + li;

@@ -1513,7 +1513,9 @@ __device__ inline void far_sym_chunk(const FarSymArgs &F, int64_t k0, int64_t k1
 {
     using R = typename std::conditional<RAW, float, double>::type;
     constexpr int W = 8 * TT;  // padded nodes per cluster
-    constexpr int NP = (TT + 4) / 5, TH = (TT + NP - 1) / NP;
+    constexpr int NP = (TT + 4) / 5;                   // passes of at most five targets per lane
+    constexpr int THL = TT / NP, NH = TT - THL * NP;  // NH passes of THL + 1 targets, NP - NH of THL
+    constexpr int THH = NH > 0 ? THL + 1 : THL;
     double *tg = lds, *sr = lds + 5 * W;  // [x | y | z | w.re | w.im] x W each
     const int q2 = F.q2;
     const R kap = RAW ? (R)(F.kappa * 0.15915494309189535) : (R)F.kappa;  // RAW: turns per unit length
@@ -1539,18 +1541,18 @@ __device__ inline void far_sym_chunk(const FarSymArgs &F, int64_t k0, int64_t k1
         // column sums: source jj*8 + lj is owned by lane li == jj % 8 (slot jj / 8)
         R c0r = (R)0, c0i = (R)0, c1r = (R)0, c1i = (R)0;
         cd *pr = part + (size_t)(2 * k) * q2, *pc = part + (size_t)(2 * k + 1) * q2;
-#pragma unroll 1
-        for (int h = 0; h < NP; ++h) {
-            const int n_h = min(TH, TT - h * TH);  // targets in this pass
-            R tx[TH], ty[TH], tz[TH], wr[TH], wi[TH], ar[TH], ai[TH];
+        // one pass over all sources for THP targets per lane starting at t0
+        auto pass = [&](auto thp, int t0) {
+            constexpr int THP = decltype(thp)::value;
+            R tx[THP], ty[THP], tz[THP], wr[THP], wi[THP], ar[THP], ai[THP];
 #pragma unroll
-            for (int ii = 0; ii < TH; ++ii) {
-                const int i = li * TT + h * TH + min(ii, n_h - 1);  // a repeated target carries weight 0
+            for (int ii = 0; ii < THP; ++ii) {
+                const int i = li * TT + t0 + ii;
                 tx[ii] = (R)(tg[i] - cx);
                 ty[ii] = (R)(tg[W + i] - cy);
                 tz[ii] = (R)(tg[2 * W + i] - cz);
-                wr[ii] = ii < n_h ? (R)tg[3 * W + i] : (R)0;
-                wi[ii] = ii < n_h ? (R)tg[4 * W + i] : (R)0;
+                wr[ii] = (R)tg[3 * W + i];
+                wi[ii] = (R)tg[4 * W + i];
                 ar[ii] = ai[ii] = (R)0;
             }
 #pragma unroll 1
@@ -1560,7 +1562,7 @@ __device__ inline void far_sym_chunk(const FarSymArgs &F, int64_t k0, int64_t k1
                 const R swr = (R)sr[3 * W + j], swi = (R)sr[4 * W + j];
                 R pr_ = (R)0, pi_ = (R)0;
 #pragma unroll
-                for (int ii = 0; ii < TH; ++ii) {
+                for (int ii = 0; ii < THP; ++ii) {
                     const R d0 = tx[ii] - sx, d1 = ty[ii] - sy, d2 = tz[ii] - sz;
                     R gr, gi;
                     helm_far_value<RAW, TAB>(d0 * d0 + d1 * d1 + d2 * d2, kap, gr, gi, tab);
@@ -1588,16 +1590,23 @@ __device__ inline void far_sym_chunk(const FarSymArgs &F, int64_t k0, int64_t k1
             }
             // rows of this pass: reduce over the 8 lanes lj; lane lj == ii writes target ii
 #pragma unroll
-            for (int ii = 0; ii < TH; ++ii) {
+            for (int ii = 0; ii < THP; ++ii) {
                 R a = ar[ii], b = ai[ii];
 #pragma unroll
                 for (int o = 8; o < 64; o <<= 1) {
                     a += __shfl_xor(a, o);
                     b += __shfl_xor(b, o);
                 }
-                const int i = li * TT + h * TH + ii;
-                if (lj == ii && ii < n_h && i < q2) pr[i] = cd{(double)a, (double)b};
+                const int i = li * TT + t0 + ii;
+                if (lj == ii && i < q2) pr[i] = cd{(double)a, (double)b};
             }
+        };
+        // TT targets per lane in NP passes: NH of THH targets, the rest of THL = THH - 1 (no padding)
+#pragma unroll 1
+        for (int h = 0; h < NH; ++h) pass(std::integral_constant<int, THH>{}, h * THH);
+        if constexpr (THL > 0) {
+#pragma unroll 1
+            for (int h = NH; h < NP; ++h) pass(std::integral_constant<int, THL>{}, NH * THH + (h - NH) * THL);
         }
         {
             const int j0 = li * 8 + lj, j1 = (li + 8) * 8 + lj;
@@ -3923,7 +3932,8 @@ static igb_status solve_gmres_dev(igb_operator *op, const igb_cnn *net, const T 
     } events{ev};
     int it = 0;
     double rel = 0.0, prev_rel = -1.0;
-    // the network is dropped for Jacobi (the fallback) once a restart cycle fails to halve the true residual
+    // the network is dropped for Jacobi (the fallback) once a restart cycle fails to cut the true residual
+    // tenfold
     const igb_cnn *pnet = net;
     int fell_back = 0;
     for (;;) {
@@ -3936,7 +3946,7 @@ static igb_status solve_gmres_dev(igb_operator *op, const igb_cnn *net, const T 
         if ((rc = norm2(r, &beta2))) return rc;
         const double beta = std::sqrt(beta2);
         rel = beta / bn;
-        if (pnet && prev_rel > 0.0 && rel > 0.5 * prev_rel) {
+        if (pnet && prev_rel > 0.0 && rel > 0.1 * prev_rel) {
             pnet = nullptr;
             fell_back = 1;
         }

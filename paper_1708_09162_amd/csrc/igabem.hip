@@ -1156,15 +1156,31 @@ __device__ inline void near_sym_wave(const NearSymArgs &N, int64_t k, const T *_
     }
 }
 
+// one block entry, widened to the type of the sums
+__device__ inline cd load1(const cd *p)
+{
+    const v2d w = *(const v2d *)p;
+    return cd{w.x, w.y};
+}
+__device__ inline cd load1(const cf *p)
+{
+    const cf w = *p;
+    return cd{(double)w.re, (double)w.im};
+}
+__device__ inline double load1(const double *p) { return *p; }
+
 // One stored near block k by one whole wave, without LDS (nl <= 64 S): lane
-// l = 8 lj + li owns rows rt + 8 li .. rt + 8 li + 7 of every 64-row tile and
-// the columns c = lj + 8 kc.  A lane's 8 rows are consecutive in the column-major
-// block, so the 8 lanes of a group read 64 consecutive rows of one column.  Row
-// sums (B x_s) are reduced over the 8 lanes lj at the end of a tile (shuffles);
-// column sums (B^T x_t, the mirrored block's product) over the 8 adjacent lanes
-// li after every column step (DPP) and kept by the lane li == kc % 8 in slot
-// kc / 8.  Writes the same partial rows as near_sym_wave.
-template <class T, int S, class BT = T>
+// l = 8 lj + li owns rows rt + RPL li .. rt + RPL li + RPL - 1 of every 8 RPL-row
+// tile and the columns c = lj + 8 kc.  A lane's RPL rows are consecutive in the
+// column-major block, so the 8 lanes of a group read 8 RPL consecutive rows of one
+// column.  Row sums (B x_s) are reduced over the 8 lanes lj at the end of a tile
+// (shuffles); column sums (B^T x_t, the mirrored block's product) over the 8
+// adjacent lanes li after every column step (DPP) and kept by the lane
+// li == kc % 8 in slot kc / 8.  Writes the same partial rows as near_sym_wave.
+// RPL = 8 (whole 64-row tiles) fits blocks of 64 and 256 functions; 144 (p = 2,
+// 16 elements per leaf) takes RPL = 9, two full tiles instead of 64 + 64 + 16
+// rows, and 36 takes RPL = 5.
+template <class T, int S, class BT = T, int RPL = 8>
 __device__ inline void near_sym_wave_reg(const NearSymArgs &N, int64_t k, const BT *__restrict__ blocks,
                                          const T *__restrict__ x, T *__restrict__ part)
 {
@@ -1179,12 +1195,12 @@ __device__ inline void near_sym_wave_reg(const NearSymArgs &N, int64_t k, const 
 #pragma unroll
     for (int q = 0; q < S; ++q) own[q] = zero<T>();
     const int ncs = lj < nl ? (nl - lj + 7) / 8 : 0;  // columns lj + 8 kc < nl (the same for a whole group)
-    for (int rt = 0; rt < nl; rt += 64) {
-        const int r0 = rt + 8 * li;
+    for (int rt = 0; rt < nl; rt += 8 * RPL) {
+        const int r0 = rt + RPL * li;
         const bool rows = r0 < nl;
-        T xr[8], ra[8];
+        T xr[RPL], ra[RPL];
 #pragma unroll
-        for (int r = 0; r < 8; ++r) {
+        for (int r = 0; r < RPL; ++r) {
             xr[r] = r0 + r < nl ? xt[r0 + r] : zero<T>();
             ra[r] = zero<T>();
         }
@@ -1192,11 +1208,18 @@ __device__ inline void near_sym_wave_reg(const NearSymArgs &N, int64_t k, const 
             const int c = lj + 8 * kc;
             T cs = zero<T>();
             if (rows) {
-                T v[8];
-                load8(B + (int64_t)c * ld + r0, v);
+                T v[RPL];
+                if constexpr (RPL == 8) {
+                    load8(B + (int64_t)c * ld + r0, v);
+                } else {
+                    // rows past nl of the last tile read padding inside the column (ld >= 8 RPL tiles is
+                    // not guaranteed, so those loads are skipped)
+#pragma unroll
+                    for (int r = 0; r < RPL; ++r) v[r] = r0 + r < nl ? load1(B + (int64_t)c * ld + r0 + r) : zero<T>();
+                }
                 const T xc = xsrc[c];
 #pragma unroll
-                for (int r = 0; r < 8; ++r) {
+                for (int r = 0; r < RPL; ++r) {
                     ra[r] += v[r] * xc;
                     cs += v[r] * xr[r];
                 }
@@ -1207,11 +1230,11 @@ __device__ inline void near_sym_wave_reg(const NearSymArgs &N, int64_t k, const 
                 if (li == (kc & 7) && (kc >> 3) == q) own[q] += cs;
         }
 #pragma unroll
-        for (int r = 0; r < 8; ++r) {
+        for (int r = 0; r < RPL; ++r) {
             T a = ra[r];
 #pragma unroll
             for (int o = 8; o < 64; o <<= 1) a += shfl_xor_(a, o);
-            if (lj == r && r0 + r < nl) prow[r0 + r] = a;
+            if (lj == (r & 7) && r0 + r < nl) prow[r0 + r] = a;
         }
     }
     if (t != sc) {
@@ -1230,8 +1253,10 @@ template <class T>
 __device__ inline void near_sym_block(const NearSymArgs &N, int64_t k, const T *__restrict__ blocks,
                                       const T *__restrict__ x, T *__restrict__ part, T *cacc)
 {
-    if (N.nl <= 64) near_sym_wave_reg<T, 1>(N, k, blocks, x, part);
+    if (N.nl == 36) near_sym_wave_reg<T, 1, T, 5>(N, k, blocks, x, part);
+    else if (N.nl <= 64) near_sym_wave_reg<T, 1>(N, k, blocks, x, part);
     else if (N.nl <= 128) near_sym_wave_reg<T, 2>(N, k, blocks, x, part);
+    else if (N.nl == 144) near_sym_wave_reg<T, 3, T, 9>(N, k, blocks, x, part);
     else if (N.nl <= 192) near_sym_wave_reg<T, 3>(N, k, blocks, x, part);
     else if (N.nl <= 256) near_sym_wave_reg<T, 4>(N, k, blocks, x, part);
     else near_sym_wave<T>(N, k, blocks, x, part, cacc);
@@ -1258,8 +1283,10 @@ __global__ void __launch_bounds__(256) k_near_sym32(NearSymArgs N, const cf *__r
     const int wave = threadIdx.x >> 6;
     const int64_t k = (int64_t)blockIdx.x * (blockDim.x >> 6) + wave;
     if (k >= N.nsb) return;
-    if (N.nl <= 64) near_sym_wave_reg<cd, 1, cf>(N, k, blocks, x, part);
+    if (N.nl == 36) near_sym_wave_reg<cd, 1, cf, 5>(N, k, blocks, x, part);
+    else if (N.nl <= 64) near_sym_wave_reg<cd, 1, cf>(N, k, blocks, x, part);
     else if (N.nl <= 128) near_sym_wave_reg<cd, 2, cf>(N, k, blocks, x, part);
+    else if (N.nl == 144) near_sym_wave_reg<cd, 3, cf, 9>(N, k, blocks, x, part);
     else if (N.nl <= 192) near_sym_wave_reg<cd, 3, cf>(N, k, blocks, x, part);
     else near_sym_wave_reg<cd, 4, cf>(N, k, blocks, x, part);
 }

@@ -3436,14 +3436,15 @@ static igb_status assemble(igb_operator *op)
     if ((rc = dalloc(op, &op->nearb, op->near_bytes))) return rc;
     HIPCHK(hipMemsetAsync(op->nearb, 0, op->near_bytes, op->st));
     {
-        std::vector<PairRec> lists[3];
-        for (const PairRec &R : s.pairs)
-            if (R.cls == kRegular) lists[R.order == ords[0] ? 0 : (R.order == ords[1] ? 1 : 2)].push_back(R);
+        // the plan keeps the regular pairs grouped by Gauss order (ords[k] is group k): one upload, one launch
+        // per group
+        const int64_t nreg = s.pair_off[3];
+        PairRec *d = nullptr;
+        if (nreg > 0 && (rc = upload(op, &d, s.pairs.data(), (size_t)nreg * sizeof(PairRec)))) return rc;
         for (int k = 0; k < 3; ++k) {
-            if (lists[k].empty()) continue;
-            PairRec *d = nullptr;
-            if ((rc = upload(op, &d, lists[k].data(), lists[k].size() * sizeof(PairRec)))) return rc;
-            if ((rc = launch_regular<T>(op, d, (int64_t)lists[k].size(), ords[k], op->gpts[k]))) return rc;
+            const int64_t n = s.pair_off[k + 1] - s.pair_off[k];
+            if (n == 0) continue;
+            if ((rc = launch_regular<T>(op, d + s.pair_off[k], n, ords[k], op->gpts[k]))) return rc;
         }
         for (int part = 0; part < 2; ++part) {
             const std::vector<PairRec> &lst = part == 0 ? touch_id : touch_adj;

@@ -5,6 +5,7 @@
 #include "setup.h"
 
 #include <algorithm>
+#include <array>
 #include <atomic>
 #include <condition_variable>
 #include <functional>
@@ -746,10 +747,13 @@ static std::string build_pairs(Setup &s)
     int nL = 1 << s.L;
     int64_t nnear = (int64_t)(s.near.size() / 2);
     int nw = num_workers(nnear / 16 + 1);
-    std::vector<std::vector<PairRec>> part(nw);
+    // per worker, four groups: regular pairs by Gauss order (g0, g0 + 2, g0 + 4, capped at 40), touching
+    const int o1 = std::min(40, s.g0 + 2);
+    auto group = [&](const PairRec &R) { return R.cls != kRegular ? 3 : (R.order == s.g0 ? 0 : (R.order == o1 ? 1 : 2)); };
+    std::vector<std::array<std::vector<PairRec>, 4>> part(nw);
     std::vector<int> bad(nw, 0);
     parallel_chunks(nnear, nw, [&](int64_t kb, int64_t ke, int w) {
-        std::vector<PairRec> &out = part[w];
+        std::array<std::vector<PairRec>, 4> &out = part[w];
         for (int64_t k = kb; k < ke; ++k) {
             int t = s.near[2 * k], src = s.near[2 * k + 1];
             int32_t blk1 = (int32_t)k, blk2 = block_index(src, t);
@@ -773,21 +777,40 @@ static std::string build_pairs(Setup &s)
                             R.elF = (int8_t)(b2 * s.side + b1);
                             R.blk1 = blk1;
                             R.blk2 = (E == F) ? -1 : blk2;
-                            out.push_back(R);
+                            out[group(R)].push_back(R);
                         }
                 }
         }
     });
-    size_t tot = 0;
-    for (int w = 0; w < nw; ++w) {
+    for (int w = 0; w < nw; ++w)
         if (bad[w]) return "near-field partition is not symmetric";
-        tot += part[w].size();
+    // group k of worker w goes to pair_off[k] + (sizes of group k in workers before w): one parallel copy
+    std::vector<std::array<int64_t, 4>> at(nw);
+    int64_t pos = 0;
+    for (int g = 0; g < 4; ++g) {
+        s.pair_off[g] = pos;
+        for (int w = 0; w < nw; ++w) {
+            at[w][g] = pos;
+            pos += (int64_t)part[w][g].size();
+        }
     }
-    s.pairs.reserve(tot);
-    for (int w = 0; w < nw; ++w) {
-        for (const PairRec &R : part[w]) s.npairs_class[R.cls]++;
-        s.pairs.insert(s.pairs.end(), part[w].begin(), part[w].end());
-    }
+    s.pair_off[4] = pos;
+    s.pairs.resize(pos);
+    // the copy in pieces of at most 32768 pairs (1 MiB), spread over the pool
+    struct Piece { int w, g; int64_t from, n; };
+    std::vector<Piece> pieces;
+    for (int w = 0; w < nw; ++w)
+        for (int g = 0; g < 4; ++g)
+            for (int64_t f = 0; f < (int64_t)part[w][g].size(); f += 32768)
+                pieces.push_back({w, g, f, std::min<int64_t>(32768, (int64_t)part[w][g].size() - f)});
+    parallel_chunks((int64_t)pieces.size(), 1 << 30, [&](int64_t pb, int64_t pe, int) {
+        for (int64_t i = pb; i < pe; ++i) {
+            const Piece &P = pieces[i];
+            std::memcpy(&s.pairs[at[P.w][P.g] + P.from], part[P.w][P.g].data() + P.from, P.n * sizeof(PairRec));
+        }
+    });
+    for (int g = 0; g < 3; ++g) s.npairs_class[kRegular] += s.pair_off[g + 1] - s.pair_off[g];
+    for (int64_t k = s.pair_off[3]; k < s.pair_off[4]; ++k) s.npairs_class[s.pairs[k].cls]++;
     return "";
 }
 
@@ -1103,8 +1126,7 @@ std::string check_touching(const Setup &s, const std::vector<PairRec> &touch, st
     std::vector<PairRec> mine;
     std::vector<PairRec> &pt = plan_touch ? *plan_touch : mine;
     pt.clear();
-    for (const PairRec &R : s.pairs)
-        if (R.cls != kRegular) pt.push_back(R);
+    for (int64_t k = s.pair_off[3]; k < s.pair_off[4]; ++k) pt.push_back(s.pairs[k]);
     std::sort(pt.begin(), pt.end(), [](const PairRec &a, const PairRec &b) {
         return ((uint64_t)(uint32_t)a.E << 32 | (uint32_t)a.F) < ((uint64_t)(uint32_t)b.E << 32 | (uint32_t)b.F);
     });

@@ -75,8 +75,10 @@ struct Setup {
     // element corners (4 x 3), 3x3 grids (9 x 3), grid diameters and the radius of
     // the grid about its centre point (grid point 4)
     std::vector<double> ecorner, egrid, ediam, erad;
-    // near-field element pairs, in near-block order
+    // near-field element pairs, grouped: regular pairs of Gauss order g0, g0 + 2, g0 + 4 (capped at 40),
+    // then the touching pairs; group k is pairs[pair_off[k] .. pair_off[k + 1])
     std::vector<PairRec> pairs;
+    int64_t pair_off[5] = {0, 0, 0, 0, 0};
     int64_t npairs_class[4] = {0, 0, 0, 0};
     // Gauss rules on [0,1], orders 1..40, concatenated: gx[goff[n] + i]
     std::vector<double> gx, gw;

@@ -160,6 +160,27 @@ def hbm_roof(kname, nbytes, ms, traffic):
             "avg_ms": round(ms, 4)}
 
 
+def near_quadrature(op, helmholtz: bool, p: int):
+    """Roofline of the near-field pair quadrature of an assembled operator: quadrature points and kernel
+    time from igb_info (HIP events around the launches inside igb_operator_create).  Flop model per point:
+    the kernel value (as the far field's) plus 2 (p+1)^2 per real component for folding it into the
+    (p+1)^2 x (p+1)^2 block (the smaller second contraction and the geometry are not counted)."""
+    nloc = (p + 1) ** 2
+    fpp = (FLOP_PER_EVAL_HELMHOLTZ if helmholtz else 14) + 2 * nloc * (2 if helmholtz else 1)
+    out = {}
+    for name, kern, pts, ms in (("regular", "k_near_regular", op.info.quad_points_regular, op.info.quad_regular_ms),
+                                ("touching", "k_near_singular", op.info.quad_points_touching,
+                                 op.info.quad_touching_ms)):
+        if ms <= 0 or pts <= 0:
+            continue
+        r = alu_roof(kern, pts * fpp, pts, fpp, ms, None)
+        r["quadrature_points"] = r.pop("kernel_evaluations")
+        r["flop_per_point"] = r.pop("flop_per_evaluation")
+        r["gpoints_per_s"] = round(pts / (ms * 1e-3) / 1e9, 2)
+        out[name] = r
+    return out
+
+
 # ---------------------------------------------------------------------------
 # headline: Helmholtz torus
 # ---------------------------------------------------------------------------
@@ -326,6 +347,7 @@ def sphere_leg(torch, igb, W, steps, reps, mode="onthefly"):
            "stage_ms": {k: round(v, 4) for k, v in stages.items()},
            "stage_ms_separate": {k: round(v, 4) for k, v in sep.items()},
            "near_blocks": int(op.info.n_near_blocks), "far_blocks": int(op.info.n_far_blocks),
+           "near_quadrature": near_quadrature(op, False, C2["p"]),
            "roofline_stages": roofs}
     log(f"sphere: {ms / 1e3:.4f} s per step, {info.iterations} it, matvec {mv:.3f} ms")
     del op
@@ -686,6 +708,7 @@ def main():
         "near_blocks": int(op.info.n_near_blocks),
         "far_blocks": int(op.info.n_far_blocks),
         "point_source_twin": twin,
+        "near_quadrature": near_quadrature(op, True, C3["p"]),
         "roofline": roofs["far_field"],
         "roofline_stages": roofs,
         "cpu_baseline": None,

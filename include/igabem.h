@@ -129,6 +129,12 @@ typedef struct {
     int64_t matvec_bytes;      /* algorithmic HBM bytes of one superspace matvec */
     double setup_seconds;      /* host part of igb_operator_create (tree, partition, lists) */
     double assembly_seconds;   /* whole igb_operator_create, device work included */
+    int64_t quad_points_regular;   /* quadrature points of the regular near-field pairs: g^4 per pair
+                                      (g = g0, g0 + 2 or g0 + 4 by distance, at most 40) */
+    int64_t quad_points_touching;  /* of the touching pairs: regions x gauss_singular^4 per pair
+                                      (identical 4 integrated regions, common edge 6, vertex 4) */
+    double quad_regular_ms;    /* kernel time of the regular-pair quadrature (operators only; 0 for plans) */
+    double quad_touching_ms;   /* kernel time of the touching-pair quadrature (identical + adjacent) */
 } igb_info;
 
 typedef struct {

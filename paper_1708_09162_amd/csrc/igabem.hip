@@ -2776,6 +2776,8 @@ struct igb_operator {
     double *rpts = nullptr;        // rhs/potential order geometry
     double *nodes = nullptr;
     double *sctab = nullptr;       // sin, cos (j pi/64), j < 128, for the complex far field
+    hipEvent_t qev[6] = {};        // around the identical, adjacent and regular pair quadrature
+    double quad_ms[2] = {0.0, 0.0};  // regular, touching (identical + adjacent) pair quadrature
     double *zdev = nullptr;        // Chebyshev nodes
     int64_t *cl_off = nullptr;
     double *M1 = nullptr, *E2 = nullptr, *Mlev = nullptr, *Tb = nullptr;
@@ -3355,7 +3357,10 @@ static igb_status assemble_identical(igb_operator *op)
     PairRec *d = nullptr;
     if ((rc = upload(op, &d, tid.data(), tid.size() * sizeof(PairRec)))) return rc;
     if ((rc = dalloc(op, &op->pairbuf_id, (size_t)s.nelem * s.nloc * s.nloc * sizeof(T)))) return rc;
-    return launch_singular<T>(op, d, (int64_t)s.nelem, op->pairbuf_id, false);
+    HIPCHK(hipEventRecord(op->qev[0], op->st));
+    rc = launch_singular<T>(op, d, (int64_t)s.nelem, op->pairbuf_id, false);
+    HIPCHK(hipEventRecord(op->qev[1], op->st));
+    return rc;
 }
 
 // The common-edge and common-vertex pairs, found from corner coincidence of the
@@ -3372,8 +3377,10 @@ static igb_status assemble_adjacent(igb_operator *op)
     PairRec *d = nullptr;
     if ((rc = upload(op, &d, touch.data(), touch.size() * sizeof(PairRec)))) return rc;
     if ((rc = dalloc(op, &op->pairbuf, (size_t)n * s.nloc * s.nloc * sizeof(T)))) return rc;
-    if (n > 0) return launch_singular<T>(op, d, n, op->pairbuf, true);
-    return IGB_OK;
+    HIPCHK(hipEventRecord(op->qev[2], op->st));
+    if (n > 0) rc = launch_singular<T>(op, d, n, op->pairbuf, true);
+    HIPCHK(hipEventRecord(op->qev[3], op->st));
+    return rc;
 }
 
 // Assembly, second part (needs the plan): near-field blocks (regular pairs by
@@ -3441,11 +3448,13 @@ static igb_status assemble(igb_operator *op)
         const int64_t nreg = s.pair_off[3];
         PairRec *d = nullptr;
         if (nreg > 0 && (rc = upload(op, &d, s.pairs.data(), (size_t)nreg * sizeof(PairRec)))) return rc;
+        HIPCHK(hipEventRecord(op->qev[4], op->st));
         for (int k = 0; k < 3; ++k) {
             const int64_t n = s.pair_off[k + 1] - s.pair_off[k];
             if (n == 0) continue;
             if ((rc = launch_regular<T>(op, d + s.pair_off[k], n, ords[k], op->gpts[k]))) return rc;
         }
+        HIPCHK(hipEventRecord(op->qev[5], op->st));
         for (int part = 0; part < 2; ++part) {
             const std::vector<PairRec> &lst = part == 0 ? touch_id : touch_adj;
             const T *buf = (const T *)(part == 0 ? op->pairbuf_id : op->pairbuf);
@@ -4144,6 +4153,8 @@ void igb_operator_destroy(igb_operator *op)
     }
     if (op->ev_fork) (void)hipEventDestroy(op->ev_fork);
     if (op->ev_join) (void)hipEventDestroy(op->ev_join);
+    for (hipEvent_t e : op->qev)
+        if (e) (void)hipEventDestroy(e);
     delete op;
 }
 
@@ -4164,6 +4175,11 @@ igb_status igb_operator_create(const igb_geometry *geo, const igb_params *prm, v
         delete op;
         return fail(IGB_EHIP, "hipGetDevice failed");
     }
+    for (hipEvent_t &e : op->qev)
+        if (hipEventCreate(&e) != hipSuccess) {
+            igb_operator_destroy(op);
+            return fail(IGB_EHIP, "hipEventCreate failed");
+        }
     std::string err;
     try {
         err = build_setup_tiles(geo->g, *prm, op->s);
@@ -4224,6 +4240,16 @@ igb_status igb_operator_create(const igb_geometry *geo, const igb_params *prm, v
         hipError_t e = hipStreamSynchronize(op->st);
         if (e != hipSuccess) rc = fail(IGB_EHIP, std::string("assembly: ") + hipGetErrorString(e));
     }
+    if (rc == IGB_OK) {
+        // kernel time of the pair quadrature (HIP events around its launches on the operator's stream)
+        float a = 0.f, b = 0.f, c = 0.f;
+        if (hipEventElapsedTime(&a, op->qev[4], op->qev[5]) == hipSuccess &&
+            hipEventElapsedTime(&b, op->qev[0], op->qev[1]) == hipSuccess &&
+            hipEventElapsedTime(&c, op->qev[2], op->qev[3]) == hipSuccess) {
+            op->quad_ms[0] = a;
+            op->quad_ms[1] = (double)b + (double)c;
+        }
+    }
     if (rc != IGB_OK) {
         std::string msg = g_err;
         igb_operator_destroy(op);
@@ -4243,6 +4269,8 @@ igb_status igb_operator_info(const igb_operator *op, igb_info *out)
     if (!out) return fail(IGB_EINVAL, "out is null");
     fill_info(op->s, op->esz, out);
     out->assembly_seconds = op->assembly_seconds;
+    out->quad_regular_ms = op->quad_ms[0];
+    out->quad_touching_ms = op->quad_ms[1];
     return IGB_OK;
 }
 
@@ -4884,6 +4912,15 @@ static void fill_info(const Setup &s, size_t esz, igb_info *out)
     out->matvec_bytes = out->near_bytes + out->coupling_bytes + (int64_t)esz * (3 * s.nsup + 4 * q2 * ncl) +
                         (s.mode == IGB_H2_ONTHEFLY ? (int64_t)32 * q2 * ncl : 0);
     out->setup_seconds = s.setup_seconds;
+    // quadrature points of the near-field pairs: g^4 per regular pair (orders g0, g0 + 2, g0 + 4 by the
+    // pair's group), regions x gs^4 per touching pair (identical 4 integrated regions, edge 6, vertex 4)
+    const int ords[3] = {s.g0, std::min(40, s.g0 + 2), std::min(40, s.g0 + 4)};
+    for (int k = 0; k < 3; ++k) {
+        const int64_t g2 = (int64_t)ords[k] * ords[k];
+        out->quad_points_regular += (s.pair_off[k + 1] - s.pair_off[k]) * g2 * g2;
+    }
+    const int64_t gs4 = (int64_t)s.gs * s.gs * s.gs * s.gs;
+    out->quad_points_touching = gs4 * (4 * s.npairs_class[1] + 6 * s.npairs_class[2] + 4 * s.npairs_class[3]);
 }
 
 igb_status igb_plan_create(const igb_geometry *geo, const igb_params *prm, igb_plan **out)

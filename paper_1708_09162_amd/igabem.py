@@ -69,7 +69,9 @@ class igb_info(C.Structure):
                 ("gauss_rhs", C.c_int32), ("layout_flags", C.c_int32), ("n_near_blocks", C.c_int64),
                 ("n_far_blocks", C.c_int64), ("n_pairs", C.c_int64 * 4), ("near_bytes", C.c_int64),
                 ("coupling_bytes", C.c_int64), ("matvec_bytes", C.c_int64), ("setup_seconds", C.c_double),
-                ("assembly_seconds", C.c_double)]
+                ("assembly_seconds", C.c_double), ("quad_points_regular", C.c_int64),
+                ("quad_points_touching", C.c_int64), ("quad_regular_ms", C.c_double),
+                ("quad_touching_ms", C.c_double)]
 
 
 class igb_solve_info(C.Structure):

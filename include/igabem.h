@@ -293,9 +293,9 @@ igb_status igb_cnn_train_operator(igb_cnn *net, const igb_operator *op, const fl
 
 /* Flexible GMRES (right preconditioned, restarted after `restart` steps) for
  * T A T^T w = b with the preconditioner M(v) = D^-1 v + f(D^-1 v) of `net`, or
- * plain Jacobi D^-1 v when net is NULL.  With a network, a restart cycle that
- * fails to cut the true relative residual tenfold drops the network for Jacobi
- * for the rest of the solve (info->fallback = 1).  Laplace operators only
+ * plain Jacobi D^-1 v when net is NULL.  With a network, a restart cycle of k
+ * steps that fails to cut the true relative residual by 0.9^k drops the network
+ * for Jacobi for the rest of the solve (info->fallback = 1).  Laplace operators only
  * (IGB_EUNSUPPORTED otherwise).  Stopping rule, initial guess and return
  * values as igb_solve, judged on the true residual of the FP64 operator.
  * restart in 1..2048 (IGB_EINVAL otherwise).  The bases take (2 restart + 1)

@@ -3967,10 +3967,10 @@ static igb_status solve_gmres_dev(igb_operator *op, const igb_cnn *net, const T 
         hipEvent_t *e;
         ~Events() { (void)hipEventDestroy(e[0]); (void)hipEventDestroy(e[1]); }
     } events{ev};
-    int it = 0;
+    int it = 0, last_k = 0;
     double rel = 0.0, prev_rel = -1.0;
-    // the network is dropped for Jacobi (the fallback) once a restart cycle fails to cut the true residual
-    // tenfold
+    // the network is dropped for Jacobi (the fallback) once a restart cycle of k steps fails to cut the true
+    // residual by 0.9^k (a rate Jacobi beats on these operators: 1e-8 in 70-100 steps)
     const igb_cnn *pnet = net;
     int fell_back = 0;
     for (;;) {
@@ -3983,7 +3983,7 @@ static igb_status solve_gmres_dev(igb_operator *op, const igb_cnn *net, const T 
         if ((rc = norm2(r, &beta2))) return rc;
         const double beta = std::sqrt(beta2);
         rel = beta / bn;
-        if (pnet && prev_rel > 0.0 && rel > 0.1 * prev_rel) {
+        if (pnet && prev_rel > 0.0 && rel > std::pow(0.9, last_k) * prev_rel) {
             pnet = nullptr;
             fell_back = 1;
         }
@@ -4052,6 +4052,7 @@ static igb_status solve_gmres_dev(igb_operator *op, const igb_cnn *net, const T 
         if (rc) return rc;
         const int k = kuse > 0 ? kuse : examined;
         it += k;
+        last_k = k;
         // y = H^-1 g (upper triangular k x k); w += Z y
         HIPCHK(hipMemcpy(H.data(), G, (size_t)k * R * sizeof(T), hipMemcpyDeviceToHost));
         HIPCHK(hipMemcpy(gh.data(), gdev, (R + 1) * sizeof(T), hipMemcpyDeviceToHost));

@@ -290,7 +290,7 @@ def test_solve_many_matches_single_solves():
 def test_selected_network_against_jacobi():
     """Model selection and fallback inside the library: four linear networks (initial-weight seeds 5-8)
     trained on the p=2 sphere with 32x32 elements per patch.  Every seed converges to 1e-8 in flexible GMRES
-    (a network whose restart cycle fails to cut the residual tenfold is dropped for Jacobi, reported in
+    (a network whose restart cycle of k steps fails to cut the residual by 0.9^k is dropped for Jacobi, reported in
     info.fallback).  igb_solve_fgmres_select keeps the seed with the fewest steps on a validation right-hand
     side (other point charges) among those that converged there without falling back and beat Jacobi, else
     Jacobi; its choice is recomputed here from single solves, and on the real right-hand side the kept

@@ -212,7 +212,8 @@ __global__ void k_pack_mfma(const uint16_t *__restrict__ w, uint16_t *__restrict
 // input tile with its halo is staged in LDS as hi, mid and lo planes, pixel-major with the 32 channels
 // innermost.  Wave w takes output rows w, w + 4, w + 8, w + 12: per tap and row, six MFMAs (two halves
 // of the output channels times the three terms) on A = the tap's weights (from wm, in operand order) and
-// B = 16 pixels x 32 channels read straight from the staged tile.
+// B = 16 pixels x 32 channels read straight from the staged tile.  The three planes take 77,760 bytes of
+// LDS (gfx950 grants up to 160 KB to a workgroup; two workgroups fit a CU).
 template <bool RELU_IN, bool MASK_OUT>
 __global__ void __launch_bounds__(256) k_conv3_mfma(const float *__restrict__ in, const uint4 *__restrict__ wm,
                                                     float *__restrict__ out, const float *__restrict__ mask, int H,
@@ -380,7 +381,7 @@ __device__ inline uint4 shift_bf16(const uint4 &a, const uint4 &b, int s)
 // aligned 16-byte pieces per lane and term, shifted by dx in registers) and, for each dy with output row
 // s - dy in the tile, adds the six products of terms of combined order at most two (hi hi, hi mid,
 // mid hi, hi lo, lo hi, mid mid) for dx = 0, 1, 2; the three left out are below 2^-23 of the product.
-// Partial sums per workgroup as k_wgrad3's, reduced by k_wreduce.
+// Partial sums per workgroup as k_wgrad3's, reduced by k_wreduce.  73,728 bytes of LDS per workgroup.
 template <bool RELU_IN>
 __global__ void __launch_bounds__(256) k_wgrad3_mfma(const float *__restrict__ in, const float *__restrict__ dz,
                                                      float *__restrict__ part, int H, int W, int tiles_x,

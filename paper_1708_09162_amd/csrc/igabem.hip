@@ -1786,8 +1786,11 @@ __global__ void __launch_bounds__(256, NComp<T>::value == 1 ? 3 : 1) k_far_sym(F
 // Complex kernel with 65 .. 104 nodes per cluster: one wave per workgroup,
 // chunks of kFarChunk pairs, grid-strided.  The host launches a fixed number
 // of waves per SIMD (kFarWaves), fewer than the registers allow, so that the
-// near-field GEMV on the side stream finds room on every CU.
-constexpr int kFarWaves[2] = {3, 3};  // double, single precision: the fastest of 2..4 measured (torus, kappa 8, q 10)
+// near-field GEMV on the side stream finds room on every CU.  Measured on the
+// torus (kappa 8, q 10), product with the near GEMV beside it: double, 3 waves
+// 6.29 ms, 2 waves 6.79 (the far field alone 4.13 and 5.74: latency-bound);
+// single, 3 waves 3.58 ms, 2 waves 3.34 (its 91 VGPRs leave room for near waves).
+constexpr int kFarWaves[2] = {3, 2};  // double, single precision
 // Double precision: the sine/cosine table (2 KB) is copied into LDS ahead of the nodes.
 template <class T, int TT, bool RAW>
 __global__ void __launch_bounds__(64, RAW ? 4 : 2) k_far_sym1(FarSymArgs F, const T *__restrict__ Xh, T *__restrict__ part)

@@ -1761,10 +1761,12 @@ __device__ inline void far_mfma_chunk(const FarSymArgs &F, int64_t k0, int64_t k
 // one (full precision only).
 template <class T, int TT, bool RAW>
 __device__ inline void far_chunk(const FarSymArgs &F, int64_t k0, int64_t k1, const T *__restrict__ Xh,
-                                 T *__restrict__ part, double *lds)
+                                 T *__restrict__ part, double *lds, const double *tab = nullptr)
 {
     if constexpr (NComp<T>::value == 1) {
         far_mfma_chunk<(TT + 1) / 2, RAW>(F, k0, k1, Xh, part, lds);
+    } else if constexpr (TT > 8 && !RAW) {
+        far_sym_chunk<TT, RAW, true>(F, k0, k1, Xh, part, lds, tab);  // sine and cosine from the LDS table
     } else {
         far_sym_chunk<TT, RAW>(F, k0, k1, Xh, part, lds);
     }
@@ -1813,15 +1815,23 @@ __global__ void __launch_bounds__(64, RAW ? 4 : 2) k_far_sym1(FarSymArgs F, cons
 // HBM-bound work on the same CUs): nf far workgroups (four waves of kFarChunk
 // pairs) and nn near workgroups (four waves of one block), the near ones spread
 // evenly through the grid (workgroup b is near iff
-// floor((b+1) nn / (nf+nn)) > floor(b nn / (nf+nn))).
+// floor((b+1) nn / (nf+nn)) > floor(b nn / (nf+nn))).  The complex kernel with
+// more than 64 nodes per cluster (double precision) takes its sine and cosine
+// from a table staged in LDS per workgroup and is held to three waves per SIMD.
 template <class T, int TT, bool RAW>
-__global__ void __launch_bounds__(256, NComp<T>::value == 1 ? 3 : 1) k_sym_products(FarSymArgs F, NearSymArgs N,
+__global__ void __launch_bounds__(256, NComp<T>::value == 1 || TT > 8 ? 3 : 1) k_sym_products(FarSymArgs F, NearSymArgs N,
                                                                                   int64_t nf, int64_t nn,
                                                       const T *__restrict__ Xh, T *__restrict__ fpart,
                                                       const T *__restrict__ blocks, const T *__restrict__ x,
                                                       T *__restrict__ npart)
 {
     extern __shared__ double sh[];
+    constexpr bool TAB = NComp<T>::value == 2 && TT > 8 && !RAW;
+    __shared__ double tabs[TAB ? 256 : 1];
+    if constexpr (TAB) {  // before any wave leaves
+        for (int i = threadIdx.x; i < 256; i += blockDim.x) tabs[i] = F.sctab[i];
+        __syncthreads();
+    }
     const int wave = threadIdx.x >> 6;
     const int64_t b = blockIdx.x, tot = nf + nn;
     const int64_t before = b * nn / tot, upto = (b + 1) * nn / tot;
@@ -1834,7 +1844,7 @@ __global__ void __launch_bounds__(256, NComp<T>::value == 1 ? 3 : 1) k_sym_produ
     } else {
         const int64_t k0 = ((b - before) * 4 + wave) * kFarChunk;
         if (k0 >= F.nup) return;
-        far_chunk<T, TT, RAW>(F, k0, min(k0 + kFarChunk, F.nup), Xh, fpart, sh + (size_t)wave * slice);
+        far_chunk<T, TT, RAW>(F, k0, min(k0 + kFarChunk, F.nup), Xh, fpart, sh + (size_t)wave * slice, tabs);
     }
 }
 
@@ -2897,7 +2907,8 @@ static NearLayout near_layout(const Setup &s, size_t esz)
 // 64 KB of LDS.
 static bool fused_products(bool near_sym, int nl, int near_ld, size_t esz, int q2)
 {
-    return near_sym && q2 <= 64 && 4 * (size_t)near_sym_lds(nl, near_ld) * esz <= 64 * 1024;
+    return near_sym && (q2 <= 64 || (esz == sizeof(cd) && q2 <= 104)) &&
+           4 * (size_t)near_sym_lds(nl, near_ld) * esz <= 64 * 1024;
 }
 
 // Far field evaluated once per mirrored pair of blocks (on the fly; q^2 <= 64 for
@@ -3031,7 +3042,16 @@ static NearSymArgs near_args(const igb_operator *op)
 template <class T, int TT, bool RAW>
 static void launch_far_sym_p(igb_operator *op, const T *Xh, const T *xs, bool fuse)
 {
-    if constexpr (TT > 8) {  // one wave per workgroup (LDS slice of far_sym_lds doubles), never fused
+    if (TT > 8 && fuse) {  // double precision: far pairs and near blocks in one launch
+        const int64_t nf = (op->nup + 4 * kFarChunk - 1) / (4 * kFarChunk), nn = (op->nsb + 3) / 4;
+        const size_t shm = 4 *
+                           std::max<size_t>((size_t)near_sym_lds(op->s.nl, op->near_ld) * NComp<T>::value,
+                                            (size_t)far_sym_lds<T, TT>()) * 8;
+        hipLaunchKernelGGL((k_sym_products<T, TT, RAW>), dim3((unsigned)(nf + nn)), dim3(256), shm, op->st, far_args(op),
+                           near_args(op), nf, nn, Xh, (T *)op->fpart, (const T *)op->nearb, xs, (T *)op->npart);
+        return;
+    }
+    if constexpr (TT > 8) {  // one wave per workgroup (LDS slice of far_sym_lds doubles)
         (void)fuse;
         const size_t shm = ((size_t)far_sym_lds<T, TT>() + (RAW ? 0 : 256)) * sizeof(double);
         const int64_t nch = (op->nup + kFarChunk - 1) / kFarChunk;
@@ -3143,7 +3163,10 @@ static igb_status matvec_internal(igb_operator *op, const T *xs, T *ys, hipEvent
     if ((rc = mark(1))) return rc;
     int64_t row0 = s.cl_off[op->lmin], nrows = s.cl_off[s.L + 1] - row0;
     const bool sym = has_far && op->fpart != nullptr;
-    const bool fuse = sym && !separate && fused_products(op->near_sym, s.nl, op->near_ld, sizeof(T), q2);
+    // the single-precision inner operator of a complex solve with more than 64 nodes per cluster keeps the
+    // forked near GEMV over its FP32 blocks (the fused launch reads the FP64 ones)
+    const bool fuse = sym && !separate && fused_products(op->near_sym, s.nl, op->near_ld, sizeof(T), q2) &&
+                      !(q2 > 64 && op->far_single && !op->force_fp64);
     // near blocks not fused into the far-field launch: their GEMV reads only xs, so it runs on the side
     // stream from the start of the product and is joined before its gather
     const bool fork = has_far && op->near_sym && !fuse && !separate;
@@ -3175,11 +3198,11 @@ static igb_status matvec_internal(igb_operator *op, const T *xs, T *ys, hipEvent
             default:  // complex kernel, 65 .. 104 nodes per cluster
                 if constexpr (NComp<T>::value == 2) {
                     switch ((q2 + 7) / 8) {
-                    case 9: launch_far_sym<T, 9>(op, Xh, xs, false); break;
-                    case 10: launch_far_sym<T, 10>(op, Xh, xs, false); break;
-                    case 11: launch_far_sym<T, 11>(op, Xh, xs, false); break;
-                    case 12: launch_far_sym<T, 12>(op, Xh, xs, false); break;
-                    default: launch_far_sym<T, 13>(op, Xh, xs, false); break;
+                    case 9: launch_far_sym<T, 9>(op, Xh, xs, fuse); break;
+                    case 10: launch_far_sym<T, 10>(op, Xh, xs, fuse); break;
+                    case 11: launch_far_sym<T, 11>(op, Xh, xs, fuse); break;
+                    case 12: launch_far_sym<T, 12>(op, Xh, xs, fuse); break;
+                    default: launch_far_sym<T, 13>(op, Xh, xs, fuse); break;
                     }
                 } else {
                     return fail(IGB_EINVAL, "mirrored far field: more than 64 nodes per cluster");

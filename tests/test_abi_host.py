@@ -153,12 +153,12 @@ def test_plan_matches_oracle_sphere_p3_m5_q8_full_size():
 
 
 @pytest.mark.parametrize("mode,q,kernel,flags", [("stored", 8, 0, 1), ("onthefly", 8, 0, 7), ("onthefly", 10, 0, 1),
-                                                  ("onthefly", 8, 1, 7), ("onthefly", 10, 1, 3),
+                                                  ("onthefly", 8, 1, 7), ("onthefly", 10, 1, 7),
                                                   ("onthefly", 11, 1, 1)])
 def test_layout_flags(mode, q, kernel, flags):
     """Symmetric near storage always at this size; mirrored far pairs only on the fly, with at most 64
     nodes per cluster for the real kernel and 104 for the complex one; the shared launch of far pairs and
-    near blocks for at most 64 nodes per cluster (near blocks of up to 256 functions need no LDS)."""
+    near blocks wherever the pairs are mirrored (near blocks of up to 256 functions need no LDS)."""
     g = igb.Geometry(W.sphere_patches())
     m = igb.IGB_H2_STORED if mode == "stored" else igb.IGB_H2_ONTHEFLY
     info = igb.Plan(g, p=1, m=4, q=q, eta=1.6, gauss_regular=4, mode=m, kernel=kernel,

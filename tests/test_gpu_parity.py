@@ -381,11 +381,12 @@ def test_helmholtz_h2_torus(mode):
 @pytest.mark.parametrize("q", [9, 10])
 def test_helmholtz_h2_torus_mirrored_many_nodes(q):
     """Complex kernel with 81 and 100 interpolation nodes per cluster: the far field is generated once
-    per mirrored block pair with 11 and 13 nodes per lane (layout flag bit 1 set, no shared launch)."""
+    per mirrored block pair with 11 and 13 nodes per lane, in one launch with the near blocks (layout
+    flags: bits 1 and 2)."""
     say(f"helmholtz h2 torus k=3 p=1 m=2 q={q} onthefly mirrored")
     op, P = make(W.torus_patches(), mode=igb.IGB_H2_ONTHEFLY, kernel=igb.IGB_HELMHOLTZ, wavenumber=3.0, p=1, m=2,
                  q=q, leaf_depth=1, eta=1.6, gauss_regular=4)
-    assert op.info.n_far_blocks > 0 and op.info.layout_flags == 3
+    assert op.info.n_far_blocks > 0 and op.info.layout_flags == 7
     P.h2_assemble(store_coupling=True)
     xs = rand(P.nsup, 30 + q, cplx=True)
     ys = to_np(op.matvec_super(torch.tensor(xs)))

@@ -120,9 +120,7 @@ typedef struct {
     int32_t gauss_rhs;
     int32_t layout_flags;      /* bit 0: near blocks stored once per mirrored leaf pair; bit 1: far
                                   field generated once per mirrored block pair; bit 2: both products
-                                  (and both partial-row gathers) share one launch (the single-precision
-                                  inner products of a complex solve with more than 64 nodes per
-                                  cluster run the near GEMV beside it instead) */
+                                  (and both partial-row gathers) share one launch */
     int64_t n_near_blocks;     /* leaf pairs in the near field */
     int64_t n_far_blocks;      /* admissible cluster pairs, all levels */
     int64_t n_pairs[4];        /* element pairs by class: regular, identical, common edge, common vertex */

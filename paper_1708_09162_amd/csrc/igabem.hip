@@ -1276,19 +1276,25 @@ __global__ void __launch_bounds__(256) k_near_sym(NearSymArgs N, const T *__rest
     near_sym_block<T>(N, k, blocks, x, part, (T *)sh + (size_t)wave * near_sym_lds(N.nl, N.ld));
 }
 
-// The same with single-precision complex blocks (nl <= 256, products and sums in FP64)
-__global__ void __launch_bounds__(256) k_near_sym32(NearSymArgs N, const cf *__restrict__ blocks,
-                                                    const cd *__restrict__ x, cd *__restrict__ part)
+// A stored near block with single-precision complex entries (nl <= 256, products and sums in FP64)
+__device__ inline void near_sym_block_c32(const NearSymArgs &N, int64_t k, const cf *__restrict__ blocks,
+                                          const cd *__restrict__ x, cd *__restrict__ part)
 {
-    const int wave = threadIdx.x >> 6;
-    const int64_t k = (int64_t)blockIdx.x * (blockDim.x >> 6) + wave;
-    if (k >= N.nsb) return;
     if (N.nl == 36) near_sym_wave_reg<cd, 1, cf, 5>(N, k, blocks, x, part);
     else if (N.nl <= 64) near_sym_wave_reg<cd, 1, cf>(N, k, blocks, x, part);
     else if (N.nl <= 128) near_sym_wave_reg<cd, 2, cf>(N, k, blocks, x, part);
     else if (N.nl == 144) near_sym_wave_reg<cd, 3, cf, 9>(N, k, blocks, x, part);
     else if (N.nl <= 192) near_sym_wave_reg<cd, 3, cf>(N, k, blocks, x, part);
     else near_sym_wave_reg<cd, 4, cf>(N, k, blocks, x, part);
+}
+
+__global__ void __launch_bounds__(256) k_near_sym32(NearSymArgs N, const cf *__restrict__ blocks,
+                                                    const cd *__restrict__ x, cd *__restrict__ part)
+{
+    const int wave = threadIdx.x >> 6;
+    const int64_t k = (int64_t)blockIdx.x * (blockDim.x >> 6) + wave;
+    if (k >= N.nsb) return;
+    near_sym_block_c32(N, k, blocks, x, part);
 }
 
 // blocks rounded to single precision, n complex values
@@ -1818,11 +1824,12 @@ __global__ void __launch_bounds__(64, RAW ? 4 : 2) k_far_sym1(FarSymArgs F, cons
 // floor((b+1) nn / (nf+nn)) > floor(b nn / (nf+nn))).  The complex kernel with
 // more than 64 nodes per cluster (double precision) takes its sine and cosine
 // from a table staged in LDS per workgroup and is held to three waves per SIMD.
-template <class T, int TT, bool RAW>
+// BT = cf: the near blocks of the single-precision complex product (FP32 copy, FP64 sums).
+template <class T, int TT, bool RAW, class BT = T>
 __global__ void __launch_bounds__(256, NComp<T>::value == 1 || TT > 8 ? 3 : 1) k_sym_products(FarSymArgs F, NearSymArgs N,
                                                                                   int64_t nf, int64_t nn,
                                                       const T *__restrict__ Xh, T *__restrict__ fpart,
-                                                      const T *__restrict__ blocks, const T *__restrict__ x,
+                                                      const BT *__restrict__ blocks, const T *__restrict__ x,
                                                       T *__restrict__ npart)
 {
     extern __shared__ double sh[];
@@ -1840,7 +1847,8 @@ __global__ void __launch_bounds__(256, NComp<T>::value == 1 || TT > 8 ? 3 : 1) k
     if (upto > before) {
         const int64_t k = before * 4 + wave;
         if (k >= N.nsb) return;
-        near_sym_block<T>(N, k, blocks, x, npart, (T *)(sh + (size_t)wave * slice));
+        if constexpr (std::is_same<BT, T>::value) near_sym_block<T>(N, k, blocks, x, npart, (T *)(sh + (size_t)wave * slice));
+        else near_sym_block_c32(N, k, blocks, x, npart);
     } else {
         const int64_t k0 = ((b - before) * 4 + wave) * kFarChunk;
         if (k0 >= F.nup) return;
@@ -3042,13 +3050,26 @@ static NearSymArgs near_args(const igb_operator *op)
 template <class T, int TT, bool RAW>
 static void launch_far_sym_p(igb_operator *op, const T *Xh, const T *xs, bool fuse)
 {
-    if (TT > 8 && fuse) {  // double precision: far pairs and near blocks in one launch
+    // far pairs and near blocks in one launch; the single-precision complex product reads the FP32 copy
+    // of the near blocks when there is one
+    auto fused = [&]() {
         const int64_t nf = (op->nup + 4 * kFarChunk - 1) / (4 * kFarChunk), nn = (op->nsb + 3) / 4;
         const size_t shm = 4 *
                            std::max<size_t>((size_t)near_sym_lds(op->s.nl, op->near_ld) * NComp<T>::value,
                                             (size_t)far_sym_lds<T, TT>()) * 8;
+        if constexpr (NComp<T>::value == 2 && RAW) {
+            if (op->nearb32) {
+                hipLaunchKernelGGL((k_sym_products<T, TT, RAW, cf>), dim3((unsigned)(nf + nn)), dim3(256), shm, op->st,
+                                   far_args(op), near_args(op), nf, nn, Xh, (T *)op->fpart, (const cf *)op->nearb32, xs,
+                                   (T *)op->npart);
+                return;
+            }
+        }
         hipLaunchKernelGGL((k_sym_products<T, TT, RAW>), dim3((unsigned)(nf + nn)), dim3(256), shm, op->st, far_args(op),
                            near_args(op), nf, nn, Xh, (T *)op->fpart, (const T *)op->nearb, xs, (T *)op->npart);
+    };
+    if (TT > 8 && fuse) {
+        fused();
         return;
     }
     if constexpr (TT > 8) {  // one wave per workgroup (LDS slice of far_sym_lds doubles)
@@ -3065,12 +3086,7 @@ static void launch_far_sym_p(igb_operator *op, const T *Xh, const T *xs, bool fu
                                far_args(op), Xh, (T *)op->fpart);
             return;
         }
-        const int64_t nf = (op->nup + 4 * kFarChunk - 1) / (4 * kFarChunk), nn = (op->nsb + 3) / 4;
-        const size_t shm = 4 *
-                           std::max<size_t>((size_t)near_sym_lds(op->s.nl, op->near_ld) * NComp<T>::value,
-                                            (size_t)far_sym_lds<T, TT>()) * 8;
-        hipLaunchKernelGGL((k_sym_products<T, TT, RAW>), dim3((unsigned)(nf + nn)), dim3(256), shm, op->st, far_args(op),
-                           near_args(op), nf, nn, Xh, (T *)op->fpart, (const T *)op->nearb, xs, (T *)op->npart);
+        fused();
     }
 }
 
@@ -3163,10 +3179,7 @@ static igb_status matvec_internal(igb_operator *op, const T *xs, T *ys, hipEvent
     if ((rc = mark(1))) return rc;
     int64_t row0 = s.cl_off[op->lmin], nrows = s.cl_off[s.L + 1] - row0;
     const bool sym = has_far && op->fpart != nullptr;
-    // the single-precision inner operator of a complex solve with more than 64 nodes per cluster keeps the
-    // forked near GEMV over its FP32 blocks (the fused launch reads the FP64 ones)
-    const bool fuse = sym && !separate && fused_products(op->near_sym, s.nl, op->near_ld, sizeof(T), q2) &&
-                      !(q2 > 64 && op->far_single && !op->force_fp64);
+    const bool fuse = sym && !separate && fused_products(op->near_sym, s.nl, op->near_ld, sizeof(T), q2);
     // near blocks not fused into the far-field launch: their GEMV reads only xs, so it runs on the side
     // stream from the start of the product and is joined before its gather
     const bool fork = has_far && op->near_sym && !fuse && !separate;

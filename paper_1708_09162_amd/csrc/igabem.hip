@@ -1456,7 +1456,7 @@ struct FarSymArgs {
     int q2;
     const double *nodes;
     double kappa;
-    const double *sctab;  // sin, cos (j pi/64), j < 128 (complex kernel, see sincos_tab)
+    const double *sctab;  // sin, cos (j pi/128), j < 256 (complex kernel, see sincos_tab)
 };
 
 // Mirrored far-field pairs handled by one wave in a row (node data of the next
@@ -1471,13 +1471,16 @@ constexpr int far_mfma_lds() { return 21 * 16 * NTI + 4; }
 
 // LDS doubles per wave for the far-field pairs: the matrix-core path for the
 // real kernel; for the complex one (far_sym_chunk) the pair's target and
-// source nodes (x, y, z, weighted moment re, im), 8 TT each.
+// source nodes (x, y, z, weighted moment re, im) and its column sums (re,
+// im), 8 TT each.
 template <class T, int TT>
 constexpr int far_sym_lds()
 {
     if constexpr (NComp<T>::value == 1) return far_mfma_lds<(TT + 1) / 2>();
-    else return 2 * 5 * 8 * TT;
+    else return 12 * 8 * TT;
 }
+// entries (sin, cos) of the sine/cosine table of the complex far field
+constexpr int kSinCosTab = 256;
 
 // Node data of one cluster's node j for the far field: position and the
 // weighted moment kappa_j X^[j] (padding nodes j >= q2: far from every node,
@@ -1529,17 +1532,26 @@ __device__ inline void helm_far_value(typename std::conditional<RAW, float, doub
     }
 }
 
+// Add v into an LDS word (no return value).
+template <class R>
+__device__ inline void lds_add(R *p, R v)
+{
+    __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+}
+
 // Complex kernel: pairs k0 .. k1-1 of the far field, executed by one whole wave;
 // lds is the wave's slice of far_sym_lds<cd, TT>() doubles (the two clusters'
-// nodes).  Lane (li, lj) owns targets li*TT + ii and sources jj*8 + lj
-// (ii, jj < TT).  The targets go in NP passes of at most TH, so that few of
-// them are held in registers at a time; the column sums of the lane's TT
-// sources stay in registers over the passes.  Row sums are reduced over the 8
-// lanes of a target group and column sums over the 8 groups by lane shuffles,
-// and the owner lanes write the two partial rows (no LDS beyond the nodes).
-// Positions are taken relative to the pair's first target node.  RAW: kernel
-// values and the sums inside the pair in FP32 (positions rounded after the
-// shift, so the rounding is relative to the cluster separation).
+// nodes, then the pair's column sums).  Lane (li, lj) owns targets li*TT + ii
+// and sources jj*8 + lj (ii, jj < TT).  The targets go in NP passes of at most
+// five, so that few of them are held in registers at a time.  For each source
+// the lane's targets are summed in registers, reduced over the 8 lanes li
+// (DPP) and added by lane li = 0 into the source's LDS column sum (eight
+// distinct words per instruction); rows are reduced over the 8 lanes lj by
+// lane shuffles at the end of the pass and written by the owner lanes.  The
+// column sums are written after the last pass.  Positions are taken relative
+// to the pair's first target node.  RAW: kernel values and the sums inside the
+// pair in FP32 (positions rounded after the shift, so the rounding is relative
+// to the cluster separation).
 template <int TT, bool RAW, bool TAB = false>
 __device__ inline void far_sym_chunk(const FarSymArgs &F, int64_t k0, int64_t k1, const cd *__restrict__ Xh,
                                      cd *__restrict__ part, double *lds, const double *tab = nullptr)
@@ -1550,6 +1562,7 @@ __device__ inline void far_sym_chunk(const FarSymArgs &F, int64_t k0, int64_t k1
     constexpr int THL = TT / NP, NH = TT - THL * NP;  // NH passes of THL + 1 targets, NP - NH of THL
     constexpr int THH = NH > 0 ? THL + 1 : THL;
     double *tg = lds, *sr = lds + 5 * W;  // [x | y | z | w.re | w.im] x W each
+    R *csum = (R *)(lds + 10 * W);        // (re, im) x W
     const int q2 = F.q2;
     const R kap = RAW ? (R)(F.kappa * 0.15915494309189535) : (R)F.kappa;  // RAW: turns per unit length
     const double pad = RAW ? 1e4 : 1e100;
@@ -1563,16 +1576,15 @@ __device__ inline void far_sym_chunk(const FarSymArgs &F, int64_t k0, int64_t k1
         d[4 * W + j] = n.w.im;
     };
     for (int64_t k = k0; k < k1; ++k) {
-        // the pair's nodes into LDS (the other waves of the SIMD cover the load latency)
+        // the pair's nodes into LDS (the other waves of the SIMD cover the load latency), sums cleared
         for (int j = lane; j < W; j += 64) {
             stage(tg, j, far_node<cd>(F, Xh, F.up_t[k], j, pad));
             stage(sr, j, far_node<cd>(F, Xh, F.up_s[k], j, -pad));
+            csum[2 * j] = csum[2 * j + 1] = (R)0;
         }
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
         const double cx = tg[0], cy = tg[W], cz = tg[2 * W];
-        // column sums: source jj*8 + lj is owned by lane li == jj % 8 (slot jj / 8)
-        R c0r = (R)0, c0i = (R)0, c1r = (R)0, c1i = (R)0;
         cd *pr = part + (size_t)(2 * k) * q2, *pc = part + (size_t)(2 * k + 1) * q2;
         // one pass over all sources for THP targets per lane starting at t0
         auto pass = [&](auto thp, int t0) {
@@ -1611,14 +1623,9 @@ __device__ inline void far_sym_chunk(const FarSymArgs &F, int64_t k0, int64_t k1
                 }
                 pr_ = group8_sum(pr_);
                 pi_ = group8_sum(pi_);
-                if (li == (jj & 7)) {
-                    if (jj < 8) {
-                        c0r += pr_;
-                        c0i += pi_;
-                    } else {
-                        c1r += pr_;
-                        c1i += pi_;
-                    }
+                if (li == 0) {
+                    lds_add(csum + 2 * j, pr_);
+                    lds_add(csum + 2 * j + 1, pi_);
                 }
             }
             // rows of this pass: reduce over the 8 lanes lj; lane lj == ii writes target ii
@@ -1641,12 +1648,10 @@ __device__ inline void far_sym_chunk(const FarSymArgs &F, int64_t k0, int64_t k1
 #pragma unroll 1
             for (int h = NH; h < NP; ++h) pass(std::integral_constant<int, THL>{}, NH * THH + (h - NH) * THL);
         }
-        {
-            const int j0 = li * 8 + lj, j1 = (li + 8) * 8 + lj;
-            if (li < TT && j0 < q2) pc[j0] = cd{(double)c0r, (double)c0i};
-            if (li + 8 < TT && j1 < q2) pc[j1] = cd{(double)c1r, (double)c1i};
-        }
-        __builtin_amdgcn_wave_barrier();  // every lane has read the nodes before the next staging
+        __builtin_amdgcn_wave_barrier();  // every lane's additions are in before the sums are read
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        for (int j = lane; j < q2; j += 64) pc[j] = cd{(double)csum[2 * j], (double)csum[2 * j + 1]};
+        __builtin_amdgcn_wave_barrier();  // every lane has read the nodes and sums before the next staging
         __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
     }
 }
@@ -1791,39 +1796,14 @@ __global__ void __launch_bounds__(256, NComp<T>::value == 1 ? 3 : 1) k_far_sym(F
     far_chunk<T, TT, RAW>(F, k0, min(k0 + kFarChunk, F.nup), Xh, part, buf[wave]);
 }
 
-// Complex kernel with 65 .. 104 nodes per cluster: one wave per workgroup,
-// chunks of kFarChunk pairs, grid-strided.  The host launches a fixed number
-// of waves per SIMD (kFarWaves), fewer than the registers allow, so that the
-// near-field GEMV on the side stream finds room on every CU.  Measured on the
-// torus (kappa 8, q 10), product with the near GEMV beside it: double, 3 waves
-// 6.29 ms, 2 waves 6.79 (the far field alone 4.13 and 5.74: latency-bound);
-// single, 3 waves 3.58 ms, 2 waves 3.34 (its 91 VGPRs leave room for near waves).
-constexpr int kFarWaves[2] = {3, 2};  // double, single precision
-// Double precision: the sine/cosine table (2 KB) is copied into LDS ahead of the nodes.
-template <class T, int TT, bool RAW>
-__global__ void __launch_bounds__(64, RAW ? 4 : 2) k_far_sym1(FarSymArgs F, const T *__restrict__ Xh, T *__restrict__ part)
-{
-    extern __shared__ double sh[];
-    constexpr int ntab = RAW ? 0 : 256;
-    if constexpr (!RAW) {
-        for (int i = threadIdx.x; i < ntab; i += 64) sh[i] = F.sctab[i];
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-    }
-    const int64_t nch = (F.nup + kFarChunk - 1) / kFarChunk;
-    for (int64_t c = blockIdx.x; c < nch; c += gridDim.x) {
-        const int64_t k0 = c * kFarChunk;
-        far_sym_chunk<TT, RAW, !RAW>(F, k0, min(k0 + kFarChunk, F.nup), Xh, part, sh + ntab, sh);
-    }
-}
-
 // The far-field pairs and the stored near blocks in one launch (ALU-bound and
 // HBM-bound work on the same CUs): nf far workgroups (four waves of kFarChunk
 // pairs) and nn near workgroups (four waves of one block), the near ones spread
 // evenly through the grid (workgroup b is near iff
-// floor((b+1) nn / (nf+nn)) > floor(b nn / (nf+nn))).  The complex kernel with
-// more than 64 nodes per cluster (double precision) takes its sine and cosine
-// from a table staged in LDS per workgroup and is held to three waves per SIMD.
+// floor((b+1) nn / (nf+nn)) > floor(b nn / (nf+nn))); nn = 0 gives the far
+// pairs alone.  The complex kernel with more than 64 nodes per cluster (double
+// precision) takes its sine and cosine from a table staged in LDS per
+// workgroup and is held to three waves per SIMD.
 // BT = cf: the near blocks of the single-precision complex product (FP32 copy, FP64 sums).
 template <class T, int TT, bool RAW, class BT = T>
 __global__ void __launch_bounds__(256, NComp<T>::value == 1 || TT > 8 ? 3 : 1) k_sym_products(FarSymArgs F, NearSymArgs N,
@@ -1834,9 +1814,9 @@ __global__ void __launch_bounds__(256, NComp<T>::value == 1 || TT > 8 ? 3 : 1) k
 {
     extern __shared__ double sh[];
     constexpr bool TAB = NComp<T>::value == 2 && TT > 8 && !RAW;
-    __shared__ double tabs[TAB ? 256 : 1];
+    __shared__ __attribute__((aligned(16))) double tabs[TAB ? 2 * kSinCosTab : 1];
     if constexpr (TAB) {  // before any wave leaves
-        for (int i = threadIdx.x; i < 256; i += blockDim.x) tabs[i] = F.sctab[i];
+        for (int i = threadIdx.x; i < 2 * kSinCosTab; i += blockDim.x) tabs[i] = F.sctab[i];
         __syncthreads();
     }
     const int wave = threadIdx.x >> 6;
@@ -2796,7 +2776,7 @@ struct igb_operator {
     int gord[3] = {0, 0, 0};
     double *rpts = nullptr;        // rhs/potential order geometry
     double *nodes = nullptr;
-    double *sctab = nullptr;       // sin, cos (j pi/64), j < 128, for the complex far field
+    double *sctab = nullptr;       // sin, cos (j pi/128), j < 256, for the complex far field
     hipEvent_t qev[6] = {};        // around the identical, adjacent and regular pair quadrature
     double quad_ms[2] = {0.0, 0.0};  // regular, touching (identical + adjacent) pair quadrature
     double *zdev = nullptr;        // Chebyshev nodes
@@ -3050,10 +3030,10 @@ static NearSymArgs near_args(const igb_operator *op)
 template <class T, int TT, bool RAW>
 static void launch_far_sym_p(igb_operator *op, const T *Xh, const T *xs, bool fuse)
 {
-    // far pairs and near blocks in one launch; the single-precision complex product reads the FP32 copy
-    // of the near blocks when there is one
-    auto fused = [&]() {
-        const int64_t nf = (op->nup + 4 * kFarChunk - 1) / (4 * kFarChunk), nn = (op->nsb + 3) / 4;
+    // far pairs and near blocks in one launch (with_near false: the far pairs alone); the single-precision
+    // complex product reads the FP32 copy of the near blocks when there is one
+    auto fused = [&](bool with_near) {
+        const int64_t nf = (op->nup + 4 * kFarChunk - 1) / (4 * kFarChunk), nn = with_near ? (op->nsb + 3) / 4 : 0;
         const size_t shm = 4 *
                            std::max<size_t>((size_t)near_sym_lds(op->s.nl, op->near_ld) * NComp<T>::value,
                                             (size_t)far_sym_lds<T, TT>()) * 8;
@@ -3068,26 +3048,12 @@ static void launch_far_sym_p(igb_operator *op, const T *Xh, const T *xs, bool fu
         hipLaunchKernelGGL((k_sym_products<T, TT, RAW>), dim3((unsigned)(nf + nn)), dim3(256), shm, op->st, far_args(op),
                            near_args(op), nf, nn, Xh, (T *)op->fpart, (const T *)op->nearb, xs, (T *)op->npart);
     };
-    if (TT > 8 && fuse) {
-        fused();
+    if (TT > 8 || fuse) {
+        fused(fuse);
         return;
     }
-    if constexpr (TT > 8) {  // one wave per workgroup (LDS slice of far_sym_lds doubles)
-        (void)fuse;
-        const size_t shm = ((size_t)far_sym_lds<T, TT>() + (RAW ? 0 : 256)) * sizeof(double);
-        const int64_t nch = (op->nup + kFarChunk - 1) / kFarChunk;
-        const int64_t grid = std::min<int64_t>(nch, (int64_t)op->ncu * 4 * kFarWaves[RAW ? 1 : 0]);
-        hipLaunchKernelGGL((k_far_sym1<T, TT, RAW>), dim3((unsigned)grid), dim3(64), shm, op->st, far_args(op), Xh,
-                           (T *)op->fpart);
-    } else {
-        if (!fuse) {
-            hipLaunchKernelGGL((k_far_sym<T, TT, RAW>),
-                               dim3((unsigned)((op->nup + 4 * kFarChunk - 1) / (4 * kFarChunk))), dim3(256), 0, op->st,
-                               far_args(op), Xh, (T *)op->fpart);
-            return;
-        }
-        fused();
-    }
+    hipLaunchKernelGGL((k_far_sym<T, TT, RAW>), dim3((unsigned)((op->nup + 4 * kFarChunk - 1) / (4 * kFarChunk))),
+                       dim3(256), 0, op->st, far_args(op), Xh, (T *)op->fpart);
 }
 
 template <class T, int TT>
@@ -3514,10 +3480,10 @@ static igb_status assemble(igb_operator *op)
     op->coup_bytes = nfar * q2 * q2 * (int64_t)sizeof(T);
     if ((rc = dalloc(op, (void **)&op->nodes, (size_t)ncl_all * q2 * 4 * sizeof(double)))) return rc;
     if (op->cplx) {
-        // one period of sine and cosine at multiples of pi/64, from extended-precision host values
-        std::vector<double> tab(256);
-        for (int j = 0; j < 128; ++j) {
-            const long double a = (long double)j * 3.141592653589793238462643383279502884L / 64.0L;
+        // one period of sine and cosine at multiples of pi/128, from extended-precision host values
+        std::vector<double> tab(2 * kSinCosTab);
+        for (int j = 0; j < kSinCosTab; ++j) {
+            const long double a = (long double)j * 3.141592653589793238462643383279502884L / 128.0L;
             tab[2 * j] = (double)sinl(a);
             tab[2 * j + 1] = (double)cosl(a);
         }

@@ -73,25 +73,29 @@ __host__ __device__ inline void sincos_red(double t, double *sn, double *cs)
     *cs = __builtin_bit_cast(double, __builtin_bit_cast(unsigned long long, cy) ^ flip);
 }
 
-// sin t and cos t for 0 <= t <= 2^19 from a table tab[2 j] = sin(j pi/64), tab[2 j + 1] = cos(j pi/64),
-// j < 128 (one period): t = n pi/64 + y with |y| <= pi/128 (Cody-Waite reduction with pi/64 = C1 + C2:
-// C1 has 29 bits, so n C1 is exact for n < 2^24 and t - n C1 is exact by Sterbenz; C2 is the rest rounded
-// to 53 bits and enters by one fused multiply-add, leaving |n (pi/64 - C1 - C2)| < 6e-21), sin y and cos y
-// by their Taylor series through y^7 and y^6 (truncation below 4e-18), then the angle-sum formulas with
-// entry j = n mod 128.  Seventeen double operations against twenty-nine for sincos_red.
+// sin t and cos t for 0 <= t <= 2^19 from a table of 256 pairs tab[j] = (sin(j pi/128), cos(j pi/128)),
+// j < 256 (one period, 16-byte aligned): t = n pi/128 + y with |y| <= pi/256 (Cody-Waite reduction with
+// pi/128 = C1 + C2: C1 has 29 bits, so n C1 is exact for n < 2^24 and t - n C1 is exact by Sterbenz; C2
+// is the rest rounded to 53 bits and enters by one fused multiply-add, leaving |n (pi/128 - C1 - C2)| <
+// 6e-21), sin y by its Taylor series through y^5 and cos y - 1 through y^6 (truncation below 1e-17), then
+// the angle-sum formulas sin(a + y) = sin a (1 + (cos y - 1)) + cos a sin y and cos(a + y) = cos a (1 +
+// (cos y - 1)) - sin a sin y with entry j = n mod 256.  Fifteen double operations against twenty-nine
+// for sincos_red.
+typedef double v2d_tab __attribute__((ext_vector_type(2)));
 __device__ inline void sincos_tab(double t, const double *tab, double *sn, double *cs)
 {
-    const double m = fma(t, 0x1.45f306dc9c883p+4, 0x1.8p52);  // t (64/pi) + 1.5 2^52: n in the low bits
+    const double m = fma(t, 0x1.45f306dc9c883p+5, 0x1.8p52);  // t (128/pi) + 1.5 2^52: n in the low bits
     const double n = m - 0x1.8p52;
-    double y = fma(-n, 0x1.921fb54p-5, t);
-    y = fma(-n, 0x1.10b4611a62633p-35, y);
-    const int j = (int)(__builtin_bit_cast(unsigned long long, m) & 127u);
-    const double sa = tab[2 * j], ca = tab[2 * j + 1];
+    double y = fma(-n, 0x1.921fb54p-6, t);
+    y = fma(-n, 0x1.10b4611a62633p-36, y);
+    const int j = (int)(__builtin_bit_cast(unsigned long long, m) & 255u);
+    const v2d_tab e = reinterpret_cast<const v2d_tab *>(tab)[j];
+    const double sa = e.x, ca = e.y;
     const double z = y * y;
-    const double sy = fma(y * z, fma(z, fma(z, -0x1.a01a01a01a01ap-13, 0x1.1111111111111p-7), -0x1.5555555555555p-3), y);
-    const double cy = fma(z * z, fma(z, -0x1.6c16c16c16c17p-10, 0x1.5555555555555p-5), fma(z, -0.5, 1.0));
-    *sn = fma(sa, cy, ca * sy);
-    *cs = fma(ca, cy, -(sa * sy));
+    const double sy = fma(y * z, fma(z, 0x1.1111111111111p-7, -0x1.5555555555555p-3), y);
+    const double cm = z * fma(z, fma(z, -0x1.6c16c16c16c17p-10, 0x1.5555555555555p-5), -0.5);
+    *sn = fma(sa, cm, fma(ca, sy, sa));
+    *cs = fma(ca, cm, fma(-sa, sy, ca));
 }
 
 // Fundamental solutions of Sec. 3.1 (eq. fundament1 / fundament2) at distance r.

@@ -1179,8 +1179,9 @@ __device__ inline double load1(const double *p) { return *p; }
 // li == kc % 8 in slot kc / 8.  Writes the same partial rows as near_sym_wave.
 // RPL = 8 (whole 64-row tiles) fits blocks of 64 and 256 functions; 144 (p = 2,
 // 16 elements per leaf) takes RPL = 9, two full tiles instead of 64 + 64 + 16
-// rows, and 36 takes RPL = 5.
-template <class T, int S, class BT = T, int RPL = 8>
+// rows, and 36 takes RPL = 5.  U columns go per step, their loads issued
+// together (the single-precision copy of the 144 blocks: RPL = 6, U = 2).
+template <class T, int S, class BT = T, int RPL = 8, int U = 1>
 __device__ inline void near_sym_wave_reg(const NearSymArgs &N, int64_t k, const BT *__restrict__ blocks,
                                          const T *__restrict__ x, T *__restrict__ part)
 {
@@ -1204,30 +1205,42 @@ __device__ inline void near_sym_wave_reg(const NearSymArgs &N, int64_t k, const 
             xr[r] = r0 + r < nl ? xt[r0 + r] : zero<T>();
             ra[r] = zero<T>();
         }
-        for (int kc = 0; kc < ncs; ++kc) {
-            const int c = lj + 8 * kc;
-            T cs = zero<T>();
-            if (rows) {
-                T v[RPL];
-                if constexpr (RPL == 8) {
-                    load8(B + (int64_t)c * ld + r0, v);
+        for (int kc = 0; kc < ncs; kc += U) {
+            // U columns per step: all their loads are issued before the products
+            T v[U][RPL], xc[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int c = lj + 8 * (kc + u);
+                if (rows && kc + u < ncs) {
+                    if constexpr (RPL == 8) {
+                        load8(B + (int64_t)c * ld + r0, v[u]);
+                    } else {
+                        // rows past nl of the last tile read padding inside the column (ld >= 8 RPL tiles is
+                        // not guaranteed, so those loads are skipped)
+#pragma unroll
+                        for (int r = 0; r < RPL; ++r)
+                            v[u][r] = r0 + r < nl ? load1(B + (int64_t)c * ld + r0 + r) : zero<T>();
+                    }
+                    xc[u] = xsrc[c];
                 } else {
-                    // rows past nl of the last tile read padding inside the column (ld >= 8 RPL tiles is
-                    // not guaranteed, so those loads are skipped)
 #pragma unroll
-                    for (int r = 0; r < RPL; ++r) v[r] = r0 + r < nl ? load1(B + (int64_t)c * ld + r0 + r) : zero<T>();
-                }
-                const T xc = xsrc[c];
-#pragma unroll
-                for (int r = 0; r < RPL; ++r) {
-                    ra[r] += v[r] * xc;
-                    cs += v[r] * xr[r];
+                    for (int r = 0; r < RPL; ++r) v[u][r] = zero<T>();
+                    xc[u] = zero<T>();
                 }
             }
-            cs = group8_sum(cs);
 #pragma unroll
-            for (int q = 0; q < S; ++q)
-                if (li == (kc & 7) && (kc >> 3) == q) own[q] += cs;
+            for (int u = 0; u < U; ++u) {
+                T cs = zero<T>();
+#pragma unroll
+                for (int r = 0; r < RPL; ++r) {
+                    ra[r] += v[u][r] * xc[u];
+                    cs += v[u][r] * xr[r];
+                }
+                cs = group8_sum(cs);
+#pragma unroll
+                for (int q = 0; q < S; ++q)
+                    if (li == ((kc + u) & 7) && ((kc + u) >> 3) == q) own[q] += cs;
+            }
         }
 #pragma unroll
         for (int r = 0; r < RPL; ++r) {
@@ -1283,7 +1296,7 @@ __device__ inline void near_sym_block_c32(const NearSymArgs &N, int64_t k, const
     if (N.nl == 36) near_sym_wave_reg<cd, 1, cf, 5>(N, k, blocks, x, part);
     else if (N.nl <= 64) near_sym_wave_reg<cd, 1, cf>(N, k, blocks, x, part);
     else if (N.nl <= 128) near_sym_wave_reg<cd, 2, cf>(N, k, blocks, x, part);
-    else if (N.nl == 144) near_sym_wave_reg<cd, 3, cf, 9>(N, k, blocks, x, part);
+    else if (N.nl == 144) near_sym_wave_reg<cd, 3, cf, 6, 2>(N, k, blocks, x, part);  // two columns in flight
     else if (N.nl <= 192) near_sym_wave_reg<cd, 3, cf>(N, k, blocks, x, part);
     else near_sym_wave_reg<cd, 4, cf>(N, k, blocks, x, part);
 }

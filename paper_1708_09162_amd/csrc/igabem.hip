@@ -130,6 +130,15 @@ __device__ inline void near_targets(const int32_t *sb, const PairRec &R, int64_t
     out2 = b2 >= 0 ? blocks + (int64_t)b2 * bsz : nullptr;
 }
 
+// 1/sqrt(r2) for finite r2 > 0: the hardware estimate refined by the
+// second-order expansion of (1 - e)^(-1/2) = 1 + e/2 + 3e^2/8, e = 1 - r2 y^2.
+__device__ inline double rsqrt_pos(double r2)
+{
+    double y = __builtin_amdgcn_rsq(r2);
+    double e = fma(-r2 * y, y, 1.0);
+    return fma(y * e, fma(e, 0.375, 0.5), y);
+}
+
 // Well separated pairs: tensor Gauss of order g in all four variables.
 // One workgroup per pair; kernel rows K(x_i, .) are formed by thread i and
 // contracted with the Bernstein values of F, then with those of E.
@@ -165,8 +174,17 @@ __global__ void __launch_bounds__(128) k_near_regular(const PairRec *__restrict_
         double x0 = X[4 * i], x1 = X[4 * i + 1], x2 = X[4 * i + 2];
         for (int j = 0; j < gg; ++j) {
             double d0 = x0 - Y[4 * j], d1 = x1 - Y[4 * j + 1], d2 = x2 - Y[4 * j + 2];
-            double r = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
-            T k = green<T>(r, kappa) * Y[4 * j + 3];
+            // the kernel value (eq. fundament1 / fundament2) from one refined reciprocal square root
+            const double r2 = d0 * d0 + d1 * d1 + d2 * d2, ir = rsqrt_pos(r2);
+            const double f = 0.07957747154594767 * ir * Y[4 * j + 3];
+            T k;
+            if constexpr (NComp<T>::value == 2) {
+                double sn, cs;
+                sincos_red(kappa * (r2 * ir), &sn, &cs);
+                k = T{cs * f, sn * f};
+            } else {
+                k = f;
+            }
             const double *ps = psi + j * NLOC;
 #pragma unroll
             for (int b = 0; b < NLOC; ++b) acc[b] += k * ps[b];
@@ -185,15 +203,6 @@ __global__ void __launch_bounds__(128) k_near_regular(const PairRec *__restrict_
         if (out1) out1[blk_pos(ld, NLOC, R.elE, a, R.elF, b)] = s;
         if (out2) out2[blk_pos(ld, NLOC, R.elF, b, R.elE, a)] = s;
     }
-}
-
-// 1/sqrt(r2) for finite r2 > 0: the hardware estimate refined by the
-// second-order expansion of (1 - e)^(-1/2) = 1 + e/2 + 3e^2/8, e = 1 - r2 y^2.
-__device__ inline double rsqrt_pos(double r2)
-{
-    double y = __builtin_amdgcn_rsq(r2);
-    double e = fma(-r2 * y, y, 1.0);
-    return fma(y * e, fma(e, 0.375, 0.5), y);
 }
 
 // Line-contraction tiles (see tile_fix): for every element, the tile with both

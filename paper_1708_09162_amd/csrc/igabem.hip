@@ -2067,14 +2067,24 @@ __global__ void k_pot_prep(Layout lo, int nelem, int g, const double *__restrict
 template <class T>
 __global__ void __launch_bounds__(256) k_pot_eval(int64_t npts, const double *__restrict__ X, int64_t nsrc,
                                                   const double *__restrict__ rp, const T *__restrict__ c, double kappa,
-                                                  int64_t chunk, T *__restrict__ part)
+                                                  int64_t chunk, T *__restrict__ part, const double *__restrict__ tab,
+                                                  double hx, double hy, double hz, double hr)
 {
+    constexpr bool CPLX = NComp<T>::value == 2;
     __shared__ double sy[256 * 3];
     __shared__ T sc[256];
+    __shared__ __attribute__((aligned(16))) double stab[CPLX ? 2 * kSinCosTab : 1];
+    if constexpr (CPLX)
+        for (int i = threadIdx.x; i < 2 * kSinCosTab; i += blockDim.x) stab[i] = tab[i];
     int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int64_t s0 = (int64_t)blockIdx.y * chunk, s1 = s0 + chunk < nsrc ? s0 + chunk : nsrc;
     double px = 0, py = 0, pz = 0;
     if (x < npts) { px = X[3 * x]; py = X[3 * x + 1]; pz = X[3 * x + 2]; }
+    // a point within 2^19 / kappa of the ball (hx, hy, hz; hr) around the surface has every phase
+    // kappa |x - y| below 2^19: refined reciprocal square root and table sine and cosine; farther
+    // points take the library's square root, sine and cosine
+    const double hd = sqrt((px - hx) * (px - hx) + (py - hy) * (py - hy) + (pz - hz) * (pz - hz));
+    const bool fast = kappa * (hd + hr) < 0x1p19;
     T acc = zero<T>();
     for (int64_t b = s0; b < s1; b += 256) {
         int64_t q = b + threadIdx.x;
@@ -2086,9 +2096,25 @@ __global__ void __launch_bounds__(256) k_pot_eval(int64_t npts, const double *__
         }
         __syncthreads();
         int nb = (int)((s1 - b) < 256 ? (s1 - b) : 256);
-        for (int k = 0; k < nb; ++k) {
-            double d0 = px - sy[3 * k], d1 = py - sy[3 * k + 1], d2 = pz - sy[3 * k + 2];
-            acc += green_any<T>(sqrt(d0 * d0 + d1 * d1 + d2 * d2), kappa) * sc[k];
+        if (fast) {
+            for (int k = 0; k < nb; ++k) {
+                double d0 = px - sy[3 * k], d1 = py - sy[3 * k + 1], d2 = pz - sy[3 * k + 2];
+                const double r2 = d0 * d0 + d1 * d1 + d2 * d2;
+                const double ir = r2 > 0.0 ? rsqrt_pos(r2) : __builtin_inf();
+                const double f = 0.07957747154594767 * ir;
+                if constexpr (CPLX) {
+                    double sn, cs;
+                    sincos_tab(kappa * (r2 * ir), stab, &sn, &cs);
+                    acc += T{cs * f, sn * f} * sc[k];
+                } else {
+                    acc += f * sc[k];
+                }
+            }
+        } else {
+            for (int k = 0; k < nb; ++k) {
+                double d0 = px - sy[3 * k], d1 = py - sy[3 * k + 1], d2 = pz - sy[3 * k + 2];
+                acc += green_any<T>(sqrt(d0 * d0 + d1 * d1 + d2 * d2), kappa) * sc[k];
+            }
         }
         __syncthreads();
     }
@@ -4709,9 +4735,11 @@ static igb_status potential_launch(igb_operator *op, const T *w, int64_t npts, c
                        op->gx + s.goff[s.grhs], op->rpts, (const T *)op->xs, (T *)op->potc);
     LAUNCHCHK();
     if (npts == 0) return IGB_OK;
+    if (NComp<T>::value == 2 && !op->sctab) return fail(IGB_EHIP, "potential: sine/cosine table missing");
     const int64_t tb = (npts + 255) / 256, chunk = (nq + nchunk - 1) / nchunk;
     hipLaunchKernelGGL((k_pot_eval<T>), dim3((unsigned)tb, (unsigned)nchunk), dim3(256), 0, op->st, npts, X, nq, op->rpts,
-                       (const T *)op->potc, s.kappa, chunk, part);
+                       (const T *)op->potc, s.kappa, chunk, part, (const double *)op->sctab, s.hull_c[0], s.hull_c[1],
+                       s.hull_c[2], s.hull_r);
     LAUNCHCHK();
     hipLaunchKernelGGL((k_pot_reduce<T>), dim3((unsigned)tb), dim3(256), 0, op->st, npts, (int)nchunk, (const T *)part, u);
     LAUNCHCHK();

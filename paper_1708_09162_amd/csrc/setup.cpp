@@ -879,21 +879,22 @@ std::string build_setup_tiles(const Geometry &geo, const igb_params &prm, Setup 
         (prm.mode != IGB_H2_ONTHEFLY || prm.q * prm.q > (prm.kernel == IGB_HELMHOLTZ ? 104 : 64)))
         return "far_precision IGB_FP32 needs on-the-fly coupling and q <= 8 (Laplace) or q <= 10 (Helmholtz)";
     if (prm.leaf_depth < -1 || prm.leaf_depth > 10) return "leaf_depth outside -1..10";
-    if (prm.kernel == IGB_HELMHOLTZ) {
-        // the kernels reduce the phase kappa |x - y| between surface points for |kappa r| < 2^19; the
-        // surface lies in the hull of its control points, whose bounding box bounds |x - y|
-        double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
-        for (const auto &pt : geo.patches)
-            for (size_t i = 0; i + 3 < pt.cpw.size(); i += 4)
-                for (int c = 0; c < 3; ++c) {
-                    lo[c] = std::min(lo[c], pt.cpw[i + c]);
-                    hi[c] = std::max(hi[c], pt.cpw[i + c]);
-                }
-        double d2 = 0.0;
-        for (int c = 0; c < 3; ++c) d2 += (hi[c] - lo[c]) * (hi[c] - lo[c]);
-        if (prm.wavenumber * std::sqrt(d2) >= 262144.0)
-            return "wavenumber times the size of the geometry must stay below 2^18";
-    }
+    // the surface lies in the hull of its control points, whose bounding box bounds |x - y| between
+    // surface points (and places the surface in a ball for the potential's phase range)
+    double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+    for (const auto &pt : geo.patches)
+        for (size_t i = 0; i + 3 < pt.cpw.size(); i += 4)
+            for (int c = 0; c < 3; ++c) {
+                lo[c] = std::min(lo[c], pt.cpw[i + c]);
+                hi[c] = std::max(hi[c], pt.cpw[i + c]);
+            }
+    double d2 = 0.0;
+    for (int c = 0; c < 3; ++c) d2 += (hi[c] - lo[c]) * (hi[c] - lo[c]);
+    // the kernels reduce the phase kappa |x - y| between surface points for |kappa r| < 2^19
+    if (prm.kernel == IGB_HELMHOLTZ && prm.wavenumber * std::sqrt(d2) >= 262144.0)
+        return "wavenumber times the size of the geometry must stay below 2^18";
+    for (int c = 0; c < 3; ++c) s.hull_c[c] = 0.5 * (lo[c] + hi[c]);
+    s.hull_r = 0.5 * std::sqrt(d2);
 
     s.kernel = prm.kernel;
     s.kappa = prm.kernel == IGB_HELMHOLTZ ? prm.wavenumber : 0.0;

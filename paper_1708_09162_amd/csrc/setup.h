@@ -41,6 +41,7 @@ struct Setup {
     int p = 0, m = 0, q = 1, d = 0, L = 0;
     double eta = 1.0;
     double kappa_diam = 0.0;  // > 0: blocks with kappa max(diam) above it are not admissible
+    double hull_c[3] = {0.0, 0.0, 0.0}, hull_r = 0.0;  // ball around the control points' bounding box
     int g0 = 6, gs = 8, grhs = 6;
     int mode = 0;
     // derived sizes

@@ -293,6 +293,31 @@ def point_source_twin(torch, W, cfg, op, grid_dev):
     return twin
 
 
+def potential_h2_leg(torch, W, op, w, grid_dev, n_large=1 << 20):
+    """The potential of the step's density on the grid by the direct sum (the step's own evaluator) and
+    with the far field interpolated (igb_potential_h2), and the interpolated one on a large point set."""
+    def timed(f, pts, reps=5):
+        f(w, pts[:64])
+        ts = []
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            u = f(w, pts)
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        return u, float(np.median(ts))
+    ud, td = timed(op.potential, grid_dev)
+    uh, th = timed(op.potential_h2, grid_dev)
+    d = (uh - ud).abs().max().item() / ud.abs().max().item()
+    rng = np.random.default_rng(2)
+    big = torch.tensor(4.0 * W.random_directions(n_large, 5) * rng.uniform(0.8, 1.5, size=(n_large, 1)),
+                       device="cuda:0")
+    _, tb = timed(op.potential_h2, big, reps=2)
+    return {"grid_points": int(grid_dev.shape[0]), "direct_ms": round(1e3 * td, 3), "h2_ms": round(1e3 * th, 3),
+            "max_rel_diff_vs_direct": d, "large_set_points": n_large, "large_set_h2_ms": round(1e3 * tb, 2),
+            "large_set": "points at distance 3.2-6 from the torus centre in seeded random directions"}
+
+
 def lambda_ps(torch, vt, k):
     def g(pts):
         d = torch.linalg.norm(pts - vt, dim=1)
@@ -707,6 +732,10 @@ def main():
     mv, stages, sep, roofs, twin = c3_details(torch, igb, W, geo, cfg, op, grid_dev, args.matvec_reps)
     if args.no_twin:
         twin = None
+    pot_h2 = potential_h2_leg(torch, W, op, w, grid_dev)
+    log(f"potential on the grid: direct {pot_h2['direct_ms']} ms, interpolated far field {pot_h2['h2_ms']} ms "
+        f"(max rel diff {pot_h2['max_rel_diff_vs_direct']:.1e}); {pot_h2['large_set_points']} points "
+        f"{pot_h2['large_set_h2_ms']} ms")
     mean = {k: float(np.mean([t[k] for t in times])) for k in times[0]} if times else {}
     out = {
         "metric": METRIC,
@@ -740,6 +769,7 @@ def main():
         "near_blocks": int(op.info.n_near_blocks),
         "far_blocks": int(op.info.n_far_blocks),
         "point_source_twin": twin,
+        "potential_h2": pot_h2,
         "near_quadrature": near_quadrature(op, True, C3["p"]),
         "roofline": roofs["fused"] if "fused" in roofs else roofs["far_field"],
         "roofline_stages": roofs,

@@ -357,6 +357,26 @@ igb_status igb_potential(const igb_operator *op, const void *w_dev, int64_t n_pt
 igb_status igb_potential_noalloc(const igb_operator *op, const void *w_dev, int64_t n_pts, const double *xyz_dev,
                                  void *u_dev);
 
+/* The potential of igb_potential with the far field interpolated (Sec. 4.2
+ * applied to eq. eq::repform), for large point sets: the density's moments at
+ * the Chebyshev nodes of every cluster come from the operator's upward pass;
+ * from the coarsest far-field level down, a cluster s is used through its
+ * nodes when diam(s) < eta (|x - c_s| - r_s) (c_s, r_s: centre and radius of
+ * its surface grid, eta the operator's) and, for Helmholtz, kappa diam(s)
+ * <= 4 (or the operator's kappa_diam if smaller), so that the phase is
+ * interpolated over at most 2/3 of a wavelength; else its children are
+ * visited, and
+ * leaves never admitted are summed directly over their quadrature points
+ * (Gauss order gauss_rhs).  The error against igb_potential is that of the
+ * interpolation, falling with q.  Same arguments, layout and errors as
+ * igb_potential; synchronous.  An operator without far-field levels (dense,
+ * or a tree too shallow) and a point whose traversal would hold more than
+ * 1024 clusters of one level fall back to the direct sum of igb_potential.
+ * The first call on an operator uploads its cluster bounds (5 doubles per
+ * cluster), kept until igb_operator_destroy. */
+igb_status igb_potential_h2(const igb_operator *op, const void *w_dev, int64_t n_pts, const double *xyz_dev,
+                            void *u_dev);
+
 /* Timing of the superspace matvec by stage: runs `reps` products on the
  * operator's internal work vectors with HIP events recorded on its stream
  * between stages and writes the mean milliseconds per stage to

@@ -2121,6 +2121,138 @@ __global__ void __launch_bounds__(256) k_pot_eval(int64_t npts, const double *__
     if (x < npts) part[(int64_t)blockIdx.y * npts + x] = acc;
 }
 
+// Sum over the 64 lanes of a wave (every lane gets it).
+__device__ inline double wave_sum64(double s)
+{
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+    return s;
+}
+__device__ inline cd wave_sum64(cd s) { return {wave_sum64(s.re), wave_sum64(s.im)}; }
+
+// The potential with the far field interpolated (the H2 approximation of Sec. 4.2 applied to the point
+// evaluation of Sec. 3.1, eq. eq::repform): from the clusters of the coarsest far-field level down, a
+// cluster s is admissible for the point x when diam(s) < eta (|x - c_s| - r_s) (centre c_s and radius r_s
+// of its surface grid) and kappa diam(s) <= kappa_diam (kPotKappaDiam, or the operator's smaller
+// wavenumber option: the interpolation of exp(i kappa r) over the cluster then stays accurate); it then
+// contributes sum_nu G(x, F(xi_nu)) kappa(xi_nu) X^_nu at its Chebyshev nodes
+// (moments X^ of the density from the upward pass), else its children are visited; leaves that are never
+// admissible contribute the direct sum over their quadrature points.  One wave per point: the lanes test
+// 64 candidate clusters at a time, then evaluate the admissible clusters' nodes and the near leaves'
+// points together.  A level with more than kH2Cap candidates sets *flag and leaves the point unwritten.
+constexpr int kH2Cap = 1024;
+// kappa diam(s) of the clusters the Helmholtz potential interpolates: Chebyshev interpolation of the phase
+// over a cluster of kappa diam = 4 errs by about (kappa diam / 2)^q / (2^(q-1) q!), 5e-7 at q = 10
+constexpr double kPotKappaDiam = 4.0;
+constexpr int kH2MaxLevel = 15;
+struct PotH2Args {
+    int lmin, L, npatch, q2, ne, side, gg;
+    int64_t cl_off[kH2MaxLevel + 2];
+    const double *clg;    // per global cluster: centre (3), radius, diameter
+    const double *nodes;  // per global cluster: q2 x (x, y, z, surface measure)
+    const void *Xh;       // moments, q2 per global cluster
+    const double *rp;     // quadrature points of the potential rule (x, y, z, weight)
+    const void *c;        // weighted density at them
+    double eta, kappa, kappa_diam, hx, hy, hz, hr;
+    const double *tab;
+    int *flag;
+};
+
+template <class T>
+__global__ void __launch_bounds__(256) k_pot_h2(int64_t npts, const double *__restrict__ X, PotH2Args A,
+                                                T *__restrict__ u)
+{
+    constexpr bool CPLX = NComp<T>::value == 2;
+    __shared__ int32_t lists[4][2][kH2Cap];
+    __shared__ __attribute__((aligned(16))) double stab[CPLX ? 2 * kSinCosTab : 1];
+    if constexpr (CPLX)
+        for (int i = threadIdx.x; i < 2 * kSinCosTab; i += blockDim.x) stab[i] = A.tab[i];
+    __syncthreads();
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t x = (int64_t)blockIdx.x * 4 + wave;
+    if (x >= npts) return;  // whole waves; no barrier follows
+    const double px = X[3 * x], py = X[3 * x + 1], pz = X[3 * x + 2];
+    const double hd = sqrt((px - A.hx) * (px - A.hx) + (py - A.hy) * (py - A.hy) + (pz - A.hz) * (pz - A.hz));
+    const bool fast = A.kappa * (hd + A.hr) < 0x1p19;  // every phase in the range of the table sine/cosine
+    const T *Xh = (const T *)A.Xh, *cq = (const T *)A.c;
+    auto gval = [&](double y0, double y1, double y2) -> T {
+        const double d0 = px - y0, d1 = py - y1, d2 = pz - y2;
+        const double r2 = d0 * d0 + d1 * d1 + d2 * d2;
+        if (fast) {
+            const double ir = r2 > 0.0 ? rsqrt_pos(r2) : __builtin_inf();
+            const double f = 0.07957747154594767 * ir;
+            if constexpr (CPLX) {
+                double sn, cs;
+                sincos_tab(A.kappa * (r2 * ir), stab, &sn, &cs);
+                return T{cs * f, sn * f};
+            } else {
+                return f;
+            }
+        }
+        return green_any<T>(sqrt(r2), A.kappa);
+    };
+    T acc = zero<T>();
+    int32_t *cur = lists[wave][0], *nxt = lists[wave][1];
+    int ncur = A.npatch << (2 * A.lmin);  // the coarsest level: every cluster, by index
+    bool all = true;
+    for (int l = A.lmin; l <= A.L && ncur > 0; ++l) {
+        const int n = 1 << l;
+        int nnext = 0;
+        for (int base = 0; base < ncur; base += 64) {
+            const int k = base + lane;
+            const bool valid = k < ncur;
+            const int c = valid ? (all ? k : cur[k]) : 0;
+            bool adm = false;
+            if (valid) {
+                const double *cg = A.clg + (A.cl_off[l] + c) * 5;
+                const double dc = sqrt((px - cg[0]) * (px - cg[0]) + (py - cg[1]) * (py - cg[1]) +
+                                       (pz - cg[2]) * (pz - cg[2]));
+                adm = dc - cg[3] > 0.0 && cg[4] < A.eta * (dc - cg[3]) && A.kappa * cg[4] <= A.kappa_diam;
+            }
+            const unsigned long long mfar = __ballot(valid && adm);
+            const unsigned long long mnear = __ballot(valid && !adm && l == A.L);
+            const unsigned long long msplit = __ballot(valid && !adm && l < A.L);
+            if (valid && !adm && l < A.L) {  // the four children, in lane order
+                const int pos = nnext + 4 * __popcll(msplit & ((1ull << lane) - 1ull));
+                const int patch = c / (n * n), r = c % (n * n), k2 = r / n, k1 = r % n, nn = 2 * n;
+                for (int a = 0; a < 4; ++a)
+                    if (pos + a < kH2Cap) nxt[pos + a] = patch * nn * nn + (2 * k2 + (a >> 1)) * nn + 2 * k1 + (a & 1);
+            }
+            nnext += 4 * __popcll(msplit);
+            for (unsigned long long m = mfar; m; m &= m - 1) {  // admissible: the cluster's nodes
+                const int64_t g = A.cl_off[l] + __shfl(c, __ffsll((long long)m) - 1);
+                for (int nu = lane; nu < A.q2; nu += 64) {
+                    const double *nd = A.nodes + (g * A.q2 + nu) * 4;
+                    acc += gval(nd[0], nd[1], nd[2]) * (Xh[g * A.q2 + nu] * nd[3]);
+                }
+            }
+            for (unsigned long long m = mnear; m; m &= m - 1) {  // near leaf: its quadrature points
+                const int cl = __shfl(c, __ffsll((long long)m) - 1);
+                const int patch = cl / (n * n), r = cl % (n * n), k2 = r / n, k1 = r % n;
+                const int row = A.side * A.gg, npl = A.side * row;
+                for (int t = lane; t < npl; t += 64) {
+                    const int64_t kq = ((int64_t)patch * A.ne * A.ne + (int64_t)(k2 * A.side + t / row) * A.ne +
+                                        (int64_t)k1 * A.side) * A.gg + t % row;
+                    const double *y = A.rp + kq * 4;
+                    acc += gval(y[0], y[1], y[2]) * cq[kq];
+                }
+            }
+        }
+        if (nnext > kH2Cap) {  // uniform: the host evaluates these points by the direct sum instead
+            if (lane == 0) *A.flag = 1;
+            return;
+        }
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        int32_t *t = cur;
+        cur = nxt;
+        nxt = t;
+        ncur = nnext;
+        all = false;
+    }
+    acc = wave_sum64(acc);
+    if (lane == 0) u[x] = acc;
+}
+
 template <class T>
 __global__ void k_pot_reduce(int64_t npts, int nchunk, const T *__restrict__ part, T *__restrict__ u)
 {
@@ -2590,12 +2722,6 @@ __global__ void k_div<cd>(int64_t n, const cd *__restrict__ x, const cd *__restr
 // block: block (b, c) takes rows b*256 + u + m*nblk*256 (u < 256), its wave q
 // the vectors j = 4c + q, 4c + q + 4 gridDim.y, ..., reduced with cross-lane
 // shuffles, so no barrier is needed; part[j*nblk + b].
-__device__ inline double wave_sum64(double s)
-{
-    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
-    return s;
-}
-__device__ inline cd wave_sum64(cd s) { return {wave_sum64(s.re), wave_sum64(s.im)}; }
 
 template <class T>
 __global__ void __launch_bounds__(256) k_multidot_partial(int64_t n, int k, const T *__restrict__ V, int64_t ldv,
@@ -2863,6 +2989,7 @@ struct igb_operator {
     void *hdev = nullptr;      // GMRES projection coefficients
     void *mpart = nullptr;     // GMRES multi-dot partial sums
     void *potc = nullptr;      // potential: weighted density at the quadrature points
+    double *clgeo = nullptr;   // H2 potential: cluster bounds (5 per global cluster) and a flag word
     void *tz = nullptr;        // intermediate of the separable T application
     // staged touching-pair blocks (nloc^2 per pair, row-major): identical pairs (E, E) in
     // element order, and the common-edge / common-vertex pairs in (E, F) order
@@ -4764,6 +4891,77 @@ static igb_status potential_impl(igb_operator *op, const T *w, int64_t npts, con
     return IGB_OK;
 }
 
+// The potential with the far field interpolated (k_pot_h2): density to S*, the upward pass to the moments,
+// the weighted density at the quadrature points, then one wave per point.  Without far-field levels, or
+// when a point's traversal overflows, the direct sum.
+template <class T>
+static igb_status potential_h2_impl(igb_operator *op, const T *w, int64_t npts, const double *X, T *u)
+{
+    const Setup &s = op->s;
+    if (op->lmin > s.L || s.L > kH2MaxLevel || s.mode == IGB_DENSE) return potential_impl<T>(op, w, npts, X, u);
+    if (npts == 0) return IGB_OK;
+    if (NComp<T>::value == 2 && !op->sctab) return fail(IGB_EHIP, "potential: sine/cosine table missing");
+    igb_status rc;
+    const int64_t ncl_all = s.cl_off[s.L + 1];
+    if (!op->clgeo) {  // first call: the cluster bounds of the far-field levels
+        std::vector<double> h((size_t)ncl_all * 5 + 1, 0.0), lv;
+        for (int l = op->lmin; l <= s.L; ++l) {
+            cluster_spheres(s, l, lv);
+            std::copy(lv.begin(), lv.end(), h.begin() + s.cl_off[l] * 5);
+        }
+        if ((rc = upload(op, &op->clgeo, h.data(), h.size() * sizeof(double)))) return rc;
+        HIPCHK(hipStreamSynchronize(op->st));  // the host array goes out of scope
+    }
+    if ((rc = apply_Tt<T>(op, w, (T *)op->xs))) return rc;
+    for (const TreeLaunch &t : tree_slices(op, sizeof(T))) {
+        if (t.shm > 64 * 1024) {
+            if (t.shm > 160 * 1024) return fail(IGB_EUNSUPPORTED, "cluster-tree transfers: q too large for LDS");
+            (void)hipFuncSetAttribute((const void *)k_up_tree<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)t.shm);
+        }
+        hipLaunchKernelGGL((k_up_tree<T>), dim3(t.roots), dim3(64 * t.waves), t.shm, op->st, t.A, t.SL,
+                           (const T *)op->xs, (T *)op->Xh);
+        LAUNCHCHK();
+    }
+    const int64_t nq = (int64_t)s.nelem * s.grhs * s.grhs;
+    hipLaunchKernelGGL((k_pot_prep<T>), dim3(nblk(nq, 256)), dim3(256), 0, op->st, op->lo, s.nelem, s.grhs,
+                       op->gx + s.goff[s.grhs], op->rpts, (const T *)op->xs, (T *)op->potc);
+    LAUNCHCHK();
+    int *flag = (int *)(op->clgeo + (size_t)ncl_all * 5);
+    HIPCHK(hipMemsetAsync(flag, 0, sizeof(int), op->st));
+    PotH2Args A{};
+    A.lmin = op->lmin;
+    A.L = s.L;
+    A.npatch = s.npatch;
+    A.q2 = s.q * s.q;
+    A.ne = s.ne;
+    A.side = s.side;
+    A.gg = s.grhs * s.grhs;
+    for (int l = 0; l <= s.L + 1; ++l) A.cl_off[l] = s.cl_off[l];
+    A.clg = op->clgeo;
+    A.nodes = op->nodes;
+    A.Xh = op->Xh;
+    A.rp = op->rpts;
+    A.c = op->potc;
+    A.eta = s.eta;
+    A.kappa = s.kappa;
+    A.kappa_diam = s.kernel == IGB_HELMHOLTZ
+                       ? (s.kappa_diam > 0.0 ? std::min(s.kappa_diam, kPotKappaDiam) : kPotKappaDiam)
+                       : __builtin_inf();
+    A.hx = s.hull_c[0];
+    A.hy = s.hull_c[1];
+    A.hz = s.hull_c[2];
+    A.hr = s.hull_r;
+    A.tab = op->sctab;
+    A.flag = flag;
+    hipLaunchKernelGGL((k_pot_h2<T>), dim3((unsigned)((npts + 3) / 4)), dim3(256), 0, op->st, npts, X, A, u);
+    LAUNCHCHK();
+    int hflag = 0;
+    HIPCHK(hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, op->st));
+    HIPCHK(hipStreamSynchronize(op->st));
+    if (hflag) return potential_impl<T>(op, w, npts, X, u);
+    return IGB_OK;
+}
+
 // Scratch of igb_potential_noalloc: the partial sums of the potential's direct sum, a file-scope device
 // array of kScratchBytes on every device the library runs on (held until the process ends).  Host code
 // never passes the array's name to a kernel: on the first call on a device, with that device current, its
@@ -4825,6 +5023,17 @@ igb_status igb_potential_noalloc(const igb_operator *cop, const void *w_dev, int
     return op->cplx ? potential_launch<cd>(op, (const cd *)w_dev, n_pts, xyz_dev, (cd *)u_dev, (cd *)part, nchunk)
                     : potential_launch<double>(op, (const double *)w_dev, n_pts, xyz_dev, (double *)u_dev,
                                                (double *)part, nchunk);
+}
+
+igb_status igb_potential_h2(const igb_operator *cop, const void *w_dev, int64_t n_pts, const double *xyz_dev,
+                            void *u_dev)
+{
+    CHECK_OP(cop);
+    if (n_pts < 0) return fail(IGB_EINVAL, "n_pts < 0");
+    if (!w_dev || (n_pts > 0 && (!xyz_dev || !u_dev))) return fail(IGB_EINVAL, "null device pointer");
+    igb_operator *op = const_cast<igb_operator *>(cop);
+    return op->cplx ? potential_h2_impl<cd>(op, (const cd *)w_dev, n_pts, xyz_dev, (cd *)u_dev)
+                    : potential_h2_impl<double>(op, (const double *)w_dev, n_pts, xyz_dev, (double *)u_dev);
 }
 
 igb_status igb_export_partition(const igb_operator *op, int32_t *near_host, int32_t *far_host)

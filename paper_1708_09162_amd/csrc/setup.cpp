@@ -460,6 +460,21 @@ static bool admissible(const Setup &s, const LevelGeo &G, int a, int b)
     return true;
 }
 
+void cluster_spheres(const Setup &s, int l, std::vector<double> &out)
+{
+    LevelGeo G;
+    level_geo(s, l, G);
+    const size_t ncl = G.rad.size();
+    out.resize(ncl * 5);
+    for (size_t c = 0; c < ncl; ++c) {
+        out[5 * c] = G.cen[3 * c];
+        out[5 * c + 1] = G.cen[3 * c + 1];
+        out[5 * c + 2] = G.cen[3 * c + 2];
+        out[5 * c + 3] = G.rad[c];
+        out[5 * c + 4] = G.diam[c];
+    }
+}
+
 static void build_partition(Setup &s)
 {
     struct BP { int32_t t, src; };

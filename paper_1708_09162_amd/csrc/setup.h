@@ -100,6 +100,11 @@ std::string build_setup_tiles(const Geometry &g, const igb_params &prm, Setup &s
 void build_setup_elements(Setup &s);
 std::string build_setup_plan(Setup &s);
 
+// Bounds of the clusters of level l (level-local index patch 4^l + k2 2^l + k1), five doubles each: the
+// centre (the cluster's mid parameter point), the largest distance from it to the cluster's 5 x 5 grid of
+// surface points, and the grid's diameter (the quantities of the block admissibility).
+void cluster_spheres(const Setup &s, int l, std::vector<double> &out);
+
 // Touching element pairs (common edge, common vertex, and identical ones when
 // with_identical; E <= F, sorted) from physical corner coincidence alone, without
 // the partition.  Every touching pair lies in the near field, so this list equals

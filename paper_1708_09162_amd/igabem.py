@@ -40,7 +40,7 @@ EXPORTED = [
     "igb_plan_export_pair_classes", "igb_matvec_profile", "igb_release_cached_memory",
     "igb_cnn_create", "igb_cnn_destroy", "igb_cnn_get_weights", "igb_cnn_forward", "igb_cnn_gradient",
     "igb_cnn_training_pairs", "igb_cnn_train", "igb_cnn_train_operator", "igb_solve_fgmres", "igb_solve_many",
-    "igb_potential_noalloc", "igb_solve_fgmres_select",
+    "igb_potential_noalloc", "igb_solve_fgmres_select", "igb_potential_h2",
 ]
 IGB_CNN_NUM_WEIGHTS = 28224
 IGB_CNN_RELU = 0
@@ -107,6 +107,7 @@ def _load():
         "igb_solve": (C.c_int32, [vp, vp, vp, C.c_double, C.c_int32, C.c_int32, C.POINTER(igb_solve_info)]),
         "igb_potential": (C.c_int32, [vp, vp, C.c_int64, vp, vp]),
         "igb_potential_noalloc": (C.c_int32, [vp, vp, C.c_int64, vp, vp]),
+        "igb_potential_h2": (C.c_int32, [vp, vp, C.c_int64, vp, vp]),
         "igb_export_partition": (C.c_int32, [vp, ip, ip]),
         "igb_export_pair_classes": (C.c_int32, [vp, ip]),
         "igb_export_near_block": (C.c_int32, [vp, C.c_int32, C.c_int32, dp]),
@@ -340,6 +341,11 @@ def igb_potential(op, w, xyz, u):
 def igb_potential_noalloc(op, w, xyz, u):
     n = xyz.shape[0]
     _check(_lib.igb_potential_noalloc(op, _ptr(w), int(n), _ptr(xyz) if n else None, _ptr(u) if n else None))
+
+
+def igb_potential_h2(op, w, xyz, u):
+    n = xyz.shape[0]
+    _check(_lib.igb_potential_h2(op, _ptr(w), int(n), _ptr(xyz) if n else None, _ptr(u) if n else None))
 
 
 def igb_export_partition(op, info: igb_info):
@@ -596,6 +602,14 @@ class Operator(_StreamOrdered):
         u, w = self._vec(pts.shape[0]), self._in(w, self.info.n_dof)
         with self._ordered():
             igb_potential(self.h, w, pts, u)
+        return u
+
+    def potential_h2(self, w, points):
+        """Potential with the far field interpolated at the clusters' Chebyshev nodes (igb_potential_h2)."""
+        pts = self.torch.as_tensor(points, dtype=self.torch.float64).to(self.device).reshape(-1, 3).contiguous()
+        u, w = self._vec(pts.shape[0]), self._in(w, self.info.n_dof)
+        with self._ordered():
+            igb_potential_h2(self.h, w, pts, u)
         return u
 
     def potential_noalloc(self, w, points, out):

@@ -1528,7 +1528,8 @@ __device__ inline FarNode<T> far_node(const FarSymArgs &F, const T *__restrict__
 
 // Kernel value G(x, y) 4 pi = exp(i kappa r) / r of the complex far field from r^2.  Double precision:
 // refined reciprocal square root, the phase clamped into the range of sincos_red (padding nodes sit 1e100
-// away; their weight is zero on one side and their value below 1e-100 on the other).  Single precision
+// away; their weight is zero on one side and their value below 1e-100 on the other); with the table
+// (TAB) the caller places the padding nodes so that no clamp is needed.  Single precision
 // (RAW): the hardware reciprocal square root, the phase kappa r / (2 pi) in turns reduced to one turn
 // (v_fract) for the hardware sine and cosine, which take turns.  TAB (double precision): sine and cosine
 // from the table in LDS (sincos_tab) instead of sincos_red.
@@ -1547,7 +1548,7 @@ __device__ inline void helm_far_value(typename std::conditional<RAW, float, doub
     } else {
         const double ir = rsqrt_pos(r2);
         double sn, cs;
-        if constexpr (TAB) sincos_tab(fmin(kap * (r2 * ir), 0x1p19), tab, &sn, &cs);
+        if constexpr (TAB) sincos_tab(kap * (r2 * ir), tab, &sn, &cs);  // phases bounded by the padding
         else sincos_red(fmin(kap * (r2 * ir), 0x1p19), &sn, &cs);
         gr = cs * ir;
         gi = sn * ir;
@@ -1606,7 +1607,38 @@ __device__ inline void far_sym_chunk(const FarSymArgs &F, int64_t k0, int64_t k1
         }
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-        const double cx = tg[0], cy = tg[W], cz = tg[2 * W];
+        {
+            // positions relative to the pair's first target node, in FP64, once per pair
+            const double cx = tg[0], cy = tg[W], cz = tg[2 * W];
+            double ext = 0.0;  // largest relative coordinate of a real node
+            for (int j = lane; j < W; j += 64) {
+                const double a0 = tg[j] - cx, a1 = tg[W + j] - cy, a2 = tg[2 * W + j] - cz;
+                const double b0 = sr[j] - cx, b1 = sr[W + j] - cy, b2 = sr[2 * W + j] - cz;
+                if (j < q2)
+                    ext = fmax(ext, fmax(fmax(fmax(fabs(a0), fabs(a1)), fmax(fabs(a2), fabs(b0))),
+                                         fmax(fabs(b1), fabs(b2))));
+                tg[j] = a0;
+                tg[W + j] = a1;
+                tg[2 * W + j] = a2;
+                sr[j] = b0;
+                sr[W + j] = b1;
+                sr[2 * W + j] = b2;
+            }
+            if constexpr (TAB) {
+                // padding targets to (P, 0, 0), sources to (-P, 0, 0), P four times the pair's extent:
+                // every distance from a padding node stays positive and every phase finite (the table
+                // sine/cosine takes no clamp), and their zero weights cancel them exactly
+                for (int o = 32; o > 0; o >>= 1) ext = fmax(ext, __shfl_xor(ext, o, 64));
+                const double P = fmax(4.0 * ext, 1e-30);
+                for (int j = q2 + lane; j < W; j += 64) {
+                    tg[j] = P;
+                    sr[j] = -P;
+                    tg[W + j] = tg[2 * W + j] = sr[W + j] = sr[2 * W + j] = 0.0;
+                }
+            }
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        }
         cd *pr = part + (size_t)(2 * k) * q2, *pc = part + (size_t)(2 * k + 1) * q2;
         // one pass over all sources for THP targets per lane starting at t0
         auto pass = [&](auto thp, int t0) {
@@ -1615,9 +1647,9 @@ __device__ inline void far_sym_chunk(const FarSymArgs &F, int64_t k0, int64_t k1
 #pragma unroll
             for (int ii = 0; ii < THP; ++ii) {
                 const int i = li * TT + t0 + ii;
-                tx[ii] = (R)(tg[i] - cx);
-                ty[ii] = (R)(tg[W + i] - cy);
-                tz[ii] = (R)(tg[2 * W + i] - cz);
+                tx[ii] = (R)tg[i];
+                ty[ii] = (R)tg[W + i];
+                tz[ii] = (R)tg[2 * W + i];
                 wr[ii] = (R)tg[3 * W + i];
                 wi[ii] = (R)tg[4 * W + i];
                 ar[ii] = ai[ii] = (R)0;
@@ -1625,7 +1657,7 @@ __device__ inline void far_sym_chunk(const FarSymArgs &F, int64_t k0, int64_t k1
 #pragma unroll 1
             for (int jj = 0; jj < TT; ++jj) {
                 const int j = jj * 8 + lj;
-                const R sx = (R)(sr[j] - cx), sy = (R)(sr[W + j] - cy), sz = (R)(sr[2 * W + j] - cz);
+                const R sx = (R)sr[j], sy = (R)sr[W + j], sz = (R)sr[2 * W + j];
                 const R swr = (R)sr[3 * W + j], swi = (R)sr[4 * W + j];
                 R pr_ = (R)0, pi_ = (R)0;
 #pragma unroll

@@ -491,7 +491,7 @@ def test_full_size_helmholtz_torus_sampled_rows():
     torch.cuda.empty_cache()
     rng = np.random.default_rng(14)
     nleaf = 16 * 16 * 16
-    leaves = np.sort(rng.choice(nleaf, 16, replace=False)).astype(np.int32)
+    leaves = np.sort(rng.choice(nleaf, 64, replace=False)).astype(np.int32)  # about a minute of oracle time
     say(f"full size helmholtz: oracle rows for leaves {leaves.tolist()}")
     rows = P.h2_matvec_rows(xs, leaves)
     ne, side, n, nloc = 64, 4, 16, 9

@@ -156,3 +156,46 @@ def test_partition_is_symmetric_and_covers_all_pairs():
     farset = {tuple(map(int, r)) for r in far}
     assert all((lv, s, t) in farset for lv, t, s in farset)
     assert side == 2
+
+
+def _two_squares(gap):
+    """Unit squares [0,1]^2 and [1+gap, 2+gap] x [0,1] in the plane z = 0: every cluster is a square whose
+    diameter (its diagonal) and distances to the other square's clusters have closed forms."""
+    a = W.flat_patch([0, 0, 0], [1, 0, 0], [0, 1, 0], [1, 1, 0])
+    o = 1.0 + gap
+    b = W.flat_patch([o, 0, 0], [o + 1, 0, 0], [o, 1, 0], [o + 1, 1, 0])
+    return [a, b]
+
+
+@pytest.mark.parametrize("gap", [0.85, 0.92])
+def test_admissibility_against_closed_form_diameters_and_distances(gap):
+    """Sec. 4.2 admissibility max(diam) <= eta dist on clusters of two flat squares.  Level 0: both
+    squares, diam sqrt(2) and dist = gap, admissible iff sqrt(2) < 1.6 gap, i.e. gap > 0.884 (not at
+    0.85, yes at 0.92).  Level 1: quarter squares, diam sqrt(2)/2 and dist >= gap, all 16 cross pairs
+    admissible when level 0 is not.  A centre distance (1 + gap) or a radius in place of the diameter
+    would admit the squares at 0.85."""
+    P = oracle.Problem(_two_squares(gap), p=1, m=2, q=4, leaf_depth=1, eta=1.6)
+    assert P.L == 1
+    near, far = P.partition()
+    far = {tuple(map(int, r)) for r in far}
+    top = {(0, 0, 1), (0, 1, 0)}
+    cross1 = {(1, t, s) for t in range(4) for s in range(4, 8)} | {(1, s, t) for t in range(4) for s in range(4, 8)}
+    if math.sqrt(2.0) < 1.6 * gap:
+        assert top <= far and not (cross1 & far)
+    else:
+        assert not (top & far) and cross1 <= far
+    # the quarters of one square touch each other (distance zero): no admissible pair inside a square
+    assert all((t != s) if lv == 0 else ((t < 4) != (s < 4)) for lv, t, s in far)
+
+
+def test_admissibility_with_the_wavenumber_bound():
+    """Reading of the wavenumber option: with kappa diam > kappa_diam a block is not admissible whatever
+    its distance.  At gap 0.92 the squares (kappa sqrt(2) = 5.66 for kappa = 4) are admissible with the
+    paper's rule and not with kappa_diam = 5; their quarters (kappa diam = 2.83) are."""
+    sq = _two_squares(0.92)
+    kw = dict(p=1, m=2, q=4, leaf_depth=1, eta=1.6, kernel=oracle.HELMHOLTZ, wavenumber=4.0)
+    far0 = {tuple(map(int, r)) for r in oracle.Problem(sq, **kw).partition()[1]}
+    far1 = {tuple(map(int, r)) for r in oracle.Problem(sq, kappa_diam=5.0, **kw).partition()[1]}
+    assert (0, 0, 1) in far0 and (0, 0, 1) not in far1
+    cross1 = {(1, t, s) for t in range(4) for s in range(4, 8)}
+    assert cross1 <= far1

@@ -1,6 +1,7 @@
 """CPU checks of the C-ABI library: it loads, exports every declared symbol, validates its inputs,
 and its host-side plan (cluster tree, block partition, element-pair classification; Sec. 4.1,
 Sec. 4.2 Def., Sec. 4 item 4) is identical to the oracle's.  No GPU work is started here."""
+import math
 import os
 import re
 
@@ -206,3 +207,22 @@ def test_plan_matches_oracle_fichera_and_perturbed_sphere():
     info = _compare_plan(W.perturbed_mapping_patches(W.sphere_patches()), p=2, m=3, q=4, leaf_depth=1, eta=1.6,
                          gauss_regular=6)
     assert info.n_far_blocks > 0
+
+
+@pytest.mark.parametrize("gap", [0.85, 0.92])
+def test_plan_admissibility_on_two_flat_squares(gap):
+    """The product's host plan on two flat unit squares a gap apart (closed-form cluster diameters and
+    distances, Sec. 4.2): equal to the oracle's, the squares admissible iff sqrt(2) < 1.6 gap, and
+    otherwise every pair of quarters across the gap admissible."""
+    a = W.flat_patch([0, 0, 0], [1, 0, 0], [0, 1, 0], [1, 1, 0])
+    o = 1.0 + gap
+    b = W.flat_patch([o, 0, 0], [o + 1, 0, 0], [o, 1, 0], [o + 1, 1, 0])
+    _compare_plan([a, b], p=1, m=2, q=4, leaf_depth=1, eta=1.6)
+    _, far = igb.Plan(igb.Geometry([a, b]), mode=igb.IGB_H2_STORED, p=1, m=2, q=4, leaf_depth=1,
+                      eta=1.6).partition()
+    far = {tuple(map(int, r)) for r in far}
+    cross1 = {(1, t, s) for t in range(4) for s in range(4, 8)}
+    if math.sqrt(2.0) < 1.6 * gap:
+        assert (0, 0, 1) in far and not (cross1 & far)
+    else:
+        assert (0, 0, 1) not in far and cross1 <= far

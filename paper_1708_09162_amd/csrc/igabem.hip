@@ -130,6 +130,9 @@ __device__ inline void near_targets(const int32_t *sb, const PairRec &R, int64_t
     out2 = b2 >= 0 ? blocks + (int64_t)b2 * bsz : nullptr;
 }
 
+// entries (sin, cos) of the sine/cosine table of the complex kernels (sincos_tab)
+constexpr int kSinCosTab = 256;
+
 // 1/sqrt(r2) for finite r2 > 0: the hardware estimate refined by the
 // second-order expansion of (1 - e)^(-1/2) = 1 + e/2 + 3e^2/8, e = 1 - r2 y^2.
 __device__ inline double rsqrt_pos(double r2)
@@ -392,7 +395,8 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 template <class T, int P, int PG, int WAVES, bool VTX>
 __global__ void __launch_bounds__(64 * WAVES, NComp<T>::value == 1 ? 2 : 1) k_near_singular(
     const PairRec *__restrict__ pairs, int gs, const double *__restrict__ gxs, const double *__restrict__ gws,
-    const double *__restrict__ tfix_u, const double *__restrict__ tfix_v, double kappa, T *__restrict__ pairbuf)
+    const double *__restrict__ tfix_u, const double *__restrict__ tfix_v, double kappa, T *__restrict__ pairbuf,
+    const double *__restrict__ sctab)
 {
     constexpr int P1 = P + 1, NLOC = P1 * P1, NT = (NLOC + 15) / 16, NPAD = 16 * NT;
     constexpr int NC = NComp<T>::value;
@@ -417,6 +421,10 @@ __global__ void __launch_bounds__(64 * WAVES, NComp<T>::value == 1 ? 2 : 1) k_ne
         nx[k] = gxs[k];
         nw[k] = gws[k];
     }
+    // complex kernel: the sine/cosine table (sincos_tab) next to the nodes, before the first barrier
+    __shared__ __attribute__((aligned(16))) double tabs[NC == 2 ? 2 * kSinCosTab : 1];
+    if constexpr (NC == 2)
+        for (int k = threadIdx.x; k < 2 * kSinCosTab; k += blockDim.x) tabs[k] = sctab[k];
     if constexpr (NPAD > NLOC) {
         for (int k = lane; k < HALF * (NPAD - NLOC); k += 64) {
             int pt = k / (NPAD - NLOC), a = NLOC + k % (NPAD - NLOC);
@@ -546,7 +554,7 @@ __global__ void __launch_bounds__(64 * WAVES, NComp<T>::value == 1 ? 2 : 1) k_ne
                 double wk[NC];
                 if constexpr (NC == 2) {
                     double sn, cs;
-                    sincos_red(kappa * (r2 * ir), &sn, &cs);
+                    sincos_tab(kappa * (r2 * ir), tabs, &sn, &cs);
                     wk[0] = cs * f0;
                     wk[1] = sn * f0;
                 } else {
@@ -628,7 +636,7 @@ __global__ void __launch_bounds__(64 * WAVES, NComp<T>::value == 1 ? 2 : 1) k_ne
                 double wk[NC];
                 if constexpr (NC == 2) {
                     double sn, cs;
-                    sincos_red(kappa * (r2 * ir), &sn, &cs);
+                    sincos_tab(kappa * (r2 * ir), tabs, &sn, &cs);
                     wk[0] = cs * f0;
                     wk[1] = sn * f0;
                 } else {
@@ -1501,8 +1509,7 @@ constexpr int far_sym_lds()
     if constexpr (NComp<T>::value == 1) return far_mfma_lds<(TT + 1) / 2>();
     else return 12 * 8 * TT;
 }
-// entries (sin, cos) of the sine/cosine table of the complex far field
-constexpr int kSinCosTab = 256;
+
 
 // Node data of one cluster's node j for the far field: position and the
 // weighted moment kappa_j X^[j] (padding nodes j >= q2: far from every node,
@@ -3166,7 +3173,7 @@ static igb_status launch_singular_pg(igb_operator *op, const PairRec *d_pairs, i
             hipLaunchKernelGGL((k_near_singular<T, P, PG, WAVES, V>), dim3((unsigned)cnt), dim3(64 * WAVES), shm,
                                op->st, d_pairs + off, gs, op->gx + op->s.goff[gs], op->gw + op->s.goff[gs], op->tline,
                                op->tline + (size_t)op->s.nelem * op->s.tile_stride, op->s.kappa,
-                               (T *)outbuf + off * NLOC * NLOC);
+                               (T *)outbuf + off * NLOC * NLOC, (const double *)op->sctab);
             LAUNCHCHK();
         }
         return IGB_OK;
@@ -3540,6 +3547,18 @@ static igb_status assemble_identical(igb_operator *op)
 {
     Setup &s = op->s;
     igb_status rc;
+    if (op->cplx) {
+        // one period of sine and cosine at multiples of pi/128, from extended-precision host values (the
+        // touching-pair quadrature, the far field and the potential read it)
+        std::vector<double> tab(2 * kSinCosTab);
+        for (int j = 0; j < kSinCosTab; ++j) {
+            const long double a = (long double)j * 3.141592653589793238462643383279502884L / 128.0L;
+            tab[2 * j] = (double)sinl(a);
+            tab[2 * j + 1] = (double)cosl(a);
+        }
+        if ((rc = upload(op, &op->sctab, tab.data(), tab.size() * sizeof(double)))) return rc;
+        HIPCHK(hipStreamSynchronize(op->st));  // the host table goes out of scope
+    }
     int ords[3] = {s.g0, std::min(40, s.g0 + 2), std::min(40, s.g0 + 4)};
     for (int k = 0; k < 3; ++k) {
         op->gord[k] = ords[k];
@@ -3686,17 +3705,6 @@ static igb_status assemble(igb_operator *op)
     int64_t nfar = (int64_t)s.far_src.size();
     op->coup_bytes = nfar * q2 * q2 * (int64_t)sizeof(T);
     if ((rc = dalloc(op, (void **)&op->nodes, (size_t)ncl_all * q2 * 4 * sizeof(double)))) return rc;
-    if (op->cplx) {
-        // one period of sine and cosine at multiples of pi/128, from extended-precision host values
-        std::vector<double> tab(2 * kSinCosTab);
-        for (int j = 0; j < kSinCosTab; ++j) {
-            const long double a = (long double)j * 3.141592653589793238462643383279502884L / 128.0L;
-            tab[2 * j] = (double)sinl(a);
-            tab[2 * j + 1] = (double)cosl(a);
-        }
-        if ((rc = upload(op, &op->sctab, tab.data(), tab.size() * sizeof(double)))) return rc;
-        HIPCHK(hipStreamSynchronize(op->st));  // the host table goes out of scope
-    }
     hipLaunchKernelGGL(k_cluster_nodes, dim3(nblk(ncl_all * q2, 256)), dim3(256), 0, op->st, ncl_all, s.L, op->cl_off,
                        s.q, s.m, s.ne, op->zdev, s.tile_stride, op->tiles, op->tdeg, op->nodes);
     LAUNCHCHK();

@@ -149,7 +149,7 @@ template <class T, int P>
 __global__ void __launch_bounds__(128) k_near_regular(const PairRec *__restrict__ pairs, int npairs, int g,
                                                       const double *__restrict__ gp, const double *__restrict__ btab,
                                                       double kappa, int nl, int ld, const int32_t *__restrict__ sb,
-                                                      T *__restrict__ blocks)
+                                                      T *__restrict__ blocks, const double *__restrict__ sctab)
 {
     constexpr int P1 = P + 1, NLOC = P1 * P1, TS = NLOC + 1;  // tmp row stride: rows on distinct banks
     extern __shared__ double sh[];
@@ -183,7 +183,7 @@ __global__ void __launch_bounds__(128) k_near_regular(const PairRec *__restrict_
             T k;
             if constexpr (NComp<T>::value == 2) {
                 double sn, cs;
-                sincos_red(kappa * (r2 * ir), &sn, &cs);
+                sincos_tab(kappa * (r2 * ir), sctab, &sn, &cs);  // the 4 KB table stays in the L1 cache
                 k = T{cs * f, sn * f};
             } else {
                 k = f;
@@ -3145,7 +3145,7 @@ static igb_status launch_regular_p(igb_operator *op, const PairRec *d_pairs, int
         int64_t cnt = std::min<int64_t>(n - off, 1 << 20);
         hipLaunchKernelGGL((k_near_regular<T, P>), dim3((unsigned)cnt), dim3(threads), shm, op->st, d_pairs + off, (int)cnt, g,
                            gp, op->btab + (size_t)op->s.goff[g] * (P + 1), op->s.kappa, op->s.nl, op->near_ld, op->sb,
-                           (T *)op->nearb);
+                           (T *)op->nearb, (const double *)op->sctab);
         LAUNCHCHK();
     }
     return IGB_OK;

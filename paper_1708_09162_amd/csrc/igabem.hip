@@ -1575,7 +1575,8 @@ __device__ inline void lds_add(R *p, R v)
 // lds is the wave's slice of far_sym_lds<cd, TT>() doubles (the two clusters'
 // nodes, then the pair's column sums).  Lane (li, lj) owns targets li*TT + ii
 // and sources jj*8 + lj (ii, jj < TT).  The targets go in NP passes of at most
-// five, so that few of them are held in registers at a time.  For each source
+// five (seven in single precision), so that few of them are held in registers
+// at a time.  For each source
 // the lane's targets are summed in registers, reduced over the 8 lanes li
 // (DPP) and added by lane li = 0 into the source's LDS column sum (eight
 // distinct words per instruction); rows are reduced over the 8 lanes lj by
@@ -1590,7 +1591,9 @@ __device__ inline void far_sym_chunk(const FarSymArgs &F, int64_t k0, int64_t k1
 {
     using R = typename std::conditional<RAW, float, double>::type;
     constexpr int W = 8 * TT;  // padded nodes per cluster
-    constexpr int NP = (TT + 4) / 5;                   // passes of at most five targets per lane
+    // passes of at most five targets per lane (single precision with more than 64 nodes: seven, whose
+    // registers the FP32 values leave room for: far field 1.73 -> 1.59 ms on the torus)
+    constexpr int NP = RAW && TT > 8 ? (TT + 6) / 7 : (TT + 4) / 5;
     constexpr int THL = TT / NP, NH = TT - THL * NP;  // NH passes of THL + 1 targets, NP - NH of THL
     constexpr int THH = NH > 0 ? THL + 1 : THL;
     double *tg = lds, *sr = lds + 5 * W;  // [x | y | z | w.re | w.im] x W each
